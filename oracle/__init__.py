@@ -1,0 +1,273 @@
+"""FP64 CPU oracle for the e-ph collision integral and its consumers.
+
+TEST INFRASTRUCTURE ONLY.  Only tests/, the smoke check and the benchmark's
+cpu_baseline leg may import this package.  It shares no code with the GPU
+library (paper_2511_03683_amd): it has its own C file (eph_oracle.c), its own
+constants and its own q-index, Gaussian and occupation-factor arithmetic.
+
+Contents, each following the paper (arXiv 2511.03683):
+
+* collision(sys, f, nph)        -- Eq. 2 over a channel list (Results,
+  "Collision integral ..."; the channel-list loop is the Baseline-CPU loop
+  shape of "Reference CPU algorithm", run sequentially).
+* collision_brute(sys, f, nph)  -- Eq. 2 written out over the full q grid,
+  all bands and modes, for tiny grids (numpy; independent of the C code).
+* collision_vjp(...)            -- hand-derived reverse mode of Eq. 2.
+* rk4_step / rk4_adjoint_step   -- classical RK4 for df/dt = I[f] (the
+  paper's real-time BTE; the integrator is not named in the text, RK4 is the
+  reading adopted here) and its exact discrete adjoint.
+* transport_*                   -- linearised steady-state BTE (Eq. 1 with the
+  collision integral linearised at f0), iterated to self-consistency.
+
+Parity status: every function here is pinned by tests/test_oracle.py
+(closed forms, invariants, brute force, finite differences); the absolute
+physics of the paper's materials is "parity unpinned" (no data).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+HBAR_EV_FS = 0.6582119569
+KB_EV_K = 8.617333262e-5
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        path = os.path.join(HERE, "liboracle.so")
+        if not os.path.exists(path):
+            from . import build as _b
+            _b.build()
+        lib = ctypes.CDLL(path)
+        P = ctypes.c_void_p
+        common = [ctypes.c_int, P, P, P, P, ctypes.c_int, P, P, ctypes.c_double,
+                  ctypes.c_double, ctypes.c_int64, P, P, P, P]
+        lib.orc_collision.argtypes = common + [P, P, P]
+        lib.orc_collision.restype = None
+        lib.orc_collision_vjp.argtypes = common + [P, P, P, P]
+        lib.orc_collision_vjp.restype = None
+        lib.orc_transport_coeffs.argtypes = common + [P, P, P, P]
+        lib.orc_transport_coeffs.restype = None
+        _LIB = lib
+    return _LIB
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+class _Args:
+    """Holds contiguous copies of a system's arrays for the C calls."""
+
+    def __init__(self, sys, nph, g2=None):
+        self.S = sys.n_states
+        self.state_k = _c(sys.state_k, np.int32)
+        self.eps = _c(sys.eps, np.float64)
+        self.kgrid = _c(sys.kgrid, np.int32)
+        self.qgrid = _c(sys.qgrid, np.int32)
+        self.nm = int(sys.n_modes)
+        self.hw = _c(sys.hw, np.float64)
+        self.nph = _c(nph, np.float64)
+        assert self.hw.shape == self.nph.shape
+        self.sigma = float(sys.sigma)
+        self.nq = float(sys.n_q_norm)
+        self.ci = _c(sys.ch_i, np.int32)
+        self.cj = _c(sys.ch_j, np.int32)
+        self.cn = _c(sys.ch_nu, np.int8)
+        self.g2 = _c(sys.g2 if g2 is None else g2, np.float64)
+
+    def common(self):
+        return [self.S, _ptr(self.state_k), _ptr(self.eps), _ptr(self.kgrid), _ptr(self.qgrid),
+                self.nm, _ptr(self.hw), _ptr(self.nph), self.sigma, self.nq,
+                int(self.ci.size), _ptr(self.ci), _ptr(self.cj), _ptr(self.cn), _ptr(self.g2)]
+
+
+# ---------------------------------------------------------------------------
+# collision integral (Eq. 2)
+# ---------------------------------------------------------------------------
+def collision(sys, f, nph, g2=None, mask=None, args=None):
+    """I[f] [S] in FP64 by the sequential channel-list loop.  mask (bool [S])
+    restricts the accumulation to sampled destinations."""
+    a = args or _Args(sys, nph, g2)
+    f = _c(f, np.float64)
+    I = np.zeros(a.S)
+    m = None if mask is None else _c(mask, np.uint8)
+    _lib().orc_collision(*a.common(), _ptr(f), _ptr(m), _ptr(I))
+    return I
+
+
+def collision_batched(sys, F, nph, g2=None):
+    """Columns of I for a batch F [B, S]: the plain oracle applied per vector."""
+    a = _Args(sys, nph, g2)
+    return np.stack([collision(sys, F[b], nph, args=a) for b in range(F.shape[0])])
+
+
+def collision_vjp(sys, f, nph, lam, g2=None, want_f=True, want_g2=True):
+    """(dL/df [S], dL/dg2 [Nch]) for L = sum_d lam_d I_d."""
+    a = _Args(sys, nph, g2)
+    f = _c(f, np.float64)
+    lam = _c(lam, np.float64)
+    gf = np.zeros(a.S) if want_f else None
+    gg = np.zeros(a.ci.size) if want_g2 else None
+    _lib().orc_collision_vjp(*a.common(), _ptr(f), _ptr(lam), _ptr(gf), _ptr(gg))
+    return gf, gg
+
+
+def collision_brute(sys, f, nph):
+    """Eq. 2 literally: for every state (n,k), sum over every q of the q grid,
+    every band m and mode nu, with the partner (m, k+q) looked up on the k grid.
+    |g|^2 comes from the channel list (0 for inactive channels); terms with
+    hw < 1e-6 eV have no active channel.  Tiny grids only (dense [S,S,modes])."""
+    S, nm = sys.n_states, sys.n_modes
+    kg = np.asarray(sys.kgrid)
+    qg = np.asarray(sys.qgrid)
+    r = kg // qg
+    g2d = np.zeros((S, S, nm))
+    np.add.at(g2d, (sys.ch_i, sys.ch_j, sys.ch_nu.astype(np.int64)), sys.g2)
+    np.add.at(g2d, (sys.ch_j, sys.ch_i, sys.ch_nu.astype(np.int64)), sys.g2)
+    nk = int(np.prod(kg))
+    kc = np.stack(np.unravel_index(sys.state_k, tuple(kg)), axis=1)
+    at_k = [[] for _ in range(nk)]
+    for s, k in enumerate(sys.state_k):
+        at_k[int(k)].append(s)
+    qc = np.stack(np.unravel_index(np.arange(int(np.prod(qg))), tuple(qg)), axis=1)
+    pref = 2.0 * np.pi / HBAR_EV_FS / sys.n_q_norm
+    sig = sys.sigma
+    G = lambda x: np.exp(-0.5 * (x / sig) ** 2) / (sig * np.sqrt(2.0 * np.pi))
+    I = np.zeros(S)
+    for d in range(S):
+        kp = (kc[d][None, :] + r[None, :] * qc) % kg[None, :]
+        kp_lin = np.ravel_multi_index(tuple(kp.T), tuple(kg))
+        total = 0.0
+        for qi in range(qc.shape[0]):
+            for p in at_k[int(kp_lin[qi])]:
+                for nu in range(nm):
+                    g = g2d[d, p, nu]
+                    if g == 0.0:
+                        continue
+                    w = sys.hw[qi, nu]
+                    N = nph[qi, nu]
+                    fd, fp = f[d], f[p]
+                    F_abs = fd * (1 - fp) * N - fp * (1 - fd) * (N + 1)
+                    F_em = fd * (1 - fp) * (N + 1) - fp * (1 - fd) * N
+                    de = sys.eps[d] - sys.eps[p]
+                    total += -pref * g * (G(de + w) * F_abs + G(de - w) * F_em)
+        I[d] = total
+    return I
+
+
+# ---------------------------------------------------------------------------
+# real-time BTE: classical RK4 and its discrete adjoint
+# ---------------------------------------------------------------------------
+def rk4_step(sys, f, nph, dt, g2=None, return_stages=False):
+    """One classical fourth-order Runge-Kutta step of df/dt = I[f]."""
+    a = _Args(sys, nph, g2)
+    I = lambda u: collision(sys, u, nph, args=a)
+    u1 = np.array(f, dtype=np.float64)
+    k1 = I(u1)
+    u2 = u1 + 0.5 * dt * k1
+    k2 = I(u2)
+    u3 = u1 + 0.5 * dt * k2
+    k3 = I(u3)
+    u4 = u1 + dt * k3
+    k4 = I(u4)
+    out = u1 + (dt / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+    return (out, (u1, u2, u3, u4)) if return_stages else out
+
+
+def rk4_adjoint_step(sys, stages, nph, dt, gbar, g2=None):
+    """Reverse of one RK4 step.  Given gbar = dL/df_{n+1} and the stage inputs
+    (u1..u4) of the step, return (dL/df_n, dL/dg2 contribution of the step)."""
+    u1, u2, u3, u4 = stages
+    vjp = lambda u, lam: collision_vjp(sys, u, nph, lam, g2=g2)
+    kb4 = (dt / 6.0) * gbar
+    ub4, gg4 = vjp(u4, kb4)
+    kb3 = (dt / 3.0) * gbar + dt * ub4
+    ub3, gg3 = vjp(u3, kb3)
+    kb2 = (dt / 3.0) * gbar + 0.5 * dt * ub3
+    ub2, gg2_ = vjp(u2, kb2)
+    kb1 = (dt / 6.0) * gbar + 0.5 * dt * ub2
+    ub1, gg1 = vjp(u1, kb1)
+    return gbar + ub1 + ub2 + ub3 + ub4, gg1 + gg2_ + gg3 + gg4
+
+
+def rk4_trajectory_grad(sys, f0, nph, dt, n_steps, gT, g2=None):
+    """Gradients of L(f_T) through n_steps RK4 steps, storing every stage."""
+    f = np.array(f0, dtype=np.float64)
+    stages = []
+    for _ in range(n_steps):
+        f, st = rk4_step(sys, f, nph, dt, g2=g2, return_stages=True)
+        stages.append(st)
+    g = np.array(gT, dtype=np.float64)
+    gg = np.zeros(sys.n_channels)
+    for st in reversed(stages):
+        g, dg = rk4_adjoint_step(sys, st, nph, dt, g, g2=g2)
+        gg += dg
+    return f, g, gg
+
+
+# ---------------------------------------------------------------------------
+# transport: linearised steady-state BTE
+# ---------------------------------------------------------------------------
+def transport_coeffs(sys, f0, nph, g2=None):
+    """(tau_inv [S], W_ij [Nch], W_ji [Nch]): dI/df at f0 split into its
+    diagonal (-tau_inv) and the off-diagonal entries of each channel."""
+    a = _Args(sys, nph, g2)
+    f0 = _c(f0, np.float64)
+    tau_inv = np.zeros(a.S)
+    Wij = np.zeros(a.ci.size)
+    Wji = np.zeros(a.ci.size)
+    _lib().orc_transport_coeffs(*a.common(), _ptr(f0), _ptr(tau_inv), _ptr(Wij), _ptr(Wji))
+    return tau_inv, Wij, Wji
+
+
+def dfde_fd(f0, T):
+    """d f0 / d eps of a Fermi-Dirac distribution at temperature T, from f0."""
+    return -np.asarray(f0) * (1.0 - np.asarray(f0)) / (KB_EV_K * T)
+
+
+def mobility_cm2(vel, x, f0):
+    """mu_ab = -e sum_d v_a x_b / sum_d f0 with x in fs*(m/s)/eV and v in m/s
+    (e = 1 in eV units): 1 fs = 1e-15 s and 1 m^2 = 1e4 cm^2."""
+    return -1e-15 * 1e4 * (np.asarray(vel).T @ np.asarray(x)) / float(np.sum(f0))
+
+
+def transport_apply_W(sys, Wij, Wji, x):
+    """(W x)_d = sum over channels of the off-diagonal rows, for x [S, 3]."""
+    S = sys.n_states
+    out = np.zeros_like(x)
+    for b in range(x.shape[1]):
+        out[:, b] = (np.bincount(sys.ch_i, weights=Wij * x[sys.ch_j, b], minlength=S)
+                     + np.bincount(sys.ch_j, weights=Wji * x[sys.ch_i, b], minlength=S))
+    return out
+
+
+def transport_solve(sys, f0, vel, T, nph, tol=1e-8, max_iter=200, g2=None):
+    """Iterate x_d = tau_d (v_d df0/de + sum_p W_dp x_p) from the RTA start
+    until the mobility changes by at most tol (relative, max norm).
+    Returns dict(mu [3,3] cm^2/Vs, x [S,3], iters, converged, history)."""
+    tau_inv, Wij, Wji = transport_coeffs(sys, f0, nph, g2)
+    tau = 1.0 / tau_inv
+    b = np.asarray(vel) * dfde_fd(f0, T)[:, None]
+    x = tau[:, None] * b
+    mu = mobility_cm2(vel, x, f0)
+    hist = [mu]
+    for it in range(1, max_iter + 1):
+        x = tau[:, None] * (b + transport_apply_W(sys, Wij, Wji, x))
+        mu_new = mobility_cm2(vel, x, f0)
+        rel = np.abs(mu_new - mu).max() / np.abs(mu_new).max()
+        mu = mu_new
+        hist.append(mu)
+        if rel <= tol:
+            return dict(mu=mu, x=x, iters=it, converged=True, history=hist, resid=rel)
+    return dict(mu=mu, x=x, iters=max_iter, converged=False, history=hist, resid=rel)

@@ -1,0 +1,302 @@
+"""Pins for the FP64 CPU oracle (no GPU).
+
+Each test checks the oracle against something other than itself: the
+brute-force form of Eq. 2 written independently in numpy, conservation laws,
+detailed balance, closed forms from Fermi's golden rule, finite differences
+(exact up to rounding because I is quadratic in f and linear in |g|^2),
+the RK4 amplification polynomial and the Drude mobility.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+HBAR = 0.6582119569          # eV fs
+KB = 8.617333262e-5          # eV/K
+
+
+@pytest.fixture(scope="module")
+def c1():
+    s = synth.parabolic_system(8)
+    return s, synth.c1_occupations(s), s.nph(300.0)
+
+
+def _G(x, sig):
+    return math.exp(-0.5 * (x / sig) ** 2) / (sig * math.sqrt(2 * math.pi))
+
+
+# --------------------------------------------------------------- brute force
+@pytest.mark.parametrize("maker", [lambda: synth.parabolic_system(4),
+                                   lambda: synth.multiband_system(),
+                                   lambda: synth.multiband_system(kn=4, qn=2, nb=3, n_k=10, seed=5)])
+def test_list_equals_brute_force_tiny(maker):
+    """Channel-list loop == Eq. 2 summed over the full q grid, bands and modes
+    (Eq. 2; pairing of the two contributions of a channel: GPU algorithm step 1)."""
+    s = maker()
+    f = synth.random_occupations(s, 5)
+    nph = s.nph(300.0)
+    I = oracle.collision(s, f, nph)
+    Ib = oracle.collision_brute(s, f, nph)
+    assert np.abs(I - Ib).max() <= 1e-14 * np.abs(Ib).max()
+
+
+def test_c1_counts_and_brute_force(c1):
+    s, f, nph = c1
+    assert s.n_states == 512
+    assert s.n_channels == 512 * 511 // 2 * 3
+    I = oracle.collision(s, f, nph)
+    Ib = oracle.collision_brute(s, f, nph)
+    assert np.abs(I - Ib).max() <= 1e-14 * np.abs(Ib).max()
+
+
+# --------------------------------------------------------------- invariants
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_particle_number_conserved(seed):
+    """sum_s I_s = 0 for any f: each channel moves an electron between two states."""
+    s = synth.multiband_system(seed=seed + 20)
+    f = synth.random_occupations(s, seed)
+    I = oracle.collision(s, f, s.nph(250.0))
+    gross = np.abs(I).sum()
+    assert abs(I.sum()) <= 1e-14 * gross
+
+
+def test_pauli_blocking(c1):
+    """Empty and completely full bands do not scatter."""
+    s, _, nph = c1
+    assert np.all(oracle.collision(s, np.zeros(s.n_states), nph) == 0.0)
+    assert np.all(oracle.collision(s, np.ones(s.n_states), nph) == 0.0)
+
+
+def test_linear_in_g2(c1):
+    s, f, nph = c1
+    I1 = oracle.collision(s, f, nph)
+    I3 = oracle.collision(s, f, nph, g2=3.0 * s.g2)
+    assert np.allclose(I3, 3.0 * I1, rtol=1e-14, atol=0)
+
+
+def test_detailed_balance_resonant_ladder():
+    """Fermi-Dirac electrons with Bose-Einstein phonons at the same T are a
+    fixed point when every channel is on resonance (counter-process Gaussian
+    underflows): I = 0 to rounding.  With electrons hotter than the phonons
+    the same system relaxes (I != 0)."""
+    s = synth.ladder_system()
+    nph = s.nph(300.0)
+    f_eq = synth.fermi_dirac(s.eps, 0.1, 300.0)
+    I_eq = oracle.collision(s, f_eq, nph)
+    f_hot = synth.fermi_dirac(s.eps, 0.1, 900.0)
+    I_hot = oracle.collision(s, f_hot, nph)
+    assert np.abs(I_hot).max() > 0
+    assert np.abs(I_eq).max() <= 1e-13 * np.abs(I_hot).max()
+
+
+def test_two_state_golden_rule():
+    """One channel, the upper state exactly one phonon above the lower one.
+    Golden rule: the lower state gains (N+1) f2 (1-f1) by emission from the
+    upper one and loses N f1 (1-f2) by absorption, at rate
+    (2 pi / hbar) |g|^2 / N_q * G(0); the upper state loses the same amount."""
+    s = synth.two_state_system(dE=0.05, hw=0.05, g2=2e-3, sigma=0.004, nq=2)
+    T = 300.0
+    N = 1.0 / math.expm1(0.05 / (KB * T))
+    nph = np.full((2, 1), N)
+    f = np.array([0.7, 0.2])
+    I = oracle.collision(s, f, nph)
+    rate = 2 * math.pi / HBAR * 2e-3 / 2 * _G(0.0, 0.004)
+    expect1 = rate * ((N + 1) * f[1] * (1 - f[0]) - N * f[0] * (1 - f[1]))
+    assert I[0] == pytest.approx(expect1, rel=1e-13)
+    assert I[1] == pytest.approx(-expect1, rel=1e-13)
+
+
+def test_two_state_off_resonance_tail():
+    """Detuned pair: absorption and emission Gaussians are evaluated at
+    e1 - e2 + hw and e1 - e2 - hw respectively."""
+    sig = 0.01
+    s = synth.two_state_system(dE=0.03, hw=0.05, g2=1e-3, sigma=sig, nq=1)
+    N = 0.4
+    nph = np.full((1, 1), N)
+    f = np.array([0.3, 0.6])
+    I = oracle.collision(s, f, nph)
+    pref = 2 * math.pi / HBAR * 1e-3
+    de = -0.03
+    absorb = _G(de + 0.05, sig) * (N * f[0] * (1 - f[1]) - (N + 1) * f[1] * (1 - f[0]))
+    emit = _G(de - 0.05, sig) * ((N + 1) * f[0] * (1 - f[1]) - N * f[1] * (1 - f[0]))
+    assert I[0] == pytest.approx(-pref * (absorb + emit), rel=1e-13)
+
+
+# --------------------------------------------------------------- derivatives
+def test_vjp_matches_central_differences():
+    """I is quadratic in f and linear in |g|^2, so central differences are exact
+    up to rounding; the hand-written reverse mode must reproduce them."""
+    s = synth.multiband_system()
+    f = synth.random_occupations(s, 8)
+    nph = s.nph(300.0)
+    lam = np.random.default_rng(4).normal(size=s.n_states)
+    gf, gg = oracle.collision_vjp(s, f, nph, lam)
+    h = 1e-3
+    fd_f = np.empty(s.n_states)
+    for k in range(s.n_states):
+        e = np.zeros(s.n_states)
+        e[k] = h
+        fd_f[k] = lam @ (oracle.collision(s, f + e, nph) - oracle.collision(s, f - e, nph)) / (2 * h)
+    assert np.abs(gf - fd_f).max() <= 1e-10 * np.abs(fd_f).max()
+    fd_g = np.empty(s.n_channels)
+    for c in range(s.n_channels):
+        g2 = s.g2.copy()
+        g2[c] += s.g2[c]
+        fd_g[c] = lam @ (oracle.collision(s, f, nph, g2=g2) - oracle.collision(s, f, nph)) / s.g2[c]
+    assert np.abs(gg - fd_g).max() <= 1e-10 * np.abs(fd_g).max()
+
+
+def test_vjp_euler_identity(c1):
+    """L = lam . I is homogeneous of degree 1 in |g|^2: sum_c g2_c dL/dg2_c = L."""
+    s, f, nph = c1
+    lam = np.random.default_rng(1).normal(size=s.n_states)
+    _, gg = oracle.collision_vjp(s, f, nph, lam)
+    L = lam @ oracle.collision(s, f, nph)
+    assert (s.g2 @ gg) == pytest.approx(L, rel=1e-12)
+
+
+# --------------------------------------------------------------- RK4
+def test_rk4_degenerate_pair_amplification():
+    """Two degenerate states (e1 = e2): absorption and emission weights are
+    equal, the equation is linear, d(f1-f2)/dt = -2a (f1-f2) with
+    a = (2 pi/hbar)(|g|^2/N_q) G(hw) (2N+1), and one RK4 step multiplies
+    f1 - f2 by 1 - z + z^2/2 - z^3/6 + z^4/24, z = 2 a dt."""
+    sig, hw, g2, N = 0.02, 0.01, 1e-3, 0.7
+    s = synth.two_state_system(dE=0.0, hw=hw, g2=g2, sigma=sig, nq=1)
+    nph = np.full((1, 1), N)
+    a = 2 * math.pi / HBAR * g2 * _G(hw, sig) * (2 * N + 1)
+    dt = 0.2
+    z = 2 * a * dt
+    R = 1 - z + z * z / 2 - z ** 3 / 6 + z ** 4 / 24
+    f = np.array([0.9, 0.1])
+    d0 = f[0] - f[1]
+    for n in range(1, 6):
+        f = oracle.rk4_step(s, f, nph, dt)
+        assert (f[0] - f[1]) == pytest.approx(d0 * R ** n, rel=1e-12)
+        assert f.sum() == pytest.approx(1.0, rel=1e-15)
+
+
+def test_rk4_fourth_order():
+    s = synth.multiband_system()
+    f0 = synth.random_occupations(s, 2)
+    nph = s.nph(300.0)
+    def run(dt, n):
+        f = f0.copy()
+        for _ in range(n):
+            f = oracle.rk4_step(s, f, nph, dt)
+        return f
+    ref = run(0.25, 64)
+    e1 = np.abs(run(2.0, 8) - ref).max()
+    e2 = np.abs(run(1.0, 16) - ref).max()
+    assert 12.0 < e1 / e2 < 20.0
+
+
+def _mean_energy(s, f):
+    return (s.eps @ f) / f.sum()
+
+
+def test_rk4_adjoint_matches_finite_differences():
+    """Discrete RK4 adjoint of L = sum eps f_T / sum f_T through 4 steps."""
+    s = synth.multiband_system(n_k=10, seed=23)
+    f0 = synth.random_occupations(s, 9) * 0.8 + 0.1
+    nph = s.nph(300.0)
+    dt, n = 0.5, 4
+    fT = f0.copy()
+    for _ in range(n):
+        fT = oracle.rk4_step(s, fT, nph, dt)
+    gT = (s.eps * fT.sum() - s.eps @ fT) / fT.sum() ** 2
+    _, gf0, gg2 = oracle.rk4_trajectory_grad(s, f0, nph, dt, n, gT)
+    def L(f0_, g2_=None):
+        f = f0_.copy()
+        for _ in range(n):
+            f = oracle.rk4_step(s, f, nph, dt, g2=g2_)
+        return _mean_energy(s, f)
+    h = 1e-5
+    for k in range(0, s.n_states, 3):
+        e = np.zeros(s.n_states)
+        e[k] = h
+        fd = (L(f0 + e) - L(f0 - e)) / (2 * h)
+        assert gf0[k] == pytest.approx(fd, rel=1e-6, abs=1e-9 * np.abs(gf0).max())
+    for c in range(0, s.n_channels, 7):
+        g = s.g2.copy()
+        hc = 1e-4 * g[c]
+        gp, gm = g.copy(), g.copy()
+        gp[c] += hc
+        gm[c] -= hc
+        fd = (L(f0, gp) - L(f0, gm)) / (2 * hc)
+        assert gg2[c] == pytest.approx(fd, rel=1e-5, abs=1e-8 * np.abs(gg2).max())
+
+
+# --------------------------------------------------------------- transport
+def test_transport_coeffs_are_the_jacobian():
+    """tau_inv and W are dI/df at f0 (diagonal and off-diagonal)."""
+    s = synth.multiband_system()
+    f0 = synth.fermi_dirac(s.eps, 0.05, 300.0)
+    nph = s.nph(300.0)
+    tau_inv, Wij, Wji = oracle.transport_coeffs(s, f0, nph)
+    S = s.n_states
+    J = np.zeros((S, S))
+    h = 1e-3
+    for k in range(S):
+        e = np.zeros(S)
+        e[k] = h
+        J[:, k] = (oracle.collision(s, f0 + e, nph) - oracle.collision(s, f0 - e, nph)) / (2 * h)
+    Jw = np.zeros((S, S))
+    np.add.at(Jw, (s.ch_i, s.ch_j), Wij)
+    np.add.at(Jw, (s.ch_j, s.ch_i), Wji)
+    Jw[np.diag_indices(S)] -= tau_inv
+    assert np.abs(J - Jw).max() <= 1e-10 * np.abs(J).max()
+
+
+def test_drude_mobility_rta():
+    """Constant relaxation time, parabolic band, non-degenerate statistics:
+    mu = e tau / m*, here evaluated in SI units independently of the oracle."""
+    m_eff, tau_fs, T = 0.3, 25.0, 300.0
+    eps, vel = synth.parabolic_states(n=60, a=20.0, m_eff=m_eff)
+    f0 = synth.fermi_dirac(eps, -0.2, T)
+    x = tau_fs * vel * oracle.dfde_fd(f0, T)[:, None]
+    mu = oracle.mobility_cm2(vel, x, f0)
+    e_si, me_si = 1.602176634e-19, 9.1093837015e-31
+    drude = e_si * tau_fs * 1e-15 / (m_eff * me_si) * 1e4
+    assert mu[0, 0] == pytest.approx(drude, rel=2e-4)
+    assert mu[1, 1] == pytest.approx(mu[0, 0], rel=1e-12)
+    assert abs(mu[0, 1]) < 1e-9 * mu[0, 0]
+
+
+def test_transport_fixed_point_equals_direct_solve():
+    """The iteration x <- tau (v df0/de + W x) started from the RTA solution
+    converges to the solution of the linear system (1/tau - W) x = v df0/de,
+    obtained here by a dense least-squares solve."""
+    s = synth.tb_system(kn=20, qn=10, target_states=300, sigma=0.05)
+    T = 300.0
+    f0 = synth.fermi_dirac(s.eps, -0.1, T)
+    nph = s.nph(T)
+    out = oracle.transport_solve(s, f0, s.vel, T, nph, tol=1e-12, max_iter=500)
+    assert out["converged"]
+    tau_inv, Wij, Wji = oracle.transport_coeffs(s, f0, nph)
+    S = s.n_states
+    W = np.zeros((S, S))
+    np.add.at(W, (s.ch_i, s.ch_j), Wij)
+    np.add.at(W, (s.ch_j, s.ch_i), Wji)
+    b = s.vel * oracle.dfde_fd(f0, T)[:, None]
+    x_direct = np.linalg.lstsq(np.diag(tau_inv) - W, b, rcond=None)[0]
+    mu_direct = oracle.mobility_cm2(s.vel, x_direct, f0)
+    assert np.abs(out["mu"] - mu_direct).max() <= 1e-9 * np.abs(mu_direct).max()
+    x = out["x"]
+    resid = x - (b + oracle.transport_apply_W(s, Wij, Wji, x)) / tau_inv[:, None]
+    assert np.abs(resid).max() <= 1e-9 * np.abs(x).max()
+    assert np.all(np.diag(out["mu"]) > 0)
+
+
+def test_c1_matches_stored_oracle_sample(c1):
+    """Regression fixture written by tests/golden/make_golden.py (oracle only)."""
+    import json, os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "c1_oracle_sample.json")) as fh:
+        g = json.load(fh)
+    s, f, nph = c1
+    I = oracle.collision(s, f, nph)
+    assert s.n_channels == g["n_channels"]
+    assert np.allclose(I[g["states"]], g["I"], rtol=1e-13, atol=1e-13 * g["max_abs"])
