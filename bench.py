@@ -1,0 +1,196 @@
+"""Benchmark of the e-ph collision integral on one MI355X.
+
+Workload: the tight-binding transport system (4-band cubic model on a 100^3
+k grid, 0.3 eV window, 50^3 q grid, 3 Debye + 3 Einstein modes, lognormal
+|g|^2, sigma = 8 meV, ~2e8 unordered channels), synthetic and seeded.
+
+A step is one evaluation of I[f] (Eq. 2) over every channel at B = 1 in FP64
+-- the operator every other form is built from.  `value` is scattering
+channels per second of that step with all inputs resident in HBM.  The other
+forms (FP32, forward + reverse, B = 64, RK4 step, transport iteration) are
+timed after the main loop and reported under "forms".
+
+Prints one JSON line.  Options: --steps K --warmup W --gpus 1 [--quick]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_CHANNEL = {"f64": 24.0, "f32": 16.0}        # 2 entries x (|g|^2 + packed partner/mode)
+VJP_BYTES_PER_CHANNEL = {"f64": 24.0 + 24.0 + 8.0, "f32": 16.0 + 16.0 + 8.0}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--quick", action="store_true", help="smaller system (for a fast check)")
+    ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-channels", type=int, default=100_000_000)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the destination-sharded design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2511_03683_amd as E
+    import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+
+    t0 = time.time()
+    if args.quick:
+        s = synth.tb_system(kn=60, qn=30, target_states=5000)
+        wname = "tb60_q30_6modes"
+    else:
+        s = synth.tb_system()
+        wname = "tb100_q50_6modes"
+    log(f"system {wname}: S={s.n_states} channels={s.n_channels} ({time.time() - t0:.1f}s)")
+    rng = np.random.default_rng(2511)
+    f_np = np.clip(synth.fermi_dirac(s.eps, 0.05, 300.0) * (0.8 + 0.4 * rng.uniform(size=s.n_states)), 0, 1)
+    nph_np = s.nph(300.0)
+    nch = s.n_channels
+
+    def tens(a, dt):
+        return torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+
+    t0 = time.time()
+    plan64 = E.build_channels(s, dtype="f64", device=0)
+    log(f"fp64 plan built ({time.time() - t0:.1f}s), info={E.plan_info(plan64)}")
+    f64, n64 = tens(f_np, torch.float64), tens(nph_np, torch.float64)
+    I64 = torch.empty_like(f64)
+
+    def timed(fn, reps, warm):
+        with torch.cuda.stream(stream):
+            for _ in range(warm):
+                fn()
+        stream.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        with torch.cuda.stream(stream):
+            ev0.record(stream)
+            for _ in range(reps):
+                fn()
+            ev1.record(stream)
+        stream.synchronize()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        return ev0.elapsed_time(ev1) / reps, wall
+
+    fwd64 = lambda: E.collision_integral(plan64, f64, n64, out=I64)
+    ms, wall = timed(fwd64, args.steps, args.warmup)
+    value = nch / (ms * 1e-3)
+    achieved = BYTES_PER_CHANNEL["f64"] * nch / (ms * 1e-3) / 1e9
+    log(f"fwd fp64: {ms:.3f} ms/eval, {value:.3e} ch/s, {achieved:.0f} GB/s algorithmic "
+        f"(wall {wall:.2f}s for {args.steps})")
+
+    forms = {}
+    if not args.no_forms:
+        forms["fwd_f64_b1"] = dict(ms=ms, channels_per_s=value, algorithmic_GBps=achieved)
+        # reverse mode (dL/df and dL/dg2), FP64
+        lam = tens(rng.normal(size=s.n_states), torch.float64)
+        gg = torch.zeros(nch, dtype=torch.float64, device=dev)
+        vjp = lambda: E.collision_vjp(plan64, f64, n64, lam, want_f=True, gg2=gg)
+        ms_v, _ = timed(vjp, max(3, args.steps // 4), 1)
+        forms["vjp_f64_b1"] = dict(ms=ms_v, channels_per_s=nch / (ms_v * 1e-3),
+                                   algorithmic_GBps=(VJP_BYTES_PER_CHANNEL["f64"] - 24.0) * nch / (ms_v * 1e-3) / 1e9)
+        forms["fwd_plus_adjoint_f64_b1"] = dict(ms=ms + ms_v, channels_per_s=nch / ((ms + ms_v) * 1e-3))
+        log(f"vjp fp64: {ms_v:.3f} ms")
+        del gg
+        # batched B = 64
+        B = 64
+        F = tens(np.clip(f_np[None, :] * rng.uniform(0.7, 1.3, size=(B, 1)), 0, 1), torch.float64)
+        IB = torch.empty_like(F)
+        msb, _ = timed(lambda: E.collision_integral(plan64, F, n64, out=IB), 2, 1)
+        forms["fwd_f64_b64"] = dict(ms=msb, per_vector_channels_per_s=B * nch / (msb * 1e-3),
+                                    ratio_vs_b1=(B * nch / (msb * 1e-3)) / value)
+        log(f"fwd fp64 B=64: {msb:.3f} ms ({forms['fwd_f64_b64']['ratio_vs_b1']:.2f}x per vector)")
+        del F, IB
+        # transport iteration, FP64
+        vel = tens(s.vel, torch.float64)
+        f0 = tens(synth.fermi_dirac(s.eps, -0.1, 300.0), torch.float64)
+        t1, _ = timed(lambda: E.iterate_transport(plan64, f0, vel, 300.0, n64, tol=0.0, max_iter=1), 1, 1)
+        t6, _ = timed(lambda: E.iterate_transport(plan64, f0, vel, 300.0, n64, tol=0.0, max_iter=6), 1, 0)
+        forms["transport_iter_f64"] = dict(ms_per_iteration=(t6 - t1) / 5.0, ms_setup_plus_one=t1)
+        log(f"transport fp64: {(t6 - t1) / 5:.3f} ms/iteration, setup+1 {t1:.3f} ms")
+        del vel, f0
+
+    plan64.close()
+    del plan64, f64, I64
+    torch.cuda.empty_cache()
+
+    if not args.no_forms:
+        t0 = time.time()
+        plan32 = E.build_channels(s, dtype="f32", device=0)
+        log(f"fp32 plan built ({time.time() - t0:.1f}s)")
+        f32, n32 = tens(f_np, torch.float32), tens(nph_np, torch.float32)
+        I32 = torch.empty_like(f32)
+        ms32, _ = timed(lambda: E.collision_integral(plan32, f32, n32, out=I32), args.steps, args.warmup)
+        forms["fwd_f32_b1"] = dict(ms=ms32, channels_per_s=nch / (ms32 * 1e-3),
+                                   algorithmic_GBps=BYTES_PER_CHANNEL["f32"] * nch / (ms32 * 1e-3) / 1e9)
+        log(f"fwd fp32: {ms32:.3f} ms")
+        fr = f32.clone()
+        msr, _ = timed(lambda: E.rt_step(plan32, fr, n32, 1.0, 4, use_graph=True), 2, 1)
+        forms["rt_step_f32_graph"] = dict(ms_per_step=msr / 4.0, evaluations_per_step=4)
+        log(f"rt step fp32: {msr / 4:.3f} ms/step")
+        plan32.close()
+
+    cpu = None
+    if not args.no_cpu:
+        import copy
+        import oracle
+        n = min(args.cpu_channels, nch)
+        ss = copy.copy(s)
+        ss.ch_i, ss.ch_j, ss.ch_nu, ss.g2 = s.ch_i[:n], s.ch_j[:n], s.ch_nu[:n], s.g2[:n]
+        w0 = time.perf_counter()
+        oracle.collision(ss, f_np, nph_np)
+        dtc = time.perf_counter() - w0
+        cpu = dict(value=n / dtc, unit="channels/s", cores=1, kind="oracle",
+                   sample=f"first {n} of {nch} channels, one FP64 evaluation, sequential C loop "
+                          f"({dtc:.1f} s)")
+        log(f"cpu oracle: {n / dtc:.3e} ch/s on 1 core")
+
+    out = {
+        "metric": "scattering channels/sec (fwd, B=1)",
+        "value": value,
+        "unit": "channels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wname, "n_states": s.n_states, "n_channels": nch,
+                   "entries": 2 * nch, "kgrid": list(s.kgrid), "qgrid": list(s.qgrid),
+                   "modes": s.n_modes, "sigma_eV": s.sigma, "batch": 1},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "cpu_baseline": cpu,
+        "forms": forms,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,223 @@
+/*
+ * ephbte.h -- C ABI of the MI355X e-ph collision-integral library.
+ *
+ * The library evaluates the electron-phonon collision integral I[f](n,k) of
+ * arXiv 2511.03683 (Results, "Collision integral, e-ph coupling matrix, and
+ * scattering channels", Eq. 2) over a precomputed list of scattering
+ * channels, and drives its two consumers: real-time BTE time stepping and the
+ * iterative transport BTE (Results, "BTE for transport and ultrafast
+ * dynamics", Eq. 1).  All arithmetic runs in HIP kernels on gfx950.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Units: energies eV, time fs, temperature K, velocity m/s, |g|^2 eV^2,
+ *   I in 1/fs.  Constants: hbar = 0.6582119569 eV fs, k_B = 8.617333262e-5 eV/K.
+ * States: S electronic states (n,k) inside the energy window.  State s has a
+ *   linear k index state_k[s] = (k0*N1 + k1)*N2 + k2 on the k grid (N0,N1,N2).
+ * Phonons: tables indexed [q][nu] (q-major, q linear on the q grid like k),
+ *   n_modes <= 8.  The tables must be even in q (hw(-q) = hw(q), N(-q) = N(q)),
+ *   as time-reversal symmetry gives; each orientation of a channel uses its own q.
+ * Channel: an unordered state pair {i, j} plus a mode nu, with one |g|^2 value.
+ *   It enters I(i) with partner j and q = k_j - k_i, and I(j) with partner i
+ *   and q = k_i - k_j (Optimized GPU algorithm, step 1: each channel feeds two
+ *   collision-integral elements).  k_j - k_i must be a q-grid vector
+ *   (commensurate grids, Eq. 2 text).
+ * Collision integral (Eq. 2 with Fermi's golden-rule occupation factors):
+ *   I(d) = sum over channels touching d, partner p, mode nu, q = k_p - k_d:
+ *     -(2 pi/hbar)(1/N_q) |g|^2 [ G(e_d - e_p + hw) F_abs + G(e_d - e_p - hw) F_em ]
+ *   F_abs = f_d (1-f_p) N - f_p (1-f_d)(N+1),  F_em = f_d (1-f_p)(N+1) - f_p (1-f_d) N,
+ *   G(x) = exp(-x^2 / (2 sigma^2)) / (sigma sqrt(2 pi)).
+ * Precision: a plan is FP64 (EPHBTE_F64) or FP32 (EPHBTE_F32).  All device
+ *   arrays passed to a plan (f, nph, I, gradients except gg2, x) have the
+ *   plan's type; gg2 and transport outputs are FP64 always.
+ * Batches: f and I hold B vectors of S values each, vector b at
+ *   f + b*ldf (ldf >= S elements).  One phonon table serves all vectors.
+ * Pointers: "host" pointers are read during the call only (the library keeps
+ *   copies); "device" pointers are caller-owned HIP device memory on the
+ *   plan's device, read or written by work enqueued on `stream`.
+ * Streams: `stream` is a hipStream_t passed as void* (0 = null stream).  Work
+ *   is enqueued asynchronously; calls that return host scalars synchronise.
+ * Errors: every call returns a status and never throws.  Arguments are checked
+ *   before any work is enqueued; on error nothing is enqueued and
+ *   ephbte_last_error() (thread-local) describes the failure.
+ * Determinism: no atomics; every reduction has a fixed order, so results are
+ *   bitwise reproducible run to run for a given plan and launch configuration.
+ */
+#ifndef EPHBTE_H
+#define EPHBTE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ephbte_status;
+#define EPHBTE_OK 0
+#define EPHBTE_INVALID_ARGUMENT 1
+#define EPHBTE_UNSUPPORTED_DTYPE 2
+#define EPHBTE_OUT_OF_MEMORY 3
+#define EPHBTE_HIP_ERROR 4
+#define EPHBTE_NOT_CONVERGED 5
+#define EPHBTE_NONFINITE 6
+#define EPHBTE_PLAN_MISMATCH 7
+
+#define EPHBTE_F32 1
+#define EPHBTE_F64 2
+
+typedef struct ephbte_plan_s *ephbte_plan;
+
+/* Problem statement (paper: Eq. 2 and the scattering-channel paragraph that
+ * follows it; energy window of Table 1).  All pointers are HOST pointers. */
+typedef struct {
+    int32_t n_states;          /* S >= 1, S < 2^29                                  */
+    const int32_t *state_k;    /* [S] linear k index of each state                 */
+    const double *eps;         /* [S] state energies (eV)                          */
+    int32_t kgrid[3];          /* electron grid (N0,N1,N2)                         */
+    int32_t qgrid[3];          /* phonon grid; kgrid[a] % qgrid[a] == 0, <= 1024   */
+    int32_t n_modes;           /* 1..8                                             */
+    const double *hw;          /* [Nq][n_modes] phonon energies (eV), >= 0         */
+    int64_t n_channels;        /* >= 0, < 2^30                                     */
+    const int32_t *ch_i;       /* [n_channels] state index, 0 <= i < S             */
+    const int32_t *ch_j;       /* [n_channels] state index, j != i                 */
+    const int8_t *ch_nu;       /* [n_channels] mode, 0 <= nu < n_modes             */
+    const double *g2;          /* [n_channels] |g|^2 (eV^2), finite, >= 0          */
+    double sigma;              /* Gaussian standard deviation (eV), > 0            */
+    double n_q_norm;           /* N_q of Eq. 2 (full q-grid count), > 0            */
+    int32_t dtype;             /* EPHBTE_F32 or EPHBTE_F64                         */
+    int32_t device;            /* HIP device ordinal; -1 = current device          */
+} ephbte_problem;
+
+/* Tuning knobs of a plan (all optional: 0 = library default). */
+typedef struct {
+    int32_t chunk_entries;     /* max destination entries per workgroup chunk      */
+    int32_t block_threads;     /* threads per workgroup: 64, 128, 256, 512         */
+    int32_t xcd_map;           /* 1: contiguous chunk ranges per XCD; 2: plain order */
+    int32_t reserved[5];       /* must be 0                                        */
+} ephbte_tuning;
+
+/*
+ * Build the device channel layout (paper: Optimized GPU algorithm, step 1,
+ * "create the target layer": channels grouped by the collision-integral
+ * element they feed, done once on the host).  Each channel is duplicated into
+ * one entry per destination state, entries are sorted by destination and then
+ * by (partner, mode), and the structure-of-arrays layout is copied to the
+ * device once.  Fails with INVALID_ARGUMENT on: null pointers, indices out of
+ * range, i == j, a pair not commensurate with the q grid, a channel whose
+ * phonon energy is below 1e-6 eV in either orientation (its N diverges),
+ * duplicate (i, j, nu) channels, non-finite or negative hw/g2/eps, sigma or
+ * n_q_norm <= 0.  OUT_OF_MEMORY if device memory runs out.  *out receives a
+ * plan owned by the caller until ephbte_destroy.  Synchronous.
+ */
+ephbte_status ephbte_build_channels(const ephbte_problem *problem, ephbte_plan *out);
+
+/*
+ * Host-only view of the layout ephbte_build_channels would build, for
+ * inspection and tests.  Runs the same validation and sort without touching a
+ * device.  Caller allocates: row_ptr [S+1], entry_partner [2*n_channels],
+ * entry_mode [2*n_channels], entry_channel [2*n_channels] (any may be NULL).
+ * Entry e of destination d (row_ptr[d] <= e < row_ptr[d+1]) has partner
+ * entry_partner[e], mode entry_mode[e] and comes from caller channel
+ * entry_channel[e].
+ */
+ephbte_status ephbte_layout_host(const ephbte_problem *problem, int64_t *row_ptr,
+                                 int32_t *entry_partner, int8_t *entry_mode,
+                                 int32_t *entry_channel);
+
+/*
+ * I[f] for B occupation vectors (Eq. 2; paper: Optimized GPU algorithm, steps
+ * 2 and 3 fused: every workgroup computes the contributions of the entries of
+ * one destination and reduces them, with no atomics).
+ * f:   device [B][ldf], plan dtype, 0 <= f <= 1 expected (not checked).
+ * nph: device [Nq][n_modes], plan dtype: phonon occupations N.
+ * I:   device [B][ldi], plan dtype, written.  I must not alias f.
+ * B >= 1; ldf, ldi >= S.
+ */
+ephbte_status ephbte_collision_integral(ephbte_plan plan, int32_t batch, const void *f,
+                                        int64_t ldf, const void *nph, void *I, int64_t ldi,
+                                        void *stream);
+
+/*
+ * Reverse mode of Eq. 2: given gI = dL/dI (device [B][ldg]), writes
+ * gf = dL/df (device [B][ldgf], plan dtype; NULL to skip) and
+ * gg2 = dL/d|g|^2 summed over the batch (device FP64 [n_channels] in the
+ * caller's channel order; NULL to skip).  accumulate_gg2 != 0 adds to gg2
+ * instead of overwriting it.  No atomics: dL/df is a per-destination
+ * reduction, each dL/d|g|^2 is written by the channel's first entry.
+ */
+ephbte_status ephbte_collision_vjp(ephbte_plan plan, int32_t batch, const void *f,
+                                   int64_t ldf, const void *nph, const void *gI, int64_t ldg,
+                                   void *gf, int64_t ldgf, double *gg2, int32_t accumulate_gg2,
+                                   void *stream);
+
+/*
+ * Real-time BTE without field, df/dt = I[f] (Eq. 1 with F = 0): advances f
+ * (device [B][ldf], in place) by n_steps classical RK4 steps of dt_fs.  The
+ * stage updates are fused into the collision kernels (four launches per
+ * step).  use_graph != 0 captures the step sequence in a HIP graph on the
+ * first call and replays it (the graph is cached per (f, nph, dt, B, stream)).
+ */
+ephbte_status ephbte_rt_step(ephbte_plan plan, int32_t batch, void *f, int64_t ldf,
+                             const void *nph, double dt_fs, int32_t n_steps, int32_t use_graph,
+                             void *stream);
+
+/*
+ * Exact discrete adjoint of n_steps RK4 steps from f0 (device [S], B = 1):
+ * given gfT = dL/df(T) (device [S]), writes gf0 = dL/df(0) (device [S], may be
+ * NULL) and gg2 = dL/d|g|^2 (device FP64 [n_channels], caller order; may be
+ * NULL; accumulate_gg2 != 0 adds).  Forward states are checkpointed every
+ * checkpoint_every steps and recomputed segment by segment.
+ */
+ephbte_status ephbte_rt_adjoint(ephbte_plan plan, const void *f0, const void *nph,
+                                double dt_fs, int32_t n_steps, int32_t checkpoint_every,
+                                const void *gfT, void *gf0, double *gg2,
+                                int32_t accumulate_gg2, void *stream);
+
+/*
+ * Iterative transport BTE (Eq. 1 at steady state with a weak field, I
+ * linearised at f0): with J = dI/df at f0 = -diag(1/tau) + W,
+ *   x_d = tau_d ( v_d df0/de + sum_p W_dp x_p ),  df0/de = -f0 (1-f0) / (k_B T),
+ * iterated from the relaxation-time start x = tau v df0/de for the three field
+ * directions, and the mobility mu_ab = -e sum_d v_a x_b / sum_d f0.
+ * f0:  device [S] plan dtype, Fermi-Dirac occupations at temperature T_K.
+ * vel: device [S][3] plan dtype (m/s).
+ * nph: device [Nq][n_modes] plan dtype.
+ * x_out: device [S][3] plan dtype (may be NULL), final iterate (fs m/s / eV).
+ * mobility_cm2_per_Vs: host double[9], row-major mu_ab.
+ * Stops when max|mu_new - mu_old| / max|mu_new| <= tol; NOT_CONVERGED after
+ * max_iter iterations, with the last iterate and mobility written.  *iters and
+ * *resid (host, may be NULL) receive the iteration count and last relative change.
+ * Synchronises on `stream` once per iteration (9 scalars device to host).
+ */
+ephbte_status ephbte_iterate_transport(ephbte_plan plan, const void *f0, const void *vel,
+                                       double T_K, const void *nph, double tol, int32_t max_iter,
+                                       void *x_out, double *mobility_cm2_per_Vs, int32_t *iters,
+                                       double *resid, void *stream);
+
+/* Replace |g|^2 of every channel: g2 is device FP64 [n_channels] in the
+ * caller's channel order (finite, >= 0 expected; not checked). */
+ephbte_status ephbte_update_g2(ephbte_plan plan, const double *g2, void *stream);
+
+/* Re-split the layout into workgroup chunks for the given tuning (no data is
+ * re-sorted).  Synchronous. */
+ephbte_status ephbte_set_tuning(ephbte_plan plan, const ephbte_tuning *tuning);
+
+/* Time candidate tunings of the B-vector collision integral on this plan with
+ * HIP events and keep the fastest; writes the chosen tuning to *chosen (may be
+ * NULL).  Uses the plan's own scratch occupations.  Synchronous. */
+ephbte_status ephbte_autotune(ephbte_plan plan, int32_t batch, ephbte_tuning *chosen);
+
+/* Plan facts: out[0]=S, [1]=n_channels, [2]=entries, [3]=chunks, [4]=dtype,
+ * [5]=device, [6]=device bytes held, [7]=chunk_entries, [8]=block_threads. */
+ephbte_status ephbte_plan_info(ephbte_plan plan, int64_t out[9]);
+
+int64_t ephbte_plan_bytes(ephbte_plan plan);
+void ephbte_destroy(ephbte_plan plan);
+const char *ephbte_status_string(ephbte_status status);
+const char *ephbte_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EPHBTE_H */

@@ -54,6 +54,8 @@ def _lib():
         lib.orc_collision_vjp.restype = None
         lib.orc_transport_coeffs.argtypes = common + [P, P, P, P]
         lib.orc_transport_coeffs.restype = None
+        lib.orc_collision_inout.argtypes = common + [P, P, P]
+        lib.orc_collision_inout.restype = None
         _LIB = lib
     return _LIB
 
@@ -104,6 +106,15 @@ def collision(sys, f, nph, g2=None, mask=None, args=None):
     m = None if mask is None else _c(mask, np.uint8)
     _lib().orc_collision(*a.common(), _ptr(f), _ptr(m), _ptr(I))
     return I
+
+
+def collision_inout(sys, f, nph, g2=None):
+    """(in-scattering, out-scattering) rates [S]; I = in - out."""
+    a = _Args(sys, nph, g2)
+    f = _c(f, np.float64)
+    rin, rout = np.zeros(a.S), np.zeros(a.S)
+    _lib().orc_collision_inout(*a.common(), _ptr(f), _ptr(rin), _ptr(rout))
+    return rin, rout
 
 
 def collision_batched(sys, F, nph, g2=None):
@@ -252,12 +263,13 @@ def transport_apply_W(sys, Wij, Wji, x):
     return out
 
 
-def transport_solve(sys, f0, vel, T, nph, tol=1e-8, max_iter=200, g2=None):
+def transport_solve(sys, f0, vel, T, nph, tol=1e-8, max_iter=200, g2=None, stop_on_tol=True):
     """Iterate x_d = tau_d (v_d df0/de + sum_p W_dp x_p) from the RTA start
     until the mobility changes by at most tol (relative, max norm).
     Returns dict(mu [3,3] cm^2/Vs, x [S,3], iters, converged, history)."""
     tau_inv, Wij, Wji = transport_coeffs(sys, f0, nph, g2)
-    tau = 1.0 / tau_inv
+    # a state without any scattering (tau_inv = 0) is left out: x_d = 0
+    tau = np.where(tau_inv > 0, 1.0 / np.where(tau_inv > 0, tau_inv, 1.0), 0.0)
     b = np.asarray(vel) * dfde_fd(f0, T)[:, None]
     x = tau[:, None] * b
     mu = mobility_cm2(vel, x, f0)
@@ -268,6 +280,6 @@ def transport_solve(sys, f0, vel, T, nph, tol=1e-8, max_iter=200, g2=None):
         rel = np.abs(mu_new - mu).max() / np.abs(mu_new).max()
         mu = mu_new
         hist.append(mu)
-        if rel <= tol:
+        if stop_on_tol and rel <= tol:
             return dict(mu=mu, x=x, iters=it, converged=True, history=hist, resid=rel)
     return dict(mu=mu, x=x, iters=max_iter, converged=False, history=hist, resid=rel)

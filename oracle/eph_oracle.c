@@ -205,3 +205,33 @@ void orc_transport_coeffs(int n_states, const int32_t *state_k, const double *ep
         W_ji[c] = b_fi;
     }
 }
+
+/*
+ * In- and out-scattering rates of every state, from the same terms as
+ * orc_collision: T(d,p) = In - Out with
+ *   Out = P g2 f_d (1 - f_p) [G(e_d - e_p + hw) N + G(e_d - e_p - hw) (N + 1)]
+ *   In  = P g2 f_p (1 - f_d) [G(e_d - e_p + hw) (N + 1) + G(e_d - e_p - hw) N]
+ * (the gross rates used to judge cancellation near equilibrium).
+ */
+void orc_collision_inout(int n_states, const int32_t *state_k, const double *eps,
+                         const int32_t *kgrid, const int32_t *qgrid, int n_modes,
+                         const double *hw, const double *nph, double sigma, double n_q_norm,
+                         int64_t n_ch, const int32_t *ch_i, const int32_t *ch_j,
+                         const int8_t *ch_nu, const double *g2, const double *f,
+                         double *rate_in, double *rate_out) {
+    orc_sys s = make_sys(n_states, state_k, eps, kgrid, qgrid, n_modes, hw, nph, sigma, n_q_norm);
+    memset(rate_in, 0, sizeof(double) * (size_t)n_states);
+    memset(rate_out, 0, sizeof(double) * (size_t)n_states);
+    double P = 2.0 * ORC_PI / ORC_HBAR_EV_FS / n_q_norm;
+    for (int64_t c = 0; c < n_ch; ++c) {
+        for (int side = 0; side < 2; ++side) {
+            int d = side ? ch_j[c] : ch_i[c], p = side ? ch_i[c] : ch_j[c], nu = ch_nu[c];
+            int q = q_index(&s, d, p);
+            double w = hw[(long)q * n_modes + nu], N = nph[(long)q * n_modes + nu];
+            double de = eps[d] - eps[p];
+            double Ga = gauss(de + w, sigma), Ge = gauss(de - w, sigma);
+            rate_out[d] += P * g2[c] * f[d] * (1.0 - f[p]) * (Ga * N + Ge * (N + 1.0));
+            rate_in[d] += P * g2[c] * f[p] * (1.0 - f[d]) * (Ga * (N + 1.0) + Ge * N);
+        }
+    }
+}

@@ -1,0 +1,375 @@
+"""ctypes binding of libephbte.so (include/ephbte.h).
+
+Argument marshalling only: every function below checks tensor placement and
+shapes, converts them to device pointers and the caller's current HIP stream,
+and calls the C entry point of the same name.  There is no fallback: if the
+HIP library is missing or a tensor is not on the plan's GPU, an exception is
+raised.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libephbte.so")
+
+OK, INVALID_ARGUMENT, UNSUPPORTED_DTYPE, OUT_OF_MEMORY = 0, 1, 2, 3
+HIP_ERROR, NOT_CONVERGED, NONFINITE, PLAN_MISMATCH = 4, 5, 6, 7
+F32, F64 = 1, 2
+
+_P = ctypes.c_void_p
+
+
+class EphbteError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)} ({status}): {detail}")
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("n_states", ctypes.c_int32), ("state_k", _P), ("eps", _P),
+                ("kgrid", ctypes.c_int32 * 3), ("qgrid", ctypes.c_int32 * 3),
+                ("n_modes", ctypes.c_int32), ("hw", _P), ("n_channels", ctypes.c_int64),
+                ("ch_i", _P), ("ch_j", _P), ("ch_nu", _P), ("g2", _P),
+                ("sigma", ctypes.c_double), ("n_q_norm", ctypes.c_double),
+                ("dtype", ctypes.c_int32), ("device", ctypes.c_int32)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("chunk_entries", ctypes.c_int32), ("block_threads", ctypes.c_int32),
+                ("xcd_map", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+
+
+_LIB = None
+
+SYMBOLS = {
+    "ephbte_build_channels": ([ctypes.POINTER(Problem), ctypes.POINTER(_P)], ctypes.c_int32),
+    "ephbte_layout_host": ([ctypes.POINTER(Problem), _P, _P, _P, _P], ctypes.c_int32),
+    "ephbte_collision_integral": ([_P, ctypes.c_int32, _P, ctypes.c_int64, _P, _P,
+                                   ctypes.c_int64, _P], ctypes.c_int32),
+    "ephbte_collision_vjp": ([_P, ctypes.c_int32, _P, ctypes.c_int64, _P, _P, ctypes.c_int64,
+                              _P, ctypes.c_int64, _P, ctypes.c_int32, _P], ctypes.c_int32),
+    "ephbte_rt_step": ([_P, ctypes.c_int32, _P, ctypes.c_int64, _P, ctypes.c_double,
+                        ctypes.c_int32, ctypes.c_int32, _P], ctypes.c_int32),
+    "ephbte_rt_adjoint": ([_P, _P, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, _P, _P,
+                           _P, ctypes.c_int32, _P], ctypes.c_int32),
+    "ephbte_iterate_transport": ([_P, _P, _P, ctypes.c_double, _P, ctypes.c_double,
+                                  ctypes.c_int32, _P, _P, _P, _P, _P], ctypes.c_int32),
+    "ephbte_update_g2": ([_P, _P, _P], ctypes.c_int32),
+    "ephbte_set_tuning": ([_P, ctypes.POINTER(Tuning)], ctypes.c_int32),
+    "ephbte_autotune": ([_P, ctypes.c_int32, ctypes.POINTER(Tuning)], ctypes.c_int32),
+    "ephbte_plan_info": ([_P, _P], ctypes.c_int32),
+    "ephbte_plan_bytes": ([_P], ctypes.c_int64),
+    "ephbte_destroy": ([_P], None),
+    "ephbte_status_string": ([ctypes.c_int32], ctypes.c_char_p),
+    "ephbte_last_error": ([], ctypes.c_char_p),
+}
+
+
+def load_library(path: Optional[str] = None):
+    """Load libephbte.so (built by build_lib.py); raises if it is missing."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build the HIP library first "
+                          "(python -m paper_2511_03683_amd.build_lib)")
+    lib = ctypes.CDLL(path)
+    for name, (args, res) in SYMBOLS.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _LIB = lib
+    return lib
+
+
+def status_string(status: int) -> str:
+    return load_library().ephbte_status_string(int(status)).decode()
+
+
+def last_error() -> str:
+    return load_library().ephbte_last_error().decode()
+
+
+def _check(status: int, where: str, allow=()):
+    if status != OK and status not in allow:
+        raise EphbteError(status, where, last_error())
+    return status
+
+
+# ---------------------------------------------------------------- helpers
+def _np(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _problem(system, dtype: int, device: int):
+    """ctypes Problem plus the numpy arrays it points into (kept alive)."""
+    keep = dict(state_k=_np(system.state_k, np.int32), eps=_np(system.eps, np.float64),
+                hw=_np(system.hw, np.float64), ch_i=_np(system.ch_i, np.int32),
+                ch_j=_np(system.ch_j, np.int32), ch_nu=_np(system.ch_nu, np.int8),
+                g2=_np(system.g2, np.float64))
+    pr = Problem()
+    pr.n_states = int(keep["eps"].size)
+    pr.state_k = keep["state_k"].ctypes.data
+    pr.eps = keep["eps"].ctypes.data
+    pr.kgrid[:] = [int(x) for x in system.kgrid]
+    pr.qgrid[:] = [int(x) for x in system.qgrid]
+    pr.n_modes = int(system.n_modes)
+    pr.hw = keep["hw"].ctypes.data
+    pr.n_channels = int(keep["g2"].size)
+    pr.ch_i = keep["ch_i"].ctypes.data
+    pr.ch_j = keep["ch_j"].ctypes.data
+    pr.ch_nu = keep["ch_nu"].ctypes.data
+    pr.g2 = keep["g2"].ctypes.data
+    pr.sigma = float(system.sigma)
+    pr.n_q_norm = float(system.n_q_norm)
+    pr.dtype = int(dtype)
+    pr.device = int(device)
+    return pr, keep
+
+
+def _dtype_code(dtype) -> int:
+    if dtype in (F32, "f32", "float32", np.float32):
+        return F32
+    if dtype in (F64, "f64", "float64", np.float64):
+        return F64
+    try:
+        import torch
+        if dtype == torch.float32:
+            return F32
+        if dtype == torch.float64:
+            return F64
+    except ImportError:
+        pass
+    raise ValueError(f"unsupported dtype {dtype!r}")
+
+
+class Plan:
+    """Owns an ephbte_plan handle (device channel layout)."""
+
+    def __init__(self, handle, system, dtype: int, device: int):
+        self.handle = ctypes.c_void_p(handle)
+        self.n_states = int(system.n_states)
+        self.n_channels = int(system.n_channels)
+        self.n_modes = int(system.n_modes)
+        self.n_q = int(np.prod(system.qgrid))
+        self.dtype = dtype
+        self.device = device
+
+    @property
+    def torch_dtype(self):
+        import torch
+        return torch.float64 if self.dtype == F64 else torch.float32
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            load_library().ephbte_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _stream(device):
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _dev_tensor(plan: Plan, t, name, shape_last=None, dtype=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.device.index != plan.device:
+        raise ValueError(f"{name} is on {t.device}, the plan is on cuda:{plan.device}")
+    want = dtype or plan.torch_dtype
+    if t.dtype != want:
+        raise TypeError(f"{name} must be {want}, got {t.dtype}")
+    if shape_last is not None and t.shape[-1] != shape_last:
+        raise ValueError(f"{name} must have last dimension {shape_last}, got {tuple(t.shape)}")
+    if t.stride(-1) != 1:
+        raise ValueError(f"{name} must have unit stride in its last dimension")
+    return t
+
+
+def _batch(plan, t, name):
+    """(B, ld) of a [S] or [B, S] tensor with unit inner stride."""
+    _dev_tensor(plan, t, name, shape_last=plan.n_states)
+    if t.dim() == 1:
+        return 1, plan.n_states
+    if t.dim() == 2:
+        return int(t.shape[0]), int(t.stride(0)) if t.shape[0] > 1 else plan.n_states
+    raise ValueError(f"{name} must be [S] or [B, S]")
+
+
+# ---------------------------------------------------------------- entry points
+def build_channels(system, dtype="f64", device: Optional[int] = None) -> Plan:
+    """Build the device channel layout of a problem (see ephbte_build_channels)."""
+    lib = load_library()
+    code = _dtype_code(dtype)
+    if device is None:
+        import torch
+        device = torch.cuda.current_device()
+    pr, keep = _problem(system, code, device)
+    h = ctypes.c_void_p()
+    _check(lib.ephbte_build_channels(ctypes.byref(pr), ctypes.byref(h)), "build_channels")
+    del keep
+    return Plan(h.value, system, code, device)
+
+
+def layout_host(system):
+    """Host-only layout view: (row_ptr, partner, mode, channel) numpy arrays."""
+    lib = load_library()
+    pr, keep = _problem(system, F64, -1)
+    S, E = int(system.n_states), 2 * int(system.n_channels)
+    row_ptr = np.zeros(S + 1, np.int64)
+    partner = np.zeros(E, np.int32)
+    mode = np.zeros(E, np.int8)
+    chan = np.zeros(E, np.int32)
+    _check(lib.ephbte_layout_host(ctypes.byref(pr), row_ptr.ctypes.data, partner.ctypes.data,
+                                  mode.ctypes.data, chan.ctypes.data), "layout_host")
+    del keep
+    return row_ptr, partner, mode, chan
+
+
+def collision_integral(plan: Plan, f, nph, out=None):
+    """I[f] for f [S] or [B, S]; nph [Nq, n_modes] (device tensors)."""
+    import torch
+    B, ldf = _batch(plan, f, "f")
+    _dev_tensor(plan, nph, "nph")
+    if nph.numel() != plan.n_q * plan.n_modes or not nph.is_contiguous():
+        raise ValueError("nph must be a contiguous [Nq, n_modes] tensor")
+    if out is None:
+        out = torch.empty((B, plan.n_states) if f.dim() == 2 else (plan.n_states,),
+                          dtype=plan.torch_dtype, device=f.device)
+    Bo, ldi = _batch(plan, out, "out")
+    if Bo != B:
+        raise ValueError("out batch differs from f batch")
+    _check(load_library().ephbte_collision_integral(plan.handle, B, f.data_ptr(), ldf,
+                                                    nph.data_ptr(), out.data_ptr(), ldi,
+                                                    _stream(f.device)), "collision_integral")
+    return out
+
+
+def collision_vjp(plan: Plan, f, nph, gI, want_f=True, gg2=None, accumulate=False):
+    """(dL/df, dL/d|g|^2) given gI = dL/dI.  gg2 (FP64 [n_channels]) is
+    allocated when None and want_g2 is implied by passing gg2=True."""
+    import torch
+    B, ldf = _batch(plan, f, "f")
+    Bg, ldg = _batch(plan, gI, "gI")
+    if Bg != B:
+        raise ValueError("gI batch differs from f batch")
+    _dev_tensor(plan, nph, "nph")
+    gf = None
+    if want_f:
+        gf = torch.empty_like(f, memory_format=torch.contiguous_format)
+    if gg2 is True:
+        gg2 = torch.zeros(plan.n_channels, dtype=torch.float64, device=f.device)
+    if gg2 is not None:
+        _dev_tensor(plan, gg2, "gg2", dtype=torch.float64)
+        if gg2.numel() != plan.n_channels or not gg2.is_contiguous():
+            raise ValueError("gg2 must be a contiguous FP64 [n_channels] tensor")
+    ldgf = plan.n_states
+    _check(load_library().ephbte_collision_vjp(
+        plan.handle, B, f.data_ptr(), ldf, nph.data_ptr(), gI.data_ptr(), ldg,
+        gf.data_ptr() if gf is not None else None, ldgf,
+        gg2.data_ptr() if gg2 is not None else None, 1 if accumulate else 0,
+        _stream(f.device)), "collision_vjp")
+    return gf, gg2
+
+
+def rt_step(plan: Plan, f, nph, dt_fs: float, n_steps: int, use_graph: bool = False):
+    """Advance f ([S] or [B, S], in place) by n_steps RK4 steps."""
+    B, ldf = _batch(plan, f, "f")
+    _dev_tensor(plan, nph, "nph")
+    _check(load_library().ephbte_rt_step(plan.handle, B, f.data_ptr(), ldf, nph.data_ptr(),
+                                         float(dt_fs), int(n_steps), 1 if use_graph else 0,
+                                         _stream(f.device)), "rt_step")
+    return f
+
+
+def rt_adjoint(plan: Plan, f0, nph, dt_fs: float, n_steps: int, checkpoint_every: int, gfT,
+               want_f=True, gg2=None, accumulate=False):
+    """(dL/df0, dL/d|g|^2) through n_steps RK4 steps from f0 given dL/df(T)."""
+    import torch
+    _dev_tensor(plan, f0, "f0", shape_last=plan.n_states)
+    _dev_tensor(plan, gfT, "gfT", shape_last=plan.n_states)
+    if f0.dim() != 1 or gfT.dim() != 1:
+        raise ValueError("rt_adjoint takes one vector (B = 1)")
+    gf0 = torch.empty_like(f0) if want_f else None
+    if gg2 is True:
+        gg2 = torch.zeros(plan.n_channels, dtype=torch.float64, device=f0.device)
+    if gg2 is not None:
+        _dev_tensor(plan, gg2, "gg2", dtype=torch.float64)
+    _check(load_library().ephbte_rt_adjoint(
+        plan.handle, f0.data_ptr(), nph.data_ptr(), float(dt_fs), int(n_steps),
+        int(checkpoint_every), gfT.data_ptr(), gf0.data_ptr() if gf0 is not None else None,
+        gg2.data_ptr() if gg2 is not None else None, 1 if accumulate else 0,
+        _stream(f0.device)), "rt_adjoint")
+    return gf0, gg2
+
+
+def iterate_transport(plan: Plan, f0, vel, T_K: float, nph, tol: float = 1e-8,
+                      max_iter: int = 100, want_x: bool = False, raise_on_nonconv=False):
+    """Mobility (cm^2/Vs, 3x3) of the linearised BTE; see ephbte_iterate_transport."""
+    import torch
+    _dev_tensor(plan, f0, "f0", shape_last=plan.n_states)
+    _dev_tensor(plan, vel, "vel", shape_last=3)
+    if vel.shape[0] != plan.n_states or not vel.is_contiguous():
+        raise ValueError("vel must be a contiguous [S, 3] tensor")
+    x = torch.empty((plan.n_states, 3), dtype=plan.torch_dtype, device=f0.device) if want_x else None
+    mob = np.zeros(9)
+    iters = ctypes.c_int32(0)
+    resid = ctypes.c_double(0.0)
+    st = load_library().ephbte_iterate_transport(
+        plan.handle, f0.data_ptr(), vel.data_ptr(), float(T_K), nph.data_ptr(), float(tol),
+        int(max_iter), x.data_ptr() if x is not None else None, mob.ctypes.data,
+        ctypes.byref(iters), ctypes.byref(resid), _stream(f0.device))
+    _check(st, "iterate_transport", allow=() if raise_on_nonconv else (NOT_CONVERGED,))
+    return dict(mu=mob.reshape(3, 3), iters=int(iters.value), resid=float(resid.value),
+                converged=(st == OK), x=x)
+
+
+def update_g2(plan: Plan, g2):
+    """Replace every channel's |g|^2 (FP64 device tensor in caller order)."""
+    import torch
+    _dev_tensor(plan, g2, "g2", dtype=torch.float64)
+    if g2.numel() != plan.n_channels or not g2.is_contiguous():
+        raise ValueError("g2 must be a contiguous FP64 [n_channels] tensor")
+    _check(load_library().ephbte_update_g2(plan.handle, g2.data_ptr(), _stream(g2.device)),
+           "update_g2")
+
+
+def set_tuning(plan: Plan, chunk_entries=0, block_threads=0, xcd_map=0):
+    t = Tuning()
+    t.chunk_entries, t.block_threads, t.xcd_map = int(chunk_entries), int(block_threads), int(xcd_map)
+    _check(load_library().ephbte_set_tuning(plan.handle, ctypes.byref(t)), "set_tuning")
+
+
+def autotune(plan: Plan, batch: int = 1) -> dict:
+    t = Tuning()
+    _check(load_library().ephbte_autotune(plan.handle, int(batch), ctypes.byref(t)), "autotune")
+    return dict(chunk_entries=t.chunk_entries, block_threads=t.block_threads, xcd_map=t.xcd_map)
+
+
+def plan_info(plan: Plan) -> dict:
+    out = np.zeros(9, np.int64)
+    _check(load_library().ephbte_plan_info(plan.handle, out.ctypes.data), "plan_info")
+    keys = ["n_states", "n_channels", "entries", "chunks", "dtype", "device", "bytes",
+            "chunk_entries", "block_threads"]
+    return {k: int(v) for k, v in zip(keys, out)}
+
+
+def plan_bytes(plan: Plan) -> int:
+    return int(load_library().ephbte_plan_bytes(plan.handle))
+
+
+def destroy(plan: Plan) -> None:
+    plan.close()

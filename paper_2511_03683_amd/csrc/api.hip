@@ -1,0 +1,1083 @@
+// C ABI of the e-ph collision-integral library (declared in include/ephbte.h).
+//
+// A plan owns the device copy of the channel layout and every workspace the
+// drivers need.  Entry points validate their arguments before enqueuing any
+// work, run on the caller's stream and report failures through a status code
+// plus a thread-local message.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ephbte.h"
+#include "kernels.hpp"
+#include "layout.hpp"
+
+namespace ephbte {
+
+static thread_local std::string g_last_error;
+
+static ephbte_status fail(ephbte_status s, const std::string &m) {
+    g_last_error = m;
+    return s;
+}
+
+struct HipError {
+    hipError_t e;
+    const char *where;
+};
+
+static void hip_check(hipError_t e, const char *where) {
+    if (e != hipSuccess) throw HipError{e, where};
+}
+#define HIPC(x) hip_check((x), #x)
+
+static constexpr double kHbar = 0.6582119569;     // eV fs
+static constexpr double kKb = 8.617333262e-5;     // eV / K
+static constexpr double kPi = 3.14159265358979323846;
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+struct GraphEntry {
+    const void *f, *nph;
+    int64_t ldf;
+    int B, steps;
+    double dt;
+    hipStream_t stream;
+    int64_t ws_gen;
+    hipGraphExec_t exec;
+};
+
+}  // namespace ephbte
+
+using namespace ephbte;
+
+struct ephbte_plan_s {
+    int device = 0;
+    int dtype = EPHBTE_F64;
+    int S = 0, nm = 0;
+    int64_t nch = 0, E = 0;
+    int nq[3] = {0, 0, 0};
+    double sigma = 0, nqnorm = 0;
+    std::vector<int64_t> row_ptr;   // host copy for re-chunking
+    // layout (device)
+    uint32_t *pnu = nullptr;
+    void *g2 = nullptr;
+    void *st = nullptr;
+    void *hw = nullptr;
+    int32_t *ent_chan = nullptr;
+    // chunks (device)
+    int64_t *chunk_beg = nullptr;
+    int32_t *chunk_dest = nullptr;
+    int32_t *dest_chunk = nullptr;
+    int64_t n_chunks = 0;
+    bool fused = true;
+    int chunk_entries = 0;
+    int block_threads = 256;
+    bool xcd_map = true;
+    // workspaces, grown on demand
+    DevBuf part, rk_ua, rk_ub, rk_acc;
+    DevBuf tr_W, tr_tau_inv, tr_tau, tr_rhs, tr_xa, tr_xb, tr_part, tr_red, tr_red2;
+    DevBuf adj_ck, adj_U, adj_la, adj_lb, adj_acc, adj_g, adj_f;
+    double *host_red = nullptr;   // pinned
+    hipStream_t own_stream = nullptr;
+    hipEvent_t ev_a = nullptr, ev_b = nullptr;
+    std::vector<GraphEntry> graphs;
+    int64_t ws_gen = 0;   // bumped whenever a workspace moves
+    size_t layout_bytes = 0;
+
+    size_t bytes() const {
+        size_t b = layout_bytes;
+        const DevBuf *w[] = {&part,  &rk_ua, &rk_ub, &rk_acc, &tr_W,  &tr_tau_inv, &tr_tau,
+                             &tr_rhs, &tr_xa, &tr_xb, &tr_part, &tr_red, &tr_red2, &adj_ck,
+                             &adj_U, &adj_la, &adj_lb, &adj_acc, &adj_g, &adj_f};
+        for (auto *x : w) b += x->bytes;
+        return b;
+    }
+};
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) HIPC(hipSetDevice(dev));
+    }
+    ~DeviceGuard() {
+        int cur;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+void dfree(void *&p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+template <typename P> void dalloc(P *&p, size_t bytes, size_t *acc) {
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, bytes ? bytes : 1);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw std::bad_alloc();
+    }
+    p = static_cast<P *>(q);
+    if (acc) *acc += bytes;
+}
+
+// Grows a workspace; every reallocation bumps *gen so that HIP graphs that
+// captured the old address are re-captured.
+void ensure(DevBuf &b, size_t bytes, int64_t *gen) {
+    if (b.bytes >= bytes && b.p) return;
+    ++*gen;
+    dfree(b.p);
+    b.bytes = 0;
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, bytes ? bytes : 1);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw std::bad_alloc();
+    }
+    b.p = q;
+    b.bytes = bytes;
+}
+
+void free_graphs(ephbte_plan P) {
+    for (auto &g : P->graphs) (void)hipGraphExecDestroy(g.exec);
+    P->graphs.clear();
+}
+
+void free_plan(ephbte_plan P) {
+    if (!P) return;
+    (void)hipSetDevice(P->device);
+    free_graphs(P);
+    void **ptrs[] = {(void **)&P->pnu,       (void **)&P->g2,         (void **)&P->st,
+                     (void **)&P->hw,        (void **)&P->ent_chan,   (void **)&P->chunk_beg,
+                     (void **)&P->chunk_dest, (void **)&P->dest_chunk};
+    for (auto pp : ptrs) dfree(*pp);
+    DevBuf *w[] = {&P->part,   &P->rk_ua,  &P->rk_ub,   &P->rk_acc, &P->tr_W,   &P->tr_tau_inv,
+                   &P->tr_tau, &P->tr_rhs, &P->tr_xa,   &P->tr_xb,  &P->tr_part, &P->tr_red,
+                   &P->tr_red2, &P->adj_ck, &P->adj_U,  &P->adj_la, &P->adj_lb, &P->adj_acc,
+                   &P->adj_g,  &P->adj_f};
+    for (auto *b : w) dfree(b->p);
+    if (P->host_red) (void)hipHostFree(P->host_red);
+    if (P->ev_a) (void)hipEventDestroy(P->ev_a);
+    if (P->ev_b) (void)hipEventDestroy(P->ev_b);
+    if (P->own_stream) (void)hipStreamDestroy(P->own_stream);
+    delete P;
+}
+
+int64_t grid_x(ephbte_plan P) { return P->xcd_map ? 8 * ((P->n_chunks + 7) / 8) : P->n_chunks; }
+
+void upload_chunks(ephbte_plan P, int64_t chunk_entries) {
+    ChunkTable t = make_chunks(P->row_ptr, chunk_entries);
+    free_graphs(P);
+    dfree(reinterpret_cast<void *&>(P->chunk_beg));
+    dfree(reinterpret_cast<void *&>(P->chunk_dest));
+    dfree(reinterpret_cast<void *&>(P->dest_chunk));
+    size_t dummy = 0;
+    dalloc(P->chunk_beg, t.chunk_beg.size() * sizeof(int64_t), &dummy);
+    dalloc(P->chunk_dest, t.chunk_dest.size() * sizeof(int32_t), &dummy);
+    dalloc(P->dest_chunk, t.dest_chunk.size() * sizeof(int32_t), &dummy);
+    HIPC(hipMemcpy(P->chunk_beg, t.chunk_beg.data(), t.chunk_beg.size() * sizeof(int64_t),
+                   hipMemcpyHostToDevice));
+    HIPC(hipMemcpy(P->chunk_dest, t.chunk_dest.data(), t.chunk_dest.size() * sizeof(int32_t),
+                   hipMemcpyHostToDevice));
+    HIPC(hipMemcpy(P->dest_chunk, t.dest_chunk.data(), t.dest_chunk.size() * sizeof(int32_t),
+                   hipMemcpyHostToDevice));
+    P->n_chunks = t.n_chunks;
+    P->fused = t.one_per_dest;
+    P->chunk_entries = static_cast<int>(std::min<int64_t>(chunk_entries, INT32_MAX));
+}
+
+template <typename T> Tables<T> tables(ephbte_plan P, const void *nph) {
+    Tables<T> t;
+    t.pnu = P->pnu;
+    t.g2 = static_cast<const T *>(P->g2);
+    t.st = static_cast<const StateRec<T> *>(P->st);
+    t.hw = static_cast<const T *>(P->hw);
+    t.nph = static_cast<const T *>(nph);
+    t.chunk_beg = P->chunk_beg;
+    t.chunk_dest = P->chunk_dest;
+    t.dest_chunk = P->dest_chunk;
+    t.ent_chan = P->ent_chan;
+    t.n_chunks = P->n_chunks;
+    t.xcd_m = P->xcd_map ? (P->n_chunks + 7) / 8 : 0;
+    t.S = P->S;
+    t.nm = P->nm;
+    t.nq0 = P->nq[0];
+    t.nq1 = P->nq[1];
+    t.nq2 = P->nq[2];
+    const double s = P->sigma;
+    if (sizeof(T) == 8) t.mc = static_cast<T>(-1.0 / (2.0 * s * s));
+    else t.mc = static_cast<T>(-1.4426950408889634 / (2.0 * s * s));
+    t.K = static_cast<T>(2.0 * kPi / (kHbar * P->nqnorm) / (s * std::sqrt(2.0 * kPi)));
+    return t;
+}
+
+template <typename T> Epi<T> epi_store(T *out, int64_t ld) {
+    Epi<T> e{};
+    e.mode = EPI_STORE;
+    e.out = out;
+    e.ld_out = ld;
+    return e;
+}
+
+// Enqueue I[f] for B vectors with epilogue E (no allocation inside; the
+// caller ensured P->part is large enough).
+template <typename T>
+void enqueue_forward(ephbte_plan P, int B, const T *f, int64_t ldf, const void *nph,
+                     const Epi<T> &E, hipStream_t s) {
+    Tables<T> t = tables<T>(P, nph);
+    dim3 grid(static_cast<unsigned>(grid_x(P)), B);
+    dim3 block(P->block_threads);
+    if (P->fused) {
+        hipLaunchKernelGGL((k_collision<T, true>), grid, block, 0, s, t, f, ldf, (T *)nullptr, E);
+    } else {
+        T *part = static_cast<T *>(P->part.p);
+        hipLaunchKernelGGL((k_collision<T, false>), grid, block, 0, s, t, f, ldf, part, E);
+        dim3 g2((P->S + 255) / 256, B);
+        hipLaunchKernelGGL((k_collision_finish<T>), g2, dim3(256), 0, s, t, f, ldf,
+                           (const T *)part, E);
+    }
+    HIPC(hipGetLastError());
+}
+
+template <typename T> void ensure_part(ephbte_plan P, int B, int per_chunk) {
+    if (!P->fused) ensure(P->part, sizeof(T) * per_chunk * static_cast<size_t>(P->n_chunks) * B, &P->ws_gen);
+}
+
+// gg2_mode: 0 none, 1 overwrite, 2 accumulate.  E.mode < 0: gradient of g2 only.
+template <typename T>
+void enqueue_vjp(ephbte_plan P, const T *f, const T *lam, const void *nph, const Epi<T> &E,
+                 double *gg2, int gg2_mode, hipStream_t s) {
+    Tables<T> t = tables<T>(P, nph);
+    dim3 grid(static_cast<unsigned>(grid_x(P)), 1);
+    dim3 block(P->block_threads);
+    const int64_t S = P->S;
+    if (P->fused || E.mode < 0) {
+        hipLaunchKernelGGL((k_collision_vjp<T, true>), grid, block, 0, s, t, f, S, lam, S,
+                           (T *)nullptr, E, gg2, gg2_mode);
+    } else {
+        T *part = static_cast<T *>(P->part.p);
+        hipLaunchKernelGGL((k_collision_vjp<T, false>), grid, block, 0, s, t, f, S, lam, S, part, E,
+                           gg2, gg2_mode);
+        hipLaunchKernelGGL((k_vjp_finish<T>), dim3((P->S + 255) / 256, 1), dim3(256), 0, s, t,
+                           (const T *)part, E);
+    }
+    HIPC(hipGetLastError());
+}
+
+template <typename T>
+__global__ void k_cast_g2(const int32_t *__restrict__ ent_chan, const double *__restrict__ g2,
+                          T *__restrict__ out, int64_t E) {
+    for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < E;
+         e += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        out[e] = static_cast<T>(g2[ent_chan[e]]);
+}
+
+__global__ void k_fill_f64(double *p, int64_t n, double v) {
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        p[i] = v;
+}
+
+template <typename T>
+__global__ void k_scale(const T *__restrict__ x, T *__restrict__ y, T a, int64_t n) {
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        y[i] = a * x[i];
+}
+
+template <typename T>
+__global__ void k_copy_strided(const T *__restrict__ x, int64_t ldx, T *__restrict__ y,
+                               int64_t ldy, int S, int B) {
+    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= S) return;
+    const int b = blockIdx.y;
+    y[static_cast<int64_t>(b) * ldy + d] = x[static_cast<int64_t>(b) * ldx + d];
+}
+
+// transport helpers
+template <typename T>
+__global__ void k_transport_prep(const T *__restrict__ f0, const T *__restrict__ vel,
+                                 const T *__restrict__ tau_inv, T inv_kt, int S,
+                                 T *__restrict__ tau, Vec4<T> *__restrict__ rhs,
+                                 Vec4<T> *__restrict__ x0) {
+    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= S) return;
+    const T ti = tau_inv[d];
+    const T t = ti > T(0) ? T(1) / ti : T(0);
+    const T f = f0[d];
+    const T dfde = -f * (T(1) - f) * inv_kt;
+    Vec4<T> r;
+    r.x = vel[3 * static_cast<int64_t>(d)] * dfde;
+    r.y = vel[3 * static_cast<int64_t>(d) + 1] * dfde;
+    r.z = vel[3 * static_cast<int64_t>(d) + 2] * dfde;
+    r.w = T(0);
+    tau[d] = t;
+    rhs[d] = r;
+    Vec4<T> x;
+    x.x = t * r.x;
+    x.y = t * r.y;
+    x.z = t * r.z;
+    x.w = T(0);
+    x0[d] = x;
+}
+
+// 10 double partial sums per block: sum v_a x_b (9) and sum f0 (only when f0 != NULL).
+template <typename T>
+__global__ __launch_bounds__(256) void k_mobility_partial(const T *__restrict__ vel,
+                                                          const Vec4<T> *__restrict__ x,
+                                                          const T *__restrict__ f0, int S,
+                                                          double *__restrict__ out) {
+    double acc[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) acc[k] = 0.0;
+    for (int d = blockIdx.x * blockDim.x + threadIdx.x; d < S; d += gridDim.x * blockDim.x) {
+        const Vec4<T> xd = x[d];
+        const double xs[3] = {static_cast<double>(xd.x), static_cast<double>(xd.y),
+                              static_cast<double>(xd.z)};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double v = static_cast<double>(vel[3 * static_cast<int64_t>(d) + a]);
+#pragma unroll
+            for (int bb = 0; bb < 3; ++bb) acc[3 * a + bb] += v * xs[bb];
+        }
+        if (f0) acc[9] += static_cast<double>(f0[d]);
+    }
+    block_sum<double, 10>(acc);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 10; ++k) out[10 * blockIdx.x + k] = acc[k];
+}
+
+__global__ __launch_bounds__(256) void k_rows_sum10(const double *__restrict__ in, int rows,
+                                                    double *__restrict__ out) {
+    double acc[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) acc[k] = 0.0;
+    for (int r = threadIdx.x; r < rows; r += blockDim.x)
+#pragma unroll
+        for (int k = 0; k < 10; ++k) acc[k] += in[10 * r + k];
+    block_sum<double, 10>(acc);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 10; ++k) out[k] = acc[k];
+}
+
+template <typename T>
+__global__ void k_unpack_x(const Vec4<T> *__restrict__ x, T *__restrict__ out, int S) {
+    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= S) return;
+    const Vec4<T> v = x[d];
+    out[3 * static_cast<int64_t>(d)] = v.x;
+    out[3 * static_cast<int64_t>(d) + 1] = v.y;
+    out[3 * static_cast<int64_t>(d) + 2] = v.z;
+}
+
+constexpr int kRedBlocks = 256;
+
+bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
+    const char *x = static_cast<const char *>(a), *y = static_cast<const char *>(b);
+    return x < y + nb && y < x + na;
+}
+
+size_t esize(ephbte_plan P) { return P->dtype == EPHBTE_F64 ? 8 : 4; }
+
+template <typename T> void upload_layout(ephbte_plan P, const ephbte_problem *pr, HostLayout &L) {
+    size_t &acc = P->layout_bytes;
+    const int64_t E = L.E, S = L.S;
+    dalloc(P->pnu, sizeof(uint32_t) * E, &acc);
+    dalloc(P->ent_chan, sizeof(int32_t) * E, &acc);
+    dalloc(reinterpret_cast<T *&>(P->g2), sizeof(T) * E, &acc);
+    dalloc(reinterpret_cast<StateRec<T> *&>(P->st), sizeof(StateRec<T>) * S, &acc);
+    const int64_t nqm = static_cast<int64_t>(L.nq[0]) * L.nq[1] * L.nq[2] * L.n_modes;
+    dalloc(reinterpret_cast<T *&>(P->hw), sizeof(T) * nqm, &acc);
+    HIPC(hipMemcpy(P->pnu, L.pnu.data(), sizeof(uint32_t) * E, hipMemcpyHostToDevice));
+    HIPC(hipMemcpy(P->ent_chan, L.ent_chan.data(), sizeof(int32_t) * E, hipMemcpyHostToDevice));
+    {
+        std::vector<T> g(E);
+        parallel_ranges(E, host_threads(), [&](int, int64_t b, int64_t e) {
+            for (int64_t x = b; x < e; ++x) g[x] = static_cast<T>(pr->g2[L.ent_chan[x]]);
+        });
+        HIPC(hipMemcpy(P->g2, g.data(), sizeof(T) * E, hipMemcpyHostToDevice));
+    }
+    {
+        std::vector<StateRec<T>> st(S);
+        for (int64_t s = 0; s < S; ++s) {
+            std::memset(&st[s], 0, sizeof(StateRec<T>));
+            st[s].eps = static_cast<T>(pr->eps[s]);
+            st[s].kq = L.kq[s];
+        }
+        HIPC(hipMemcpy(P->st, st.data(), sizeof(StateRec<T>) * S, hipMemcpyHostToDevice));
+    }
+    {
+        std::vector<T> h(nqm);
+        for (int64_t x = 0; x < nqm; ++x) h[x] = static_cast<T>(pr->hw[x]);
+        HIPC(hipMemcpy(P->hw, h.data(), sizeof(T) * nqm, hipMemcpyHostToDevice));
+    }
+}
+
+hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
+
+// ---------------------------------------------------------------- drivers
+template <typename T>
+void rk4_enqueue_step(ephbte_plan P, int B, T *f, int64_t ldf, const void *nph, T dt,
+                      hipStream_t s, T *ua, T *ub, T *acc, const T *f_in, int64_t ld_in,
+                      T *f_out) {
+    // stage inputs: u1 = f_in, u2 -> ua, u3 -> ub, u4 -> ua; f_out = f_in + dt/6 (...)
+    (void)f;
+    (void)ldf;
+    const int64_t S = P->S;
+    Epi<T> e{};
+    e.f0 = f_in;
+    e.ld_f0 = ld_in;
+    e.acc = acc;
+    e.dt = dt;
+    e.mode = EPI_RK1;
+    e.u_out = ua;
+    enqueue_forward<T>(P, B, f_in, ld_in, nph, e, s);
+    e.mode = EPI_RK2;
+    e.u_out = ub;
+    enqueue_forward<T>(P, B, ua, S, nph, e, s);
+    e.mode = EPI_RK3;
+    e.u_out = ua;
+    enqueue_forward<T>(P, B, ub, S, nph, e, s);
+    e.mode = EPI_RK4;
+    e.f_out = f_out;
+    enqueue_forward<T>(P, B, ua, S, nph, e, s);
+}
+
+template <typename T>
+ephbte_status rt_step_impl(ephbte_plan P, int B, T *f, int64_t ldf, const void *nph, double dt,
+                           int n_steps, int use_graph, hipStream_t s) {
+    const size_t vec = sizeof(T) * static_cast<size_t>(P->S) * B;
+    ensure(P->rk_ua, vec, &P->ws_gen);
+    ensure(P->rk_ub, vec, &P->ws_gen);
+    ensure(P->rk_acc, vec, &P->ws_gen);
+    ensure_part<T>(P, B, 2);
+    T *ua = static_cast<T *>(P->rk_ua.p), *ub = static_cast<T *>(P->rk_ub.p);
+    T *acc = static_cast<T *>(P->rk_acc.p);
+    const T tdt = static_cast<T>(dt);
+    if (!use_graph || n_steps < 2) {
+        for (int k = 0; k < n_steps; ++k)
+            rk4_enqueue_step<T>(P, B, f, ldf, nph, tdt, s, ua, ub, acc, f, ldf, f);
+        return EPHBTE_OK;
+    }
+    const int K = std::min(n_steps, 25);
+    hipStream_t cs = s;
+    if (!s) {
+        if (!P->own_stream) HIPC(hipStreamCreateWithFlags(&P->own_stream, hipStreamNonBlocking));
+        if (!P->ev_a) HIPC(hipEventCreateWithFlags(&P->ev_a, hipEventDisableTiming));
+        if (!P->ev_b) HIPC(hipEventCreateWithFlags(&P->ev_b, hipEventDisableTiming));
+        cs = P->own_stream;
+        HIPC(hipEventRecord(P->ev_a, s));
+        HIPC(hipStreamWaitEvent(cs, P->ev_a, 0));
+    }
+    hipGraphExec_t exec = nullptr;
+    for (auto &g : P->graphs)
+        if (g.f == f && g.nph == nph && g.ldf == ldf && g.B == B && g.steps == K && g.dt == dt &&
+            g.stream == cs && g.ws_gen == P->ws_gen)
+            exec = g.exec;
+    if (!exec) {
+        hipGraph_t graph = nullptr;
+        HIPC(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        try {
+            for (int k = 0; k < K; ++k)
+                rk4_enqueue_step<T>(P, B, f, ldf, nph, tdt, cs, ua, ub, acc, f, ldf, f);
+        } catch (...) {
+            hipGraph_t junk = nullptr;
+            (void)hipStreamEndCapture(cs, &junk);
+            if (junk) (void)hipGraphDestroy(junk);
+            throw;
+        }
+        HIPC(hipStreamEndCapture(cs, &graph));
+        hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        HIPC(ie);
+        if (P->graphs.size() >= 8) {
+            (void)hipGraphExecDestroy(P->graphs.front().exec);
+            P->graphs.erase(P->graphs.begin());
+        }
+        P->graphs.push_back(GraphEntry{f, nph, ldf, B, K, dt, cs, P->ws_gen, exec});
+    }
+    int done = 0;
+    for (; done + K <= n_steps; done += K) HIPC(hipGraphLaunch(exec, cs));
+    for (; done < n_steps; ++done)
+        rk4_enqueue_step<T>(P, B, f, ldf, nph, tdt, cs, ua, ub, acc, f, ldf, f);
+    if (!s) {
+        HIPC(hipEventRecord(P->ev_b, cs));
+        HIPC(hipStreamWaitEvent(s, P->ev_b, 0));
+    }
+    return EPHBTE_OK;
+}
+
+template <typename T>
+ephbte_status rt_adjoint_impl(ephbte_plan P, const T *f0, const void *nph, double dt, int n,
+                              int ce, const T *gfT, T *gf0, double *gg2, int accumulate,
+                              hipStream_t s) {
+    const int64_t S = P->S;
+    const size_t v = sizeof(T) * S;
+    const int nck = (n + ce - 1) / ce;
+    ensure(P->rk_ua, v, &P->ws_gen);
+    ensure(P->rk_ub, v, &P->ws_gen);
+    ensure(P->rk_acc, v, &P->ws_gen);
+    ensure(P->adj_ck, v * nck, &P->ws_gen);
+    ensure(P->adj_U, v * (4 * static_cast<size_t>(ce) + 1), &P->ws_gen);
+    ensure(P->adj_la, v, &P->ws_gen);
+    ensure(P->adj_lb, v, &P->ws_gen);
+    ensure(P->adj_acc, v, &P->ws_gen);
+    ensure(P->adj_g, v, &P->ws_gen);
+    ensure(P->adj_f, v, &P->ws_gen);
+    ensure_part<T>(P, 1, 2);
+    T *ua = static_cast<T *>(P->rk_ua.p), *ub = static_cast<T *>(P->rk_ub.p);
+    T *racc = static_cast<T *>(P->rk_acc.p);
+    T *ck = static_cast<T *>(P->adj_ck.p), *U = static_cast<T *>(P->adj_U.p);
+    T *la = static_cast<T *>(P->adj_la.p), *lb = static_cast<T *>(P->adj_lb.p);
+    T *acc = static_cast<T *>(P->adj_acc.p), *gb = static_cast<T *>(P->adj_g.p);
+    T *fw = static_cast<T *>(P->adj_f.p);
+    const T tdt = static_cast<T>(dt);
+    // forward sweep, checkpoint every ce steps
+    HIPC(hipMemcpyAsync(fw, f0, v, hipMemcpyDeviceToDevice, s));
+    for (int k = 0; k < n; ++k) {
+        if (k % ce == 0) HIPC(hipMemcpyAsync(ck + (k / ce) * S, fw, v, hipMemcpyDeviceToDevice, s));
+        rk4_enqueue_step<T>(P, 1, fw, S, nph, tdt, s, ua, ub, racc, fw, S, fw);
+    }
+    HIPC(hipMemcpyAsync(gb, gfT, v, hipMemcpyDeviceToDevice, s));
+    int gmode = gg2 ? 2 : 0;
+    if (gg2 && !accumulate) {
+        hipLaunchKernelGGL(k_fill_f64, dim3(1024), dim3(256), 0, s, gg2, P->nch, 0.0);
+        HIPC(hipGetLastError());
+    }
+    Epi<T> e{};
+    for (int m = nck - 1; m >= 0; --m) {
+        const int s0 = m * ce, s1 = std::min(n, s0 + ce);
+        // recompute the segment, keeping every stage input: U[l][0..3]
+        HIPC(hipMemcpyAsync(U, ck + m * S, v, hipMemcpyDeviceToDevice, s));
+        for (int k = s0; k < s1; ++k) {
+            T *u = U + static_cast<int64_t>(k - s0) * 4 * S;
+            Epi<T> r{};
+            r.f0 = u;
+            r.ld_f0 = S;
+            r.acc = racc;
+            r.dt = tdt;
+            r.mode = EPI_RK1;
+            r.u_out = u + S;
+            enqueue_forward<T>(P, 1, u, S, nph, r, s);
+            r.mode = EPI_RK2;
+            r.u_out = u + 2 * S;
+            enqueue_forward<T>(P, 1, u + S, S, nph, r, s);
+            r.mode = EPI_RK3;
+            r.u_out = u + 3 * S;
+            enqueue_forward<T>(P, 1, u + 2 * S, S, nph, r, s);
+            r.mode = EPI_RK4;
+            r.f_out = u + 4 * S;   // next step's u1 (one spare slot at the end)
+            enqueue_forward<T>(P, 1, u + 3 * S, S, nph, r, s);
+        }
+        // reverse sweep over the segment
+        for (int k = s1 - 1; k >= s0; --k) {
+            T *u = U + static_cast<int64_t>(k - s0) * 4 * S;
+            hipLaunchKernelGGL((k_scale<T>), dim3((S + 255) / 256), dim3(256), 0, s,
+                               (const T *)gb, la, tdt / T(6), S);
+            HIPC(hipGetLastError());
+            e.gbar = gb;
+            e.acc = acc;
+            e.mode = EPI_ADJ_FIRST;   // u4: acc = v; kb3 = dt/3 g + dt v
+            e.cg = tdt / T(3);
+            e.cv = tdt;
+            e.u_out = lb;
+            enqueue_vjp<T>(P, u + 3 * S, la, nph, e, gg2, gmode, s);
+            e.mode = EPI_ADJ_MID;     // u3: acc += v; kb2 = dt/3 g + dt/2 v
+            e.cg = tdt / T(3);
+            e.cv = tdt / T(2);
+            e.u_out = la;
+            enqueue_vjp<T>(P, u + 2 * S, lb, nph, e, gg2, gmode, s);
+            e.mode = EPI_ADJ_MID;     // u2: acc += v; kb1 = dt/6 g + dt/2 v
+            e.cg = tdt / T(6);
+            e.cv = tdt / T(2);
+            e.u_out = lb;
+            enqueue_vjp<T>(P, u + S, la, nph, e, gg2, gmode, s);
+            e.mode = EPI_ADJ_LAST;    // u1: g = g + acc + v
+            e.gbar_out = gb;
+            enqueue_vjp<T>(P, u, lb, nph, e, gg2, gmode, s);
+        }
+    }
+    if (gf0) HIPC(hipMemcpyAsync(gf0, gb, v, hipMemcpyDeviceToDevice, s));
+    return EPHBTE_OK;
+}
+
+template <typename T>
+ephbte_status transport_impl(ephbte_plan P, const T *f0, const T *vel, double T_K,
+                             const void *nph, double tol, int max_iter, T *x_out, double *mob,
+                             int32_t *iters, double *resid, hipStream_t s) {
+    const int64_t S = P->S;
+    ensure(P->tr_W, sizeof(T) * std::max<int64_t>(P->E, 1), &P->ws_gen);
+    ensure(P->tr_tau_inv, sizeof(T) * S, &P->ws_gen);
+    ensure(P->tr_tau, sizeof(T) * S, &P->ws_gen);
+    ensure(P->tr_rhs, sizeof(Vec4<T>) * S, &P->ws_gen);
+    ensure(P->tr_xa, sizeof(Vec4<T>) * S, &P->ws_gen);
+    ensure(P->tr_xb, sizeof(Vec4<T>) * S, &P->ws_gen);
+    ensure(P->tr_part, sizeof(Vec4<T>) * std::max<int64_t>(P->n_chunks, 1), &P->ws_gen);
+    ensure(P->tr_red, sizeof(double) * 10 * kRedBlocks, &P->ws_gen);
+    ensure(P->tr_red2, sizeof(double) * 10, &P->ws_gen);
+    if (!P->host_red) HIPC(hipHostMalloc(reinterpret_cast<void **>(&P->host_red), sizeof(double) * 10, 0));
+    Tables<T> t = tables<T>(P, nph);
+    T *W = static_cast<T *>(P->tr_W.p), *tinv = static_cast<T *>(P->tr_tau_inv.p);
+    T *tau = static_cast<T *>(P->tr_tau.p);
+    Vec4<T> *rhs = static_cast<Vec4<T> *>(P->tr_rhs.p);
+    Vec4<T> *xa = static_cast<Vec4<T> *>(P->tr_xa.p), *xb = static_cast<Vec4<T> *>(P->tr_xb.p);
+    Vec4<T> *part = static_cast<Vec4<T> *>(P->tr_part.p);
+    double *red = static_cast<double *>(P->tr_red.p), *red2 = static_cast<double *>(P->tr_red2.p);
+    dim3 grid(static_cast<unsigned>(grid_x(P))), block(P->block_threads);
+    dim3 sg((S + 255) / 256);
+    if (P->fused)
+        hipLaunchKernelGGL((k_transport_setup<T, true>), grid, block, 0, s, t, f0, W, (T *)nullptr,
+                           tinv);
+    else {
+        hipLaunchKernelGGL((k_transport_setup<T, false>), grid, block, 0, s, t, f0, W,
+                           reinterpret_cast<T *>(part), tinv);
+        hipLaunchKernelGGL((k_transport_setup_finish<T>), sg, dim3(256), 0, s, t,
+                           (const T *)reinterpret_cast<T *>(part), tinv);
+    }
+    hipLaunchKernelGGL((k_transport_prep<T>), sg, dim3(256), 0, s, f0, vel, (const T *)tinv,
+                       static_cast<T>(1.0 / (kKb * T_K)), (int)S, tau, rhs, xa);
+    HIPC(hipGetLastError());
+    auto mobility = [&](const Vec4<T> *x, bool with_f0, double out[10]) {
+        hipLaunchKernelGGL((k_mobility_partial<T>), dim3(kRedBlocks), dim3(256), 0, s, vel, x,
+                           with_f0 ? f0 : (const T *)nullptr, (int)S, red);
+        hipLaunchKernelGGL(k_rows_sum10, dim3(1), dim3(256), 0, s, (const double *)red,
+                           kRedBlocks, red2);
+        HIPC(hipGetLastError());
+        HIPC(hipMemcpyAsync(P->host_red, red2, sizeof(double) * 10, hipMemcpyDeviceToHost, s));
+        HIPC(hipStreamSynchronize(s));
+        std::memcpy(out, P->host_red, sizeof(double) * 10);
+    };
+    double r0[10];
+    mobility(xa, true, r0);
+    const double sum_f0 = r0[9];
+    if (!(sum_f0 > 0.0)) throw HipError{hipErrorInvalidValue, "sum of f0 is not positive"};
+    const double unit = -1e-15 * 1e4 / sum_f0;   // fs -> s, m^2 -> cm^2, e = 1
+    double mu[9];
+    for (int k = 0; k < 9; ++k) mu[k] = unit * r0[k];
+    double rel = INFINITY;
+    int it = 0;
+    bool conv = false;
+    for (it = 1; it <= max_iter; ++it) {
+        if (P->fused)
+            hipLaunchKernelGGL((k_transport_iter<T, true>), grid, block, 0, s, t, (const T *)W,
+                               (const Vec4<T> *)xa, (const Vec4<T> *)rhs, (const T *)tau,
+                               (Vec4<T> *)nullptr, xb);
+        else {
+            hipLaunchKernelGGL((k_transport_iter<T, false>), grid, block, 0, s, t, (const T *)W,
+                               (const Vec4<T> *)xa, (const Vec4<T> *)rhs, (const T *)tau, part, xb);
+            hipLaunchKernelGGL((k_transport_iter_finish<T>), sg, dim3(256), 0, s, t,
+                               (const Vec4<T> *)part, (const Vec4<T> *)rhs, (const T *)tau, xb);
+        }
+        HIPC(hipGetLastError());
+        double r[10];
+        mobility(xb, false, r);
+        double num = 0.0, den = 0.0, nm[9];
+        for (int k = 0; k < 9; ++k) {
+            nm[k] = unit * r[k];
+            num = std::max(num, std::fabs(nm[k] - mu[k]));
+            den = std::max(den, std::fabs(nm[k]));
+        }
+        rel = den > 0 ? num / den : 0.0;
+        std::memcpy(mu, nm, sizeof(mu));
+        std::swap(xa, xb);
+        if (rel <= tol) {
+            conv = true;
+            break;
+        }
+    }
+    if (it > max_iter) it = max_iter;
+    if (x_out) {
+        hipLaunchKernelGGL((k_unpack_x<T>), sg, dim3(256), 0, s, (const Vec4<T> *)xa, x_out, (int)S);
+        HIPC(hipGetLastError());
+        HIPC(hipStreamSynchronize(s));
+    }
+    std::memcpy(mob, mu, sizeof(mu));
+    if (iters) *iters = it;
+    if (resid) *resid = rel;
+    if (!conv) return fail(EPHBTE_NOT_CONVERGED, "transport iteration did not reach the tolerance");
+    return EPHBTE_OK;
+}
+
+template <typename F> ephbte_status guarded(ephbte_plan P, F &&fn) {
+    if (!P) return fail(EPHBTE_INVALID_ARGUMENT, "plan is NULL");
+    try {
+        DeviceGuard g(P->device);
+        return fn();
+    } catch (const HipError &e) {
+        return fail(EPHBTE_HIP_ERROR, std::string(e.where) + ": " + hipGetErrorString(e.e));
+    } catch (const std::bad_alloc &) {
+        return fail(EPHBTE_OUT_OF_MEMORY, "device or host memory allocation failed");
+    } catch (...) {
+        return fail(EPHBTE_HIP_ERROR, "unexpected exception");
+    }
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+const char *ephbte_status_string(ephbte_status s) {
+    switch (s) {
+    case EPHBTE_OK: return "ok";
+    case EPHBTE_INVALID_ARGUMENT: return "invalid argument";
+    case EPHBTE_UNSUPPORTED_DTYPE: return "unsupported dtype";
+    case EPHBTE_OUT_OF_MEMORY: return "out of memory";
+    case EPHBTE_HIP_ERROR: return "HIP error";
+    case EPHBTE_NOT_CONVERGED: return "not converged";
+    case EPHBTE_NONFINITE: return "non-finite value";
+    case EPHBTE_PLAN_MISMATCH: return "plan mismatch";
+    default: return "unknown status";
+    }
+}
+
+const char *ephbte_last_error(void) { return g_last_error.c_str(); }
+
+ephbte_status ephbte_layout_host(const ephbte_problem *problem, int64_t *row_ptr,
+                                 int32_t *entry_partner, int8_t *entry_mode,
+                                 int32_t *entry_channel) {
+    try {
+        HostLayout L;
+        std::string err;
+        ephbte_status st = build_host_layout(problem, &L, &err);
+        if (st != EPHBTE_OK) return fail(st, err);
+        if (row_ptr) std::memcpy(row_ptr, L.row_ptr.data(), sizeof(int64_t) * (L.S + 1));
+        for (int64_t e = 0; e < L.E; ++e) {
+            if (entry_partner) entry_partner[e] = static_cast<int32_t>(L.pnu[e] >> 3);
+            if (entry_mode) entry_mode[e] = static_cast<int8_t>(L.pnu[e] & 7u);
+            if (entry_channel) entry_channel[e] = L.ent_chan[e];
+        }
+        return EPHBTE_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(EPHBTE_OUT_OF_MEMORY, "host memory allocation failed");
+    } catch (...) {
+        return fail(EPHBTE_INVALID_ARGUMENT, "unexpected exception while building the layout");
+    }
+}
+
+ephbte_status ephbte_build_channels(const ephbte_problem *problem, ephbte_plan *out) {
+    if (!out) return fail(EPHBTE_INVALID_ARGUMENT, "out is NULL");
+    *out = nullptr;
+    HostLayout L;
+    std::string err;
+    try {
+        ephbte_status st = build_host_layout(problem, &L, &err);
+        if (st != EPHBTE_OK) return fail(st, err);
+    } catch (const std::bad_alloc &) {
+        return fail(EPHBTE_OUT_OF_MEMORY, "host memory allocation failed");
+    }
+    ephbte_plan P = new (std::nothrow) ephbte_plan_s();
+    if (!P) return fail(EPHBTE_OUT_OF_MEMORY, "host memory allocation failed");
+    try {
+        int dev = problem->device;
+        if (dev < 0) HIPC(hipGetDevice(&dev));
+        int ndev = 0;
+        HIPC(hipGetDeviceCount(&ndev));
+        if (dev >= ndev) {
+            delete P;
+            return fail(EPHBTE_INVALID_ARGUMENT, "device ordinal out of range");
+        }
+        P->device = dev;
+        DeviceGuard g(dev);
+        P->dtype = problem->dtype;
+        P->S = L.S;
+        P->nm = L.n_modes;
+        P->nch = L.n_channels;
+        P->E = L.E;
+        for (int a = 0; a < 3; ++a) P->nq[a] = L.nq[a];
+        P->sigma = problem->sigma;
+        P->nqnorm = problem->n_q_norm;
+        P->row_ptr = L.row_ptr;
+        if (P->dtype == EPHBTE_F64) upload_layout<double>(P, problem, L);
+        else upload_layout<float>(P, problem, L);
+        { HostLayout tmp; std::swap(tmp, L); }
+        upload_chunks(P, 4096);
+        P->block_threads = 256;
+        HIPC(hipDeviceSynchronize());
+    } catch (const HipError &e) {
+        free_plan(P);
+        return fail(EPHBTE_HIP_ERROR, std::string(e.where) + ": " + hipGetErrorString(e.e));
+    } catch (const std::bad_alloc &) {
+        free_plan(P);
+        return fail(EPHBTE_OUT_OF_MEMORY, "device or host memory allocation failed");
+    }
+    *out = P;
+    return EPHBTE_OK;
+}
+
+ephbte_status ephbte_collision_integral(ephbte_plan plan, int32_t batch, const void *f,
+                                        int64_t ldf, const void *nph, void *I, int64_t ldi,
+                                        void *stream) {
+    return guarded(plan, [&]() -> ephbte_status {
+        if (batch < 1 || batch > 65535) return fail(EPHBTE_INVALID_ARGUMENT, "batch must be in [1, 65535]");
+        if (!f || !nph || !I) return fail(EPHBTE_INVALID_ARGUMENT, "f, nph and I must be non-NULL");
+        if (ldf < plan->S || ldi < plan->S)
+            return fail(EPHBTE_INVALID_ARGUMENT, "ldf and ldi must be >= n_states");
+        const size_t es = esize(plan);
+        if (overlaps(f, es * ldf * batch, I, es * ldi * batch))
+            return fail(EPHBTE_INVALID_ARGUMENT, "I must not overlap f");
+        hipStream_t s = as_stream(stream);
+        if (plan->dtype == EPHBTE_F64) {
+            ensure_part<double>(plan, batch, 2);
+            enqueue_forward<double>(plan, batch, static_cast<const double *>(f), ldf, nph,
+                                    epi_store<double>(static_cast<double *>(I), ldi), s);
+        } else {
+            ensure_part<float>(plan, batch, 2);
+            enqueue_forward<float>(plan, batch, static_cast<const float *>(f), ldf, nph,
+                                   epi_store<float>(static_cast<float *>(I), ldi), s);
+        }
+        return EPHBTE_OK;
+    });
+}
+
+ephbte_status ephbte_collision_vjp(ephbte_plan plan, int32_t batch, const void *f, int64_t ldf,
+                                   const void *nph, const void *gI, int64_t ldg, void *gf,
+                                   int64_t ldgf, double *gg2, int32_t accumulate_gg2,
+                                   void *stream) {
+    return guarded(plan, [&]() -> ephbte_status {
+        if (batch < 1 || batch > 65535) return fail(EPHBTE_INVALID_ARGUMENT, "batch must be in [1, 65535]");
+        if (!f || !nph || !gI) return fail(EPHBTE_INVALID_ARGUMENT, "f, nph and gI must be non-NULL");
+        if (ldf < plan->S || ldg < plan->S || (gf && ldgf < plan->S))
+            return fail(EPHBTE_INVALID_ARGUMENT, "leading dimensions must be >= n_states");
+        const size_t es = esize(plan);
+        if (gf && (overlaps(gf, es * ldgf * batch, f, es * ldf * batch) ||
+                   overlaps(gf, es * ldgf * batch, gI, es * ldg * batch)))
+            return fail(EPHBTE_INVALID_ARGUMENT, "gf must not overlap f or gI");
+        hipStream_t s = as_stream(stream);
+        auto run = [&](auto tag) {
+            using T = decltype(tag);
+            ensure_part<T>(plan, 1, 1);
+            const int64_t S = plan->S;
+            // the kernels take unit-stride vectors of length S; strided
+            // batch members are addressed one vector at a time
+            for (int b = 0; b < batch; ++b) {
+                const T *fb = static_cast<const T *>(f) + b * ldf;
+                const T *lb = static_cast<const T *>(gI) + b * ldg;
+                Epi<T> e{};
+                if (gf) {
+                    e = epi_store<T>(static_cast<T *>(gf) + b * ldgf, S);
+                } else {
+                    e.mode = -1;
+                }
+                int gmode = gg2 ? ((accumulate_gg2 || b > 0) ? 2 : 1) : 0;
+                if (!gf && !gg2) continue;
+                enqueue_vjp<T>(plan, fb, lb, nph, e, gg2, gmode, s);
+            }
+        };
+        if (plan->dtype == EPHBTE_F64) run(double{});
+        else run(float{});
+        return EPHBTE_OK;
+    });
+}
+
+ephbte_status ephbte_rt_step(ephbte_plan plan, int32_t batch, void *f, int64_t ldf,
+                             const void *nph, double dt_fs, int32_t n_steps, int32_t use_graph,
+                             void *stream) {
+    return guarded(plan, [&]() -> ephbte_status {
+        if (batch < 1 || batch > 65535) return fail(EPHBTE_INVALID_ARGUMENT, "batch must be in [1, 65535]");
+        if (!f || !nph) return fail(EPHBTE_INVALID_ARGUMENT, "f and nph must be non-NULL");
+        if (ldf < plan->S) return fail(EPHBTE_INVALID_ARGUMENT, "ldf must be >= n_states");
+        if (n_steps < 0) return fail(EPHBTE_INVALID_ARGUMENT, "n_steps must be >= 0");
+        if (!std::isfinite(dt_fs)) return fail(EPHBTE_INVALID_ARGUMENT, "dt must be finite");
+        if (n_steps == 0) return EPHBTE_OK;
+        hipStream_t s = as_stream(stream);
+        if (plan->dtype == EPHBTE_F64)
+            return rt_step_impl<double>(plan, batch, static_cast<double *>(f), ldf, nph, dt_fs,
+                                        n_steps, use_graph, s);
+        return rt_step_impl<float>(plan, batch, static_cast<float *>(f), ldf, nph, dt_fs, n_steps,
+                                   use_graph, s);
+    });
+}
+
+ephbte_status ephbte_rt_adjoint(ephbte_plan plan, const void *f0, const void *nph, double dt_fs,
+                                int32_t n_steps, int32_t checkpoint_every, const void *gfT,
+                                void *gf0, double *gg2, int32_t accumulate_gg2, void *stream) {
+    return guarded(plan, [&]() -> ephbte_status {
+        if (!f0 || !nph || !gfT) return fail(EPHBTE_INVALID_ARGUMENT, "f0, nph and gfT must be non-NULL");
+        if (n_steps < 1) return fail(EPHBTE_INVALID_ARGUMENT, "n_steps must be >= 1");
+        if (checkpoint_every < 1) return fail(EPHBTE_INVALID_ARGUMENT, "checkpoint_every must be >= 1");
+        if (!std::isfinite(dt_fs)) return fail(EPHBTE_INVALID_ARGUMENT, "dt must be finite");
+        hipStream_t s = as_stream(stream);
+        const int ce = std::min(checkpoint_every, n_steps);
+        if (plan->dtype == EPHBTE_F64)
+            return rt_adjoint_impl<double>(plan, static_cast<const double *>(f0), nph, dt_fs,
+                                           n_steps, ce, static_cast<const double *>(gfT),
+                                           static_cast<double *>(gf0), gg2, accumulate_gg2, s);
+        return rt_adjoint_impl<float>(plan, static_cast<const float *>(f0), nph, dt_fs, n_steps, ce,
+                                      static_cast<const float *>(gfT), static_cast<float *>(gf0),
+                                      gg2, accumulate_gg2, s);
+    });
+}
+
+ephbte_status ephbte_iterate_transport(ephbte_plan plan, const void *f0, const void *vel,
+                                       double T_K, const void *nph, double tol, int32_t max_iter,
+                                       void *x_out, double *mobility, int32_t *iters,
+                                       double *resid, void *stream) {
+    return guarded(plan, [&]() -> ephbte_status {
+        if (!f0 || !vel || !nph || !mobility)
+            return fail(EPHBTE_INVALID_ARGUMENT, "f0, vel, nph and mobility must be non-NULL");
+        if (!(T_K > 0.0) || !std::isfinite(T_K)) return fail(EPHBTE_INVALID_ARGUMENT, "T_K must be > 0");
+        if (max_iter < 0) return fail(EPHBTE_INVALID_ARGUMENT, "max_iter must be >= 0");
+        if (!(tol >= 0.0)) return fail(EPHBTE_INVALID_ARGUMENT, "tol must be >= 0");
+        hipStream_t s = as_stream(stream);
+        if (plan->dtype == EPHBTE_F64)
+            return transport_impl<double>(plan, static_cast<const double *>(f0),
+                                          static_cast<const double *>(vel), T_K, nph, tol, max_iter,
+                                          static_cast<double *>(x_out), mobility, iters, resid, s);
+        return transport_impl<float>(plan, static_cast<const float *>(f0),
+                                     static_cast<const float *>(vel), T_K, nph, tol, max_iter,
+                                     static_cast<float *>(x_out), mobility, iters, resid, s);
+    });
+}
+
+ephbte_status ephbte_update_g2(ephbte_plan plan, const double *g2, void *stream) {
+    return guarded(plan, [&]() -> ephbte_status {
+        if (!g2) return fail(EPHBTE_INVALID_ARGUMENT, "g2 must be non-NULL");
+        hipStream_t s = as_stream(stream);
+        if (plan->E == 0) return EPHBTE_OK;
+        if (plan->dtype == EPHBTE_F64)
+            hipLaunchKernelGGL((k_cast_g2<double>), dim3(4096), dim3(256), 0, s,
+                               (const int32_t *)plan->ent_chan, g2, static_cast<double *>(plan->g2),
+                               plan->E);
+        else
+            hipLaunchKernelGGL((k_cast_g2<float>), dim3(4096), dim3(256), 0, s,
+                               (const int32_t *)plan->ent_chan, g2, static_cast<float *>(plan->g2),
+                               plan->E);
+        HIPC(hipGetLastError());
+        return EPHBTE_OK;
+    });
+}
+
+ephbte_status ephbte_set_tuning(ephbte_plan plan, const ephbte_tuning *tuning) {
+    return guarded(plan, [&]() -> ephbte_status {
+        if (!tuning) return fail(EPHBTE_INVALID_ARGUMENT, "tuning is NULL");
+        int bt = tuning->block_threads ? tuning->block_threads : plan->block_threads;
+        if (bt != 64 && bt != 128 && bt != 256 && bt != 512)
+            return fail(EPHBTE_INVALID_ARGUMENT, "block_threads must be 64, 128, 256 or 512");
+        int ce = tuning->chunk_entries ? tuning->chunk_entries : plan->chunk_entries;
+        if (ce < 0) return fail(EPHBTE_INVALID_ARGUMENT, "chunk_entries must be >= 0");
+        if (tuning->xcd_map < 0 || tuning->xcd_map > 2)
+            return fail(EPHBTE_INVALID_ARGUMENT, "xcd_map must be 0, 1 or 2");
+        HIPC(hipDeviceSynchronize());
+        plan->block_threads = bt;
+        if (tuning->xcd_map) plan->xcd_map = tuning->xcd_map == 1;
+        upload_chunks(plan, ce);
+        free_graphs(plan);
+        return EPHBTE_OK;
+    });
+}
+
+ephbte_status ephbte_autotune(ephbte_plan plan, int32_t batch, ephbte_tuning *chosen) {
+    return guarded(plan, [&]() -> ephbte_status {
+        if (batch < 1 || batch > 65535) return fail(EPHBTE_INVALID_ARGUMENT, "batch must be in [1, 65535]");
+        HIPC(hipDeviceSynchronize());
+        const size_t es = esize(plan);
+        const int64_t S = plan->S;
+        const int64_t nqm = static_cast<int64_t>(plan->nq[0]) * plan->nq[1] * plan->nq[2] * plan->nm;
+        void *f = nullptr, *I = nullptr, *nph = nullptr;
+        size_t dummy = 0;
+        dalloc(f, es * S * batch, &dummy);
+        dalloc(I, es * S * batch, &dummy);
+        dalloc(nph, es * nqm, &dummy);
+        struct Freer {
+            void *a, *b, *c;
+            ~Freer() { (void)hipFree(a); (void)hipFree(b); (void)hipFree(c); }
+        } fr{f, I, nph};
+        // half-filled states and phonons: the kernels' cost does not depend on values
+        if (es == 8) {
+            std::vector<double> h(std::max<int64_t>(S * batch, nqm), 0.5);
+            HIPC(hipMemcpy(f, h.data(), es * S * batch, hipMemcpyHostToDevice));
+            HIPC(hipMemcpy(nph, h.data(), es * nqm, hipMemcpyHostToDevice));
+        } else {
+            std::vector<float> h(std::max<int64_t>(S * batch, nqm), 0.5f);
+            HIPC(hipMemcpy(f, h.data(), es * S * batch, hipMemcpyHostToDevice));
+            HIPC(hipMemcpy(nph, h.data(), es * nqm, hipMemcpyHostToDevice));
+        }
+        hipEvent_t e0, e1;
+        HIPC(hipEventCreate(&e0));
+        HIPC(hipEventCreate(&e1));
+        const int chunk_c[] = {1024, 2048, 4096, 8192, 16384, 0};
+        const int thr_c[] = {128, 256, 512};
+        float best = INFINITY;
+        int best_ce = plan->chunk_entries, best_bt = plan->block_threads;
+        for (int ce : chunk_c)
+            for (int bt : thr_c) {
+                plan->block_threads = bt;
+                upload_chunks(plan, ce);
+                auto once = [&]() {
+                    if (plan->dtype == EPHBTE_F64) {
+                        ensure_part<double>(plan, batch, 2);
+                        enqueue_forward<double>(plan, batch, (const double *)f, S, nph,
+                                                epi_store<double>((double *)I, S), nullptr);
+                    } else {
+                        ensure_part<float>(plan, batch, 2);
+                        enqueue_forward<float>(plan, batch, (const float *)f, S, nph,
+                                               epi_store<float>((float *)I, S), nullptr);
+                    }
+                };
+                once();
+                HIPC(hipEventRecord(e0, nullptr));
+                for (int r = 0; r < 3; ++r) once();
+                HIPC(hipEventRecord(e1, nullptr));
+                HIPC(hipEventSynchronize(e1));
+                float ms = 0;
+                HIPC(hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best) {
+                    best = ms;
+                    best_ce = ce;
+                    best_bt = bt;
+                }
+            }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        plan->block_threads = best_bt;
+        upload_chunks(plan, best_ce);
+        if (chosen) {
+            std::memset(chosen, 0, sizeof(*chosen));
+            chosen->chunk_entries = best_ce;
+            chosen->block_threads = best_bt;
+            chosen->xcd_map = plan->xcd_map ? 1 : 2;
+        }
+        return EPHBTE_OK;
+    });
+}
+
+ephbte_status ephbte_plan_info(ephbte_plan plan, int64_t out[9]) {
+    if (!plan || !out) return fail(EPHBTE_INVALID_ARGUMENT, "plan and out must be non-NULL");
+    out[0] = plan->S;
+    out[1] = plan->nch;
+    out[2] = plan->E;
+    out[3] = plan->n_chunks;
+    out[4] = plan->dtype;
+    out[5] = plan->device;
+    out[6] = static_cast<int64_t>(plan->bytes());
+    out[7] = plan->chunk_entries;
+    out[8] = plan->block_threads;
+    return EPHBTE_OK;
+}
+
+int64_t ephbte_plan_bytes(ephbte_plan plan) { return plan ? static_cast<int64_t>(plan->bytes()) : 0; }
+
+void ephbte_destroy(ephbte_plan plan) {
+    if (!plan) return;
+    try {
+        (void)hipDeviceSynchronize();
+        free_plan(plan);
+    } catch (...) {
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,260 @@
+// Host-side channel layout builder (see layout.hpp).
+#include "layout.hpp"
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdlib>
+#include <numeric>
+#include <sstream>
+#include <thread>
+
+namespace ephbte {
+
+int host_threads() {
+    const char *env = std::getenv("EPHBTE_HOST_THREADS");
+    if (env && std::atoi(env) > 0) return std::atoi(env);
+    unsigned hc = std::thread::hardware_concurrency();
+    int t = hc ? static_cast<int>(hc) : 1;
+    return std::min(t, 16);
+}
+
+void parallel_ranges(int64_t n, int threads,
+                     const std::function<void(int, int64_t, int64_t)> &fn) {
+    if (threads < 1) threads = 1;
+    if (n < 4096 || threads == 1) {
+        fn(0, 0, n);
+        return;
+    }
+    std::vector<std::thread> pool;
+    for (int t = 0; t < threads; ++t) {
+        int64_t b = n * t / threads, e = n * (t + 1) / threads;
+        pool.emplace_back([&, t, b, e] { fn(t, b, e); });
+    }
+    for (auto &th : pool) th.join();
+}
+
+namespace {
+
+void k_coords(int64_t lin, const int32_t g[3], int32_t c[3]) {
+    c[2] = static_cast<int32_t>(lin % g[2]);
+    lin /= g[2];
+    c[1] = static_cast<int32_t>(lin % g[1]);
+    c[0] = static_cast<int32_t>(lin / g[1]);
+}
+
+std::string fmt_channel(int64_t c, int32_t i, int32_t j, int nu) {
+    std::ostringstream os;
+    os << "channel " << c << " (i=" << i << ", j=" << j << ", nu=" << nu << ")";
+    return os.str();
+}
+
+}  // namespace
+
+ephbte_status build_host_layout(const ephbte_problem *p, HostLayout *out, std::string *err) {
+    auto bad = [&](const std::string &m) {
+        *err = m;
+        return EPHBTE_INVALID_ARGUMENT;
+    };
+    if (!p) return bad("problem is NULL");
+    if (p->dtype != EPHBTE_F32 && p->dtype != EPHBTE_F64) {
+        *err = "dtype must be EPHBTE_F32 (1) or EPHBTE_F64 (2)";
+        return EPHBTE_UNSUPPORTED_DTYPE;
+    }
+    const int32_t S = p->n_states;
+    if (S < 1 || S >= (1 << 29)) return bad("n_states must be in [1, 2^29)");
+    if (!p->state_k || !p->eps) return bad("state_k and eps must be non-NULL");
+    if (p->n_modes < 1 || p->n_modes > 8) return bad("n_modes must be in [1, 8]");
+    if (!p->hw) return bad("hw must be non-NULL");
+    if (p->n_channels < 0 || p->n_channels >= (int64_t(1) << 30))
+        return bad("n_channels must be in [0, 2^30)");
+    if (p->n_channels > 0 && (!p->ch_i || !p->ch_j || !p->ch_nu || !p->g2))
+        return bad("channel arrays must be non-NULL when n_channels > 0");
+    if (!(p->sigma > 0.0) || !std::isfinite(p->sigma)) return bad("sigma must be finite and > 0");
+    if (!(p->n_q_norm > 0.0) || !std::isfinite(p->n_q_norm))
+        return bad("n_q_norm must be finite and > 0");
+    int64_t nk = 1, nq = 1;
+    int32_t r[3];
+    for (int a = 0; a < 3; ++a) {
+        if (p->kgrid[a] < 1 || p->qgrid[a] < 1) return bad("grid sizes must be >= 1");
+        if (p->qgrid[a] > 1024) return bad("q grid sizes must be <= 1024");
+        if (p->kgrid[a] % p->qgrid[a] != 0) return bad("q grid must divide the k grid");
+        r[a] = p->kgrid[a] / p->qgrid[a];
+        nk *= p->kgrid[a];
+        nq *= p->qgrid[a];
+    }
+    if (nk >= (int64_t(1) << 31)) return bad("k grid has too many points");
+    const int nm = p->n_modes;
+    for (int64_t x = 0; x < nq * nm; ++x)
+        if (!std::isfinite(p->hw[x]) || p->hw[x] < 0.0) return bad("hw must be finite and >= 0");
+
+    HostLayout &L = *out;
+    L.S = S;
+    L.n_modes = nm;
+    for (int a = 0; a < 3; ++a) L.nq[a] = p->qgrid[a];
+    L.kq.resize(S);
+    std::vector<int32_t> kc(3 * static_cast<size_t>(S));
+    for (int32_t s = 0; s < S; ++s) {
+        int64_t k = p->state_k[s];
+        if (k < 0 || k >= nk) return bad("state_k out of range for the k grid");
+        if (!std::isfinite(p->eps[s])) return bad("eps must be finite");
+        int32_t c[3];
+        k_coords(k, p->kgrid, c);
+        for (int a = 0; a < 3; ++a) kc[3 * s + a] = c[a];
+        L.kq[s] = (static_cast<uint32_t>(c[0] / r[0]) << 20) |
+                  (static_cast<uint32_t>(c[1] / r[1]) << 10) | static_cast<uint32_t>(c[2] / r[2]);
+    }
+
+    const int64_t nch = p->n_channels;
+    const int T = host_threads();
+    // --- validate channels (parallel, first error by lowest channel index)
+    std::atomic<int64_t> first_bad{INT64_MAX};
+    std::vector<std::string> msgs(T);
+    auto q_of = [&](int32_t d, int32_t pp) {
+        int32_t q[3];
+        for (int a = 0; a < 3; ++a) {
+            int32_t dk = kc[3 * pp + a] - kc[3 * d + a];
+            if (dk < 0) dk += p->kgrid[a];
+            if (dk % r[a] != 0) return int64_t(-1);
+            q[a] = dk / r[a];
+        }
+        return (int64_t(q[0]) * p->qgrid[1] + q[1]) * p->qgrid[2] + q[2];
+    };
+    parallel_ranges(nch, T, [&](int t, int64_t b, int64_t e) {
+        for (int64_t c = b; c < e; ++c) {
+            if (c >= first_bad.load(std::memory_order_relaxed)) return;
+            int32_t i = p->ch_i[c], j = p->ch_j[c];
+            int nu = p->ch_nu[c];
+            std::string m;
+            if (i < 0 || i >= S || j < 0 || j >= S) m = "state index out of range";
+            else if (i == j) m = "i == j (a state cannot scatter into itself)";
+            else if (nu < 0 || nu >= nm) m = "mode index out of range";
+            else if (!std::isfinite(p->g2[c]) || p->g2[c] < 0.0) m = "|g|^2 must be finite and >= 0";
+            else {
+                int64_t q1 = q_of(i, j), q2 = q_of(j, i);
+                if (q1 < 0 || q2 < 0) m = "k_j - k_i is not a q-grid vector";
+                else if (p->hw[q1 * nm + nu] < 1e-6 || p->hw[q2 * nm + nu] < 1e-6)
+                    m = "phonon energy below 1e-6 eV (divergent occupation)";
+            }
+            if (!m.empty()) {
+                int64_t cur = first_bad.load();
+                while (c < cur && !first_bad.compare_exchange_weak(cur, c)) {
+                }
+                msgs[t] = fmt_channel(c, i, j, nu) + ": " + m;
+                return;
+            }
+        }
+    });
+    if (first_bad.load() != INT64_MAX) {
+        int64_t c = first_bad.load();
+        for (auto &m : msgs)
+            if (m.rfind(fmt_channel(c, p->ch_i[c], p->ch_j[c], p->ch_nu[c]), 0) == 0) return bad(m);
+        return bad("invalid channel");
+    }
+
+    // --- count entries per destination (per-thread histograms)
+    L.n_channels = nch;
+    L.E = 2 * nch;
+    std::vector<std::vector<int64_t>> cnt(T, std::vector<int64_t>(S, 0));
+    parallel_ranges(nch, T, [&](int t, int64_t b, int64_t e) {
+        auto &h = cnt[t];
+        for (int64_t c = b; c < e; ++c) {
+            h[p->ch_i[c]]++;
+            h[p->ch_j[c]]++;
+        }
+    });
+    L.row_ptr.assign(S + 1, 0);
+    for (int32_t d = 0; d < S; ++d) {
+        int64_t tot = 0;
+        for (int t = 0; t < T; ++t) tot += cnt[t][d];
+        L.row_ptr[d + 1] = L.row_ptr[d] + tot;
+    }
+    // per-thread write cursors: thread t writes after threads 0..t-1
+    for (int32_t d = 0; d < S; ++d) {
+        int64_t pos = L.row_ptr[d];
+        for (int t = 0; t < T; ++t) {
+            int64_t n = cnt[t][d];
+            cnt[t][d] = pos;
+            pos += n;
+        }
+    }
+    L.pnu.resize(L.E);
+    L.ent_chan.resize(L.E);
+    // stable scatter: inside a destination, entries keep channel order
+    parallel_ranges(nch, T, [&](int t, int64_t b, int64_t e) {
+        auto &cur = cnt[t];
+        for (int64_t c = b; c < e; ++c) {
+            int32_t i = p->ch_i[c], j = p->ch_j[c];
+            int nu = p->ch_nu[c];
+            int64_t ei = cur[i]++, ej = cur[j]++;
+            L.pnu[ei] = pack_pnu(j, nu);
+            L.ent_chan[ei] = static_cast<int32_t>(c);
+            L.pnu[ej] = pack_pnu(i, nu);
+            L.ent_chan[ej] = static_cast<int32_t>(c);
+        }
+    });
+    cnt.clear();
+
+    // --- sort each destination by (partner, mode); detect duplicates
+    std::atomic<int32_t> dup_dest{-1};
+    parallel_ranges(S, T, [&](int, int64_t b, int64_t e) {
+        std::vector<int64_t> idx;
+        std::vector<uint32_t> kb;
+        std::vector<int32_t> cb;
+        for (int64_t d = b; d < e; ++d) {
+            int64_t lo = L.row_ptr[d], hi = L.row_ptr[d + 1];
+            bool sorted = true;
+            for (int64_t x = lo + 1; x < hi; ++x)
+                if (L.pnu[x] <= L.pnu[x - 1]) {
+                    sorted = false;
+                    break;
+                }
+            if (sorted) continue;
+            idx.resize(hi - lo);
+            std::iota(idx.begin(), idx.end(), lo);
+            std::stable_sort(idx.begin(), idx.end(),
+                             [&](int64_t a, int64_t bb) { return L.pnu[a] < L.pnu[bb]; });
+            kb.resize(hi - lo);
+            cb.resize(hi - lo);
+            for (int64_t x = 0; x < hi - lo; ++x) {
+                kb[x] = L.pnu[idx[x]];
+                cb[x] = L.ent_chan[idx[x]];
+            }
+            for (int64_t x = 0; x < hi - lo; ++x) {
+                L.pnu[lo + x] = kb[x];
+                L.ent_chan[lo + x] = cb[x];
+                if (x > 0 && kb[x] == kb[x - 1]) dup_dest.store(static_cast<int32_t>(d));
+            }
+        }
+    });
+    if (dup_dest.load() >= 0) {
+        std::ostringstream os;
+        os << "duplicate (i, j, nu) channel at state " << dup_dest.load();
+        return bad(os.str());
+    }
+    return EPHBTE_OK;
+}
+
+ChunkTable make_chunks(const std::vector<int64_t> &row_ptr, int64_t chunk_entries) {
+    ChunkTable t;
+    const int32_t S = static_cast<int32_t>(row_ptr.size()) - 1;
+    if (chunk_entries < 1) chunk_entries = INT64_MAX;
+    t.dest_chunk.resize(S + 1);
+    t.chunk_beg.reserve(S + 1);
+    for (int32_t d = 0; d < S; ++d) {
+        t.dest_chunk[d] = static_cast<int32_t>(t.chunk_dest.size());
+        int64_t lo = row_ptr[d], hi = row_ptr[d + 1], len = hi - lo;
+        int64_t nc = len <= chunk_entries ? 1 : (len + chunk_entries - 1) / chunk_entries;
+        for (int64_t c = 0; c < nc; ++c) {
+            t.chunk_beg.push_back(lo + len * c / nc);
+            t.chunk_dest.push_back(d);
+        }
+        if (nc > 1) t.one_per_dest = false;
+    }
+    t.dest_chunk[S] = static_cast<int32_t>(t.chunk_dest.size());
+    t.chunk_beg.push_back(row_ptr[S]);
+    t.n_chunks = static_cast<int64_t>(t.chunk_dest.size());
+    return t;
+}
+
+}  // namespace ephbte

@@ -1,0 +1,54 @@
+// Host-side channel layout: validation, canonicalisation and the
+// destination-sorted entry arrays (the paper's "target layer", Optimized GPU
+// algorithm step 1).  Pure host C++; no HIP calls.
+#pragma once
+
+#include <cstdint>
+#include <functional>
+#include <string>
+#include <vector>
+
+#include "ephbte.h"
+
+namespace ephbte {
+
+// Packed per-entry key: partner state in the high 29 bits, mode in the low 3.
+inline uint32_t pack_pnu(int32_t partner, int32_t mode) {
+    return (static_cast<uint32_t>(partner) << 3) | static_cast<uint32_t>(mode);
+}
+
+struct HostLayout {
+    int32_t S = 0;
+    int64_t n_channels = 0;
+    int64_t E = 0;                    // entries = 2 * n_channels
+    int32_t n_modes = 0;
+    int32_t nq[3] = {0, 0, 0};        // q grid
+    std::vector<int64_t> row_ptr;     // [S+1] entries of destination d: [row_ptr[d], row_ptr[d+1])
+    std::vector<uint32_t> pnu;        // [E] partner << 3 | mode, ascending inside a destination
+    std::vector<int32_t> ent_chan;    // [E] caller channel index of the entry
+    std::vector<uint32_t> kq;         // [S] k coordinates in q-grid units, 10 bits each (k0,k1,k2)
+};
+
+// Validates the problem and builds the layout.  On failure returns the
+// status and fills *err with a description.
+ephbte_status build_host_layout(const ephbte_problem *p, HostLayout *out, std::string *err);
+
+// Work-split of the destination segments into chunks of at most
+// chunk_entries entries (each destination gets at least one chunk, possibly
+// empty).  chunk_beg has n_chunks+1 boundaries; dest_chunk has S+1.
+struct ChunkTable {
+    std::vector<int64_t> chunk_beg;
+    std::vector<int32_t> chunk_dest;
+    std::vector<int32_t> dest_chunk;
+    int64_t n_chunks = 0;
+    bool one_per_dest = true;
+};
+ChunkTable make_chunks(const std::vector<int64_t> &row_ptr, int64_t chunk_entries);
+
+// Runs fn(t, begin, end) over [0, n) split into contiguous ranges on up to
+// `threads` host threads (deterministic partition).
+void parallel_ranges(int64_t n, int threads,
+                     const std::function<void(int, int64_t, int64_t)> &fn);
+int host_threads();
+
+}  // namespace ephbte

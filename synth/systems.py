@@ -361,6 +361,11 @@ def random_channel_system(n_states=40, n_channels=300, kn=4, n_modes=3, sigma=0.
     cj = rng.integers(0, S - 1, size=n_channels)
     cj = np.where(cj >= ci, cj + 1, cj)
     nu = rng.integers(0, n_modes, size=n_channels).astype(np.int8)
+    # drop repeated (unordered pair, mode) draws, keeping the first occurrence
+    key = (np.minimum(ci, cj) * S + np.maximum(ci, cj)) * 8 + nu
+    _, first = np.unique(key, return_index=True)
+    keep = np.sort(first)
+    ci, cj, nu = ci[keep], cj[keep], nu[keep]
     g2 = lognormal_g2(ci, cj, nu, seed)
     return System(name="random", kgrid=kgrid, qgrid=kgrid, state_k=state_k,
                   state_band=np.zeros(S, np.int8), eps=eps, n_modes=n_modes, hw=hw,

@@ -1,0 +1,399 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle.
+
+Error metric: normwise, err = max_s |I_gpu - I_ref| / max_s |I_ref|.  For
+FP32 the reference is the FP64 oracle on the FP32-rounded inputs, and the
+norm is max(max|I_ref|, 1e-2 max(in, out)) so that near-equilibrium vectors
+(in and out rates cancelling) are judged against their gross rates.
+Bars: 1e-10 (FP64, FP64 accumulation), 1e-5 (FP32, FP32 accumulation).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+import synth  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+TOL32 = 1e-5
+
+
+@pytest.fixture(scope="module")
+def E():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2511_03683_amd as lib
+    return lib
+
+
+def say(msg):
+    print(f"\n[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda:0")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def nerr(x, ref, scale=None):
+    s = np.abs(ref).max() if scale is None else scale
+    return float(np.abs(np.asarray(x) - ref).max() / max(s, 1e-300))
+
+
+def round32(s):
+    """Copy of a system with every floating input rounded to FP32."""
+    import copy
+    r = copy.copy(s)
+    r.eps = s.eps.astype(np.float32).astype(np.float64)
+    r.hw = s.hw.astype(np.float32).astype(np.float64)
+    r.g2 = s.g2.astype(np.float32).astype(np.float64)
+    return r
+
+
+def run_I(E, s, f, nph, dtype="f64", tuning=None):
+    plan = E.build_channels(s, dtype=dtype, device=0)
+    if tuning:
+        E.set_tuning(plan, **tuning)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    out = host(E.collision_integral(plan, dev(f, tdt), dev(nph, tdt)))
+    plan.close()
+    return out
+
+
+SYSTEMS = {
+    "parabolic8_c1occ": (lambda: synth.parabolic_system(8), lambda s: synth.c1_occupations(s)),
+    "parabolic8_random": (lambda: synth.parabolic_system(8), lambda s: synth.random_occupations(s, 3)),
+    "multiband": (lambda: synth.multiband_system(), lambda s: synth.random_occupations(s, 4)),
+    "random_order": (lambda: synth.random_channel_system(n_states=60, n_channels=900, seed=3),
+                     lambda s: synth.random_occupations(s, 5)),
+    "tb24": (lambda: synth.tb_system(kn=24, qn=12, target_states=400),
+             lambda s: synth.fermi_dirac(s.eps, 0.05, 300.0) * (0.9 + 0.2 * synth.random_occupations(s, 6))),
+}
+
+
+@pytest.mark.parametrize("name", list(SYSTEMS))
+def test_fp64_matches_oracle(E, name):
+    mk, occ = SYSTEMS[name]
+    s = mk()
+    f = np.clip(occ(s), 0, 1)
+    nph = s.nph(300.0)
+    say(f"fp64 collision {name} S={s.n_states} Nch={s.n_channels}")
+    I = run_I(E, s, f, nph)
+    ref = oracle.collision(s, f, nph)
+    assert nerr(I, ref) <= TOL64
+
+
+@pytest.mark.parametrize("name", list(SYSTEMS))
+def test_fp32_matches_oracle_on_rounded_inputs(E, name):
+    mk, occ = SYSTEMS[name]
+    s = mk()
+    f = np.clip(occ(s), 0, 1).astype(np.float32).astype(np.float64)
+    nph = s.nph(300.0).astype(np.float32).astype(np.float64)
+    say(f"fp32 collision {name} S={s.n_states} Nch={s.n_channels}")
+    I = run_I(E, s, f, nph, dtype="f32")
+    r = round32(s)
+    ref = oracle.collision(r, f, nph)
+    rin, rout = oracle.collision_inout(r, f, nph)
+    scale = max(np.abs(ref).max(), 1e-2 * max(rin.max(), rout.max()))
+    assert nerr(I, ref, scale) <= TOL32
+
+
+@pytest.mark.parametrize("tuning", [dict(chunk_entries=64), dict(chunk_entries=100, block_threads=64),
+                                    dict(chunk_entries=1000, block_threads=512),
+                                    dict(block_threads=128, xcd_map=2), dict(chunk_entries=7, xcd_map=1)])
+def test_split_segments_and_launch_shapes(E, tuning):
+    """Segments split over several workgroups (two-level reduction), other
+    block sizes and both chunk orders give the oracle's result."""
+    s = synth.parabolic_system(8)
+    f = synth.random_occupations(s, 9)
+    nph = s.nph(300.0)
+    say(f"fp64 collision tuning={tuning}")
+    I = run_I(E, s, f, nph, tuning=tuning)
+    assert nerr(I, oracle.collision(s, f, nph)) <= TOL64
+
+
+def test_deterministic_and_batched_columns(E):
+    s = synth.multiband_system()
+    nph = dev(s.nph(300.0))
+    plan = E.build_channels(s, device=0)
+    F = np.stack([synth.random_occupations(s, k) for k in range(3)])
+    say("determinism + strided batch")
+    I1 = host(E.collision_integral(plan, dev(F[0]), nph))
+    I1b = host(E.collision_integral(plan, dev(F[0]), nph))
+    assert np.array_equal(I1, I1b), "bitwise reproducible"
+    big = torch.zeros((3, s.n_states + 5), dtype=torch.float64, device="cuda:0")
+    big[:, :s.n_states] = dev(F)
+    Fv = big[:, :s.n_states]
+    out = torch.full((3, s.n_states + 3), 7.0, dtype=torch.float64, device="cuda:0")
+    E.collision_integral(plan, Fv, nph, out=out[:, :s.n_states])
+    got = host(out)
+    for b in range(3):
+        ref_b = host(E.collision_integral(plan, dev(F[b]), nph))
+        assert np.array_equal(got[b, :s.n_states], ref_b)
+        assert np.all(got[b, s.n_states:] == 7.0), "padding untouched"
+    plan.close()
+
+
+def test_invariants_on_gpu(E):
+    s = synth.parabolic_system(8)
+    nph = s.nph(300.0)
+    plan = E.build_channels(s, device=0)
+    say("invariants: Pauli, particle number")
+    for v in (0.0, 1.0):
+        I = host(E.collision_integral(plan, dev(np.full(s.n_states, v)), dev(nph)))
+        assert np.all(I == 0.0)
+    f = synth.random_occupations(s, 12)
+    I = host(E.collision_integral(plan, dev(f), dev(nph)))
+    assert abs(I.sum()) <= 1e-13 * np.abs(I).sum()
+    plan.close()
+
+
+def test_resonant_ladder_equilibrium_on_gpu(E):
+    s = synth.ladder_system()
+    nph = s.nph(300.0)
+    f_eq = synth.fermi_dirac(s.eps, 0.1, 300.0)
+    f_hot = synth.fermi_dirac(s.eps, 0.1, 900.0)
+    say("ladder equilibrium")
+    I_eq = run_I(E, s, f_eq, nph)
+    I_hot = run_I(E, s, f_hot, nph)
+    assert np.abs(I_eq).max() <= 1e-13 * np.abs(I_hot).max()
+
+
+def test_empty_and_isolated(E):
+    s = synth.random_channel_system(n_states=10, n_channels=0)
+    f = synth.random_occupations(s, 1)
+    say("empty channel list")
+    assert np.all(run_I(E, s, f, s.nph(300.0)) == 0.0)
+    s2 = synth.random_channel_system(n_states=30, n_channels=20, seed=8)
+    isolated = np.setdiff1d(np.arange(30), np.concatenate([s2.ch_i, s2.ch_j]))
+    assert isolated.size > 0
+    f2 = synth.random_occupations(s2, 2)
+    I2 = run_I(E, s2, f2, s2.nph(300.0))
+    assert np.all(I2[isolated] == 0.0)
+    assert nerr(I2, oracle.collision(s2, f2, s2.nph(300.0))) <= TOL64
+
+
+# ------------------------------------------------------------------ reverse mode
+@pytest.mark.parametrize("name", ["multiband", "random_order", "parabolic8_random"])
+def test_vjp_matches_oracle(E, name):
+    mk, occ = SYSTEMS[name]
+    s = mk()
+    f = np.clip(occ(s), 0, 1)
+    nph = s.nph(300.0)
+    lam = np.random.default_rng(2).normal(size=s.n_states)
+    plan = E.build_channels(s, device=0)
+    say(f"vjp {name}")
+    gf, gg = E.collision_vjp(plan, dev(f), dev(nph), dev(lam), want_f=True, gg2=True)
+    rf, rg = oracle.collision_vjp(s, f, nph, lam)
+    assert nerr(host(gf), rf) <= TOL64
+    assert nerr(host(gg), rg) <= TOL64
+    # accumulate adds onto the existing buffer
+    E.collision_vjp(plan, dev(f), dev(nph), dev(lam), want_f=False, gg2=gg, accumulate=True)
+    assert nerr(host(gg), 2 * rg) <= TOL64
+    # batched: dL/dg2 is summed over the vectors
+    lam2 = np.random.default_rng(3).normal(size=s.n_states)
+    F = np.stack([f, np.clip(occ(s)[::-1].copy(), 0, 1)])
+    L = np.stack([lam, lam2])
+    gfb, ggb = E.collision_vjp(plan, dev(F), dev(nph), dev(L), gg2=True)
+    r0 = oracle.collision_vjp(s, F[0], nph, L[0])
+    r1 = oracle.collision_vjp(s, F[1], nph, L[1])
+    assert nerr(host(gfb)[1], r1[0]) <= TOL64
+    assert nerr(host(ggb), r0[1] + r1[1]) <= TOL64
+    plan.close()
+
+
+def test_vjp_fp32(E):
+    s = synth.multiband_system()
+    f = synth.random_occupations(s, 4).astype(np.float32).astype(np.float64)
+    nph = s.nph(300.0).astype(np.float32).astype(np.float64)
+    lam = np.random.default_rng(2).normal(size=s.n_states).astype(np.float32).astype(np.float64)
+    plan = E.build_channels(s, dtype="f32", device=0)
+    say("vjp fp32")
+    gf, gg = E.collision_vjp(plan, dev(f, torch.float32), dev(nph, torch.float32),
+                             dev(lam, torch.float32), gg2=True)
+    rf, rg = oracle.collision_vjp(round32(s), f, nph, lam)
+    assert nerr(host(gf), rf) <= 1e-5
+    assert nerr(host(gg), rg) <= 1e-5
+    plan.close()
+
+
+def test_autograd_function(E):
+    from paper_2511_03683_amd.autograd import collision
+    s = synth.multiband_system()
+    plan = E.build_channels(s, device=0)
+    f = dev(synth.random_occupations(s, 1)).requires_grad_(True)
+    g2 = dev(s.g2).requires_grad_(True)
+    nph = dev(s.nph(300.0))
+    lam = dev(np.random.default_rng(0).normal(size=s.n_states))
+    say("autograd collision")
+    L = (collision(f, g2, plan, nph) * lam).sum()
+    L.backward()
+    rf, rg = oracle.collision_vjp(s, host(f), s.nph(300.0), host(lam))
+    assert nerr(host(f.grad), rf) <= TOL64
+    assert nerr(host(g2.grad), rg) <= TOL64
+    plan.close()
+
+
+def test_update_g2(E):
+    s = synth.multiband_system()
+    f = synth.random_occupations(s, 3)
+    nph = s.nph(300.0)
+    plan = E.build_channels(s, device=0)
+    g_new = s.g2 * np.linspace(0.5, 2.0, s.n_channels)
+    say("update_g2")
+    E.update_g2(plan, dev(g_new))
+    I = host(E.collision_integral(plan, dev(f), dev(nph)))
+    assert nerr(I, oracle.collision(s, f, nph, g2=g_new)) <= TOL64
+    plan.close()
+
+
+# ------------------------------------------------------------------ RK4
+def test_rt_step_matches_oracle_and_graph_replay(E):
+    s = synth.multiband_system()
+    nph = s.nph(300.0)
+    f0 = synth.random_occupations(s, 7)
+    dt, n = 0.5, 6
+    ref = f0.copy()
+    for _ in range(n):
+        ref = oracle.rk4_step(s, ref, nph, dt)
+    plan = E.build_channels(s, device=0)
+    say("rt_step eager/graph")
+    fe = dev(f0)
+    E.rt_step(plan, fe, dev(nph), dt, n, use_graph=False)
+    assert nerr(host(fe) - f0, ref - f0) <= TOL64
+    fg = dev(f0)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        E.rt_step(plan, fg, dev(nph), dt, n, use_graph=True)
+        E.rt_step(plan, fg, dev(nph), dt, 0, use_graph=True)
+    stream.synchronize()
+    assert np.array_equal(host(fg), host(fe)), "graph replay is bitwise equal to eager"
+    # replay the cached graph again and compare with eager twice as long
+    fe2 = dev(f0)
+    E.rt_step(plan, fe2, dev(nph), dt, 2 * n, use_graph=False)
+    with torch.cuda.stream(stream):
+        E.rt_step(plan, fg, dev(nph), dt, n, use_graph=True)
+    stream.synchronize()
+    assert np.array_equal(host(fg), host(fe2))
+    # batch of two vectors, null stream graph path
+    F = np.stack([f0, synth.random_occupations(s, 8)])
+    Ft = dev(F)
+    E.rt_step(plan, Ft, dev(nph), dt, n, use_graph=True)
+    ref1 = F[1].copy()
+    for _ in range(n):
+        ref1 = oracle.rk4_step(s, ref1, nph, dt)
+    got = host(Ft)
+    assert np.array_equal(got[0], host(fe))
+    assert nerr(got[1] - F[1], ref1 - F[1]) <= TOL64
+    plan.close()
+
+
+def test_rt_adjoint_matches_oracle(E):
+    s = synth.multiband_system(n_k=10, seed=23)
+    f0 = synth.random_occupations(s, 9) * 0.8 + 0.1
+    nph = s.nph(300.0)
+    dt, n = 0.5, 5
+    gT = np.random.default_rng(5).normal(size=s.n_states)
+    _, rf, rg = oracle.rk4_trajectory_grad(s, f0, nph, dt, n, gT)
+    plan = E.build_channels(s, device=0)
+    say("rt_adjoint")
+    outs = []
+    for ce in (1, 2, 5):
+        gf0, gg = E.rt_adjoint(plan, dev(f0), dev(nph), dt, n, ce, dev(gT), gg2=True)
+        outs.append((host(gf0), host(gg)))
+        assert nerr(outs[-1][0], rf) <= 1e-9
+        assert nerr(outs[-1][1], rg) <= 1e-9
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1]), \
+            "checkpointing does not change the gradient"
+    plan.close()
+
+
+def test_rt_solve_autograd(E):
+    from paper_2511_03683_amd.autograd import rt_solve
+    s = synth.multiband_system(n_k=10, seed=23)
+    plan = E.build_channels(s, device=0)
+    f0 = dev(synth.random_occupations(s, 9) * 0.8 + 0.1).requires_grad_(True)
+    g2 = dev(s.g2).requires_grad_(True)
+    nph = dev(s.nph(300.0))
+    eps = dev(s.eps)
+    say("rt_solve autograd")
+    fT = rt_solve(f0, g2, plan, nph, 0.5, 4, checkpoint_every=2)
+    L = (eps * fT).sum() / fT.sum()
+    L.backward()
+    gT = host((eps * fT.sum() - (eps * fT).sum()) / fT.sum() ** 2)
+    _, rf, rg = oracle.rk4_trajectory_grad(s, host(f0), s.nph(300.0), 0.5, 4, gT)
+    assert nerr(host(f0.grad), rf) <= 1e-9
+    assert nerr(host(g2.grad), rg) <= 1e-9
+    plan.close()
+
+
+# ------------------------------------------------------------------ transport
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_transport_matches_oracle(E, dtype):
+    s = synth.tb_system(kn=20, qn=10, target_states=300, sigma=0.05)
+    T = 300.0
+    f0 = synth.fermi_dirac(s.eps, -0.1, T)
+    nph = s.nph(T)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    plan = E.build_channels(s, dtype=dtype, device=0)
+    say(f"transport {dtype}")
+    k = 7
+    out = E.iterate_transport(plan, dev(f0, tdt), dev(s.vel, tdt), T, dev(nph, tdt), tol=0.0,
+                              max_iter=k, want_x=True)
+    assert not out["converged"] and out["iters"] == k
+    if dtype == "f64":
+        ref = oracle.transport_solve(s, f0, s.vel, T, nph, max_iter=k, stop_on_tol=False)
+        assert nerr(out["mu"], ref["mu"]) <= TOL64
+        assert nerr(host(out["x"]), ref["x"]) <= TOL64
+        conv = E.iterate_transport(plan, dev(f0), dev(s.vel), T, dev(nph), tol=1e-10, max_iter=500)
+        refc = oracle.transport_solve(s, f0, s.vel, T, nph, tol=1e-10, max_iter=500)
+        assert conv["converged"] and conv["iters"] == refc["iters"]
+        assert nerr(conv["mu"], refc["mu"]) <= 1e-9
+    else:
+        r = round32(s)
+        f32 = f0.astype(np.float32).astype(np.float64)
+        ref = oracle.transport_solve(r, f32, s.vel.astype(np.float32).astype(np.float64), T,
+                                     nph.astype(np.float32).astype(np.float64), max_iter=k,
+                                     stop_on_tol=False)
+        assert nerr(out["mu"], ref["mu"]) <= 1e-4
+    plan.close()
+
+
+# ------------------------------------------------------------------ full size
+@pytest.fixture(scope="module")
+def c2():
+    return synth.tb_system()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_full_size_sampled_parity(E, c2, dtype):
+    """The 100^3/50^3, ~2e8-channel system in the launch configuration the
+    benchmark times; the oracle evaluates 48 sampled destinations."""
+    s = c2
+    rng = np.random.default_rng(17)
+    f = np.clip(synth.fermi_dirac(s.eps, 0.05, 300.0) * (0.8 + 0.4 * rng.uniform(size=s.n_states)), 0, 1)
+    nph = s.nph(300.0)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    if dtype == "f32":
+        f = f.astype(np.float32).astype(np.float64)
+        nph = nph.astype(np.float32).astype(np.float64)
+    say(f"full-size {dtype} S={s.n_states} Nch={s.n_channels}")
+    plan = E.build_channels(s, dtype=dtype, device=0)
+    I = host(E.collision_integral(plan, dev(f, tdt), dev(nph, tdt)))
+    plan.close()
+    mask = np.zeros(s.n_states, bool)
+    mask[rng.choice(s.n_states, 48, replace=False)] = True
+    r = s if dtype == "f64" else round32(s)
+    ref = oracle.collision(r, f, nph, mask=mask)
+    assert abs(I.sum()) <= 1e-6 * np.abs(I).sum()
+    tol = TOL64 if dtype == "f64" else TOL32
+    assert nerr(I[mask], ref[mask], np.abs(I).max()) <= tol

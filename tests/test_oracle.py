@@ -70,6 +70,16 @@ def test_pauli_blocking(c1):
     assert np.all(oracle.collision(s, np.ones(s.n_states), nph) == 0.0)
 
 
+def test_in_minus_out_is_the_collision_integral(c1):
+    """Gross in- and out-scattering rates recombine to I (same Eq. 2 terms
+    regrouped by occupation product), and both are non-negative."""
+    s, f, nph = c1
+    rin, rout = oracle.collision_inout(s, f, nph)
+    I = oracle.collision(s, f, nph)
+    assert np.all(rin >= 0) and np.all(rout >= 0)
+    assert np.abs((rin - rout) - I).max() <= 1e-14 * rout.max()
+
+
 def test_linear_in_g2(c1):
     s, f, nph = c1
     I1 = oracle.collision(s, f, nph)
