@@ -37,6 +37,10 @@
  *   plan's device, read or written by work enqueued on `stream`.
  * Streams: `stream` is a hipStream_t passed as void* (0 = null stream).  Work
  *   is enqueued asynchronously; calls that return host scalars synchronise.
+ *   A plan's workspaces are shared by all its calls, so the library orders
+ *   them: a call on a different stream than the plan's previous call first
+ *   waits (device side) for that call's work.  Calls made while the caller is
+ *   capturing the stream into a graph are not ordered this way.
  * Errors: every call returns a status and never throws.  Arguments are checked
  *   before any work is enqueued; on error nothing is enqueued and
  *   ephbte_last_error() (thread-local) describes the failure.

@@ -76,6 +76,13 @@ def load_library(path: Optional[str] = None):
     if _LIB is not None:
         return _LIB
     path = path or LIB_PATH
+    # torch ships its own HIP runtime with the same soname as /opt/rocm's;
+    # importing it first makes this library bind to that one runtime instead
+    # of bringing a second copy into the process.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build the HIP library first "
                           "(python -m paper_2511_03683_amd.build_lib)")

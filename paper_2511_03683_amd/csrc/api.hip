@@ -90,6 +90,11 @@ struct ephbte_plan_s {
     double *host_red = nullptr;   // pinned
     hipStream_t own_stream = nullptr;
     hipEvent_t ev_a = nullptr, ev_b = nullptr;
+    // work of consecutive calls is ordered even across streams: the plan's
+    // workspaces are shared by every call
+    hipEvent_t ev_last = nullptr;
+    hipStream_t last_stream = nullptr;
+    bool has_last = false;
     std::vector<GraphEntry> graphs;
     int64_t ws_gen = 0;   // bumped whenever a workspace moves
     size_t layout_bytes = 0;
@@ -172,6 +177,7 @@ void free_plan(ephbte_plan P) {
     if (P->host_red) (void)hipHostFree(P->host_red);
     if (P->ev_a) (void)hipEventDestroy(P->ev_a);
     if (P->ev_b) (void)hipEventDestroy(P->ev_b);
+    if (P->ev_last) (void)hipEventDestroy(P->ev_last);
     if (P->own_stream) (void)hipStreamDestroy(P->own_stream);
     delete P;
 }
@@ -711,11 +717,40 @@ ephbte_status transport_impl(ephbte_plan P, const T *f0, const T *vel, double T_
     return EPHBTE_OK;
 }
 
-template <typename F> ephbte_status guarded(ephbte_plan P, F &&fn) {
+bool capturing(hipStream_t s) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &st) != hipSuccess) return false;
+    return st != hipStreamCaptureStatusNone;
+}
+
+// Orders this call's work after the previous call on the plan (if that ran
+// on another stream) and records completion for the next call.
+struct PlanUse {
+    ephbte_plan P;
+    hipStream_t s;
+    bool active = false;
+    PlanUse(ephbte_plan p, hipStream_t st) : P(p), s(st) {
+        if (capturing(s)) return;
+        if (!P->ev_last) HIPC(hipEventCreateWithFlags(&P->ev_last, hipEventDisableTiming));
+        if (P->has_last && P->last_stream != s) HIPC(hipStreamWaitEvent(s, P->ev_last, 0));
+        active = true;
+    }
+    void done() {
+        if (!active) return;
+        HIPC(hipEventRecord(P->ev_last, s));
+        P->last_stream = s;
+        P->has_last = true;
+    }
+};
+
+template <typename F> ephbte_status guarded(ephbte_plan P, void *stream, F &&fn) {
     if (!P) return fail(EPHBTE_INVALID_ARGUMENT, "plan is NULL");
     try {
         DeviceGuard g(P->device);
-        return fn();
+        PlanUse use(P, static_cast<hipStream_t>(stream));
+        ephbte_status st = fn();
+        use.done();
+        return st;
     } catch (const HipError &e) {
         return fail(EPHBTE_HIP_ERROR, std::string(e.where) + ": " + hipGetErrorString(e.e));
     } catch (const std::bad_alloc &) {
@@ -821,7 +856,7 @@ ephbte_status ephbte_build_channels(const ephbte_problem *problem, ephbte_plan *
 ephbte_status ephbte_collision_integral(ephbte_plan plan, int32_t batch, const void *f,
                                         int64_t ldf, const void *nph, void *I, int64_t ldi,
                                         void *stream) {
-    return guarded(plan, [&]() -> ephbte_status {
+    return guarded(plan, stream, [&]() -> ephbte_status {
         if (batch < 1 || batch > 65535) return fail(EPHBTE_INVALID_ARGUMENT, "batch must be in [1, 65535]");
         if (!f || !nph || !I) return fail(EPHBTE_INVALID_ARGUMENT, "f, nph and I must be non-NULL");
         if (ldf < plan->S || ldi < plan->S)
@@ -847,7 +882,7 @@ ephbte_status ephbte_collision_vjp(ephbte_plan plan, int32_t batch, const void *
                                    const void *nph, const void *gI, int64_t ldg, void *gf,
                                    int64_t ldgf, double *gg2, int32_t accumulate_gg2,
                                    void *stream) {
-    return guarded(plan, [&]() -> ephbte_status {
+    return guarded(plan, stream, [&]() -> ephbte_status {
         if (batch < 1 || batch > 65535) return fail(EPHBTE_INVALID_ARGUMENT, "batch must be in [1, 65535]");
         if (!f || !nph || !gI) return fail(EPHBTE_INVALID_ARGUMENT, "f, nph and gI must be non-NULL");
         if (ldf < plan->S || ldg < plan->S || (gf && ldgf < plan->S))
@@ -886,7 +921,7 @@ ephbte_status ephbte_collision_vjp(ephbte_plan plan, int32_t batch, const void *
 ephbte_status ephbte_rt_step(ephbte_plan plan, int32_t batch, void *f, int64_t ldf,
                              const void *nph, double dt_fs, int32_t n_steps, int32_t use_graph,
                              void *stream) {
-    return guarded(plan, [&]() -> ephbte_status {
+    return guarded(plan, stream, [&]() -> ephbte_status {
         if (batch < 1 || batch > 65535) return fail(EPHBTE_INVALID_ARGUMENT, "batch must be in [1, 65535]");
         if (!f || !nph) return fail(EPHBTE_INVALID_ARGUMENT, "f and nph must be non-NULL");
         if (ldf < plan->S) return fail(EPHBTE_INVALID_ARGUMENT, "ldf must be >= n_states");
@@ -905,7 +940,7 @@ ephbte_status ephbte_rt_step(ephbte_plan plan, int32_t batch, void *f, int64_t l
 ephbte_status ephbte_rt_adjoint(ephbte_plan plan, const void *f0, const void *nph, double dt_fs,
                                 int32_t n_steps, int32_t checkpoint_every, const void *gfT,
                                 void *gf0, double *gg2, int32_t accumulate_gg2, void *stream) {
-    return guarded(plan, [&]() -> ephbte_status {
+    return guarded(plan, stream, [&]() -> ephbte_status {
         if (!f0 || !nph || !gfT) return fail(EPHBTE_INVALID_ARGUMENT, "f0, nph and gfT must be non-NULL");
         if (n_steps < 1) return fail(EPHBTE_INVALID_ARGUMENT, "n_steps must be >= 1");
         if (checkpoint_every < 1) return fail(EPHBTE_INVALID_ARGUMENT, "checkpoint_every must be >= 1");
@@ -926,7 +961,7 @@ ephbte_status ephbte_iterate_transport(ephbte_plan plan, const void *f0, const v
                                        double T_K, const void *nph, double tol, int32_t max_iter,
                                        void *x_out, double *mobility, int32_t *iters,
                                        double *resid, void *stream) {
-    return guarded(plan, [&]() -> ephbte_status {
+    return guarded(plan, stream, [&]() -> ephbte_status {
         if (!f0 || !vel || !nph || !mobility)
             return fail(EPHBTE_INVALID_ARGUMENT, "f0, vel, nph and mobility must be non-NULL");
         if (!(T_K > 0.0) || !std::isfinite(T_K)) return fail(EPHBTE_INVALID_ARGUMENT, "T_K must be > 0");
@@ -944,7 +979,7 @@ ephbte_status ephbte_iterate_transport(ephbte_plan plan, const void *f0, const v
 }
 
 ephbte_status ephbte_update_g2(ephbte_plan plan, const double *g2, void *stream) {
-    return guarded(plan, [&]() -> ephbte_status {
+    return guarded(plan, stream, [&]() -> ephbte_status {
         if (!g2) return fail(EPHBTE_INVALID_ARGUMENT, "g2 must be non-NULL");
         hipStream_t s = as_stream(stream);
         if (plan->E == 0) return EPHBTE_OK;
@@ -962,7 +997,7 @@ ephbte_status ephbte_update_g2(ephbte_plan plan, const double *g2, void *stream)
 }
 
 ephbte_status ephbte_set_tuning(ephbte_plan plan, const ephbte_tuning *tuning) {
-    return guarded(plan, [&]() -> ephbte_status {
+    return guarded(plan, nullptr, [&]() -> ephbte_status {
         if (!tuning) return fail(EPHBTE_INVALID_ARGUMENT, "tuning is NULL");
         int bt = tuning->block_threads ? tuning->block_threads : plan->block_threads;
         if (bt != 64 && bt != 128 && bt != 256 && bt != 512)
@@ -981,7 +1016,7 @@ ephbte_status ephbte_set_tuning(ephbte_plan plan, const ephbte_tuning *tuning) {
 }
 
 ephbte_status ephbte_autotune(ephbte_plan plan, int32_t batch, ephbte_tuning *chosen) {
-    return guarded(plan, [&]() -> ephbte_status {
+    return guarded(plan, nullptr, [&]() -> ephbte_status {
         if (batch < 1 || batch > 65535) return fail(EPHBTE_INVALID_ARGUMENT, "batch must be in [1, 65535]");
         HIPC(hipDeviceSynchronize());
         const size_t es = esize(plan);

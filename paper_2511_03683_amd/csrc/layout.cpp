@@ -87,6 +87,21 @@ ephbte_status build_host_layout(const ephbte_problem *p, HostLayout *out, std::s
     const int nm = p->n_modes;
     for (int64_t x = 0; x < nq * nm; ++x)
         if (!std::isfinite(p->hw[x]) || p->hw[x] < 0.0) return bad("hw must be finite and >= 0");
+    // both orientations of a channel use their own q (q and -q); the two
+    // contributions cancel exactly only for tables even in q
+    for (int32_t a0 = 0; a0 < p->qgrid[0]; ++a0)
+        for (int32_t a1 = 0; a1 < p->qgrid[1]; ++a1)
+            for (int32_t a2 = 0; a2 < p->qgrid[2]; ++a2) {
+                int64_t q = (int64_t(a0) * p->qgrid[1] + a1) * p->qgrid[2] + a2;
+                int64_t m = (int64_t((p->qgrid[0] - a0) % p->qgrid[0]) * p->qgrid[1] +
+                             (p->qgrid[1] - a1) % p->qgrid[1]) * p->qgrid[2] +
+                            (p->qgrid[2] - a2) % p->qgrid[2];
+                for (int nu = 0; nu < nm; ++nu) {
+                    double x = p->hw[q * nm + nu], y = p->hw[m * nm + nu];
+                    if (std::fabs(x - y) > 1e-9 * std::max(std::fabs(x), std::fabs(y)))
+                        return bad("hw must be even in q (hw(-q) = hw(q))");
+                }
+            }
 
     HostLayout &L = *out;
     L.S = S;

@@ -154,9 +154,12 @@ def linear_index(coords: np.ndarray, grid) -> np.ndarray:
 
 
 def minimal_image_frac(coords: np.ndarray, grid) -> np.ndarray:
-    """Fractional coordinates folded into [-1/2, 1/2)."""
-    f = np.asarray(coords, dtype=np.float64) / np.asarray(grid, dtype=np.float64)
-    return f - np.floor(f + 0.5)
+    """Fractional coordinates folded into [-1/2, 1/2), via the integer minimal
+    image so that c and N - c give values of exactly opposite sign."""
+    c = np.asarray(coords, dtype=np.int64)
+    n = np.asarray(grid, dtype=np.int64)
+    m = (c + n // 2) % n - n // 2
+    return m.astype(np.float64) / n.astype(np.float64)
 
 
 def phonon_table(qgrid, a: float, debye_speeds_kms=(), einstein_eV=()) -> np.ndarray:
@@ -356,7 +359,9 @@ def random_channel_system(n_states=40, n_channels=300, kn=4, n_modes=3, sigma=0.
     S = min(n_states, kn ** 3)
     state_k = rng.choice(kn ** 3, size=S, replace=False).astype(np.int32)
     eps = rng.uniform(0.0, e_max, size=S)
-    hw = rng.uniform(0.005, 0.06, size=(kn ** 3, n_modes))
+    h = rng.uniform(0.005, 0.06, size=(kn ** 3, n_modes))
+    minus_q = inverse_k(np.arange(kn ** 3), kgrid)
+    hw = 0.5 * (h + h[minus_q])                      # even in q, as time reversal requires
     ci = rng.integers(0, S, size=n_channels)
     cj = rng.integers(0, S - 1, size=n_channels)
     cj = np.where(cj >= ci, cj + 1, cj)

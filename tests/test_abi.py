@@ -143,6 +143,9 @@ def test_validation_errors():
     _bad(_mutate(ch_i=np.append(i, j[5]).astype(np.int32), ch_j=np.append(j, i[5]).astype(np.int32),
                  ch_nu=np.append(base.ch_nu, base.ch_nu[5]).astype(np.int8),
                  g2=np.append(base.g2, 1e-3)), "duplicate")
+    hw = base.hw.copy()
+    hw[1, 2] *= 1.5
+    _bad(_mutate(hw=hw), "even in q")
     sk = base.state_k.copy()
     sk[0] = 10 ** 6
     _bad(_mutate(state_k=sk), "state_k")
