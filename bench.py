@@ -41,6 +41,9 @@ def main():
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-channels", type=int, default=100_000_000)
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run a plain 1 GiB read + 1 GiB write elementwise kernel "
+                         "(hardware-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -54,6 +57,15 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream(device=dev)
+
+    if args.copy_calib:
+        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.mul(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 x (1 GiB read + 1 GiB write) elementwise kernels")
+        del a, b
 
     t0 = time.time()
     if args.quick:
