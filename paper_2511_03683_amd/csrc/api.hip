@@ -68,6 +68,8 @@ struct ephbte_plan_s {
     int nq[3] = {0, 0, 0};
     double sigma = 0, nqnorm = 0;
     std::vector<int64_t> row_ptr;   // host copy for re-chunking
+    std::vector<int32_t> pmin, pmax; // host: partner range of each destination
+    int n_cu = 256;
     // layout (device)
     uint32_t *pnu = nullptr;
     void *g2 = nullptr;
@@ -79,12 +81,21 @@ struct ephbte_plan_s {
     int32_t *chunk_dest = nullptr;
     int32_t *dest_chunk = nullptr;
     int64_t n_chunks = 0;
+    TileRec *tiles = nullptr;
+    int64_t n_tiles = 0;
+    // batched pass: tiles of destinations and per-destination sub-tile offsets
+    BTileRec *btiles = nullptr;
+    int64_t *sub_off = nullptr;
+    int64_t n_btiles = 0;
+    int pt = 0;                 // partners per sub-tile
+    int batch_min = 8;          // smallest B that uses the batched kernel
+    int lds_states = 0;
     bool fused = true;
     int chunk_entries = 0;
     int block_threads = 256;
     bool xcd_map = true;
     // workspaces, grown on demand
-    DevBuf part, rk_ua, rk_ub, rk_acc;
+    DevBuf part, rk_ua, rk_ub, rk_acc, hwN;
     DevBuf tr_W, tr_tau_inv, tr_tau, tr_rhs, tr_xa, tr_xb, tr_part, tr_red, tr_red2;
     DevBuf adj_ck, adj_U, adj_la, adj_lb, adj_acc, adj_g, adj_f;
     double *host_red = nullptr;   // pinned
@@ -101,7 +112,7 @@ struct ephbte_plan_s {
 
     size_t bytes() const {
         size_t b = layout_bytes;
-        const DevBuf *w[] = {&part,  &rk_ua, &rk_ub, &rk_acc, &tr_W,  &tr_tau_inv, &tr_tau,
+        const DevBuf *w[] = {&part,  &rk_ua, &rk_ub, &rk_acc, &hwN, &tr_W,  &tr_tau_inv, &tr_tau,
                              &tr_rhs, &tr_xa, &tr_xb, &tr_part, &tr_red, &tr_red2, &adj_ck,
                              &adj_U, &adj_la, &adj_lb, &adj_acc, &adj_g, &adj_f};
         for (auto *x : w) b += x->bytes;
@@ -167,9 +178,10 @@ void free_plan(ephbte_plan P) {
     free_graphs(P);
     void **ptrs[] = {(void **)&P->pnu,       (void **)&P->g2,         (void **)&P->st,
                      (void **)&P->hw,        (void **)&P->ent_chan,   (void **)&P->chunk_beg,
-                     (void **)&P->chunk_dest, (void **)&P->dest_chunk};
+                     (void **)&P->chunk_dest, (void **)&P->dest_chunk, (void **)&P->tiles,
+                     (void **)&P->btiles,    (void **)&P->sub_off};
     for (auto pp : ptrs) dfree(*pp);
-    DevBuf *w[] = {&P->part,   &P->rk_ua,  &P->rk_ub,   &P->rk_acc, &P->tr_W,   &P->tr_tau_inv,
+    DevBuf *w[] = {&P->part,   &P->rk_ua,  &P->rk_ub,   &P->rk_acc, &P->hwN, &P->tr_W,   &P->tr_tau_inv,
                    &P->tr_tau, &P->tr_rhs, &P->tr_xa,   &P->tr_xb,  &P->tr_part, &P->tr_red,
                    &P->tr_red2, &P->adj_ck, &P->adj_U,  &P->adj_la, &P->adj_lb, &P->adj_acc,
                    &P->adj_g,  &P->adj_f};
@@ -203,6 +215,15 @@ void upload_chunks(ephbte_plan P, int64_t chunk_entries) {
     P->n_chunks = t.n_chunks;
     P->fused = t.one_per_dest;
     P->chunk_entries = static_cast<int>(std::min<int64_t>(chunk_entries, INT32_MAX));
+    // tiles: about 8 per compute unit, each at least a few chunks
+    const int64_t target = std::max<int64_t>(P->E / (8 * static_cast<int64_t>(P->n_cu)) + 1,
+                                             4 * static_cast<int64_t>(std::max(1, P->chunk_entries)));
+    std::vector<Tile> tl = make_tiles(t, P->row_ptr, P->pmin, P->pmax, P->lds_states, target);
+    static_assert(sizeof(Tile) == sizeof(TileRec), "tile record layout");
+    dfree(reinterpret_cast<void *&>(P->tiles));
+    dalloc(P->tiles, tl.size() * sizeof(TileRec), &dummy);
+    HIPC(hipMemcpy(P->tiles, tl.data(), tl.size() * sizeof(TileRec), hipMemcpyHostToDevice));
+    P->n_tiles = static_cast<int64_t>(tl.size());
 }
 
 template <typename T> Tables<T> tables(ephbte_plan P, const void *nph) {
@@ -230,6 +251,33 @@ template <typename T> Tables<T> tables(ephbte_plan P, const void *nph) {
     return t;
 }
 
+template <typename T> TiledArgs<T> tiled_args(ephbte_plan P) {
+    TiledArgs<T> a;
+    a.pnu = P->pnu;
+    a.g2 = static_cast<const T *>(P->g2);
+    a.st = static_cast<const StateRec<T> *>(P->st);
+    a.hwN = static_cast<const Pair2<T> *>(P->hwN.p);
+    a.chunk_beg = P->chunk_beg;
+    a.chunk_dest = P->chunk_dest;
+    a.dest_chunk = P->dest_chunk;
+    a.tiles = P->tiles;
+    a.n_chunks = P->n_chunks;
+    a.S = P->S;
+    a.nm = P->nm;
+    a.nq0 = P->nq[0];
+    a.nq1 = P->nq[1];
+    a.nq2 = P->nq[2];
+    a.lds_states = P->lds_states;
+    Tables<T> t = tables<T>(P, nullptr);
+    a.mc = t.mc;
+    a.K = t.K;
+    return a;
+}
+
+int64_t nqm_of(ephbte_plan P) {
+    return static_cast<int64_t>(P->nq[0]) * P->nq[1] * P->nq[2] * P->nm;
+}
+
 template <typename T> Epi<T> epi_store(T *out, int64_t ld) {
     Epi<T> e{};
     e.mode = EPI_STORE;
@@ -238,24 +286,79 @@ template <typename T> Epi<T> epi_store(T *out, int64_t ld) {
     return e;
 }
 
+constexpr int kBatchDPW = 4;       // destinations per wave in the batched kernel
+constexpr int kBatchThreads = 512;
+
+template <typename T> BArgs<T> batch_args(ephbte_plan P) {
+    BArgs<T> a;
+    a.pnu = P->pnu;
+    a.g2 = static_cast<const T *>(P->g2);
+    a.st = static_cast<const StateRec<T> *>(P->st);
+    a.hwN = static_cast<const Pair2<T> *>(P->hwN.p);
+    a.btiles = P->btiles;
+    a.sub_off = P->sub_off;
+    a.S = P->S;
+    a.nm = P->nm;
+    a.nq0 = P->nq[0];
+    a.nq1 = P->nq[1];
+    a.nq2 = P->nq[2];
+    a.pt = P->pt;
+    Tables<T> t = tables<T>(P, nullptr);
+    a.mc = t.mc;
+    a.K = t.K;
+    return a;
+}
+
+template <typename T>
+void enqueue_forward_batched(ephbte_plan P, int B, const T *f, int64_t ldf, const Epi<T> &E,
+                             hipStream_t s) {
+    const size_t shm = static_cast<size_t>(P->pt) * (65 * sizeof(T) + sizeof(StateRec<T>));
+    dim3 grid(static_cast<unsigned>(P->n_btiles), (B + 63) / 64);
+    hipLaunchKernelGGL((k_fwd_batched<T, kBatchDPW>), grid, dim3(kBatchThreads), shm, s,
+                       batch_args<T>(P), f, ldf, B, E);
+    HIPC(hipGetLastError());
+}
+
+// Interleave the plan's phonon energies with the caller's occupations into
+// one {hw, N} table (one gather per entry instead of two).
+template <typename T> void enqueue_pack(ephbte_plan P, const void *nph, hipStream_t s) {
+    const int64_t n = nqm_of(P);
+    hipLaunchKernelGGL((k_pack_hwN<T>), dim3(static_cast<unsigned>(std::min<int64_t>((n + 255) / 256, 4096))),
+                       dim3(256), 0, s, static_cast<const T *>(P->hw), static_cast<const T *>(nph),
+                       static_cast<Pair2<T> *>(P->hwN.p), n);
+}
+
+size_t tiled_lds_bytes(ephbte_plan P) {
+    const size_t es = P->dtype == EPHBTE_F64 ? 8 : 4;
+    return static_cast<size_t>(P->lds_states) * (2 * es + 4);
+}
+
 // Enqueue I[f] for B vectors with epilogue E (no allocation inside; the
-// caller ensured P->part is large enough).
+// caller ensured P->part and P->hwN are large enough).  pack = false when the
+// {hw, N} table already holds this call's occupations.
 template <typename T>
 void enqueue_forward(ephbte_plan P, int B, const T *f, int64_t ldf, const void *nph,
-                     const Epi<T> &E, hipStream_t s) {
-    Tables<T> t = tables<T>(P, nph);
-    dim3 grid(static_cast<unsigned>(grid_x(P)), B);
-    dim3 block(P->block_threads);
-    if (P->fused) {
-        hipLaunchKernelGGL((k_collision<T, true>), grid, block, 0, s, t, f, ldf, (T *)nullptr, E);
-    } else {
-        T *part = static_cast<T *>(P->part.p);
-        hipLaunchKernelGGL((k_collision<T, false>), grid, block, 0, s, t, f, ldf, part, E);
+                     const Epi<T> &E, hipStream_t s, bool pack = true) {
+    if (pack) enqueue_pack<T>(P, nph, s);
+    if (B >= P->batch_min && P->n_btiles > 0) {
+        enqueue_forward_batched<T>(P, B, f, ldf, E, s);
+        return;
+    }
+    TiledArgs<T> a = tiled_args<T>(P);
+    T *part = static_cast<T *>(P->part.p);
+    dim3 grid(static_cast<unsigned>(P->n_tiles), B);
+    hipLaunchKernelGGL((k_fwd_tiled<T, 4>), grid, dim3(P->block_threads), tiled_lds_bytes(P), s, a, f,
+                       ldf, part, E);
+    if (!P->fused) {
         dim3 g2((P->S + 255) / 256, B);
-        hipLaunchKernelGGL((k_collision_finish<T>), g2, dim3(256), 0, s, t, f, ldf,
-                           (const T *)part, E);
+        hipLaunchKernelGGL((k_tiled_finish<T>), g2, dim3(256), 0, s, a, f, ldf, (const T *)part, E);
     }
     HIPC(hipGetLastError());
+}
+
+template <typename T> void ensure_fwd(ephbte_plan P, int B) {
+    if (!P->fused) ensure(P->part, sizeof(T) * 2 * static_cast<size_t>(P->n_chunks) * B, &P->ws_gen);
+    ensure(P->hwN, sizeof(Pair2<T>) * static_cast<size_t>(std::max<int64_t>(nqm_of(P), 1)), &P->ws_gen);
 }
 
 template <typename T> void ensure_part(ephbte_plan P, int B, int per_chunk) {
@@ -450,16 +553,16 @@ void rk4_enqueue_step(ephbte_plan P, int B, T *f, int64_t ldf, const void *nph, 
     e.dt = dt;
     e.mode = EPI_RK1;
     e.u_out = ua;
-    enqueue_forward<T>(P, B, f_in, ld_in, nph, e, s);
+    enqueue_forward<T>(P, B, f_in, ld_in, nph, e, s, false);
     e.mode = EPI_RK2;
     e.u_out = ub;
-    enqueue_forward<T>(P, B, ua, S, nph, e, s);
+    enqueue_forward<T>(P, B, ua, S, nph, e, s, false);
     e.mode = EPI_RK3;
     e.u_out = ua;
-    enqueue_forward<T>(P, B, ub, S, nph, e, s);
+    enqueue_forward<T>(P, B, ub, S, nph, e, s, false);
     e.mode = EPI_RK4;
     e.f_out = f_out;
-    enqueue_forward<T>(P, B, ua, S, nph, e, s);
+    enqueue_forward<T>(P, B, ua, S, nph, e, s, false);
 }
 
 template <typename T>
@@ -469,10 +572,11 @@ ephbte_status rt_step_impl(ephbte_plan P, int B, T *f, int64_t ldf, const void *
     ensure(P->rk_ua, vec, &P->ws_gen);
     ensure(P->rk_ub, vec, &P->ws_gen);
     ensure(P->rk_acc, vec, &P->ws_gen);
-    ensure_part<T>(P, B, 2);
+    ensure_fwd<T>(P, B);
     T *ua = static_cast<T *>(P->rk_ua.p), *ub = static_cast<T *>(P->rk_ub.p);
     T *acc = static_cast<T *>(P->rk_acc.p);
     const T tdt = static_cast<T>(dt);
+    enqueue_pack<T>(P, nph, s);   // the phonon occupations hold for the whole call
     if (!use_graph || n_steps < 2) {
         for (int k = 0; k < n_steps; ++k)
             rk4_enqueue_step<T>(P, B, f, ldf, nph, tdt, s, ua, ub, acc, f, ldf, f);
@@ -544,6 +648,7 @@ ephbte_status rt_adjoint_impl(ephbte_plan P, const T *f0, const void *nph, doubl
     ensure(P->adj_g, v, &P->ws_gen);
     ensure(P->adj_f, v, &P->ws_gen);
     ensure_part<T>(P, 1, 2);
+    ensure_fwd<T>(P, 1);
     T *ua = static_cast<T *>(P->rk_ua.p), *ub = static_cast<T *>(P->rk_ub.p);
     T *racc = static_cast<T *>(P->rk_acc.p);
     T *ck = static_cast<T *>(P->adj_ck.p), *U = static_cast<T *>(P->adj_U.p);
@@ -551,6 +656,7 @@ ephbte_status rt_adjoint_impl(ephbte_plan P, const T *f0, const void *nph, doubl
     T *acc = static_cast<T *>(P->adj_acc.p), *gb = static_cast<T *>(P->adj_g.p);
     T *fw = static_cast<T *>(P->adj_f.p);
     const T tdt = static_cast<T>(dt);
+    enqueue_pack<T>(P, nph, s);
     // forward sweep, checkpoint every ce steps
     HIPC(hipMemcpyAsync(fw, f0, v, hipMemcpyDeviceToDevice, s));
     for (int k = 0; k < n; ++k) {
@@ -577,16 +683,16 @@ ephbte_status rt_adjoint_impl(ephbte_plan P, const T *f0, const void *nph, doubl
             r.dt = tdt;
             r.mode = EPI_RK1;
             r.u_out = u + S;
-            enqueue_forward<T>(P, 1, u, S, nph, r, s);
+            enqueue_forward<T>(P, 1, u, S, nph, r, s, false);
             r.mode = EPI_RK2;
             r.u_out = u + 2 * S;
-            enqueue_forward<T>(P, 1, u + S, S, nph, r, s);
+            enqueue_forward<T>(P, 1, u + S, S, nph, r, s, false);
             r.mode = EPI_RK3;
             r.u_out = u + 3 * S;
-            enqueue_forward<T>(P, 1, u + 2 * S, S, nph, r, s);
+            enqueue_forward<T>(P, 1, u + 2 * S, S, nph, r, s, false);
             r.mode = EPI_RK4;
             r.f_out = u + 4 * S;   // next step's u1 (one spare slot at the end)
-            enqueue_forward<T>(P, 1, u + 3 * S, S, nph, r, s);
+            enqueue_forward<T>(P, 1, u + 3 * S, S, nph, r, s, false);
         }
         // reverse sweep over the segment
         for (int k = s1 - 1; k >= s0; --k) {
@@ -836,11 +942,33 @@ ephbte_status ephbte_build_channels(const ephbte_problem *problem, ephbte_plan *
         P->sigma = problem->sigma;
         P->nqnorm = problem->n_q_norm;
         P->row_ptr = L.row_ptr;
+        P->pmin = L.pmin;
+        P->pmax = L.pmax;
+        int ncu = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            ncu > 0)
+            P->n_cu = ncu;
+        // LDS window per workgroup: {eps, f} + packed k = 20 B (FP64) / 12 B (FP32) per
+        // state, kept under 64 KB so two (FP64) or three (FP32) workgroups share a CU
+        P->lds_states = P->dtype == EPHBTE_F64 ? 3072 : 4096;
         if (P->dtype == EPHBTE_F64) upload_layout<double>(P, problem, L);
         else upload_layout<float>(P, problem, L);
+        {
+            P->pt = P->dtype == EPHBTE_F64 ? 96 : 192;
+            std::vector<BTile> bt;
+            std::vector<int64_t> so;
+            make_btiles(L, P->pt, kBatchDPW * (kBatchThreads / 64), 4096, &bt, &so);
+            static_assert(sizeof(BTile) == sizeof(BTileRec), "batch tile record layout");
+            dalloc(P->btiles, bt.size() * sizeof(BTileRec), &P->layout_bytes);
+            dalloc(P->sub_off, std::max<size_t>(so.size(), 1) * sizeof(int64_t), &P->layout_bytes);
+            HIPC(hipMemcpy(P->btiles, bt.data(), bt.size() * sizeof(BTileRec), hipMemcpyHostToDevice));
+            if (!so.empty())
+                HIPC(hipMemcpy(P->sub_off, so.data(), so.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+            P->n_btiles = static_cast<int64_t>(bt.size());
+        }
         { HostLayout tmp; std::swap(tmp, L); }
-        upload_chunks(P, 4096);
-        P->block_threads = 256;
+        P->block_threads = 512;
+        upload_chunks(P, 2048);
         HIPC(hipDeviceSynchronize());
     } catch (const HipError &e) {
         free_plan(P);
@@ -866,11 +994,11 @@ ephbte_status ephbte_collision_integral(ephbte_plan plan, int32_t batch, const v
             return fail(EPHBTE_INVALID_ARGUMENT, "I must not overlap f");
         hipStream_t s = as_stream(stream);
         if (plan->dtype == EPHBTE_F64) {
-            ensure_part<double>(plan, batch, 2);
+            ensure_fwd<double>(plan, batch);
             enqueue_forward<double>(plan, batch, static_cast<const double *>(f), ldf, nph,
                                     epi_store<double>(static_cast<double *>(I), ldi), s);
         } else {
-            ensure_part<float>(plan, batch, 2);
+            ensure_fwd<float>(plan, batch);
             enqueue_forward<float>(plan, batch, static_cast<const float *>(f), ldf, nph,
                                    epi_store<float>(static_cast<float *>(I), ldi), s);
         }
@@ -1044,8 +1172,8 @@ ephbte_status ephbte_autotune(ephbte_plan plan, int32_t batch, ephbte_tuning *ch
         hipEvent_t e0, e1;
         HIPC(hipEventCreate(&e0));
         HIPC(hipEventCreate(&e1));
-        const int chunk_c[] = {1024, 2048, 4096, 8192, 16384, 0};
-        const int thr_c[] = {128, 256, 512};
+        const int chunk_c[] = {1024, 2048, 4096, 8192};
+        const int thr_c[] = {256, 512};
         float best = INFINITY;
         int best_ce = plan->chunk_entries, best_bt = plan->block_threads;
         for (int ce : chunk_c)
@@ -1054,11 +1182,11 @@ ephbte_status ephbte_autotune(ephbte_plan plan, int32_t batch, ephbte_tuning *ch
                 upload_chunks(plan, ce);
                 auto once = [&]() {
                     if (plan->dtype == EPHBTE_F64) {
-                        ensure_part<double>(plan, batch, 2);
+                        ensure_fwd<double>(plan, batch);
                         enqueue_forward<double>(plan, batch, (const double *)f, S, nph,
                                                 epi_store<double>((double *)I, S), nullptr);
                     } else {
-                        ensure_part<float>(plan, batch, 2);
+                        ensure_fwd<float>(plan, batch);
                         enqueue_forward<float>(plan, batch, (const float *)f, S, nph,
                                                epi_store<float>((float *)I, S), nullptr);
                     }

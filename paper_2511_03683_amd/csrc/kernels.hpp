@@ -276,6 +276,313 @@ __global__ void k_collision_finish(Tables<T> P, const T *__restrict__ f, int64_t
     apply_epi(E, b, d, P.S, P.K * ((T(1) - fd) * bb - fd * a));
 }
 
+// ---- forward, LDS-tiled --------------------------------------------------
+// One workgroup per tile (a run of chunks whose destinations' partners fit an
+// LDS window).  The tile's partner states {eps, f} and packed k are staged in
+// LDS once; wave w then reduces chunks w, w + n_waves, ... of the tile, each
+// with a fixed shuffle tree.  A destination with a single chunk is finished
+// by that wave; others leave two partial sums for k_tiled_finish.  All loop
+// bounds are wave-uniform scalars (chunk index, entry range), so every wave
+// runs its loops in lock step with no divergent exits.
+struct TileRec {
+    int64_t c0, c1;
+    int32_t p_lo, p_hi, lds, pad;
+};
+
+template <typename T> struct alignas(2 * sizeof(T)) Pair2 {
+    T a, b;
+};
+
+template <typename T> struct TiledArgs {
+    const uint32_t *__restrict__ pnu;
+    const T *__restrict__ g2;
+    const StateRec<T> *__restrict__ st;
+    const Pair2<T> *__restrict__ hwN;   // [Nq * n_modes] {hw, N}
+    const int64_t *__restrict__ chunk_beg;
+    const int32_t *__restrict__ chunk_dest;
+    const int32_t *__restrict__ dest_chunk;
+    const TileRec *__restrict__ tiles;
+    int64_t n_chunks;
+    int S, nm, nq0, nq1, nq2, lds_states;
+    T mc, K;
+};
+
+template <typename T>
+__global__ void k_pack_hwN(const T *__restrict__ hw, const T *__restrict__ nph,
+                           Pair2<T> *__restrict__ out, int64_t n) {
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        Pair2<T> v;
+        v.a = hw[i];
+        v.b = nph[i];
+        out[i] = v;
+    }
+}
+
+template <typename T, bool LDS, int U>
+__device__ __forceinline__ void fwd_chunk(const TiledArgs<T> &A, const T *__restrict__ fb,
+                                          const Pair2<T> *s_ef, const uint32_t *s_kq, int p_lo,
+                                          int64_t c, int b, T *__restrict__ part,
+                                          const Epi<T> &E) {
+    const int lane = threadIdx.x & 63;
+    const int d = A.chunk_dest[c];
+    const int64_t beg = A.chunk_beg[c], end = A.chunk_beg[c + 1];
+    const StateRec<T> sd = A.st[d];
+    T acc_a = T(0), acc_b = T(0);
+    uint32_t pn[U];
+    T g[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t i = beg + u * 64 + lane;
+        pn[u] = i < end ? A.pnu[i] : 0u;
+        g[u] = i < end ? A.g2[i] : T(0);
+    }
+    for (int64_t e0 = beg; e0 < end; e0 += 64 * U) {
+        // next batch of the stream, issued before this batch's gathers
+        uint32_t pn_n[U];
+        T g_n[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = e0 + 64 * U + u * 64 + lane;
+            pn_n[u] = i < end ? A.pnu[i] : 0u;
+            g_n[u] = i < end ? A.g2[i] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (e0 + u * 64 + lane < end) {
+                const int p = static_cast<int>(pn[u] >> 3);
+                T ep, fp;
+                uint32_t kp;
+                if (LDS) {
+                    const Pair2<T> ef = s_ef[p - p_lo];
+                    ep = ef.a;
+                    fp = ef.b;
+                    kp = s_kq[p - p_lo];
+                } else {
+                    const StateRec<T> sp = A.st[p];
+                    ep = sp.eps;
+                    kp = sp.kq;
+                    fp = fb[p];
+                }
+                const int q = q_linear(sd.kq, kp, A.nq0, A.nq1, A.nq2);
+                const Pair2<T> wn = A.hwN[static_cast<int64_t>(q) * A.nm + (pn[u] & 7u)];
+                const T de = sd.eps - ep;
+                const T xa = de + wn.a, xe = de - wn.a;
+                const T da = gauss_exp(xa * xa * A.mc);
+                const T dem = gauss_exp(xe * xe * A.mc);
+                const T t = wn.b * (da + dem);
+                acc_a += g[u] * (t + dem) * (T(1) - fp);
+                acc_b += g[u] * (t + da) * fp;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            pn[u] = pn_n[u];
+            g[u] = g_n[u];
+        }
+    }
+    acc_a = wave_sum(acc_a);
+    acc_b = wave_sum(acc_b);
+    if (lane == 0) {
+        if (A.dest_chunk[d + 1] - A.dest_chunk[d] == 1) {
+            const T fd = fb[d];
+            apply_epi(E, b, d, A.S, A.K * ((T(1) - fd) * acc_b - fd * acc_a));
+        } else {
+            T *pp = part + (static_cast<int64_t>(b) * A.n_chunks + c) * 2;
+            pp[0] = acc_a;
+            pp[1] = acc_b;
+        }
+    }
+}
+
+template <typename T, int U>
+__global__ __launch_bounds__(512) void k_fwd_tiled(TiledArgs<T> A, const T *__restrict__ f,
+                                                   int64_t ldf, T *__restrict__ part, Epi<T> E) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const TileRec t = A.tiles[blockIdx.x];
+    const int b = blockIdx.y;
+    const T *fb = f + static_cast<int64_t>(b) * ldf;
+    Pair2<T> *s_ef = reinterpret_cast<Pair2<T> *>(smem);
+    uint32_t *s_kq = reinterpret_cast<uint32_t *>(s_ef + A.lds_states);
+    if (t.lds) {
+        const int n = t.p_hi - t.p_lo + 1;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            const StateRec<T> sr = A.st[t.p_lo + i];
+            Pair2<T> ef;
+            ef.a = sr.eps;
+            ef.b = fb[t.p_lo + i];
+            s_ef[i] = ef;
+            s_kq[i] = sr.kq;
+        }
+    }
+    __syncthreads();
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    const int nw = static_cast<int>(blockDim.x >> 6);
+    for (int64_t c = t.c0 + wave; c < t.c1; c += nw) {
+        if (t.lds)
+            fwd_chunk<T, true, U>(A, fb, s_ef, s_kq, t.p_lo, c, b, part, E);
+        else
+            fwd_chunk<T, false, U>(A, fb, s_ef, s_kq, t.p_lo, c, b, part, E);
+    }
+}
+
+// destinations with several chunks: sum their partials in chunk order
+template <typename T>
+__global__ void k_tiled_finish(TiledArgs<T> A, const T *__restrict__ f, int64_t ldf,
+                               const T *__restrict__ part, Epi<T> E) {
+    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= A.S) return;
+    const int c0 = A.dest_chunk[d], c1 = A.dest_chunk[d + 1];
+    if (c1 - c0 == 1) return;
+    const int b = blockIdx.y;
+    const T *pb = part + static_cast<int64_t>(b) * A.n_chunks * 2;
+    T a = T(0), bb = T(0);
+    for (int c = c0; c < c1; ++c) {
+        a += pb[2 * c];
+        bb += pb[2 * c + 1];
+    }
+    const T fd = f[static_cast<int64_t>(b) * ldf + d];
+    apply_epi(E, b, d, A.S, A.K * ((T(1) - fd) * bb - fd * a));
+}
+
+// ---- forward, batched (B vectors in one pass) -----------------------------
+// Workgroup = batch tile: up to DPW destinations per wave, consecutive
+// destinations sharing a partner window.  The window is walked in sub-tiles
+// of PT partners; for each, f[p][0:64] (64 vectors, transposed, padded) and
+// the partners' {eps, k} are staged in LDS.  For each of its destinations a
+// wave then computes the coefficients of the entries whose partner lies in
+// the sub-tile (lane = entry), merges entries with the same partner by a
+// segmented shuffle reduction, and applies every merged coefficient pair to
+// the 64 vectors (lane = vector):
+//   acc_a[b] += a_p (1 - f_{p,b}),  acc_b[b] += b_p f_{p,b}.
+// Each entry's coefficients are evaluated once per pass, not once per vector.
+struct BTileRec {
+    int32_t d0, d1;        // destinations [d0, d1)
+    int32_t p_lo, n_sub;   // window start and number of sub-tiles
+    int64_t off_base;      // sub_off index of destination d0
+};
+
+template <typename T> struct BArgs {
+    const uint32_t *__restrict__ pnu;
+    const T *__restrict__ g2;
+    const StateRec<T> *__restrict__ st;
+    const Pair2<T> *__restrict__ hwN;
+    const BTileRec *__restrict__ btiles;
+    const int64_t *__restrict__ sub_off;   // per destination: n_sub + 1 entry offsets
+    int S, nm, nq0, nq1, nq2, pt;
+    T mc, K;
+};
+
+template <typename T> __device__ __forceinline__ T lane_bcast(T v, int src);
+template <> __device__ __forceinline__ double lane_bcast(double v, int src) {
+    const long long bits = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane(static_cast<int>(bits & 0xffffffffLL), src);
+    const int hi = __builtin_amdgcn_readlane(static_cast<int>(bits >> 32), src);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) |
+                                (static_cast<long long>(lo) & 0xffffffffLL));
+}
+template <> __device__ __forceinline__ float lane_bcast(float v, int src) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+
+template <typename T, int DPW>
+__global__ __launch_bounds__(512) void k_fwd_batched(BArgs<T> A, const T *__restrict__ f,
+                                                     int64_t ldf, int B, Epi<T> E) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int PT = A.pt;
+    T *s_F = reinterpret_cast<T *>(smem);                                   // [PT][65]
+    StateRec<T> *s_ek = reinterpret_cast<StateRec<T> *>(s_F + PT * 65);    // [PT]
+    const BTileRec t = A.btiles[blockIdx.x];
+    const int b0 = blockIdx.y * 64;
+    const int nb = min(64, B - b0);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    const int nw = static_cast<int>(blockDim.x >> 6);
+    const int nd = t.d1 - t.d0;
+    T acc_a[DPW], acc_b[DPW];
+#pragma unroll
+    for (int j = 0; j < DPW; ++j) {
+        acc_a[j] = T(0);
+        acc_b[j] = T(0);
+    }
+    for (int k = 0; k < t.n_sub; ++k) {
+        const int pa = t.p_lo + k * PT;
+        const int pc = min(PT, A.S - pa);
+        __syncthreads();
+        for (int i = threadIdx.x; i < pc * nb; i += blockDim.x) {
+            const int bb = i / pc, pl = i - bb * pc;
+            s_F[pl * 65 + bb] = f[static_cast<int64_t>(b0 + bb) * ldf + pa + pl];
+        }
+        for (int i = threadIdx.x; i < pc; i += blockDim.x) s_ek[i] = A.st[pa + i];
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < DPW; ++j) {
+            const int dl = wave + j * nw;
+            if (dl < nd) {
+                const int d = t.d0 + dl;
+                const int64_t *so = A.sub_off + t.off_base + static_cast<int64_t>(dl) * (t.n_sub + 1);
+                const int64_t e_lo = so[k], e_hi = so[k + 1];
+                const StateRec<T> sd = A.st[d];
+                for (int64_t e0 = e_lo; e0 < e_hi; e0 += 64) {
+                    const int64_t e = e0 + lane;
+                    const bool valid = e < e_hi;
+                    int pl = -1 - lane;     // distinct for invalid lanes: never merged
+                    T ca = T(0), cb = T(0);
+                    if (valid) {
+                        const uint32_t pn = A.pnu[e];
+                        const T g = A.g2[e];
+                        pl = static_cast<int>(pn >> 3) - pa;
+                        const StateRec<T> sp = s_ek[pl];
+                        const int q = q_linear(sd.kq, sp.kq, A.nq0, A.nq1, A.nq2);
+                        const Pair2<T> wn = A.hwN[static_cast<int64_t>(q) * A.nm + (pn & 7u)];
+                        const T de = sd.eps - sp.eps;
+                        const T xa = de + wn.a, xe = de - wn.a;
+                        const T da = gauss_exp(xa * xa * A.mc);
+                        const T dem = gauss_exp(xe * xe * A.mc);
+                        const T tt = wn.b * (da + dem);
+                        ca = g * (tt + dem);
+                        cb = g * (tt + da);
+                    }
+                    // sum each run of equal partners into its first lane
+#pragma unroll
+                    for (int off = 1; off < 64; off <<= 1) {
+                        const T oa = __shfl_down(ca, off, 64);
+                        const T ob = __shfl_down(cb, off, 64);
+                        const int op = __shfl_down(pl, off, 64);
+                        if (lane + off < 64 && op == pl) {
+                            ca += oa;
+                            cb += ob;
+                        }
+                    }
+                    const int prev = __shfl_up(pl, 1, 64);
+                    const bool head = valid && (lane == 0 || prev != pl);
+                    unsigned long long m = __ballot(head);
+                    while (m) {
+                        const int src = __builtin_ctzll(m);
+                        m &= m - 1;
+                        const T a = lane_bcast(ca, src);
+                        const T bq = lane_bcast(cb, src);
+                        const int pls = __builtin_amdgcn_readlane(pl, src);
+                        const T fpb = s_F[pls * 65 + lane];
+                        acc_a[j] += a * (T(1) - fpb);
+                        acc_b[j] += bq * fpb;
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < DPW; ++j) {
+        const int dl = wave + j * nw;
+        if (dl < nd && lane < nb) {
+            const int d = t.d0 + dl;
+            const int b = b0 + lane;
+            const T fd = f[static_cast<int64_t>(b) * ldf + d];
+            apply_epi(E, b, d, A.S, A.K * ((T(1) - fd) * acc_b[j] - fd * acc_a[j]));
+        }
+    }
+}
+
 // ---- reverse: dL/df and dL/d|g|^2 ---------------------------------------
 // dL/df_d = -K sum_entries (lam_d - lam_p) (a (1 - f_p) + b f_p)
 // dL/dg2_c = K (lam_d - lam_p) (bh f_p (1 - f_d) - ah f_d (1 - f_p)), written by

@@ -247,6 +247,15 @@ ephbte_status build_host_layout(const ephbte_problem *p, HostLayout *out, std::s
         os << "duplicate (i, j, nu) channel at state " << dup_dest.load();
         return bad(os.str());
     }
+    // partners are sorted, so the range of destination d is its first and last entry
+    L.pmin.assign(S, 0);
+    L.pmax.assign(S, -1);
+    for (int32_t d = 0; d < S; ++d) {
+        if (L.row_ptr[d + 1] > L.row_ptr[d]) {
+            L.pmin[d] = static_cast<int32_t>(L.pnu[L.row_ptr[d]] >> 3);
+            L.pmax[d] = static_cast<int32_t>(L.pnu[L.row_ptr[d + 1] - 1] >> 3);
+        }
+    }
     return EPHBTE_OK;
 }
 
@@ -270,6 +279,85 @@ ChunkTable make_chunks(const std::vector<int64_t> &row_ptr, int64_t chunk_entrie
     t.chunk_beg.push_back(row_ptr[S]);
     t.n_chunks = static_cast<int64_t>(t.chunk_dest.size());
     return t;
+}
+
+std::vector<Tile> make_tiles(const ChunkTable &ct, const std::vector<int64_t> &row_ptr,
+                             const std::vector<int32_t> &pmin, const std::vector<int32_t> &pmax,
+                             int32_t lds_states, int64_t target_entries) {
+    (void)row_ptr;
+    std::vector<Tile> tiles;
+    if (target_entries < 1) target_entries = 1;
+    const int64_t n = ct.n_chunks;
+    int64_t c = 0;
+    while (c < n) {
+        Tile t{c, c, 0, -1, 1, 0};
+        int32_t lo = INT32_MAX, hi = -1;
+        int64_t ent = 0;
+        int kind = -1;   // 1 LDS, 0 global
+        while (c < n) {
+            const int32_t d = ct.chunk_dest[c];
+            const int64_t ce = ct.chunk_beg[c + 1] - ct.chunk_beg[c];
+            const bool has = pmax[d] >= pmin[d];
+            const int32_t nlo = has ? std::min(lo, pmin[d]) : lo;
+            const int32_t nhi = has ? std::max(hi, pmax[d]) : hi;
+            const int ckind = (!has || int64_t(pmax[d]) - pmin[d] + 1 <= lds_states) ? 1 : 0;
+            if (c > t.c0) {
+                if (ckind != kind || ent + ce > target_entries) break;
+                if (kind == 1 && has && int64_t(nhi) - nlo + 1 > lds_states) break;
+            } else {
+                kind = ckind;
+            }
+            if (kind == 1) {
+                lo = nlo;
+                hi = nhi;
+            }
+            ent += ce;
+            ++c;
+        }
+        t.c1 = c;
+        t.lds = kind;
+        if (kind == 1 && hi >= lo) {
+            t.p_lo = lo;
+            t.p_hi = hi;
+        }
+        tiles.push_back(t);
+    }
+    return tiles;
+}
+
+void make_btiles(const HostLayout &L, int32_t pt, int32_t dmax, int32_t window_cap,
+                 std::vector<BTile> *tiles, std::vector<int64_t> *sub_off) {
+    tiles->clear();
+    sub_off->clear();
+    const int32_t S = L.S;
+    int32_t d = 0;
+    while (d < S) {
+        BTile t{d, d, 0, 0, static_cast<int64_t>(sub_off->size())};
+        int32_t lo = INT32_MAX, hi = -1;
+        while (d < S && d - t.d0 < dmax) {
+            const bool has = L.pmax[d] >= L.pmin[d];
+            const int32_t nlo = has ? std::min(lo, L.pmin[d]) : lo;
+            const int32_t nhi = has ? std::max(hi, L.pmax[d]) : hi;
+            if (d > t.d0 && has && int64_t(nhi) - nlo + 1 > window_cap) break;
+            lo = nlo;
+            hi = nhi;
+            ++d;
+        }
+        t.d1 = d;
+        if (hi >= lo) {
+            t.p_lo = lo;
+            t.n_sub = static_cast<int32_t>((int64_t(hi) - lo + pt) / pt);
+        }
+        for (int32_t x = t.d0; x < t.d1; ++x) {
+            const auto b = L.pnu.begin() + L.row_ptr[x], e = L.pnu.begin() + L.row_ptr[x + 1];
+            for (int32_t k = 0; k <= t.n_sub; ++k) {
+                const int64_t p = int64_t(t.p_lo) + int64_t(k) * pt;
+                const uint32_t key = p >= S ? UINT32_MAX : static_cast<uint32_t>(p) << 3;
+                sub_off->push_back(std::lower_bound(b, e, key) - L.pnu.begin());
+            }
+        }
+        tiles->push_back(t);
+    }
 }
 
 }  // namespace ephbte

@@ -27,6 +27,7 @@ struct HostLayout {
     std::vector<uint32_t> pnu;        // [E] partner << 3 | mode, ascending inside a destination
     std::vector<int32_t> ent_chan;    // [E] caller channel index of the entry
     std::vector<uint32_t> kq;         // [S] k coordinates in q-grid units, 10 bits each (k0,k1,k2)
+    std::vector<int32_t> pmin, pmax;  // [S] smallest / largest partner of each destination
 };
 
 // Validates the problem and builds the layout.  On failure returns the
@@ -44,6 +45,32 @@ struct ChunkTable {
     bool one_per_dest = true;
 };
 ChunkTable make_chunks(const std::vector<int64_t> &row_ptr, int64_t chunk_entries);
+
+// Workgroup tiles: runs of consecutive chunks [c0, c1).  When the partners of
+// all their destinations lie in [p_lo, p_hi] with at most lds_states states,
+// the tile stages those partners in LDS (lds = 1); a chunk whose destination's
+// partners span more than lds_states states goes to a global-memory tile.
+// Each tile holds at most target_entries entries (at least one chunk).
+struct Tile {
+    int64_t c0, c1;        // chunks [c0, c1)
+    int32_t p_lo, p_hi;    // LDS window of partner states (inclusive; empty if p_hi < p_lo)
+    int32_t lds;           // 1: partners staged in LDS, 0: read from global memory
+    int32_t pad;
+};
+std::vector<Tile> make_tiles(const ChunkTable &ct, const std::vector<int64_t> &row_ptr,
+                             const std::vector<int32_t> &pmin, const std::vector<int32_t> &pmax,
+                             int32_t lds_states, int64_t target_entries);
+
+// Batch tiles: up to dmax consecutive destinations whose partner ranges
+// span at most window_cap states (a single destination may exceed it).  For
+// every destination, sub_off holds n_sub + 1 entry offsets: entries with
+// partners in [p_lo + k pt, p_lo + (k+1) pt) are [sub_off[k], sub_off[k+1]).
+struct BTile {
+    int32_t d0, d1, p_lo, n_sub;
+    int64_t off_base;
+};
+void make_btiles(const HostLayout &L, int32_t pt, int32_t dmax, int32_t window_cap,
+                 std::vector<BTile> *tiles, std::vector<int64_t> *sub_off);
 
 // Runs fn(t, begin, end) over [0, n) split into contiguous ranges on up to
 // `threads` host threads (deterministic partition).
