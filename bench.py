@@ -144,6 +144,31 @@ def main():
         forms["transport_iter_f64"] = dict(ms_per_iteration=(t6 - t1) / 5.0, ms_setup_plus_one=t1)
         log(f"transport fp64: {(t6 - t1) / 5:.3f} ms/iteration, setup+1 {t1:.3f} ms")
         del vel, f0
+        # differentiation: adjoint through 200 RK4 steps (checkpoint every 20) of
+        # L = sum eps f(T) / sum f(T), FP64
+        eps = tens(s.eps, torch.float64)
+        fp0 = tens(synth.pulse_occupations(s), torch.float64)
+        fT = fp0.clone()
+        n_adj = 20 if args.quick else 200
+        with torch.cuda.stream(stream):
+            E.rt_step(plan64, fT, n64, 1.0, n_adj, use_graph=True)
+            gT = (eps * fT.sum() - (eps * fT).sum()) / fT.sum() ** 2
+        stream.synchronize()
+        gg2 = torch.zeros(nch, dtype=torch.float64, device=dev)
+        msa, _ = timed(lambda: E.rt_adjoint(plan64, fp0, n64, 1.0, n_adj, 20, gT, gg2=gg2), 1, 0)
+        forms["rt_adjoint_f64"] = dict(steps=n_adj, checkpoint_every=20, ms_total=msa,
+                                       ms_per_step=msa / n_adj,
+                                       collision_evaluations=8 * n_adj, vjp_calls=4 * n_adj,
+                                       loss="mean carrier energy at t = steps x 1 fs")
+        log(f"rt adjoint fp64 ({n_adj} steps): {msa:.1f} ms")
+        # FP64 reference trajectory for the FP32 dynamics check below
+        n_ref = 20 if args.quick else 200
+        fref = fp0.clone()
+        with torch.cuda.stream(stream):
+            E.rt_step(plan64, fref, n64, 1.0, n_ref, use_graph=True)
+        stream.synchronize()
+        E64_ref = float((eps * fref).sum() / fref.sum())
+        del gg2, fT, gT, fref
 
     plan64.close()
     del plan64, f64, I64
@@ -159,10 +184,25 @@ def main():
         forms["fwd_f32_b1"] = dict(ms=ms32, channels_per_s=nch / (ms32 * 1e-3),
                                    algorithmic_GBps=BYTES_PER_CHANNEL["f32"] * nch / (ms32 * 1e-3) / 1e9)
         log(f"fwd fp32: {ms32:.3f} ms")
-        fr = f32.clone()
-        msr, _ = timed(lambda: E.rt_step(plan32, fr, n32, 1.0, 4, use_graph=True), 2, 1)
-        forms["rt_step_f32_graph"] = dict(ms_per_step=msr / 4.0, evaluations_per_step=4)
-        log(f"rt step fp32: {msr / 4:.3f} ms/step")
+        # dynamics: hot pulse, phonons fixed at 300 K, RK4 dt = 1 fs in HIP graphs
+        n_dyn = 200 if args.quick else 2000
+        eps32 = tens(s.eps, torch.float64)
+        fr = tens(synth.pulse_occupations(s), torch.float32)
+        N0 = float(fr.double().sum())
+        with torch.cuda.stream(stream):
+            E.rt_step(plan32, fr, n32, 1.0, n_ref, use_graph=True)
+        stream.synchronize()
+        E32_ref = float((eps32 * fr.double()).sum() / fr.double().sum())
+        msr, wall_r = timed(lambda: E.rt_step(plan32, fr, n32, 1.0, n_dyn - n_ref, use_graph=True), 1, 0)
+        N1 = float(fr.double().sum())
+        forms["rt_bte_f32"] = dict(steps=n_dyn, dt_fs=1.0, ms_per_step=msr / (n_dyn - n_ref),
+                                   evaluations_per_step=4, wall_s=wall_r,
+                                   particle_drift=abs(N1 - N0) / N0,
+                                   mean_energy_rel_diff_vs_f64=abs(E32_ref - E64_ref) / abs(E64_ref),
+                                   compared_at_step=n_ref)
+        log(f"rt-BTE fp32: {msr / (n_dyn - n_ref):.3f} ms/step over {n_dyn - n_ref} steps, "
+            f"particle drift {abs(N1 - N0) / N0:.2e}, mean energy vs fp64 at step {n_ref}: "
+            f"{abs(E32_ref - E64_ref) / abs(E64_ref):.2e}")
         plan32.close()
 
     cpu = None

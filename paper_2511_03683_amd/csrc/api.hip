@@ -347,7 +347,7 @@ void enqueue_forward(ephbte_plan P, int B, const T *f, int64_t ldf, const void *
     TiledArgs<T> a = tiled_args<T>(P);
     T *part = static_cast<T *>(P->part.p);
     dim3 grid(static_cast<unsigned>(P->n_tiles), B);
-    hipLaunchKernelGGL((k_fwd_tiled<T, 4>), grid, dim3(P->block_threads), tiled_lds_bytes(P), s, a, f,
+    hipLaunchKernelGGL((k_fwd_tiled<T, 4, false, 512>), grid, dim3(P->block_threads), tiled_lds_bytes(P), s, a, f,
                        ldf, part, E);
     if (!P->fused) {
         dim3 g2((P->S + 255) / 256, B);

@@ -395,9 +395,114 @@ __device__ __forceinline__ void fwd_chunk(const TiledArgs<T> &A, const T *__rest
     }
 }
 
-template <typename T, int U>
-__global__ __launch_bounds__(512) void k_fwd_tiled(TiledArgs<T> A, const T *__restrict__ f,
-                                                   int64_t ldf, T *__restrict__ part, Epi<T> E) {
+// Same reduction as fwd_chunk with a three-stage software pipeline: while
+// batch i is evaluated, the phonon-table gathers of batch i+1 and the stream
+// loads of batch i+2 are already in flight.
+template <typename T, bool LDS, int U>
+__device__ __forceinline__ void fwd_chunk_pipe(const TiledArgs<T> &A, const T *__restrict__ fb,
+                                               const Pair2<T> *s_ef, const uint32_t *s_kq,
+                                               int p_lo, int64_t c, int b, T *__restrict__ part,
+                                               const Epi<T> &E) {
+    const int lane = threadIdx.x & 63;
+    const int d = A.chunk_dest[c];
+    const int64_t beg = A.chunk_beg[c], end = A.chunk_beg[c + 1];
+    const StateRec<T> sd = A.st[d];
+    T acc_a = T(0), acc_b = T(0);
+    // stage registers: stream (pn, g) for batch i+1, table/partner data for batch i
+    uint32_t pn1[U];
+    T g1[U];
+    T g0[U], de0[U], fp0[U];
+    Pair2<T> wn0[U];
+    auto load_stream = [&](int64_t e0, uint32_t (&pn)[U], T (&g)[U]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = e0 + u * 64 + lane;
+            pn[u] = i < end ? A.pnu[i] : 0u;
+            g[u] = i < end ? A.g2[i] : T(0);
+        }
+    };
+    // partner data + table gather for one batch (entries past the end get g = 0)
+    auto gather = [&](const uint32_t (&pn)[U], const T (&g)[U], int64_t e0, T (&go)[U],
+                      T (&deo)[U], T (&fpo)[U], Pair2<T> (&wno)[U]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool v = e0 + u * 64 + lane < end;
+            const int p = static_cast<int>(pn[u] >> 3);
+            T ep = T(0), fp = T(0);
+            uint32_t kp = sd.kq;
+            if (v) {
+                if (LDS) {
+                    const Pair2<T> ef = s_ef[p - p_lo];
+                    ep = ef.a;
+                    fp = ef.b;
+                    kp = s_kq[p - p_lo];
+                } else {
+                    const StateRec<T> sp = A.st[p];
+                    ep = sp.eps;
+                    kp = sp.kq;
+                    fp = fb[p];
+                }
+            }
+            if (v) {
+                const int q = q_linear(sd.kq, kp, A.nq0, A.nq1, A.nq2);
+                wno[u] = A.hwN[static_cast<int64_t>(q) * A.nm + (pn[u] & 7u)];
+            } else {
+                wno[u].a = T(0);
+                wno[u].b = T(0);
+            }
+            go[u] = v ? g[u] : T(0);
+            deo[u] = sd.eps - ep;
+            fpo[u] = fp;
+        }
+    };
+    {
+        uint32_t pn0[U];
+        T gs0[U];
+        load_stream(beg, pn0, gs0);
+        load_stream(beg + 64 * U, pn1, g1);
+        gather(pn0, gs0, beg, g0, de0, fp0, wn0);
+    }
+    for (int64_t e0 = beg; e0 < end; e0 += 64 * U) {
+        // batch i+1: table gathers now; batch i+2: stream loads now
+        T g1o[U], de1[U], fp1[U];
+        Pair2<T> wn1[U];
+        gather(pn1, g1, e0 + 64 * U, g1o, de1, fp1, wn1);
+        load_stream(e0 + 128 * U, pn1, g1);
+        // evaluate batch i (entries past the end carry g = 0)
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const T xa = de0[u] + wn0[u].a, xe = de0[u] - wn0[u].a;
+            const T da = gauss_exp(xa * xa * A.mc);
+            const T dem = gauss_exp(xe * xe * A.mc);
+            const T t = wn0[u].b * (da + dem);
+            acc_a += g0[u] * (t + dem) * (T(1) - fp0[u]);
+            acc_b += g0[u] * (t + da) * fp0[u];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            g0[u] = g1o[u];
+            de0[u] = de1[u];
+            fp0[u] = fp1[u];
+            wn0[u] = wn1[u];
+        }
+    }
+    acc_a = wave_sum(acc_a);
+    acc_b = wave_sum(acc_b);
+    if (lane == 0) {
+        if (A.dest_chunk[d + 1] - A.dest_chunk[d] == 1) {
+            const T fd = fb[d];
+            apply_epi(E, b, d, A.S, A.K * ((T(1) - fd) * acc_b - fd * acc_a));
+        } else {
+            T *pp = part + (static_cast<int64_t>(b) * A.n_chunks + c) * 2;
+            pp[0] = acc_a;
+            pp[1] = acc_b;
+        }
+    }
+}
+
+template <typename T, int U, bool PIPE, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_fwd_tiled(TiledArgs<T> A, const T *__restrict__ f,
+                                                    int64_t ldf, T *__restrict__ part, Epi<T> E) {
     extern __shared__ __align__(16) unsigned char smem[];
     const TileRec t = A.tiles[blockIdx.x];
     const int b = blockIdx.y;
@@ -419,10 +524,17 @@ __global__ __launch_bounds__(512) void k_fwd_tiled(TiledArgs<T> A, const T *__re
     const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
     const int nw = static_cast<int>(blockDim.x >> 6);
     for (int64_t c = t.c0 + wave; c < t.c1; c += nw) {
-        if (t.lds)
-            fwd_chunk<T, true, U>(A, fb, s_ef, s_kq, t.p_lo, c, b, part, E);
-        else
-            fwd_chunk<T, false, U>(A, fb, s_ef, s_kq, t.p_lo, c, b, part, E);
+        if (PIPE) {
+            if (t.lds)
+                fwd_chunk_pipe<T, true, U>(A, fb, s_ef, s_kq, t.p_lo, c, b, part, E);
+            else
+                fwd_chunk_pipe<T, false, U>(A, fb, s_ef, s_kq, t.p_lo, c, b, part, E);
+        } else {
+            if (t.lds)
+                fwd_chunk<T, true, U>(A, fb, s_ef, s_kq, t.p_lo, c, b, part, E);
+            else
+                fwd_chunk<T, false, U>(A, fb, s_ef, s_kq, t.p_lo, c, b, part, E);
+        }
     }
 }
 

@@ -509,3 +509,12 @@ def parabolic_states(n=60, a=20.0, m_eff=0.3) -> tuple:
     eps = (HBAR2_OVER_2ME / m_eff) * (kcart ** 2).sum(axis=1)
     vel = (kcart * (2.0 * HBAR2_OVER_2ME / m_eff) / HBAR_EV_FS) * 1e5
     return eps, vel
+
+
+def pulse_occupations(system: System, mu=-0.1, T=300.0, amplitude=0.1, center=0.5,
+                      width=0.05) -> np.ndarray:
+    """Fermi-Dirac background plus a Gaussian electron pulse:
+    f = FD(eps; mu, T) + amplitude * exp(-(eps - center)^2 / (2 width^2)), clipped to [0, 1]."""
+    e = np.asarray(system.eps, dtype=np.float64)
+    f = fermi_dirac(e, mu, T) + amplitude * np.exp(-0.5 * ((e - center) / width) ** 2)
+    return np.clip(f, 0.0, 1.0)
