@@ -91,6 +91,10 @@ struct ephbte_plan_s {
     int batch_min = 8;          // smallest B that uses the batched kernel
     int lds_states = 0;
     bool fused = true;
+    // phonon table indexed by padded k differences (one subtraction per entry)
+    bool padq = false;
+    int qoff = 0;
+    int64_t qpad_n = 0;         // padded q points
     int chunk_entries = 0;
     int block_threads = 256;
     bool xcd_map = true;
@@ -245,8 +249,8 @@ template <typename T> Tables<T> tables(ephbte_plan P, const void *nph) {
     t.nq1 = P->nq[1];
     t.nq2 = P->nq[2];
     const double s = P->sigma;
-    if (sizeof(T) == 8) t.mc = static_cast<T>(-1.0 / (2.0 * s * s));
-    else t.mc = static_cast<T>(-1.4426950408889634 / (2.0 * s * s));
+    // both precisions evaluate the Gaussian as 2^(x^2 mc)
+    t.mc = static_cast<T>(-1.4426950408889634 / (2.0 * s * s));
     t.K = static_cast<T>(2.0 * kPi / (kHbar * P->nqnorm) / (s * std::sqrt(2.0 * kPi)));
     return t;
 }
@@ -268,6 +272,8 @@ template <typename T> TiledArgs<T> tiled_args(ephbte_plan P) {
     a.nq1 = P->nq[1];
     a.nq2 = P->nq[2];
     a.lds_states = P->lds_states;
+    a.padq = P->padq ? 1 : 0;
+    a.qoff = P->qoff;
     Tables<T> t = tables<T>(P, nullptr);
     a.mc = t.mc;
     a.K = t.K;
@@ -303,6 +309,8 @@ template <typename T> BArgs<T> batch_args(ephbte_plan P) {
     a.nq1 = P->nq[1];
     a.nq2 = P->nq[2];
     a.pt = P->pt;
+    a.padq = P->padq ? 1 : 0;
+    a.qoff = P->qoff;
     Tables<T> t = tables<T>(P, nullptr);
     a.mc = t.mc;
     a.K = t.K;
@@ -322,6 +330,14 @@ void enqueue_forward_batched(ephbte_plan P, int B, const T *f, int64_t ldf, cons
 // Interleave the plan's phonon energies with the caller's occupations into
 // one {hw, N} table (one gather per entry instead of two).
 template <typename T> void enqueue_pack(ephbte_plan P, const void *nph, hipStream_t s) {
+    if (P->padq) {
+        const int64_t n = P->qpad_n * P->nm;
+        hipLaunchKernelGGL((k_pack_hwN_pad<T>),
+                           dim3(static_cast<unsigned>(std::min<int64_t>((n + 255) / 256, 8192))),
+                           dim3(256), 0, s, static_cast<const T *>(P->hw), static_cast<const T *>(nph),
+                           static_cast<Pair2<T> *>(P->hwN.p), P->nq[0], P->nq[1], P->nq[2], P->nm, n);
+        return;
+    }
     const int64_t n = nqm_of(P);
     hipLaunchKernelGGL((k_pack_hwN<T>), dim3(static_cast<unsigned>(std::min<int64_t>((n + 255) / 256, 4096))),
                        dim3(256), 0, s, static_cast<const T *>(P->hw), static_cast<const T *>(nph),
@@ -347,8 +363,12 @@ void enqueue_forward(ephbte_plan P, int B, const T *f, int64_t ldf, const void *
     TiledArgs<T> a = tiled_args<T>(P);
     T *part = static_cast<T *>(P->part.p);
     dim3 grid(static_cast<unsigned>(P->n_tiles), B);
-    hipLaunchKernelGGL((k_fwd_tiled<T, 4, false, 512>), grid, dim3(P->block_threads), tiled_lds_bytes(P), s, a, f,
-                       ldf, part, E);
+    if (P->padq)
+        hipLaunchKernelGGL((k_fwd_tiled<T, 4, true, 512, true, true>), grid, dim3(P->block_threads),
+                           tiled_lds_bytes(P), s, a, f, ldf, part, E);
+    else
+        hipLaunchKernelGGL((k_fwd_tiled<T, 4, true, 512, true, false>), grid, dim3(P->block_threads),
+                           tiled_lds_bytes(P), s, a, f, ldf, part, E);
     if (!P->fused) {
         dim3 g2((P->S + 255) / 256, B);
         hipLaunchKernelGGL((k_tiled_finish<T>), g2, dim3(256), 0, s, a, f, ldf, (const T *)part, E);
@@ -358,7 +378,8 @@ void enqueue_forward(ephbte_plan P, int B, const T *f, int64_t ldf, const void *
 
 template <typename T> void ensure_fwd(ephbte_plan P, int B) {
     if (!P->fused) ensure(P->part, sizeof(T) * 2 * static_cast<size_t>(P->n_chunks) * B, &P->ws_gen);
-    ensure(P->hwN, sizeof(Pair2<T>) * static_cast<size_t>(std::max<int64_t>(nqm_of(P), 1)), &P->ws_gen);
+    const int64_t tab = P->padq ? P->qpad_n * P->nm : nqm_of(P);
+    ensure(P->hwN, sizeof(Pair2<T>) * static_cast<size_t>(std::max<int64_t>(tab, 1)), &P->ws_gen);
 }
 
 template <typename T> void ensure_part(ephbte_plan P, int B, int per_chunk) {
@@ -501,12 +522,18 @@ bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
 
 size_t esize(ephbte_plan P) { return P->dtype == EPHBTE_F64 ? 8 : 4; }
 
+// entries read past the end of the last chunk by the unconditional stream
+// loads land in this zero padding
+constexpr int64_t kEntryPad = 4096;
+
 template <typename T> void upload_layout(ephbte_plan P, const ephbte_problem *pr, HostLayout &L) {
     size_t &acc = P->layout_bytes;
     const int64_t E = L.E, S = L.S;
-    dalloc(P->pnu, sizeof(uint32_t) * E, &acc);
+    dalloc(P->pnu, sizeof(uint32_t) * (E + kEntryPad), &acc);
     dalloc(P->ent_chan, sizeof(int32_t) * E, &acc);
-    dalloc(reinterpret_cast<T *&>(P->g2), sizeof(T) * E, &acc);
+    dalloc(reinterpret_cast<T *&>(P->g2), sizeof(T) * (E + kEntryPad), &acc);
+    HIPC(hipMemset(P->pnu + E, 0, sizeof(uint32_t) * kEntryPad));
+    HIPC(hipMemset(static_cast<T *>(P->g2) + E, 0, sizeof(T) * kEntryPad));
     dalloc(reinterpret_cast<StateRec<T> *&>(P->st), sizeof(StateRec<T>) * S, &acc);
     const int64_t nqm = static_cast<int64_t>(L.nq[0]) * L.nq[1] * L.nq[2] * L.n_modes;
     dalloc(reinterpret_cast<T *&>(P->hw), sizeof(T) * nqm, &acc);
@@ -525,6 +552,10 @@ template <typename T> void upload_layout(ephbte_plan P, const ephbte_problem *pr
             std::memset(&st[s], 0, sizeof(StateRec<T>));
             st[s].eps = static_cast<T>(pr->eps[s]);
             st[s].kq = L.kq[s];
+            if (P->padq) {
+                const uint32_t a0 = L.kq[s] >> 20, a1 = (L.kq[s] >> 10) & 1023u, a2 = L.kq[s] & 1023u;
+                st[s].kqp = (a0 * (2u * L.nq[1]) + a1) * (2u * L.nq[2]) + a2;
+            }
         }
         HIPC(hipMemcpy(P->st, st.data(), sizeof(StateRec<T>) * S, hipMemcpyHostToDevice));
     }
@@ -941,6 +972,15 @@ ephbte_status ephbte_build_channels(const ephbte_problem *problem, ephbte_plan *
         for (int a = 0; a < 3; ++a) P->nq[a] = L.nq[a];
         P->sigma = problem->sigma;
         P->nqnorm = problem->n_q_norm;
+        {
+            const int64_t qp = int64_t(2) * L.nq[0] * 2 * L.nq[1] * 2 * L.nq[2];
+            const size_t pair_bytes = P->dtype == EPHBTE_F64 ? 16 : 8;
+            if (qp * L.n_modes * static_cast<int64_t>(pair_bytes) <= (int64_t(256) << 20)) {
+                P->padq = true;
+                P->qpad_n = qp;
+                P->qoff = (L.nq[0] * (2 * L.nq[1]) + L.nq[1]) * (2 * L.nq[2]) + L.nq[2];
+            }
+        }
         P->row_ptr = L.row_ptr;
         P->pmin = L.pmin;
         P->pmax = L.pmax;
@@ -968,7 +1008,7 @@ ephbte_status ephbte_build_channels(const ephbte_problem *problem, ephbte_plan *
         }
         { HostLayout tmp; std::swap(tmp, L); }
         P->block_threads = 512;
-        upload_chunks(P, 2048);
+        upload_chunks(P, 8192);
         HIPC(hipDeviceSynchronize());
     } catch (const HipError &e) {
         free_plan(P);
@@ -1172,7 +1212,7 @@ ephbte_status ephbte_autotune(ephbte_plan plan, int32_t batch, ephbte_tuning *ch
         hipEvent_t e0, e1;
         HIPC(hipEventCreate(&e0));
         HIPC(hipEventCreate(&e1));
-        const int chunk_c[] = {1024, 2048, 4096, 8192};
+        const int chunk_c[] = {2048, 4096, 8192, 16384};
         const int thr_c[] = {256, 512};
         float best = INFINITY;
         int best_ce = plan->chunk_entries, best_bt = plan->block_threads;

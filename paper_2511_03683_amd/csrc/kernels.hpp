@@ -15,7 +15,8 @@
 // shuffle tree and waves through LDS in fixed order.  No atomics anywhere.
 //
 // Entry algebra (Eq. 2 with the golden-rule occupation factors).  With
-// da = exp(-(e_d - e_p + hw)^2 / 2 s^2), de = exp(-(e_d - e_p - hw)^2 / 2 s^2),
+// da = exp(-(e_d - e_p + hw)^2 / 2 s^2), de = exp(-(e_d - e_p - hw)^2 / 2 s^2)
+// (evaluated as powers of two),
 // t = N (da + de):
 //   a = g2 (t + de)  (weight of the out-scattering product f_d (1 - f_p))
 //   b = g2 (t + da)  (weight of the in-scattering product  f_p (1 - f_d))
@@ -28,21 +29,50 @@
 
 namespace ephbte {
 
+// kq:  k in q-grid units, 10 bits per axis (a0 << 20 | a1 << 10 | a2)
+// kqp: the same k as a linear index on a grid padded to (2 Nq0, 2 Nq1, 2 Nq2),
+//      so that kqp_p - kqp_d + offset is the padded index of q = k_p - k_d
+//      (each axis difference + Nq lies in [1, 2 Nq), so no borrow crosses axes)
 template <typename T> struct StateRec;
 template <> struct alignas(16) StateRec<double> {
     double eps;
     uint32_t kq;
-    uint32_t pad;
+    uint32_t kqp;
 };
-template <> struct alignas(8) StateRec<float> {
+template <> struct alignas(16) StateRec<float> {
     float eps;
     uint32_t kq;
+    uint32_t kqp;
+    uint32_t pad;
 };
 
-// exp of the (pre-scaled) Gaussian exponent: FP64 uses the accurate libm
-// exp; FP32 uses the hardware base-2 exponential with the log2(e) factor
-// folded into the exponent scale on the host.
-__device__ __forceinline__ double gauss_exp(double a) { return exp(a); }
+// Base-2 exponential of the (pre-scaled, never positive) Gaussian exponent;
+// the log2(e) factor is folded into the exponent scale on the host.
+// FP32: the hardware exponential.  FP64: y = n + r with n = rint(y), which
+// is exact, so |r| <= 1/2; 2^r = exp(r ln2) by its Taylor series to degree
+// 12 (truncation below 2e-16 relative for |r ln2| <= 0.347, Horner form);
+// 2^n by ldexp.  y is clamped at -1100, where the result is already 0.
+__device__ __forceinline__ double gauss_exp2(double y) {
+    y = fmax(y, -1100.0);
+    const double n = __builtin_rint(y);
+    const double r = y - n;
+    // coefficients (ln 2)^k / k!, k = 12 .. 0
+    double p = 2.5678435993488196e-11;
+    p = fma(p, r, 4.44553827187081e-10);
+    p = fma(p, r, 7.054911620801121e-09);
+    p = fma(p, r, 1.0178086009239696e-07);
+    p = fma(p, r, 1.3215486790144305e-06);
+    p = fma(p, r, 1.5252733804059838e-05);
+    p = fma(p, r, 0.00015403530393381606);
+    p = fma(p, r, 0.0013333558146428441);
+    p = fma(p, r, 0.009618129107628477);
+    p = fma(p, r, 0.055504108664821576);
+    p = fma(p, r, 0.2402265069591007);
+    p = fma(p, r, 0.6931471805599453);
+    p = fma(p, r, 1.0);
+    return ldexp(p, static_cast<int>(n));
+}
+__device__ __forceinline__ double gauss_exp(double a) { return gauss_exp2(a); }
 __device__ __forceinline__ float gauss_exp(float a) { return __builtin_amdgcn_exp2f(a); }
 
 // linear q index of k_p - k_d (both given in q-grid units, 10 bits per axis)
@@ -78,7 +108,7 @@ template <typename T> struct Tables {
     int64_t n_chunks;
     int64_t xcd_m;
     int S, nm, nq0, nq1, nq2;
-    T mc;   // Gaussian exponent scale (FP64: -1/(2 s^2); FP32: -log2(e)/(2 s^2))
+    T mc;   // Gaussian exponent scale, base 2: -log2(e) / (2 s^2)
     T K;    // 2 pi / (hbar N_q) / (s sqrt(2 pi))
 };
 
@@ -304,6 +334,8 @@ template <typename T> struct TiledArgs {
     const TileRec *__restrict__ tiles;
     int64_t n_chunks;
     int S, nm, nq0, nq1, nq2, lds_states;
+    int padq;          // 1: hwN is the padded table indexed by kqp differences
+    int qoff;          // padded index of q = 0 difference
     T mc, K;
 };
 
@@ -316,6 +348,138 @@ __global__ void k_pack_hwN(const T *__restrict__ hw, const T *__restrict__ nph,
         v.a = hw[i];
         v.b = nph[i];
         out[i] = v;
+    }
+}
+
+// Padded table: entry (qp, nu) holds {hw, N} of q = (c - Nq) mod Nq per axis,
+// where c are the axis coordinates of qp on the (2 Nq0, 2 Nq1, 2 Nq2) grid.
+template <typename T>
+__global__ void k_pack_hwN_pad(const T *__restrict__ hw, const T *__restrict__ nph,
+                               Pair2<T> *__restrict__ out, int n0, int n1, int n2, int nm,
+                               int64_t n) {
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int nu = static_cast<int>(i % nm);
+        int64_t qp = i / nm;
+        const int c2 = static_cast<int>(qp % (2 * n2));
+        qp /= 2 * n2;
+        const int c1 = static_cast<int>(qp % (2 * n1));
+        const int c0 = static_cast<int>(qp / (2 * n1));
+        int a0 = c0 - n0, a1 = c1 - n1, a2 = c2 - n2;
+        a0 += a0 < 0 ? n0 : 0;
+        a1 += a1 < 0 ? n1 : 0;
+        a2 += a2 < 0 ? n2 : 0;
+        const int64_t q = (static_cast<int64_t>(a0) * n1 + a1) * n2 + a2;
+        Pair2<T> v;
+        v.a = hw[q * nm + nu];
+        v.b = nph[q * nm + nu];
+        out[i] = v;
+    }
+}
+
+// Chunk reduction with a three-stage pipeline (stream loads two batches
+// ahead, partner/table gathers one batch ahead of the evaluation).  The entry
+// arrays are padded past their end, so stream loads are unconditional; lanes
+// past the chunk end read the padding or the next chunk and contribute zero.
+// Offsets are 32-bit and relative to the chunk start.
+template <typename T, bool LDS, bool PADQ, int U>
+__device__ __forceinline__ void fwd_chunk2(const TiledArgs<T> &A, const T *__restrict__ fb,
+                                           const Pair2<T> *s_ef, const uint32_t *s_kq, int p_lo,
+                                           int64_t c, int b, T *__restrict__ part,
+                                           const Epi<T> &E) {
+    const int lane = threadIdx.x & 63;
+    const int d = A.chunk_dest[c];
+    const int64_t beg = A.chunk_beg[c];
+    const int len = static_cast<int>(A.chunk_beg[c + 1] - beg);
+    const uint32_t *__restrict__ pb = A.pnu + beg;
+    const T *__restrict__ gb = A.g2 + beg;
+    const StateRec<T> sd = A.st[d];
+    const uint32_t kd = PADQ ? sd.kqp : sd.kq;
+    T acc_a = T(0), acc_b = T(0);
+    uint32_t pn1[U];
+    T gs1[U];
+    T g0[U], de0[U], fp0[U];
+    Pair2<T> wn0[U];
+    auto load_stream = [&](int r0, uint32_t (&pn)[U], T (&gs)[U]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            pn[u] = pb[r0 + u * 64 + lane];
+            gs[u] = gb[r0 + u * 64 + lane];
+        }
+    };
+    auto gather = [&](const uint32_t (&pn)[U], const T (&gs)[U], int r0, T (&go)[U],
+                      T (&deo)[U], T (&fpo)[U], Pair2<T> (&wno)[U]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool v = r0 + u * 64 + lane < len;
+            const int p = static_cast<int>(pn[u] >> 3);
+            T ep, fp;
+            uint32_t kp;
+            if (LDS) {
+                const int pl = v ? p - p_lo : 0;
+                const Pair2<T> ef = s_ef[pl];
+                ep = ef.a;
+                fp = ef.b;
+                kp = s_kq[pl];
+            } else {
+                const StateRec<T> sp = A.st[p];
+                ep = sp.eps;
+                kp = PADQ ? sp.kqp : sp.kq;
+                fp = fb[p];
+            }
+            const int q = PADQ ? static_cast<int>(kp - kd) + A.qoff
+                               : q_linear(kd, kp, A.nq0, A.nq1, A.nq2);
+            const Pair2<T> w = A.hwN[static_cast<int64_t>(q) * A.nm + (pn[u] & 7u)];
+            // lanes past the chunk end contribute nothing (a table entry without
+            // channels may hold a non-finite N, so both fields are replaced; using
+            // both keeps the {hw, N} pair a single 16-byte load)
+            wno[u].a = v ? w.a : T(0);
+            wno[u].b = v ? w.b : T(0);
+            go[u] = v ? gs[u] : T(0);
+            deo[u] = sd.eps - ep;
+            fpo[u] = fp;
+        }
+    };
+    {
+        uint32_t pn0[U];
+        T gs0[U];
+        load_stream(0, pn0, gs0);
+        load_stream(64 * U, pn1, gs1);
+        gather(pn0, gs0, 0, g0, de0, fp0, wn0);
+    }
+    for (int r = 0; r < len; r += 64 * U) {
+        T g1[U], de1[U], fp1[U];
+        Pair2<T> wn1[U];
+        gather(pn1, gs1, r + 64 * U, g1, de1, fp1, wn1);
+        load_stream(r + 128 * U, pn1, gs1);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const T xa = de0[u] + wn0[u].a, xe = de0[u] - wn0[u].a;
+            const T da = gauss_exp(xa * xa * A.mc);
+            const T dem = gauss_exp(xe * xe * A.mc);
+            const T t = wn0[u].b * (da + dem);
+            acc_a += g0[u] * (t + dem) * (T(1) - fp0[u]);
+            acc_b += g0[u] * (t + da) * fp0[u];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            g0[u] = g1[u];
+            de0[u] = de1[u];
+            fp0[u] = fp1[u];
+            wn0[u] = wn1[u];
+        }
+    }
+    acc_a = wave_sum(acc_a);
+    acc_b = wave_sum(acc_b);
+    if (lane == 0) {
+        if (A.dest_chunk[d + 1] - A.dest_chunk[d] == 1) {
+            const T fd = fb[d];
+            apply_epi(E, b, d, A.S, A.K * ((T(1) - fd) * acc_b - fd * acc_a));
+        } else {
+            T *pp = part + (static_cast<int64_t>(b) * A.n_chunks + c) * 2;
+            pp[0] = acc_a;
+            pp[1] = acc_b;
+        }
     }
 }
 
@@ -500,7 +664,7 @@ __device__ __forceinline__ void fwd_chunk_pipe(const TiledArgs<T> &A, const T *_
     }
 }
 
-template <typename T, int U, bool PIPE, int MAXT>
+template <typename T, int U, bool PIPE, int MAXT, bool V2 = false, bool PADQ = false>
 __global__ __launch_bounds__(MAXT) void k_fwd_tiled(TiledArgs<T> A, const T *__restrict__ f,
                                                     int64_t ldf, T *__restrict__ part, Epi<T> E) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -517,14 +681,19 @@ __global__ __launch_bounds__(MAXT) void k_fwd_tiled(TiledArgs<T> A, const T *__r
             ef.a = sr.eps;
             ef.b = fb[t.p_lo + i];
             s_ef[i] = ef;
-            s_kq[i] = sr.kq;
+            s_kq[i] = PADQ ? sr.kqp : sr.kq;
         }
     }
     __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
     const int nw = static_cast<int>(blockDim.x >> 6);
     for (int64_t c = t.c0 + wave; c < t.c1; c += nw) {
-        if (PIPE) {
+        if constexpr (V2) {
+            if (t.lds)
+                fwd_chunk2<T, true, PADQ, U>(A, fb, s_ef, s_kq, t.p_lo, c, b, part, E);
+            else
+                fwd_chunk2<T, false, PADQ, U>(A, fb, s_ef, s_kq, t.p_lo, c, b, part, E);
+        } else if constexpr (PIPE) {
             if (t.lds)
                 fwd_chunk_pipe<T, true, U>(A, fb, s_ef, s_kq, t.p_lo, c, b, part, E);
             else
@@ -582,6 +751,7 @@ template <typename T> struct BArgs {
     const BTileRec *__restrict__ btiles;
     const int64_t *__restrict__ sub_off;   // per destination: n_sub + 1 entry offsets
     int S, nm, nq0, nq1, nq2, pt;
+    int padq, qoff;                          // as in TiledArgs
     T mc, K;
 };
 
@@ -645,7 +815,8 @@ __global__ __launch_bounds__(512) void k_fwd_batched(BArgs<T> A, const T *__rest
                         const T g = A.g2[e];
                         pl = static_cast<int>(pn >> 3) - pa;
                         const StateRec<T> sp = s_ek[pl];
-                        const int q = q_linear(sd.kq, sp.kq, A.nq0, A.nq1, A.nq2);
+                        const int q = A.padq ? static_cast<int>(sp.kqp - sd.kqp) + A.qoff
+                                             : q_linear(sd.kq, sp.kq, A.nq0, A.nq1, A.nq2);
                         const Pair2<T> wn = A.hwN[static_cast<int64_t>(q) * A.nm + (pn & 7u)];
                         const T de = sd.eps - sp.eps;
                         const T xa = de + wn.a, xe = de - wn.a;
