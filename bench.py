@@ -205,6 +205,26 @@ def main():
             f"{abs(E32_ref - E64_ref) / abs(E64_ref):.2e}")
         plan32.close()
 
+    if not args.no_forms:
+        # uneven batch: 16 systems of 1e5 .. 1e7 channels in one launch
+        t0 = time.time()
+        gsys = synth.grouped_system(n_systems=16, ch_min=1e5, ch_max=1e6 if args.quick else 1e7)
+        gf = np.clip(synth.fermi_dirac(gsys.eps, 0.05, 300.0)
+                     * (0.8 + 0.4 * rng.uniform(size=gsys.n_states)), 0, 1)
+        for dname, tdt in (("f64", torch.float64), ("f32", torch.float32)):
+            gplan = E.build_channels(gsys, dtype=dname, device=0)
+            gft, gnt = tens(gf, tdt), tens(gsys.nph(300.0), tdt)
+            gI = torch.empty_like(gft)
+            msg, _ = timed(lambda: E.collision_integral(gplan, gft, gnt, out=gI), args.steps, args.warmup)
+            forms[f"grouped16_{dname}"] = dict(
+                ms=msg, channels_per_s=gsys.n_channels / (msg * 1e-3), systems=16,
+                channels=gsys.n_channels, smallest=int(np.diff(gsys.meta["ch_offsets"]).min()),
+                largest=int(np.diff(gsys.meta["ch_offsets"]).max()),
+                algorithmic_GBps=BYTES_PER_CHANNEL[dname] * gsys.n_channels / (msg * 1e-3) / 1e9)
+            log(f"grouped 16 systems {dname}: {msg:.3f} ms, {gsys.n_channels / (msg * 1e-3):.3e} ch/s "
+                f"({time.time() - t0:.1f}s incl. generation)")
+            gplan.close()
+
     cpu = None
     if not args.no_cpu:
         import copy

@@ -387,23 +387,23 @@ template <typename T> void ensure_part(ephbte_plan P, int B, int per_chunk) {
 }
 
 // gg2_mode: 0 none, 1 overwrite, 2 accumulate.  E.mode < 0: gradient of g2 only.
+// The caller packed the {hw, N} table for nph and ensured P->part (n_chunks).
 template <typename T>
 void enqueue_vjp(ephbte_plan P, const T *f, const T *lam, const void *nph, const Epi<T> &E,
                  double *gg2, int gg2_mode, hipStream_t s) {
-    Tables<T> t = tables<T>(P, nph);
-    dim3 grid(static_cast<unsigned>(grid_x(P)), 1);
-    dim3 block(P->block_threads);
-    const int64_t S = P->S;
-    if (P->fused || E.mode < 0) {
-        hipLaunchKernelGGL((k_collision_vjp<T, true>), grid, block, 0, s, t, f, S, lam, S,
-                           (T *)nullptr, E, gg2, gg2_mode);
-    } else {
-        T *part = static_cast<T *>(P->part.p);
-        hipLaunchKernelGGL((k_collision_vjp<T, false>), grid, block, 0, s, t, f, S, lam, S, part, E,
-                           gg2, gg2_mode);
-        hipLaunchKernelGGL((k_vjp_finish<T>), dim3((P->S + 255) / 256, 1), dim3(256), 0, s, t,
+    (void)nph;
+    TiledArgs<T> a = tiled_args<T>(P);
+    T *part = static_cast<T *>(P->part.p);
+    dim3 grid(static_cast<unsigned>(P->n_tiles));
+    if (P->padq)
+        hipLaunchKernelGGL((k_vjp_tiled<T, 4, true>), grid, dim3(P->block_threads), tiled_lds_bytes(P),
+                           s, a, f, lam, part, E, (const int32_t *)P->ent_chan, gg2, gg2_mode);
+    else
+        hipLaunchKernelGGL((k_vjp_tiled<T, 4, false>), grid, dim3(P->block_threads), tiled_lds_bytes(P),
+                           s, a, f, lam, part, E, (const int32_t *)P->ent_chan, gg2, gg2_mode);
+    if (!P->fused && E.mode >= 0)
+        hipLaunchKernelGGL((k_vjp_tiled_finish<T>), dim3((P->S + 255) / 256), dim3(256), 0, s, a,
                            (const T *)part, E);
-    }
     HIPC(hipGetLastError());
 }
 
@@ -1063,6 +1063,8 @@ ephbte_status ephbte_collision_vjp(ephbte_plan plan, int32_t batch, const void *
         auto run = [&](auto tag) {
             using T = decltype(tag);
             ensure_part<T>(plan, 1, 1);
+            ensure_fwd<T>(plan, 1);
+            enqueue_pack<T>(plan, nph, s);
             const int64_t S = plan->S;
             // the kernels take unit-stride vectors of length S; strided
             // batch members are addressed one vector at a time

@@ -726,6 +726,132 @@ __global__ void k_tiled_finish(TiledArgs<T> A, const T *__restrict__ f, int64_t 
     apply_epi(E, b, d, A.S, A.K * ((T(1) - fd) * bb - fd * a));
 }
 
+// ---- reverse, LDS-tiled ---------------------------------------------------
+// Same tiles, chunks and stream pipeline as the forward pass.  Per entry:
+//   dL/df_d  += -K (lam_d - lam_p) (a (1 - f_p) + b f_p)
+//   dL/dg2_c  =  K (lam_d - lam_p) (bh f_p (1 - f_d) - ah f_d (1 - f_p))   (p > d only)
+// The partner's {eps, f} and k come from LDS, lam_p from global memory.
+template <typename T, bool LDS, bool PADQ, int U>
+__device__ __forceinline__ void vjp_chunk2(const TiledArgs<T> &A, const T *__restrict__ fb,
+                                           const T *__restrict__ lb, const Pair2<T> *s_ef,
+                                           const uint32_t *s_kq, int p_lo, int64_t c,
+                                           T *__restrict__ part, const Epi<T> &E,
+                                           const int32_t *__restrict__ ent_chan,
+                                           double *__restrict__ gg2, int gg2_mode) {
+    const int lane = threadIdx.x & 63;
+    const int d = A.chunk_dest[c];
+    const int64_t beg = A.chunk_beg[c];
+    const int len = static_cast<int>(A.chunk_beg[c + 1] - beg);
+    const uint32_t *__restrict__ pb = A.pnu + beg;
+    const T *__restrict__ gb = A.g2 + beg;
+    const StateRec<T> sd = A.st[d];
+    const uint32_t kd = PADQ ? sd.kqp : sd.kq;
+    const T fd = fb[d];
+    const T ld = lb[d];
+    T acc = T(0);
+    for (int r = 0; r < len; r += 64 * U) {
+        uint32_t pn[U];
+        T gs[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            pn[u] = pb[r + u * 64 + lane];
+            gs[u] = gb[r + u * 64 + lane];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int rel = r + u * 64 + lane;
+            const bool v = rel < len;
+            const int p = static_cast<int>(pn[u] >> 3);
+            T ep, fp;
+            uint32_t kp;
+            if (LDS) {
+                const int pl = v ? p - p_lo : 0;
+                const Pair2<T> ef = s_ef[pl];
+                ep = ef.a;
+                fp = ef.b;
+                kp = s_kq[pl];
+            } else {
+                const StateRec<T> sp = A.st[p];
+                ep = sp.eps;
+                kp = PADQ ? sp.kqp : sp.kq;
+                fp = fb[p];
+            }
+            const T lp = lb[p];
+            const int q = PADQ ? static_cast<int>(kp - kd) + A.qoff
+                               : q_linear(kd, kp, A.nq0, A.nq1, A.nq2);
+            const Pair2<T> w = A.hwN[static_cast<int64_t>(q) * A.nm + (pn[u] & 7u)];
+            const T wa = v ? w.a : T(0), wb = v ? w.b : T(0);
+            const T g = v ? gs[u] : T(0);
+            const T de = sd.eps - ep;
+            const T xa = de + wa, xe = de - wa;
+            const T da = gauss_exp(xa * xa * A.mc);
+            const T dem = gauss_exp(xe * xe * A.mc);
+            const T t = wb * (da + dem);
+            const T ah = t + dem, bh = t + da;
+            const T dl = ld - lp;
+            acc += dl * g * (ah * (T(1) - fp) + bh * fp);
+            if (gg2_mode && v && p > d) {
+                const double val =
+                    static_cast<double>(A.K * dl * (bh * fp * (T(1) - fd) - ah * fd * (T(1) - fp)));
+                double *o = gg2 + ent_chan[beg + rel];
+                *o = (gg2_mode == 2) ? (*o + val) : val;
+            }
+        }
+    }
+    if (E.mode < 0) return;
+    acc = wave_sum(acc);
+    if (lane == 0) {
+        if (A.dest_chunk[d + 1] - A.dest_chunk[d] == 1)
+            apply_epi(E, 0, d, A.S, -A.K * acc);
+        else
+            part[c] = acc;
+    }
+}
+
+template <typename T, int U, bool PADQ>
+__global__ __launch_bounds__(512) void k_vjp_tiled(TiledArgs<T> A, const T *__restrict__ f,
+                                                   const T *__restrict__ lam, T *__restrict__ part,
+                                                   Epi<T> E, const int32_t *__restrict__ ent_chan,
+                                                   double *__restrict__ gg2, int gg2_mode) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const TileRec t = A.tiles[blockIdx.x];
+    Pair2<T> *s_ef = reinterpret_cast<Pair2<T> *>(smem);
+    uint32_t *s_kq = reinterpret_cast<uint32_t *>(s_ef + A.lds_states);
+    if (t.lds) {
+        const int n = t.p_hi - t.p_lo + 1;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            const StateRec<T> sr = A.st[t.p_lo + i];
+            Pair2<T> ef;
+            ef.a = sr.eps;
+            ef.b = f[t.p_lo + i];
+            s_ef[i] = ef;
+            s_kq[i] = PADQ ? sr.kqp : sr.kq;
+        }
+    }
+    __syncthreads();
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    const int nw = static_cast<int>(blockDim.x >> 6);
+    for (int64_t c = t.c0 + wave; c < t.c1; c += nw) {
+        if (t.lds)
+            vjp_chunk2<T, true, PADQ, U>(A, f, lam, s_ef, s_kq, t.p_lo, c, part, E, ent_chan, gg2,
+                                         gg2_mode);
+        else
+            vjp_chunk2<T, false, PADQ, U>(A, f, lam, s_ef, s_kq, t.p_lo, c, part, E, ent_chan, gg2,
+                                          gg2_mode);
+    }
+}
+
+template <typename T>
+__global__ void k_vjp_tiled_finish(TiledArgs<T> A, const T *__restrict__ part, Epi<T> E) {
+    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= A.S) return;
+    const int c0 = A.dest_chunk[d], c1 = A.dest_chunk[d + 1];
+    if (c1 - c0 == 1) return;
+    T a = T(0);
+    for (int c = c0; c < c1; ++c) a += part[c];
+    apply_epi(E, 0, d, A.S, -A.K * a);
+}
+
 // ---- forward, batched (B vectors in one pass) -----------------------------
 // Workgroup = batch tile: up to DPW destinations per wave, consecutive
 // destinations sharing a partner window.  The window is walked in sub-tiles

@@ -401,7 +401,7 @@ def _tb_hamiltonian(cos3, H0, T, U):
 
 def tb_system(kn=100, qn=50, nb=4, target_states=23000, window=0.3, a=LATTICE_A,
               debye_kms=(5.0, 3.0, 3.0), einstein_eV=(0.020, 0.040, 0.060), sigma=0.008,
-              seed=2511, energy_cutoff=None, name=None) -> System:
+              seed=2511, energy_cutoff=None, name=None, with_channels=True) -> System:
     """Random real-symmetric nb-band tight-binding model with cubic symmetry,
     H(k) = H0 + 2T sum_a cos(k_a a) + 2U sum_{a<b} cos(k_a a) cos(k_b a), scaled so
     that about target_states states lie within `window` eV of the global
@@ -451,6 +451,14 @@ def tb_system(kn=100, qn=50, nb=4, target_states=23000, window=0.3, a=LATTICE_A,
     state_k = linear_index(kc, kgrid).astype(np.int32)
     key_ids = state_k.astype(np.int64) * nb + sel_b
     inv_ids = inverse_k(state_k, kgrid) * nb + sel_b
+    if not with_channels:
+        z = np.zeros(0, np.int32)
+        return System(name=name or f"tb{kn}-states", kgrid=kgrid, qgrid=qgrid, state_k=state_k,
+                      state_band=sel_b.astype(np.int8), eps=eps, n_modes=hw.shape[1], hw=hw,
+                      ch_i=z, ch_j=z.copy(), ch_nu=np.zeros(0, np.int8), g2=np.zeros(0),
+                      sigma=sigma, n_q_norm=float(qn ** 3), lattice_a=a, vel=vel,
+                      meta=dict(seed=seed, scale_eV=scale, window=window, nb=nb,
+                                key_ids=key_ids, inv_ids=inv_ids))
     pair_filter = None
     if energy_cutoff is not None:
         n_sig = float(energy_cutoff)
@@ -518,3 +526,49 @@ def pulse_occupations(system: System, mu=-0.1, T=300.0, amplitude=0.1, center=0.
     e = np.asarray(system.eps, dtype=np.float64)
     f = fermi_dirac(e, mu, T) + amplitude * np.exp(-0.5 * ((e - center) / width) ** 2)
     return np.clip(f, 0.0, 1.0)
+
+
+def grouped_system(n_systems=16, ch_min=1e5, ch_max=1e7, seed=2511, base=None) -> System:
+    """Uneven batch of small systems in one problem: n_systems subsets of the
+    tight-binding window states (each inside one coset of the q grid, so every
+    pair is commensurate), with channel counts log-spaced from ch_min to
+    ch_max.  Each subset keeps all its pairs and modes; subsets share no
+    states and no channels (a block-diagonal channel list), and share the
+    phonon table.  meta['offsets'] holds each subsystem's state range and
+    meta['ch_offsets'] its channel range."""
+    base = base or tb_system(seed=seed, with_channels=False)
+    kc = grid_coords(base.kgrid)[base.state_k]
+    r = np.asarray(base.kgrid) // np.asarray(base.qgrid)
+    coset = linear_index(kc % r, tuple(int(x) for x in r))
+    rng = np.random.Generator(np.random.Philox(seed + 7))
+    targets = np.geomspace(ch_min, ch_max, n_systems)
+    nm = base.n_modes
+    parts, offs, choffs = [], [0], [0]
+    ci_l, cj_l, cn_l, g_l = [], [], [], []
+    for m, tgt in enumerate(targets):
+        n = int(round((1 + np.sqrt(1 + 8 * tgt / nm)) / 2))
+        c = m % int(coset.max() + 1)
+        pool = np.nonzero(coset == c)[0]
+        n = min(n, pool.size)
+        idx = np.sort(rng.choice(pool, size=n, replace=False))
+        sk = base.state_k[idx]
+        ids = np.asarray(base.meta["key_ids"])[idx] * 64 + m
+        inv = np.asarray(base.meta["inv_ids"])[idx] * 64 + m
+        ch = enumerate_channels(sk, base.kgrid, base.qgrid, base.hw, ids, seed + m,
+                                inv_key_ids=inv)
+        ci_l.append(ch[0] + offs[-1])
+        cj_l.append(ch[1] + offs[-1])
+        cn_l.append(ch[2])
+        g_l.append(ch[3])
+        parts.append(idx)
+        offs.append(offs[-1] + n)
+        choffs.append(choffs[-1] + ch[0].size)
+    idx = np.concatenate(parts)
+    return System(name=f"grouped{n_systems}", kgrid=base.kgrid, qgrid=base.qgrid,
+                  state_k=base.state_k[idx].astype(np.int32), state_band=base.state_band[idx],
+                  eps=base.eps[idx], n_modes=nm, hw=base.hw,
+                  ch_i=np.concatenate(ci_l).astype(np.int32), ch_j=np.concatenate(cj_l).astype(np.int32),
+                  ch_nu=np.concatenate(cn_l).astype(np.int8), g2=np.concatenate(g_l),
+                  sigma=base.sigma, n_q_norm=base.n_q_norm, lattice_a=base.lattice_a,
+                  vel=base.vel[idx], meta=dict(offsets=offs, ch_offsets=choffs,
+                                                targets=targets.tolist()))

@@ -487,3 +487,101 @@ def test_full_size_batched_sampled_parity(E, c2, dtype):
     for b in (7, 63):
         ref = oracle.collision(r, F[b], nph, mask=mask)
         assert nerr(I[b][mask], ref[mask], np.abs(I[b]).max()) <= tol, b
+
+
+# ------------------------------------------------------------------ uneven batch
+@pytest.fixture(scope="module")
+def grouped():
+    return synth.grouped_system()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_grouped_uneven_systems_one_launch(E, grouped, dtype):
+    """16 systems of 1e5 .. 1e7 channels concatenated into one problem and
+    evaluated by one launch; sampled states of every system against the oracle."""
+    s = grouped
+    rng = np.random.default_rng(31)
+    f = np.clip(synth.fermi_dirac(s.eps, 0.05, 300.0) * (0.8 + 0.4 * rng.uniform(size=s.n_states)), 0, 1)
+    nph = s.nph(300.0)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    if dtype == "f32":
+        f = f.astype(np.float32).astype(np.float64)
+        nph = nph.astype(np.float32).astype(np.float64)
+    say(f"grouped {dtype} S={s.n_states} Nch={s.n_channels}")
+    plan = E.build_channels(s, dtype=dtype, device=0)
+    I = host(E.collision_integral(plan, dev(f, tdt), dev(nph, tdt)))
+    plan.close()
+    offs = s.meta["offsets"]
+    mask = np.zeros(s.n_states, bool)
+    for m in range(len(offs) - 1):
+        mask[rng.choice(np.arange(offs[m], offs[m + 1]), 3, replace=False)] = True
+    r = s if dtype == "f64" else round32(s)
+    ref = oracle.collision(r, f, nph, mask=mask)
+    tol = TOL64 if dtype == "f64" else TOL32
+    for m in range(len(offs) - 1):
+        sl = slice(offs[m], offs[m + 1])
+        sub = mask[sl]
+        assert nerr(I[sl][sub], ref[sl][sub], np.abs(I[sl]).max()) <= tol, m
+
+
+# ------------------------------------------------------------------ gradients
+def test_rt_adjoint_cpu_reference_512k(E):
+    """Gradient through 6 RK4 steps on the 512-k case against the oracle's
+    discrete adjoint (FP64)."""
+    s = synth.parabolic_system(8)
+    f0 = synth.c1_occupations(s)
+    nph = s.nph(300.0)
+    dt, n = 1.0, 6
+    fT = f0.copy()
+    for _ in range(n):
+        fT = oracle.rk4_step(s, fT, nph, dt)
+    gT = (s.eps * fT.sum() - s.eps @ fT) / fT.sum() ** 2
+    _, rf, rg = oracle.rk4_trajectory_grad(s, f0, nph, dt, n, gT)
+    plan = E.build_channels(s, device=0)
+    say("rt_adjoint 512-k vs oracle")
+    gf0, gg = E.rt_adjoint(plan, dev(f0), dev(nph), dt, n, 2, dev(gT), gg2=True)
+    plan.close()
+    assert nerr(host(gf0), rf) <= 1e-9
+    assert nerr(host(gg), rg) <= 1e-9
+
+
+def test_full_size_rt_adjoint_finite_differences(E, c2):
+    """dL/d|g|^2 through 20 RK4 steps (checkpoint every 5) of the full-size
+    system, L = mean carrier energy at the end, against central differences
+    on the 32 entries of largest |dL/dg2| and along one random direction."""
+    s = c2
+    nph = dev(s.nph(300.0))
+    eps = dev(s.eps)
+    f0 = dev(synth.pulse_occupations(s, center=0.2))
+    dt, n = 1.0, 20
+    plan = E.build_channels(s, device=0)
+    g2 = dev(s.g2)
+
+    def loss(g):
+        E.update_g2(plan, g)
+        f = f0.clone()
+        E.rt_step(plan, f, nph, dt, n, use_graph=True)
+        torch.cuda.synchronize()
+        return float((eps * f).sum() / f.sum()), f
+
+    say("full-size adjoint vs finite differences")
+    L0, fT = loss(g2)
+    gT = ((eps * fT.sum() - (eps * fT).sum()) / fT.sum() ** 2).contiguous()
+    _, gg = E.rt_adjoint(plan, f0, nph, dt, n, 5, gT, want_f=False, gg2=True)
+    gg = host(gg)
+    top = np.argsort(-np.abs(gg))[:32]
+    for c in top:
+        h = 1e-2 * s.g2[c]
+        gp = g2.clone()
+        gp[c] += h
+        gm = g2.clone()
+        gm[c] -= h
+        fd = (loss(gp)[0] - loss(gm)[0]) / (2 * h)
+        assert fd == pytest.approx(gg[c], rel=2e-3, abs=1e-3 * np.abs(gg[top]).max()), c
+    v = np.random.default_rng(3).normal(size=s.n_channels) * s.g2
+    hstep = 1e-3
+    Lp = loss(g2 + hstep * dev(v))[0]
+    Lm = loss(g2 - hstep * dev(v))[0]
+    fd = (Lp - Lm) / (2 * hstep)
+    assert fd == pytest.approx(float(gg @ v), rel=1e-4)
+    plan.close()
