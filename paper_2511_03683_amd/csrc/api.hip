@@ -90,6 +90,7 @@ struct ephbte_plan_s {
     int pt = 0;                 // partners per sub-tile
     int batch_min = 8;          // smallest B that uses the batched kernel
     int lds_states = 0;
+    size_t lds_max = 65536;      // device limit of LDS per workgroup
     bool fused = true;
     // phonon table indexed by padded k differences (one subtraction per entry)
     bool padq = false;
@@ -762,7 +763,7 @@ ephbte_status transport_impl(ephbte_plan P, const T *f0, const T *vel, double T_
                              const void *nph, double tol, int max_iter, T *x_out, double *mob,
                              int32_t *iters, double *resid, hipStream_t s) {
     const int64_t S = P->S;
-    ensure(P->tr_W, sizeof(T) * std::max<int64_t>(P->E, 1), &P->ws_gen);
+    ensure(P->tr_W, sizeof(T) * (P->E + kEntryPad), &P->ws_gen);
     ensure(P->tr_tau_inv, sizeof(T) * S, &P->ws_gen);
     ensure(P->tr_tau, sizeof(T) * S, &P->ws_gen);
     ensure(P->tr_rhs, sizeof(Vec4<T>) * S, &P->ws_gen);
@@ -814,15 +815,17 @@ ephbte_status transport_impl(ephbte_plan P, const T *f0, const T *vel, double T_
     int it = 0;
     bool conv = false;
     for (it = 1; it <= max_iter; ++it) {
-        if (P->fused)
-            hipLaunchKernelGGL((k_transport_iter<T, true>), grid, block, 0, s, t, (const T *)W,
-                               (const Vec4<T> *)xa, (const Vec4<T> *)rhs, (const T *)tau,
-                               (Vec4<T> *)nullptr, xb);
-        else {
-            hipLaunchKernelGGL((k_transport_iter<T, false>), grid, block, 0, s, t, (const T *)W,
-                               (const Vec4<T> *)xa, (const Vec4<T> *)rhs, (const T *)tau, part, xb);
-            hipLaunchKernelGGL((k_transport_iter_finish<T>), sg, dim3(256), 0, s, t,
-                               (const Vec4<T> *)part, (const Vec4<T> *)rhs, (const T *)tau, xb);
+        {
+            TiledArgs<T> ta = tiled_args<T>(P);
+            const size_t shm = static_cast<size_t>(P->lds_states) * 3 * sizeof(T);
+            const int use_lds = shm <= P->lds_max ? 1 : 0;
+            hipLaunchKernelGGL((k_tr_tiled<T>), dim3(static_cast<unsigned>(P->n_tiles)),
+                               dim3(P->block_threads), use_lds ? shm : 0, s, ta, use_lds,
+                               (const T *)W, (const Vec4<T> *)xa, (const Vec4<T> *)rhs,
+                               (const T *)tau, part, xb);
+            if (!P->fused)
+                hipLaunchKernelGGL((k_tr_tiled_finish<T>), sg, dim3(256), 0, s, ta,
+                                   (const Vec4<T> *)part, (const Vec4<T> *)rhs, (const T *)tau, xb);
         }
         HIPC(hipGetLastError());
         double r[10];
@@ -991,6 +994,10 @@ ephbte_status ephbte_build_channels(const ephbte_problem *problem, ephbte_plan *
         // LDS window per workgroup: {eps, f} + packed k = 20 B (FP64) / 12 B (FP32) per
         // state, kept under 64 KB so two (FP64) or three (FP32) workgroups share a CU
         P->lds_states = P->dtype == EPHBTE_F64 ? 3072 : 4096;
+        int shm = 0;
+        if (hipDeviceGetAttribute(&shm, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+            shm > 0)
+            P->lds_max = static_cast<size_t>(shm);
         if (P->dtype == EPHBTE_F64) upload_layout<double>(P, problem, L);
         else upload_layout<float>(P, problem, L);
         {

@@ -75,6 +75,10 @@ __device__ __forceinline__ double gauss_exp2(double y) {
 __device__ __forceinline__ double gauss_exp(double a) { return gauss_exp2(a); }
 __device__ __forceinline__ float gauss_exp(float a) { return __builtin_amdgcn_exp2f(a); }
 
+template <typename T> struct alignas(4 * sizeof(T)) Vec4 {
+    T x, y, z, w;
+};
+
 // linear q index of k_p - k_d (both given in q-grid units, 10 bits per axis)
 __device__ __forceinline__ int q_linear(uint32_t kd, uint32_t kp, int n0, int n1, int n2) {
     int a0 = static_cast<int>(kp >> 20) - static_cast<int>(kd >> 20);
@@ -852,6 +856,133 @@ __global__ void k_vjp_tiled_finish(TiledArgs<T> A, const T *__restrict__ part, E
     apply_epi(E, 0, d, A.S, -A.K * a);
 }
 
+// ---- transport iteration, LDS-tiled -------------------------------------
+// x_new_d = tau_d (rhs_d + sum_entries W_e x_p) for the three field
+// directions.  The partner window of x is staged in LDS (3 values per state)
+// when the plan's LDS budget allows it, else x_p is gathered from global memory.
+template <typename T, bool LDS>
+__device__ __forceinline__ void tr_chunk(const TiledArgs<T> &A, const T *__restrict__ W,
+                                         const Vec4<T> *__restrict__ x, const T *s_x, int p_lo,
+                                         int64_t c, const Vec4<T> *__restrict__ rhs,
+                                         const T *__restrict__ tau, Vec4<T> *__restrict__ part,
+                                         Vec4<T> *__restrict__ x_new) {
+    constexpr int U = 4;
+    const int lane = threadIdx.x & 63;
+    const int d = A.chunk_dest[c];
+    const int64_t beg = A.chunk_beg[c];
+    const int len = static_cast<int>(A.chunk_beg[c + 1] - beg);
+    const uint32_t *__restrict__ pb = A.pnu + beg;
+    const T *__restrict__ wb = W + beg;
+    T a0 = T(0), a1 = T(0), a2 = T(0);
+    for (int r = 0; r < len; r += 64 * U) {
+        uint32_t pn[U];
+        T w[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            pn[u] = pb[r + u * 64 + lane];
+            w[u] = wb[r + u * 64 + lane];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool v = r + u * 64 + lane < len;
+            const int p = static_cast<int>(pn[u] >> 3);
+            T x0, x1, x2;
+            if (LDS) {
+                const int pl = v ? p - p_lo : 0;
+                x0 = s_x[3 * pl];
+                x1 = s_x[3 * pl + 1];
+                x2 = s_x[3 * pl + 2];
+            } else {
+                const Vec4<T> xp = x[p];
+                x0 = xp.x;
+                x1 = xp.y;
+                x2 = xp.z;
+            }
+            const T ww = v ? w[u] : T(0);
+            a0 += ww * x0;
+            a1 += ww * x1;
+            a2 += ww * x2;
+        }
+    }
+    a0 = wave_sum(a0);
+    a1 = wave_sum(a1);
+    a2 = wave_sum(a2);
+    if (lane == 0) {
+        if (A.dest_chunk[d + 1] - A.dest_chunk[d] == 1) {
+            const Vec4<T> rr = rhs[d];
+            const T t = tau[d];
+            Vec4<T> o;
+            o.x = t * (rr.x + a0);
+            o.y = t * (rr.y + a1);
+            o.z = t * (rr.z + a2);
+            o.w = T(0);
+            x_new[d] = o;
+        } else {
+            Vec4<T> o;
+            o.x = a0;
+            o.y = a1;
+            o.z = a2;
+            o.w = T(0);
+            part[c] = o;
+        }
+    }
+}
+
+// W must be padded past its end like the entry arrays.
+template <typename T>
+__global__ __launch_bounds__(512) void k_tr_tiled(TiledArgs<T> A, int use_lds, const T *__restrict__ W,
+                                                  const Vec4<T> *__restrict__ x,
+                                                  const Vec4<T> *__restrict__ rhs,
+                                                  const T *__restrict__ tau, Vec4<T> *__restrict__ part,
+                                                  Vec4<T> *__restrict__ x_new) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const TileRec t = A.tiles[blockIdx.x];
+    T *s_x = reinterpret_cast<T *>(smem);
+    const bool lds = use_lds && t.lds;
+    if (lds) {
+        const int n = t.p_hi - t.p_lo + 1;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            const Vec4<T> v = x[t.p_lo + i];
+            s_x[3 * i] = v.x;
+            s_x[3 * i + 1] = v.y;
+            s_x[3 * i + 2] = v.z;
+        }
+    }
+    __syncthreads();
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    const int nw = static_cast<int>(blockDim.x >> 6);
+    for (int64_t c = t.c0 + wave; c < t.c1; c += nw) {
+        if (lds)
+            tr_chunk<T, true>(A, W, x, s_x, t.p_lo, c, rhs, tau, part, x_new);
+        else
+            tr_chunk<T, false>(A, W, x, s_x, t.p_lo, c, rhs, tau, part, x_new);
+    }
+}
+
+template <typename T>
+__global__ void k_tr_tiled_finish(TiledArgs<T> A, const Vec4<T> *__restrict__ part,
+                                  const Vec4<T> *__restrict__ rhs, const T *__restrict__ tau,
+                                  Vec4<T> *__restrict__ x_new) {
+    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= A.S) return;
+    const int c0 = A.dest_chunk[d], c1 = A.dest_chunk[d + 1];
+    if (c1 - c0 == 1) return;
+    T a0 = T(0), a1 = T(0), a2 = T(0);
+    for (int c = c0; c < c1; ++c) {
+        a0 += part[c].x;
+        a1 += part[c].y;
+        a2 += part[c].z;
+    }
+    const Vec4<T> rr = rhs[d];
+    const T t = tau[d];
+    Vec4<T> o;
+    o.x = t * (rr.x + a0);
+    o.y = t * (rr.y + a1);
+    o.z = t * (rr.z + a2);
+    o.w = T(0);
+    x_new[d] = o;
+}
+
 // ---- forward, batched (B vectors in one pass) -----------------------------
 // Workgroup = batch tile: up to DPW destinations per wave, consecutive
 // destinations sharing a partner window.  The window is walked in sub-tiles
@@ -1093,10 +1224,6 @@ __global__ void k_transport_setup_finish(Tables<T> P, const T *__restrict__ part
     for (int c = P.dest_chunk[d]; c < P.dest_chunk[d + 1]; ++c) a += part[c];
     tau_inv[d] = P.K * a;
 }
-
-template <typename T> struct alignas(4 * sizeof(T)) Vec4 {
-    T x, y, z, w;
-};
 
 // x_new_d = tau_d (b_d + sum W_dp x_p), three field directions at once.
 template <typename T, bool FUSED>
