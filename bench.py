@@ -41,10 +41,14 @@ def main():
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-channels", type=int, default=100_000_000)
+    ap.add_argument("--dtype", choices=("f64", "f32"), default="f64",
+                    help="precision of the main step (f32 only with --no-forms, for profiling)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB read + 1 GiB write elementwise kernel "
                          "(hardware-counter calibration)")
     args = ap.parse_args()
+    if args.dtype != "f64" and not args.no_forms:
+        ap.error("--dtype f32 times the main step only; add --no-forms")
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(the destination-sharded design is described in DESIGN.md)", file=sys.stderr)
@@ -84,9 +88,10 @@ def main():
         return torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
 
     t0 = time.time()
-    plan64 = E.build_channels(s, dtype="f64", device=0)
-    log(f"fp64 plan built ({time.time() - t0:.1f}s), info={E.plan_info(plan64)}")
-    f64, n64 = tens(f_np, torch.float64), tens(nph_np, torch.float64)
+    mdt = torch.float64 if args.dtype == "f64" else torch.float32
+    plan64 = E.build_channels(s, dtype=args.dtype, device=0)
+    log(f"{args.dtype} plan built ({time.time() - t0:.1f}s), info={E.plan_info(plan64)}")
+    f64, n64 = tens(f_np, mdt), tens(nph_np, mdt)
     I64 = torch.empty_like(f64)
 
     def timed(fn, reps, warm):
@@ -110,8 +115,8 @@ def main():
     fwd64 = lambda: E.collision_integral(plan64, f64, n64, out=I64)
     ms, wall = timed(fwd64, args.steps, args.warmup)
     value = nch / (ms * 1e-3)
-    achieved = BYTES_PER_CHANNEL["f64"] * nch / (ms * 1e-3) / 1e9
-    log(f"fwd fp64: {ms:.3f} ms/eval, {value:.3e} ch/s, {achieved:.0f} GB/s algorithmic "
+    achieved = BYTES_PER_CHANNEL[args.dtype] * nch / (ms * 1e-3) / 1e9
+    log(f"fwd {args.dtype}: {ms:.3f} ms/eval, {value:.3e} ch/s, {achieved:.0f} GB/s algorithmic "
         f"(wall {wall:.2f}s for {args.steps})")
 
     forms = {}
@@ -251,7 +256,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": args.dtype,
         "data": "synthetic",
         "config": {"workload": wname, "n_states": s.n_states, "n_channels": nch,
                    "entries": 2 * nch, "kgrid": list(s.kgrid), "qgrid": list(s.qgrid),
