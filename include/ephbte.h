@@ -97,7 +97,9 @@ typedef struct {
     int32_t chunk_entries;     /* max destination entries per workgroup chunk      */
     int32_t block_threads;     /* threads per workgroup: 64, 128, 256, 512         */
     int32_t xcd_map;           /* 1: contiguous chunk ranges per XCD; 2: plain order */
-    int32_t reserved[5];       /* must be 0                                        */
+    int32_t batch_partners;    /* partner states per LDS sub-tile of the B >= 8 pass,
+                                  16 .. 1024, within the device's LDS per workgroup */
+    int32_t reserved[4];       /* must be 0                                        */
 } ephbte_tuning;
 
 /*
@@ -208,7 +210,9 @@ ephbte_status ephbte_set_tuning(ephbte_plan plan, const ephbte_tuning *tuning);
 
 /* Time candidate tunings of the B-vector collision integral on this plan with
  * HIP events and keep the fastest; writes the chosen tuning to *chosen (may be
- * NULL).  Uses the plan's own scratch occupations.  Synchronous. */
+ * NULL).  For batch < 8 the candidates are chunk sizes x block sizes of the
+ * single-vector kernel; for batch >= 8, partner sub-tile sizes of the batched
+ * kernel.  Allocates and frees its own half-filled occupations.  Synchronous. */
 ephbte_status ephbte_autotune(ephbte_plan plan, int32_t batch, ephbte_tuning *chosen);
 
 /* Plan facts: out[0]=S, [1]=n_channels, [2]=entries, [3]=chunks, [4]=dtype,

@@ -76,6 +76,7 @@ struct ephbte_plan_s {
     void *st = nullptr;
     void *hw = nullptr;
     int32_t *ent_chan = nullptr;
+    double *e2tab = nullptr;        // 2^(j/256), j = 0 .. 255
     // chunks (device)
     int64_t *chunk_beg = nullptr;
     int32_t *chunk_dest = nullptr;
@@ -184,7 +185,7 @@ void free_plan(ephbte_plan P) {
     void **ptrs[] = {(void **)&P->pnu,       (void **)&P->g2,         (void **)&P->st,
                      (void **)&P->hw,        (void **)&P->ent_chan,   (void **)&P->chunk_beg,
                      (void **)&P->chunk_dest, (void **)&P->dest_chunk, (void **)&P->tiles,
-                     (void **)&P->btiles,    (void **)&P->sub_off};
+                     (void **)&P->btiles,    (void **)&P->sub_off,    (void **)&P->e2tab};
     for (auto pp : ptrs) dfree(*pp);
     DevBuf *w[] = {&P->part,   &P->rk_ua,  &P->rk_ub,   &P->rk_acc, &P->hwN, &P->tr_W,   &P->tr_tau_inv,
                    &P->tr_tau, &P->tr_rhs, &P->tr_xa,   &P->tr_xb,  &P->tr_part, &P->tr_red,
@@ -278,6 +279,8 @@ template <typename T> TiledArgs<T> tiled_args(ephbte_plan P) {
     Tables<T> t = tables<T>(P, nullptr);
     a.mc = t.mc;
     a.K = t.K;
+    a.e2tab = P->e2tab;
+    a.mc256 = 256.0 * (-1.4426950408889634 / (2.0 * P->sigma * P->sigma));
     return a;
 }
 
@@ -318,14 +321,45 @@ template <typename T> BArgs<T> batch_args(ephbte_plan P) {
     return a;
 }
 
+// LDS of the batched kernel: f[pt][65] and the pt partner states
+size_t batch_lds_bytes(ephbte_plan P, int pt) {
+    const size_t es = P->dtype == EPHBTE_F64 ? 8 : 4;
+    return static_cast<size_t>(pt) * (65 * es + (P->dtype == EPHBTE_F64 ? sizeof(StateRec<double>)
+                                                                          : sizeof(StateRec<float>)));
+}
+
 template <typename T>
 void enqueue_forward_batched(ephbte_plan P, int B, const T *f, int64_t ldf, const Epi<T> &E,
                              hipStream_t s) {
-    const size_t shm = static_cast<size_t>(P->pt) * (65 * sizeof(T) + sizeof(StateRec<T>));
+    const size_t shm = batch_lds_bytes(P, P->pt);
     dim3 grid(static_cast<unsigned>(P->n_btiles), (B + 63) / 64);
     hipLaunchKernelGGL((k_fwd_batched<T, kBatchDPW>), grid, dim3(kBatchThreads), shm, s,
                        batch_args<T>(P), f, ldf, B, E);
     HIPC(hipGetLastError());
+}
+
+// Batch tiles for partner sub-tiles of pt states: shapes from the host's
+// partner ranges, entry offsets searched on the device.  Synchronous.
+void upload_btiles(ephbte_plan P, int pt) {
+    int64_t slots = 0;
+    const std::vector<BTile> bt =
+        make_btiles(P->pmin, P->pmax, pt, kBatchDPW * (kBatchThreads / 64), 4096, &slots);
+    static_assert(sizeof(BTile) == sizeof(BTileRec), "batch tile record layout");
+    free_graphs(P);
+    dfree(reinterpret_cast<void *&>(P->btiles));
+    dfree(reinterpret_cast<void *&>(P->sub_off));
+    size_t dummy = 0;
+    dalloc(P->btiles, std::max<size_t>(bt.size(), 1) * sizeof(BTileRec), &dummy);
+    dalloc(P->sub_off, static_cast<size_t>(std::max<int64_t>(slots, 1)) * sizeof(int64_t), &dummy);
+    if (!bt.empty()) {
+        HIPC(hipMemcpy(P->btiles, bt.data(), bt.size() * sizeof(BTileRec), hipMemcpyHostToDevice));
+        hipLaunchKernelGGL(k_sub_offsets, dim3(static_cast<unsigned>(bt.size())), dim3(256), 0, nullptr,
+                           P->btiles, P->pnu, P->chunk_beg, P->dest_chunk, P->S, pt, P->sub_off);
+        HIPC(hipGetLastError());
+    }
+    HIPC(hipDeviceSynchronize());
+    P->pt = pt;
+    P->n_btiles = static_cast<int64_t>(bt.size());
 }
 
 // Interleave the plan's phonon energies with the caller's occupations into
@@ -347,7 +381,8 @@ template <typename T> void enqueue_pack(ephbte_plan P, const void *nph, hipStrea
 
 size_t tiled_lds_bytes(ephbte_plan P) {
     const size_t es = P->dtype == EPHBTE_F64 ? 8 : 4;
-    return static_cast<size_t>(P->lds_states) * (2 * es + 4);
+    const size_t tab = P->dtype == EPHBTE_F64 ? kExpTab * sizeof(double) : 0;
+    return static_cast<size_t>(P->lds_states) * (2 * es + 4) + tab;
 }
 
 // Enqueue I[f] for B vectors with epilogue E (no allocation inside; the
@@ -396,11 +431,14 @@ void enqueue_vjp(ephbte_plan P, const T *f, const T *lam, const void *nph, const
     TiledArgs<T> a = tiled_args<T>(P);
     T *part = static_cast<T *>(P->part.p);
     dim3 grid(static_cast<unsigned>(P->n_tiles));
+    // entries per lane and pipeline stage: 2 in FP64 keeps the two stages in
+    // registers at two workgroups per compute unit
+    constexpr int U = sizeof(T) == 8 ? 2 : 4;
     if (P->padq)
-        hipLaunchKernelGGL((k_vjp_tiled<T, 4, true>), grid, dim3(P->block_threads), tiled_lds_bytes(P),
+        hipLaunchKernelGGL((k_vjp_tiled<T, U, true>), grid, dim3(P->block_threads), tiled_lds_bytes(P),
                            s, a, f, lam, part, E, (const int32_t *)P->ent_chan, gg2, gg2_mode);
     else
-        hipLaunchKernelGGL((k_vjp_tiled<T, 4, false>), grid, dim3(P->block_threads), tiled_lds_bytes(P),
+        hipLaunchKernelGGL((k_vjp_tiled<T, U, false>), grid, dim3(P->block_threads), tiled_lds_bytes(P),
                            s, a, f, lam, part, E, (const int32_t *)P->ent_chan, gg2, gg2_mode);
     if (!P->fused && E.mode >= 0)
         hipLaunchKernelGGL((k_vjp_tiled_finish<T>), dim3((P->S + 255) / 256), dim3(256), 0, s, a,
@@ -1001,21 +1039,17 @@ ephbte_status ephbte_build_channels(const ephbte_problem *problem, ephbte_plan *
         if (P->dtype == EPHBTE_F64) upload_layout<double>(P, problem, L);
         else upload_layout<float>(P, problem, L);
         {
-            P->pt = P->dtype == EPHBTE_F64 ? 96 : 192;
-            std::vector<BTile> bt;
-            std::vector<int64_t> so;
-            make_btiles(L, P->pt, kBatchDPW * (kBatchThreads / 64), 4096, &bt, &so);
-            static_assert(sizeof(BTile) == sizeof(BTileRec), "batch tile record layout");
-            dalloc(P->btiles, bt.size() * sizeof(BTileRec), &P->layout_bytes);
-            dalloc(P->sub_off, std::max<size_t>(so.size(), 1) * sizeof(int64_t), &P->layout_bytes);
-            HIPC(hipMemcpy(P->btiles, bt.data(), bt.size() * sizeof(BTileRec), hipMemcpyHostToDevice));
-            if (!so.empty())
-                HIPC(hipMemcpy(P->sub_off, so.data(), so.size() * sizeof(int64_t), hipMemcpyHostToDevice));
-            P->n_btiles = static_cast<int64_t>(bt.size());
+            // 2^(j/256) rounded from extended precision
+            double tab[kExpTab];
+            for (int j = 0; j < kExpTab; ++j)
+                tab[j] = static_cast<double>(std::exp2(static_cast<long double>(j) / kExpTab));
+            dalloc(P->e2tab, sizeof(tab), &P->layout_bytes);
+            HIPC(hipMemcpy(P->e2tab, tab, sizeof(tab), hipMemcpyHostToDevice));
         }
         { HostLayout tmp; std::swap(tmp, L); }
         P->block_threads = 512;
         upload_chunks(P, 8192);
+        upload_btiles(P, P->dtype == EPHBTE_F64 ? 96 : 192);
         HIPC(hipDeviceSynchronize());
     } catch (const HipError &e) {
         free_plan(P);
@@ -1183,10 +1217,17 @@ ephbte_status ephbte_set_tuning(ephbte_plan plan, const ephbte_tuning *tuning) {
         if (ce < 0) return fail(EPHBTE_INVALID_ARGUMENT, "chunk_entries must be >= 0");
         if (tuning->xcd_map < 0 || tuning->xcd_map > 2)
             return fail(EPHBTE_INVALID_ARGUMENT, "xcd_map must be 0, 1 or 2");
+        const int pt = tuning->batch_partners;
+        if (pt != 0 && (pt < 16 || pt > 1024 || batch_lds_bytes(plan, pt) > plan->lds_max))
+            return fail(EPHBTE_INVALID_ARGUMENT,
+                        "batch_partners must be in [16, 1024] and fit the LDS of one workgroup");
+        for (int r : tuning->reserved)
+            if (r != 0) return fail(EPHBTE_INVALID_ARGUMENT, "reserved tuning fields must be 0");
         HIPC(hipDeviceSynchronize());
         plan->block_threads = bt;
         if (tuning->xcd_map) plan->xcd_map = tuning->xcd_map == 1;
         upload_chunks(plan, ce);
+        if (pt != 0) upload_btiles(plan, pt);
         free_graphs(plan);
         return EPHBTE_OK;
     });
@@ -1221,6 +1262,55 @@ ephbte_status ephbte_autotune(ephbte_plan plan, int32_t batch, ephbte_tuning *ch
         hipEvent_t e0, e1;
         HIPC(hipEventCreate(&e0));
         HIPC(hipEventCreate(&e1));
+        auto once = [&]() {
+            if (plan->dtype == EPHBTE_F64) {
+                ensure_fwd<double>(plan, batch);
+                enqueue_forward<double>(plan, batch, (const double *)f, S, nph,
+                                        epi_store<double>((double *)I, S), nullptr);
+            } else {
+                ensure_fwd<float>(plan, batch);
+                enqueue_forward<float>(plan, batch, (const float *)f, S, nph,
+                                       epi_store<float>((float *)I, S), nullptr);
+            }
+        };
+        auto time_it = [&]() -> float {
+            once();
+            HIPC(hipEventRecord(e0, nullptr));
+            for (int r = 0; r < 3; ++r) once();
+            HIPC(hipEventRecord(e1, nullptr));
+            HIPC(hipEventSynchronize(e1));
+            float ms = 0;
+            HIPC(hipEventElapsedTime(&ms, e0, e1));
+            return ms;
+        };
+        if (batch >= plan->batch_min) {
+            // batched pass: partner sub-tile sizes that fit the LDS of a workgroup
+            const int pt64[] = {48, 64, 96, 128, 160};
+            const int pt32[] = {96, 128, 192, 256, 320};
+            const int *cand = plan->dtype == EPHBTE_F64 ? pt64 : pt32;
+            float best = INFINITY;
+            int best_pt = plan->pt;
+            for (int i = 0; i < 5; ++i) {
+                if (batch_lds_bytes(plan, cand[i]) > plan->lds_max) continue;
+                upload_btiles(plan, cand[i]);
+                const float ms = time_it();
+                if (ms < best) {
+                    best = ms;
+                    best_pt = cand[i];
+                }
+            }
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            upload_btiles(plan, best_pt);
+            if (chosen) {
+                std::memset(chosen, 0, sizeof(*chosen));
+                chosen->chunk_entries = plan->chunk_entries;
+                chosen->block_threads = plan->block_threads;
+                chosen->xcd_map = plan->xcd_map ? 1 : 2;
+                chosen->batch_partners = best_pt;
+            }
+            return EPHBTE_OK;
+        }
         const int chunk_c[] = {2048, 4096, 8192, 16384};
         const int thr_c[] = {256, 512};
         float best = INFINITY;
@@ -1229,24 +1319,7 @@ ephbte_status ephbte_autotune(ephbte_plan plan, int32_t batch, ephbte_tuning *ch
             for (int bt : thr_c) {
                 plan->block_threads = bt;
                 upload_chunks(plan, ce);
-                auto once = [&]() {
-                    if (plan->dtype == EPHBTE_F64) {
-                        ensure_fwd<double>(plan, batch);
-                        enqueue_forward<double>(plan, batch, (const double *)f, S, nph,
-                                                epi_store<double>((double *)I, S), nullptr);
-                    } else {
-                        ensure_fwd<float>(plan, batch);
-                        enqueue_forward<float>(plan, batch, (const float *)f, S, nph,
-                                               epi_store<float>((float *)I, S), nullptr);
-                    }
-                };
-                once();
-                HIPC(hipEventRecord(e0, nullptr));
-                for (int r = 0; r < 3; ++r) once();
-                HIPC(hipEventRecord(e1, nullptr));
-                HIPC(hipEventSynchronize(e1));
-                float ms = 0;
-                HIPC(hipEventElapsedTime(&ms, e0, e1));
+                const float ms = time_it();
                 if (ms < best) {
                     best = ms;
                     best_ce = ce;
@@ -1262,6 +1335,7 @@ ephbte_status ephbte_autotune(ephbte_plan plan, int32_t batch, ephbte_tuning *ch
             chosen->chunk_entries = best_ce;
             chosen->block_threads = best_bt;
             chosen->xcd_map = plan->xcd_map ? 1 : 2;
+            chosen->batch_partners = plan->pt;
         }
         return EPHBTE_OK;
     });

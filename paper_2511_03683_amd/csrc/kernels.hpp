@@ -27,6 +27,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace ephbte {
 
 // kq:  k in q-grid units, 10 bits per axis (a0 << 20 | a1 << 10 | a2)
@@ -72,6 +74,27 @@ __device__ __forceinline__ double gauss_exp2(double y) {
     p = fma(p, r, 1.0);
     return ldexp(p, static_cast<int>(n));
 }
+// Table-driven base-2 exponential (Tang, ACM TOMS 15(2), 1989) for the
+// streaming kernels.  Takes y256 = 256 y.  With n = rint(y256) and
+// r = y256 - n (exact, |r| <= 1/2): 2^y = 2^(n >> 8) 2^((n & 255)/256) 2^(r/256).
+// The middle factor comes from a 256-entry table of 2^(j/256) held in LDS;
+// the last is exp(r ln2/256) by its Taylor series to degree 4
+// (|r ln2/256| <= 1.36e-3, truncation below 4e-17 relative); coefficients
+// (ln2/256)^k / k!.  y256 is clamped where the result is already 0, which
+// keeps the integer conversion in range.
+__device__ __forceinline__ double gauss_exp2_tab(double y256, const double *tab) {
+    y256 = fmax(y256, -300000.0);
+    const double n = __builtin_rint(y256);
+    const double r = y256 - n;
+    double p = 2.239395190875157e-12;
+    p = fma(p, r, 3.3083026805413713e-09);
+    p = fma(p, r, 3.6655655969101062e-06);
+    p = fma(p, r, 0.0027076061740622863);
+    p = fma(p, r, 1.0);
+    const int i = static_cast<int>(n);
+    return ldexp(tab[i & 255] * p, i >> 8);
+}
+
 __device__ __forceinline__ double gauss_exp(double a) { return gauss_exp2(a); }
 __device__ __forceinline__ float gauss_exp(float a) { return __builtin_amdgcn_exp2f(a); }
 
@@ -341,7 +364,12 @@ template <typename T> struct TiledArgs {
     int padq;          // 1: hwN is the padded table indexed by kqp differences
     int qoff;          // padded index of q = 0 difference
     T mc, K;
+    const double *__restrict__ e2tab;   // 2^(j/256), j = 0 .. 255 (FP64 kernels)
+    double mc256;                       // 256 mc, the table exponential's scale
 };
+
+// entries of the exponential table that the FP64 streaming kernels keep in LDS
+constexpr int kExpTab = 256;
 
 template <typename T>
 __global__ void k_pack_hwN(const T *__restrict__ hw, const T *__restrict__ nph,
@@ -381,16 +409,25 @@ __global__ void k_pack_hwN_pad(const T *__restrict__ hw, const T *__restrict__ n
     }
 }
 
+// exp of the Gaussian exponent x2 * (-1/(2 s^2)) for the streaming kernels
+template <typename T>
+__device__ __forceinline__ T stream_gauss(const TiledArgs<T> &A, T x2, const double *tab) {
+    if constexpr (sizeof(T) == 8) return gauss_exp2_tab(x2 * A.mc256, tab);
+    else return __builtin_amdgcn_exp2f(x2 * A.mc);
+}
+
 // Chunk reduction with a three-stage pipeline (stream loads two batches
 // ahead, partner/table gathers one batch ahead of the evaluation).  The entry
-// arrays are padded past their end, so stream loads are unconditional; lanes
-// past the chunk end read the padding or the next chunk and contribute zero.
+// arrays are padded past their end, so stream loads are unconditional.  Only
+// a chunk's last batch can hold lanes past its end (they read the padding or
+// the next chunk); that batch is gathered with a mask that makes those lanes
+// contribute zero, the others without one (the choice is uniform per wave).
 // Offsets are 32-bit and relative to the chunk start.
 template <typename T, bool LDS, bool PADQ, int U>
 __device__ __forceinline__ void fwd_chunk2(const TiledArgs<T> &A, const T *__restrict__ fb,
                                            const Pair2<T> *s_ef, const uint32_t *s_kq, int p_lo,
-                                           int64_t c, int b, T *__restrict__ part,
-                                           const Epi<T> &E) {
+                                           const double *s_tab, int64_t c, int b,
+                                           T *__restrict__ part, const Epi<T> &E) {
     const int lane = threadIdx.x & 63;
     const int d = A.chunk_dest[c];
     const int64_t beg = A.chunk_beg[c];
@@ -411,11 +448,12 @@ __device__ __forceinline__ void fwd_chunk2(const TiledArgs<T> &A, const T *__res
             gs[u] = gb[r0 + u * 64 + lane];
         }
     };
-    auto gather = [&](const uint32_t (&pn)[U], const T (&gs)[U], int r0, T (&go)[U],
-                      T (&deo)[U], T (&fpo)[U], Pair2<T> (&wno)[U]) {
+    auto gather = [&](auto masked, const uint32_t (&pn)[U], const T (&gs)[U], int r0,
+                      T (&go)[U], T (&deo)[U], T (&fpo)[U], Pair2<T> (&wno)[U]) {
+        constexpr bool M = decltype(masked)::value;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const bool v = r0 + u * 64 + lane < len;
+            const bool v = !M || r0 + u * 64 + lane < len;
             const int p = static_cast<int>(pn[u] >> 3);
             T ep, fp;
             uint32_t kp;
@@ -434,33 +472,42 @@ __device__ __forceinline__ void fwd_chunk2(const TiledArgs<T> &A, const T *__res
             const int q = PADQ ? static_cast<int>(kp - kd) + A.qoff
                                : q_linear(kd, kp, A.nq0, A.nq1, A.nq2);
             const Pair2<T> w = A.hwN[static_cast<int64_t>(q) * A.nm + (pn[u] & 7u)];
-            // lanes past the chunk end contribute nothing (a table entry without
-            // channels may hold a non-finite N, so both fields are replaced; using
-            // both keeps the {hw, N} pair a single 16-byte load)
-            wno[u].a = v ? w.a : T(0);
-            wno[u].b = v ? w.b : T(0);
-            go[u] = v ? gs[u] : T(0);
+            if constexpr (M) {
+                // a table entry without channels may hold a non-finite N, so both
+                // fields are replaced (using both keeps the {hw, N} pair one
+                // 16-byte load)
+                wno[u].a = v ? w.a : T(0);
+                wno[u].b = v ? w.b : T(0);
+                go[u] = v ? gs[u] : T(0);
+            } else {
+                wno[u] = w;
+                go[u] = gs[u];
+            }
             deo[u] = sd.eps - ep;
             fpo[u] = fp;
         }
     };
+    using Masked = std::integral_constant<bool, true>;
+    using Full = std::integral_constant<bool, false>;
     {
         uint32_t pn0[U];
         T gs0[U];
         load_stream(0, pn0, gs0);
         load_stream(64 * U, pn1, gs1);
-        gather(pn0, gs0, 0, g0, de0, fp0, wn0);
+        if (64 * U <= len) gather(Full{}, pn0, gs0, 0, g0, de0, fp0, wn0);
+        else gather(Masked{}, pn0, gs0, 0, g0, de0, fp0, wn0);
     }
     for (int r = 0; r < len; r += 64 * U) {
         T g1[U], de1[U], fp1[U];
         Pair2<T> wn1[U];
-        gather(pn1, gs1, r + 64 * U, g1, de1, fp1, wn1);
+        if (r + 128 * U <= len) gather(Full{}, pn1, gs1, r + 64 * U, g1, de1, fp1, wn1);
+        else gather(Masked{}, pn1, gs1, r + 64 * U, g1, de1, fp1, wn1);
         load_stream(r + 128 * U, pn1, gs1);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const T xa = de0[u] + wn0[u].a, xe = de0[u] - wn0[u].a;
-            const T da = gauss_exp(xa * xa * A.mc);
-            const T dem = gauss_exp(xe * xe * A.mc);
+            const T da = stream_gauss(A, xa * xa, s_tab);
+            const T dem = stream_gauss(A, xe * xe, s_tab);
             const T t = wn0[u].b * (da + dem);
             acc_a += g0[u] * (t + dem) * (T(1) - fp0[u]);
             acc_b += g0[u] * (t + da) * fp0[u];
@@ -677,6 +724,7 @@ __global__ __launch_bounds__(MAXT) void k_fwd_tiled(TiledArgs<T> A, const T *__r
     const T *fb = f + static_cast<int64_t>(b) * ldf;
     Pair2<T> *s_ef = reinterpret_cast<Pair2<T> *>(smem);
     uint32_t *s_kq = reinterpret_cast<uint32_t *>(s_ef + A.lds_states);
+    double *s_tab = reinterpret_cast<double *>(s_kq + A.lds_states);
     if (t.lds) {
         const int n = t.p_hi - t.p_lo + 1;
         for (int i = threadIdx.x; i < n; i += blockDim.x) {
@@ -688,15 +736,17 @@ __global__ __launch_bounds__(MAXT) void k_fwd_tiled(TiledArgs<T> A, const T *__r
             s_kq[i] = PADQ ? sr.kqp : sr.kq;
         }
     }
+    if constexpr (V2 && sizeof(T) == 8)
+        for (int i = threadIdx.x; i < kExpTab; i += blockDim.x) s_tab[i] = A.e2tab[i];
     __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
     const int nw = static_cast<int>(blockDim.x >> 6);
     for (int64_t c = t.c0 + wave; c < t.c1; c += nw) {
         if constexpr (V2) {
             if (t.lds)
-                fwd_chunk2<T, true, PADQ, U>(A, fb, s_ef, s_kq, t.p_lo, c, b, part, E);
+                fwd_chunk2<T, true, PADQ, U>(A, fb, s_ef, s_kq, t.p_lo, s_tab, c, b, part, E);
             else
-                fwd_chunk2<T, false, PADQ, U>(A, fb, s_ef, s_kq, t.p_lo, c, b, part, E);
+                fwd_chunk2<T, false, PADQ, U>(A, fb, s_ef, s_kq, t.p_lo, s_tab, c, b, part, E);
         } else if constexpr (PIPE) {
             if (t.lds)
                 fwd_chunk_pipe<T, true, U>(A, fb, s_ef, s_kq, t.p_lo, c, b, part, E);
@@ -738,8 +788,8 @@ __global__ void k_tiled_finish(TiledArgs<T> A, const T *__restrict__ f, int64_t 
 template <typename T, bool LDS, bool PADQ, int U>
 __device__ __forceinline__ void vjp_chunk2(const TiledArgs<T> &A, const T *__restrict__ fb,
                                            const T *__restrict__ lb, const Pair2<T> *s_ef,
-                                           const uint32_t *s_kq, int p_lo, int64_t c,
-                                           T *__restrict__ part, const Epi<T> &E,
+                                           const uint32_t *s_kq, int p_lo, const double *s_tab,
+                                           int64_t c, T *__restrict__ part, const Epi<T> &E,
                                            const int32_t *__restrict__ ent_chan,
                                            double *__restrict__ gg2, int gg2_mode) {
     const int lane = threadIdx.x & 63;
@@ -748,23 +798,37 @@ __device__ __forceinline__ void vjp_chunk2(const TiledArgs<T> &A, const T *__res
     const int len = static_cast<int>(A.chunk_beg[c + 1] - beg);
     const uint32_t *__restrict__ pb = A.pnu + beg;
     const T *__restrict__ gb = A.g2 + beg;
+    const int32_t *__restrict__ cb = ent_chan + beg;
     const StateRec<T> sd = A.st[d];
     const uint32_t kd = PADQ ? sd.kqp : sd.kq;
     const T fd = fb[d];
     const T ld = lb[d];
     T acc = T(0);
-    for (int r = 0; r < len; r += 64 * U) {
-        uint32_t pn[U];
-        T gs[U];
+    // one batch of gathered operands: coupling, energy difference, partner
+    // occupation, lam_d - lam_p, {hw, N}, and the dL/d|g|^2 slot this entry
+    // writes (-1: none) with its previous value when accumulating
+    struct Gath {
+        T g[U], de[U], fp[U], dl[U];
+        Pair2<T> wn[U];
+        int32_t ch[U];
+        double old[U];
+    };
+    uint32_t pn1[U];
+    T gs1[U];
+    Gath G0;
+    auto load_stream = [&](int r0, uint32_t (&pn)[U], T (&gs)[U]) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            pn[u] = pb[r + u * 64 + lane];
-            gs[u] = gb[r + u * 64 + lane];
+            pn[u] = pb[r0 + u * 64 + lane];
+            gs[u] = gb[r0 + u * 64 + lane];
         }
+    };
+    auto gather = [&](auto masked, const uint32_t (&pn)[U], const T (&gs)[U], int r0, Gath &o) {
+        constexpr bool M = decltype(masked)::value;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int rel = r + u * 64 + lane;
-            const bool v = rel < len;
+            const int rel = r0 + u * 64 + lane;
+            const bool v = !M || rel < len;
             const int p = static_cast<int>(pn[u] >> 3);
             T ep, fp;
             uint32_t kp;
@@ -784,23 +848,52 @@ __device__ __forceinline__ void vjp_chunk2(const TiledArgs<T> &A, const T *__res
             const int q = PADQ ? static_cast<int>(kp - kd) + A.qoff
                                : q_linear(kd, kp, A.nq0, A.nq1, A.nq2);
             const Pair2<T> w = A.hwN[static_cast<int64_t>(q) * A.nm + (pn[u] & 7u)];
-            const T wa = v ? w.a : T(0), wb = v ? w.b : T(0);
-            const T g = v ? gs[u] : T(0);
-            const T de = sd.eps - ep;
-            const T xa = de + wa, xe = de - wa;
-            const T da = gauss_exp(xa * xa * A.mc);
-            const T dem = gauss_exp(xe * xe * A.mc);
-            const T t = wb * (da + dem);
-            const T ah = t + dem, bh = t + da;
-            const T dl = ld - lp;
-            acc += dl * g * (ah * (T(1) - fp) + bh * fp);
-            if (gg2_mode && v && p > d) {
-                const double val =
-                    static_cast<double>(A.K * dl * (bh * fp * (T(1) - fd) - ah * fd * (T(1) - fp)));
-                double *o = gg2 + ent_chan[beg + rel];
-                *o = (gg2_mode == 2) ? (*o + val) : val;
+            if constexpr (M) {
+                // a table entry without channels may hold a non-finite N
+                o.wn[u].a = v ? w.a : T(0);
+                o.wn[u].b = v ? w.b : T(0);
+                o.g[u] = v ? gs[u] : T(0);
+            } else {
+                o.wn[u] = w;
+                o.g[u] = gs[u];
             }
+            o.de[u] = sd.eps - ep;
+            o.fp[u] = fp;
+            o.dl[u] = ld - lp;
+            const bool wr = gg2_mode && v && p > d;
+            o.ch[u] = wr ? cb[rel] : -1;
+            o.old[u] = (wr && gg2_mode == 2) ? gg2[o.ch[u]] : 0.0;
         }
+    };
+    using Masked = std::integral_constant<bool, true>;
+    using Full = std::integral_constant<bool, false>;
+    {
+        uint32_t pn0[U];
+        T gs0[U];
+        load_stream(0, pn0, gs0);
+        load_stream(64 * U, pn1, gs1);
+        if (64 * U <= len) gather(Full{}, pn0, gs0, 0, G0);
+        else gather(Masked{}, pn0, gs0, 0, G0);
+    }
+    for (int r = 0; r < len; r += 64 * U) {
+        Gath G1;
+        if (r + 128 * U <= len) gather(Full{}, pn1, gs1, r + 64 * U, G1);
+        else gather(Masked{}, pn1, gs1, r + 64 * U, G1);
+        load_stream(r + 128 * U, pn1, gs1);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const T xa = G0.de[u] + G0.wn[u].a, xe = G0.de[u] - G0.wn[u].a;
+            const T da = stream_gauss(A, xa * xa, s_tab);
+            const T dem = stream_gauss(A, xe * xe, s_tab);
+            const T t = G0.wn[u].b * (da + dem);
+            const T ah = t + dem, bh = t + da;
+            const T fp = G0.fp[u], dl = G0.dl[u];
+            acc += dl * G0.g[u] * (ah * (T(1) - fp) + bh * fp);
+            if (G0.ch[u] >= 0)
+                gg2[G0.ch[u]] = G0.old[u] + static_cast<double>(
+                                                A.K * dl * (bh * fp * (T(1) - fd) - ah * fd * (T(1) - fp)));
+        }
+        G0 = G1;
     }
     if (E.mode < 0) return;
     acc = wave_sum(acc);
@@ -821,6 +914,7 @@ __global__ __launch_bounds__(512) void k_vjp_tiled(TiledArgs<T> A, const T *__re
     const TileRec t = A.tiles[blockIdx.x];
     Pair2<T> *s_ef = reinterpret_cast<Pair2<T> *>(smem);
     uint32_t *s_kq = reinterpret_cast<uint32_t *>(s_ef + A.lds_states);
+    double *s_tab = reinterpret_cast<double *>(s_kq + A.lds_states);
     if (t.lds) {
         const int n = t.p_hi - t.p_lo + 1;
         for (int i = threadIdx.x; i < n; i += blockDim.x) {
@@ -832,16 +926,18 @@ __global__ __launch_bounds__(512) void k_vjp_tiled(TiledArgs<T> A, const T *__re
             s_kq[i] = PADQ ? sr.kqp : sr.kq;
         }
     }
+    if constexpr (sizeof(T) == 8)
+        for (int i = threadIdx.x; i < kExpTab; i += blockDim.x) s_tab[i] = A.e2tab[i];
     __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
     const int nw = static_cast<int>(blockDim.x >> 6);
     for (int64_t c = t.c0 + wave; c < t.c1; c += nw) {
         if (t.lds)
-            vjp_chunk2<T, true, PADQ, U>(A, f, lam, s_ef, s_kq, t.p_lo, c, part, E, ent_chan, gg2,
-                                         gg2_mode);
+            vjp_chunk2<T, true, PADQ, U>(A, f, lam, s_ef, s_kq, t.p_lo, s_tab, c, part, E,
+                                         ent_chan, gg2, gg2_mode);
         else
-            vjp_chunk2<T, false, PADQ, U>(A, f, lam, s_ef, s_kq, t.p_lo, c, part, E, ent_chan, gg2,
-                                          gg2_mode);
+            vjp_chunk2<T, false, PADQ, U>(A, f, lam, s_ef, s_kq, t.p_lo, s_tab, c, part, E,
+                                          ent_chan, gg2, gg2_mode);
     }
 }
 
@@ -874,17 +970,18 @@ __device__ __forceinline__ void tr_chunk(const TiledArgs<T> &A, const T *__restr
     const uint32_t *__restrict__ pb = A.pnu + beg;
     const T *__restrict__ wb = W + beg;
     T a0 = T(0), a1 = T(0), a2 = T(0);
-    for (int r = 0; r < len; r += 64 * U) {
-        uint32_t pn[U];
-        T w[U];
+    auto load = [&](int r0, uint32_t (&pn)[U], T (&w)[U]) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            pn[u] = pb[r + u * 64 + lane];
-            w[u] = wb[r + u * 64 + lane];
+            pn[u] = pb[r0 + u * 64 + lane];
+            w[u] = wb[r0 + u * 64 + lane];
         }
+    };
+    auto body = [&](auto masked, int r, const uint32_t (&pn)[U], const T (&w)[U]) {
+        constexpr bool M = decltype(masked)::value;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const bool v = r + u * 64 + lane < len;
+            const bool v = !M || r + u * 64 + lane < len;
             const int p = static_cast<int>(pn[u] >> 3);
             T x0, x1, x2;
             if (LDS) {
@@ -898,10 +995,27 @@ __device__ __forceinline__ void tr_chunk(const TiledArgs<T> &A, const T *__restr
                 x1 = xp.y;
                 x2 = xp.z;
             }
-            const T ww = v ? w[u] : T(0);
+            const T ww = M ? (v ? w[u] : T(0)) : w[u];
             a0 += ww * x0;
             a1 += ww * x1;
             a2 += ww * x2;
+        }
+    };
+    // the next batch's stream loads are in flight while this batch is
+    // reduced; the arrays are padded, so they need no bound
+    uint32_t pn0[U];
+    T w0[U];
+    load(0, pn0, w0);
+    for (int r = 0; r < len; r += 64 * U) {
+        uint32_t pn1[U];
+        T w1[U];
+        load(r + 64 * U, pn1, w1);
+        if (r + 64 * U <= len) body(std::integral_constant<bool, false>{}, r, pn0, w0);
+        else body(std::integral_constant<bool, true>{}, r, pn0, w0);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            pn0[u] = pn1[u];
+            w0[u] = w1[u];
         }
     }
     a0 = wave_sum(a0);
@@ -1011,6 +1125,33 @@ template <typename T> struct BArgs {
     int padq, qoff;                          // as in TiledArgs
     T mc, K;
 };
+
+// Sub-tile entry offsets of the batch tiles: one workgroup per tile, one
+// thread per (destination, slot); slot k is the first entry of the
+// destination whose partner is >= p_lo + k pt (a lower bound on the sorted
+// partner << 3 | mode keys; the row end if there is none).  A destination's
+// entries are [chunk_beg[dest_chunk[x]], chunk_beg[dest_chunk[x + 1]]).
+__global__ void k_sub_offsets(const BTileRec *__restrict__ tiles, const uint32_t *__restrict__ pnu,
+                              const int64_t *__restrict__ chunk_beg,
+                              const int32_t *__restrict__ dest_chunk, int S, int pt,
+                              int64_t *__restrict__ sub_off) {
+    const BTileRec t = tiles[blockIdx.x];
+    const int per = t.n_sub + 1;
+    const int n = (t.d1 - t.d0) * per;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const int x = t.d0 + i / per;
+        const int k = i % per;
+        int64_t lo = chunk_beg[dest_chunk[x]], hi = chunk_beg[dest_chunk[x + 1]];
+        const int64_t p = static_cast<int64_t>(t.p_lo) + static_cast<int64_t>(k) * pt;
+        const uint32_t key = p >= S ? UINT32_MAX : static_cast<uint32_t>(p) << 3;
+        while (lo < hi) {
+            const int64_t mid = lo + (hi - lo) / 2;
+            if (pnu[mid] < key) lo = mid + 1;
+            else hi = mid;
+        }
+        sub_off[t.off_base + i] = lo;
+    }
+}
 
 template <typename T> __device__ __forceinline__ T lane_bcast(T v, int src);
 template <> __device__ __forceinline__ double lane_bcast(double v, int src) {

@@ -325,19 +325,19 @@ std::vector<Tile> make_tiles(const ChunkTable &ct, const std::vector<int64_t> &r
     return tiles;
 }
 
-void make_btiles(const HostLayout &L, int32_t pt, int32_t dmax, int32_t window_cap,
-                 std::vector<BTile> *tiles, std::vector<int64_t> *sub_off) {
-    tiles->clear();
-    sub_off->clear();
-    const int32_t S = L.S;
+std::vector<BTile> make_btiles(const std::vector<int32_t> &pmin, const std::vector<int32_t> &pmax,
+                               int32_t pt, int32_t dmax, int32_t window_cap, int64_t *slots) {
+    std::vector<BTile> tiles;
+    const int32_t S = static_cast<int32_t>(pmin.size());
+    int64_t off = 0;
     int32_t d = 0;
     while (d < S) {
-        BTile t{d, d, 0, 0, static_cast<int64_t>(sub_off->size())};
+        BTile t{d, d, 0, 0, off};
         int32_t lo = INT32_MAX, hi = -1;
         while (d < S && d - t.d0 < dmax) {
-            const bool has = L.pmax[d] >= L.pmin[d];
-            const int32_t nlo = has ? std::min(lo, L.pmin[d]) : lo;
-            const int32_t nhi = has ? std::max(hi, L.pmax[d]) : hi;
+            const bool has = pmax[d] >= pmin[d];
+            const int32_t nlo = has ? std::min(lo, pmin[d]) : lo;
+            const int32_t nhi = has ? std::max(hi, pmax[d]) : hi;
             if (d > t.d0 && has && int64_t(nhi) - nlo + 1 > window_cap) break;
             lo = nlo;
             hi = nhi;
@@ -348,16 +348,11 @@ void make_btiles(const HostLayout &L, int32_t pt, int32_t dmax, int32_t window_c
             t.p_lo = lo;
             t.n_sub = static_cast<int32_t>((int64_t(hi) - lo + pt) / pt);
         }
-        for (int32_t x = t.d0; x < t.d1; ++x) {
-            const auto b = L.pnu.begin() + L.row_ptr[x], e = L.pnu.begin() + L.row_ptr[x + 1];
-            for (int32_t k = 0; k <= t.n_sub; ++k) {
-                const int64_t p = int64_t(t.p_lo) + int64_t(k) * pt;
-                const uint32_t key = p >= S ? UINT32_MAX : static_cast<uint32_t>(p) << 3;
-                sub_off->push_back(std::lower_bound(b, e, key) - L.pnu.begin());
-            }
-        }
-        tiles->push_back(t);
+        off += int64_t(t.d1 - t.d0) * (t.n_sub + 1);
+        tiles.push_back(t);
     }
+    *slots = off;
+    return tiles;
 }
 
 }  // namespace ephbte

@@ -62,15 +62,18 @@ std::vector<Tile> make_tiles(const ChunkTable &ct, const std::vector<int64_t> &r
                              int32_t lds_states, int64_t target_entries);
 
 // Batch tiles: up to dmax consecutive destinations whose partner ranges
-// span at most window_cap states (a single destination may exceed it).  For
-// every destination, sub_off holds n_sub + 1 entry offsets: entries with
-// partners in [p_lo + k pt, p_lo + (k+1) pt) are [sub_off[k], sub_off[k+1]).
+// span at most window_cap states (a single destination may exceed it), cut
+// into n_sub partner sub-tiles of pt states from p_lo.  Every destination x
+// of a tile owns n_sub + 1 slots of the sub-tile offset array, from
+// off_base + (x - d0) (n_sub + 1): slot k is the first entry of x whose
+// partner is >= p_lo + k pt (so sub-tile k is [slot k, slot k+1)).  The
+// offsets themselves are searched on the device; *slots receives their count.
 struct BTile {
     int32_t d0, d1, p_lo, n_sub;
     int64_t off_base;
 };
-void make_btiles(const HostLayout &L, int32_t pt, int32_t dmax, int32_t window_cap,
-                 std::vector<BTile> *tiles, std::vector<int64_t> *sub_off);
+std::vector<BTile> make_btiles(const std::vector<int32_t> &pmin, const std::vector<int32_t> &pmax,
+                               int32_t pt, int32_t dmax, int32_t window_cap, int64_t *slots);
 
 // Runs fn(t, begin, end) over [0, n) split into contiguous ranges on up to
 // `threads` host threads (deterministic partition).

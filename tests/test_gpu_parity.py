@@ -185,6 +185,48 @@ def test_batched_pass_matches_oracle(E, B, dtype, name):
     plan.close()
 
 
+@pytest.mark.parametrize("pt", [16, 48, 160])
+def test_batch_partner_tiles(E, pt):
+    """Other partner sub-tile sizes of the batched pass (tile shapes from the
+    host, sub-tile entry offsets searched on the device) against the oracle."""
+    s = synth.tb_system(kn=24, qn=12, target_states=400)
+    B = 16
+    F = np.random.default_rng(pt).uniform(size=(B, s.n_states))
+    nph = s.nph(300.0)
+    plan = E.build_channels(s, device=0)
+    say(f"batch partner sub-tile {pt}")
+    try:
+        E.set_tuning(plan, batch_partners=pt)
+    except E.EphbteError as e:
+        plan.close()
+        assert "LDS" in str(e)
+        pytest.skip(f"sub-tile of {pt} partners exceeds this device's LDS per workgroup")
+    got = host(E.collision_integral(plan, dev(F), dev(nph)))
+    for b in (0, 7, B - 1):
+        assert nerr(got[b], oracle.collision(s, F[b], nph)) <= TOL64, b
+    plan.close()
+
+
+def test_autotune_keeps_results(E):
+    """The autotuner's choice (single-vector chunking, then the batched
+    sub-tile size) leaves the results at the oracle's."""
+    s = synth.tb_system(kn=24, qn=12, target_states=400)
+    nph = s.nph(300.0)
+    plan = E.build_channels(s, device=0)
+    say("autotune B=1 and B=16")
+    t1 = E.autotune(plan, 1)
+    assert t1["chunk_entries"] in (2048, 4096, 8192, 16384) and t1["block_threads"] in (256, 512)
+    f = synth.random_occupations(s, 21)
+    assert nerr(host(E.collision_integral(plan, dev(f), dev(nph))), oracle.collision(s, f, nph)) <= TOL64
+    t16 = E.autotune(plan, 16)
+    assert t16["batch_partners"] in (48, 64, 96, 128, 160)
+    F = np.random.default_rng(16).uniform(size=(16, s.n_states))
+    got = host(E.collision_integral(plan, dev(F), dev(nph)))
+    for b in (0, 15):
+        assert nerr(got[b], oracle.collision(s, F[b], nph)) <= TOL64, b
+    plan.close()
+
+
 def test_batched_rk4_matches_oracle(E):
     s = synth.multiband_system()
     nph = s.nph(300.0)
