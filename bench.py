@@ -34,6 +34,53 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def kernels_source_hash():
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2511_03683_amd", "csrc", "kernels.hpp"), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def profiled_traffic(tag):
+    """HBM bytes per launch of the kernel `tag`, from the committed counter
+    summary under profiles/ (FETCH_SIZE and WRITE_SIZE scaled by a copy
+    kernel), or None when there is none or the kernel source has changed
+    since the counters were taken."""
+    import glob
+    h = kernels_source_hash()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.txt"))):
+        kv = {}
+        with open(path) as fh:
+            for line in fh:
+                if ":" in line:
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("kernel_tag") == tag and kv.get("kernels_hpp_sha256_16") == h:
+            try:
+                return float(kv["traffic_bytes_per_launch"])
+            except (KeyError, ValueError):
+                return None
+    return None
+
+
+def transport_solve(E, plan, f0, vel, nph, timed, tol=1e-8, max_iter=2000):
+    """Mobility at 300 K iterated to a relative change of tol (or to the
+    working precision's floor), timed as one call."""
+    res = {}
+
+    def run():
+        res.update(E.iterate_transport(plan, f0, vel, 300.0, nph, tol=tol, max_iter=max_iter))
+
+    ms, _ = timed(run, 1, 0)
+    mu = res["mu"]
+    out = dict(tol=tol, iterations=res["iters"], converged=res["converged"],
+               stagnated=res["stagnated"], last_relative_change=res["resid"], ms_total=ms,
+               mobility_xx_cm2_per_Vs=float(mu[0, 0]), mobility_yy_cm2_per_Vs=float(mu[1, 1]))
+    log(f"transport solve: {res['iters']} iterations, converged={res['converged']} "
+        f"stagnated={res['stagnated']} change={res['resid']:.2e}, mu_xx={mu[0, 0]:.2f} cm2/Vs, "
+        f"{ms:.1f} ms")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,6 +200,7 @@ def main():
         t6, _ = timed(lambda: E.iterate_transport(plan64, f0, vel, 300.0, n64, tol=0.0, max_iter=6), 1, 0)
         forms["transport_iter_f64"] = dict(ms_per_iteration=(t6 - t1) / 5.0, ms_setup_plus_one=t1)
         log(f"transport fp64: {(t6 - t1) / 5:.3f} ms/iteration, setup+1 {t1:.3f} ms")
+        forms["transport_solve_f64"] = transport_solve(E, plan64, f0, vel, n64, timed)
         del vel, f0
         # differentiation: adjoint through 200 RK4 steps (checkpoint every 20) of
         # L = sum eps f(T) / sum f(T), FP64
@@ -194,6 +242,9 @@ def main():
         forms["fwd_f32_b1"] = dict(ms=ms32, channels_per_s=nch / (ms32 * 1e-3),
                                    algorithmic_GBps=BYTES_PER_CHANNEL["f32"] * nch / (ms32 * 1e-3) / 1e9)
         log(f"fwd fp32: {ms32:.3f} ms")
+        forms["transport_solve_f32"] = transport_solve(
+            E, plan32, tens(synth.fermi_dirac(s.eps, -0.1, 300.0), torch.float32),
+            tens(s.vel, torch.float32), n32, timed)
         # dynamics: hot pulse, phonons fixed at 300 K, RK4 dt = 1 fs in HIP graphs
         n_dyn = 200 if args.quick else 2000
         eps32 = tens(s.eps, torch.float64)
@@ -267,7 +318,8 @@ def main():
                    "entries": 2 * nch, "kgrid": list(s.kgrid), "qgrid": list(s.qgrid),
                    "modes": s.n_modes, "sigma_eV": s.sigma, "batch": 1},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": profiled_traffic(f"k_fwd_tiled_{args.dtype}_{wname}")},
         "cpu_baseline": cpu,
         "forms": forms,
     }

@@ -191,7 +191,10 @@ ephbte_status ephbte_rt_adjoint(ephbte_plan plan, const void *f0, const void *np
  * x_out: device [S][3] plan dtype (may be NULL), final iterate (fs m/s / eV).
  * mobility_cm2_per_Vs: host double[9], row-major mu_ab.
  * Stops when max|mu_new - mu_old| / max|mu_new| <= tol; NOT_CONVERGED after
- * max_iter iterations, with the last iterate and mobility written.  *iters and
+ * max_iter iterations, or earlier when that relative change has not set a new
+ * minimum for 5 iterations (the floor of the working precision, e.g. FP32
+ * above a 1e-8 tolerance; ephbte_last_error says "stagnated"), with the last
+ * iterate and mobility written in either case.  *iters and
  * *resid (host, may be NULL) receive the iteration count and last relative change.
  * Synchronises on `stream` once per iteration (9 scalars device to host).
  */

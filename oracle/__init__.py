@@ -263,10 +263,14 @@ def transport_apply_W(sys, Wij, Wji, x):
     return out
 
 
-def transport_solve(sys, f0, vel, T, nph, tol=1e-8, max_iter=200, g2=None, stop_on_tol=True):
+def transport_solve(sys, f0, vel, T, nph, tol=1e-8, max_iter=200, g2=None, stop_on_tol=True,
+                    stall=5):
     """Iterate x_d = tau_d (v_d df0/de + sum_p W_dp x_p) from the RTA start
-    until the mobility changes by at most tol (relative, max norm).
-    Returns dict(mu [3,3] cm^2/Vs, x [S,3], iters, converged, history)."""
+    until the mobility changes by at most tol (relative, max norm), or until
+    that change has not fallen below its smallest value for `stall`
+    iterations (the floor of the working precision; stagnated=True).
+    Returns dict(mu [3,3] cm^2/Vs, x [S,3], iters, converged, stagnated,
+    history, resid)."""
     tau_inv, Wij, Wji = transport_coeffs(sys, f0, nph, g2)
     # a state without any scattering (tau_inv = 0) is left out: x_d = 0
     tau = np.where(tau_inv > 0, 1.0 / np.where(tau_inv > 0, tau_inv, 1.0), 0.0)
@@ -274,6 +278,7 @@ def transport_solve(sys, f0, vel, T, nph, tol=1e-8, max_iter=200, g2=None, stop_
     x = tau[:, None] * b
     mu = mobility_cm2(vel, x, f0)
     hist = [mu]
+    best, since = np.inf, 0
     for it in range(1, max_iter + 1):
         x = tau[:, None] * (b + transport_apply_W(sys, Wij, Wji, x))
         mu_new = mobility_cm2(vel, x, f0)
@@ -281,5 +286,11 @@ def transport_solve(sys, f0, vel, T, nph, tol=1e-8, max_iter=200, g2=None, stop_
         mu = mu_new
         hist.append(mu)
         if stop_on_tol and rel <= tol:
-            return dict(mu=mu, x=x, iters=it, converged=True, history=hist, resid=rel)
-    return dict(mu=mu, x=x, iters=max_iter, converged=False, history=hist, resid=rel)
+            return dict(mu=mu, x=x, iters=it, converged=True, stagnated=False, history=hist, resid=rel)
+        if rel < best:
+            best, since = rel, 0
+        else:
+            since += 1
+        if stop_on_tol and since >= stall:
+            return dict(mu=mu, x=x, iters=it, converged=False, stagnated=True, history=hist, resid=rel)
+    return dict(mu=mu, x=x, iters=max_iter, converged=False, stagnated=False, history=hist, resid=rel)

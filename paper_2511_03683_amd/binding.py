@@ -341,8 +341,9 @@ def iterate_transport(plan: Plan, f0, vel, T_K: float, nph, tol: float = 1e-8,
         int(max_iter), x.data_ptr() if x is not None else None, mob.ctypes.data,
         ctypes.byref(iters), ctypes.byref(resid), _stream(f0.device))
     _check(st, "iterate_transport", allow=() if raise_on_nonconv else (NOT_CONVERGED,))
+    stagnated = st == NOT_CONVERGED and "stagnated" in last_error()
     return dict(mu=mob.reshape(3, 3), iters=int(iters.value), resid=float(resid.value),
-                converged=(st == OK), x=x)
+                converged=(st == OK), stagnated=stagnated, x=x)
 
 
 def update_g2(plan: Plan, g2):

@@ -796,6 +796,10 @@ ephbte_status rt_adjoint_impl(ephbte_plan P, const T *f0, const void *nph, doubl
     return EPHBTE_OK;
 }
 
+// iterations without a new smallest relative change after which the
+// transport iteration stops at its precision floor
+constexpr int kStall = 5;
+
 template <typename T>
 ephbte_status transport_impl(ephbte_plan P, const T *f0, const T *vel, double T_K,
                              const void *nph, double tol, int max_iter, T *x_out, double *mob,
@@ -849,9 +853,9 @@ ephbte_status transport_impl(ephbte_plan P, const T *f0, const T *vel, double T_
     const double unit = -1e-15 * 1e4 / sum_f0;   // fs -> s, m^2 -> cm^2, e = 1
     double mu[9];
     for (int k = 0; k < 9; ++k) mu[k] = unit * r0[k];
-    double rel = INFINITY;
-    int it = 0;
-    bool conv = false;
+    double rel = INFINITY, best = INFINITY;
+    int it = 0, since_best = 0;
+    bool conv = false, stalled = false;
     for (it = 1; it <= max_iter; ++it) {
         {
             TiledArgs<T> ta = tiled_args<T>(P);
@@ -881,6 +885,14 @@ ephbte_status transport_impl(ephbte_plan P, const T *f0, const T *vel, double T_
             conv = true;
             break;
         }
+        // the working precision's floor: no new smallest change in kStall iterations
+        if (rel < best) {
+            best = rel;
+            since_best = 0;
+        } else if (++since_best >= kStall) {
+            stalled = true;
+            break;
+        }
     }
     if (it > max_iter) it = max_iter;
     if (x_out) {
@@ -891,6 +903,10 @@ ephbte_status transport_impl(ephbte_plan P, const T *f0, const T *vel, double T_
     std::memcpy(mob, mu, sizeof(mu));
     if (iters) *iters = it;
     if (resid) *resid = rel;
+    if (stalled)
+        return fail(EPHBTE_NOT_CONVERGED,
+                    "transport iteration stagnated: the relative change stopped decreasing above "
+                    "the tolerance (the working precision's floor)");
     if (!conv) return fail(EPHBTE_NOT_CONVERGED, "transport iteration did not reach the tolerance");
     return EPHBTE_OK;
 }

@@ -471,6 +471,27 @@ def test_transport_matches_oracle(E, dtype):
     plan.close()
 
 
+def test_transport_fp32_stops_at_its_floor(E):
+    """FP32 cannot resolve a 1e-12 change: the iteration stops on stagnation
+    (reported as such) well before max_iter, with the mobility of the FP64
+    fixed point to FP32 accuracy."""
+    s = synth.tb_system(kn=20, qn=10, target_states=300, sigma=0.05)
+    T = 300.0
+    f0 = synth.fermi_dirac(s.eps, -0.1, T)
+    nph = s.nph(T)
+    plan = E.build_channels(s, dtype="f32", device=0)
+    say("transport f32 stagnation stop")
+    out = E.iterate_transport(plan, dev(f0, torch.float32), dev(s.vel, torch.float32), T,
+                              dev(nph, torch.float32), tol=1e-12, max_iter=2000)
+    # either the change stopped decreasing, or FP32 landed on an exact fixed point
+    assert out["iters"] < 2000
+    assert out["stagnated"] or (out["converged"] and out["resid"] == 0.0)
+    ref = oracle.transport_solve(s, f0, s.vel, T, nph, tol=1e-12, max_iter=2000)
+    assert ref["converged"]
+    assert nerr(out["mu"], ref["mu"]) <= 1e-4
+    plan.close()
+
+
 # ------------------------------------------------------------------ full size
 @pytest.fixture(scope="module")
 def c2():

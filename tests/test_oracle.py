@@ -301,6 +301,21 @@ def test_transport_fixed_point_equals_direct_solve():
     assert np.all(np.diag(out["mu"]) > 0)
 
 
+def test_transport_stops_at_precision_floor():
+    """With a tolerance below what FP64 can resolve, the iteration stops once
+    the relative mobility change has not set a new minimum for 5 iterations,
+    at a change near the rounding level, before max_iter."""
+    s = synth.tb_system(kn=20, qn=10, target_states=300, sigma=0.05)
+    T = 300.0
+    f0 = synth.fermi_dirac(s.eps, -0.1, T)
+    out = oracle.transport_solve(s, f0, s.vel, T, s.nph(T), tol=0.0, max_iter=3000)
+    assert out["stagnated"] and not out["converged"]
+    assert out["iters"] < 3000
+    assert out["resid"] < 1e-13
+    hist = np.array([np.abs(h).max() for h in out["history"]])
+    assert np.all(np.isfinite(hist))
+
+
 def test_c1_matches_stored_oracle_sample(c1):
     """Regression fixture written by tests/golden/make_golden.py (oracle only)."""
     import json, os
