@@ -528,6 +528,23 @@ def pulse_occupations(system: System, mu=-0.1, T=300.0, amplitude=0.1, center=0.
     return np.clip(f, 0.0, 1.0)
 
 
+def batch_occupations(system: System, mu=0.05, temps=None, fields=None, tau0_fs=10.0) -> np.ndarray:
+    """A family of electron occupation vectors, one per (temperature, field):
+    Fermi-Dirac at T_b displaced by a field E_b along x,
+    f_b(s) = FD(eps_s + tau0 e E_b v_x(s); mu, T_b), with tau0 e E_b v_x in eV
+    for E in V/m, tau0 in fs and v in m/s.  Default: 16 temperatures from
+    100 to 400 K times 4 fields from 0 to 1e5 V/m (64 rows, temperature-major)."""
+    temps = np.linspace(100.0, 400.0, 16) if temps is None else np.asarray(temps, dtype=np.float64)
+    fields = np.linspace(0.0, 1e5, 4) if fields is None else np.asarray(fields, dtype=np.float64)
+    vx = np.asarray(system.vel, dtype=np.float64)[:, 0]
+    rows = []
+    for T in temps:
+        for Ef in fields:
+            shift = tau0_fs * 1e-15 * Ef * vx
+            rows.append(fermi_dirac(np.asarray(system.eps) + shift, mu, T))
+    return np.stack(rows)
+
+
 def grouped_system(n_systems=16, ch_min=1e5, ch_max=1e7, seed=2511, base=None) -> System:
     """Uneven batch of small systems in one problem: n_systems subsets of the
     tight-binding window states (each inside one coset of the q grid, so every
