@@ -400,10 +400,10 @@ void enqueue_forward(ephbte_plan P, int B, const T *f, int64_t ldf, const void *
     T *part = static_cast<T *>(P->part.p);
     dim3 grid(static_cast<unsigned>(P->n_tiles), B);
     if (P->padq)
-        hipLaunchKernelGGL((k_fwd_tiled<T, 4, true, 512, true, true>), grid, dim3(P->block_threads),
+        hipLaunchKernelGGL((k_fwd_tiled<T, 4, 512, true>), grid, dim3(P->block_threads),
                            tiled_lds_bytes(P), s, a, f, ldf, part, E);
     else
-        hipLaunchKernelGGL((k_fwd_tiled<T, 4, true, 512, true, false>), grid, dim3(P->block_threads),
+        hipLaunchKernelGGL((k_fwd_tiled<T, 4, 512, false>), grid, dim3(P->block_threads),
                            tiled_lds_bytes(P), s, a, f, ldf, part, E);
     if (!P->fused) {
         dim3 g2((P->S + 255) / 256, B);

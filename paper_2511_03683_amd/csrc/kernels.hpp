@@ -260,79 +260,6 @@ __device__ __forceinline__ EntryCoef<T> entry_coef(const Tables<T> &P, T eps_d, 
     return c;
 }
 
-// ---- forward: I[f] -------------------------------------------------------
-// FUSED: one chunk per destination, the workgroup applies the epilogue.
-// Otherwise the two sums of each chunk go to part[b][chunk][2].
-template <typename T, bool FUSED>
-__global__ __launch_bounds__(512) void k_collision(Tables<T> P, const T *__restrict__ f,
-                                                   int64_t ldf, T *__restrict__ part, Epi<T> E) {
-    const int64_t c = chunk_of_block(P.n_chunks, P.xcd_m);
-    if (c >= P.n_chunks) return;
-    const int b = blockIdx.y;
-    const T *fb = f + static_cast<int64_t>(b) * ldf;
-    const int d = P.chunk_dest[c];
-    const int64_t beg = P.chunk_beg[c], end = P.chunk_beg[c + 1];
-    const StateRec<T> sd = P.st[d];
-    T acc[2] = {T(0), T(0)};   // sum a (1 - f_p), sum b f_p
-    const int stride = blockDim.x;
-    int64_t e = beg + threadIdx.x;
-    for (; e + 3 * stride < end; e += 4 * stride) {
-        uint32_t pn[4];
-        T g[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            pn[u] = P.pnu[e + u * stride];
-            g[u] = P.g2[e + u * stride];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int p = static_cast<int>(pn[u] >> 3);
-            const StateRec<T> sp = P.st[p];
-            const T fp = fb[p];
-            EntryCoef<T> k = entry_coef(P, sd.eps, sd.kq, pn[u], sp);
-            acc[0] += g[u] * k.ah * (T(1) - fp);
-            acc[1] += g[u] * k.bh * fp;
-        }
-    }
-    for (; e < end; e += stride) {
-        const uint32_t pn = P.pnu[e];
-        const T g = P.g2[e];
-        const int p = static_cast<int>(pn >> 3);
-        const StateRec<T> sp = P.st[p];
-        const T fp = fb[p];
-        EntryCoef<T> k = entry_coef(P, sd.eps, sd.kq, pn, sp);
-        acc[0] += g * k.ah * (T(1) - fp);
-        acc[1] += g * k.bh * fp;
-    }
-    block_sum<T, 2>(acc);
-    if (threadIdx.x == 0) {
-        if (FUSED) {
-            const T fd = fb[d];
-            apply_epi(E, b, d, P.S, P.K * ((T(1) - fd) * acc[1] - fd * acc[0]));
-        } else {
-            T *pp = part + (static_cast<int64_t>(b) * P.n_chunks + c) * 2;
-            pp[0] = acc[0];
-            pp[1] = acc[1];
-        }
-    }
-}
-
-template <typename T>
-__global__ void k_collision_finish(Tables<T> P, const T *__restrict__ f, int64_t ldf,
-                                   const T *__restrict__ part, Epi<T> E) {
-    const int d = blockIdx.x * blockDim.x + threadIdx.x;
-    if (d >= P.S) return;
-    const int b = blockIdx.y;
-    T a = T(0), bb = T(0);
-    const T *pb = part + static_cast<int64_t>(b) * P.n_chunks * 2;
-    for (int c = P.dest_chunk[d]; c < P.dest_chunk[d + 1]; ++c) {
-        a += pb[2 * c];
-        bb += pb[2 * c + 1];
-    }
-    const T fd = f[static_cast<int64_t>(b) * ldf + d];
-    apply_epi(E, b, d, P.S, P.K * ((T(1) - fd) * bb - fd * a));
-}
-
 // ---- forward, LDS-tiled --------------------------------------------------
 // One workgroup per tile (a run of chunks whose destinations' partners fit an
 // LDS window).  The tile's partner states {eps, f} and packed k are staged in
@@ -534,188 +461,7 @@ __device__ __forceinline__ void fwd_chunk2(const TiledArgs<T> &A, const T *__res
     }
 }
 
-template <typename T, bool LDS, int U>
-__device__ __forceinline__ void fwd_chunk(const TiledArgs<T> &A, const T *__restrict__ fb,
-                                          const Pair2<T> *s_ef, const uint32_t *s_kq, int p_lo,
-                                          int64_t c, int b, T *__restrict__ part,
-                                          const Epi<T> &E) {
-    const int lane = threadIdx.x & 63;
-    const int d = A.chunk_dest[c];
-    const int64_t beg = A.chunk_beg[c], end = A.chunk_beg[c + 1];
-    const StateRec<T> sd = A.st[d];
-    T acc_a = T(0), acc_b = T(0);
-    uint32_t pn[U];
-    T g[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const int64_t i = beg + u * 64 + lane;
-        pn[u] = i < end ? A.pnu[i] : 0u;
-        g[u] = i < end ? A.g2[i] : T(0);
-    }
-    for (int64_t e0 = beg; e0 < end; e0 += 64 * U) {
-        // next batch of the stream, issued before this batch's gathers
-        uint32_t pn_n[U];
-        T g_n[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t i = e0 + 64 * U + u * 64 + lane;
-            pn_n[u] = i < end ? A.pnu[i] : 0u;
-            g_n[u] = i < end ? A.g2[i] : T(0);
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (e0 + u * 64 + lane < end) {
-                const int p = static_cast<int>(pn[u] >> 3);
-                T ep, fp;
-                uint32_t kp;
-                if (LDS) {
-                    const Pair2<T> ef = s_ef[p - p_lo];
-                    ep = ef.a;
-                    fp = ef.b;
-                    kp = s_kq[p - p_lo];
-                } else {
-                    const StateRec<T> sp = A.st[p];
-                    ep = sp.eps;
-                    kp = sp.kq;
-                    fp = fb[p];
-                }
-                const int q = q_linear(sd.kq, kp, A.nq0, A.nq1, A.nq2);
-                const Pair2<T> wn = A.hwN[static_cast<int64_t>(q) * A.nm + (pn[u] & 7u)];
-                const T de = sd.eps - ep;
-                const T xa = de + wn.a, xe = de - wn.a;
-                const T da = gauss_exp(xa * xa * A.mc);
-                const T dem = gauss_exp(xe * xe * A.mc);
-                const T t = wn.b * (da + dem);
-                acc_a += g[u] * (t + dem) * (T(1) - fp);
-                acc_b += g[u] * (t + da) * fp;
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            pn[u] = pn_n[u];
-            g[u] = g_n[u];
-        }
-    }
-    acc_a = wave_sum(acc_a);
-    acc_b = wave_sum(acc_b);
-    if (lane == 0) {
-        if (A.dest_chunk[d + 1] - A.dest_chunk[d] == 1) {
-            const T fd = fb[d];
-            apply_epi(E, b, d, A.S, A.K * ((T(1) - fd) * acc_b - fd * acc_a));
-        } else {
-            T *pp = part + (static_cast<int64_t>(b) * A.n_chunks + c) * 2;
-            pp[0] = acc_a;
-            pp[1] = acc_b;
-        }
-    }
-}
-
-// Same reduction as fwd_chunk with a three-stage software pipeline: while
-// batch i is evaluated, the phonon-table gathers of batch i+1 and the stream
-// loads of batch i+2 are already in flight.
-template <typename T, bool LDS, int U>
-__device__ __forceinline__ void fwd_chunk_pipe(const TiledArgs<T> &A, const T *__restrict__ fb,
-                                               const Pair2<T> *s_ef, const uint32_t *s_kq,
-                                               int p_lo, int64_t c, int b, T *__restrict__ part,
-                                               const Epi<T> &E) {
-    const int lane = threadIdx.x & 63;
-    const int d = A.chunk_dest[c];
-    const int64_t beg = A.chunk_beg[c], end = A.chunk_beg[c + 1];
-    const StateRec<T> sd = A.st[d];
-    T acc_a = T(0), acc_b = T(0);
-    // stage registers: stream (pn, g) for batch i+1, table/partner data for batch i
-    uint32_t pn1[U];
-    T g1[U];
-    T g0[U], de0[U], fp0[U];
-    Pair2<T> wn0[U];
-    auto load_stream = [&](int64_t e0, uint32_t (&pn)[U], T (&g)[U]) {
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t i = e0 + u * 64 + lane;
-            pn[u] = i < end ? A.pnu[i] : 0u;
-            g[u] = i < end ? A.g2[i] : T(0);
-        }
-    };
-    // partner data + table gather for one batch (entries past the end get g = 0)
-    auto gather = [&](const uint32_t (&pn)[U], const T (&g)[U], int64_t e0, T (&go)[U],
-                      T (&deo)[U], T (&fpo)[U], Pair2<T> (&wno)[U]) {
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const bool v = e0 + u * 64 + lane < end;
-            const int p = static_cast<int>(pn[u] >> 3);
-            T ep = T(0), fp = T(0);
-            uint32_t kp = sd.kq;
-            if (v) {
-                if (LDS) {
-                    const Pair2<T> ef = s_ef[p - p_lo];
-                    ep = ef.a;
-                    fp = ef.b;
-                    kp = s_kq[p - p_lo];
-                } else {
-                    const StateRec<T> sp = A.st[p];
-                    ep = sp.eps;
-                    kp = sp.kq;
-                    fp = fb[p];
-                }
-            }
-            if (v) {
-                const int q = q_linear(sd.kq, kp, A.nq0, A.nq1, A.nq2);
-                wno[u] = A.hwN[static_cast<int64_t>(q) * A.nm + (pn[u] & 7u)];
-            } else {
-                wno[u].a = T(0);
-                wno[u].b = T(0);
-            }
-            go[u] = v ? g[u] : T(0);
-            deo[u] = sd.eps - ep;
-            fpo[u] = fp;
-        }
-    };
-    {
-        uint32_t pn0[U];
-        T gs0[U];
-        load_stream(beg, pn0, gs0);
-        load_stream(beg + 64 * U, pn1, g1);
-        gather(pn0, gs0, beg, g0, de0, fp0, wn0);
-    }
-    for (int64_t e0 = beg; e0 < end; e0 += 64 * U) {
-        // batch i+1: table gathers now; batch i+2: stream loads now
-        T g1o[U], de1[U], fp1[U];
-        Pair2<T> wn1[U];
-        gather(pn1, g1, e0 + 64 * U, g1o, de1, fp1, wn1);
-        load_stream(e0 + 128 * U, pn1, g1);
-        // evaluate batch i (entries past the end carry g = 0)
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const T xa = de0[u] + wn0[u].a, xe = de0[u] - wn0[u].a;
-            const T da = gauss_exp(xa * xa * A.mc);
-            const T dem = gauss_exp(xe * xe * A.mc);
-            const T t = wn0[u].b * (da + dem);
-            acc_a += g0[u] * (t + dem) * (T(1) - fp0[u]);
-            acc_b += g0[u] * (t + da) * fp0[u];
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            g0[u] = g1o[u];
-            de0[u] = de1[u];
-            fp0[u] = fp1[u];
-            wn0[u] = wn1[u];
-        }
-    }
-    acc_a = wave_sum(acc_a);
-    acc_b = wave_sum(acc_b);
-    if (lane == 0) {
-        if (A.dest_chunk[d + 1] - A.dest_chunk[d] == 1) {
-            const T fd = fb[d];
-            apply_epi(E, b, d, A.S, A.K * ((T(1) - fd) * acc_b - fd * acc_a));
-        } else {
-            T *pp = part + (static_cast<int64_t>(b) * A.n_chunks + c) * 2;
-            pp[0] = acc_a;
-            pp[1] = acc_b;
-        }
-    }
-}
-
-template <typename T, int U, bool PIPE, int MAXT, bool V2 = false, bool PADQ = false>
+template <typename T, int U, int MAXT, bool PADQ>
 __global__ __launch_bounds__(MAXT) void k_fwd_tiled(TiledArgs<T> A, const T *__restrict__ f,
                                                     int64_t ldf, T *__restrict__ part, Epi<T> E) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -736,28 +482,16 @@ __global__ __launch_bounds__(MAXT) void k_fwd_tiled(TiledArgs<T> A, const T *__r
             s_kq[i] = PADQ ? sr.kqp : sr.kq;
         }
     }
-    if constexpr (V2 && sizeof(T) == 8)
+    if constexpr (sizeof(T) == 8)
         for (int i = threadIdx.x; i < kExpTab; i += blockDim.x) s_tab[i] = A.e2tab[i];
     __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
     const int nw = static_cast<int>(blockDim.x >> 6);
     for (int64_t c = t.c0 + wave; c < t.c1; c += nw) {
-        if constexpr (V2) {
-            if (t.lds)
-                fwd_chunk2<T, true, PADQ, U>(A, fb, s_ef, s_kq, t.p_lo, s_tab, c, b, part, E);
-            else
-                fwd_chunk2<T, false, PADQ, U>(A, fb, s_ef, s_kq, t.p_lo, s_tab, c, b, part, E);
-        } else if constexpr (PIPE) {
-            if (t.lds)
-                fwd_chunk_pipe<T, true, U>(A, fb, s_ef, s_kq, t.p_lo, c, b, part, E);
-            else
-                fwd_chunk_pipe<T, false, U>(A, fb, s_ef, s_kq, t.p_lo, c, b, part, E);
-        } else {
-            if (t.lds)
-                fwd_chunk<T, true, U>(A, fb, s_ef, s_kq, t.p_lo, c, b, part, E);
-            else
-                fwd_chunk<T, false, U>(A, fb, s_ef, s_kq, t.p_lo, c, b, part, E);
-        }
+        if (t.lds)
+            fwd_chunk2<T, true, PADQ, U>(A, fb, s_ef, s_kq, t.p_lo, s_tab, c, b, part, E);
+        else
+            fwd_chunk2<T, false, PADQ, U>(A, fb, s_ef, s_kq, t.p_lo, s_tab, c, b, part, E);
     }
 }
 
@@ -1264,63 +998,6 @@ __global__ __launch_bounds__(512) void k_fwd_batched(BArgs<T> A, const T *__rest
     }
 }
 
-// ---- reverse: dL/df and dL/d|g|^2 ---------------------------------------
-// dL/df_d = -K sum_entries (lam_d - lam_p) (a (1 - f_p) + b f_p)
-// dL/dg2_c = K (lam_d - lam_p) (bh f_p (1 - f_d) - ah f_d (1 - f_p)), written by
-// the entry with p > d (each channel has exactly one such entry).
-template <typename T, bool FUSED>
-__global__ __launch_bounds__(512) void k_collision_vjp(Tables<T> P, const T *__restrict__ f,
-                                                       int64_t ldf, const T *__restrict__ lam,
-                                                       int64_t ldl, T *__restrict__ part, Epi<T> E,
-                                                       double *__restrict__ gg2, int gg2_mode) {
-    const int64_t c = chunk_of_block(P.n_chunks, P.xcd_m);
-    if (c >= P.n_chunks) return;
-    const int b = blockIdx.y;
-    const T *fb = f + static_cast<int64_t>(b) * ldf;
-    const T *lb = lam + static_cast<int64_t>(b) * ldl;
-    const int d = P.chunk_dest[c];
-    const int64_t beg = P.chunk_beg[c], end = P.chunk_beg[c + 1];
-    const StateRec<T> sd = P.st[d];
-    const T fd = fb[d];
-    const T ld = lb[d];
-    T acc[1] = {T(0)};
-    for (int64_t e = beg + threadIdx.x; e < end; e += blockDim.x) {
-        const uint32_t pn = P.pnu[e];
-        const T g = P.g2[e];
-        const int p = static_cast<int>(pn >> 3);
-        const StateRec<T> sp = P.st[p];
-        const T fp = fb[p];
-        const T dl = ld - lb[p];
-        EntryCoef<T> k = entry_coef(P, sd.eps, sd.kq, pn, sp);
-        acc[0] += dl * g * (k.ah * (T(1) - fp) + k.bh * fp);
-        if (gg2_mode && p > d) {
-            const double v = static_cast<double>(P.K * dl * (k.bh * fp * (T(1) - fd) - k.ah * fd * (T(1) - fp)));
-            double *o = gg2 + P.ent_chan[e];
-            *o = (gg2_mode == 2) ? (*o + v) : v;
-        }
-    }
-    if (E.mode < 0) return;   // |g|^2 gradient only
-    block_sum<T, 1>(acc);
-    if (threadIdx.x == 0) {
-        if (FUSED) {
-            apply_epi(E, b, d, P.S, -P.K * acc[0]);
-        } else {
-            part[static_cast<int64_t>(b) * P.n_chunks + c] = acc[0];
-        }
-    }
-}
-
-template <typename T>
-__global__ void k_vjp_finish(Tables<T> P, const T *__restrict__ part, Epi<T> E) {
-    const int d = blockIdx.x * blockDim.x + threadIdx.x;
-    if (d >= P.S) return;
-    const int b = blockIdx.y;
-    T a = T(0);
-    const T *pb = part + static_cast<int64_t>(b) * P.n_chunks;
-    for (int c = P.dest_chunk[d]; c < P.dest_chunk[d + 1]; ++c) a += pb[c];
-    apply_epi(E, b, d, P.S, -P.K * a);
-}
-
 // ---- transport ----------------------------------------------------------
 // Linearisation at f0: per entry W_dp = K g2 [da (N + 1 - f0_d) + de (N + f0_d)]
 // is stored; 1/tau_d = K sum g2 [da (N + f0_p) + de (N + 1 - f0_p)].
@@ -1364,71 +1041,6 @@ __global__ void k_transport_setup_finish(Tables<T> P, const T *__restrict__ part
     T a = T(0);
     for (int c = P.dest_chunk[d]; c < P.dest_chunk[d + 1]; ++c) a += part[c];
     tau_inv[d] = P.K * a;
-}
-
-// x_new_d = tau_d (b_d + sum W_dp x_p), three field directions at once.
-template <typename T, bool FUSED>
-__global__ __launch_bounds__(512) void k_transport_iter(Tables<T> P, const T *__restrict__ W,
-                                                        const Vec4<T> *__restrict__ x,
-                                                        const Vec4<T> *__restrict__ rhs,
-                                                        const T *__restrict__ tau,
-                                                        Vec4<T> *__restrict__ part,
-                                                        Vec4<T> *__restrict__ x_new) {
-    const int64_t c = chunk_of_block(P.n_chunks, P.xcd_m);
-    if (c >= P.n_chunks) return;
-    const int d = P.chunk_dest[c];
-    const int64_t beg = P.chunk_beg[c], end = P.chunk_beg[c + 1];
-    T acc[3] = {T(0), T(0), T(0)};
-    for (int64_t e = beg + threadIdx.x; e < end; e += blockDim.x) {
-        const int p = static_cast<int>(P.pnu[e] >> 3);
-        const T w = W[e];
-        const Vec4<T> xp = x[p];
-        acc[0] += w * xp.x;
-        acc[1] += w * xp.y;
-        acc[2] += w * xp.z;
-    }
-    block_sum<T, 3>(acc);
-    if (threadIdx.x == 0) {
-        if (FUSED) {
-            const Vec4<T> r = rhs[d];
-            const T t = tau[d];
-            Vec4<T> o;
-            o.x = t * (r.x + acc[0]);
-            o.y = t * (r.y + acc[1]);
-            o.z = t * (r.z + acc[2]);
-            o.w = T(0);
-            x_new[d] = o;
-        } else {
-            Vec4<T> o;
-            o.x = acc[0];
-            o.y = acc[1];
-            o.z = acc[2];
-            o.w = T(0);
-            part[c] = o;
-        }
-    }
-}
-
-template <typename T>
-__global__ void k_transport_iter_finish(Tables<T> P, const Vec4<T> *__restrict__ part,
-                                        const Vec4<T> *__restrict__ rhs, const T *__restrict__ tau,
-                                        Vec4<T> *__restrict__ x_new) {
-    const int d = blockIdx.x * blockDim.x + threadIdx.x;
-    if (d >= P.S) return;
-    T a0 = T(0), a1 = T(0), a2 = T(0);
-    for (int c = P.dest_chunk[d]; c < P.dest_chunk[d + 1]; ++c) {
-        a0 += part[c].x;
-        a1 += part[c].y;
-        a2 += part[c].z;
-    }
-    const Vec4<T> r = rhs[d];
-    const T t = tau[d];
-    Vec4<T> o;
-    o.x = t * (r.x + a0);
-    o.y = t * (r.y + a1);
-    o.z = t * (r.z + a2);
-    o.w = T(0);
-    x_new[d] = o;
 }
 
 }  // namespace ephbte
