@@ -92,14 +92,19 @@ typedef struct {
     int32_t device;            /* HIP device ordinal; -1 = current device          */
 } ephbte_problem;
 
-/* Tuning knobs of a plan (all optional: 0 = library default). */
+/* Tuning knobs of a plan (all optional: 0 keeps the plan's current value). */
 typedef struct {
     int32_t chunk_entries;     /* max destination entries per workgroup chunk      */
     int32_t block_threads;     /* threads per workgroup: 64, 128, 256, 512         */
-    int32_t xcd_map;           /* 1: contiguous chunk ranges per XCD; 2: plain order */
+    int32_t xcd_map;           /* single-vector forward pass: 1 = each of the 8 XCDs
+                                  takes a contiguous range of tiles (default),
+                                  2 = tiles in plain order                         */
     int32_t batch_partners;    /* partner states per LDS sub-tile of the B >= 8 pass,
                                   16 .. 1024, within the device's LDS per workgroup */
-    int32_t reserved[4];       /* must be 0                                        */
+    int32_t tile_entries;      /* target entries per workgroup tile of the B < 8
+                                  passes (a tile never splits a chunk); -1 = the
+                                  library's default                               */
+    int32_t reserved[3];       /* must be 0                                        */
 } ephbte_tuning;
 
 /*

@@ -42,7 +42,7 @@ class Problem(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("chunk_entries", ctypes.c_int32), ("block_threads", ctypes.c_int32),
                 ("xcd_map", ctypes.c_int32), ("batch_partners", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("tile_entries", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 _LIB = None
@@ -356,10 +356,12 @@ def update_g2(plan: Plan, g2):
            "update_g2")
 
 
-def set_tuning(plan: Plan, chunk_entries=0, block_threads=0, xcd_map=0, batch_partners=0):
+def set_tuning(plan: Plan, chunk_entries=0, block_threads=0, xcd_map=0, batch_partners=0,
+               tile_entries=0):
+    """Knobs left at 0 keep the plan's value; tile_entries=-1 restores its default."""
     t = Tuning()
     t.chunk_entries, t.block_threads, t.xcd_map = int(chunk_entries), int(block_threads), int(xcd_map)
-    t.batch_partners = int(batch_partners)
+    t.batch_partners, t.tile_entries = int(batch_partners), int(tile_entries)
     _check(load_library().ephbte_set_tuning(plan.handle, ctypes.byref(t)), "set_tuning")
 
 
@@ -367,7 +369,7 @@ def autotune(plan: Plan, batch: int = 1) -> dict:
     t = Tuning()
     _check(load_library().ephbte_autotune(plan.handle, int(batch), ctypes.byref(t)), "autotune")
     return dict(chunk_entries=t.chunk_entries, block_threads=t.block_threads, xcd_map=t.xcd_map,
-                batch_partners=t.batch_partners)
+                batch_partners=t.batch_partners, tile_entries=t.tile_entries)
 
 
 def plan_info(plan: Plan) -> dict:

@@ -98,6 +98,7 @@ struct ephbte_plan_s {
     int qoff = 0;
     int64_t qpad_n = 0;         // padded q points
     int chunk_entries = 0;
+    int64_t tile_entries = 0;   // 0: default target per tile
     int block_threads = 256;
     bool xcd_map = true;
     // workspaces, grown on demand
@@ -202,6 +203,11 @@ void free_plan(ephbte_plan P) {
 
 int64_t grid_x(ephbte_plan P) { return P->xcd_map ? 8 * ((P->n_chunks + 7) / 8) : P->n_chunks; }
 
+// workgroups for n tiles (tile_of_block pads to a multiple of the 8 XCDs)
+unsigned tile_grid(ephbte_plan P, int64_t n) {
+    return static_cast<unsigned>(P->xcd_map ? 8 * ((n + 7) / 8) : n);
+}
+
 void upload_chunks(ephbte_plan P, int64_t chunk_entries) {
     ChunkTable t = make_chunks(P->row_ptr, chunk_entries);
     free_graphs(P);
@@ -222,8 +228,11 @@ void upload_chunks(ephbte_plan P, int64_t chunk_entries) {
     P->fused = t.one_per_dest;
     P->chunk_entries = static_cast<int>(std::min<int64_t>(chunk_entries, INT32_MAX));
     // tiles: about 8 per compute unit, each at least a few chunks
-    const int64_t target = std::max<int64_t>(P->E / (8 * static_cast<int64_t>(P->n_cu)) + 1,
-                                             4 * static_cast<int64_t>(std::max(1, P->chunk_entries)));
+    // tiles: by default about 6 per compute unit (3 per resident workgroup slot
+    // at two workgroups per CU), measured best on the 100^3 system
+    const int64_t target = P->tile_entries > 0
+                               ? P->tile_entries
+                               : P->E / (6 * static_cast<int64_t>(P->n_cu)) + 1;
     std::vector<Tile> tl = make_tiles(t, P->row_ptr, P->pmin, P->pmax, P->lds_states, target);
     static_assert(sizeof(Tile) == sizeof(TileRec), "tile record layout");
     dfree(reinterpret_cast<void *&>(P->tiles));
@@ -281,6 +290,8 @@ template <typename T> TiledArgs<T> tiled_args(ephbte_plan P) {
     a.K = t.K;
     a.e2tab = P->e2tab;
     a.mc256 = 256.0 * (-1.4426950408889634 / (2.0 * P->sigma * P->sigma));
+    a.n_tiles = P->n_tiles;
+    a.xcd = P->xcd_map ? 1 : 0;
     return a;
 }
 
@@ -315,6 +326,8 @@ template <typename T> BArgs<T> batch_args(ephbte_plan P) {
     a.pt = P->pt;
     a.padq = P->padq ? 1 : 0;
     a.qoff = P->qoff;
+    a.n_btiles = P->n_btiles;
+    a.xcd = 0;   // measured: plain order is at least as fast for the batched pass
     Tables<T> t = tables<T>(P, nullptr);
     a.mc = t.mc;
     a.K = t.K;
@@ -398,7 +411,7 @@ void enqueue_forward(ephbte_plan P, int B, const T *f, int64_t ldf, const void *
     }
     TiledArgs<T> a = tiled_args<T>(P);
     T *part = static_cast<T *>(P->part.p);
-    dim3 grid(static_cast<unsigned>(P->n_tiles), B);
+    dim3 grid(tile_grid(P, P->n_tiles), B);
     if (P->padq)
         hipLaunchKernelGGL((k_fwd_tiled<T, 4, 512, true>), grid, dim3(P->block_threads),
                            tiled_lds_bytes(P), s, a, f, ldf, part, E);
@@ -429,6 +442,7 @@ void enqueue_vjp(ephbte_plan P, const T *f, const T *lam, const void *nph, const
                  double *gg2, int gg2_mode, hipStream_t s) {
     (void)nph;
     TiledArgs<T> a = tiled_args<T>(P);
+    a.xcd = 0;   // measured: plain tile order is faster for the reverse pass
     T *part = static_cast<T *>(P->part.p);
     dim3 grid(static_cast<unsigned>(P->n_tiles));
     // entries per lane and pipeline stage: 2 in FP64 keeps the two stages in
@@ -586,14 +600,43 @@ template <typename T> void upload_layout(ephbte_plan P, const ephbte_problem *pr
         HIPC(hipMemcpy(P->g2, g.data(), sizeof(T) * E, hipMemcpyHostToDevice));
     }
     {
+        // Padded coordinates are taken from a per-axis origin o: c' = (c - o) mod Nq.
+        // Differences of c' agree with those of c modulo Nq, so the padded table
+        // gives the same q for any origin; placing o at the end of the largest
+        // unoccupied (circular) run of coordinates keeps the states of a window
+        // around k = 0 in one box instead of split across the wrap, so the
+        // differences of all pairs fall in one compact region of the table (one
+        // image per q), which is what the L2 has to hold.
+        uint32_t org[3] = {0, 0, 0};
+        for (int a = 0; a < 3; ++a) {
+            const int n = L.nq[a], sh = 20 - 10 * a;
+            std::vector<char> occ(n, 0);
+            for (int64_t s = 0; s < S; ++s) occ[(L.kq[s] >> sh) & 1023u] = 1;
+            int best_len = 0, best_end = 0;
+            for (int c = 0; c < n; ++c) {
+                if (occ[c]) continue;
+                int len = 0;
+                while (len < n && !occ[(c + len) % n]) ++len;
+                if (len > best_len) {
+                    best_len = len;
+                    best_end = (c + len) % n;
+                }
+                if (len == n) break;
+            }
+            org[a] = best_len > 0 && best_len < n ? static_cast<uint32_t>(best_end) : 0u;
+        }
         std::vector<StateRec<T>> st(S);
         for (int64_t s = 0; s < S; ++s) {
             std::memset(&st[s], 0, sizeof(StateRec<T>));
             st[s].eps = static_cast<T>(pr->eps[s]);
             st[s].kq = L.kq[s];
             if (P->padq) {
-                const uint32_t a0 = L.kq[s] >> 20, a1 = (L.kq[s] >> 10) & 1023u, a2 = L.kq[s] & 1023u;
-                st[s].kqp = (a0 * (2u * L.nq[1]) + a1) * (2u * L.nq[2]) + a2;
+                uint32_t c[3];
+                for (int a = 0; a < 3; ++a) {
+                    const uint32_t n = static_cast<uint32_t>(L.nq[a]);
+                    c[a] = (((L.kq[s] >> (20 - 10 * a)) & 1023u) + n - org[a]) % n;
+                }
+                st[s].kqp = (c[0] * (2u * L.nq[1]) + c[1]) * (2u * L.nq[2]) + c[2];
             }
         }
         HIPC(hipMemcpy(P->st, st.data(), sizeof(StateRec<T>) * S, hipMemcpyHostToDevice));
@@ -859,6 +902,7 @@ ephbte_status transport_impl(ephbte_plan P, const T *f0, const T *vel, double T_
     for (it = 1; it <= max_iter; ++it) {
         {
             TiledArgs<T> ta = tiled_args<T>(P);
+            ta.xcd = 0;
             const size_t shm = static_cast<size_t>(P->lds_states) * 3 * sizeof(T);
             const int use_lds = shm <= P->lds_max ? 1 : 0;
             hipLaunchKernelGGL((k_tr_tiled<T>), dim3(static_cast<unsigned>(P->n_tiles)),
@@ -1064,7 +1108,7 @@ ephbte_status ephbte_build_channels(const ephbte_problem *problem, ephbte_plan *
         }
         { HostLayout tmp; std::swap(tmp, L); }
         P->block_threads = 512;
-        upload_chunks(P, 8192);
+        upload_chunks(P, 65536);
         upload_btiles(P, P->dtype == EPHBTE_F64 ? 96 : 192);
         HIPC(hipDeviceSynchronize());
     } catch (const HipError &e) {
@@ -1239,9 +1283,12 @@ ephbte_status ephbte_set_tuning(ephbte_plan plan, const ephbte_tuning *tuning) {
                         "batch_partners must be in [16, 1024] and fit the LDS of one workgroup");
         for (int r : tuning->reserved)
             if (r != 0) return fail(EPHBTE_INVALID_ARGUMENT, "reserved tuning fields must be 0");
+        if (tuning->tile_entries < -1)
+            return fail(EPHBTE_INVALID_ARGUMENT, "tile_entries must be -1 (default), 0 (keep) or > 0");
         HIPC(hipDeviceSynchronize());
         plan->block_threads = bt;
         if (tuning->xcd_map) plan->xcd_map = tuning->xcd_map == 1;
+        if (tuning->tile_entries) plan->tile_entries = tuning->tile_entries > 0 ? tuning->tile_entries : 0;
         upload_chunks(plan, ce);
         if (pt != 0) upload_btiles(plan, pt);
         free_graphs(plan);
@@ -1327,24 +1374,33 @@ ephbte_status ephbte_autotune(ephbte_plan plan, int32_t batch, ephbte_tuning *ch
             }
             return EPHBTE_OK;
         }
-        const int chunk_c[] = {2048, 4096, 8192, 16384};
-        const int thr_c[] = {256, 512};
+        // chunk size x tile size (default target, and about 4 and 12 tiles per
+        // compute unit) at 512 threads, plus the default tiles at 256 threads
+        const int chunk_c[] = {8192, 16384, 32768, 65536};
+        const int64_t cu = static_cast<int64_t>(plan->n_cu);
+        const int64_t tile_c[] = {0, plan->E / (4 * cu) + 1, plan->E / (12 * cu) + 1};
         float best = INFINITY;
         int best_ce = plan->chunk_entries, best_bt = plan->block_threads;
-        for (int ce : chunk_c)
-            for (int bt : thr_c) {
-                plan->block_threads = bt;
-                upload_chunks(plan, ce);
-                const float ms = time_it();
-                if (ms < best) {
-                    best = ms;
-                    best_ce = ce;
-                    best_bt = bt;
+        int64_t best_te = plan->tile_entries;
+        for (int bt : {512, 256})
+            for (int ce : chunk_c)
+                for (int64_t te : tile_c) {
+                    if (bt == 256 && te != 0) continue;
+                    plan->block_threads = bt;
+                    plan->tile_entries = te;
+                    upload_chunks(plan, ce);
+                    const float ms = time_it();
+                    if (ms < best) {
+                        best = ms;
+                        best_ce = ce;
+                        best_bt = bt;
+                        best_te = te;
+                    }
                 }
-            }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         plan->block_threads = best_bt;
+        plan->tile_entries = best_te;
         upload_chunks(plan, best_ce);
         if (chosen) {
             std::memset(chosen, 0, sizeof(*chosen));
@@ -1352,6 +1408,7 @@ ephbte_status ephbte_autotune(ephbte_plan plan, int32_t batch, ephbte_tuning *ch
             chosen->block_threads = best_bt;
             chosen->xcd_map = plan->xcd_map ? 1 : 2;
             chosen->batch_partners = plan->pt;
+            chosen->tile_entries = best_te > 0 ? static_cast<int32_t>(std::min<int64_t>(best_te, INT32_MAX)) : -1;
         }
         return EPHBTE_OK;
     });

@@ -122,6 +122,18 @@ __device__ __forceinline__ int64_t chunk_of_block(int64_t n_chunks, int64_t xcd_
     return b;
 }
 
+// Tile served by this workgroup.  Workgroups are dispatched to the 8 XCDs
+// round-robin (block b runs on XCD b % 8); with xcd set, each XCD gets a
+// contiguous range of tiles, so the workgroups sharing one L2 work on
+// neighbouring destinations, whose partner and {hw, N} gathers overlap.
+// The grid then has 8 ceil(n / 8) blocks; the extra ones get -1.
+__device__ __forceinline__ int64_t tile_of_block(int64_t n, int xcd) {
+    const int64_t b = blockIdx.x;
+    if (!xcd) return b;
+    const int64_t t = (b & 7) * ((n + 7) / 8) + (b >> 3);
+    return t < n ? t : -1;
+}
+
 template <typename T> struct Tables {
     const uint32_t *__restrict__ pnu;
     const T *__restrict__ g2;
@@ -293,6 +305,8 @@ template <typename T> struct TiledArgs {
     T mc, K;
     const double *__restrict__ e2tab;   // 2^(j/256), j = 0 .. 255 (FP64 kernels)
     double mc256;                       // 256 mc, the table exponential's scale
+    int64_t n_tiles;
+    int xcd;                            // tile ranges per XCD (tile_of_block)
 };
 
 // entries of the exponential table that the FP64 streaming kernels keep in LDS
@@ -312,6 +326,8 @@ __global__ void k_pack_hwN(const T *__restrict__ hw, const T *__restrict__ nph,
 
 // Padded table: entry (qp, nu) holds {hw, N} of q = (c - Nq) mod Nq per axis,
 // where c are the axis coordinates of qp on the (2 Nq0, 2 Nq1, 2 Nq2) grid.
+// The modes of one q are contiguous, so partners at neighbouring k (consecutive
+// q along the last axis) read neighbouring table bytes.
 template <typename T>
 __global__ void k_pack_hwN_pad(const T *__restrict__ hw, const T *__restrict__ nph,
                                Pair2<T> *__restrict__ out, int n0, int n1, int n2, int nm,
@@ -465,7 +481,9 @@ template <typename T, int U, int MAXT, bool PADQ>
 __global__ __launch_bounds__(MAXT) void k_fwd_tiled(TiledArgs<T> A, const T *__restrict__ f,
                                                     int64_t ldf, T *__restrict__ part, Epi<T> E) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const TileRec t = A.tiles[blockIdx.x];
+    const int64_t ti = tile_of_block(A.n_tiles, A.xcd);
+    if (ti < 0) return;
+    const TileRec t = A.tiles[ti];
     const int b = blockIdx.y;
     const T *fb = f + static_cast<int64_t>(b) * ldf;
     Pair2<T> *s_ef = reinterpret_cast<Pair2<T> *>(smem);
@@ -645,7 +663,9 @@ __global__ __launch_bounds__(512) void k_vjp_tiled(TiledArgs<T> A, const T *__re
                                                    Epi<T> E, const int32_t *__restrict__ ent_chan,
                                                    double *__restrict__ gg2, int gg2_mode) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const TileRec t = A.tiles[blockIdx.x];
+    const int64_t ti = tile_of_block(A.n_tiles, A.xcd);
+    if (ti < 0) return;
+    const TileRec t = A.tiles[ti];
     Pair2<T> *s_ef = reinterpret_cast<Pair2<T> *>(smem);
     uint32_t *s_kq = reinterpret_cast<uint32_t *>(s_ef + A.lds_states);
     double *s_tab = reinterpret_cast<double *>(s_kq + A.lds_states);
@@ -784,7 +804,9 @@ __global__ __launch_bounds__(512) void k_tr_tiled(TiledArgs<T> A, int use_lds, c
                                                   const T *__restrict__ tau, Vec4<T> *__restrict__ part,
                                                   Vec4<T> *__restrict__ x_new) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const TileRec t = A.tiles[blockIdx.x];
+    const int64_t ti = tile_of_block(A.n_tiles, A.xcd);
+    if (ti < 0) return;
+    const TileRec t = A.tiles[ti];
     T *s_x = reinterpret_cast<T *>(smem);
     const bool lds = use_lds && t.lds;
     if (lds) {
@@ -858,6 +880,8 @@ template <typename T> struct BArgs {
     int S, nm, nq0, nq1, nq2, pt;
     int padq, qoff;                          // as in TiledArgs
     T mc, K;
+    int64_t n_btiles;
+    int xcd;                                 // as in TiledArgs
 };
 
 // Sub-tile entry offsets of the batch tiles: one workgroup per tile, one
@@ -906,7 +930,9 @@ __global__ __launch_bounds__(512) void k_fwd_batched(BArgs<T> A, const T *__rest
     const int PT = A.pt;
     T *s_F = reinterpret_cast<T *>(smem);                                   // [PT][65]
     StateRec<T> *s_ek = reinterpret_cast<StateRec<T> *>(s_F + PT * 65);    // [PT]
-    const BTileRec t = A.btiles[blockIdx.x];
+    const int64_t ti = tile_of_block(A.n_btiles, A.xcd);
+    if (ti < 0) return;
+    const BTileRec t = A.btiles[ti];
     const int b0 = blockIdx.y * 64;
     const int nb = min(64, B - b0);
     const int lane = threadIdx.x & 63;

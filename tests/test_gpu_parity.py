@@ -107,6 +107,8 @@ def test_fp32_matches_oracle_on_rounded_inputs(E, name):
 
 
 @pytest.mark.parametrize("tuning", [dict(chunk_entries=64), dict(chunk_entries=100, block_threads=64),
+                                    dict(chunk_entries=300, tile_entries=1000),
+                                    dict(chunk_entries=65536, tile_entries=-1),
                                     dict(chunk_entries=1000, block_threads=512),
                                     dict(block_threads=128, xcd_map=2), dict(chunk_entries=7, xcd_map=1)])
 def test_split_segments_and_launch_shapes(E, tuning):
@@ -215,7 +217,8 @@ def test_autotune_keeps_results(E):
     plan = E.build_channels(s, device=0)
     say("autotune B=1 and B=16")
     t1 = E.autotune(plan, 1)
-    assert t1["chunk_entries"] in (2048, 4096, 8192, 16384) and t1["block_threads"] in (256, 512)
+    assert t1["chunk_entries"] in (8192, 16384, 32768, 65536) and t1["block_threads"] in (256, 512)
+    assert t1["tile_entries"] == -1 or t1["tile_entries"] > 0
     f = synth.random_occupations(s, 21)
     assert nerr(host(E.collision_integral(plan, dev(f), dev(nph))), oracle.collision(s, f, nph)) <= TOL64
     t16 = E.autotune(plan, 16)
