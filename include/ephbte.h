@@ -104,7 +104,11 @@ typedef struct {
     int32_t tile_entries;      /* target entries per workgroup tile of the B < 8
                                   passes (a tile never splits a chunk); -1 = the
                                   library's default                               */
-    int32_t reserved[3];       /* must be 0                                        */
+    int32_t layout;            /* single-vector forward pass: 1 = every channel
+                                  evaluated in both of its rows, 2 = once, from
+                                  the row of its smaller state (default where the
+                                  LDS per workgroup allows it)                     */
+    int32_t reserved[2];       /* must be 0                                        */
 } ephbte_tuning;
 
 /*

@@ -42,7 +42,8 @@ class Problem(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("chunk_entries", ctypes.c_int32), ("block_threads", ctypes.c_int32),
                 ("xcd_map", ctypes.c_int32), ("batch_partners", ctypes.c_int32),
-                ("tile_entries", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("tile_entries", ctypes.c_int32), ("layout", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 _LIB = None
@@ -357,11 +358,12 @@ def update_g2(plan: Plan, g2):
 
 
 def set_tuning(plan: Plan, chunk_entries=0, block_threads=0, xcd_map=0, batch_partners=0,
-               tile_entries=0):
-    """Knobs left at 0 keep the plan's value; tile_entries=-1 restores its default."""
+               tile_entries=0, layout=0):
+    """Knobs left at 0 keep the plan's value; tile_entries=-1 restores its default;
+    layout 1 = duplicated rows, 2 = single copy (B = 1 forward pass)."""
     t = Tuning()
     t.chunk_entries, t.block_threads, t.xcd_map = int(chunk_entries), int(block_threads), int(xcd_map)
-    t.batch_partners, t.tile_entries = int(batch_partners), int(tile_entries)
+    t.batch_partners, t.tile_entries, t.layout = int(batch_partners), int(tile_entries), int(layout)
     _check(load_library().ephbte_set_tuning(plan.handle, ctypes.byref(t)), "set_tuning")
 
 

@@ -84,6 +84,19 @@ struct ephbte_plan_s {
     int64_t n_chunks = 0;
     TileRec *tiles = nullptr;
     int64_t n_tiles = 0;
+    // single-copy pass: chunks over the upper part (p > d) of each row
+    int64_t *sym_chunk_beg = nullptr, *sym_chunk_end = nullptr;
+    int32_t *sym_chunk_dest = nullptr, *sym_dest_chunk = nullptr;
+    TileRec *sym_tiles = nullptr;
+    int64_t n_sym_chunks = 0, n_sym_tiles = 0;
+    std::vector<int64_t> upper_beg;        // host: first entry of row d with p > d
+    std::vector<int32_t> pmin_up, pmax_up;  // host: partner range of that part
+    unsigned long long *jacc = nullptr;     // [S] partner-side fixed-point sums (zero between calls)
+    unsigned long long *nmax_bits = nullptr, *gmax_bits = nullptr;
+    double *pack_bmax = nullptr;            // per-block max |N| of the last pack
+    int sym_lds_states = 0;
+    bool sym_ok = false;                    // the single-copy window fits the LDS of a workgroup
+    int layout = 2;                         // B = 1 forward: 1 duplicated rows, 2 single copy
     // batched pass: tiles of destinations and per-destination sub-tile offsets
     BTileRec *btiles = nullptr;
     int64_t *sub_off = nullptr;
@@ -102,7 +115,7 @@ struct ephbte_plan_s {
     int block_threads = 256;
     bool xcd_map = true;
     // workspaces, grown on demand
-    DevBuf part, rk_ua, rk_ub, rk_acc, hwN;
+    DevBuf part, sym_part, rk_ua, rk_ub, rk_acc, hwN;
     DevBuf tr_W, tr_tau_inv, tr_tau, tr_rhs, tr_xa, tr_xb, tr_part, tr_red, tr_red2;
     DevBuf adj_ck, adj_U, adj_la, adj_lb, adj_acc, adj_g, adj_f;
     double *host_red = nullptr;   // pinned
@@ -119,7 +132,7 @@ struct ephbte_plan_s {
 
     size_t bytes() const {
         size_t b = layout_bytes;
-        const DevBuf *w[] = {&part,  &rk_ua, &rk_ub, &rk_acc, &hwN, &tr_W,  &tr_tau_inv, &tr_tau,
+        const DevBuf *w[] = {&part,  &sym_part, &rk_ua, &rk_ub, &rk_acc, &hwN, &tr_W,  &tr_tau_inv, &tr_tau,
                              &tr_rhs, &tr_xa, &tr_xb, &tr_part, &tr_red, &tr_red2, &adj_ck,
                              &adj_U, &adj_la, &adj_lb, &adj_acc, &adj_g, &adj_f};
         for (auto *x : w) b += x->bytes;
@@ -186,9 +199,12 @@ void free_plan(ephbte_plan P) {
     void **ptrs[] = {(void **)&P->pnu,       (void **)&P->g2,         (void **)&P->st,
                      (void **)&P->hw,        (void **)&P->ent_chan,   (void **)&P->chunk_beg,
                      (void **)&P->chunk_dest, (void **)&P->dest_chunk, (void **)&P->tiles,
-                     (void **)&P->btiles,    (void **)&P->sub_off,    (void **)&P->e2tab};
+                     (void **)&P->btiles,    (void **)&P->sub_off,    (void **)&P->e2tab,
+                     (void **)&P->sym_chunk_beg, (void **)&P->sym_chunk_end, (void **)&P->sym_chunk_dest,
+                     (void **)&P->sym_dest_chunk, (void **)&P->sym_tiles, (void **)&P->jacc,
+                     (void **)&P->nmax_bits, (void **)&P->gmax_bits, (void **)&P->pack_bmax};
     for (auto pp : ptrs) dfree(*pp);
-    DevBuf *w[] = {&P->part,   &P->rk_ua,  &P->rk_ub,   &P->rk_acc, &P->hwN, &P->tr_W,   &P->tr_tau_inv,
+    DevBuf *w[] = {&P->part,   &P->sym_part, &P->rk_ua,  &P->rk_ub,   &P->rk_acc, &P->hwN, &P->tr_W,   &P->tr_tau_inv,
                    &P->tr_tau, &P->tr_rhs, &P->tr_xa,   &P->tr_xb,  &P->tr_part, &P->tr_red,
                    &P->tr_red2, &P->adj_ck, &P->adj_U,  &P->adj_la, &P->adj_lb, &P->adj_acc,
                    &P->adj_g,  &P->adj_f};
@@ -227,7 +243,6 @@ void upload_chunks(ephbte_plan P, int64_t chunk_entries) {
     P->n_chunks = t.n_chunks;
     P->fused = t.one_per_dest;
     P->chunk_entries = static_cast<int>(std::min<int64_t>(chunk_entries, INT32_MAX));
-    // tiles: about 8 per compute unit, each at least a few chunks
     // tiles: by default about 6 per compute unit (3 per resident workgroup slot
     // at two workgroups per CU), measured best on the 100^3 system
     const int64_t target = P->tile_entries > 0
@@ -239,6 +254,39 @@ void upload_chunks(ephbte_plan P, int64_t chunk_entries) {
     dalloc(P->tiles, tl.size() * sizeof(TileRec), &dummy);
     HIPC(hipMemcpy(P->tiles, tl.data(), tl.size() * sizeof(TileRec), hipMemcpyHostToDevice));
     P->n_tiles = static_cast<int64_t>(tl.size());
+    if (P->upper_beg.empty()) return;
+    // single-copy tables over the upper parts of the rows; one workgroup per CU
+    // (1024 threads), about 3 tiles each
+    std::vector<int64_t> row_end(P->row_ptr.begin() + 1, P->row_ptr.end());
+    ChunkTable u = make_chunks_seg(P->upper_beg, row_end, chunk_entries);
+    const int64_t nch = P->E / 2;
+    const int64_t target_u = P->tile_entries > 0 ? P->tile_entries / 2 + 1
+                                                 : nch / (3 * static_cast<int64_t>(P->n_cu)) + 1;
+    std::vector<Tile> tu = make_tiles(u, P->row_ptr, P->pmin_up, P->pmax_up, P->sym_lds_states, target_u);
+    dfree(reinterpret_cast<void *&>(P->sym_chunk_beg));
+    dfree(reinterpret_cast<void *&>(P->sym_chunk_end));
+    dfree(reinterpret_cast<void *&>(P->sym_chunk_dest));
+    dfree(reinterpret_cast<void *&>(P->sym_dest_chunk));
+    dfree(reinterpret_cast<void *&>(P->sym_tiles));
+    dalloc(P->sym_chunk_beg, u.chunk_beg.size() * sizeof(int64_t), &dummy);
+    dalloc(P->sym_chunk_end, std::max<size_t>(u.chunk_end.size(), 1) * sizeof(int64_t), &dummy);
+    dalloc(P->sym_chunk_dest, std::max<size_t>(u.chunk_dest.size(), 1) * sizeof(int32_t), &dummy);
+    dalloc(P->sym_dest_chunk, u.dest_chunk.size() * sizeof(int32_t), &dummy);
+    dalloc(P->sym_tiles, std::max<size_t>(tu.size(), 1) * sizeof(TileRec), &dummy);
+    HIPC(hipMemcpy(P->sym_chunk_beg, u.chunk_beg.data(), u.chunk_beg.size() * sizeof(int64_t),
+                   hipMemcpyHostToDevice));
+    if (!u.chunk_end.empty()) {
+        HIPC(hipMemcpy(P->sym_chunk_end, u.chunk_end.data(), u.chunk_end.size() * sizeof(int64_t),
+                       hipMemcpyHostToDevice));
+        HIPC(hipMemcpy(P->sym_chunk_dest, u.chunk_dest.data(), u.chunk_dest.size() * sizeof(int32_t),
+                       hipMemcpyHostToDevice));
+    }
+    HIPC(hipMemcpy(P->sym_dest_chunk, u.dest_chunk.data(), u.dest_chunk.size() * sizeof(int32_t),
+                   hipMemcpyHostToDevice));
+    if (!tu.empty())
+        HIPC(hipMemcpy(P->sym_tiles, tu.data(), tu.size() * sizeof(TileRec), hipMemcpyHostToDevice));
+    P->n_sym_chunks = u.n_chunks;
+    P->n_sym_tiles = static_cast<int64_t>(tu.size());
 }
 
 template <typename T> Tables<T> tables(ephbte_plan P, const void *nph) {
@@ -292,7 +340,51 @@ template <typename T> TiledArgs<T> tiled_args(ephbte_plan P) {
     a.mc256 = 256.0 * (-1.4426950408889634 / (2.0 * P->sigma * P->sigma));
     a.n_tiles = P->n_tiles;
     a.xcd = P->xcd_map ? 1 : 0;
+    a.chunk_end = nullptr;
+    a.jacc = P->jacc;
+    a.nmax_bits = P->nmax_bits;
+    a.gmax_bits = P->gmax_bits;
     return a;
+}
+
+// arguments of the single-copy pass: its own chunks, tiles and LDS window
+template <typename T> TiledArgs<T> sym_args(ephbte_plan P) {
+    TiledArgs<T> a = tiled_args<T>(P);
+    a.chunk_beg = P->sym_chunk_beg;
+    a.chunk_end = P->sym_chunk_end;
+    a.chunk_dest = P->sym_chunk_dest;
+    a.dest_chunk = P->sym_dest_chunk;
+    a.tiles = P->sym_tiles;
+    a.n_chunks = P->n_sym_chunks;
+    a.n_tiles = P->n_sym_tiles;
+    a.lds_states = P->sym_lds_states;
+    return a;
+}
+
+// LDS of the single-copy pass: fixed-point sums, {eps, f}, packed k per window
+// state, and the FP64 exponential table
+size_t sym_lds_bytes(int dtype, int states) {
+    const size_t es = dtype == EPHBTE_F64 ? 8 : 4;
+    const size_t tab = dtype == EPHBTE_F64 ? kExpTab * sizeof(double) : 0;
+    return static_cast<size_t>(states) * (8 + 2 * es + 4) + tab;
+}
+
+// max over states of the sum of |g|^2 of the state's channels (device scalar)
+void update_gmax(ephbte_plan P, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, P->gmax_bits, 1);
+    if (P->S == 0) return;
+    const unsigned blocks = static_cast<unsigned>((static_cast<int64_t>(P->S) * 64 + 255) / 256);
+    if (P->dtype == EPHBTE_F64)
+        hipLaunchKernelGGL((k_row_gmax<double>), dim3(blocks), dim3(256), 0, s,
+                           static_cast<const double *>(P->g2), P->chunk_beg, P->dest_chunk, P->S, P->gmax_bits);
+    else
+        hipLaunchKernelGGL((k_row_gmax<float>), dim3(blocks), dim3(256), 0, s,
+                           static_cast<const float *>(P->g2), P->chunk_beg, P->dest_chunk, P->S, P->gmax_bits);
+    HIPC(hipGetLastError());
+}
+
+bool use_sym(ephbte_plan P, int B) {
+    return B == 1 && P->layout == 2 && P->sym_ok && P->n_sym_tiles > 0;
 }
 
 int64_t nqm_of(ephbte_plan P) {
@@ -375,21 +467,30 @@ void upload_btiles(ephbte_plan P, int pt) {
     P->n_btiles = static_cast<int64_t>(bt.size());
 }
 
+// workgroups of the {hw, N} pack kernels
+constexpr int64_t kPackBlocks = 8192;
+
 // Interleave the plan's phonon energies with the caller's occupations into
 // one {hw, N} table (one gather per entry instead of two).
 template <typename T> void enqueue_pack(ephbte_plan P, const void *nph, hipStream_t s) {
+    // each pack block also stores the max |N| it saw; one more workgroup reduces
+    // those to the max |N| of this call (the single-copy pass's fixed-point scale)
+    double *bmax = P->pack_bmax;
+    unsigned nb;
     if (P->padq) {
         const int64_t n = P->qpad_n * P->nm;
-        hipLaunchKernelGGL((k_pack_hwN_pad<T>),
-                           dim3(static_cast<unsigned>(std::min<int64_t>((n + 255) / 256, 8192))),
-                           dim3(256), 0, s, static_cast<const T *>(P->hw), static_cast<const T *>(nph),
-                           static_cast<Pair2<T> *>(P->hwN.p), P->nq[0], P->nq[1], P->nq[2], P->nm, n);
-        return;
+        nb = static_cast<unsigned>(std::max<int64_t>(std::min<int64_t>((n + 255) / 256, kPackBlocks), 1));
+        hipLaunchKernelGGL((k_pack_hwN_pad<T>), dim3(nb), dim3(256), 0, s, static_cast<const T *>(P->hw),
+                           static_cast<const T *>(nph), static_cast<Pair2<T> *>(P->hwN.p), P->nq[0],
+                           P->nq[1], P->nq[2], P->nm, n, bmax);
+    } else {
+        const int64_t n = nqm_of(P);
+        nb = static_cast<unsigned>(std::max<int64_t>(std::min<int64_t>((n + 255) / 256, kPackBlocks), 1));
+        hipLaunchKernelGGL((k_pack_hwN<T>), dim3(nb), dim3(256), 0, s, static_cast<const T *>(P->hw),
+                           static_cast<const T *>(nph), static_cast<Pair2<T> *>(P->hwN.p), n, bmax);
     }
-    const int64_t n = nqm_of(P);
-    hipLaunchKernelGGL((k_pack_hwN<T>), dim3(static_cast<unsigned>(std::min<int64_t>((n + 255) / 256, 4096))),
-                       dim3(256), 0, s, static_cast<const T *>(P->hw), static_cast<const T *>(nph),
-                       static_cast<Pair2<T> *>(P->hwN.p), n);
+    hipLaunchKernelGGL(k_max_blocks, dim3(1), dim3(1024), 0, s, (const double *)bmax, static_cast<int>(nb),
+                       P->nmax_bits);
 }
 
 size_t tiled_lds_bytes(ephbte_plan P) {
@@ -407,6 +508,24 @@ void enqueue_forward(ephbte_plan P, int B, const T *f, int64_t ldf, const void *
     if (pack) enqueue_pack<T>(P, nph, s);
     if (B >= P->batch_min && P->n_btiles > 0) {
         enqueue_forward_batched<T>(P, B, f, ldf, E, s);
+        return;
+    }
+    if (use_sym(P, B)) {
+        TiledArgs<T> a = sym_args<T>(P);
+        T *part = static_cast<T *>(P->sym_part.p);
+        // entries per lane and stage: 2 in FP64 keeps the pipeline in the 128
+        // registers a lane has at 1024 threads per workgroup
+        constexpr int U = sizeof(T) == 8 ? 2 : 4;
+        const size_t shm = sym_lds_bytes(P->dtype, P->sym_lds_states);
+        if (P->padq)
+            hipLaunchKernelGGL((k_fwd_sym<T, U, true>), dim3(tile_grid(P, P->n_sym_tiles)), dim3(1024), shm,
+                               s, a, f, part);
+        else
+            hipLaunchKernelGGL((k_fwd_sym<T, U, false>), dim3(tile_grid(P, P->n_sym_tiles)), dim3(1024), shm,
+                               s, a, f, part);
+        hipLaunchKernelGGL((k_sym_finish<T>), dim3((P->S + 255) / 256), dim3(256), 0, s, a, f,
+                           (const T *)part, E);
+        HIPC(hipGetLastError());
         return;
     }
     TiledArgs<T> a = tiled_args<T>(P);
@@ -427,6 +546,9 @@ void enqueue_forward(ephbte_plan P, int B, const T *f, int64_t ldf, const void *
 
 template <typename T> void ensure_fwd(ephbte_plan P, int B) {
     if (!P->fused) ensure(P->part, sizeof(T) * 2 * static_cast<size_t>(P->n_chunks) * B, &P->ws_gen);
+    if (use_sym(P, B))
+        ensure(P->sym_part, sizeof(T) * 2 * static_cast<size_t>(std::max<int64_t>(P->n_sym_chunks, 1)),
+               &P->ws_gen);
     const int64_t tab = P->padq ? P->qpad_n * P->nm : nqm_of(P);
     ensure(P->hwN, sizeof(Pair2<T>) * static_cast<size_t>(std::max<int64_t>(tab, 1)), &P->ws_gen);
 }
@@ -1106,10 +1228,36 @@ ephbte_status ephbte_build_channels(const ephbte_problem *problem, ephbte_plan *
             dalloc(P->e2tab, sizeof(tab), &P->layout_bytes);
             HIPC(hipMemcpy(P->e2tab, tab, sizeof(tab), hipMemcpyHostToDevice));
         }
+        {
+            // single-copy pass: the part p > d of each row (entries are sorted by
+            // partner inside a row, so it is a suffix) and its partner range
+            P->upper_beg.resize(P->S);
+            P->pmin_up.resize(P->S);
+            P->pmax_up.resize(P->S);
+            parallel_ranges(P->S, host_threads(), [&](int, int64_t b, int64_t e) {
+                for (int64_t d = b; d < e; ++d) {
+                    const auto lo = L.pnu.begin() + L.row_ptr[d], hi = L.pnu.begin() + L.row_ptr[d + 1];
+                    const auto u = std::lower_bound(lo, hi, static_cast<uint32_t>(d + 1) << 3);
+                    P->upper_beg[d] = u - L.pnu.begin();
+                    const bool has = u != hi;
+                    P->pmin_up[d] = has ? static_cast<int32_t>(*u >> 3) : 1;
+                    P->pmax_up[d] = has ? L.pmax[d] : 0;
+                }
+            });
+            P->sym_lds_states = P->dtype == EPHBTE_F64 ? 3072 : 4096;
+            P->sym_ok = sym_lds_bytes(P->dtype, P->sym_lds_states) <= P->lds_max;
+            dalloc(P->jacc, sizeof(unsigned long long) * std::max(P->S, 1), &P->layout_bytes);
+            HIPC(hipMemset(P->jacc, 0, sizeof(unsigned long long) * std::max(P->S, 1)));
+            dalloc(P->nmax_bits, sizeof(unsigned long long), &P->layout_bytes);
+            dalloc(P->gmax_bits, sizeof(unsigned long long), &P->layout_bytes);
+            dalloc(P->pack_bmax, sizeof(double) * kPackBlocks, &P->layout_bytes);
+            HIPC(hipMemset(P->nmax_bits, 0, sizeof(unsigned long long)));
+        }
         { HostLayout tmp; std::swap(tmp, L); }
         P->block_threads = 512;
         upload_chunks(P, 65536);
         upload_btiles(P, P->dtype == EPHBTE_F64 ? 96 : 192);
+        update_gmax(P, nullptr);
         HIPC(hipDeviceSynchronize());
     } catch (const HipError &e) {
         free_plan(P);
@@ -1263,6 +1411,7 @@ ephbte_status ephbte_update_g2(ephbte_plan plan, const double *g2, void *stream)
                                (const int32_t *)plan->ent_chan, g2, static_cast<float *>(plan->g2),
                                plan->E);
         HIPC(hipGetLastError());
+        update_gmax(plan, s);
         return EPHBTE_OK;
     });
 }
@@ -1285,10 +1434,16 @@ ephbte_status ephbte_set_tuning(ephbte_plan plan, const ephbte_tuning *tuning) {
             if (r != 0) return fail(EPHBTE_INVALID_ARGUMENT, "reserved tuning fields must be 0");
         if (tuning->tile_entries < -1)
             return fail(EPHBTE_INVALID_ARGUMENT, "tile_entries must be -1 (default), 0 (keep) or > 0");
+        if (tuning->layout < 0 || tuning->layout > 2)
+            return fail(EPHBTE_INVALID_ARGUMENT, "layout must be 0 (keep), 1 or 2");
+        if (tuning->layout == 2 && !plan->sym_ok)
+            return fail(EPHBTE_INVALID_ARGUMENT,
+                        "the single-copy pass needs more LDS per workgroup than this device has");
         HIPC(hipDeviceSynchronize());
         plan->block_threads = bt;
         if (tuning->xcd_map) plan->xcd_map = tuning->xcd_map == 1;
         if (tuning->tile_entries) plan->tile_entries = tuning->tile_entries > 0 ? tuning->tile_entries : 0;
+        if (tuning->layout) plan->layout = tuning->layout;
         upload_chunks(plan, ce);
         if (pt != 0) upload_btiles(plan, pt);
         free_graphs(plan);

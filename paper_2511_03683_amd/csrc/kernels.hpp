@@ -307,21 +307,92 @@ template <typename T> struct TiledArgs {
     double mc256;                       // 256 mc, the table exponential's scale
     int64_t n_tiles;
     int xcd;                            // tile ranges per XCD (tile_of_block)
+    // single-copy pass only
+    const int64_t *__restrict__ chunk_end;           // chunk c is [chunk_beg[c], chunk_end[c])
+    unsigned long long *__restrict__ jacc;           // [S] partner-side sums, fixed point
+    const unsigned long long *__restrict__ nmax_bits;  // max |N| of the packed table (double bits)
+    const unsigned long long *__restrict__ gmax_bits;  // max over states of sum |g|^2 (double bits)
 };
+
+// ---- fixed point for the partner side of the single-copy pass -------------
+// Contributions to I_p (p > d) arrive from many rows; they are rounded to
+// integers on a common scale 2^s and summed with integer atomics, which are
+// associative, so the sums do not depend on the order of arrival.  With
+// |N| <= N_max, f in [0, 1] and the Gaussians <= 1, one entry's share is at
+// most |g|^2 (2 N_max + 1), a state's column at most (2 N_max + 1) G_max with
+// G_max the largest sum of |g|^2 over one state's channels; s puts that bound
+// below 2^61.
+__device__ __forceinline__ double sym_scale(const unsigned long long *nmax_bits,
+                                            const unsigned long long *gmax_bits) {
+    const double nmax = __longlong_as_double(static_cast<long long>(*nmax_bits));
+    const double gmax = __longlong_as_double(static_cast<long long>(*gmax_bits));
+    const double bound = (2.0 * nmax + 1.0) * gmax;
+    if (!(bound > 0.0) || !(bound < 1e300)) return 1.0;
+    int e;
+    (void)frexp(bound, &e);   // bound < 2^e
+    return ldexp(1.0, 61 - e);
+}
+
+// y integral-valued with |y| < 2^62, as a two's-complement 64-bit integer
+template <typename T> __device__ __forceinline__ unsigned long long to_fixed(T y) {
+    const T hi = floor(y * T(2.3283064365386963e-10));   // y / 2^32, rounded down
+    const T lo = fma(hi, T(-4294967296.0), y);           // y - hi 2^32, exact, in [0, 2^32)
+    const uint32_t l = static_cast<uint32_t>(lo);
+    const uint32_t h = static_cast<uint32_t>(static_cast<int32_t>(hi));
+    return (static_cast<unsigned long long>(h) << 32) | l;
+}
+
+// max of v over the workgroup (blockDim.x <= 1024), stored by thread 0 to *dst
+__device__ __forceinline__ void block_max_to(double v, double *dst) {
+    __shared__ double s_m[16];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    if ((threadIdx.x & 63) == 0) s_m[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = s_m[0];
+        for (int w = 1; w < static_cast<int>(blockDim.x >> 6); ++w) m = fmax(m, s_m[w]);
+        *dst = m;
+    }
+}
+
+// one workgroup: the max of n per-block values, as double bits
+__global__ void k_max_blocks(const double *__restrict__ bm, int n, unsigned long long *out_bits) {
+    double m = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, bm[i]);
+    __shared__ double s_m[16];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+    if ((threadIdx.x & 63) == 0) s_m[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < static_cast<int>(blockDim.x >> 6); ++w) m = fmax(m, s_m[w]);
+        m = fmax(m, s_m[0]);
+        *out_bits = static_cast<unsigned long long>(__double_as_longlong(m));
+    }
+}
+
+__global__ void k_zero_u64(unsigned long long *p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
 
 // entries of the exponential table that the FP64 streaming kernels keep in LDS
 constexpr int kExpTab = 256;
 
 template <typename T>
 __global__ void k_pack_hwN(const T *__restrict__ hw, const T *__restrict__ nph,
-                           Pair2<T> *__restrict__ out, int64_t n) {
+                           Pair2<T> *__restrict__ out, int64_t n, double *bmax) {
+    double m = 0.0;
     for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
          i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         Pair2<T> v;
         v.a = hw[i];
         v.b = nph[i];
         out[i] = v;
+        m = fmax(m, fabs(static_cast<double>(v.b)));
     }
+    block_max_to(m, bmax + blockIdx.x);
 }
 
 // Padded table: entry (qp, nu) holds {hw, N} of q = (c - Nq) mod Nq per axis,
@@ -331,7 +402,8 @@ __global__ void k_pack_hwN(const T *__restrict__ hw, const T *__restrict__ nph,
 template <typename T>
 __global__ void k_pack_hwN_pad(const T *__restrict__ hw, const T *__restrict__ nph,
                                Pair2<T> *__restrict__ out, int n0, int n1, int n2, int nm,
-                               int64_t n) {
+                               int64_t n, double *bmax) {
+    double m = 0.0;
     for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
          i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         const int nu = static_cast<int>(i % nm);
@@ -349,7 +421,9 @@ __global__ void k_pack_hwN_pad(const T *__restrict__ hw, const T *__restrict__ n
         v.a = hw[q * nm + nu];
         v.b = nph[q * nm + nu];
         out[i] = v;
+        m = fmax(m, fabs(static_cast<double>(v.b)));
     }
+    block_max_to(m, bmax + blockIdx.x);
 }
 
 // exp of the Gaussian exponent x2 * (-1/(2 s^2)) for the streaming kernels
@@ -511,6 +585,210 @@ __global__ __launch_bounds__(MAXT) void k_fwd_tiled(TiledArgs<T> A, const T *__r
         else
             fwd_chunk2<T, false, PADQ, U>(A, fb, s_ef, s_kq, t.p_lo, s_tab, c, b, part, E);
     }
+}
+
+// ---- forward, single copy ---------------------------------------------------
+// Each channel is evaluated once, from the row of its smaller state d (the
+// entries p > d of that row, the upper part of the destination-sorted layout).
+// With Y = (1 - f_d) b f_p - f_d a (1 - f_p) (a, b as in the duplicated pass),
+// I_d receives K Y and I_p receives -K Y: the row side is reduced in registers
+// as in fwd_chunk2, the partner side is added to a fixed-point accumulator per
+// partner (LDS for an LDS tile, then flushed to the global one).
+
+// max over states of the sum of |g|^2 over the state's entries, one wave per state
+template <typename T>
+__global__ void k_row_gmax(const T *__restrict__ g2, const int64_t *__restrict__ chunk_beg,
+                           const int32_t *__restrict__ dest_chunk, int S,
+                           unsigned long long *gmax_bits) {
+    const int d = static_cast<int>((blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) >> 6);
+    const int lane = threadIdx.x & 63;
+    double sum = 0.0;
+    if (d < S) {
+        const int64_t b = chunk_beg[dest_chunk[d]], e = chunk_beg[dest_chunk[d + 1]];
+        for (int64_t x = b + lane; x < e; x += 64) sum += fabs(static_cast<double>(g2[x]));
+    }
+    sum = wave_sum(sum);
+    if (lane == 0 && d < S)
+        atomicMax(gmax_bits, static_cast<unsigned long long>(__double_as_longlong(sum)));
+}
+
+template <typename T, bool LDS, bool PADQ, int U>
+__device__ __forceinline__ void sym_chunk(const TiledArgs<T> &A, const T *__restrict__ fb,
+                                          const Pair2<T> *s_ef, const uint32_t *s_kq, int p_lo,
+                                          const double *s_tab, unsigned long long *s_j, T scale,
+                                          int64_t c, T *__restrict__ part) {
+    const int lane = threadIdx.x & 63;
+    const int d = A.chunk_dest[c];
+    const int64_t beg = A.chunk_beg[c];
+    const int len = static_cast<int>(A.chunk_end[c] - beg);
+    const uint32_t *__restrict__ pb = A.pnu + beg;
+    const T *__restrict__ gb = A.g2 + beg;
+    const StateRec<T> sd = A.st[d];
+    const uint32_t kd = PADQ ? sd.kqp : sd.kq;
+    const T fd = fb[d];
+    const T cfd = T(1) - fd;
+    T acc_a = T(0), acc_b = T(0);
+    uint32_t pn1[U];
+    T gs1[U];
+    T g0[U], de0[U], fp0[U];
+    int pl0[U];
+    Pair2<T> wn0[U];
+    auto load_stream = [&](int r0, uint32_t (&pn)[U], T (&gs)[U]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            pn[u] = pb[r0 + u * 64 + lane];
+            gs[u] = gb[r0 + u * 64 + lane];
+        }
+    };
+    auto gather = [&](auto masked, const uint32_t (&pn)[U], const T (&gs)[U], int r0, T (&go)[U],
+                      T (&deo)[U], T (&fpo)[U], Pair2<T> (&wno)[U], int (&plo)[U]) {
+        constexpr bool M = decltype(masked)::value;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool v = !M || r0 + u * 64 + lane < len;
+            const int p = static_cast<int>(pn[u] >> 3);
+            T ep, fp;
+            uint32_t kp;
+            if (LDS) {
+                const int pl = v ? p - p_lo : 0;
+                const Pair2<T> ef = s_ef[pl];
+                ep = ef.a;
+                fp = ef.b;
+                kp = s_kq[pl];
+                plo[u] = pl;
+            } else {
+                const StateRec<T> sp = A.st[p];
+                ep = sp.eps;
+                kp = PADQ ? sp.kqp : sp.kq;
+                fp = fb[p];
+                plo[u] = p;
+            }
+            const int q = PADQ ? static_cast<int>(kp - kd) + A.qoff
+                               : q_linear(kd, kp, A.nq0, A.nq1, A.nq2);
+            const Pair2<T> w = A.hwN[static_cast<int64_t>(q) * A.nm + (pn[u] & 7u)];
+            if constexpr (M) {
+                // a table entry without channels may hold a non-finite N; the
+                // masked lanes then add zero to partner slot 0 (or state p)
+                wno[u].a = v ? w.a : T(0);
+                wno[u].b = v ? w.b : T(0);
+                go[u] = v ? gs[u] : T(0);
+            } else {
+                wno[u] = w;
+                go[u] = gs[u];
+            }
+            deo[u] = sd.eps - ep;
+            fpo[u] = fp;
+        }
+    };
+    using Masked = std::integral_constant<bool, true>;
+    using Full = std::integral_constant<bool, false>;
+    {
+        uint32_t pn0[U];
+        T gs0[U];
+        load_stream(0, pn0, gs0);
+        load_stream(64 * U, pn1, gs1);
+        if (64 * U <= len) gather(Full{}, pn0, gs0, 0, g0, de0, fp0, wn0, pl0);
+        else gather(Masked{}, pn0, gs0, 0, g0, de0, fp0, wn0, pl0);
+    }
+    for (int r = 0; r < len; r += 64 * U) {
+        T g1[U], de1[U], fp1[U];
+        int pl1[U];
+        Pair2<T> wn1[U];
+        if (r + 128 * U <= len) gather(Full{}, pn1, gs1, r + 64 * U, g1, de1, fp1, wn1, pl1);
+        else gather(Masked{}, pn1, gs1, r + 64 * U, g1, de1, fp1, wn1, pl1);
+        load_stream(r + 128 * U, pn1, gs1);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const T xa = de0[u] + wn0[u].a, xe = de0[u] - wn0[u].a;
+            const T da = stream_gauss(A, xa * xa, s_tab);
+            const T dem = stream_gauss(A, xe * xe, s_tab);
+            const T t = wn0[u].b * (da + dem);
+            const T ta = g0[u] * (t + dem) * (T(1) - fp0[u]);
+            const T tb = g0[u] * (t + da) * fp0[u];
+            acc_a += ta;
+            acc_b += tb;
+            // partner side: -Y = f_d ta - (1 - f_d) tb, on the fixed-point scale
+            const unsigned long long v = to_fixed(__builtin_rint(fma(fd, ta, -cfd * tb) * scale));
+            if (LDS) atomicAdd(s_j + pl0[u], v);
+            else atomicAdd(A.jacc + pl0[u], v);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            g0[u] = g1[u];
+            de0[u] = de1[u];
+            fp0[u] = fp1[u];
+            wn0[u] = wn1[u];
+            pl0[u] = pl1[u];
+        }
+    }
+    acc_a = wave_sum(acc_a);
+    acc_b = wave_sum(acc_b);
+    if (lane == 0) {
+        part[2 * c] = acc_a;
+        part[2 * c + 1] = acc_b;
+    }
+}
+
+template <typename T, int U, bool PADQ>
+__global__ __launch_bounds__(1024) void k_fwd_sym(TiledArgs<T> A, const T *__restrict__ f,
+                                                  T *__restrict__ part) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int64_t ti = tile_of_block(A.n_tiles, A.xcd);
+    if (ti < 0) return;
+    const TileRec t = A.tiles[ti];
+    // LDS: partner-side sums (8 B), {eps, f}, packed k, exponential table
+    unsigned long long *s_j = reinterpret_cast<unsigned long long *>(smem);
+    Pair2<T> *s_ef = reinterpret_cast<Pair2<T> *>(s_j + A.lds_states);
+    uint32_t *s_kq = reinterpret_cast<uint32_t *>(s_ef + A.lds_states);
+    double *s_tab = reinterpret_cast<double *>(s_kq + A.lds_states);
+    const int n = t.lds ? t.p_hi - t.p_lo + 1 : 0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const StateRec<T> sr = A.st[t.p_lo + i];
+        Pair2<T> ef;
+        ef.a = sr.eps;
+        ef.b = f[t.p_lo + i];
+        s_ef[i] = ef;
+        s_kq[i] = PADQ ? sr.kqp : sr.kq;
+        s_j[i] = 0ull;
+    }
+    if constexpr (sizeof(T) == 8)
+        for (int i = threadIdx.x; i < kExpTab; i += blockDim.x) s_tab[i] = A.e2tab[i];
+    const T scale = static_cast<T>(sym_scale(A.nmax_bits, A.gmax_bits));
+    __syncthreads();
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    const int nw = static_cast<int>(blockDim.x >> 6);
+    for (int64_t c = t.c0 + wave; c < t.c1; c += nw) {
+        if (t.lds)
+            sym_chunk<T, true, PADQ, U>(A, f, s_ef, s_kq, t.p_lo, s_tab, s_j, scale, c, part);
+        else
+            sym_chunk<T, false, PADQ, U>(A, f, s_ef, s_kq, t.p_lo, s_tab, s_j, scale, c, part);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const unsigned long long v = s_j[i];
+        if (v) atomicAdd(A.jacc + t.p_lo + i, v);
+    }
+}
+
+// I_d = K [(1 - f_d) sum b - f_d sum a] from the row side (chunk partials in
+// chunk order) plus the partner side, then the epilogue; the partner-side
+// accumulator of d is cleared for the next call.
+template <typename T>
+__global__ void k_sym_finish(TiledArgs<T> A, const T *__restrict__ f, const T *__restrict__ part,
+                             Epi<T> E) {
+    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= A.S) return;
+    T a = T(0), b = T(0);
+    for (int c = A.dest_chunk[d]; c < A.dest_chunk[d + 1]; ++c) {
+        a += part[2 * c];
+        b += part[2 * c + 1];
+    }
+    const double inv = 1.0 / sym_scale(A.nmax_bits, A.gmax_bits);
+    const long long j = static_cast<long long>(A.jacc[d]);
+    A.jacc[d] = 0ull;
+    const T fd = f[d];
+    const T jside = static_cast<T>(static_cast<double>(j) * inv);
+    apply_epi(E, 0, d, A.S, A.K * ((T(1) - fd) * b - fd * a + jside));
 }
 
 // destinations with several chunks: sum their partials in chunk order

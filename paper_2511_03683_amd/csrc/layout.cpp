@@ -259,26 +259,34 @@ ephbte_status build_host_layout(const ephbte_problem *p, HostLayout *out, std::s
     return EPHBTE_OK;
 }
 
-ChunkTable make_chunks(const std::vector<int64_t> &row_ptr, int64_t chunk_entries) {
+ChunkTable make_chunks_seg(const std::vector<int64_t> &seg_beg, const std::vector<int64_t> &seg_end,
+                           int64_t chunk_entries) {
     ChunkTable t;
-    const int32_t S = static_cast<int32_t>(row_ptr.size()) - 1;
+    const int32_t S = static_cast<int32_t>(seg_beg.size());
     if (chunk_entries < 1) chunk_entries = INT64_MAX;
     t.dest_chunk.resize(S + 1);
     t.chunk_beg.reserve(S + 1);
+    t.chunk_end.reserve(S);
     for (int32_t d = 0; d < S; ++d) {
         t.dest_chunk[d] = static_cast<int32_t>(t.chunk_dest.size());
-        int64_t lo = row_ptr[d], hi = row_ptr[d + 1], len = hi - lo;
-        int64_t nc = len <= chunk_entries ? 1 : (len + chunk_entries - 1) / chunk_entries;
+        const int64_t lo = seg_beg[d], len = seg_end[d] - seg_beg[d];
+        const int64_t nc = len <= chunk_entries ? 1 : (len + chunk_entries - 1) / chunk_entries;
         for (int64_t c = 0; c < nc; ++c) {
             t.chunk_beg.push_back(lo + len * c / nc);
+            t.chunk_end.push_back(lo + len * (c + 1) / nc);
             t.chunk_dest.push_back(d);
         }
         if (nc > 1) t.one_per_dest = false;
     }
     t.dest_chunk[S] = static_cast<int32_t>(t.chunk_dest.size());
-    t.chunk_beg.push_back(row_ptr[S]);
+    t.chunk_beg.push_back(S > 0 ? seg_end[S - 1] : 0);
     t.n_chunks = static_cast<int64_t>(t.chunk_dest.size());
     return t;
+}
+
+ChunkTable make_chunks(const std::vector<int64_t> &row_ptr, int64_t chunk_entries) {
+    const std::vector<int64_t> beg(row_ptr.begin(), row_ptr.end() - 1), end(row_ptr.begin() + 1, row_ptr.end());
+    return make_chunks_seg(beg, end, chunk_entries);
 }
 
 std::vector<Tile> make_tiles(const ChunkTable &ct, const std::vector<int64_t> &row_ptr,
@@ -296,7 +304,7 @@ std::vector<Tile> make_tiles(const ChunkTable &ct, const std::vector<int64_t> &r
         int kind = -1;   // 1 LDS, 0 global
         while (c < n) {
             const int32_t d = ct.chunk_dest[c];
-            const int64_t ce = ct.chunk_beg[c + 1] - ct.chunk_beg[c];
+            const int64_t ce = ct.chunk_end[c] - ct.chunk_beg[c];
             const bool has = pmax[d] >= pmin[d];
             const int32_t nlo = has ? std::min(lo, pmin[d]) : lo;
             const int32_t nhi = has ? std::max(hi, pmax[d]) : hi;

@@ -38,13 +38,19 @@ ephbte_status build_host_layout(const ephbte_problem *p, HostLayout *out, std::s
 // chunk_entries entries (each destination gets at least one chunk, possibly
 // empty).  chunk_beg has n_chunks+1 boundaries; dest_chunk has S+1.
 struct ChunkTable {
-    std::vector<int64_t> chunk_beg;
+    std::vector<int64_t> chunk_beg;   // n_chunks + 1 (the last is the end of the last segment)
+    std::vector<int64_t> chunk_end;   // n_chunks
     std::vector<int32_t> chunk_dest;
     std::vector<int32_t> dest_chunk;
     int64_t n_chunks = 0;
     bool one_per_dest = true;
 };
 ChunkTable make_chunks(const std::vector<int64_t> &row_ptr, int64_t chunk_entries);
+
+// The same split over per-destination segments [seg_beg[d], seg_end[d]) that
+// need not be contiguous with each other (the upper part p > d of each row).
+ChunkTable make_chunks_seg(const std::vector<int64_t> &seg_beg, const std::vector<int64_t> &seg_end,
+                           int64_t chunk_entries);
 
 // Workgroup tiles: runs of consecutive chunks [c0, c1).  When the partners of
 // all their destinations lie in [p_lo, p_hi] with at most lds_states states,
