@@ -24,7 +24,11 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_CHANNEL = {"f64": 24.0, "f32": 16.0}        # 2 entries x (|g|^2 + packed partner/mode)
+# Algorithmic bytes per unordered channel.  The single-copy pass (the default
+# for B = 1) streams one entry per channel: |g|^2 + packed partner/mode word;
+# the per-row pass streams both entries of each channel.
+BYTES_PER_CHANNEL = {"f64": 12.0, "f32": 8.0}
+BYTES_PER_CHANNEL_ROWS = {"f64": 24.0, "f32": 16.0}
 # reverse pass: the same entry stream, the channel index of the entry that
 # writes dL/d|g|^2 (4 B) and that FP64 value (8 B), per unordered channel
 VJP_BYTES_PER_CHANNEL = {"f64": 24.0 + 4.0 + 8.0, "f32": 16.0 + 4.0 + 8.0}
@@ -186,7 +190,16 @@ def main():
 
     forms = {}
     if not args.no_forms:
-        forms["fwd_f64_b1"] = dict(ms=ms, channels_per_s=value, algorithmic_GBps=achieved)
+        forms["fwd_f64_b1"] = dict(ms=ms, channels_per_s=value, algorithmic_GBps=achieved,
+                                   layout="single copy")
+        # the per-row pass (each channel evaluated in both of its rows)
+        E.set_tuning(plan64, layout=1)
+        msr, _ = timed(fwd64, args.steps, args.warmup)
+        E.set_tuning(plan64, layout=2)
+        forms["fwd_f64_b1_rows"] = dict(ms=msr, channels_per_s=nch / (msr * 1e-3),
+                                        algorithmic_GBps=BYTES_PER_CHANNEL_ROWS["f64"] * nch / (msr * 1e-3) / 1e9,
+                                        layout="duplicated rows")
+        log(f"fwd fp64 per-row pass: {msr:.3f} ms")
         # reverse mode (dL/df and dL/dg2), FP64
         lam = tens(rng.normal(size=s.n_states), torch.float64)
         gg = torch.zeros(nch, dtype=torch.float64, device=dev)
@@ -261,8 +274,16 @@ def main():
         I32 = torch.empty_like(f32)
         ms32, _ = timed(lambda: E.collision_integral(plan32, f32, n32, out=I32), args.steps, args.warmup)
         forms["fwd_f32_b1"] = dict(ms=ms32, channels_per_s=nch / (ms32 * 1e-3),
-                                   algorithmic_GBps=BYTES_PER_CHANNEL["f32"] * nch / (ms32 * 1e-3) / 1e9)
+                                   algorithmic_GBps=BYTES_PER_CHANNEL["f32"] * nch / (ms32 * 1e-3) / 1e9,
+                                   layout="single copy")
         log(f"fwd fp32: {ms32:.3f} ms")
+        E.set_tuning(plan32, layout=1)
+        ms32r, _ = timed(lambda: E.collision_integral(plan32, f32, n32, out=I32), args.steps, args.warmup)
+        E.set_tuning(plan32, layout=2)
+        forms["fwd_f32_b1_rows"] = dict(ms=ms32r, channels_per_s=nch / (ms32r * 1e-3),
+                                        algorithmic_GBps=BYTES_PER_CHANNEL_ROWS["f32"] * nch / (ms32r * 1e-3) / 1e9,
+                                        layout="duplicated rows")
+        log(f"fwd fp32 per-row pass: {ms32r:.3f} ms")
         tuned32 = E.autotune(plan32, 64)
         F32 = tens(synth.batch_occupations(s), torch.float32)
         IB32 = torch.empty_like(F32)
@@ -358,7 +379,9 @@ def main():
         "frac_of_copy": achieved / copy_gbps,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": profiled_traffic(f"k_fwd_tiled_{args.dtype}_{wname}")},
+                     "traffic": profiled_traffic(f"k_fwd_sym_{args.dtype}_{wname}"),
+                     "kernel": "k_fwd_sym (single-copy forward pass)",
+                     "bytes_per_channel": BYTES_PER_CHANNEL[args.dtype]},
         "cpu_baseline": cpu,
         "forms": forms,
     }

@@ -256,12 +256,13 @@ void upload_chunks(ephbte_plan P, int64_t chunk_entries) {
     P->n_tiles = static_cast<int64_t>(tl.size());
     if (P->upper_beg.empty()) return;
     // single-copy tables over the upper parts of the rows; one workgroup per CU
-    // (1024 threads), about 3 tiles each
+    // (1024 threads), about 4 tiles each (measured; smaller tiles pay more
+    // window staging and partner-side flushes)
     std::vector<int64_t> row_end(P->row_ptr.begin() + 1, P->row_ptr.end());
     ChunkTable u = make_chunks_seg(P->upper_beg, row_end, chunk_entries);
     const int64_t nch = P->E / 2;
     const int64_t target_u = P->tile_entries > 0 ? P->tile_entries / 2 + 1
-                                                 : nch / (3 * static_cast<int64_t>(P->n_cu)) + 1;
+                                                 : nch / (4 * static_cast<int64_t>(P->n_cu)) + 1;
     std::vector<Tile> tu = make_tiles(u, P->row_ptr, P->pmin_up, P->pmax_up, P->sym_lds_states, target_u);
     dfree(reinterpret_cast<void *&>(P->sym_chunk_beg));
     dfree(reinterpret_cast<void *&>(P->sym_chunk_end));
@@ -358,6 +359,7 @@ template <typename T> TiledArgs<T> sym_args(ephbte_plan P) {
     a.n_chunks = P->n_sym_chunks;
     a.n_tiles = P->n_sym_tiles;
     a.lds_states = P->sym_lds_states;
+    a.xcd = 0;   // measured: plain tile order is faster for this pass
     return a;
 }
 
@@ -518,10 +520,10 @@ void enqueue_forward(ephbte_plan P, int B, const T *f, int64_t ldf, const void *
         constexpr int U = sizeof(T) == 8 ? 2 : 4;
         const size_t shm = sym_lds_bytes(P->dtype, P->sym_lds_states);
         if (P->padq)
-            hipLaunchKernelGGL((k_fwd_sym<T, U, true>), dim3(tile_grid(P, P->n_sym_tiles)), dim3(1024), shm,
+            hipLaunchKernelGGL((k_fwd_sym<T, U, true>), dim3(static_cast<unsigned>(P->n_sym_tiles)), dim3(1024), shm,
                                s, a, f, part);
         else
-            hipLaunchKernelGGL((k_fwd_sym<T, U, false>), dim3(tile_grid(P, P->n_sym_tiles)), dim3(1024), shm,
+            hipLaunchKernelGGL((k_fwd_sym<T, U, false>), dim3(static_cast<unsigned>(P->n_sym_tiles)), dim3(1024), shm,
                                s, a, f, part);
         hipLaunchKernelGGL((k_sym_finish<T>), dim3((P->S + 255) / 256), dim3(256), 0, s, a, f,
                            (const T *)part, E);
