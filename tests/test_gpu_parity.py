@@ -327,6 +327,7 @@ def test_empty_and_isolated(E):
 # ------------------------------------------------------------------ reverse mode
 @pytest.mark.parametrize("name", ["multiband", "random_order", "parabolic8_random"])
 def test_vjp_matches_oracle(E, name):
+    """Reverse pass: overwrite and accumulate of dL/d|g|^2, batched vectors."""
     mk, occ = SYSTEMS[name]
     s = mk()
     f = np.clip(occ(s), 0, 1)
@@ -338,6 +339,9 @@ def test_vjp_matches_oracle(E, name):
     rf, rg = oracle.collision_vjp(s, f, nph, lam)
     assert nerr(host(gf), rf) <= TOL64
     assert nerr(host(gg), rg) <= TOL64
+    # bitwise reproducible
+    gf2, gg2 = E.collision_vjp(plan, dev(f), dev(nph), dev(lam), want_f=True, gg2=True)
+    assert np.array_equal(host(gf2), host(gf)) and np.array_equal(host(gg2), host(gg))
     # accumulate adds onto the existing buffer
     E.collision_vjp(plan, dev(f), dev(nph), dev(lam), want_f=False, gg2=gg, accumulate=True)
     assert nerr(host(gg), 2 * rg) <= TOL64
