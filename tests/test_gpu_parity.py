@@ -157,6 +157,49 @@ def test_single_copy_and_duplicated_layouts(E, name, dtype):
     plan.close()
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_single_copy_scale_adapts(E, dtype):
+    """The single-copy pass's fixed-point scale follows the inputs: |g|^2 scaled
+    by 1e6 and 1e-6, phonon occupations of a 3000 K bath, and |g|^2 replaced
+    through update_g2 (its per-state bound is recomputed) all match the oracle."""
+    s0 = synth.multiband_system()
+    f = synth.random_occupations(s0, 31)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    for scale, T in ((1e6, 300.0), (1e-6, 300.0), (1.0, 3000.0)):
+        import copy
+        s = copy.copy(s0)
+        s.g2 = s0.g2 * scale
+        nph = s.nph(T)
+        ff, nn, r = f, nph, s
+        if dtype == "f32":
+            ff = f.astype(np.float32).astype(np.float64)
+            nn = nph.astype(np.float32).astype(np.float64)
+            r = round32(s)
+        ref = oracle.collision(r, ff, nn)
+        plan = E.build_channels(s, dtype=dtype, device=0)
+        say(f"single-copy scale {dtype} g2 x {scale:g}, {T} K")
+        got = host(E.collision_integral(plan, dev(ff, tdt), dev(nn, tdt)))
+        if dtype == "f64":
+            assert nerr(got, ref) <= TOL64, (scale, T)
+        else:
+            rin, rout = oracle.collision_inout(r, ff, nn)
+            assert nerr(got, ref, max(np.abs(ref).max(), 1e-2 * max(rin.max(), rout.max()))) <= TOL32
+        if scale == 1.0:
+            # |g|^2 x 1e3 through update_g2
+            s2 = copy.copy(s)
+            s2.g2 = s.g2 * 1e3
+            E.update_g2(plan, dev(s2.g2))
+            r2 = s2 if dtype == "f64" else round32(s2)
+            ref2 = oracle.collision(r2, ff, nn)
+            got2 = host(E.collision_integral(plan, dev(ff, tdt), dev(nn, tdt)))
+            if dtype == "f64":
+                assert nerr(got2, ref2) <= TOL64
+            else:
+                rin, rout = oracle.collision_inout(r2, ff, nn)
+                assert nerr(got2, ref2, max(np.abs(ref2).max(), 1e-2 * max(rin.max(), rout.max()))) <= TOL32
+        plan.close()
+
+
 def test_deterministic_and_batched_columns(E):
     s = synth.multiband_system()
     nph = dev(s.nph(300.0))
