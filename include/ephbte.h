@@ -141,29 +141,38 @@ ephbte_status ephbte_layout_host(const ephbte_problem *problem, int64_t *row_ptr
 
 /*
  * I[f] for B occupation vectors (Eq. 2; paper: Optimized GPU algorithm, steps
- * 2 and 3 fused: every workgroup computes the contributions of the entries of
- * one destination and reduces them, with no atomics).
+ * 2 and 3 fused into one pass over the channel list).
  * f:   device [B][ldf], plan dtype, 0 <= f <= 1 expected (not checked).
- * nph: device [Nq][n_modes], plan dtype: phonon occupations N.
+ * nph: device, plan dtype, phonon occupations N.  nph_per_batch == 0: one
+ *      table [Nq][n_modes] shared by every vector (one (alpha, beta) per
+ *      entry serves the whole batch).  nph_per_batch != 0: B tables
+ *      [B][Nq][n_modes], vector b with its own bath; the vectors are then
+ *      evaluated one after another, each a single-vector pass.
  * I:   device [B][ldi], plan dtype, written.  I must not alias f.
  * B >= 1; ldf, ldi >= S.
+ * Reductions: with B = 1 and the single-copy layout every channel is read
+ * once; the row side is summed in registers in a fixed order and the partner
+ * side in 64-bit fixed point with integer atomics (associative, so the result
+ * is bitwise reproducible).  Other forms reduce each destination's entries
+ * with no atomics.
  */
 ephbte_status ephbte_collision_integral(ephbte_plan plan, int32_t batch, const void *f,
-                                        int64_t ldf, const void *nph, void *I, int64_t ldi,
-                                        void *stream);
+                                        int64_t ldf, const void *nph, int32_t nph_per_batch,
+                                        void *I, int64_t ldi, void *stream);
 
 /*
  * Reverse mode of Eq. 2: given gI = dL/dI (device [B][ldg]), writes
  * gf = dL/df (device [B][ldgf], plan dtype; NULL to skip) and
  * gg2 = dL/d|g|^2 summed over the batch (device FP64 [n_channels] in the
  * caller's channel order; NULL to skip).  accumulate_gg2 != 0 adds to gg2
- * instead of overwriting it.  No atomics: dL/df is a per-destination
+ * instead of overwriting it.  nph and nph_per_batch as for
+ * ephbte_collision_integral.  No atomics: dL/df is a per-destination
  * reduction, each dL/d|g|^2 is written by the channel's first entry.
  */
 ephbte_status ephbte_collision_vjp(ephbte_plan plan, int32_t batch, const void *f,
-                                   int64_t ldf, const void *nph, const void *gI, int64_t ldg,
-                                   void *gf, int64_t ldgf, double *gg2, int32_t accumulate_gg2,
-                                   void *stream);
+                                   int64_t ldf, const void *nph, int32_t nph_per_batch,
+                                   const void *gI, int64_t ldg, void *gf, int64_t ldgf,
+                                   double *gg2, int32_t accumulate_gg2, void *stream);
 
 /*
  * Real-time BTE without field, df/dt = I[f] (Eq. 1 with F = 0): advances f

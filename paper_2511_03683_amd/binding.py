@@ -51,10 +51,11 @@ _LIB = None
 SYMBOLS = {
     "ephbte_build_channels": ([ctypes.POINTER(Problem), ctypes.POINTER(_P)], ctypes.c_int32),
     "ephbte_layout_host": ([ctypes.POINTER(Problem), _P, _P, _P, _P], ctypes.c_int32),
-    "ephbte_collision_integral": ([_P, ctypes.c_int32, _P, ctypes.c_int64, _P, _P,
-                                   ctypes.c_int64, _P], ctypes.c_int32),
-    "ephbte_collision_vjp": ([_P, ctypes.c_int32, _P, ctypes.c_int64, _P, _P, ctypes.c_int64,
-                              _P, ctypes.c_int64, _P, ctypes.c_int32, _P], ctypes.c_int32),
+    "ephbte_collision_integral": ([_P, ctypes.c_int32, _P, ctypes.c_int64, _P, ctypes.c_int32,
+                                   _P, ctypes.c_int64, _P], ctypes.c_int32),
+    "ephbte_collision_vjp": ([_P, ctypes.c_int32, _P, ctypes.c_int64, _P, ctypes.c_int32, _P,
+                              ctypes.c_int64, _P, ctypes.c_int64, _P, ctypes.c_int32, _P],
+                             ctypes.c_int32),
     "ephbte_rt_step": ([_P, ctypes.c_int32, _P, ctypes.c_int64, _P, ctypes.c_double,
                         ctypes.c_int32, ctypes.c_int32, _P], ctypes.c_int32),
     "ephbte_rt_adjoint": ([_P, _P, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, _P, _P,
@@ -248,13 +249,28 @@ def layout_host(system):
     return row_ptr, partner, mode, chan
 
 
+def _nph_arg(plan: Plan, nph, B: int, f):
+    """1 when nph holds one table per vector ([B, Nq, n_modes]), 0 when one
+    [Nq, n_modes] table serves the whole batch."""
+    _dev_tensor(plan, nph, "nph")
+    if not nph.is_contiguous():
+        raise ValueError("nph must be contiguous")
+    tab = plan.n_q * plan.n_modes
+    if nph.dim() == 3 and f.dim() == 2:
+        if nph.shape[0] != B or nph.numel() != B * tab:
+            raise ValueError("a per-vector nph must be [B, Nq, n_modes]")
+        return 1
+    if nph.numel() != tab:
+        raise ValueError("nph must be a [Nq, n_modes] tensor (or [B, Nq, n_modes] with f [B, S])")
+    return 0
+
+
 def collision_integral(plan: Plan, f, nph, out=None):
-    """I[f] for f [S] or [B, S]; nph [Nq, n_modes] (device tensors)."""
+    """I[f] for f [S] or [B, S]; nph [Nq, n_modes], or [B, Nq, n_modes] for a
+    bath per vector (device tensors)."""
     import torch
     B, ldf = _batch(plan, f, "f")
-    _dev_tensor(plan, nph, "nph")
-    if nph.numel() != plan.n_q * plan.n_modes or not nph.is_contiguous():
-        raise ValueError("nph must be a contiguous [Nq, n_modes] tensor")
+    per_batch = _nph_arg(plan, nph, B, f)
     if out is None:
         out = torch.empty((B, plan.n_states) if f.dim() == 2 else (plan.n_states,),
                           dtype=plan.torch_dtype, device=f.device)
@@ -262,8 +278,8 @@ def collision_integral(plan: Plan, f, nph, out=None):
     if Bo != B:
         raise ValueError("out batch differs from f batch")
     _check(load_library().ephbte_collision_integral(plan.handle, B, f.data_ptr(), ldf,
-                                                    nph.data_ptr(), out.data_ptr(), ldi,
-                                                    _stream(f.device)), "collision_integral")
+                                                    nph.data_ptr(), per_batch, out.data_ptr(),
+                                                    ldi, _stream(f.device)), "collision_integral")
     return out
 
 
@@ -275,7 +291,7 @@ def collision_vjp(plan: Plan, f, nph, gI, want_f=True, gg2=None, accumulate=Fals
     Bg, ldg = _batch(plan, gI, "gI")
     if Bg != B:
         raise ValueError("gI batch differs from f batch")
-    _dev_tensor(plan, nph, "nph")
+    per_batch = _nph_arg(plan, nph, B, f)
     gf = None
     if want_f:
         gf = torch.empty_like(f, memory_format=torch.contiguous_format)
@@ -287,7 +303,7 @@ def collision_vjp(plan: Plan, f, nph, gI, want_f=True, gg2=None, accumulate=Fals
             raise ValueError("gg2 must be a contiguous FP64 [n_channels] tensor")
     ldgf = plan.n_states
     _check(load_library().ephbte_collision_vjp(
-        plan.handle, B, f.data_ptr(), ldf, nph.data_ptr(), gI.data_ptr(), ldg,
+        plan.handle, B, f.data_ptr(), ldf, nph.data_ptr(), per_batch, gI.data_ptr(), ldg,
         gf.data_ptr() if gf is not None else None, ldgf,
         gg2.data_ptr() if gg2 is not None else None, 1 if accumulate else 0,
         _stream(f.device)), "collision_vjp")

@@ -1273,8 +1273,8 @@ ephbte_status ephbte_build_channels(const ephbte_problem *problem, ephbte_plan *
 }
 
 ephbte_status ephbte_collision_integral(ephbte_plan plan, int32_t batch, const void *f,
-                                        int64_t ldf, const void *nph, void *I, int64_t ldi,
-                                        void *stream) {
+                                        int64_t ldf, const void *nph, int32_t nph_per_batch,
+                                        void *I, int64_t ldi, void *stream) {
     return guarded(plan, stream, [&]() -> ephbte_status {
         if (batch < 1 || batch > 65535) return fail(EPHBTE_INVALID_ARGUMENT, "batch must be in [1, 65535]");
         if (!f || !nph || !I) return fail(EPHBTE_INVALID_ARGUMENT, "f, nph and I must be non-NULL");
@@ -1284,23 +1284,33 @@ ephbte_status ephbte_collision_integral(ephbte_plan plan, int32_t batch, const v
         if (overlaps(f, es * ldf * batch, I, es * ldi * batch))
             return fail(EPHBTE_INVALID_ARGUMENT, "I must not overlap f");
         hipStream_t s = as_stream(stream);
-        if (plan->dtype == EPHBTE_F64) {
-            ensure_fwd<double>(plan, batch);
-            enqueue_forward<double>(plan, batch, static_cast<const double *>(f), ldf, nph,
-                                    epi_store<double>(static_cast<double *>(I), ldi), s);
-        } else {
-            ensure_fwd<float>(plan, batch);
-            enqueue_forward<float>(plan, batch, static_cast<const float *>(f), ldf, nph,
-                                   epi_store<float>(static_cast<float *>(I), ldi), s);
-        }
+        auto run = [&](auto tag) {
+            using T = decltype(tag);
+            const T *ft = static_cast<const T *>(f);
+            T *It = static_cast<T *>(I);
+            if (!nph_per_batch || batch == 1) {
+                ensure_fwd<T>(plan, batch);
+                enqueue_forward<T>(plan, batch, ft, ldf, nph, epi_store<T>(It, ldi), s);
+                return;
+            }
+            // one bath per vector: the {hw, N} table differs per vector, so
+            // each vector is a single-vector pass after its own pack
+            ensure_fwd<T>(plan, 1);
+            const int64_t tab = nqm_of(plan);
+            for (int b = 0; b < batch; ++b)
+                enqueue_forward<T>(plan, 1, ft + b * ldf, ldf, static_cast<const T *>(nph) + b * tab,
+                                   epi_store<T>(It + b * ldi, ldi), s);
+        };
+        if (plan->dtype == EPHBTE_F64) run(double{});
+        else run(float{});
         return EPHBTE_OK;
     });
 }
 
 ephbte_status ephbte_collision_vjp(ephbte_plan plan, int32_t batch, const void *f, int64_t ldf,
-                                   const void *nph, const void *gI, int64_t ldg, void *gf,
-                                   int64_t ldgf, double *gg2, int32_t accumulate_gg2,
-                                   void *stream) {
+                                   const void *nph, int32_t nph_per_batch, const void *gI,
+                                   int64_t ldg, void *gf, int64_t ldgf, double *gg2,
+                                   int32_t accumulate_gg2, void *stream) {
     return guarded(plan, stream, [&]() -> ephbte_status {
         if (batch < 1 || batch > 65535) return fail(EPHBTE_INVALID_ARGUMENT, "batch must be in [1, 65535]");
         if (!f || !nph || !gI) return fail(EPHBTE_INVALID_ARGUMENT, "f, nph and gI must be non-NULL");
@@ -1310,16 +1320,19 @@ ephbte_status ephbte_collision_vjp(ephbte_plan plan, int32_t batch, const void *
         if (gf && (overlaps(gf, es * ldgf * batch, f, es * ldf * batch) ||
                    overlaps(gf, es * ldgf * batch, gI, es * ldg * batch)))
             return fail(EPHBTE_INVALID_ARGUMENT, "gf must not overlap f or gI");
+        if (!gf && !gg2) return EPHBTE_OK;
         hipStream_t s = as_stream(stream);
         auto run = [&](auto tag) {
             using T = decltype(tag);
             ensure_part<T>(plan, 1, 1);
             ensure_fwd<T>(plan, 1);
-            enqueue_pack<T>(plan, nph, s);
-            const int64_t S = plan->S;
+            const int64_t S = plan->S, tab = nqm_of(plan);
+            const bool per_batch = nph_per_batch && batch > 1;
             // the kernels take unit-stride vectors of length S; strided
             // batch members are addressed one vector at a time
             for (int b = 0; b < batch; ++b) {
+                const T *nb = static_cast<const T *>(nph) + (per_batch ? b * tab : 0);
+                if (b == 0 || per_batch) enqueue_pack<T>(plan, nb, s);
                 const T *fb = static_cast<const T *>(f) + b * ldf;
                 const T *lb = static_cast<const T *>(gI) + b * ldg;
                 Epi<T> e{};
@@ -1328,9 +1341,8 @@ ephbte_status ephbte_collision_vjp(ephbte_plan plan, int32_t batch, const void *
                 } else {
                     e.mode = -1;
                 }
-                int gmode = gg2 ? ((accumulate_gg2 || b > 0) ? 2 : 1) : 0;
-                if (!gf && !gg2) continue;
-                enqueue_vjp<T>(plan, fb, lb, nph, e, gg2, gmode, s);
+                const int gmode = gg2 ? ((accumulate_gg2 || b > 0) ? 2 : 1) : 0;
+                enqueue_vjp<T>(plan, fb, lb, nb, e, gg2, gmode, s);
             }
         };
         if (plan->dtype == EPHBTE_F64) run(double{});

@@ -39,7 +39,7 @@ def test_status_strings():
 
 def test_null_plan_is_rejected():
     lib = E.load_library()
-    st = lib.ephbte_collision_integral(None, 1, None, 1, None, None, 1, None)
+    st = lib.ephbte_collision_integral(None, 1, None, 1, None, 0, None, 1, None)
     assert st == binding.INVALID_ARGUMENT
     assert "plan" in E.last_error()
     assert lib.ephbte_plan_bytes(None) == 0

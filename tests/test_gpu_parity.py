@@ -415,6 +415,45 @@ def test_vjp_fp32(E):
     plan.close()
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_bath_per_vector(E, dtype):
+    """nph [B, Nq, n_modes]: vector b sees the bath of its own temperature,
+    forward and reverse (dL/d|g|^2 summed over the vectors)."""
+    s = synth.tb_system(kn=24, qn=12, target_states=400)
+    temps = [150.0, 300.0, 450.0, 220.0, 600.0]
+    B = len(temps)
+    F = np.stack([np.clip(synth.random_occupations(s, 20 + b), 0, 1) for b in range(B)])
+    NPH = np.stack([s.nph(T) for T in temps])
+    L = np.random.default_rng(5).normal(size=(B, s.n_states))
+    r = s
+    tdt, tol = torch.float64, TOL64
+    if dtype == "f32":
+        F, NPH, L = (a.astype(np.float32).astype(np.float64) for a in (F, NPH, L))
+        r, tdt, tol = round32(s), torch.float32, TOL32
+    plan = E.build_channels(s, dtype=dtype, device=0)
+    say(f"bath per vector {dtype} B={B} S={s.n_states} Nch={s.n_channels}")
+    I = host(E.collision_integral(plan, dev(F, tdt), dev(NPH, tdt)))
+    for b in range(B):
+        ref = oracle.collision(r, F[b], NPH[b])
+        rin, rout = oracle.collision_inout(r, F[b], NPH[b])
+        scale = max(np.abs(ref).max(), 1e-2 * max(rin.max(), rout.max()))
+        assert nerr(I[b], ref, scale) <= tol, b
+    # the shared-table call on the same vectors differs from it
+    Ish = host(E.collision_integral(plan, dev(F, tdt), dev(NPH[1], tdt)))
+    assert np.abs(Ish[0] - I[0]).max() > 1e-3 * np.abs(I[0]).max()
+    gf, gg = E.collision_vjp(plan, dev(F, tdt), dev(NPH, tdt), dev(L, tdt), gg2=True)
+    gf, gg = host(gf), host(gg)
+    rg_sum = 0
+    for b in range(B):
+        rf, rg = oracle.collision_vjp(r, F[b], NPH[b], L[b])
+        assert nerr(gf[b], rf) <= tol, b
+        rg_sum = rg_sum + rg
+    assert nerr(gg, rg_sum) <= tol
+    with pytest.raises(ValueError):
+        E.collision_integral(plan, dev(F, tdt), dev(NPH[:2], tdt))
+    plan.close()
+
+
 def test_autograd_function(E):
     from paper_2511_03683_amd.autograd import collision
     s = synth.multiband_system()
