@@ -111,6 +111,18 @@ typedef struct {
     int32_t reserved[2];       /* must be 0                                        */
 } ephbte_tuning;
 
+/* Channel selection applied at build (paper: scattering-channel paragraph
+ * after Eq. 2: approximate energy conservation with the Gaussian delta and a
+ * cutoff on |g|).  Zero-initialised options keep every channel. */
+typedef struct {
+    double energy_nsigma;      /* > 0: keep channel (i, j, nu) only if
+                                  min(|D + hw|, |D - hw|) < energy_nsigma * sigma,
+                                  D = eps_i - eps_j, hw = hw(q = k_j - k_i, nu)
+                                  (FP64); 0 = no energy cut                     */
+    double g2_min;             /* keep a channel only if |g|^2 >= g2_min; 0 = all */
+    int32_t reserved[4];       /* must be 0                                        */
+} ephbte_build_opts;
+
 /*
  * Build the device channel layout (paper: Optimized GPU algorithm, step 1,
  * "create the target layer": channels grouped by the collision-integral
@@ -121,22 +133,29 @@ typedef struct {
  * range, i == j, a pair not commensurate with the q grid, a channel whose
  * phonon energy is below 1e-6 eV in either orientation (its N diverges),
  * duplicate (i, j, nu) channels, non-finite or negative hw/g2/eps, sigma or
- * n_q_norm <= 0.  OUT_OF_MEMORY if device memory runs out.  *out receives a
- * plan owned by the caller until ephbte_destroy.  Synchronous.
+ * n_q_norm <= 0, and options out of range.  Every channel is validated; the
+ * selection of opts (NULL: none) then removes channels, and the plan computes
+ * Eq. 2 over the ones kept: their |g|^2 gradients are 0, and ephbte_update_g2
+ * does not re-run the selection.  Duplicates are detected among kept
+ * channels.  OUT_OF_MEMORY if device memory runs out.  *out receives a plan
+ * owned by the caller until ephbte_destroy.  Synchronous.
  */
-ephbte_status ephbte_build_channels(const ephbte_problem *problem, ephbte_plan *out);
+ephbte_status ephbte_build_channels(const ephbte_problem *problem, const ephbte_build_opts *opts,
+                                    ephbte_plan *out);
 
 /*
- * Host-only view of the layout ephbte_build_channels would build, for
- * inspection and tests.  Runs the same validation and sort without touching a
- * device.  Caller allocates: row_ptr [S+1], entry_partner [2*n_channels],
- * entry_mode [2*n_channels], entry_channel [2*n_channels] (any may be NULL).
+ * Host-only view of the layout ephbte_build_channels would build with the
+ * same options, for inspection and tests.  Runs the same validation,
+ * selection and sort without touching a device.  Caller allocates: row_ptr
+ * [S+1], entry_partner [2*n_channels], entry_mode [2*n_channels],
+ * entry_channel [2*n_channels] (any may be NULL; the kept entries fill the
+ * first row_ptr[S] slots).
  * Entry e of destination d (row_ptr[d] <= e < row_ptr[d+1]) has partner
  * entry_partner[e], mode entry_mode[e] and comes from caller channel
  * entry_channel[e].
  */
-ephbte_status ephbte_layout_host(const ephbte_problem *problem, int64_t *row_ptr,
-                                 int32_t *entry_partner, int8_t *entry_mode,
+ephbte_status ephbte_layout_host(const ephbte_problem *problem, const ephbte_build_opts *opts,
+                                 int64_t *row_ptr, int32_t *entry_partner, int8_t *entry_mode,
                                  int32_t *entry_channel);
 
 /*
@@ -236,9 +255,10 @@ ephbte_status ephbte_set_tuning(ephbte_plan plan, const ephbte_tuning *tuning);
  * kernel.  Allocates and frees its own half-filled occupations.  Synchronous. */
 ephbte_status ephbte_autotune(ephbte_plan plan, int32_t batch, ephbte_tuning *chosen);
 
-/* Plan facts: out[0]=S, [1]=n_channels, [2]=entries, [3]=chunks, [4]=dtype,
- * [5]=device, [6]=device bytes held, [7]=chunk_entries, [8]=block_threads. */
-ephbte_status ephbte_plan_info(ephbte_plan plan, int64_t out[9]);
+/* Plan facts: out[0]=S, [1]=n_channels passed at build, [2]=entries,
+ * [3]=chunks, [4]=dtype, [5]=device, [6]=device bytes held,
+ * [7]=chunk_entries, [8]=block_threads, [9]=channels kept by the selection. */
+ephbte_status ephbte_plan_info(ephbte_plan plan, int64_t out[10]);
 
 int64_t ephbte_plan_bytes(ephbte_plan plan);
 void ephbte_destroy(ephbte_plan plan);

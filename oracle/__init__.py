@@ -7,6 +7,9 @@ constants and its own q-index, Gaussian and occupation-factor arithmetic.
 
 Contents, each following the paper (arXiv 2511.03683):
 
+* select_channels(sys, ...)     -- the channel selection that precedes the
+  list (scattering-channel paragraph after Eq. 2: approximate energy
+  conservation with the Gaussian delta, a cutoff on |g|), as a keep mask.
 * collision(sys, f, nph)        -- Eq. 2 over a channel list (Results,
   "Collision integral ..."; the channel-list loop is the Baseline-CPU loop
   shape of "Reference CPU algorithm", run sequentially).
@@ -92,6 +95,50 @@ class _Args:
         return [self.S, _ptr(self.state_k), _ptr(self.eps), _ptr(self.kgrid), _ptr(self.qgrid),
                 self.nm, _ptr(self.hw), _ptr(self.nph), self.sigma, self.nq,
                 int(self.ci.size), _ptr(self.ci), _ptr(self.cj), _ptr(self.cn), _ptr(self.g2)]
+
+
+# ---------------------------------------------------------------------------
+# channel selection (scattering-channel paragraph after Eq. 2)
+# ---------------------------------------------------------------------------
+def channel_phonon_energy(sys):
+    """hw(q, nu) of every channel, with q = k_j - k_i folded onto the q grid
+    (the k grid is an integer multiple of the q grid along each axis)."""
+    kg = np.asarray(sys.kgrid, np.int64)
+    qg = np.asarray(sys.qgrid, np.int64)
+    k = np.asarray(sys.state_k, np.int64)
+    kc = np.stack([k // (kg[1] * kg[2]), (k // kg[2]) % kg[1], k % kg[2]], axis=1)
+    dk = (kc[np.asarray(sys.ch_j)] - kc[np.asarray(sys.ch_i)]) % kg
+    ratio = kg // qg
+    assert np.all(dk % ratio == 0), "k_j - k_i must be a q-grid vector"
+    q = dk // ratio
+    qlin = (q[:, 0] * qg[1] + q[:, 1]) * qg[2] + q[:, 2]
+    return np.asarray(sys.hw, np.float64)[qlin, np.asarray(sys.ch_nu, np.int64)]
+
+
+def select_channels(sys, energy_nsigma=0.0, g2_min=0.0):
+    """Keep mask [n_channels] of the channel selection.  A channel survives
+    approximate energy conservation when one of its two Gaussian deltas, of
+    eps_i - eps_j + hw (absorption) or eps_i - eps_j - hw (emission), lies
+    within energy_nsigma standard deviations of its centre (0 disables the
+    energy cut), and the |g|^2 cut when |g|^2 >= g2_min.  The comparison is
+    taken in FP64, as the library takes it."""
+    eps = np.asarray(sys.eps, np.float64)
+    g2 = np.asarray(sys.g2, np.float64)
+    keep = g2 >= float(g2_min)
+    if energy_nsigma:
+        d = eps[np.asarray(sys.ch_i)] - eps[np.asarray(sys.ch_j)]
+        w = channel_phonon_energy(sys)
+        keep &= np.minimum(np.abs(d + w), np.abs(d - w)) < float(energy_nsigma) * float(sys.sigma)
+    return keep
+
+
+def subset(sys, keep):
+    """Copy of a system holding only the channels where keep is True."""
+    import copy
+    r = copy.copy(sys)
+    for name in ("ch_i", "ch_j", "ch_nu", "g2"):
+        setattr(r, name, np.asarray(getattr(sys, name))[keep])
+    return r
 
 
 # ---------------------------------------------------------------------------

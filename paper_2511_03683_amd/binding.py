@@ -39,6 +39,11 @@ class Problem(ctypes.Structure):
                 ("dtype", ctypes.c_int32), ("device", ctypes.c_int32)]
 
 
+class BuildOpts(ctypes.Structure):
+    _fields_ = [("energy_nsigma", ctypes.c_double), ("g2_min", ctypes.c_double),
+                ("reserved", ctypes.c_int32 * 4)]
+
+
 class Tuning(ctypes.Structure):
     _fields_ = [("chunk_entries", ctypes.c_int32), ("block_threads", ctypes.c_int32),
                 ("xcd_map", ctypes.c_int32), ("batch_partners", ctypes.c_int32),
@@ -49,8 +54,10 @@ class Tuning(ctypes.Structure):
 _LIB = None
 
 SYMBOLS = {
-    "ephbte_build_channels": ([ctypes.POINTER(Problem), ctypes.POINTER(_P)], ctypes.c_int32),
-    "ephbte_layout_host": ([ctypes.POINTER(Problem), _P, _P, _P, _P], ctypes.c_int32),
+    "ephbte_build_channels": ([ctypes.POINTER(Problem), ctypes.POINTER(BuildOpts),
+                               ctypes.POINTER(_P)], ctypes.c_int32),
+    "ephbte_layout_host": ([ctypes.POINTER(Problem), ctypes.POINTER(BuildOpts), _P, _P, _P, _P],
+                           ctypes.c_int32),
     "ephbte_collision_integral": ([_P, ctypes.c_int32, _P, ctypes.c_int64, _P, ctypes.c_int32,
                                    _P, ctypes.c_int64, _P], ctypes.c_int32),
     "ephbte_collision_vjp": ([_P, ctypes.c_int32, _P, ctypes.c_int64, _P, ctypes.c_int32, _P,
@@ -220,8 +227,20 @@ def _batch(plan, t, name):
 
 
 # ---------------------------------------------------------------- entry points
-def build_channels(system, dtype="f64", device: Optional[int] = None) -> Plan:
-    """Build the device channel layout of a problem (see ephbte_build_channels)."""
+def _opts(energy_nsigma: float, g2_min: float):
+    """BuildOpts pointer, or None (keep every channel) when both are 0."""
+    if not energy_nsigma and not g2_min:
+        return None
+    o = BuildOpts()
+    o.energy_nsigma = float(energy_nsigma)
+    o.g2_min = float(g2_min)
+    return ctypes.byref(o)
+
+
+def build_channels(system, dtype="f64", device: Optional[int] = None,
+                   energy_nsigma: float = 0.0, g2_min: float = 0.0) -> Plan:
+    """Build the device channel layout of a problem (see ephbte_build_channels).
+    energy_nsigma > 0 and g2_min > 0 select channels (ephbte_build_opts)."""
     lib = load_library()
     code = _dtype_code(dtype)
     if device is None:
@@ -229,13 +248,15 @@ def build_channels(system, dtype="f64", device: Optional[int] = None) -> Plan:
         device = torch.cuda.current_device()
     pr, keep = _problem(system, code, device)
     h = ctypes.c_void_p()
-    _check(lib.ephbte_build_channels(ctypes.byref(pr), ctypes.byref(h)), "build_channels")
+    _check(lib.ephbte_build_channels(ctypes.byref(pr), _opts(energy_nsigma, g2_min),
+                                     ctypes.byref(h)), "build_channels")
     del keep
     return Plan(h.value, system, code, device)
 
 
-def layout_host(system):
-    """Host-only layout view: (row_ptr, partner, mode, channel) numpy arrays."""
+def layout_host(system, energy_nsigma: float = 0.0, g2_min: float = 0.0):
+    """Host-only layout view: (row_ptr, partner, mode, channel) numpy arrays
+    over the channels the selection keeps."""
     lib = load_library()
     pr, keep = _problem(system, F64, -1)
     S, E = int(system.n_states), 2 * int(system.n_channels)
@@ -243,10 +264,12 @@ def layout_host(system):
     partner = np.zeros(E, np.int32)
     mode = np.zeros(E, np.int8)
     chan = np.zeros(E, np.int32)
-    _check(lib.ephbte_layout_host(ctypes.byref(pr), row_ptr.ctypes.data, partner.ctypes.data,
-                                  mode.ctypes.data, chan.ctypes.data), "layout_host")
+    _check(lib.ephbte_layout_host(ctypes.byref(pr), _opts(energy_nsigma, g2_min),
+                                  row_ptr.ctypes.data, partner.ctypes.data, mode.ctypes.data,
+                                  chan.ctypes.data), "layout_host")
     del keep
-    return row_ptr, partner, mode, chan
+    n = int(row_ptr[S])
+    return row_ptr, partner[:n], mode[:n], chan[:n]
 
 
 def _nph_arg(plan: Plan, nph, B: int, f):
@@ -391,10 +414,10 @@ def autotune(plan: Plan, batch: int = 1) -> dict:
 
 
 def plan_info(plan: Plan) -> dict:
-    out = np.zeros(9, np.int64)
+    out = np.zeros(10, np.int64)
     _check(load_library().ephbte_plan_info(plan.handle, out.ctypes.data), "plan_info")
     keys = ["n_states", "n_channels", "entries", "chunks", "dtype", "device", "bytes",
-            "chunk_entries", "block_threads"]
+            "chunk_entries", "block_threads", "channels_kept"]
     return {k: int(v) for k, v in zip(keys, out)}
 
 

@@ -64,7 +64,10 @@ struct ephbte_plan_s {
     int device = 0;
     int dtype = EPHBTE_F64;
     int S = 0, nm = 0;
-    int64_t nch = 0, E = 0;
+    int64_t nch = 0, E = 0;          // channels passed at build; entries of the kept channels
+    int64_t nch_kept = 0;
+    int32_t *drop_idx = nullptr;     // [n_drop] caller indices removed by the channel selection
+    int64_t n_drop = 0;
     int nq[3] = {0, 0, 0};
     double sigma = 0, nqnorm = 0;
     std::vector<int64_t> row_ptr;   // host copy for re-chunking
@@ -202,7 +205,8 @@ void free_plan(ephbte_plan P) {
                      (void **)&P->btiles,    (void **)&P->sub_off,    (void **)&P->e2tab,
                      (void **)&P->sym_chunk_beg, (void **)&P->sym_chunk_end, (void **)&P->sym_chunk_dest,
                      (void **)&P->sym_dest_chunk, (void **)&P->sym_tiles, (void **)&P->jacc,
-                     (void **)&P->nmax_bits, (void **)&P->gmax_bits, (void **)&P->pack_bmax};
+                     (void **)&P->nmax_bits, (void **)&P->gmax_bits, (void **)&P->pack_bmax,
+                     (void **)&P->drop_idx};
     for (auto pp : ptrs) dfree(*pp);
     DevBuf *w[] = {&P->part,   &P->sym_part, &P->rk_ua,  &P->rk_ub,   &P->rk_acc, &P->hwN, &P->tr_W,   &P->tr_tau_inv,
                    &P->tr_tau, &P->tr_rhs, &P->tr_xa,   &P->tr_xb,  &P->tr_part, &P->tr_red,
@@ -596,6 +600,13 @@ __global__ void k_fill_f64(double *p, int64_t n, double v) {
     for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
          i += static_cast<int64_t>(gridDim.x) * blockDim.x)
         p[i] = v;
+}
+
+// p[idx[x]] = 0 for x < n (the |g|^2 gradients of channels the selection removed)
+__global__ void k_zero_at(double *p, const int32_t *__restrict__ idx, int64_t n) {
+    for (int64_t x = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; x < n;
+         x += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        p[idx[x]] = 0.0;
 }
 
 template <typename T>
@@ -1143,13 +1154,13 @@ const char *ephbte_status_string(ephbte_status s) {
 
 const char *ephbte_last_error(void) { return g_last_error.c_str(); }
 
-ephbte_status ephbte_layout_host(const ephbte_problem *problem, int64_t *row_ptr,
-                                 int32_t *entry_partner, int8_t *entry_mode,
+ephbte_status ephbte_layout_host(const ephbte_problem *problem, const ephbte_build_opts *opts,
+                                 int64_t *row_ptr, int32_t *entry_partner, int8_t *entry_mode,
                                  int32_t *entry_channel) {
     try {
         HostLayout L;
         std::string err;
-        ephbte_status st = build_host_layout(problem, &L, &err);
+        ephbte_status st = build_host_layout(problem, opts, &L, &err);
         if (st != EPHBTE_OK) return fail(st, err);
         if (row_ptr) std::memcpy(row_ptr, L.row_ptr.data(), sizeof(int64_t) * (L.S + 1));
         for (int64_t e = 0; e < L.E; ++e) {
@@ -1165,13 +1176,14 @@ ephbte_status ephbte_layout_host(const ephbte_problem *problem, int64_t *row_ptr
     }
 }
 
-ephbte_status ephbte_build_channels(const ephbte_problem *problem, ephbte_plan *out) {
+ephbte_status ephbte_build_channels(const ephbte_problem *problem, const ephbte_build_opts *opts,
+                                    ephbte_plan *out) {
     if (!out) return fail(EPHBTE_INVALID_ARGUMENT, "out is NULL");
     *out = nullptr;
     HostLayout L;
     std::string err;
     try {
-        ephbte_status st = build_host_layout(problem, &L, &err);
+        ephbte_status st = build_host_layout(problem, opts, &L, &err);
         if (st != EPHBTE_OK) return fail(st, err);
     } catch (const std::bad_alloc &) {
         return fail(EPHBTE_OUT_OF_MEMORY, "host memory allocation failed");
@@ -1192,8 +1204,15 @@ ephbte_status ephbte_build_channels(const ephbte_problem *problem, ephbte_plan *
         P->dtype = problem->dtype;
         P->S = L.S;
         P->nm = L.n_modes;
-        P->nch = L.n_channels;
+        P->nch = L.n_input;
+        P->nch_kept = L.n_channels;
         P->E = L.E;
+        P->n_drop = static_cast<int64_t>(L.dropped.size());
+        if (P->n_drop > 0) {
+            dalloc(P->drop_idx, sizeof(int32_t) * P->n_drop, &P->layout_bytes);
+            HIPC(hipMemcpy(P->drop_idx, L.dropped.data(), sizeof(int32_t) * P->n_drop,
+                           hipMemcpyHostToDevice));
+        }
         for (int a = 0; a < 3; ++a) P->nq[a] = L.nq[a];
         P->sigma = problem->sigma;
         P->nqnorm = problem->n_q_norm;
@@ -1328,6 +1347,11 @@ ephbte_status ephbte_collision_vjp(ephbte_plan plan, int32_t batch, const void *
             ensure_fwd<T>(plan, 1);
             const int64_t S = plan->S, tab = nqm_of(plan);
             const bool per_batch = nph_per_batch && batch > 1;
+            if (gg2 && !accumulate_gg2 && plan->n_drop > 0) {
+                const unsigned nb = static_cast<unsigned>(std::min<int64_t>((plan->n_drop + 255) / 256, 1024));
+                hipLaunchKernelGGL(k_zero_at, dim3(nb), dim3(256), 0, s, gg2, (const int32_t *)plan->drop_idx,
+                                   plan->n_drop);
+            }
             // the kernels take unit-stride vectors of length S; strided
             // batch members are addressed one vector at a time
             for (int b = 0; b < batch; ++b) {
@@ -1583,7 +1607,7 @@ ephbte_status ephbte_autotune(ephbte_plan plan, int32_t batch, ephbte_tuning *ch
     });
 }
 
-ephbte_status ephbte_plan_info(ephbte_plan plan, int64_t out[9]) {
+ephbte_status ephbte_plan_info(ephbte_plan plan, int64_t out[10]) {
     if (!plan || !out) return fail(EPHBTE_INVALID_ARGUMENT, "plan and out must be non-NULL");
     out[0] = plan->S;
     out[1] = plan->nch;
@@ -1594,6 +1618,7 @@ ephbte_status ephbte_plan_info(ephbte_plan plan, int64_t out[9]) {
     out[6] = static_cast<int64_t>(plan->bytes());
     out[7] = plan->chunk_entries;
     out[8] = plan->block_threads;
+    out[9] = plan->nch_kept;
     return EPHBTE_OK;
 }
 

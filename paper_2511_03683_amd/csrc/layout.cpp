@@ -51,12 +51,22 @@ std::string fmt_channel(int64_t c, int32_t i, int32_t j, int nu) {
 
 }  // namespace
 
-ephbte_status build_host_layout(const ephbte_problem *p, HostLayout *out, std::string *err) {
+ephbte_status build_host_layout(const ephbte_problem *p, const ephbte_build_opts *opts,
+                                HostLayout *out, std::string *err) {
     auto bad = [&](const std::string &m) {
         *err = m;
         return EPHBTE_INVALID_ARGUMENT;
     };
     if (!p) return bad("problem is NULL");
+    double e_nsig = 0.0, g2_min = 0.0;
+    if (opts) {
+        e_nsig = opts->energy_nsigma;
+        g2_min = opts->g2_min;
+        if (!std::isfinite(e_nsig) || e_nsig < 0.0) return bad("energy_nsigma must be finite and >= 0");
+        if (!std::isfinite(g2_min) || g2_min < 0.0) return bad("g2_min must be finite and >= 0");
+        for (int32_t x : opts->reserved)
+            if (x != 0) return bad("reserved build options must be 0");
+    }
     if (p->dtype != EPHBTE_F32 && p->dtype != EPHBTE_F64) {
         *err = "dtype must be EPHBTE_F32 (1) or EPHBTE_F64 (2)";
         return EPHBTE_UNSUPPORTED_DTYPE;
@@ -125,6 +135,12 @@ ephbte_status build_host_layout(const ephbte_problem *p, HostLayout *out, std::s
     // --- validate channels (parallel, first error by lowest channel index)
     std::atomic<int64_t> first_bad{INT64_MAX};
     std::vector<std::string> msgs(T);
+    // channel selection (paper: scattering-channel paragraph after Eq. 2):
+    // approximate energy conservation keeps a channel when one of its two
+    // Gaussians, at Delta + hw or Delta - hw, lies within e_nsig standard
+    // deviations; couplings below g2_min are discarded
+    std::vector<uint8_t> keep(static_cast<size_t>(nch), 1);
+    const double e_cut = e_nsig * p->sigma;
     auto q_of = [&](int32_t d, int32_t pp) {
         int32_t q[3];
         for (int a = 0; a < 3; ++a) {
@@ -150,6 +166,11 @@ ephbte_status build_host_layout(const ephbte_problem *p, HostLayout *out, std::s
                 if (q1 < 0 || q2 < 0) m = "k_j - k_i is not a q-grid vector";
                 else if (p->hw[q1 * nm + nu] < 1e-6 || p->hw[q2 * nm + nu] < 1e-6)
                     m = "phonon energy below 1e-6 eV (divergent occupation)";
+                else {
+                    const double dl = p->eps[i] - p->eps[j], w = p->hw[q1 * nm + nu];
+                    const bool e_ok = e_nsig == 0.0 || std::min(std::fabs(dl + w), std::fabs(dl - w)) < e_cut;
+                    keep[c] = (e_ok && p->g2[c] >= g2_min) ? 1 : 0;
+                }
             }
             if (!m.empty()) {
                 int64_t cur = first_bad.load();
@@ -167,13 +188,20 @@ ephbte_status build_host_layout(const ephbte_problem *p, HostLayout *out, std::s
         return bad("invalid channel");
     }
 
+    L.n_input = nch;
+    L.dropped.clear();
+    for (int64_t c = 0; c < nch; ++c)
+        if (!keep[c]) L.dropped.push_back(static_cast<int32_t>(c));
+    const int64_t nkeep = nch - static_cast<int64_t>(L.dropped.size());
+
     // --- count entries per destination (per-thread histograms)
-    L.n_channels = nch;
-    L.E = 2 * nch;
+    L.n_channels = nkeep;
+    L.E = 2 * nkeep;
     std::vector<std::vector<int64_t>> cnt(T, std::vector<int64_t>(S, 0));
     parallel_ranges(nch, T, [&](int t, int64_t b, int64_t e) {
         auto &h = cnt[t];
         for (int64_t c = b; c < e; ++c) {
+            if (!keep[c]) continue;
             h[p->ch_i[c]]++;
             h[p->ch_j[c]]++;
         }
@@ -199,6 +227,7 @@ ephbte_status build_host_layout(const ephbte_problem *p, HostLayout *out, std::s
     parallel_ranges(nch, T, [&](int t, int64_t b, int64_t e) {
         auto &cur = cnt[t];
         for (int64_t c = b; c < e; ++c) {
+            if (!keep[c]) continue;
             int32_t i = p->ch_i[c], j = p->ch_j[c];
             int nu = p->ch_nu[c];
             int64_t ei = cur[i]++, ej = cur[j]++;

@@ -19,7 +19,8 @@ inline uint32_t pack_pnu(int32_t partner, int32_t mode) {
 
 struct HostLayout {
     int32_t S = 0;
-    int64_t n_channels = 0;
+    int64_t n_input = 0;              // channels the caller passed
+    int64_t n_channels = 0;           // channels kept by the selection
     int64_t E = 0;                    // entries = 2 * n_channels
     int32_t n_modes = 0;
     int32_t nq[3] = {0, 0, 0};        // q grid
@@ -28,11 +29,14 @@ struct HostLayout {
     std::vector<int32_t> ent_chan;    // [E] caller channel index of the entry
     std::vector<uint32_t> kq;         // [S] k coordinates in q-grid units, 10 bits each (k0,k1,k2)
     std::vector<int32_t> pmin, pmax;  // [S] smallest / largest partner of each destination
+    std::vector<int32_t> dropped;     // caller indices of the channels the selection removed
 };
 
-// Validates the problem and builds the layout.  On failure returns the
-// status and fills *err with a description.
-ephbte_status build_host_layout(const ephbte_problem *p, HostLayout *out, std::string *err);
+// Validates the problem, applies the channel selection of opts (may be NULL:
+// keep every channel) and builds the layout.  On failure returns the status
+// and fills *err with a description.
+ephbte_status build_host_layout(const ephbte_problem *p, const ephbte_build_opts *opts,
+                                HostLayout *out, std::string *err);
 
 // Work-split of the destination segments into chunks of at most
 // chunk_entries entries (each destination gets at least one chunk, possibly

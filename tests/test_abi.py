@@ -92,6 +92,42 @@ def test_layout_empty_and_isolated_states():
     assert rp.tolist() == [0, 1, 2, 2]
 
 
+@pytest.mark.parametrize("nsig,g2min", [(2.5, 0.0), (1.0, 1e-3), (0.0, 1.5e-3), (40.0, 0.0)])
+def test_channel_selection_matches_oracle(nsig, g2min):
+    """The library's build-time selection keeps exactly the channels of the
+    oracle's mask (the FP64 comparison is taken the same way on both sides),
+    and the kept set has a valid layout."""
+    import oracle
+    s = synth.tb_system(kn=24, qn=12, target_states=400)
+    keep = oracle.select_channels(s, nsig, g2min)
+    rp, partner, mode, chan = E.layout_host(s, energy_nsigma=nsig, g2_min=g2min)
+    assert rp[-1] == 2 * keep.sum()
+    kept = np.unique(chan)
+    assert np.array_equal(kept, np.nonzero(keep)[0])
+    assert np.all(np.bincount(chan, minlength=s.n_channels)[keep] == 2)
+    _check_layout(oracle.subset(s, keep))
+
+
+def test_selection_of_every_channel_and_option_errors():
+    s = synth.two_state_system(dE=0.07, hw=0.03, g2=2e-3, sigma=0.008)
+    rp, partner, *_ = E.layout_host(s, energy_nsigma=4.9)
+    assert rp.tolist() == [0, 0, 0] and partner.size == 0
+    rp, *_ = E.layout_host(s, energy_nsigma=5.1)
+    assert rp.tolist() == [0, 1, 2]
+    with pytest.raises(E.EphbteError, match="energy_nsigma"):
+        E.layout_host(s, energy_nsigma=-1.0)
+    with pytest.raises(E.EphbteError, match="g2_min"):
+        E.layout_host(s, g2_min=float("nan"))
+    lib = E.load_library()
+    pr, keep = binding._problem(s, binding.F64, -1)
+    o = binding.BuildOpts()
+    o.reserved[2] = 1
+    rp = np.zeros(3, np.int64)
+    assert lib.ephbte_layout_host(ctypes.byref(pr), ctypes.byref(o), rp.ctypes.data, None, None,
+                                  None) == binding.INVALID_ARGUMENT
+    assert "reserved" in E.last_error()
+
+
 def _bad(system, match):
     with pytest.raises(E.EphbteError, match=match) as ei:
         E.layout_host(system)
@@ -156,13 +192,13 @@ def test_bad_dtype_and_validation_precede_device_use():
     s = synth.multiband_system()
     pr, keep = binding._problem(s, 3, 0)
     h = ctypes.c_void_p()
-    assert lib.ephbte_build_channels(ctypes.byref(pr), ctypes.byref(h)) == binding.UNSUPPORTED_DTYPE
+    assert lib.ephbte_build_channels(ctypes.byref(pr), None, ctypes.byref(h)) == binding.UNSUPPORTED_DTYPE
     g = s.g2.copy()
     g[0] = -1
     s.g2 = g
     pr, keep = binding._problem(s, binding.F64, 0)
     # invalid input is reported as such even on a machine without a GPU
-    assert lib.ephbte_build_channels(ctypes.byref(pr), ctypes.byref(h)) == binding.INVALID_ARGUMENT
+    assert lib.ephbte_build_channels(ctypes.byref(pr), None, ctypes.byref(h)) == binding.INVALID_ARGUMENT
     assert h.value is None
 
 

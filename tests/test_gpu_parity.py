@@ -454,6 +454,41 @@ def test_bath_per_vector(E, dtype):
     plan.close()
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_channel_selection_at_build(E, dtype):
+    """A plan built with the energy and |g|^2 selection computes Eq. 2 over the
+    oracle's kept channels; the |g|^2 gradients of removed channels are 0."""
+    s = synth.tb_system(kn=24, qn=12, target_states=400)
+    nsig, g2min = 2.5, 5e-4
+    keep = oracle.select_channels(s, nsig, g2min)
+    sub = oracle.subset(s, keep)
+    f = np.clip(synth.random_occupations(s, 31), 0, 1)
+    nph = s.nph(300.0)
+    lam = np.random.default_rng(8).normal(size=s.n_states)
+    r, tdt, tol = sub, torch.float64, TOL64
+    if dtype == "f32":
+        f, nph, lam = (a.astype(np.float32).astype(np.float64) for a in (f, nph, lam))
+        r, tdt, tol = round32(sub), torch.float32, TOL32
+    plan = E.build_channels(s, dtype=dtype, device=0, energy_nsigma=nsig, g2_min=g2min)
+    say(f"selection at build {dtype} kept {int(keep.sum())} of {s.n_channels}")
+    info = E.plan_info(plan)
+    assert info["n_channels"] == s.n_channels and info["channels_kept"] == int(keep.sum())
+    assert info["entries"] == 2 * int(keep.sum())
+    I = host(E.collision_integral(plan, dev(f, tdt), dev(nph, tdt)))
+    ref = oracle.collision(r, f, nph)
+    rin, rout = oracle.collision_inout(r, f, nph)
+    scale = max(np.abs(ref).max(), 1e-2 * max(rin.max(), rout.max()))
+    assert nerr(I, ref, scale) <= tol
+    gg = torch.full((s.n_channels,), 7.0, dtype=torch.float64, device="cuda:0")
+    gf, gg = E.collision_vjp(plan, dev(f, tdt), dev(nph, tdt), dev(lam, tdt), gg2=gg)
+    rf, rg = oracle.collision_vjp(r, f, nph, lam)
+    gg = host(gg)
+    assert np.all(gg[~keep] == 0.0)
+    assert nerr(gg[keep], rg) <= tol
+    assert nerr(host(gf), rf) <= tol
+    plan.close()
+
+
 def test_autograd_function(E):
     from paper_2511_03683_amd.autograd import collision
     s = synth.multiband_system()

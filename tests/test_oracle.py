@@ -135,6 +135,63 @@ def test_two_state_off_resonance_tail():
     assert I[0] == pytest.approx(-pref * (absorb + emit), rel=1e-13)
 
 
+# --------------------------------------------------------- channel selection
+@pytest.mark.parametrize("swap", [False, True])
+def test_selection_two_state_by_hand(swap):
+    """One channel, e_j - e_i = 0.07 eV.  With hw = 0.03 eV the emission
+    Gaussian sits 0.04 eV = 5 sigma from its centre and the absorption one
+    0.10 eV; with hw = 0.2 eV the nearest is absorption at 0.13 eV = 16.25
+    sigma.  The channel survives exactly when n_sigma exceeds that distance,
+    in either orientation; the |g|^2 cut keeps |g|^2 >= g2_min."""
+    def mk(hw):
+        s = synth.two_state_system(dE=0.07, hw=hw, g2=2e-3, sigma=0.008, nq=2)
+        if swap:
+            s.ch_i, s.ch_j = s.ch_j.copy(), s.ch_i.copy()
+        return s
+    s = mk(0.03)
+    assert not oracle.select_channels(s, 4.9)[0]
+    assert oracle.select_channels(s, 5.1)[0]
+    s = mk(0.2)
+    assert not oracle.select_channels(s, 16.2)[0]
+    assert oracle.select_channels(s, 16.3)[0]
+    assert oracle.select_channels(s, 0.0, 2e-3)[0]
+    assert not oracle.select_channels(s, 0.0, 2.0001e-3)[0]
+    assert not oracle.select_channels(s, 16.3, 2.0001e-3)[0]
+
+
+def test_selection_disabled_keeps_everything(c1):
+    s, _, _ = c1
+    assert oracle.select_channels(s).all()
+    assert oracle.select_channels(s, 1e4, 0.0).all()
+    assert oracle.channel_phonon_energy(s).min() > 0
+
+
+@pytest.mark.parametrize("nsig,g2min", [(2.0, 0.0), (3.0, 5e-4), (0.0, 2e-3)])
+def test_selection_changes_I_by_at_most_the_dropped_tails(c1, nsig, g2min):
+    """A dropped channel contributes |X| <= C |g|^2 (N+1) (G(Delta+hw) +
+    G(Delta-hw)) to each of its two states (Eq. 2 with 0 <= f <= 1).  Energy-cut
+    channels have both Gaussians below G(n sigma), |g|^2-cut ones below G(0);
+    so I(all) - I(kept) is bounded state by state.  A selection that dropped a
+    near-resonant channel it should keep would break the bound."""
+    s, f, nph = c1
+    keep = oracle.select_channels(s, nsig, g2min)
+    assert 0 < keep.sum() < keep.size
+    diff = oracle.collision(s, f, nph) - oracle.collision(oracle.subset(s, keep), f, nph)
+    w = oracle.channel_phonon_energy(s)
+    N = 1.0 / np.expm1(w / (KB * 300.0))
+    C = 2 * math.pi / (HBAR * s.n_q_norm)
+    sig = s.sigma
+    g0 = 1.0 / (sig * math.sqrt(2 * math.pi))
+    e_cut = ~oracle.select_channels(s, nsig)
+    gmax = np.where(e_cut, math.exp(-0.5 * nsig ** 2) * g0, g0)
+    per = np.where(keep, 0.0, C * s.g2 * (N + 1) * 2 * gmax)
+    bound = np.zeros(s.n_states)
+    np.add.at(bound, s.ch_i, per)
+    np.add.at(bound, s.ch_j, per)
+    assert np.all(np.abs(diff) <= bound * (1 + 1e-12) + 1e-300)
+    assert np.abs(diff).max() > 0
+
+
 # --------------------------------------------------------------- derivatives
 def test_vjp_matches_central_differences():
     """I is quadratic in f and linear in |g|^2, so central differences are exact
