@@ -226,7 +226,17 @@ def main():
                                     vectors="16 temperatures (100-400 K) x 4 fields (0-1e5 V/m)")
         log(f"fwd fp64 B=64: {msb:.3f} ms ({forms['fwd_f64_b64']['ratio_vs_b1']:.2f}x per vector, "
             f"sub-tile {tuned['batch_partners']})")
-        del F, IB
+        # batched reverse mode: dL/df of the 64 vectors and dL/d|g|^2 summed over them
+        LB = tens(rng.normal(size=(B, s.n_states)), torch.float64)
+        ggb = torch.zeros(nch, dtype=torch.float64, device=dev)
+        msbv, _ = timed(lambda: E.collision_vjp(plan64, F, n64, LB, want_f=True, gg2=ggb), 3, 1)
+        forms["vjp_f64_b64"] = dict(ms=msbv, per_vector_channels_per_s=B * nch / (msbv * 1e-3),
+                                    ratio_vs_b1=(B * nch / (msbv * 1e-3)) / (nch / (ms_v * 1e-3)))
+        forms["fwd_plus_adjoint_f64_b64"] = dict(
+            ms=msb + msbv, per_vector_channels_per_s=B * nch / ((msb + msbv) * 1e-3),
+            ratio_vs_b1=(ms + ms_v) * B / (msb + msbv))
+        log(f"vjp fp64 B=64: {msbv:.3f} ms ({forms['vjp_f64_b64']['ratio_vs_b1']:.2f}x per vector)")
+        del F, IB, LB, ggb
         # transport iteration, FP64
         vel = tens(s.vel, torch.float64)
         f0 = tens(synth.fermi_dirac(s.eps, -0.1, 300.0), torch.float64)
@@ -292,7 +302,12 @@ def main():
                                     ratio_vs_b1=(64 * nch / (msb32 * 1e-3)) / (nch / (ms32 * 1e-3)),
                                     batch_partners=tuned32["batch_partners"])
         log(f"fwd fp32 B=64: {msb32:.3f} ms ({forms['fwd_f32_b64']['ratio_vs_b1']:.2f}x per vector)")
-        del F32, IB32
+        LB32 = tens(rng.normal(size=(64, s.n_states)), torch.float32)
+        gg32 = torch.zeros(nch, dtype=torch.float64, device=dev)
+        msbv32, _ = timed(lambda: E.collision_vjp(plan32, F32, n32, LB32, want_f=True, gg2=gg32), 3, 1)
+        forms["vjp_f32_b64"] = dict(ms=msbv32, per_vector_channels_per_s=64 * nch / (msbv32 * 1e-3))
+        log(f"vjp fp32 B=64: {msbv32:.3f} ms")
+        del F32, IB32, LB32, gg32
         forms["transport_solve_f32"] = transport_solve(
             E, plan32, tens(synth.fermi_dirac(s.eps, -0.1, 300.0), torch.float32),
             tens(s.vel, torch.float32), n32, timed)

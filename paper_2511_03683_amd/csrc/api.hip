@@ -105,7 +105,12 @@ struct ephbte_plan_s {
     int64_t *sub_off = nullptr;
     int64_t n_btiles = 0;
     int pt = 0;                 // partners per sub-tile
-    int batch_min = 8;          // smallest B that uses the batched kernel
+    // batched reverse pass: its own tiles (twice the LDS per partner), built on first use
+    BTileRec *vbtiles = nullptr;
+    int64_t *vsub_off = nullptr;
+    int64_t n_vbtiles = 0;
+    int vpt = 0;
+    int batch_min = 8;          // smallest B that uses the batched kernels
     int lds_states = 0;
     size_t lds_max = 65536;      // device limit of LDS per workgroup
     bool fused = true;
@@ -206,7 +211,7 @@ void free_plan(ephbte_plan P) {
                      (void **)&P->sym_chunk_beg, (void **)&P->sym_chunk_end, (void **)&P->sym_chunk_dest,
                      (void **)&P->sym_dest_chunk, (void **)&P->sym_tiles, (void **)&P->jacc,
                      (void **)&P->nmax_bits, (void **)&P->gmax_bits, (void **)&P->pack_bmax,
-                     (void **)&P->drop_idx};
+                     (void **)&P->drop_idx, (void **)&P->vbtiles, (void **)&P->vsub_off};
     for (auto pp : ptrs) dfree(*pp);
     DevBuf *w[] = {&P->part,   &P->sym_part, &P->rk_ua,  &P->rk_ub,   &P->rk_acc, &P->hwN, &P->tr_W,   &P->tr_tau_inv,
                    &P->tr_tau, &P->tr_rhs, &P->tr_xa,   &P->tr_xb,  &P->tr_part, &P->tr_red,
@@ -408,28 +413,33 @@ template <typename T> Epi<T> epi_store(T *out, int64_t ld) {
 constexpr int kBatchDPW = 4;       // destinations per wave in the batched kernel
 constexpr int kBatchThreads = 512;
 
-template <typename T> BArgs<T> batch_args(ephbte_plan P) {
+template <typename T>
+BArgs<T> batch_args(ephbte_plan P, const BTileRec *tiles, const int64_t *sub_off, int pt, int64_t n) {
     BArgs<T> a;
     a.pnu = P->pnu;
     a.g2 = static_cast<const T *>(P->g2);
     a.st = static_cast<const StateRec<T> *>(P->st);
     a.hwN = static_cast<const Pair2<T> *>(P->hwN.p);
-    a.btiles = P->btiles;
-    a.sub_off = P->sub_off;
+    a.btiles = tiles;
+    a.sub_off = sub_off;
     a.S = P->S;
     a.nm = P->nm;
     a.nq0 = P->nq[0];
     a.nq1 = P->nq[1];
     a.nq2 = P->nq[2];
-    a.pt = P->pt;
+    a.pt = pt;
     a.padq = P->padq ? 1 : 0;
     a.qoff = P->qoff;
-    a.n_btiles = P->n_btiles;
+    a.n_btiles = n;
     a.xcd = 0;   // measured: plain order is at least as fast for the batched pass
     Tables<T> t = tables<T>(P, nullptr);
     a.mc = t.mc;
     a.K = t.K;
     return a;
+}
+
+template <typename T> BArgs<T> batch_args(ephbte_plan P) {
+    return batch_args<T>(P, P->btiles, P->sub_off, P->pt, P->n_btiles);
 }
 
 // LDS of the batched kernel: f[pt][65] and the pt partner states
@@ -451,26 +461,68 @@ void enqueue_forward_batched(ephbte_plan P, int B, const T *f, int64_t ldf, cons
 
 // Batch tiles for partner sub-tiles of pt states: shapes from the host's
 // partner ranges, entry offsets searched on the device.  Synchronous.
-void upload_btiles(ephbte_plan P, int pt) {
+void build_btiles(ephbte_plan P, int pt, BTileRec *&tiles, int64_t *&sub_off, int64_t &n) {
     int64_t slots = 0;
     const std::vector<BTile> bt =
         make_btiles(P->pmin, P->pmax, pt, kBatchDPW * (kBatchThreads / 64), 4096, &slots);
     static_assert(sizeof(BTile) == sizeof(BTileRec), "batch tile record layout");
-    free_graphs(P);
-    dfree(reinterpret_cast<void *&>(P->btiles));
-    dfree(reinterpret_cast<void *&>(P->sub_off));
+    dfree(reinterpret_cast<void *&>(tiles));
+    dfree(reinterpret_cast<void *&>(sub_off));
+    n = 0;
     size_t dummy = 0;
-    dalloc(P->btiles, std::max<size_t>(bt.size(), 1) * sizeof(BTileRec), &dummy);
-    dalloc(P->sub_off, static_cast<size_t>(std::max<int64_t>(slots, 1)) * sizeof(int64_t), &dummy);
+    dalloc(tiles, std::max<size_t>(bt.size(), 1) * sizeof(BTileRec), &dummy);
+    dalloc(sub_off, static_cast<size_t>(std::max<int64_t>(slots, 1)) * sizeof(int64_t), &dummy);
     if (!bt.empty()) {
-        HIPC(hipMemcpy(P->btiles, bt.data(), bt.size() * sizeof(BTileRec), hipMemcpyHostToDevice));
+        HIPC(hipMemcpy(tiles, bt.data(), bt.size() * sizeof(BTileRec), hipMemcpyHostToDevice));
         hipLaunchKernelGGL(k_sub_offsets, dim3(static_cast<unsigned>(bt.size())), dim3(256), 0, nullptr,
-                           P->btiles, P->pnu, P->chunk_beg, P->dest_chunk, P->S, pt, P->sub_off);
+                           tiles, P->pnu, P->chunk_beg, P->dest_chunk, P->S, pt, sub_off);
         HIPC(hipGetLastError());
     }
     HIPC(hipDeviceSynchronize());
+    n = static_cast<int64_t>(bt.size());
+}
+
+void upload_btiles(ephbte_plan P, int pt) {
+    free_graphs(P);   // captured forward passes hold the old tiles
+    build_btiles(P, pt, P->btiles, P->sub_off, P->n_btiles);
     P->pt = pt;
-    P->n_btiles = static_cast<int64_t>(bt.size());
+}
+
+// LDS of the batched reverse kernel: {f, lam}[pt][65] and the pt partner states
+size_t vjp_batch_lds_bytes(ephbte_plan P, int pt) {
+    const size_t es = P->dtype == EPHBTE_F64 ? 8 : 4;
+    return static_cast<size_t>(pt) * (65 * 2 * es + (P->dtype == EPHBTE_F64 ? sizeof(StateRec<double>)
+                                                                              : sizeof(StateRec<float>)));
+}
+
+// partners per sub-tile of the batched reverse pass
+int vjp_default_pt(ephbte_plan P) { return P->dtype == EPHBTE_F64 ? 48 : 96; }
+
+// Tiles of the batched reverse pass (at plan build).  Synchronous.
+void upload_vjp_btiles(ephbte_plan P, int pt) {
+    if (vjp_batch_lds_bytes(P, pt) > P->lds_max) return;   // vpt stays 0: per-vector pass
+    build_btiles(P, pt, P->vbtiles, P->vsub_off, P->n_vbtiles);
+    P->vpt = pt;
+}
+
+// Batched reverse pass over B vectors in groups of 64 (false: not available
+// for this plan; the caller takes the per-vector pass).  The {hw, N} table
+// must already be packed.
+template <typename T>
+bool enqueue_vjp_batched(ephbte_plan P, int B, const T *f, int64_t ldf, const T *lam, int64_t ldl,
+                         T *gf, int64_t ldgf, double *gg2, int gg2_mode, hipStream_t s) {
+    if (B < P->batch_min || P->vpt == 0 || P->n_vbtiles == 0) return false;
+    const BArgs<T> a = batch_args<T>(P, P->vbtiles, P->vsub_off, P->vpt, P->n_vbtiles);
+    const size_t shm = vjp_batch_lds_bytes(P, P->vpt);
+    for (int b0 = 0; b0 < B; b0 += 64) {
+        const int nb = std::min(64, B - b0);
+        const int gm = gg2_mode == 0 ? 0 : (b0 == 0 ? gg2_mode : 2);
+        hipLaunchKernelGGL((k_vjp_batched<T, kBatchDPW>), dim3(static_cast<unsigned>(P->n_vbtiles)),
+                           dim3(kBatchThreads), shm, s, a, f, ldf, lam, ldl, b0, nb, gf, ldgf,
+                           (const int32_t *)P->ent_chan, gg2, gm);
+    }
+    HIPC(hipGetLastError());
+    return true;
 }
 
 // workgroups of the {hw, N} pack kernels
@@ -1278,6 +1330,7 @@ ephbte_status ephbte_build_channels(const ephbte_problem *problem, const ephbte_
         P->block_threads = 512;
         upload_chunks(P, 65536);
         upload_btiles(P, P->dtype == EPHBTE_F64 ? 96 : 192);
+        upload_vjp_btiles(P, vjp_default_pt(P));
         update_gmax(P, nullptr);
         HIPC(hipDeviceSynchronize());
     } catch (const HipError &e) {
@@ -1352,11 +1405,18 @@ ephbte_status ephbte_collision_vjp(ephbte_plan plan, int32_t batch, const void *
                 hipLaunchKernelGGL(k_zero_at, dim3(nb), dim3(256), 0, s, gg2, (const int32_t *)plan->drop_idx,
                                    plan->n_drop);
             }
+            if (!per_batch) {
+                enqueue_pack<T>(plan, nph, s);
+                if (enqueue_vjp_batched<T>(plan, batch, static_cast<const T *>(f), ldf,
+                                           static_cast<const T *>(gI), ldg, static_cast<T *>(gf), ldgf,
+                                           gg2, gg2 ? (accumulate_gg2 ? 2 : 1) : 0, s))
+                    return;
+            }
             // the kernels take unit-stride vectors of length S; strided
             // batch members are addressed one vector at a time
             for (int b = 0; b < batch; ++b) {
                 const T *nb = static_cast<const T *>(nph) + (per_batch ? b * tab : 0);
-                if (b == 0 || per_batch) enqueue_pack<T>(plan, nb, s);
+                if (per_batch) enqueue_pack<T>(plan, nb, s);
                 const T *fb = static_cast<const T *>(f) + b * ldf;
                 const T *lb = static_cast<const T *>(gI) + b * ldg;
                 Epi<T> e{};

@@ -1302,6 +1302,147 @@ __global__ __launch_bounds__(512) void k_fwd_batched(BArgs<T> A, const T *__rest
     }
 }
 
+// Reverse mode of Eq. 2 for up to 64 vectors sharing one phonon table
+// (vectors b0 .. b0 + nb - 1; lane = vector).  Tiles and sub-tiles as in
+// k_fwd_batched; the LDS tile holds {f_p, lam_p} per (partner, vector).
+//   dL/df_d = -K sum_e (lam_d - lam_p) u_e,  u_e = a_e (1 - f_p) + b_e f_p,
+// summed per lane as lam_d sum u - sum lam_p u.  The |g|^2 gradient of a
+// channel, written by its entry with p > d, is
+//   K [bh sum_b (lam_d - lam_p) f_p (1 - f_d) - ah sum_b (lam_d - lam_p) f_d (1 - f_p)],
+// where the two sums over the vectors depend only on the pair (d, p): they are
+// reduced across the wave once per run of equal partners and serve every mode
+// of the run.  gg2_mode: 0 none, 1 overwrite, 2 add.  Every slot is written by
+// one lane of one launch: deterministic.
+template <typename T, int DPW>
+__global__ __launch_bounds__(512) void k_vjp_batched(BArgs<T> A, const T *__restrict__ f, int64_t ldf,
+                                                     const T *__restrict__ lam, int64_t ldl, int b0,
+                                                     int nb, T *__restrict__ gf, int64_t ldgf,
+                                                     const int32_t *__restrict__ ent_chan,
+                                                     double *__restrict__ gg2, int gg2_mode) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int PT = A.pt;
+    Pair2<T> *s_FL = reinterpret_cast<Pair2<T> *>(smem);                   // [PT][65]
+    StateRec<T> *s_ek = reinterpret_cast<StateRec<T> *>(s_FL + PT * 65);  // [PT]
+    const int64_t ti = tile_of_block(A.n_btiles, A.xcd);
+    if (ti < 0) return;
+    const BTileRec t = A.btiles[ti];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    const int nw = static_cast<int>(blockDim.x >> 6);
+    const int nd = t.d1 - t.d0;
+    const bool lv = lane < nb;
+    T fd[DPW], ld[DPW], acc_u[DPW], acc_l[DPW];
+#pragma unroll
+    for (int j = 0; j < DPW; ++j) {
+        const int dl = wave + j * nw;
+        const bool ok = dl < nd && lv;
+        const int64_t row = static_cast<int64_t>(b0 + lane);
+        fd[j] = ok ? f[row * ldf + t.d0 + dl] : T(0);
+        ld[j] = ok ? lam[row * ldl + t.d0 + dl] : T(0);
+        acc_u[j] = T(0);
+        acc_l[j] = T(0);
+    }
+    for (int k = 0; k < t.n_sub; ++k) {
+        const int pa = t.p_lo + k * PT;
+        const int pc = min(PT, A.S - pa);
+        __syncthreads();
+        // vectors past nb hold f = lam = 0: their terms vanish in every sum
+        for (int i = threadIdx.x; i < pc * 64; i += blockDim.x) {
+            const int bb = i / pc, pl = i - bb * pc;
+            Pair2<T> v;
+            v.a = T(0);
+            v.b = T(0);
+            if (bb < nb) {
+                const int64_t row = static_cast<int64_t>(b0 + bb);
+                v.a = f[row * ldf + pa + pl];
+                v.b = lam[row * ldl + pa + pl];
+            }
+            s_FL[pl * 65 + bb] = v;
+        }
+        for (int i = threadIdx.x; i < pc; i += blockDim.x) s_ek[i] = A.st[pa + i];
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < DPW; ++j) {
+            const int dl = wave + j * nw;
+            if (dl < nd) {
+                const int d = t.d0 + dl;
+                const int64_t *so = A.sub_off + t.off_base + static_cast<int64_t>(dl) * (t.n_sub + 1);
+                const int64_t e_lo = so[k], e_hi = so[k + 1];
+                const StateRec<T> sd = A.st[d];
+                // the pairs of this sub-tile with p > d carry the |g|^2 gradients
+                const bool g_any = gg2_mode != 0 && pa + pc - 1 > d;
+                for (int64_t e0 = e_lo; e0 < e_hi; e0 += 64) {
+                    const int64_t e = e0 + lane;
+                    const bool valid = e < e_hi;
+                    int pl = -1 - lane;     // distinct for invalid lanes: never merged
+                    T ca = T(0), cb = T(0), ah = T(0), bh = T(0);
+                    int32_t ch = -1;
+                    if (valid) {
+                        const uint32_t pn = A.pnu[e];
+                        const T g = A.g2[e];
+                        pl = static_cast<int>(pn >> 3) - pa;
+                        const StateRec<T> sp = s_ek[pl];
+                        const int q = A.padq ? static_cast<int>(sp.kqp - sd.kqp) + A.qoff
+                                             : q_linear(sd.kq, sp.kq, A.nq0, A.nq1, A.nq2);
+                        const Pair2<T> wn = A.hwN[static_cast<int64_t>(q) * A.nm + (pn & 7u)];
+                        const T de = sd.eps - sp.eps;
+                        const T xa = de + wn.a, xe = de - wn.a;
+                        const T da = gauss_exp(xa * xa * A.mc);
+                        const T dem = gauss_exp(xe * xe * A.mc);
+                        const T tt = wn.b * (da + dem);
+                        ah = tt + dem;
+                        bh = tt + da;
+                        ca = g * ah;
+                        cb = g * bh;
+                        if (g_any && pa + pl > d) ch = ent_chan[e];
+                    }
+                    // sum each run of equal partners into its first lane
+#pragma unroll
+                    for (int off = 1; off < 64; off <<= 1) {
+                        const T oa = __shfl_down(ca, off, 64);
+                        const T ob = __shfl_down(cb, off, 64);
+                        const int op = __shfl_down(pl, off, 64);
+                        if (lane + off < 64 && op == pl) {
+                            ca += oa;
+                            cb += ob;
+                        }
+                    }
+                    const int prev = __shfl_up(pl, 1, 64);
+                    const bool head = valid && (lane == 0 || prev != pl);
+                    unsigned long long m = __ballot(head);
+                    while (m) {
+                        const int src = __builtin_ctzll(m);
+                        m &= m - 1;
+                        const T a = lane_bcast(ca, src);
+                        const T bq = lane_bcast(cb, src);
+                        const int pls = __builtin_amdgcn_readlane(pl, src);
+                        const Pair2<T> fl = s_FL[pls * 65 + lane];
+                        const T u = a + (bq - a) * fl.a;
+                        acc_u[j] += u;
+                        acc_l[j] += fl.b * u;
+                        if (g_any && pa + pls > d) {
+                            const T dlm = ld[j] - fl.b;
+                            const T p1 = wave_sum(dlm * fd[j] * (T(1) - fl.a));
+                            const T p2 = wave_sum(dlm * fl.a * (T(1) - fd[j]));
+                            if (pl == pls && ch >= 0) {
+                                const double v = static_cast<double>(A.K * (bh * p2 - ah * p1));
+                                gg2[ch] = gg2_mode == 2 ? gg2[ch] + v : v;
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if (!gf) return;
+#pragma unroll
+    for (int j = 0; j < DPW; ++j) {
+        const int dl = wave + j * nw;
+        if (dl < nd && lv)
+            gf[static_cast<int64_t>(b0 + lane) * ldgf + t.d0 + dl] = -A.K * (ld[j] * acc_u[j] - acc_l[j]);
+    }
+}
+
 // ---- transport ----------------------------------------------------------
 // Linearisation at f0: per entry W_dp = K g2 [da (N + 1 - f0_d) + de (N + f0_d)]
 // is stored; 1/tau_d = K sum g2 [da (N + f0_p) + de (N + 1 - f0_p)].

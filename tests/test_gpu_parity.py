@@ -489,6 +489,49 @@ def test_channel_selection_at_build(E, dtype):
     plan.close()
 
 
+@pytest.mark.parametrize("dtype,B", [("f64", 8), ("f64", 70), ("f32", 64), ("f32", 9)])
+def test_batched_vjp(E, dtype, B):
+    """B >= 8 vectors sharing one bath in one reverse pass per 64 vectors:
+    dL/df per column and dL/d|g|^2 summed over the columns match the oracle;
+    overwrite, accumulate, gradient-only and strided (ld > S) forms; repeat
+    calls are bitwise equal."""
+    s = synth.tb_system(kn=24, qn=12, target_states=400)
+    S = s.n_states
+    rng = np.random.default_rng(40 + B)
+    F = np.clip(rng.uniform(0, 1, size=(B, S)), 0, 1)
+    L = rng.normal(size=(B, S))
+    nph = s.nph(300.0)
+    r, tdt, tol = s, torch.float64, TOL64
+    if dtype == "f32":
+        F, L, nph = (a.astype(np.float32).astype(np.float64) for a in (F, L, nph))
+        r, tdt, tol = round32(s), torch.float32, TOL32
+    plan = E.build_channels(s, dtype=dtype, device=0)
+    say(f"batched vjp {dtype} B={B} S={S} Nch={s.n_channels}")
+    # strided operands: rows of a wider buffer
+    Fw = torch.zeros((B, S + 13), dtype=tdt, device="cuda:0")
+    Fw[:, :S] = dev(F, tdt)
+    Lw = torch.zeros((B, S + 5), dtype=tdt, device="cuda:0")
+    Lw[:, :S] = dev(L, tdt)
+    gf, gg = E.collision_vjp(plan, Fw[:, :S], dev(nph, tdt), Lw[:, :S], gg2=True)
+    gf, gg = host(gf), host(gg)
+    rg_sum = 0
+    for b in range(B):
+        rf, rg = oracle.collision_vjp(r, F[b], nph, L[b])
+        assert nerr(gf[b], rf) <= tol, b
+        rg_sum = rg_sum + rg
+    assert nerr(gg, rg_sum) <= tol
+    gf2, gg2 = E.collision_vjp(plan, dev(F, tdt), dev(nph, tdt), dev(L, tdt), gg2=True)
+    assert np.array_equal(host(gf2), gf) and np.array_equal(host(gg2), gg)
+    acc = torch.full((s.n_channels,), 0.25, dtype=torch.float64, device="cuda:0")
+    none, acc = E.collision_vjp(plan, dev(F, tdt), dev(nph, tdt), dev(L, tdt), want_f=False,
+                                gg2=acc, accumulate=True)
+    assert none is None
+    assert nerr(host(acc) - 0.25, rg_sum) <= tol
+    gf3, _ = E.collision_vjp(plan, dev(F, tdt), dev(nph, tdt), dev(L, tdt))
+    assert np.array_equal(host(gf3), gf)
+    plan.close()
+
+
 def test_autograd_function(E):
     from paper_2511_03683_amd.autograd import collision
     s = synth.multiband_system()
