@@ -495,8 +495,9 @@ size_t vjp_batch_lds_bytes(ephbte_plan P, int pt) {
                                                                               : sizeof(StateRec<float>)));
 }
 
-// partners per sub-tile of the batched reverse pass
-int vjp_default_pt(ephbte_plan P) { return P->dtype == EPHBTE_F64 ? 48 : 96; }
+// partners per sub-tile of the batched reverse pass (measured at B = 64 on
+// 2e8 channels: 64 in FP64, 96 in FP32; LDS 68 KB and 52 KB per workgroup)
+int vjp_default_pt(ephbte_plan P) { return P->dtype == EPHBTE_F64 ? 64 : 96; }
 
 // Tiles of the batched reverse pass (at plan build).  Synchronous.
 void upload_vjp_btiles(ephbte_plan P, int pt) {

@@ -1189,6 +1189,10 @@ __global__ void k_sub_offsets(const BTileRec *__restrict__ tiles, const uint32_t
     }
 }
 
+// Entries of one (destination, partner) pair: one per mode, at most 8 modes,
+// no duplicates (both checked at plan build).
+constexpr int kMaxRun = 8;
+
 template <typename T> __device__ __forceinline__ T lane_bcast(T v, int src);
 template <> __device__ __forceinline__ double lane_bcast(double v, int src) {
     const long long bits = __double_as_longlong(v);
@@ -1262,9 +1266,10 @@ __global__ __launch_bounds__(512) void k_fwd_batched(BArgs<T> A, const T *__rest
                         ca = g * (tt + dem);
                         cb = g * (tt + da);
                     }
-                    // sum each run of equal partners into its first lane
+                    // sum each run of equal partners into its first lane (a run is
+                    // one pair over its modes, at most kMaxRun lanes)
 #pragma unroll
-                    for (int off = 1; off < 64; off <<= 1) {
+                    for (int off = 1; off < kMaxRun; off <<= 1) {
                         const T oa = __shfl_down(ca, off, 64);
                         const T ob = __shfl_down(cb, off, 64);
                         const int op = __shfl_down(pl, off, 64);
@@ -1300,6 +1305,32 @@ __global__ __launch_bounds__(512) void k_fwd_batched(BArgs<T> A, const T *__rest
             apply_epi(E, b, d, A.S, A.K * ((T(1) - fd) * acc_b[j] - fd * acc_a[j]));
         }
     }
+}
+
+// Moves v from the lane the DPP control selects (rows of 16 lanes; ROWS masks
+// the rows that receive, the others and lanes without a source get 0).
+template <int CTRL, int ROWS> __device__ __forceinline__ float dpp_mov(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xf, false));
+}
+template <int CTRL, int ROWS> __device__ __forceinline__ double dpp_mov(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b), CTRL, ROWS, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), CTRL, ROWS, 0xf, false);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+
+// Sum over the 64 lanes of a wave, returned to every lane, without LDS:
+// shifts by 1, 2, 4 and 8 lanes inside each row of 16 leave the row's sum in
+// its lane 15; broadcasting lane 15 into the next row (rows 1 and 3) and then
+// lane 31 into rows 2 and 3 leaves the total in lane 63.  Fixed order.
+template <typename T> __device__ __forceinline__ T wave_total(T v) {
+    v += dpp_mov<0x111, 0xf>(v);   // row_shr:1
+    v += dpp_mov<0x112, 0xf>(v);   // row_shr:2
+    v += dpp_mov<0x114, 0xf>(v);   // row_shr:4
+    v += dpp_mov<0x118, 0xf>(v);   // row_shr:8
+    v += dpp_mov<0x142, 0xa>(v);   // row_bcast:15
+    v += dpp_mov<0x143, 0xc>(v);   // row_bcast:31
+    return lane_bcast(v, 63);
 }
 
 // Reverse mode of Eq. 2 for up to 64 vectors sharing one phonon table
@@ -1396,9 +1427,10 @@ __global__ __launch_bounds__(512) void k_vjp_batched(BArgs<T> A, const T *__rest
                         cb = g * bh;
                         if (g_any && pa + pl > d) ch = ent_chan[e];
                     }
-                    // sum each run of equal partners into its first lane
+                    // sum each run of equal partners into its first lane (a run is
+                    // one pair over its modes, at most kMaxRun lanes)
 #pragma unroll
-                    for (int off = 1; off < 64; off <<= 1) {
+                    for (int off = 1; off < kMaxRun; off <<= 1) {
                         const T oa = __shfl_down(ca, off, 64);
                         const T ob = __shfl_down(cb, off, 64);
                         const int op = __shfl_down(pl, off, 64);
@@ -1422,8 +1454,8 @@ __global__ __launch_bounds__(512) void k_vjp_batched(BArgs<T> A, const T *__rest
                         acc_l[j] += fl.b * u;
                         if (g_any && pa + pls > d) {
                             const T dlm = ld[j] - fl.b;
-                            const T p1 = wave_sum(dlm * fd[j] * (T(1) - fl.a));
-                            const T p2 = wave_sum(dlm * fl.a * (T(1) - fd[j]));
+                            const T p1 = wave_total(dlm * fd[j] * (T(1) - fl.a));
+                            const T p2 = wave_total(dlm * fl.a * (T(1) - fd[j]));
                             if (pl == pls && ch >= 0) {
                                 const double v = static_cast<double>(A.K * (bh * p2 - ah * p1));
                                 gg2[ch] = gg2_mode == 2 ? gg2[ch] + v : v;
