@@ -92,6 +92,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--quick", action="store_true", help="smaller system (for a fast check)")
     ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="after the main step run only the B = 64 forward and reverse passes "
+                         "(for tracing the batched kernels)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-channels", type=int, default=100_000_000)
     ap.add_argument("--dtype", choices=("f64", "f32"), default="f64",
@@ -100,8 +103,10 @@ def main():
                     help="also run a plain 1 GiB read + 1 GiB write elementwise kernel "
                          "(hardware-counter calibration)")
     args = ap.parse_args()
-    if args.dtype != "f64" and not args.no_forms:
-        ap.error("--dtype f32 times the main step only; add --no-forms")
+    if args.dtype != "f64" and not (args.no_forms or args.batch_only):
+        ap.error("--dtype f32 times the main step only; add --no-forms or --batch-only")
+    if args.batch_only:
+        args.no_forms = True
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(the destination-sharded design is described in DESIGN.md)", file=sys.stderr)
@@ -189,6 +194,21 @@ def main():
         f"(wall {wall:.2f}s for {args.steps})")
 
     forms = {}
+    if args.batch_only:
+        B = 64
+        tuned = E.autotune(plan64, B)
+        F = tens(synth.batch_occupations(s), mdt)
+        IB = torch.empty_like(F)
+        msb, _ = timed(lambda: E.collision_integral(plan64, F, n64, out=IB), args.steps, 1)
+        LB = tens(rng.normal(size=(B, s.n_states)), mdt)
+        ggb = torch.zeros(nch, dtype=torch.float64, device=dev)
+        msbv, _ = timed(lambda: E.collision_vjp(plan64, F, n64, LB, want_f=True, gg2=ggb), args.steps, 1)
+        forms[f"fwd_{args.dtype}_b64"] = dict(ms=msb, per_vector_channels_per_s=B * nch / (msb * 1e-3),
+                                              batch_partners=tuned["batch_partners"])
+        forms[f"vjp_{args.dtype}_b64"] = dict(ms=msbv, per_vector_channels_per_s=B * nch / (msbv * 1e-3))
+        log(f"B=64 {args.dtype}: forward {msb:.3f} ms, reverse {msbv:.3f} ms")
+        del F, IB, LB, ggb
+
     if not args.no_forms:
         forms["fwd_f64_b1"] = dict(ms=ms, channels_per_s=value, algorithmic_GBps=achieved,
                                    layout="single copy")

@@ -111,16 +111,23 @@ typedef struct {
     int32_t reserved[2];       /* must be 0                                        */
 } ephbte_tuning;
 
-/* Channel selection applied at build (paper: scattering-channel paragraph
+/* Build options.  Channel selection (paper: scattering-channel paragraph
  * after Eq. 2: approximate energy conservation with the Gaussian delta and a
- * cutoff on |g|).  Zero-initialised options keep every channel. */
+ * cutoff on |g|) and elastic mechanisms (paper, Discussion: other scattering
+ * mechanisms, such as defects, on the same data structure).  Zero-initialised
+ * options keep every channel and treat every mode as a phonon. */
 typedef struct {
     double energy_nsigma;      /* > 0: keep channel (i, j, nu) only if
                                   min(|D + hw|, |D - hw|) < energy_nsigma * sigma,
                                   D = eps_i - eps_j, hw = hw(q = k_j - k_i, nu)
                                   (FP64); 0 = no energy cut                     */
     double g2_min;             /* keep a channel only if |g|^2 >= g2_min; 0 = all */
-    int32_t reserved[4];       /* must be 0                                        */
+    uint32_t elastic_modes;    /* bit nu set: mode nu is an elastic mechanism (e-defect
+                                  scattering on the same channel list): its hw must
+                                  be 0 at every q, and the caller passes N = 0 for
+                                  it, so that Eq. 2 reduces to the elastic golden
+                                  rule K |g|^2 G(eps_i - eps_j) (f_j - f_i)         */
+    int32_t reserved[3];       /* must be 0                                        */
 } ephbte_build_opts;
 
 /*
@@ -130,8 +137,9 @@ typedef struct {
  * one entry per destination state, entries are sorted by destination and then
  * by (partner, mode), and the structure-of-arrays layout is copied to the
  * device once.  Fails with INVALID_ARGUMENT on: null pointers, indices out of
- * range, i == j, a pair not commensurate with the q grid, a channel whose
- * phonon energy is below 1e-6 eV in either orientation (its N diverges),
+ * range, i == j, a pair not commensurate with the q grid, a channel of a
+ * phonon mode whose energy is below 1e-6 eV in either orientation (its N
+ * diverges; elastic modes excepted, whose hw must be 0),
  * duplicate (i, j, nu) channels, non-finite or negative hw/g2/eps, sigma or
  * n_q_norm <= 0, and options out of range.  Every channel is validated; the
  * selection of opts (NULL: none) then removes channels, and the plan computes

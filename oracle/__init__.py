@@ -10,6 +10,9 @@ Contents, each following the paper (arXiv 2511.03683):
 * select_channels(sys, ...)     -- the channel selection that precedes the
   list (scattering-channel paragraph after Eq. 2: approximate energy
   conservation with the Gaussian delta, a cutoff on |g|), as a keep mask.
+* collision_elastic(sys, f)     -- the elastic (e-defect) golden rule over
+  the channels of given mechanisms (Discussion: other scattering mechanisms
+  on the same data structure), written out in numpy.
 * collision(sys, f, nph)        -- Eq. 2 over a channel list (Results,
   "Collision integral ..."; the channel-list loop is the Baseline-CPU loop
   shape of "Reference CPU algorithm", run sequentially).
@@ -179,6 +182,31 @@ def collision_vjp(sys, f, nph, lam, g2=None, want_f=True, want_g2=True):
     gg = np.zeros(a.ci.size) if want_g2 else None
     _lib().orc_collision_vjp(*a.common(), _ptr(f), _ptr(lam), _ptr(gf), _ptr(gg))
     return gf, gg
+
+
+def collision_elastic(sys, f, modes=None, g2=None):
+    """Elastic collision integral [S] in FP64 over the channels whose mode is
+    in modes (all when None).  A static perturbation (a defect) moves an
+    electron between states of equal energy with no phonon: by Fermi's golden
+    rule the rate is C |g|^2 G(e_i - e_j) with C = 2 pi / (hbar N_q) and G the
+    normalised Gaussian of width sigma, and the Pauli factors leave f_j - f_i.
+    Each channel adds its term to I_i and subtracts it from I_j."""
+    ci = np.asarray(sys.ch_i, np.int64)
+    cj = np.asarray(sys.ch_j, np.int64)
+    g = np.asarray(sys.g2 if g2 is None else g2, np.float64)
+    if modes is not None:
+        sel = np.isin(np.asarray(sys.ch_nu), np.asarray(modes))
+        ci, cj, g = ci[sel], cj[sel], g[sel]
+    eps = np.asarray(sys.eps, np.float64)
+    f = np.asarray(f, np.float64)
+    sig = float(sys.sigma)
+    d = eps[ci] - eps[cj]
+    G = np.exp(-0.5 * (d / sig) ** 2) / (sig * np.sqrt(2.0 * np.pi))
+    X = 2.0 * np.pi / (HBAR_EV_FS * float(sys.n_q_norm)) * g * G * (f[cj] - f[ci])
+    I = np.zeros(int(sys.n_states))
+    np.add.at(I, ci, X)
+    np.add.at(I, cj, -X)
+    return I
 
 
 def collision_brute(sys, f, nph):

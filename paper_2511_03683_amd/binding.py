@@ -41,7 +41,7 @@ class Problem(ctypes.Structure):
 
 class BuildOpts(ctypes.Structure):
     _fields_ = [("energy_nsigma", ctypes.c_double), ("g2_min", ctypes.c_double),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("elastic_modes", ctypes.c_uint32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class Tuning(ctypes.Structure):
@@ -227,20 +227,22 @@ def _batch(plan, t, name):
 
 
 # ---------------------------------------------------------------- entry points
-def _opts(energy_nsigma: float, g2_min: float):
-    """BuildOpts pointer, or None (keep every channel) when both are 0."""
-    if not energy_nsigma and not g2_min:
+def _opts(energy_nsigma: float, g2_min: float, elastic_modes: int = 0):
+    """BuildOpts pointer, or None (defaults) when every option is 0."""
+    if not energy_nsigma and not g2_min and not elastic_modes:
         return None
     o = BuildOpts()
     o.energy_nsigma = float(energy_nsigma)
     o.g2_min = float(g2_min)
+    o.elastic_modes = int(elastic_modes)
     return ctypes.byref(o)
 
 
 def build_channels(system, dtype="f64", device: Optional[int] = None,
-                   energy_nsigma: float = 0.0, g2_min: float = 0.0) -> Plan:
+                   energy_nsigma: float = 0.0, g2_min: float = 0.0, elastic_modes: int = 0) -> Plan:
     """Build the device channel layout of a problem (see ephbte_build_channels).
-    energy_nsigma > 0 and g2_min > 0 select channels (ephbte_build_opts)."""
+    energy_nsigma > 0 and g2_min > 0 select channels; elastic_modes is the bit
+    mask of elastic (hw = 0, N = 0) mechanisms (ephbte_build_opts)."""
     lib = load_library()
     code = _dtype_code(dtype)
     if device is None:
@@ -248,13 +250,13 @@ def build_channels(system, dtype="f64", device: Optional[int] = None,
         device = torch.cuda.current_device()
     pr, keep = _problem(system, code, device)
     h = ctypes.c_void_p()
-    _check(lib.ephbte_build_channels(ctypes.byref(pr), _opts(energy_nsigma, g2_min),
+    _check(lib.ephbte_build_channels(ctypes.byref(pr), _opts(energy_nsigma, g2_min, elastic_modes),
                                      ctypes.byref(h)), "build_channels")
     del keep
     return Plan(h.value, system, code, device)
 
 
-def layout_host(system, energy_nsigma: float = 0.0, g2_min: float = 0.0):
+def layout_host(system, energy_nsigma: float = 0.0, g2_min: float = 0.0, elastic_modes: int = 0):
     """Host-only layout view: (row_ptr, partner, mode, channel) numpy arrays
     over the channels the selection keeps."""
     lib = load_library()
@@ -264,7 +266,7 @@ def layout_host(system, energy_nsigma: float = 0.0, g2_min: float = 0.0):
     partner = np.zeros(E, np.int32)
     mode = np.zeros(E, np.int8)
     chan = np.zeros(E, np.int32)
-    _check(lib.ephbte_layout_host(ctypes.byref(pr), _opts(energy_nsigma, g2_min),
+    _check(lib.ephbte_layout_host(ctypes.byref(pr), _opts(energy_nsigma, g2_min, elastic_modes),
                                   row_ptr.ctypes.data, partner.ctypes.data, mode.ctypes.data,
                                   chan.ctypes.data), "layout_host")
     del keep

@@ -59,9 +59,11 @@ ephbte_status build_host_layout(const ephbte_problem *p, const ephbte_build_opts
     };
     if (!p) return bad("problem is NULL");
     double e_nsig = 0.0, g2_min = 0.0;
+    uint32_t elastic = 0;
     if (opts) {
         e_nsig = opts->energy_nsigma;
         g2_min = opts->g2_min;
+        elastic = opts->elastic_modes;
         if (!std::isfinite(e_nsig) || e_nsig < 0.0) return bad("energy_nsigma must be finite and >= 0");
         if (!std::isfinite(g2_min) || g2_min < 0.0) return bad("g2_min must be finite and >= 0");
         for (int32_t x : opts->reserved)
@@ -95,8 +97,11 @@ ephbte_status build_host_layout(const ephbte_problem *p, const ephbte_build_opts
     }
     if (nk >= (int64_t(1) << 31)) return bad("k grid has too many points");
     const int nm = p->n_modes;
-    for (int64_t x = 0; x < nq * nm; ++x)
+    if (elastic >> nm) return bad("elastic_modes names a mode >= n_modes");
+    for (int64_t x = 0; x < nq * nm; ++x) {
         if (!std::isfinite(p->hw[x]) || p->hw[x] < 0.0) return bad("hw must be finite and >= 0");
+        if (((elastic >> (x % nm)) & 1u) && p->hw[x] != 0.0) return bad("hw of an elastic mode must be 0");
+    }
     // both orientations of a channel use their own q (q and -q); the two
     // contributions cancel exactly only for tables even in q
     for (int32_t a0 = 0; a0 < p->qgrid[0]; ++a0)
@@ -164,7 +169,7 @@ ephbte_status build_host_layout(const ephbte_problem *p, const ephbte_build_opts
             else {
                 int64_t q1 = q_of(i, j), q2 = q_of(j, i);
                 if (q1 < 0 || q2 < 0) m = "k_j - k_i is not a q-grid vector";
-                else if (p->hw[q1 * nm + nu] < 1e-6 || p->hw[q2 * nm + nu] < 1e-6)
+                else if (!((elastic >> nu) & 1u) && (p->hw[q1 * nm + nu] < 1e-6 || p->hw[q2 * nm + nu] < 1e-6))
                     m = "phonon energy below 1e-6 eV (divergent occupation)";
                 else {
                     const double dl = p->eps[i] - p->eps[j], w = p->hw[q1 * nm + nu];

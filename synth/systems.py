@@ -322,6 +322,36 @@ def two_state_system(dE=0.05, hw=0.05, g2=2e-3, sigma=0.004, nq=2) -> System:
                   sigma=sigma, n_q_norm=float(nq))
 
 
+def defect_system(n=6, with_phonons=True, defect_median=2e-3, seed=2511) -> System:
+    """Parabolic band on an n^3 grid with one elastic (e-defect) mechanism as
+    an extra mode of zero energy: every pair of states is coupled through it,
+    |g|^2 lognormal with median defect_median.  With with_phonons the phonon
+    channels of parabolic_system(n) are kept beside it.  The elastic mode is
+    the last one (bit n_modes - 1 of the elastic mask); nph(T) gives it N = 0."""
+    base = parabolic_system(n, seed=seed)
+    S = base.n_states
+    hw = np.concatenate([base.hw, np.zeros((base.hw.shape[0], 1))], axis=1)
+    nu_e = hw.shape[1] - 1
+    ii, jj = np.triu_indices(S, 1)
+    ii, jj = ii.astype(np.int32), jj.astype(np.int32)
+    nu = np.full(ii.size, nu_e, np.int8)
+    g2 = lognormal_g2(ii, jj, nu, seed + 17, median=defect_median)
+    if with_phonons:
+        ci = np.concatenate([base.ch_i, ii])
+        cj = np.concatenate([base.ch_j, jj])
+        cn = np.concatenate([base.ch_nu, nu])
+        cg = np.concatenate([base.g2, g2])
+        order = np.lexsort((cn, cj, ci))
+        ci, cj, cn, cg = ci[order], cj[order], cn[order], cg[order]
+    else:
+        ci, cj, cn, cg = ii, jj, nu, g2
+    return System(name=f"defect{n}", kgrid=base.kgrid, qgrid=base.qgrid, state_k=base.state_k,
+                  state_band=base.state_band, eps=base.eps, n_modes=hw.shape[1], hw=hw,
+                  ch_i=ci.astype(np.int32), ch_j=cj.astype(np.int32), ch_nu=cn.astype(np.int8),
+                  g2=cg, sigma=base.sigma, n_q_norm=base.n_q_norm, lattice_a=base.lattice_a,
+                  vel=base.vel, meta=dict(base.meta, elastic_mode=nu_e))
+
+
 def ladder_system(n_rungs=6, per_rung=8, hw_e=0.050, sigma=0.002, seed=7) -> System:
     """Resonant ladder: state energies sit exactly on rungs n*hw_e, one
     dispersionless mode of energy hw_e, and channels only between adjacent rungs.

@@ -128,6 +128,36 @@ def test_selection_of_every_channel_and_option_errors():
     assert "reserved" in E.last_error()
 
 
+def test_elastic_modes_option():
+    """hw = 0 is accepted only for modes flagged elastic, which must be 0 at
+    every q; the flagged channels are laid out like any other."""
+    s = synth.defect_system(4, with_phonons=True)
+    e = s.meta["elastic_mode"]
+    with pytest.raises(E.EphbteError, match="below 1e-6"):
+        E.layout_host(s)
+    rp, partner, mode, chan = E.layout_host(s, elastic_modes=1 << e)
+    assert rp[-1] == 2 * s.n_channels
+    assert np.array_equal(np.sort(np.unique(chan)), np.arange(s.n_channels))
+    with pytest.raises(E.EphbteError, match="n_modes"):
+        E.layout_host(s, elastic_modes=1 << s.n_modes)
+    hw = s.hw.copy()
+    hw[3, e] = 1e-3
+    s2 = _mutate_sys(s, hw=hw)
+    with pytest.raises(E.EphbteError, match="elastic mode must be 0"):
+        E.layout_host(s2, elastic_modes=1 << e)
+    # a phonon mode flagged elastic has nonzero energies
+    with pytest.raises(E.EphbteError, match="elastic mode must be 0"):
+        E.layout_host(s, elastic_modes=(1 << e) | 1)
+
+
+def _mutate_sys(s, **kw):
+    import copy
+    r = copy.copy(s)
+    for k, v in kw.items():
+        setattr(r, k, v)
+    return r
+
+
 def _bad(system, match):
     with pytest.raises(E.EphbteError, match=match) as ei:
         E.layout_host(system)

@@ -532,6 +532,39 @@ def test_batched_vjp(E, dtype, B):
     plan.close()
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_elastic_mechanism(E, dtype):
+    """A defect mechanism flagged elastic (hw = 0, N = 0) beside three phonon
+    modes: forward and reverse passes match Eq. 2 in the oracle, and the
+    elastic part alone matches the oracle's elastic golden rule."""
+    s = synth.defect_system(6, with_phonons=True)
+    e = s.meta["elastic_mode"]
+    f = synth.random_occupations(s, 14)
+    nph = s.nph(300.0)
+    lam = np.random.default_rng(9).normal(size=s.n_states)
+    r, tdt, tol = s, torch.float64, TOL64
+    if dtype == "f32":
+        f, nph, lam = (a.astype(np.float32).astype(np.float64) for a in (f, nph, lam))
+        r, tdt, tol = round32(s), torch.float32, TOL32
+    say(f"elastic mechanism {dtype} S={s.n_states} Nch={s.n_channels}")
+    plan = E.build_channels(s, dtype=dtype, device=0, elastic_modes=1 << e)
+    I = host(E.collision_integral(plan, dev(f, tdt), dev(nph, tdt)))
+    ref = oracle.collision(r, f, nph)
+    rin, rout = oracle.collision_inout(r, f, nph)
+    scale = max(np.abs(ref).max(), 1e-2 * max(rin.max(), rout.max()))
+    assert nerr(I, ref, scale) <= tol
+    gf, gg = E.collision_vjp(plan, dev(f, tdt), dev(nph, tdt), dev(lam, tdt), gg2=True)
+    rf, rg = oracle.collision_vjp(r, f, nph, lam)
+    assert nerr(host(gf), rf) <= tol and nerr(host(gg), rg) <= tol
+    plan.close()
+    el = oracle.subset(s, np.asarray(s.ch_nu) == e)
+    plan = E.build_channels(el, dtype=dtype, device=0, elastic_modes=1 << e)
+    I = host(E.collision_integral(plan, dev(f, tdt), dev(nph, tdt)))
+    ref = oracle.collision_elastic(round32(el) if dtype == "f32" else el, f)
+    assert nerr(I, ref) <= tol
+    plan.close()
+
+
 def test_autograd_function(E):
     from paper_2511_03683_amd.autograd import collision
     s = synth.multiband_system()

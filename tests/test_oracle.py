@@ -192,6 +192,58 @@ def test_selection_changes_I_by_at_most_the_dropped_tails(c1, nsig, g2min):
     assert np.abs(diff).max() > 0
 
 
+# ------------------------------------------------------- elastic mechanism
+def test_elastic_two_state_by_hand():
+    """One defect channel between states 10 meV apart: I_1 = C |g|^2 G(-0.01)
+    (f_2 - f_1), I_2 = -I_1, with C = 2 pi / (hbar N_q); Eq. 2 at hw = 0 and
+    N = 0 gives the same numbers."""
+    sig, g2, nq = 0.008, 3e-3, 2
+    s = synth.two_state_system(dE=0.01, hw=0.0, g2=g2, sigma=sig, nq=nq)
+    f = np.array([0.8, 0.3])
+    C = 2 * math.pi / (HBAR * nq)
+    expect = C * g2 * _G(-0.01, sig) * (0.3 - 0.8)
+    I = oracle.collision_elastic(s, f)
+    assert I[0] == pytest.approx(expect, rel=1e-14)
+    assert I[1] == pytest.approx(-expect, rel=1e-14)
+    I2 = oracle.collision(s, f, np.zeros((nq, 1)))
+    assert np.allclose(I2, I, rtol=1e-14, atol=0)
+
+
+def test_elastic_is_eq2_without_phonons():
+    """On every channel of a defect system, Eq. 2 (the C loop) with hw = 0 and
+    N = 0 equals the numpy elastic form, and the phonon channels beside it add
+    on top."""
+    s = synth.defect_system(4, with_phonons=True)
+    f = synth.random_occupations(s, 12)
+    nph = s.nph(300.0)
+    e = s.meta["elastic_mode"]
+    I_el = oracle.collision_elastic(s, f, modes=[e])
+    sub = oracle.subset(s, np.asarray(s.ch_nu) == e)
+    I_eq2 = oracle.collision(sub, f, nph)
+    assert np.abs(I_eq2 - I_el).max() <= 1e-14 * np.abs(I_el).max()
+    ph = oracle.subset(s, np.asarray(s.ch_nu) != e)
+    I_all = oracle.collision(s, f, nph)
+    assert np.abs(I_all - (I_el + oracle.collision(ph, f, nph))).max() <= 1e-13 * np.abs(I_all).max()
+
+
+def test_elastic_dissipation_identity():
+    """The elastic operator is symmetric and dissipative: sum_d f_d I_d =
+    -sum_c C |g|^2 G (f_i - f_j)^2 <= 0; constants are its null space and
+    particle number is conserved."""
+    s = synth.defect_system(4, with_phonons=False)
+    f = synth.random_occupations(s, 3)
+    I = oracle.collision_elastic(s, f)
+    i, j = s.ch_i, s.ch_j
+    d = s.eps[i] - s.eps[j]
+    G = np.exp(-0.5 * (d / s.sigma) ** 2) / (s.sigma * math.sqrt(2 * math.pi))
+    C = 2 * math.pi / (HBAR * s.n_q_norm)
+    q = -np.sum(C * s.g2 * G * (f[i] - f[j]) ** 2)
+    assert q < 0
+    assert float(f @ I) == pytest.approx(q, rel=1e-12)
+    assert abs(I.sum()) <= 1e-13 * np.abs(I).max()
+    assert np.abs(oracle.collision_elastic(s, np.full(s.n_states, 0.37))).max() == 0.0
+
+
 # --------------------------------------------------------------- derivatives
 def test_vjp_matches_central_differences():
     """I is quadratic in f and linear in |g|^2, so central differences are exact
