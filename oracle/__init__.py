@@ -19,6 +19,9 @@ Contents, each following the paper (arXiv 2511.03683):
 * collision_brute(sys, f, nph)  -- Eq. 2 written out over the full q grid,
   all bands and modes, for tiny grids (numpy; independent of the C code).
 * collision_vjp(...)            -- hand-derived reverse mode of Eq. 2.
+* drift(sys, f, rates)          -- the field term of Eq. 1, -(1/hbar) F . grad_k f,
+  by central differences on the k grid (the discretisation is a reading:
+  the paper defers it to its Methods), and its transpose.
 * rk4_step / rk4_adjoint_step   -- classical RK4 for df/dt = I[f] (the
   paper's real-time BTE; the integrator is not named in the text, RK4 is the
   reading adopted here) and its exact discrete adjoint.
@@ -253,12 +256,70 @@ def collision_brute(sys, f, nph):
 
 
 # ---------------------------------------------------------------------------
+# field term of Eq. 1 (drift in k space)
+# ---------------------------------------------------------------------------
+def drift_neighbors(sys):
+    """[S, 3, 2] index of the state of the same band one k-grid step above
+    (column 0) and below (column 1) along each axis, periodic over the grid;
+    -1 when that state is not in the list (outside the energy window)."""
+    kg = np.asarray(sys.kgrid, np.int64)
+    k = np.asarray(sys.state_k, np.int64)
+    band = np.asarray(sys.state_band, np.int64)
+    c = np.stack([k // (kg[1] * kg[2]), (k // kg[2]) % kg[1], k % kg[2]], axis=1)
+    where = {}
+    for s in range(k.size):
+        key = (int(k[s]), int(band[s]))
+        assert key not in where, "two states share (k, band)"
+        where[key] = s
+    nbr = np.full((k.size, 3, 2), -1, np.int64)
+    for s in range(k.size):
+        for a in range(3):
+            for col, step in ((0, 1), (1, -1)):
+                cc = c[s].copy()
+                cc[a] = (cc[a] + step) % kg[a]
+                kk = int((cc[0] * kg[1] + cc[1]) * kg[2] + cc[2])
+                nbr[s, a, col] = where.get((kk, int(band[s])), -1)
+    return nbr
+
+
+def drift(sys, f, rates, nbr=None):
+    """Field term of Eq. 1, -(1/hbar) F . grad_k f, with the derivative along
+    axis a taken as the central difference (f(k + dk_a) - f(k - dk_a)) /
+    (2 dk_a) inside the state's band: D_s = -sum_a r_a (f_up - f_down) / 2,
+    r_a = F_a / (hbar dk_a) in 1/fs.  A neighbour outside the list has f = 0."""
+    nbr = drift_neighbors(sys) if nbr is None else nbr
+    f = np.asarray(f, np.float64)
+    fx = np.concatenate([f, [0.0]])          # index -1 reads the appended 0
+    D = np.zeros(f.size)
+    for a in range(3):
+        D -= float(rates[a]) * 0.5 * (fx[nbr[:, a, 0]] - fx[nbr[:, a, 1]])
+    return D
+
+
+def drift_transpose(sys, lam, rates, nbr=None):
+    """D^T lam, by scattering each row of D: row s has -r_a/2 in the column of
+    its upper neighbour and +r_a/2 in the column of its lower one."""
+    nbr = drift_neighbors(sys) if nbr is None else nbr
+    lam = np.asarray(lam, np.float64)
+    out = np.zeros(lam.size + 1)             # slot -1 collects missing neighbours
+    for a in range(3):
+        np.add.at(out, nbr[:, a, 0], -0.5 * float(rates[a]) * lam)
+        np.add.at(out, nbr[:, a, 1], 0.5 * float(rates[a]) * lam)
+    return out[:-1]
+
+
+# ---------------------------------------------------------------------------
 # real-time BTE: classical RK4 and its discrete adjoint
 # ---------------------------------------------------------------------------
-def rk4_step(sys, f, nph, dt, g2=None, return_stages=False):
-    """One classical fourth-order Runge-Kutta step of df/dt = I[f]."""
+def rk4_step(sys, f, nph, dt, g2=None, return_stages=False, rates=None, nbr=None):
+    """One classical fourth-order Runge-Kutta step of df/dt = I[f] (+ the
+    drift term of Eq. 1 when rates is given)."""
     a = _Args(sys, nph, g2)
-    I = lambda u: collision(sys, u, nph, args=a)
+    if rates is None:
+        I = lambda u: collision(sys, u, nph, args=a)
+    else:
+        nbr = drift_neighbors(sys) if nbr is None else nbr
+        I = lambda u: collision(sys, u, nph, args=a) + drift(sys, u, rates, nbr)
     u1 = np.array(f, dtype=np.float64)
     k1 = I(u1)
     u2 = u1 + 0.5 * dt * k1
@@ -271,11 +332,19 @@ def rk4_step(sys, f, nph, dt, g2=None, return_stages=False):
     return (out, (u1, u2, u3, u4)) if return_stages else out
 
 
-def rk4_adjoint_step(sys, stages, nph, dt, gbar, g2=None):
+def rk4_adjoint_step(sys, stages, nph, dt, gbar, g2=None, rates=None, nbr=None):
     """Reverse of one RK4 step.  Given gbar = dL/df_{n+1} and the stage inputs
-    (u1..u4) of the step, return (dL/df_n, dL/dg2 contribution of the step)."""
+    (u1..u4) of the step, return (dL/df_n, dL/dg2 contribution of the step).
+    With rates, each stage's transposed Jacobian also holds D^T."""
     u1, u2, u3, u4 = stages
-    vjp = lambda u, lam: collision_vjp(sys, u, nph, lam, g2=g2)
+    if rates is None:
+        vjp = lambda u, lam: collision_vjp(sys, u, nph, lam, g2=g2)
+    else:
+        nbr = drift_neighbors(sys) if nbr is None else nbr
+
+        def vjp(u, lam):
+            gf, gg = collision_vjp(sys, u, nph, lam, g2=g2)
+            return gf + drift_transpose(sys, lam, rates, nbr), gg
     kb4 = (dt / 6.0) * gbar
     ub4, gg4 = vjp(u4, kb4)
     kb3 = (dt / 3.0) * gbar + dt * ub4
@@ -287,17 +356,18 @@ def rk4_adjoint_step(sys, stages, nph, dt, gbar, g2=None):
     return gbar + ub1 + ub2 + ub3 + ub4, gg1 + gg2_ + gg3 + gg4
 
 
-def rk4_trajectory_grad(sys, f0, nph, dt, n_steps, gT, g2=None):
+def rk4_trajectory_grad(sys, f0, nph, dt, n_steps, gT, g2=None, rates=None):
     """Gradients of L(f_T) through n_steps RK4 steps, storing every stage."""
+    nbr = None if rates is None else drift_neighbors(sys)
     f = np.array(f0, dtype=np.float64)
     stages = []
     for _ in range(n_steps):
-        f, st = rk4_step(sys, f, nph, dt, g2=g2, return_stages=True)
+        f, st = rk4_step(sys, f, nph, dt, g2=g2, return_stages=True, rates=rates, nbr=nbr)
         stages.append(st)
     g = np.array(gT, dtype=np.float64)
     gg = np.zeros(sys.n_channels)
     for st in reversed(stages):
-        g, dg = rk4_adjoint_step(sys, st, nph, dt, g, g2=g2)
+        g, dg = rk4_adjoint_step(sys, st, nph, dt, g, g2=g2, rates=rates, nbr=nbr)
         gg += dg
     return f, g, gg
 

@@ -322,6 +322,16 @@ def two_state_system(dE=0.05, hw=0.05, g2=2e-3, sigma=0.004, nq=2) -> System:
                   sigma=sigma, n_q_norm=float(nq))
 
 
+def field_drift_rates(E_V_per_m, kgrid, a=LATTICE_A, charge=-1.0) -> np.ndarray:
+    """Per-axis drift rates r_a = F_a / (hbar dk_a) in 1/fs for an electric field
+    E (V/m) on a simple-cubic k grid of lattice constant a (Angstrom):
+    F = charge * e * E in eV/Angstrom, dk_a = 2 pi / (a N_a) in 1/Angstrom."""
+    E = np.asarray(E_V_per_m, np.float64)
+    F = charge * E * 1e-10
+    dk = 2.0 * math.pi / (a * np.asarray(kgrid, np.float64))
+    return F / (HBAR_EV_FS * dk)
+
+
 def defect_system(n=6, with_phonons=True, defect_median=2e-3, seed=2511) -> System:
     """Parabolic band on an n^3 grid with one elastic (e-defect) mechanism as
     an extra mode of zero energy: every pair of states is coupled through it,

@@ -244,6 +244,119 @@ def test_elastic_dissipation_identity():
     assert np.abs(oracle.collision_elastic(s, np.full(s.n_states, 0.37))).max() == 0.0
 
 
+# ------------------------------------------------------ drift term (Eq. 1)
+def _ring(n=16, with_channels=False):
+    """One band on an n x 1 x 1 periodic grid, every state present."""
+    s = synth.parabolic_system(4)
+    import copy
+    r = copy.copy(s)
+    r.kgrid = r.qgrid = (n, 1, 1)
+    r.state_k = np.arange(n, dtype=np.int32)
+    r.state_band = np.zeros(n, np.int8)
+    r.eps = 0.01 * np.arange(n, dtype=np.float64)
+    r.hw = np.full((n, 1), 0.03)
+    r.n_modes = 1
+    r.ch_i = np.zeros(0, np.int32)
+    r.ch_j = np.zeros(0, np.int32)
+    r.ch_nu = np.zeros(0, np.int8)
+    r.g2 = np.zeros(0)
+    r.n_q_norm = float(n)
+    return r
+
+
+def test_drift_plane_wave_closed_form():
+    """On a full periodic grid cos(theta c_x) is an eigenvector pair of the
+    central difference: D = r_x sin(theta) sin(theta c_x) for each state."""
+    s = synth.parabolic_system(8)
+    c = synth.grid_coords(s.kgrid)[s.state_k]
+    th = 2 * math.pi * 3 / 8
+    f = np.cos(th * c[:, 0])
+    r = np.array([0.21, -0.4, 0.05])
+    D = oracle.drift(s, f, r)
+    assert np.allclose(D, r[0] * math.sin(th) * np.sin(th * c[:, 0]), rtol=0, atol=1e-15)
+    g = 0.3 + 0.2 * np.cos(2 * math.pi * c[:, 1] / 8) - 0.1 * np.sin(2 * math.pi * 2 * c[:, 2] / 8)
+    Dg = oracle.drift(s, g, r)
+    ty, tz = 2 * math.pi / 8, 2 * math.pi * 2 / 8
+    expect = (r[1] * 0.2 * math.sin(ty) * np.sin(ty * c[:, 1])
+              + r[2] * 0.1 * math.sin(tz) * np.cos(tz * c[:, 2]))
+    assert np.allclose(Dg, expect, rtol=0, atol=1e-15)
+
+
+def test_drift_window_edge_and_transpose():
+    """A neighbour outside the window counts as f = 0; with the neighbour
+    relation symmetric the operator is antisymmetric (D^T = -D), and on the
+    full periodic grid it conserves particle number."""
+    s = synth.multiband_system()
+    f = synth.random_occupations(s, 2)
+    lam = np.random.default_rng(1).normal(size=s.n_states)
+    r = np.array([0.3, -0.2, 0.1])
+    nbr = oracle.drift_neighbors(s)
+    assert (nbr < 0).any() and (nbr >= 0).any()
+    D = oracle.drift(s, f, r, nbr)
+    # the same states inside a full grid (every k of every band), the added
+    # states empty: no neighbour is missing there, and D must not change
+    import copy
+    nb = int(s.state_band.max()) + 1
+    nk = int(np.prod(s.kgrid))
+    full = copy.copy(s)
+    full.state_k = np.repeat(np.arange(nk, dtype=np.int32), nb)
+    full.state_band = np.tile(np.arange(nb, dtype=np.int8), nk)
+    pos = {(int(k), int(b)): i for i, (k, b) in enumerate(zip(full.state_k, full.state_band))}
+    idx = np.array([pos[(int(k), int(b))] for k, b in zip(s.state_k, s.state_band)])
+    ff = np.zeros(nk * nb)
+    ff[idx] = f
+    assert (oracle.drift_neighbors(full) >= 0).all()
+    assert np.allclose(oracle.drift(full, ff, r)[idx], D, rtol=0, atol=1e-15)
+    assert np.allclose(oracle.drift_transpose(s, lam, r, nbr), -oracle.drift(s, lam, r, nbr),
+                       rtol=0, atol=1e-15)
+    assert float(lam @ D) == pytest.approx(float(oracle.drift_transpose(s, lam, r, nbr) @ f), rel=1e-12)
+    full = synth.parabolic_system(6)
+    Df = oracle.drift(full, synth.random_occupations(full, 4), r)
+    assert abs(Df.sum()) <= 1e-14 * np.abs(Df).max()
+
+
+def test_rk4_pure_drift_amplification():
+    """No channels, a periodic ring: a plane wave e^{i theta c} has drift
+    eigenvalue -i r sin(theta), so one RK4 step multiplies it by the stability
+    polynomial of z = -i r sin(theta) dt."""
+    n, r, dt = 16, 0.35, 0.8
+    s = _ring(n)
+    c = np.arange(n)
+    th = 2 * math.pi * 5 / n
+    z = -1j * r * math.sin(th) * dt
+    P = 1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24
+    f = np.cos(th * c)
+    out = oracle.rk4_step(s, f, np.zeros((n, 1)), dt, rates=[r, 0.0, 0.0])
+    assert np.allclose(out, (P * np.exp(1j * th * c)).real, rtol=0, atol=1e-15)
+
+
+def test_rk4_adjoint_with_drift_matches_finite_differences():
+    """Discrete adjoint through RK4 steps with collisions and drift: dL/df0
+    and dL/d|g|^2 against central differences (L linear in f_T, the map
+    quadratic per stage: differences with a small step are accurate to 1e-7)."""
+    s = synth.multiband_system()
+    f0 = synth.random_occupations(s, 6) * 0.5
+    nph = s.nph(300.0)
+    r = np.array([0.02, -0.015, 0.01])
+    gT = np.random.default_rng(3).normal(size=s.n_states)
+    dt, n = 2.0, 3
+    fT, gf, gg = oracle.rk4_trajectory_grad(s, f0, nph, dt, n, gT, rates=r)
+    L = lambda ff, g2=None: float(gT @ _roll(s, ff, nph, dt, n, r, g2))
+    v = np.random.default_rng(4).normal(size=s.n_states)
+    h = 1e-4
+    fd = (L(f0 + h * v) - L(f0 - h * v)) / (2 * h)
+    assert fd == pytest.approx(float(gf @ v), rel=1e-7)
+    w = np.random.default_rng(5).normal(size=s.n_channels) * s.g2
+    fd2 = (L(f0, s.g2 + h * w) - L(f0, s.g2 - h * w)) / (2 * h)
+    assert fd2 == pytest.approx(float(gg @ w), rel=1e-7)
+
+
+def _roll(s, f, nph, dt, n, r, g2):
+    for _ in range(n):
+        f = oracle.rk4_step(s, f, nph, dt, g2=g2, rates=r)
+    return f
+
+
 # --------------------------------------------------------------- derivatives
 def test_vjp_matches_central_differences():
     """I is quadratic in f and linear in |g|^2, so central differences are exact
