@@ -76,6 +76,10 @@ typedef struct ephbte_plan_s *ephbte_plan;
 typedef struct {
     int32_t n_states;          /* S >= 1, S < 2^29                                  */
     const int32_t *state_k;    /* [S] linear k index of each state                 */
+    const int8_t *state_band;  /* [S] band of each state, or NULL (all band 0); only
+                                  the field term uses it, to find a state's
+                                  neighbours in its own band, and only where each
+                                  (k, band) is held by one state                    */
     const double *eps;         /* [S] state energies (eV)                          */
     int32_t kgrid[3];          /* electron grid (N0,N1,N2)                         */
     int32_t qgrid[3];          /* phonon grid; kgrid[a] % qgrid[a] == 0, <= 1024   */
@@ -202,7 +206,24 @@ ephbte_status ephbte_collision_vjp(ephbte_plan plan, int32_t batch, const void *
                                    double *gg2, int32_t accumulate_gg2, void *stream);
 
 /*
- * Real-time BTE without field, df/dt = I[f] (Eq. 1 with F = 0): advances f
+ * Field term of Eq. 1 for ephbte_rt_step and ephbte_rt_adjoint: they then
+ * integrate df/dt = -(1/hbar) F . grad_k f + I[f].  The k derivative along grid
+ * axis a is the central difference inside the state's band, periodic over the
+ * k grid; a neighbour that is not in the state list (outside the energy
+ * window) counts as empty.  rate[a] = F_a / (hbar dk_a) in 1/fs, with F the
+ * force on the carrier (-e E for electrons) and dk_a the k-grid step, so the
+ * term is -sum_a rate[a] (f(k + dk_a) - f(k - dk_a)) / 2.  All three 0 (the
+ * default) switch it off; ephbte_collision_integral and ephbte_collision_vjp
+ * never include it.  INVALID_ARGUMENT for a non-finite rate, or for a nonzero
+ * one when some (k, band) is held by two states of the plan.  Drops cached
+ * HIP graphs.  Synchronous.
+ * Currently switched off: any nonzero rate returns INVALID_ARGUMENT.
+ */
+ephbte_status ephbte_set_field(ephbte_plan plan, const double rate[3]);
+
+/*
+ * Real-time BTE, df/dt = I[f] (Eq. 1; with the field term when
+ * ephbte_set_field has set one): advances f
  * (device [B][ldf], in place) by n_steps classical RK4 steps of dt_fs.  The
  * stage updates are fused into the collision kernels (four launches per
  * step).  use_graph != 0 captures the step sequence in a HIP graph on the

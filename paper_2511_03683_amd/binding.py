@@ -31,7 +31,7 @@ class EphbteError(RuntimeError):
 
 
 class Problem(ctypes.Structure):
-    _fields_ = [("n_states", ctypes.c_int32), ("state_k", _P), ("eps", _P),
+    _fields_ = [("n_states", ctypes.c_int32), ("state_k", _P), ("state_band", _P), ("eps", _P),
                 ("kgrid", ctypes.c_int32 * 3), ("qgrid", ctypes.c_int32 * 3),
                 ("n_modes", ctypes.c_int32), ("hw", _P), ("n_channels", ctypes.c_int64),
                 ("ch_i", _P), ("ch_j", _P), ("ch_nu", _P), ("g2", _P),
@@ -73,6 +73,7 @@ SYMBOLS = {
     "ephbte_set_tuning": ([_P, ctypes.POINTER(Tuning)], ctypes.c_int32),
     "ephbte_autotune": ([_P, ctypes.c_int32, ctypes.POINTER(Tuning)], ctypes.c_int32),
     "ephbte_plan_info": ([_P, _P], ctypes.c_int32),
+    "ephbte_set_field": ([_P, _P], ctypes.c_int32),
     "ephbte_plan_bytes": ([_P], ctypes.c_int64),
     "ephbte_destroy": ([_P], None),
     "ephbte_status_string": ([ctypes.c_int32], ctypes.c_char_p),
@@ -126,13 +127,15 @@ def _np(a, dtype):
 
 def _problem(system, dtype: int, device: int):
     """ctypes Problem plus the numpy arrays it points into (kept alive)."""
-    keep = dict(state_k=_np(system.state_k, np.int32), eps=_np(system.eps, np.float64),
+    keep = dict(state_k=_np(system.state_k, np.int32), state_band=_np(system.state_band, np.int8),
+                eps=_np(system.eps, np.float64),
                 hw=_np(system.hw, np.float64), ch_i=_np(system.ch_i, np.int32),
                 ch_j=_np(system.ch_j, np.int32), ch_nu=_np(system.ch_nu, np.int8),
                 g2=_np(system.g2, np.float64))
     pr = Problem()
     pr.n_states = int(keep["eps"].size)
     pr.state_k = keep["state_k"].ctypes.data
+    pr.state_band = keep["state_band"].ctypes.data
     pr.eps = keep["eps"].ctypes.data
     pr.kgrid[:] = [int(x) for x in system.kgrid]
     pr.qgrid[:] = [int(x) for x in system.qgrid]
@@ -413,6 +416,15 @@ def autotune(plan: Plan, batch: int = 1) -> dict:
     _check(load_library().ephbte_autotune(plan.handle, int(batch), ctypes.byref(t)), "autotune")
     return dict(chunk_entries=t.chunk_entries, block_threads=t.block_threads, xcd_map=t.xcd_map,
                 batch_partners=t.batch_partners, tile_entries=t.tile_entries)
+
+
+def set_field(plan: Plan, rates) -> None:
+    """Field term of rt_step / rt_adjoint: rates[a] = F_a / (hbar dk_a) in 1/fs
+    (see ephbte_set_field); (0, 0, 0) switches it off."""
+    r = np.ascontiguousarray(rates, dtype=np.float64)
+    if r.shape != (3,):
+        raise ValueError("rates must hold 3 values")
+    _check(load_library().ephbte_set_field(plan.handle, r.ctypes.data), "set_field")
 
 
 def plan_info(plan: Plan) -> dict:

@@ -68,6 +68,11 @@ struct ephbte_plan_s {
     int64_t nch_kept = 0;
     int32_t *drop_idx = nullptr;     // [n_drop] caller indices removed by the channel selection
     int64_t n_drop = 0;
+    // field term of Eq. 1: neighbour table (device, [S][3][2]) and rates (1/fs)
+    int32_t *nbr = nullptr;
+    bool nbr_ok = false;
+    double drift_rate[3] = {0.0, 0.0, 0.0};
+    bool drift_on = false;
     int nq[3] = {0, 0, 0};
     double sigma = 0, nqnorm = 0;
     std::vector<int64_t> row_ptr;   // host copy for re-chunking
@@ -211,7 +216,8 @@ void free_plan(ephbte_plan P) {
                      (void **)&P->sym_chunk_beg, (void **)&P->sym_chunk_end, (void **)&P->sym_chunk_dest,
                      (void **)&P->sym_dest_chunk, (void **)&P->sym_tiles, (void **)&P->jacc,
                      (void **)&P->nmax_bits, (void **)&P->gmax_bits, (void **)&P->pack_bmax,
-                     (void **)&P->drop_idx, (void **)&P->vbtiles, (void **)&P->vsub_off};
+                     (void **)&P->drop_idx, (void **)&P->vbtiles, (void **)&P->vsub_off,
+                     (void **)&P->nbr};
     for (auto pp : ptrs) dfree(*pp);
     DevBuf *w[] = {&P->part,   &P->sym_part, &P->rk_ua,  &P->rk_ub,   &P->rk_acc, &P->hwN, &P->tr_W,   &P->tr_tau_inv,
                    &P->tr_tau, &P->tr_rhs, &P->tr_xa,   &P->tr_xb,  &P->tr_part, &P->tr_red,
@@ -839,6 +845,19 @@ template <typename T> void upload_layout(ephbte_plan P, const ephbte_problem *pr
 hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
 
 // ---------------------------------------------------------------- drivers
+// Field term in a stage epilogue: D[x] of the stage input x, times sign.
+template <typename T> void with_drift(ephbte_plan P, Epi<T> &e, const T *x, int64_t ldx, T sign) {
+    if (!P->drift_on) {
+        e.nbr = nullptr;
+        return;
+    }
+    e.nbr = P->nbr;
+    e.x = x;
+    e.ld_x = ldx;
+    for (int a = 0; a < 3; ++a) e.rate[a] = static_cast<T>(P->drift_rate[a]);
+    e.dsign = sign;
+}
+
 template <typename T>
 void rk4_enqueue_step(ephbte_plan P, int B, T *f, int64_t ldf, const void *nph, T dt,
                       hipStream_t s, T *ua, T *ub, T *acc, const T *f_in, int64_t ld_in,
@@ -854,15 +873,19 @@ void rk4_enqueue_step(ephbte_plan P, int B, T *f, int64_t ldf, const void *nph, 
     e.dt = dt;
     e.mode = EPI_RK1;
     e.u_out = ua;
+    with_drift<T>(P, e, f_in, ld_in, T(1));
     enqueue_forward<T>(P, B, f_in, ld_in, nph, e, s, false);
     e.mode = EPI_RK2;
     e.u_out = ub;
+    with_drift<T>(P, e, ua, S, T(1));
     enqueue_forward<T>(P, B, ua, S, nph, e, s, false);
     e.mode = EPI_RK3;
     e.u_out = ua;
+    with_drift<T>(P, e, ub, S, T(1));
     enqueue_forward<T>(P, B, ub, S, nph, e, s, false);
     e.mode = EPI_RK4;
     e.f_out = f_out;
+    with_drift<T>(P, e, ua, S, T(1));
     enqueue_forward<T>(P, B, ua, S, nph, e, s, false);
 }
 
@@ -984,15 +1007,19 @@ ephbte_status rt_adjoint_impl(ephbte_plan P, const T *f0, const void *nph, doubl
             r.dt = tdt;
             r.mode = EPI_RK1;
             r.u_out = u + S;
+            with_drift<T>(P, r, u, S, T(1));
             enqueue_forward<T>(P, 1, u, S, nph, r, s, false);
             r.mode = EPI_RK2;
             r.u_out = u + 2 * S;
+            with_drift<T>(P, r, u + S, S, T(1));
             enqueue_forward<T>(P, 1, u + S, S, nph, r, s, false);
             r.mode = EPI_RK3;
             r.u_out = u + 3 * S;
+            with_drift<T>(P, r, u + 2 * S, S, T(1));
             enqueue_forward<T>(P, 1, u + 2 * S, S, nph, r, s, false);
             r.mode = EPI_RK4;
             r.f_out = u + 4 * S;   // next step's u1 (one spare slot at the end)
+            with_drift<T>(P, r, u + 3 * S, S, T(1));
             enqueue_forward<T>(P, 1, u + 3 * S, S, nph, r, s, false);
         }
         // reverse sweep over the segment
@@ -1007,19 +1034,23 @@ ephbte_status rt_adjoint_impl(ephbte_plan P, const T *f0, const void *nph, doubl
             e.cg = tdt / T(3);
             e.cv = tdt;
             e.u_out = lb;
+            with_drift<T>(P, e, la, S, T(-1));
             enqueue_vjp<T>(P, u + 3 * S, la, nph, e, gg2, gmode, s);
             e.mode = EPI_ADJ_MID;     // u3: acc += v; kb2 = dt/3 g + dt/2 v
             e.cg = tdt / T(3);
             e.cv = tdt / T(2);
             e.u_out = la;
+            with_drift<T>(P, e, lb, S, T(-1));
             enqueue_vjp<T>(P, u + 2 * S, lb, nph, e, gg2, gmode, s);
             e.mode = EPI_ADJ_MID;     // u2: acc += v; kb1 = dt/6 g + dt/2 v
             e.cg = tdt / T(6);
             e.cv = tdt / T(2);
             e.u_out = lb;
+            with_drift<T>(P, e, la, S, T(-1));
             enqueue_vjp<T>(P, u + S, la, nph, e, gg2, gmode, s);
             e.mode = EPI_ADJ_LAST;    // u1: g = g + acc + v
             e.gbar_out = gb;
+            with_drift<T>(P, e, lb, S, T(-1));
             enqueue_vjp<T>(P, u, lb, nph, e, gg2, gmode, s);
         }
     }
@@ -1260,6 +1291,11 @@ ephbte_status ephbte_build_channels(const ephbte_problem *problem, const ephbte_
         P->nch = L.n_input;
         P->nch_kept = L.n_channels;
         P->E = L.E;
+        P->nbr_ok = !L.nbr.empty();
+        if (P->nbr_ok) {
+            dalloc(P->nbr, sizeof(int32_t) * L.nbr.size(), &P->layout_bytes);
+            HIPC(hipMemcpy(P->nbr, L.nbr.data(), sizeof(int32_t) * L.nbr.size(), hipMemcpyHostToDevice));
+        }
         P->n_drop = static_cast<int64_t>(L.dropped.size());
         if (P->n_drop > 0) {
             dalloc(P->drop_idx, sizeof(int32_t) * P->n_drop, &P->layout_bytes);
@@ -1666,6 +1702,30 @@ ephbte_status ephbte_autotune(ephbte_plan plan, int32_t batch, ephbte_tuning *ch
         }
         return EPHBTE_OK;
     });
+}
+
+ephbte_status ephbte_set_field(ephbte_plan plan, const double rate[3]) {
+    if (!plan || !rate) return fail(EPHBTE_INVALID_ARGUMENT, "plan and rate must be non-NULL");
+    bool on = false;
+    for (int a = 0; a < 3; ++a) {
+        if (!std::isfinite(rate[a])) return fail(EPHBTE_INVALID_ARGUMENT, "field rates must be finite");
+        on = on || rate[a] != 0.0;
+    }
+    if (on && !plan->nbr_ok)
+        return fail(EPHBTE_INVALID_ARGUMENT,
+                    "the field term needs each (k, band) held by one state (give state_band)");
+    // the field path is switched off: its device code is kept but not reached
+    if (on) return fail(EPHBTE_INVALID_ARGUMENT, "the field term is not available (only 0 rates are accepted)");
+    try {
+        DeviceGuard g(plan->device);
+        HIPC(hipDeviceSynchronize());
+        free_graphs(plan);   // captured steps hold the previous rates
+    } catch (const HipError &e) {
+        return fail(EPHBTE_HIP_ERROR, std::string(e.where) + ": " + hipGetErrorString(e.e));
+    }
+    for (int a = 0; a < 3; ++a) plan->drift_rate[a] = rate[a];
+    plan->drift_on = on;
+    return EPHBTE_OK;
 }
 
 ephbte_status ephbte_plan_info(ephbte_plan plan, int64_t out[10]) {

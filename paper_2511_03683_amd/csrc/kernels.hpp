@@ -167,7 +167,31 @@ template <typename T> struct Epi {
     const T *gbar;
     T *gbar_out;
     T cg, cv;
+    // field term of Eq. 1 (RK and adjoint modes, when nbr is set): v gains
+    // dsign * D[x], D[x]_d = -sum_a rate[a] (x[up_a] - x[down_a]) / 2, with x the
+    // stage input (forward: the stage's f, dsign = 1; adjoint: the stage's
+    // lambda, dsign = -1, since D^T = -D for a symmetric neighbour relation)
+    const int32_t *nbr;    // [S][3][2], -1: not in the list (x = 0 there)
+    const T *x;
+    int64_t ld_x;
+    T rate[3];
+    T dsign;
 };
+
+template <typename T>
+__device__ __forceinline__ T drift_term(const Epi<T> &E, int b, int d) {
+    const int32_t *nb = E.nbr + 6 * static_cast<int64_t>(d);
+    const T *xb = E.x + static_cast<int64_t>(b) * E.ld_x;
+    T s = T(0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int up = nb[2 * a], dn = nb[2 * a + 1];
+        const T xu = up >= 0 ? xb[up] : T(0);
+        const T xd = dn >= 0 ? xb[dn] : T(0);
+        s += E.rate[a] * (xu - xd);
+    }
+    return E.dsign * (T(-0.5) * s);
+}
 
 enum EpiMode {
     EPI_STORE = 0,
@@ -183,6 +207,7 @@ enum EpiMode {
 template <typename T>
 __device__ __forceinline__ void apply_epi(const Epi<T> &E, int b, int d, int S, T v) {
     const int64_t iw = static_cast<int64_t>(b) * S + d;
+    if (E.mode > EPI_STORE && E.nbr) v += drift_term(E, b, d);
     switch (E.mode) {
     case EPI_STORE: E.out[static_cast<int64_t>(b) * E.ld_out + d] = v; break;
     case EPI_RK1: {

@@ -8,6 +8,7 @@
 #include <numeric>
 #include <sstream>
 #include <thread>
+#include <unordered_map>
 
 namespace ephbte {
 
@@ -133,6 +134,40 @@ ephbte_status build_host_layout(const ephbte_problem *p, const ephbte_build_opts
         for (int a = 0; a < 3; ++a) kc[3 * s + a] = c[a];
         L.kq[s] = (static_cast<uint32_t>(c[0] / r[0]) << 20) |
                   (static_cast<uint32_t>(c[1] / r[1]) << 10) | static_cast<uint32_t>(c[2] / r[2]);
+    }
+
+    // neighbours of the field term: the state of the same band at k +/- one
+    // grid step along each axis
+    L.nbr.clear();
+    {
+        std::unordered_map<int64_t, int32_t> at;
+        at.reserve(static_cast<size_t>(S) * 2);
+        bool unique = true;
+        auto key = [&](int64_t k, int band) { return k * 256 + (band + 128); };
+        for (int32_t s = 0; s < S; ++s) {
+            const int band = p->state_band ? p->state_band[s] : 0;
+            if (!at.emplace(key(p->state_k[s], band), s).second) {
+                // a k point held twice in one band (two states without bands,
+                // or block-diagonal subsystems drawn from one grid): the field
+                // term has no single neighbour and is not available
+                unique = false;
+                break;
+            }
+        }
+        if (unique) {
+            L.nbr.assign(static_cast<size_t>(S) * 6, -1);
+            for (int32_t s = 0; s < S; ++s) {
+                const int band = p->state_band ? p->state_band[s] : 0;
+                for (int a = 0; a < 3; ++a)
+                    for (int u = 0; u < 2; ++u) {
+                        int32_t c[3] = {kc[3 * s], kc[3 * s + 1], kc[3 * s + 2]};
+                        c[a] = (c[a] + (u == 0 ? 1 : p->kgrid[a] - 1)) % p->kgrid[a];
+                        const int64_t k = (int64_t(c[0]) * p->kgrid[1] + c[1]) * p->kgrid[2] + c[2];
+                        const auto it = at.find(key(k, band));
+                        L.nbr[static_cast<size_t>(s) * 6 + 2 * a + u] = it == at.end() ? -1 : it->second;
+                    }
+            }
+        }
     }
 
     const int64_t nch = p->n_channels;

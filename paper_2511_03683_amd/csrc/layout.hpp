@@ -30,6 +30,10 @@ struct HostLayout {
     std::vector<uint32_t> kq;         // [S] k coordinates in q-grid units, 10 bits each (k0,k1,k2)
     std::vector<int32_t> pmin, pmax;  // [S] smallest / largest partner of each destination
     std::vector<int32_t> dropped;     // caller indices of the channels the selection removed
+    // field term: [S][3][2] state of the same band one k step up / down along
+    // each axis (periodic), -1 if not in the list; empty when some (k, band)
+    // is held by two states
+    std::vector<int32_t> nbr;
 };
 
 // Validates the problem, applies the channel selection of opts (may be NULL:

@@ -158,6 +158,21 @@ def _mutate_sys(s, **kw):
     return r
 
 
+def test_repeated_k_band_is_accepted():
+    """Block-diagonal subsystems may hold the same (k, band); the layout is
+    built (only the field term would be unavailable)."""
+    s = synth.multiband_system()
+    b = s.state_band.copy()
+    same_k = np.nonzero(s.state_k == s.state_k[0])[0]
+    assert same_k.size >= 2
+    b[same_k[1]] = b[same_k[0]]
+    rp, *_ = E.layout_host(_mutate_sys(s, state_band=b))
+    assert rp[-1] == 2 * s.n_channels
+    lib = E.load_library()
+    r = np.zeros(3)
+    assert lib.ephbte_set_field(None, r.ctypes.data) == binding.INVALID_ARGUMENT
+
+
 def _bad(system, match):
     with pytest.raises(E.EphbteError, match=match) as ei:
         E.layout_host(system)

@@ -658,6 +658,82 @@ def test_rt_adjoint_matches_oracle(E):
     plan.close()
 
 
+RATES = np.array([0.06, -0.035, 0.02])   # 1/fs: a strong field, so the drift is felt in a few steps
+
+
+@pytest.mark.skip(reason="field path switched off: its first GPU run faulted the GPU; the "
+                         "cause was not found (in-range neighbour table and device loads checked "
+                         "on the CPU), so the case stays off the GPU")
+@pytest.mark.parametrize("dtype,B", [("f64", 1), ("f64", 3), ("f64", 9), ("f32", 1)])
+def test_rt_step_with_field(E, dtype, B):
+    """Eq. 1 with the field term: RK4 with collisions and drift against the
+    oracle (single-copy, per-row and batched forward passes, eager and graph);
+    a zero field gives back the field-free step bitwise."""
+    s = synth.multiband_system()
+    nph = s.nph(300.0)
+    F = np.stack([synth.random_occupations(s, 30 + b) for b in range(B)])
+    dt, n = 1.0, 4
+    r, tdt, tol = s, torch.float64, 1e-9
+    if dtype == "f32":
+        F, nph = F.astype(np.float32).astype(np.float64), nph.astype(np.float32).astype(np.float64)
+        r, tdt, tol = round32(s), torch.float32, 1e-5
+    plan = E.build_channels(s, dtype=dtype, device=0)
+    say(f"rt_step field {dtype} B={B}")
+    E.set_field(plan, RATES)
+    ft = dev(F if B > 1 else F[0], tdt)
+    E.rt_step(plan, ft, dev(nph, tdt), dt, n, use_graph=False)
+    got = host(ft).reshape(B, -1)
+    for b in range(B):
+        ref = F[b].copy()
+        for _ in range(n):
+            ref = oracle.rk4_step(r, ref, nph, dt, rates=RATES)
+        assert nerr(got[b] - F[b], ref - F[b]) <= tol, b
+    fg = dev(F if B > 1 else F[0], tdt)
+    E.rt_step(plan, fg, dev(nph, tdt), dt, n, use_graph=True)
+    assert np.array_equal(host(fg), host(ft))
+    E.set_field(plan, [0.0, 0.0, 0.0])
+    f1, f2 = dev(F[0], tdt), dev(F[0], tdt)
+    E.rt_step(plan, f1, dev(nph, tdt), dt, n)
+    plan2 = E.build_channels(s, dtype=dtype, device=0)
+    E.rt_step(plan2, f2, dev(nph, tdt), dt, n)
+    assert np.array_equal(host(f1), host(f2))
+    plan.close()
+    plan2.close()
+
+
+@pytest.mark.skip(reason="field path switched off: its first GPU run faulted the GPU; the "
+                         "cause was not found (in-range neighbour table and device loads checked "
+                         "on the CPU), so the case stays off the GPU")
+def test_rt_adjoint_with_field(E):
+    """Discrete adjoint through RK4 steps with collisions and drift against the
+    oracle's (whose drift transpose is the scattered matrix, not -D)."""
+    s = synth.multiband_system(n_k=10, seed=23)
+    f0 = synth.random_occupations(s, 9) * 0.8 + 0.1
+    nph = s.nph(300.0)
+    dt, n = 1.0, 4
+    gT = np.random.default_rng(6).normal(size=s.n_states)
+    _, rf, rg = oracle.rk4_trajectory_grad(s, f0, nph, dt, n, gT, rates=RATES)
+    plan = E.build_channels(s, device=0)
+    E.set_field(plan, RATES)
+    say("rt_adjoint field")
+    gf0, gg = E.rt_adjoint(plan, dev(f0), dev(nph), dt, n, 2, dev(gT), gg2=True)
+    assert nerr(host(gf0), rf) <= 1e-9
+    assert nerr(host(gg), rg) <= 1e-9
+    plan.close()
+
+
+def test_field_term_is_refused(E):
+    """The field path is switched off: zero rates are accepted (and change
+    nothing), nonzero ones are refused."""
+    s = synth.multiband_system()
+    plan = E.build_channels(s, device=0)
+    say("field switched off")
+    E.set_field(plan, [0.0, 0.0, 0.0])
+    with pytest.raises(E.EphbteError, match="not available"):
+        E.set_field(plan, RATES)
+    plan.close()
+
+
 def test_rt_solve_autograd(E):
     from paper_2511_03683_amd.autograd import rt_solve
     s = synth.multiband_system(n_k=10, seed=23)
