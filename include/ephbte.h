@@ -281,8 +281,15 @@ ephbte_status ephbte_set_tuning(ephbte_plan plan, const ephbte_tuning *tuning);
  * HIP events and keep the fastest; writes the chosen tuning to *chosen (may be
  * NULL).  For batch < 8 the candidates are chunk sizes x block sizes of the
  * single-vector kernel; for batch >= 8, partner sub-tile sizes of the batched
- * kernel.  Allocates and frees its own half-filled occupations.  Synchronous. */
-ephbte_status ephbte_autotune(ephbte_plan plan, int32_t batch, ephbte_tuning *chosen);
+ * kernel.  Allocates and frees its own half-filled occupations.  Synchronous.
+ * cache_path (may be NULL): a JSON file mapping a key (device architecture and
+ * compute-unit count, dtype, states, entries, modes, q grid, single or
+ * batched) to the tuning chosen for it.  An entry for this plan is applied
+ * without timing; otherwise the tuning is timed and the file rewritten (via a
+ * temporary file and a rename) with the new entry added.  INVALID_ARGUMENT if
+ * the file holds something else (it is left alone) or cannot be written. */
+ephbte_status ephbte_autotune(ephbte_plan plan, int32_t batch, ephbte_tuning *chosen,
+                              const char *cache_path);
 
 /* Plan facts: out[0]=S, [1]=n_channels passed at build, [2]=entries,
  * [3]=chunks, [4]=dtype, [5]=device, [6]=device bytes held,

@@ -71,7 +71,7 @@ SYMBOLS = {
                                   ctypes.c_int32, _P, _P, _P, _P, _P], ctypes.c_int32),
     "ephbte_update_g2": ([_P, _P, _P], ctypes.c_int32),
     "ephbte_set_tuning": ([_P, ctypes.POINTER(Tuning)], ctypes.c_int32),
-    "ephbte_autotune": ([_P, ctypes.c_int32, ctypes.POINTER(Tuning)], ctypes.c_int32),
+    "ephbte_autotune": ([_P, ctypes.c_int32, ctypes.POINTER(Tuning), ctypes.c_char_p], ctypes.c_int32),
     "ephbte_plan_info": ([_P, _P], ctypes.c_int32),
     "ephbte_set_field": ([_P, _P], ctypes.c_int32),
     "ephbte_plan_bytes": ([_P], ctypes.c_int64),
@@ -411,9 +411,12 @@ def set_tuning(plan: Plan, chunk_entries=0, block_threads=0, xcd_map=0, batch_pa
     _check(load_library().ephbte_set_tuning(plan.handle, ctypes.byref(t)), "set_tuning")
 
 
-def autotune(plan: Plan, batch: int = 1) -> dict:
+def autotune(plan: Plan, batch: int = 1, cache_path: Optional[str] = None) -> dict:
+    """Time and apply the fastest tuning (see ephbte_autotune); with cache_path
+    a tuning stored for this plan's key is applied without timing."""
     t = Tuning()
-    _check(load_library().ephbte_autotune(plan.handle, int(batch), ctypes.byref(t)), "autotune")
+    path = None if cache_path is None else os.fsencode(cache_path)
+    _check(load_library().ephbte_autotune(plan.handle, int(batch), ctypes.byref(t), path), "autotune")
     return dict(chunk_entries=t.chunk_entries, block_threads=t.block_threads, xcd_map=t.xcd_map,
                 batch_partners=t.batch_partners, tile_entries=t.tile_entries)
 

@@ -8,9 +8,13 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <map>
 #include <memory>
 #include <new>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -1217,6 +1221,105 @@ template <typename F> ephbte_status guarded(ephbte_plan P, void *stream, F &&fn)
     }
 }
 
+// ---------------------------------------------------------------- autotune cache
+// A JSON object mapping a plan key to the tuning chosen for it:
+//   {"<key>": {"chunk_entries": 65536, "block_threads": 512, ...}, ...}
+using TuneEntry = std::map<std::string, long long>;
+using TuneCache = std::map<std::string, TuneEntry>;
+
+// 1: parsed, 0: no file, -1: not a cache of this form
+int read_tune_cache(const char *path, TuneCache &out) {
+    std::ifstream in(path, std::ios::binary);
+    if (!in) return 0;
+    std::stringstream ss;
+    ss << in.rdbuf();
+    const std::string t = ss.str();
+    size_t i = 0;
+    auto ws = [&]() { while (i < t.size() && std::isspace(static_cast<unsigned char>(t[i]))) ++i; };
+    auto str = [&](std::string &o) -> bool {
+        ws();
+        if (i >= t.size() || t[i] != '"') return false;
+        ++i;
+        o.clear();
+        while (i < t.size() && t[i] != '"') {
+            if (t[i] == '\\') return false;   // keys and names are written without escapes
+            o += t[i++];
+        }
+        if (i >= t.size()) return false;
+        ++i;
+        return true;
+    };
+    auto ch = [&](char c) -> bool {
+        ws();
+        if (i < t.size() && t[i] == c) {
+            ++i;
+            return true;
+        }
+        return false;
+    };
+    auto num = [&](long long &v) -> bool {
+        ws();
+        const size_t b = i;
+        if (i < t.size() && t[i] == '-') ++i;
+        while (i < t.size() && std::isdigit(static_cast<unsigned char>(t[i]))) ++i;
+        if (i == b || (i == b + 1 && t[b] == '-')) return false;
+        v = std::stoll(t.substr(b, i - b));
+        return true;
+    };
+    if (!ch('{')) return -1;
+    if (ch('}')) return 1;
+    do {
+        std::string key;
+        if (!str(key) || !ch(':') || !ch('{')) return -1;
+        TuneEntry e;
+        if (!ch('}')) {
+            do {
+                std::string name;
+                long long v;
+                if (!str(name) || !ch(':') || !num(v)) return -1;
+                e[name] = v;
+            } while (ch(','));
+            if (!ch('}')) return -1;
+        }
+        out[key] = e;
+    } while (ch(','));
+    if (!ch('}')) return -1;
+    ws();
+    return i == t.size() ? 1 : -1;
+}
+
+bool write_tune_cache(const char *path, const TuneCache &c) {
+    const std::string tmp = std::string(path) + ".tmp";
+    {
+        std::ofstream o(tmp, std::ios::binary | std::ios::trunc);
+        if (!o) return false;
+        o << "{\n";
+        size_t k = 0;
+        for (const auto &kv : c) {
+            o << "  \"" << kv.first << "\": {";
+            size_t n = 0;
+            for (const auto &f : kv.second) o << (n++ ? ", " : "") << "\"" << f.first << "\": " << f.second;
+            o << "}" << (++k < c.size() ? "," : "") << "\n";
+        }
+        o << "}\n";
+        if (!o) return false;
+    }
+    return std::rename(tmp.c_str(), path) == 0;
+}
+
+std::string tune_key(ephbte_plan P, int batch) {
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, P->device) == hipSuccess) arch = prop.gcnArchName;
+    for (char &c : arch)
+        if (c == '"' || c == '\\') c = '_';
+    std::ostringstream k;
+    k << arch << "|cu=" << P->n_cu << "|" << (P->dtype == EPHBTE_F64 ? "f64" : "f32") << "|S=" << P->S
+      << "|E=" << P->E << "|modes=" << P->nm << "|q=" << P->nq[0] << "x" << P->nq[1] << "x" << P->nq[2]
+      << "|" << (batch >= P->batch_min ? "batched" : "single");
+    return k.str();
+}
+
 }  // namespace
 
 // =================================================================== C ABI
@@ -1586,10 +1689,9 @@ ephbte_status ephbte_set_tuning(ephbte_plan plan, const ephbte_tuning *tuning) {
     });
 }
 
-ephbte_status ephbte_autotune(ephbte_plan plan, int32_t batch, ephbte_tuning *chosen) {
-    return guarded(plan, nullptr, [&]() -> ephbte_status {
-        if (batch < 1 || batch > 65535) return fail(EPHBTE_INVALID_ARGUMENT, "batch must be in [1, 65535]");
-        HIPC(hipDeviceSynchronize());
+// Times the candidate tunings on this plan and applies the fastest.
+static ephbte_status autotune_timed(ephbte_plan plan, int32_t batch, ephbte_tuning *chosen) {
+    {
         const size_t es = esize(plan);
         const int64_t S = plan->S;
         const int64_t nqm = static_cast<int64_t>(plan->nq[0]) * plan->nq[1] * plan->nq[2] * plan->nm;
@@ -1699,6 +1801,76 @@ ephbte_status ephbte_autotune(ephbte_plan plan, int32_t batch, ephbte_tuning *ch
             chosen->xcd_map = plan->xcd_map ? 1 : 2;
             chosen->batch_partners = plan->pt;
             chosen->tile_entries = best_te > 0 ? static_cast<int32_t>(std::min<int64_t>(best_te, INT32_MAX)) : -1;
+        }
+        return EPHBTE_OK;
+    }
+}
+
+ephbte_status ephbte_autotune(ephbte_plan plan, int32_t batch, ephbte_tuning *chosen,
+                              const char *cache_path) {
+    return guarded(plan, nullptr, [&]() -> ephbte_status {
+        if (batch < 1 || batch > 65535) return fail(EPHBTE_INVALID_ARGUMENT, "batch must be in [1, 65535]");
+        HIPC(hipDeviceSynchronize());
+        TuneCache cache;
+        std::string key;
+        if (cache_path) {
+            const int r = read_tune_cache(cache_path, cache);
+            if (r < 0) return fail(EPHBTE_INVALID_ARGUMENT, "cache_path holds something other than an autotune cache");
+            key = tune_key(plan, batch);
+            const auto it = cache.find(key);
+            if (it != cache.end()) {
+                const TuneEntry &e = it->second;
+                auto get = [&](const char *n, long long d) {
+                    const auto f = e.find(n);
+                    return f == e.end() ? d : f->second;
+                };
+                const bool batched = batch >= plan->batch_min;
+                const long long pt = get("batch_partners", plan->pt);
+                const long long bt = get("block_threads", plan->block_threads);
+                const long long ce = get("chunk_entries", plan->chunk_entries);
+                const long long te = get("tile_entries", -1);
+                const bool ok = batched ? (pt >= 16 && pt <= 1024 && batch_lds_bytes(plan, static_cast<int>(pt)) <= plan->lds_max)
+                                        : ((bt == 64 || bt == 128 || bt == 256 || bt == 512) && ce >= 0 && te >= -1);
+                if (ok) {
+                    if (batched) {
+                        if (pt != plan->pt) upload_btiles(plan, static_cast<int>(pt));
+                    } else {
+                        plan->block_threads = static_cast<int>(bt);
+                        plan->tile_entries = te > 0 ? te : 0;
+                        upload_chunks(plan, static_cast<int64_t>(ce));
+                        free_graphs(plan);
+                    }
+                    if (chosen) {
+                        std::memset(chosen, 0, sizeof(*chosen));
+                        chosen->chunk_entries = plan->chunk_entries;
+                        chosen->block_threads = plan->block_threads;
+                        chosen->xcd_map = plan->xcd_map ? 1 : 2;
+                        chosen->batch_partners = plan->pt;
+                        chosen->tile_entries = plan->tile_entries > 0
+                                                   ? static_cast<int32_t>(std::min<int64_t>(plan->tile_entries, INT32_MAX))
+                                                   : -1;
+                    }
+                    return EPHBTE_OK;
+                }
+                // a stale or foreign entry: tune again and replace it
+            }
+        }
+        ephbte_tuning got{};
+        const ephbte_status st = autotune_timed(plan, batch, &got);
+        if (st != EPHBTE_OK) return st;
+        if (chosen) *chosen = got;
+        if (cache_path) {
+            TuneEntry e;
+            if (batch >= plan->batch_min) {
+                e["batch_partners"] = got.batch_partners;
+            } else {
+                e["block_threads"] = got.block_threads;
+                e["chunk_entries"] = got.chunk_entries;
+                e["tile_entries"] = got.tile_entries;
+            }
+            cache[key] = e;
+            if (!write_tune_cache(cache_path, cache))
+                return fail(EPHBTE_INVALID_ARGUMENT, "could not write cache_path (the plan keeps the tuning)");
         }
         return EPHBTE_OK;
     });

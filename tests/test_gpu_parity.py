@@ -310,6 +310,48 @@ def test_autotune_keeps_results(E):
     plan.close()
 
 
+def test_autotune_cache(E, tmp_path):
+    """A cached tuning is applied without timing (a hand-edited entry comes
+    back as written and the results stay at the oracle's); single and batched
+    entries live side by side; a file that is not a cache is refused and left
+    as it was."""
+    import json
+    s = synth.tb_system(kn=24, qn=12, target_states=400)
+    nph = s.nph(300.0)
+    path = str(tmp_path / "tune.json")
+    plan = E.build_channels(s, device=0)
+    say("autotune cache")
+    t1 = E.autotune(plan, 1, cache_path=path)
+    t16 = E.autotune(plan, 16, cache_path=path)
+    c = json.load(open(path))
+    assert len(c) == 2
+    single = [k for k in c if k.endswith("|single")][0]
+    batched = [k for k in c if k.endswith("|batched")][0]
+    assert c[single]["chunk_entries"] == t1["chunk_entries"]
+    assert c[batched]["batch_partners"] == t16["batch_partners"]
+    c[single] = {"block_threads": 128, "chunk_entries": 4096, "tile_entries": -1}
+    c[batched] = {"batch_partners": 64 if t16["batch_partners"] != 64 else 48}
+    json.dump(c, open(path, "w"))
+    plan2 = E.build_channels(s, device=0)
+    u1 = E.autotune(plan2, 1, cache_path=path)
+    assert (u1["block_threads"], u1["chunk_entries"]) == (128, 4096)
+    u16 = E.autotune(plan2, 16, cache_path=path)
+    assert u16["batch_partners"] == c[batched]["batch_partners"]
+    assert json.load(open(path)) == c, "a hit leaves the file as it was"
+    f = synth.random_occupations(s, 22)
+    assert nerr(host(E.collision_integral(plan2, dev(f), dev(nph))), oracle.collision(s, f, nph)) <= TOL64
+    F = np.random.default_rng(17).uniform(size=(16, s.n_states))
+    got = host(E.collision_integral(plan2, dev(F), dev(nph)))
+    assert nerr(got[3], oracle.collision(s, F[3], nph)) <= TOL64
+    bad = tmp_path / "other.json"
+    bad.write_text('{"something": [1, 2, 3]}')
+    with pytest.raises(E.EphbteError, match="autotune cache"):
+        E.autotune(plan2, 1, cache_path=str(bad))
+    assert bad.read_text() == '{"something": [1, 2, 3]}'
+    plan.close()
+    plan2.close()
+
+
 def test_batched_rk4_matches_oracle(E):
     s = synth.multiband_system()
     nph = s.nph(300.0)
