@@ -19,6 +19,10 @@ Contents, each following the paper (arXiv 2511.03683):
 * collision_brute(sys, f, nph)  -- Eq. 2 written out over the full q grid,
   all bands and modes, for tiny grids (numpy; independent of the C code).
 * collision_vjp(...)            -- hand-derived reverse mode of Eq. 2.
+* phonon_rate(sys, f, nph)      -- dN/dt of every phonon (q, mode) from the
+  same channel list: the phonon side of the four golden-rule processes
+  behind Eq. 2 (coupled electron-phonon dynamics; the paper cites it, the
+  formula is the reading documented with the function).
 * drift(sys, f, rates)          -- the field term of Eq. 1, -(1/hbar) F . grad_k f,
   by central differences on the k grid (the discretisation is a reading:
   the paper defers it to its Methods), and its transpose.
@@ -253,6 +257,57 @@ def collision_brute(sys, f, nph):
                     total += -pref * g * (G(de + w) * F_abs + G(de - w) * F_em)
         I[d] = total
     return I
+
+
+# ---------------------------------------------------------------------------
+# phonon side of the same processes (coupled electron-phonon dynamics)
+# ---------------------------------------------------------------------------
+def phonon_rate(sys, f, nph, g2=None):
+    """dN/dt [Nq, n_modes] from electron-phonon processes over the channel list.
+
+    A channel (i, j, nu) with q = k_j - k_i (on the q grid) carries four
+    golden-rule processes: i -> j absorbing (nu, q) and its reverse j -> i
+    emitting (nu, q), both with the delta G(e_i - e_j + hw); and i -> j
+    emitting (nu, -q) with its reverse absorbing (nu, -q), both with
+    G(e_i - e_j - hw).  Phonon (nu, q) gains the emissions and loses the
+    absorptions:
+      dN(nu, q)  += Cp |g|^2 G(e_i - e_j + hw) [(N+1) f_j (1 - f_i) - N f_i (1 - f_j)]
+      dN(nu, -q) += Cp |g|^2 G(e_i - e_j - hw) [(N+1) f_i (1 - f_j) - N f_j (1 - f_i)]
+    with N and hw of the bin (tables even in q), Cp = 2 pi / (hbar N_k) and
+    N_k the full k-grid count (the electron side carries 1 / N_q)."""
+    kg = np.asarray(sys.kgrid, np.int64)
+    qg = np.asarray(sys.qgrid, np.int64)
+    nm = int(sys.n_modes)
+    k = np.asarray(sys.state_k, np.int64)
+    kc = np.stack([k // (kg[1] * kg[2]), (k // kg[2]) % kg[1], k % kg[2]], axis=1)
+    ci = np.asarray(sys.ch_i, np.int64)
+    cj = np.asarray(sys.ch_j, np.int64)
+    nu = np.asarray(sys.ch_nu, np.int64)
+    g = np.asarray(sys.g2 if g2 is None else g2, np.float64)
+    ratio = kg // qg
+
+    def qlin(dk):
+        q = (dk % kg) // ratio
+        return (q[:, 0] * qg[1] + q[:, 1]) * qg[2] + q[:, 2]
+
+    qp = qlin(kc[cj] - kc[ci])          # q = k_j - k_i
+    qm = qlin(kc[ci] - kc[cj])          # -q
+    hw = np.asarray(sys.hw, np.float64)
+    N = np.asarray(nph, np.float64)
+    eps = np.asarray(sys.eps, np.float64)
+    f = np.asarray(f, np.float64)
+    sig = float(sys.sigma)
+    G = lambda x: np.exp(-0.5 * (x / sig) ** 2) / (sig * np.sqrt(2.0 * np.pi))
+    Cp = 2.0 * np.pi / (HBAR_EV_FS * float(np.prod(kg)))
+    d = eps[ci] - eps[cj]
+    w1, n1 = hw[qp, nu], N[qp, nu]
+    w2, n2 = hw[qm, nu], N[qm, nu]
+    y1 = Cp * g * G(d + w1) * ((n1 + 1) * f[cj] * (1 - f[ci]) - n1 * f[ci] * (1 - f[cj]))
+    y2 = Cp * g * G(d - w2) * ((n2 + 1) * f[ci] * (1 - f[cj]) - n2 * f[cj] * (1 - f[ci]))
+    out = np.zeros(hw.size)
+    np.add.at(out, qp * nm + nu, y1)
+    np.add.at(out, qm * nm + nu, y2)
+    return out.reshape(hw.shape)
 
 
 # ---------------------------------------------------------------------------

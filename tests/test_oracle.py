@@ -244,6 +244,66 @@ def test_elastic_dissipation_identity():
     assert np.abs(oracle.collision_elastic(s, np.full(s.n_states, 0.37))).max() == 0.0
 
 
+# ------------------------------------------------- phonon side (dN/dt)
+def _fine_ladder():
+    """The resonant ladder with every k doubled on a k grid twice as fine
+    as the q grid: pairs stay commensurate and N_k = 8 N_q."""
+    import copy
+    s = synth.ladder_system()
+    r = copy.copy(s)
+    kg = np.asarray(s.kgrid)
+    c = synth.grid_coords(s.kgrid)[s.state_k] * 2
+    r.kgrid = tuple(int(x) for x in 2 * kg)
+    r.state_k = synth.linear_index(c, r.kgrid).astype(np.int32)
+    return r
+
+
+def test_phonon_rate_two_state_by_hand():
+    """One channel on a 3-point ring: q = 1 and -q = 2 get the emission minus
+    absorption of their own processes, q = 0 gets nothing."""
+    dE, hw, g2, sig, N = 0.045, 0.05, 2e-3, 0.01, 0.3
+    s = synth.two_state_system(dE=dE, hw=hw, g2=g2, sigma=sig, nq=3)
+    f = np.array([0.2, 0.7])
+    nph = np.full((3, 1), N)
+    dN = oracle.phonon_rate(s, f, nph)[:, 0]
+    Cp = 2 * math.pi / (HBAR * 3)
+    up = Cp * g2 * _G(-dE + hw, sig) * ((N + 1) * f[1] * (1 - f[0]) - N * f[0] * (1 - f[1]))
+    dn = Cp * g2 * _G(-dE - hw, sig) * ((N + 1) * f[0] * (1 - f[1]) - N * f[1] * (1 - f[0]))
+    assert dN[0] == 0.0
+    assert dN[1] == pytest.approx(up, rel=1e-14)
+    assert dN[2] == pytest.approx(dn, rel=1e-14)
+
+
+def test_phonon_rate_conserves_energy_with_the_electrons():
+    """On a resonant system every process moves exactly hw between the
+    electrons and one phonon: (1/N_k) sum e_s I_s + (1/N_q) sum hw dN = 0,
+    with I from the C loop of Eq. 2 (N_k = 8 N_q here)."""
+    s = _fine_ladder()
+    assert np.prod(s.kgrid) == 8 * np.prod(s.qgrid)
+    f = 0.3 + 0.4 * synth.random_occupations(s, 5)
+    nph = np.full_like(s.hw, 0.7)
+    I = oracle.collision(s, f, nph)
+    dN = oracle.phonon_rate(s, f, nph)
+    e_el = float(s.eps @ I) / np.prod(s.kgrid)
+    e_ph = float((s.hw * dN).sum()) / np.prod(s.qgrid)
+    assert abs(e_ph) > 0
+    assert abs(e_el + e_ph) <= 1e-13 * abs(e_ph)
+
+
+def test_phonon_rate_detailed_balance_and_empty_bands():
+    """At Fermi-Dirac / Bose-Einstein equilibrium of one temperature the
+    resonant processes balance, so dN = 0; empty and full bands give 0."""
+    s = _fine_ladder()
+    T = 300.0
+    f = synth.fermi_dirac(s.eps, 0.1, T)
+    nph = s.nph(T)
+    hot = oracle.phonon_rate(s, synth.fermi_dirac(s.eps, 0.1, 2 * T), nph)
+    assert np.abs(hot).max() > 0
+    assert np.abs(oracle.phonon_rate(s, f, nph)).max() <= 1e-13 * np.abs(hot).max()
+    assert np.abs(oracle.phonon_rate(s, np.zeros(s.n_states), nph)).max() == 0.0
+    assert np.abs(oracle.phonon_rate(s, np.ones(s.n_states), nph)).max() == 0.0
+
+
 # ------------------------------------------------------ drift term (Eq. 1)
 def _ring(n=16, with_channels=False):
     """One band on an n x 1 x 1 periodic grid, every state present."""
