@@ -206,6 +206,21 @@ ephbte_status ephbte_collision_vjp(ephbte_plan plan, int32_t batch, const void *
                                    double *gg2, int32_t accumulate_gg2, void *stream);
 
 /*
+ * Phonon side of the same processes (coupled electron-phonon dynamics; the
+ * paper cites this use of the method): dN/dt of every phonon (q, mode) from
+ * the channel list.  Each entry (d, p, nu) adds, to the bin of phonon
+ * (nu, q = k_p - k_d), its net emission Kp |g|^2 G(e_d - e_p + hw)
+ * [(N + 1) f_p (1 - f_d) - N f_d (1 - f_p)], with Kp = 2 pi / (hbar N_k) and
+ * N_k the full k-grid count.  Elastic mechanisms add nothing.
+ * f: device [S] (one vector), plan dtype.  nph: device [Nq][n_modes].
+ * dN: device [Nq][n_modes], plan dtype, written (1/fs).
+ * Bins are summed as 64-bit fixed point with integer atomics (bitwise
+ * reproducible).  The first call allocates the bins.
+ */
+ephbte_status ephbte_phonon_rate(ephbte_plan plan, const void *f, const void *nph, void *dN,
+                                 void *stream);
+
+/*
  * Field term of Eq. 1 for ephbte_rt_step and ephbte_rt_adjoint: they then
  * integrate df/dt = -(1/hbar) F . grad_k f + I[f].  The k derivative along grid
  * axis a is the central difference inside the state's band, periodic over the

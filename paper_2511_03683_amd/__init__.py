@@ -6,12 +6,12 @@ Importing it loads the library and fails if it has not been built.
 """
 from .binding import (F32, F64, EphbteError, Plan, autotune, build_channels, collision_integral,
                       collision_vjp, destroy, iterate_transport, last_error, layout_host,
-                      load_library, plan_bytes, plan_info, rt_adjoint, rt_step, set_field,
-                      set_tuning, status_string, update_g2)
+                      load_library, phonon_rate, plan_bytes, plan_info, rt_adjoint, rt_step,
+                      set_field, set_tuning, status_string, update_g2)
 
 load_library()
 
 __all__ = ["F32", "F64", "EphbteError", "Plan", "autotune", "build_channels",
            "collision_integral", "collision_vjp", "destroy", "iterate_transport", "last_error",
-           "layout_host", "load_library", "plan_bytes", "plan_info", "rt_adjoint", "rt_step",
-           "set_field", "set_tuning", "status_string", "update_g2"]
+           "layout_host", "load_library", "phonon_rate", "plan_bytes", "plan_info", "rt_adjoint",
+           "rt_step", "set_field", "set_tuning", "status_string", "update_g2"]

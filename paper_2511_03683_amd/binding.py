@@ -74,6 +74,7 @@ SYMBOLS = {
     "ephbte_autotune": ([_P, ctypes.c_int32, ctypes.POINTER(Tuning), ctypes.c_char_p], ctypes.c_int32),
     "ephbte_plan_info": ([_P, _P], ctypes.c_int32),
     "ephbte_set_field": ([_P, _P], ctypes.c_int32),
+    "ephbte_phonon_rate": ([_P, _P, _P, _P, _P], ctypes.c_int32),
     "ephbte_plan_bytes": ([_P], ctypes.c_int64),
     "ephbte_destroy": ([_P], None),
     "ephbte_status_string": ([ctypes.c_int32], ctypes.c_char_p),
@@ -419,6 +420,25 @@ def autotune(plan: Plan, batch: int = 1, cache_path: Optional[str] = None) -> di
     _check(load_library().ephbte_autotune(plan.handle, int(batch), ctypes.byref(t), path), "autotune")
     return dict(chunk_entries=t.chunk_entries, block_threads=t.block_threads, xcd_map=t.xcd_map,
                 batch_partners=t.batch_partners, tile_entries=t.tile_entries)
+
+
+def phonon_rate(plan: Plan, f, nph, out=None):
+    """dN/dt [Nq, n_modes] of the phonons from the channel list for f [S]."""
+    import torch
+    B, _ = _batch(plan, f, "f")
+    if f.dim() != 1:
+        raise ValueError("phonon_rate takes one occupation vector f [S]")
+    _dev_tensor(plan, nph, "nph")
+    if nph.numel() != plan.n_q * plan.n_modes or not nph.is_contiguous():
+        raise ValueError("nph must be a contiguous [Nq, n_modes] tensor")
+    if out is None:
+        out = torch.empty((plan.n_q, plan.n_modes), dtype=plan.torch_dtype, device=f.device)
+    _dev_tensor(plan, out, "out")
+    if out.numel() != plan.n_q * plan.n_modes or not out.is_contiguous():
+        raise ValueError("out must be a contiguous [Nq, n_modes] tensor")
+    _check(load_library().ephbte_phonon_rate(plan.handle, f.data_ptr(), nph.data_ptr(),
+                                             out.data_ptr(), _stream(f.device)), "phonon_rate")
+    return out
 
 
 def set_field(plan: Plan, rates) -> None:

@@ -77,6 +77,13 @@ struct ephbte_plan_s {
     bool nbr_ok = false;
     double drift_rate[3] = {0.0, 0.0, 0.0};
     bool drift_on = false;
+    // phonon side: elastic-mode mask, full k-grid count, largest entry count
+    // of a (q, mode) bin (host, at build), device bound and bins
+    uint32_t elastic = 0;
+    double nk = 1.0;
+    double ph_count = 0.0;
+    unsigned long long *ph_gmax_bits = nullptr, *ph_bound_bits = nullptr, *ph_bins = nullptr;
+    bool ph_dirty = true;   // the bound needs max |g|^2 again (after build, update_g2)
     int nq[3] = {0, 0, 0};
     double sigma = 0, nqnorm = 0;
     std::vector<int64_t> row_ptr;   // host copy for re-chunking
@@ -221,7 +228,8 @@ void free_plan(ephbte_plan P) {
                      (void **)&P->sym_dest_chunk, (void **)&P->sym_tiles, (void **)&P->jacc,
                      (void **)&P->nmax_bits, (void **)&P->gmax_bits, (void **)&P->pack_bmax,
                      (void **)&P->drop_idx, (void **)&P->vbtiles, (void **)&P->vsub_off,
-                     (void **)&P->nbr};
+                     (void **)&P->nbr, (void **)&P->ph_gmax_bits, (void **)&P->ph_bound_bits,
+                     (void **)&P->ph_bins};
     for (auto pp : ptrs) dfree(*pp);
     DevBuf *w[] = {&P->part,   &P->sym_part, &P->rk_ua,  &P->rk_ub,   &P->rk_acc, &P->hwN, &P->tr_W,   &P->tr_tau_inv,
                    &P->tr_tau, &P->tr_rhs, &P->tr_xa,   &P->tr_xb,  &P->tr_part, &P->tr_red,
@@ -1394,6 +1402,43 @@ ephbte_status ephbte_build_channels(const ephbte_problem *problem, const ephbte_
         P->nch = L.n_input;
         P->nch_kept = L.n_channels;
         P->E = L.E;
+        P->elastic = opts ? opts->elastic_modes : 0u;
+        P->nk = static_cast<double>(problem->kgrid[0]) * problem->kgrid[1] * problem->kgrid[2];
+        {
+            // largest number of entries of one (q, mode) bin of the phonon side
+            const int64_t nq0 = L.nq[0], nq1 = L.nq[1], nq2 = L.nq[2], nm = L.n_modes;
+            const int64_t nbin = nq0 * nq1 * nq2 * nm;
+            const int T = host_threads();
+            std::vector<std::vector<int32_t>> cnt(T);
+            parallel_ranges(L.S, T, [&](int t, int64_t b, int64_t e) {
+                auto &h = cnt[t];
+                h.assign(static_cast<size_t>(nbin), 0);
+                for (int64_t d = b; d < e; ++d) {
+                    const uint32_t kd = L.kq[d];
+                    for (int64_t x = L.row_ptr[d]; x < L.row_ptr[d + 1]; ++x) {
+                        const uint32_t pn = L.pnu[x];
+                        const int mode = static_cast<int>(pn & 7u);
+                        if ((P->elastic >> mode) & 1u) continue;
+                        const uint32_t kp = L.kq[pn >> 3];
+                        int64_t a0 = int64_t(kp >> 20) - int64_t(kd >> 20);
+                        int64_t a1 = int64_t((kp >> 10) & 1023u) - int64_t((kd >> 10) & 1023u);
+                        int64_t a2 = int64_t(kp & 1023u) - int64_t(kd & 1023u);
+                        a0 += a0 < 0 ? nq0 : 0;
+                        a1 += a1 < 0 ? nq1 : 0;
+                        a2 += a2 < 0 ? nq2 : 0;
+                        ++h[static_cast<size_t>(((a0 * nq1 + a1) * nq2 + a2) * nm + mode)];
+                    }
+                }
+            });
+            int64_t best = 0;
+            for (int64_t i = 0; i < nbin; ++i) {
+                int64_t c = 0;
+                for (auto &h : cnt)
+                    if (!h.empty()) c += h[static_cast<size_t>(i)];
+                best = std::max(best, c);
+            }
+            P->ph_count = static_cast<double>(best);
+        }
         P->nbr_ok = !L.nbr.empty();
         if (P->nbr_ok) {
             dalloc(P->nbr, sizeof(int32_t) * L.nbr.size(), &P->layout_bytes);
@@ -1650,6 +1695,55 @@ ephbte_status ephbte_update_g2(ephbte_plan plan, const double *g2, void *stream)
                                plan->E);
         HIPC(hipGetLastError());
         update_gmax(plan, s);
+        plan->ph_dirty = true;
+        return EPHBTE_OK;
+    });
+}
+
+ephbte_status ephbte_phonon_rate(ephbte_plan plan, const void *f, const void *nph, void *dN,
+                                 void *stream) {
+    return guarded(plan, stream, [&]() -> ephbte_status {
+        if (!f || !nph || !dN) return fail(EPHBTE_INVALID_ARGUMENT, "f, nph and dN must be non-NULL");
+        const int64_t nbin = static_cast<int64_t>(plan->nq[0]) * plan->nq[1] * plan->nq[2] * plan->nm;
+        if (overlaps(dN, esize(plan) * nbin, f, esize(plan) * plan->S))
+            return fail(EPHBTE_INVALID_ARGUMENT, "dN must not overlap f");
+        hipStream_t s = as_stream(stream);
+        if (!plan->ph_bins) {
+            size_t dummy = 0;
+            dalloc(plan->ph_bins, sizeof(unsigned long long) * std::max<int64_t>(nbin, 1), &dummy);
+            dalloc(plan->ph_gmax_bits, sizeof(unsigned long long), &dummy);
+            dalloc(plan->ph_bound_bits, sizeof(unsigned long long), &dummy);
+            HIPC(hipMemset(plan->ph_bins, 0, sizeof(unsigned long long) * std::max<int64_t>(nbin, 1)));
+        }
+        auto run = [&](auto tag) {
+            using T = decltype(tag);
+            ensure_fwd<T>(plan, 1);
+            enqueue_pack<T>(plan, nph, s);
+            if (plan->ph_dirty) {
+                hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, plan->ph_gmax_bits, 1);
+                const unsigned nb = static_cast<unsigned>(std::max<int64_t>(
+                    std::min<int64_t>((plan->E + 255) / 256, 4096), 1));
+                hipLaunchKernelGGL((k_abs_max_bits<T>), dim3(nb), dim3(256), 0, s,
+                                   static_cast<const T *>(plan->g2), plan->E, plan->ph_gmax_bits);
+                hipLaunchKernelGGL(k_phonon_bound, dim3(1), dim3(64), 0, s,
+                                   (const unsigned long long *)plan->ph_gmax_bits, plan->ph_count,
+                                   plan->ph_bound_bits);
+                plan->ph_dirty = false;
+            }
+            TiledArgs<T> a = tiled_args<T>(plan);
+            if (plan->n_chunks > 0)
+                hipLaunchKernelGGL((k_phonon_rate<T>), dim3(static_cast<unsigned>(plan->n_chunks)), dim3(256), 0, s,
+                                   a, static_cast<const T *>(f), plan->elastic,
+                                   (const unsigned long long *)plan->ph_bound_bits, plan->ph_bins);
+            const double Kp = 2.0 * kPi / (kHbar * plan->nk) / (plan->sigma * std::sqrt(2.0 * kPi));
+            const unsigned nf = static_cast<unsigned>(std::max<int64_t>(std::min<int64_t>((nbin + 255) / 256, 4096), 1));
+            hipLaunchKernelGGL((k_phonon_finish<T>), dim3(nf), dim3(256), 0, s, plan->ph_bins, nbin,
+                               (const unsigned long long *)plan->nmax_bits,
+                               (const unsigned long long *)plan->ph_bound_bits, Kp, static_cast<T *>(dN));
+            HIPC(hipGetLastError());
+        };
+        if (plan->dtype == EPHBTE_F64) run(double{});
+        else run(float{});
         return EPHBTE_OK;
     });
 }

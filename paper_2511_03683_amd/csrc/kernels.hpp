@@ -1500,6 +1500,82 @@ __global__ __launch_bounds__(512) void k_vjp_batched(BArgs<T> A, const T *__rest
     }
 }
 
+// ---- phonon side of the same processes (coupled e-ph dynamics) ----------
+// Each entry (d, p, nu) carries the processes that create or destroy phonon
+// (nu, q = k_p - k_d): d -> p absorbing it and p -> d emitting it, both with
+// the delta G(e_d - e_p + hw).  Its net emission, |g|^2 Ga [(N+1) f_p (1 - f_d)
+// - N f_d (1 - f_p)], is rounded to fixed point on the scale of sym_scale with
+// the bound phb (largest entry count of a bin times max |g|^2) and added to the
+// bin with an integer atomic, so each bin's sum does not depend on the order.
+// Entries of elastic mechanisms (bit nu of elastic) have no phonon: skipped.
+template <typename T>
+__global__ __launch_bounds__(256) void k_phonon_rate(TiledArgs<T> A, const T *__restrict__ f,
+                                                     uint32_t elastic,
+                                                     const unsigned long long *__restrict__ phb_bits,
+                                                     unsigned long long *__restrict__ bins) {
+    const int64_t c = blockIdx.x;
+    if (c >= A.n_chunks) return;
+    const int d = A.chunk_dest[c];
+    const int64_t beg = A.chunk_beg[c], end = A.chunk_beg[c + 1];
+    const StateRec<T> sd = A.st[d];
+    const T fd = f[d];
+    const T scale = static_cast<T>(sym_scale(A.nmax_bits, phb_bits));
+    for (int64_t e = beg + threadIdx.x; e < end; e += blockDim.x) {
+        const uint32_t pn = A.pnu[e];
+        const int mode = static_cast<int>(pn & 7u);
+        if ((elastic >> mode) & 1u) continue;
+        const int p = static_cast<int>(pn >> 3);
+        const StateRec<T> sp = A.st[p];
+        const int ql = q_linear(sd.kq, sp.kq, A.nq0, A.nq1, A.nq2);
+        const int qi = A.padq ? static_cast<int>(sp.kqp - sd.kqp) + A.qoff : ql;
+        const Pair2<T> wn = A.hwN[static_cast<int64_t>(qi) * A.nm + mode];
+        const T xa = (sd.eps - sp.eps) + wn.a;
+        const T da = gauss_exp(xa * xa * A.mc);
+        const T fp = f[p];
+        const T y = A.g2[e] * da * ((wn.b + T(1)) * fp * (T(1) - fd) - wn.b * fd * (T(1) - fp));
+        const unsigned long long v = to_fixed(__builtin_rint(y * scale));
+        atomicAdd(bins + static_cast<int64_t>(ql) * A.nm + mode, v);
+    }
+}
+
+// dN = Kp sum of the bin (Kp = 2 pi / (hbar N_k) / (sigma sqrt(2 pi))); clears the bins.
+template <typename T>
+__global__ void k_phonon_finish(unsigned long long *__restrict__ bins, int64_t n,
+                                const unsigned long long *__restrict__ nmax_bits,
+                                const unsigned long long *__restrict__ phb_bits, double Kp,
+                                T *__restrict__ out) {
+    const double inv = 1.0 / sym_scale(nmax_bits, phb_bits);
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const long long v = static_cast<long long>(bins[i]);
+        bins[i] = 0ull;
+        out[i] = static_cast<T>(Kp * (static_cast<double>(v) * inv));
+    }
+}
+
+// max |x| over x[0..n) as the bits of a non-negative double (integer order of
+// such bits is their numeric order, so the atomic max is order-independent)
+template <typename T>
+__global__ __launch_bounds__(256) void k_abs_max_bits(const T *__restrict__ x, int64_t n,
+                                                      unsigned long long *out) {
+    double m = 0.0;
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        m = fmax(m, fabs(static_cast<double>(x[i])));
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(out, static_cast<unsigned long long>(__double_as_longlong(m)));
+}
+
+// phb = count * max |g|^2 (the per-bin bound of the phonon-side sums)
+__global__ void k_phonon_bound(const unsigned long long *__restrict__ gmax_bits, double count,
+                               unsigned long long *__restrict__ phb_bits) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const double g = __longlong_as_double(static_cast<long long>(*gmax_bits));
+        *phb_bits = static_cast<unsigned long long>(__double_as_longlong(count * g));
+    }
+}
+
 // ---- transport ----------------------------------------------------------
 // Linearisation at f0: per entry W_dp = K g2 [da (N + 1 - f0_d) + de (N + f0_d)]
 // is stored; 1/tau_d = K sum g2 [da (N + f0_p) + de (N + 1 - f0_p)].

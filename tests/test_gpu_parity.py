@@ -607,6 +607,52 @@ def test_elastic_mechanism(E, dtype):
     plan.close()
 
 
+PH_SYSTEMS = {
+    "multiband": lambda: synth.multiband_system(),
+    "tb24": lambda: synth.tb_system(kn=24, qn=12, target_states=400),
+    "parabolic8": lambda: synth.parabolic_system(8),
+}
+
+
+@pytest.mark.parametrize("name,dtype", [(n, d) for n in PH_SYSTEMS for d in ("f64", "f32")])
+def test_phonon_rate_matches_oracle(E, name, dtype):
+    """dN/dt of every (q, mode) against the oracle; bitwise repeatable; the
+    bins are cleared between calls; update_g2 rescales it."""
+    s = PH_SYSTEMS[name]()
+    f = synth.random_occupations(s, 50)
+    nph = s.nph(300.0)
+    r, tdt, tol = s, torch.float64, TOL64
+    if dtype == "f32":
+        f, nph = f.astype(np.float32).astype(np.float64), nph.astype(np.float32).astype(np.float64)
+        r, tdt, tol = round32(s), torch.float32, TOL32
+    plan = E.build_channels(s, dtype=dtype, device=0)
+    say(f"phonon rate {name} {dtype} S={s.n_states} Nch={s.n_channels}")
+    got = host(E.phonon_rate(plan, dev(f, tdt), dev(nph, tdt)))
+    ref = oracle.phonon_rate(r, f, nph)
+    assert np.abs(ref).max() > 0
+    assert nerr(got, ref) <= tol
+    again = host(E.phonon_rate(plan, dev(f, tdt), dev(nph, tdt)))
+    assert np.array_equal(again, got)
+    E.update_g2(plan, dev(3.0 * s.g2))
+    tri = host(E.phonon_rate(plan, dev(f, tdt), dev(nph, tdt)))
+    assert nerr(tri, 3.0 * ref) <= tol
+    plan.close()
+
+
+def test_phonon_rate_skips_elastic_mechanisms(E):
+    s = synth.defect_system(6, with_phonons=True)
+    e = s.meta["elastic_mode"]
+    f = synth.random_occupations(s, 51)
+    nph = s.nph(300.0)
+    plan = E.build_channels(s, device=0, elastic_modes=1 << e)
+    say("phonon rate with an elastic mechanism")
+    got = host(E.phonon_rate(plan, dev(f), dev(nph)))
+    ref = oracle.phonon_rate(oracle.subset(s, np.asarray(s.ch_nu) != e), f, nph)
+    assert np.all(got[:, e] == 0.0)
+    assert nerr(got, ref) <= TOL64
+    plan.close()
+
+
 def test_autograd_function(E):
     from paper_2511_03683_amd.autograd import collision
     s = synth.multiband_system()
