@@ -387,6 +387,39 @@ def rk4_step(sys, f, nph, dt, g2=None, return_stages=False, rates=None, nbr=None
     return (out, (u1, u2, u3, u4)) if return_stages else out
 
 
+def even_in_q(sys, x):
+    """(x(q) + x(-q)) / 2 of a [Nq, n_modes] table."""
+    qg = np.asarray(sys.qgrid, np.int64)
+    q = np.arange(int(np.prod(qg)))
+    c = np.stack([q // (qg[1] * qg[2]), (q // qg[2]) % qg[1], q % qg[2]], axis=1)
+    m = (-c) % qg
+    qm = (m[:, 0] * qg[1] + m[:, 1]) * qg[2] + m[:, 2]
+    x = np.asarray(x, np.float64)
+    return 0.5 * (x + x[qm])
+
+
+def rk4_coupled_step(sys, f, nph, dt, g2=None):
+    """One classical RK4 step of the coupled system df/dt = I[f, N],
+    dN/dt = even part in q of phonon_rate(f, N): electrons and phonons
+    advanced together.  Eq. 2 evaluates each orientation of a channel with N
+    at its own q, which is exact for N even in q; the phonons of q and -q are
+    therefore evolved as a pair (the even part of the rate), which keeps N even
+    and, with hw even, leaves every energy transfer unchanged."""
+
+    def rhs(u, M):
+        return collision(sys, u, M, g2=g2), even_in_q(sys, phonon_rate(sys, u, M, g2=g2))
+    u1, M1 = np.array(f, dtype=np.float64), np.array(nph, dtype=np.float64)
+    k1, p1 = rhs(u1, M1)
+    u2, M2 = u1 + 0.5 * dt * k1, M1 + 0.5 * dt * p1
+    k2, p2 = rhs(u2, M2)
+    u3, M3 = u1 + 0.5 * dt * k2, M1 + 0.5 * dt * p2
+    k3, p3 = rhs(u3, M3)
+    u4, M4 = u1 + dt * k3, M1 + dt * p3
+    k4, p4 = rhs(u4, M4)
+    return (u1 + (dt / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4),
+            M1 + (dt / 6.0) * (p1 + 2.0 * p2 + 2.0 * p3 + p4))
+
+
 def rk4_adjoint_step(sys, stages, nph, dt, gbar, g2=None, rates=None, nbr=None):
     """Reverse of one RK4 step.  Given gbar = dL/df_{n+1} and the stage inputs
     (u1..u4) of the step, return (dL/df_n, dL/dg2 contribution of the step).

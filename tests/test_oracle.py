@@ -304,6 +304,53 @@ def test_phonon_rate_detailed_balance_and_empty_bands():
     assert np.abs(oracle.phonon_rate(s, np.ones(s.n_states), nph)).max() == 0.0
 
 
+def test_coupled_rk4_keeps_energy_and_particles():
+    """Electrons and phonons stepped together: total energy per cell
+    (1/N_k) sum e f + (1/N_q) sum hw N and the electron count are linear
+    invariants of the resonant system, which RK4 keeps to rounding, while the
+    phonons do change; at a common-temperature equilibrium nothing moves."""
+    s = _fine_ladder()
+    nk, nq = float(np.prod(s.kgrid)), float(np.prod(s.qgrid))
+    f = 0.2 + 0.5 * synth.random_occupations(s, 8)
+    N = np.full_like(s.hw, 0.4)
+    etot = lambda f_, N_: float(s.eps @ f_) / nk + float((s.hw * N_).sum()) / nq
+    e0, n0 = etot(f, N), f.sum()
+    f1, N1 = f, N
+    for _ in range(5):
+        f1, N1 = oracle.rk4_coupled_step(s, f1, N1, 0.5)
+    assert np.abs(N1 - N).max() > 1e-6
+    assert abs(etot(f1, N1) - e0) <= 1e-13 * abs(e0)
+    assert abs(f1.sum() - n0) <= 1e-13 * n0
+    T = 300.0
+    feq, Neq = synth.fermi_dirac(s.eps, 0.1, T), s.nph(T)
+    f2, N2 = oracle.rk4_coupled_step(s, feq, Neq, 0.5)
+    assert np.abs(f2 - feq).max() <= 1e-13 and np.abs(N2 - Neq).max() <= 1e-13 * Neq.max()
+
+
+def test_coupled_rk4_fourth_order():
+    """The error of one coupled step against a fine-step solution, over the
+    same interval, is 16 times that of two half steps for a fourth-order
+    method (2^5 / 2), electrons and phonons alike; a stage input left at the
+    step's start drops it towards 4."""
+    s = synth.multiband_system()
+    f0 = 0.1 + 0.8 * synth.random_occupations(s, 3)
+    N0 = s.nph(300.0) * 1.5
+
+    def run(dt, n):
+        f, N = f0, N0
+        for _ in range(n):
+            f, N = oracle.rk4_coupled_step(s, f, N, dt)
+        return f, N
+    T = 0.5
+    fr, Nr = run(T / 64, 64)
+    f1, N1 = run(T, 1)
+    f2, N2 = run(T / 2, 2)
+    rf = np.abs(f1 - fr).max() / np.abs(f2 - fr).max()
+    rN = np.abs(N1 - Nr).max() / np.abs(N2 - Nr).max()
+    assert np.abs(N1 - N0).max() > 1e-6
+    assert 12 < rf < 24 and 12 < rN < 24, (rf, rN)
+
+
 # ------------------------------------------------------ drift term (Eq. 1)
 def _ring(n=16, with_channels=False):
     """One band on an n x 1 x 1 periodic grid, every state present."""
