@@ -221,6 +221,21 @@ ephbte_status ephbte_phonon_rate(ephbte_plan plan, const void *f, const void *np
                                  void *stream);
 
 /*
+ * Coupled electron-phonon dynamics: advances f (device [S]) and the phonon
+ * occupations nph (device [Nq][n_modes]) together, in place, by n_steps
+ * classical RK4 steps of dt_fs: df/dt = I[f, N] (Eq. 2), dN/dt = the even
+ * part in q of the rate of ephbte_phonon_rate.  Eq. 2 evaluates each
+ * orientation of a channel with N at its own q, which is exact for N even in
+ * q; the phonons of q and -q therefore evolve as a pair, which keeps an even
+ * N even and, with hw even, moves the same energy.  Each stage packs the
+ * stage's N and runs the electron pass (stage update fused in its epilogue)
+ * and the phonon pass.  B = 1; no HIP graph.
+ * Currently switched off: n_steps > 0 returns INVALID_ARGUMENT.
+ */
+ephbte_status ephbte_rt_step_coupled(ephbte_plan plan, void *f, void *nph, double dt_fs,
+                                     int32_t n_steps, void *stream);
+
+/*
  * Field term of Eq. 1 for ephbte_rt_step and ephbte_rt_adjoint: they then
  * integrate df/dt = -(1/hbar) F . grad_k f + I[f].  The k derivative along grid
  * axis a is the central difference inside the state's band, periodic over the

@@ -7,11 +7,11 @@ Importing it loads the library and fails if it has not been built.
 from .binding import (F32, F64, EphbteError, Plan, autotune, build_channels, collision_integral,
                       collision_vjp, destroy, iterate_transport, last_error, layout_host,
                       load_library, phonon_rate, plan_bytes, plan_info, rt_adjoint, rt_step,
-                      set_field, set_tuning, status_string, update_g2)
+                      rt_step_coupled, set_field, set_tuning, status_string, update_g2)
 
 load_library()
 
 __all__ = ["F32", "F64", "EphbteError", "Plan", "autotune", "build_channels",
            "collision_integral", "collision_vjp", "destroy", "iterate_transport", "last_error",
            "layout_host", "load_library", "phonon_rate", "plan_bytes", "plan_info", "rt_adjoint",
-           "rt_step", "set_field", "set_tuning", "status_string", "update_g2"]
+           "rt_step", "rt_step_coupled", "set_field", "set_tuning", "status_string", "update_g2"]

@@ -75,6 +75,7 @@ SYMBOLS = {
     "ephbte_plan_info": ([_P, _P], ctypes.c_int32),
     "ephbte_set_field": ([_P, _P], ctypes.c_int32),
     "ephbte_phonon_rate": ([_P, _P, _P, _P, _P], ctypes.c_int32),
+    "ephbte_rt_step_coupled": ([_P, _P, _P, ctypes.c_double, ctypes.c_int32, _P], ctypes.c_int32),
     "ephbte_plan_bytes": ([_P], ctypes.c_int64),
     "ephbte_destroy": ([_P], None),
     "ephbte_status_string": ([ctypes.c_int32], ctypes.c_char_p),
@@ -439,6 +440,20 @@ def phonon_rate(plan: Plan, f, nph, out=None):
     _check(load_library().ephbte_phonon_rate(plan.handle, f.data_ptr(), nph.data_ptr(),
                                              out.data_ptr(), _stream(f.device)), "phonon_rate")
     return out
+
+
+def rt_step_coupled(plan: Plan, f, nph, dt_fs: float, n_steps: int):
+    """Advance f [S] and nph [Nq, n_modes] (in place) together by n_steps
+    coupled RK4 steps (see ephbte_rt_step_coupled)."""
+    B, _ = _batch(plan, f, "f")
+    if f.dim() != 1 or not f.is_contiguous():
+        raise ValueError("rt_step_coupled takes one contiguous occupation vector f [S]")
+    _dev_tensor(plan, nph, "nph")
+    if nph.numel() != plan.n_q * plan.n_modes or not nph.is_contiguous():
+        raise ValueError("nph must be a contiguous [Nq, n_modes] tensor")
+    _check(load_library().ephbte_rt_step_coupled(plan.handle, f.data_ptr(), nph.data_ptr(), float(dt_fs),
+                                                 int(n_steps), _stream(f.device)), "rt_step_coupled")
+    return f, nph
 
 
 def set_field(plan: Plan, rates) -> None:

@@ -142,6 +142,7 @@ struct ephbte_plan_s {
     DevBuf part, sym_part, rk_ua, rk_ub, rk_acc, hwN;
     DevBuf tr_W, tr_tau_inv, tr_tau, tr_rhs, tr_xa, tr_xb, tr_part, tr_red, tr_red2;
     DevBuf adj_ck, adj_U, adj_la, adj_lb, adj_acc, adj_g, adj_f;
+    DevBuf cp_Ma, cp_Mb, cp_acc, cp_rate;   // coupled step: phonon stages, sum, rate
     double *host_red = nullptr;   // pinned
     hipStream_t own_stream = nullptr;
     hipEvent_t ev_a = nullptr, ev_b = nullptr;
@@ -158,7 +159,8 @@ struct ephbte_plan_s {
         size_t b = layout_bytes;
         const DevBuf *w[] = {&part,  &sym_part, &rk_ua, &rk_ub, &rk_acc, &hwN, &tr_W,  &tr_tau_inv, &tr_tau,
                              &tr_rhs, &tr_xa, &tr_xb, &tr_part, &tr_red, &tr_red2, &adj_ck,
-                             &adj_U, &adj_la, &adj_lb, &adj_acc, &adj_g, &adj_f};
+                             &adj_U, &adj_la, &adj_lb, &adj_acc, &adj_g, &adj_f, &cp_Ma, &cp_Mb,
+                             &cp_acc, &cp_rate};
         for (auto *x : w) b += x->bytes;
         return b;
     }
@@ -234,7 +236,7 @@ void free_plan(ephbte_plan P) {
     DevBuf *w[] = {&P->part,   &P->sym_part, &P->rk_ua,  &P->rk_ub,   &P->rk_acc, &P->hwN, &P->tr_W,   &P->tr_tau_inv,
                    &P->tr_tau, &P->tr_rhs, &P->tr_xa,   &P->tr_xb,  &P->tr_part, &P->tr_red,
                    &P->tr_red2, &P->adj_ck, &P->adj_U,  &P->adj_la, &P->adj_lb, &P->adj_acc,
-                   &P->adj_g,  &P->adj_f};
+                   &P->adj_g,  &P->adj_f, &P->cp_Ma, &P->cp_Mb, &P->cp_acc, &P->cp_rate};
     for (auto *b : w) dfree(b->p);
     if (P->host_red) (void)hipHostFree(P->host_red);
     if (P->ev_a) (void)hipEventDestroy(P->ev_a);
@@ -1070,6 +1072,125 @@ ephbte_status rt_adjoint_impl(ephbte_plan P, const T *f0, const void *nph, doubl
     return EPHBTE_OK;
 }
 
+// Coupled electron-phonon step, phonon side of a stage: x = even part in q of
+// the rate (the phonons of q and -q evolve as a pair, so N stays even in q as
+// Eq. 2's per-orientation evaluation assumes), then the RK4 stage update of N
+// (modes as EPI_RK1 .. EPI_RK4).
+template <typename T>
+__global__ void k_rk_even(int mode, const T *__restrict__ N0, const T *__restrict__ rate,
+                          T *__restrict__ acc, T *__restrict__ out, T dt, int n0, int n1, int n2,
+                          int nm) {
+    const int64_t n = static_cast<int64_t>(n0) * n1 * n2 * nm;
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t q = i / nm;
+        const int nu = static_cast<int>(i - q * nm);
+        const int a2 = static_cast<int>(q % n2), a1 = static_cast<int>((q / n2) % n1),
+                  a0 = static_cast<int>(q / (static_cast<int64_t>(n1) * n2));
+        const int64_t qm = (static_cast<int64_t>((n0 - a0) % n0) * n1 + (n1 - a1) % n1) * n2 + (n2 - a2) % n2;
+        const T v = T(0.5) * (rate[i] + rate[qm * nm + nu]);
+        const T x0 = N0[i];
+        switch (mode) {
+        case EPI_RK1:
+            acc[i] = v;
+            out[i] = x0 + (dt * T(0.5)) * v;
+            break;
+        case EPI_RK2:
+            acc[i] += T(2) * v;
+            out[i] = x0 + (dt * T(0.5)) * v;
+            break;
+        case EPI_RK3:
+            acc[i] += T(2) * v;
+            out[i] = x0 + dt * v;
+            break;
+        default: out[i] = x0 + (dt / T(6)) * (acc[i] + v); break;
+        }
+    }
+}
+
+// Phonon-side rate of the stage input u into rate (the {hw, N} table and its
+// max |N| already packed from the stage's N).
+template <typename T> void enqueue_phonon_rate(ephbte_plan P, const T *u, T *rate, hipStream_t s) {
+    const int64_t nbin = static_cast<int64_t>(P->nq[0]) * P->nq[1] * P->nq[2] * P->nm;
+    if (P->ph_dirty) {
+        hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, P->ph_gmax_bits, 1);
+        const unsigned nb = static_cast<unsigned>(std::max<int64_t>(std::min<int64_t>((P->E + 255) / 256, 4096), 1));
+        hipLaunchKernelGGL((k_abs_max_bits<T>), dim3(nb), dim3(256), 0, s, static_cast<const T *>(P->g2), P->E,
+                           P->ph_gmax_bits);
+        hipLaunchKernelGGL(k_phonon_bound, dim3(1), dim3(64), 0, s, (const unsigned long long *)P->ph_gmax_bits,
+                           P->ph_count, P->ph_bound_bits);
+        P->ph_dirty = false;
+    }
+    TiledArgs<T> a = tiled_args<T>(P);
+    if (P->n_chunks > 0)
+        hipLaunchKernelGGL((k_phonon_rate<T>), dim3(static_cast<unsigned>(P->n_chunks)), dim3(256), 0, s, a, u,
+                           P->elastic, (const unsigned long long *)P->ph_bound_bits, P->ph_bins);
+    const double Kp = 2.0 * kPi / (kHbar * P->nk) / (P->sigma * std::sqrt(2.0 * kPi));
+    const unsigned nf = static_cast<unsigned>(std::max<int64_t>(std::min<int64_t>((nbin + 255) / 256, 4096), 1));
+    hipLaunchKernelGGL((k_phonon_finish<T>), dim3(nf), dim3(256), 0, s, P->ph_bins, nbin,
+                       (const unsigned long long *)P->nmax_bits, (const unsigned long long *)P->ph_bound_bits,
+                       Kp, rate);
+    HIPC(hipGetLastError());
+}
+
+// the phonon-side device state (bins, bound words), allocated on first use
+void ensure_phonon(ephbte_plan P) {
+    if (P->ph_bins) return;
+    const int64_t nbin = static_cast<int64_t>(P->nq[0]) * P->nq[1] * P->nq[2] * P->nm;
+    size_t dummy = 0;
+    dalloc(P->ph_bins, sizeof(unsigned long long) * std::max<int64_t>(nbin, 1), &dummy);
+    dalloc(P->ph_gmax_bits, sizeof(unsigned long long), &dummy);
+    dalloc(P->ph_bound_bits, sizeof(unsigned long long), &dummy);
+    HIPC(hipMemset(P->ph_bins, 0, sizeof(unsigned long long) * std::max<int64_t>(nbin, 1)));
+}
+
+template <typename T>
+ephbte_status rt_coupled_impl(ephbte_plan P, T *f, T *N, double dt, int n_steps, hipStream_t s) {
+    const int64_t S = P->S;
+    const int64_t nbin = static_cast<int64_t>(P->nq[0]) * P->nq[1] * P->nq[2] * P->nm;
+    const size_t v = sizeof(T) * static_cast<size_t>(S), vn = sizeof(T) * static_cast<size_t>(nbin);
+    ensure(P->rk_ua, v, &P->ws_gen);
+    ensure(P->rk_ub, v, &P->ws_gen);
+    ensure(P->rk_acc, v, &P->ws_gen);
+    ensure(P->cp_Ma, vn, &P->ws_gen);
+    ensure(P->cp_Mb, vn, &P->ws_gen);
+    ensure(P->cp_acc, vn, &P->ws_gen);
+    ensure(P->cp_rate, vn, &P->ws_gen);
+    ensure_fwd<T>(P, 1);
+    ensure_phonon(P);
+    T *ua = static_cast<T *>(P->rk_ua.p), *ub = static_cast<T *>(P->rk_ub.p);
+    T *acc = static_cast<T *>(P->rk_acc.p);
+    T *Ma = static_cast<T *>(P->cp_Ma.p), *Mb = static_cast<T *>(P->cp_Mb.p);
+    T *nacc = static_cast<T *>(P->cp_acc.p), *rate = static_cast<T *>(P->cp_rate.p);
+    const T tdt = static_cast<T>(dt);
+    const unsigned ng = static_cast<unsigned>(std::max<int64_t>(std::min<int64_t>((nbin + 255) / 256, 4096), 1));
+    for (int k = 0; k < n_steps; ++k) {
+        // stage inputs (u, M): (f, N), (ua, Ma), (ub, Mb), (ua, Ma); outputs to
+        // (ua, Ma), (ub, Mb), (ua, Ma) and finally (f, N)
+        const T *uin[4] = {f, ua, ub, ua};
+        const T *min_[4] = {N, Ma, Mb, Ma};
+        T *uout[4] = {ua, ub, ua, nullptr};
+        T *mout[4] = {Ma, Mb, Ma, N};
+        for (int st = 0; st < 4; ++st) {
+            enqueue_pack<T>(P, min_[st], s);
+            Epi<T> e{};
+            e.f0 = f;
+            e.ld_f0 = S;
+            e.acc = acc;
+            e.dt = tdt;
+            e.mode = EPI_RK1 + st;
+            e.u_out = uout[st];
+            e.f_out = f;
+            enqueue_forward<T>(P, 1, uin[st], S, min_[st], e, s, false);
+            enqueue_phonon_rate<T>(P, uin[st], rate, s);
+            hipLaunchKernelGGL((k_rk_even<T>), dim3(ng), dim3(256), 0, s, EPI_RK1 + st, (const T *)N,
+                               (const T *)rate, nacc, mout[st], tdt, P->nq[0], P->nq[1], P->nq[2], P->nm);
+            HIPC(hipGetLastError());
+        }
+    }
+    return EPHBTE_OK;
+}
+
 // iterations without a new smallest relative change after which the
 // transport iteration stops at its precision floor
 constexpr int kStall = 5;
@@ -1708,43 +1829,36 @@ ephbte_status ephbte_phonon_rate(ephbte_plan plan, const void *f, const void *np
         if (overlaps(dN, esize(plan) * nbin, f, esize(plan) * plan->S))
             return fail(EPHBTE_INVALID_ARGUMENT, "dN must not overlap f");
         hipStream_t s = as_stream(stream);
-        if (!plan->ph_bins) {
-            size_t dummy = 0;
-            dalloc(plan->ph_bins, sizeof(unsigned long long) * std::max<int64_t>(nbin, 1), &dummy);
-            dalloc(plan->ph_gmax_bits, sizeof(unsigned long long), &dummy);
-            dalloc(plan->ph_bound_bits, sizeof(unsigned long long), &dummy);
-            HIPC(hipMemset(plan->ph_bins, 0, sizeof(unsigned long long) * std::max<int64_t>(nbin, 1)));
-        }
+        ensure_phonon(plan);
         auto run = [&](auto tag) {
             using T = decltype(tag);
             ensure_fwd<T>(plan, 1);
             enqueue_pack<T>(plan, nph, s);
-            if (plan->ph_dirty) {
-                hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, plan->ph_gmax_bits, 1);
-                const unsigned nb = static_cast<unsigned>(std::max<int64_t>(
-                    std::min<int64_t>((plan->E + 255) / 256, 4096), 1));
-                hipLaunchKernelGGL((k_abs_max_bits<T>), dim3(nb), dim3(256), 0, s,
-                                   static_cast<const T *>(plan->g2), plan->E, plan->ph_gmax_bits);
-                hipLaunchKernelGGL(k_phonon_bound, dim3(1), dim3(64), 0, s,
-                                   (const unsigned long long *)plan->ph_gmax_bits, plan->ph_count,
-                                   plan->ph_bound_bits);
-                plan->ph_dirty = false;
-            }
-            TiledArgs<T> a = tiled_args<T>(plan);
-            if (plan->n_chunks > 0)
-                hipLaunchKernelGGL((k_phonon_rate<T>), dim3(static_cast<unsigned>(plan->n_chunks)), dim3(256), 0, s,
-                                   a, static_cast<const T *>(f), plan->elastic,
-                                   (const unsigned long long *)plan->ph_bound_bits, plan->ph_bins);
-            const double Kp = 2.0 * kPi / (kHbar * plan->nk) / (plan->sigma * std::sqrt(2.0 * kPi));
-            const unsigned nf = static_cast<unsigned>(std::max<int64_t>(std::min<int64_t>((nbin + 255) / 256, 4096), 1));
-            hipLaunchKernelGGL((k_phonon_finish<T>), dim3(nf), dim3(256), 0, s, plan->ph_bins, nbin,
-                               (const unsigned long long *)plan->nmax_bits,
-                               (const unsigned long long *)plan->ph_bound_bits, Kp, static_cast<T *>(dN));
-            HIPC(hipGetLastError());
+            enqueue_phonon_rate<T>(plan, static_cast<const T *>(f), static_cast<T *>(dN), s);
         };
         if (plan->dtype == EPHBTE_F64) run(double{});
         else run(float{});
         return EPHBTE_OK;
+    });
+}
+
+ephbte_status ephbte_rt_step_coupled(ephbte_plan plan, void *f, void *nph, double dt_fs,
+                                     int32_t n_steps, void *stream) {
+    return guarded(plan, stream, [&]() -> ephbte_status {
+        if (!f || !nph) return fail(EPHBTE_INVALID_ARGUMENT, "f and nph must be non-NULL");
+        if (n_steps < 0) return fail(EPHBTE_INVALID_ARGUMENT, "n_steps must be >= 0");
+        // switched off: the driver below is kept but not reached
+        if (n_steps > 0) return fail(EPHBTE_INVALID_ARGUMENT, "the coupled step is not available");
+        if (!std::isfinite(dt_fs)) return fail(EPHBTE_INVALID_ARGUMENT, "dt_fs must be finite");
+        const int64_t nbin = static_cast<int64_t>(plan->nq[0]) * plan->nq[1] * plan->nq[2] * plan->nm;
+        if (overlaps(nph, esize(plan) * nbin, f, esize(plan) * plan->S))
+            return fail(EPHBTE_INVALID_ARGUMENT, "nph must not overlap f");
+        if (n_steps == 0) return EPHBTE_OK;
+        hipStream_t s = as_stream(stream);
+        if (plan->dtype == EPHBTE_F64)
+            return rt_coupled_impl<double>(plan, static_cast<double *>(f), static_cast<double *>(nph), dt_fs,
+                                           n_steps, s);
+        return rt_coupled_impl<float>(plan, static_cast<float *>(f), static_cast<float *>(nph), dt_fs, n_steps, s);
     });
 }
 

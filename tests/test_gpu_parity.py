@@ -653,6 +653,35 @@ def test_phonon_rate_skips_elastic_mechanisms(E):
     plan.close()
 
 
+@pytest.mark.skip(reason="coupled step switched off: its first GPU run faulted the GPU and the "
+                         "cause was not found, so the case stays off the GPU")
+@pytest.mark.parametrize("name,dtype", [("multiband", "f64"), ("tb24", "f64"), ("multiband", "f32")])
+def test_rt_step_coupled_matches_oracle(E, name, dtype):
+    """Electrons and phonons stepped together against the oracle's coupled
+    RK4; N stays even in q."""
+    s = PH_SYSTEMS[name]()
+    f0 = 0.1 + 0.8 * synth.random_occupations(s, 52)
+    N0 = s.nph(300.0) * 1.5
+    dt, n = 1.0, 3
+    r, tdt, tol = s, torch.float64, 1e-9
+    if dtype == "f32":
+        f0, N0 = f0.astype(np.float32).astype(np.float64), N0.astype(np.float32).astype(np.float64)
+        r, tdt, tol = round32(s), torch.float32, 1e-5
+    rf, rN = f0, N0
+    for _ in range(n):
+        rf, rN = oracle.rk4_coupled_step(r, rf, rN, dt)
+    plan = E.build_channels(s, dtype=dtype, device=0)
+    say(f"coupled rt step {name} {dtype} S={s.n_states} Nch={s.n_channels}")
+    ft, Nt = dev(f0, tdt), dev(N0, tdt)
+    E.rt_step_coupled(plan, ft, Nt, dt, n)
+    gf, gN = host(ft), host(Nt)
+    assert np.abs(rN - N0).max() > 0
+    assert nerr(gf - f0, rf - f0) <= tol
+    assert nerr(gN - N0, rN - N0) <= tol
+    assert np.array_equal(oracle.even_in_q(s, gN), gN) or np.abs(oracle.even_in_q(s, gN) - gN).max() <= 1e-15 * np.abs(gN).max()
+    plan.close()
+
+
 def test_autograd_function(E):
     from paper_2511_03683_amd.autograd import collision
     s = synth.multiband_system()
