@@ -257,6 +257,14 @@ def main():
             ratio_vs_b1=(ms + ms_v) * B / (msb + msbv))
         log(f"vjp fp64 B=64: {msbv:.3f} ms ({forms['vjp_f64_b64']['ratio_vs_b1']:.2f}x per vector)")
         del F, IB, LB, ggb
+        # phonon side of the same processes (dN/dt of every (q, mode)), FP64
+        dN = torch.empty((s.n_q, s.n_modes), dtype=torch.float64, device=dev)
+        msp, _ = timed(lambda: E.phonon_rate(plan64, f64, n64, out=dN), max(3, args.steps // 4), 1)
+        forms["phonon_rate_f64"] = dict(ms=msp, channels_per_s=nch / (msp * 1e-3),
+                                        bins=int(s.n_q * s.n_modes),
+                                        note="one 64-bit integer atomic per entry into its (q, mode) bin")
+        log(f"phonon rate fp64: {msp:.3f} ms")
+        del dN
         # transport iteration, FP64
         vel = tens(s.vel, torch.float64)
         f0 = tens(synth.fermi_dirac(s.eps, -0.1, 300.0), torch.float64)
