@@ -1142,6 +1142,8 @@ void ensure_phonon(ephbte_plan P) {
     dalloc(P->ph_gmax_bits, sizeof(unsigned long long), &dummy);
     dalloc(P->ph_bound_bits, sizeof(unsigned long long), &dummy);
     HIPC(hipMemset(P->ph_bins, 0, sizeof(unsigned long long) * std::max<int64_t>(nbin, 1)));
+    // the caller's stream may not wait for the null stream: finish the clear here
+    HIPC(hipDeviceSynchronize());
 }
 
 template <typename T>
