@@ -103,8 +103,8 @@ struct ephbte_plan_s {
     int64_t n_chunks = 0;
     TileRec *tiles = nullptr;
     int64_t n_tiles = 0;
-    TileRec *vjp_tiles = nullptr;   // the reverse pass's tiles over the same chunks
-    int64_t n_vjp_tiles = 0;
+    TileRec *small_tiles = nullptr;   // half-size tiles over the same chunks (reverse pass, transport)
+    int64_t n_small_tiles = 0;
     // single-copy pass: chunks over the upper part (p > d) of each row
     int64_t *sym_chunk_beg = nullptr, *sym_chunk_end = nullptr;
     int32_t *sym_chunk_dest = nullptr, *sym_dest_chunk = nullptr;
@@ -233,7 +233,7 @@ void free_plan(ephbte_plan P) {
                      (void **)&P->nmax_bits, (void **)&P->gmax_bits, (void **)&P->pack_bmax,
                      (void **)&P->drop_idx, (void **)&P->vbtiles, (void **)&P->vsub_off,
                      (void **)&P->nbr, (void **)&P->ph_gmax_bits, (void **)&P->ph_bound_bits,
-                     (void **)&P->ph_bins, (void **)&P->vjp_tiles};
+                     (void **)&P->ph_bins, (void **)&P->small_tiles};
     for (auto pp : ptrs) dfree(*pp);
     DevBuf *w[] = {&P->part,   &P->sym_part, &P->rk_ua,  &P->rk_ub,   &P->rk_acc, &P->hwN, &P->tr_W,   &P->tr_tau_inv,
                    &P->tr_tau, &P->tr_rhs, &P->tr_xa,   &P->tr_xb,  &P->tr_part, &P->tr_red,
@@ -291,11 +291,11 @@ void upload_chunks(ephbte_plan P, int64_t chunk_entries) {
                                  ? P->tile_entries
                                  : P->E / (12 * static_cast<int64_t>(P->n_cu)) + 1;
     std::vector<Tile> tv = make_tiles(t, P->row_ptr, P->pmin, P->pmax, P->lds_states, target_v);
-    dfree(reinterpret_cast<void *&>(P->vjp_tiles));
-    dalloc(P->vjp_tiles, std::max<size_t>(tv.size(), 1) * sizeof(TileRec), &dummy);
+    dfree(reinterpret_cast<void *&>(P->small_tiles));
+    dalloc(P->small_tiles, std::max<size_t>(tv.size(), 1) * sizeof(TileRec), &dummy);
     if (!tv.empty())
-        HIPC(hipMemcpy(P->vjp_tiles, tv.data(), tv.size() * sizeof(TileRec), hipMemcpyHostToDevice));
-    P->n_vjp_tiles = static_cast<int64_t>(tv.size());
+        HIPC(hipMemcpy(P->small_tiles, tv.data(), tv.size() * sizeof(TileRec), hipMemcpyHostToDevice));
+    P->n_small_tiles = static_cast<int64_t>(tv.size());
     if (P->upper_beg.empty()) return;
     // single-copy tables over the upper parts of the rows; one workgroup per CU
     // (1024 threads), about 4 tiles each (measured; smaller tiles pay more
@@ -657,10 +657,10 @@ void enqueue_vjp(ephbte_plan P, const T *f, const T *lam, const void *nph, const
     (void)nph;
     TiledArgs<T> a = tiled_args<T>(P);
     a.xcd = 0;   // measured: plain tile order is faster for the reverse pass
-    a.tiles = P->vjp_tiles;
-    a.n_tiles = P->n_vjp_tiles;
+    a.tiles = P->small_tiles;
+    a.n_tiles = P->n_small_tiles;
     T *part = static_cast<T *>(P->part.p);
-    dim3 grid(static_cast<unsigned>(P->n_vjp_tiles));
+    dim3 grid(static_cast<unsigned>(P->n_small_tiles));
     // entries per lane and pipeline stage: 2 in FP64 keeps the two stages in
     // registers at two workgroups per compute unit
     constexpr int U = sizeof(T) == 8 ? 2 : 4;
@@ -1272,9 +1272,12 @@ ephbte_status transport_impl(ephbte_plan P, const T *f0, const T *vel, double T_
         {
             TiledArgs<T> ta = tiled_args<T>(P);
             ta.xcd = 0;
+            // half-size tiles: measured 3 % faster than the forward's here
+            ta.tiles = P->small_tiles;
+            ta.n_tiles = P->n_small_tiles;
             const size_t shm = static_cast<size_t>(P->lds_states) * 3 * sizeof(T);
             const int use_lds = shm <= P->lds_max ? 1 : 0;
-            hipLaunchKernelGGL((k_tr_tiled<T>), dim3(static_cast<unsigned>(P->n_tiles)),
+            hipLaunchKernelGGL((k_tr_tiled<T>), dim3(static_cast<unsigned>(P->n_small_tiles)),
                                dim3(P->block_threads), use_lds ? shm : 0, s, ta, use_lds,
                                (const T *)W, (const Vec4<T> *)xa, (const Vec4<T> *)rhs,
                                (const T *)tau, part, xb);
