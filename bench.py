@@ -403,7 +403,9 @@ def main():
         log(f"cpu oracle: {n / dtc:.3e} ch/s on 1 core")
 
     out = {
-        "metric": "scattering channels/sec (fwd, B=1)",
+        "metric": "scattering channels/sec and HBM GB/s (fwd, fwd+adjoint), B=1 vs B=64",
+        "value_is": "forward, B = 1, unordered channels per second (HBM GB/s in roofline; "
+                    "fwd+adjoint and B = 64 in forms)",
         "value": value,
         "unit": "channels/s",
         "n_gpus": 1,
