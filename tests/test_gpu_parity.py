@@ -983,6 +983,40 @@ def test_full_size_batched_sampled_parity(E, c2, dtype):
         assert nerr(I[b][mask], ref[mask], np.abs(I[b]).max()) <= tol, b
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_full_size_batched_vjp_sampled_parity(E, c2, dtype):
+    """The B = 64 reverse pass on the full-size system, as the benchmark times
+    it.  dL/df_d needs only the channels touching d and each dL/d|g|^2 only
+    its own channel, so the oracle runs on the channels incident to 24
+    sampled destinations, for all 64 vectors."""
+    s = c2
+    rng = np.random.default_rng(29)
+    B = 64
+    F = synth.batch_occupations(s)
+    L = rng.normal(size=(B, s.n_states))
+    nph = s.nph(300.0)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    if dtype == "f32":
+        F, L, nph = (a.astype(np.float32).astype(np.float64) for a in (F, L, nph))
+    say(f"full-size batched reverse {dtype} B={B}")
+    plan = E.build_channels(s, dtype=dtype, device=0)
+    gf, gg = E.collision_vjp(plan, dev(F, tdt), dev(nph, tdt), dev(L, tdt), gg2=True)
+    gf, gg = host(gf), host(gg)
+    plan.close()
+    dests = rng.choice(s.n_states, 24, replace=False)
+    inc = np.isin(s.ch_i, dests) | np.isin(s.ch_j, dests)
+    sub = oracle.subset(s if dtype == "f64" else round32(s), inc)
+    rf = np.zeros((B, s.n_states))
+    rg = np.zeros(int(inc.sum()))
+    for b in range(B):
+        f_b, g_b = oracle.collision_vjp(sub, F[b], nph, L[b])
+        rf[b] = f_b
+        rg += g_b
+    tol = TOL64 if dtype == "f64" else TOL32
+    assert nerr(gf[:, dests], rf[:, dests], np.abs(gf).max()) <= tol
+    assert nerr(gg[inc], rg, np.abs(gg).max()) <= tol
+
+
 # ------------------------------------------------------------------ uneven batch
 @pytest.fixture(scope="module")
 def grouped():
