@@ -1017,6 +1017,66 @@ def test_full_size_batched_vjp_sampled_parity(E, c2, dtype):
     assert nerr(gg[inc], rg, np.abs(gg).max()) <= tol
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_full_size_vjp_sampled_parity(E, c2, dtype):
+    """The B = 1 reverse pass on the full-size system: dL/df on 32 sampled
+    destinations and dL/d|g|^2 of every channel touching them, from the oracle
+    on those incident channels."""
+    s = c2
+    rng = np.random.default_rng(37)
+    f = np.clip(synth.fermi_dirac(s.eps, 0.05, 300.0) * (0.8 + 0.4 * rng.uniform(size=s.n_states)), 0, 1)
+    lam = rng.normal(size=s.n_states)
+    nph = s.nph(300.0)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    if dtype == "f32":
+        f, lam, nph = (a.astype(np.float32).astype(np.float64) for a in (f, lam, nph))
+    say(f"full-size reverse {dtype}")
+    plan = E.build_channels(s, dtype=dtype, device=0)
+    gf, gg = E.collision_vjp(plan, dev(f, tdt), dev(nph, tdt), dev(lam, tdt), gg2=True)
+    gf, gg = host(gf), host(gg)
+    plan.close()
+    dests = rng.choice(s.n_states, 32, replace=False)
+    inc = np.isin(s.ch_i, dests) | np.isin(s.ch_j, dests)
+    rf, rg = oracle.collision_vjp(oracle.subset(s if dtype == "f64" else round32(s), inc), f, nph, lam)
+    tol = TOL64 if dtype == "f64" else TOL32
+    assert nerr(gf[dests], rf[dests], np.abs(gf).max()) <= tol
+    assert nerr(gg[inc], rg, np.abs(gg).max()) <= tol
+
+
+def test_full_size_phonon_rate_sampled_parity(E, c2):
+    """dN/dt of the full-size system (FP64): a bin depends only on the
+    channels whose q or -q falls in it, so the oracle runs on the channels of
+    12 sampled (q, mode) bins and their partners at -q."""
+    s = c2
+    rng = np.random.default_rng(41)
+    f = np.clip(synth.fermi_dirac(s.eps, 0.05, 300.0) * (0.8 + 0.4 * rng.uniform(size=s.n_states)), 0, 1)
+    nph = s.nph(300.0)
+    say("full-size phonon rate")
+    plan = E.build_channels(s, device=0)
+    dN = host(E.phonon_rate(plan, dev(f), dev(nph)))
+    plan.close()
+    kg = np.asarray(s.kgrid, np.int64)
+    qg = np.asarray(s.qgrid, np.int64)
+    kc = synth.grid_coords(s.kgrid)[s.state_k].astype(np.int32)
+    r = (kg // qg).astype(np.int32)
+    qlin = np.zeros(s.n_channels, np.int64)
+    for a in range(3):
+        qa = ((kc[s.ch_j, a] - kc[s.ch_i, a]) % int(kg[a])) // int(r[a])
+        qlin = qlin * int(qg[a]) + qa
+    qneg = np.zeros(s.n_channels, np.int64)
+    for a in range(3):
+        qa = ((kc[s.ch_i, a] - kc[s.ch_j, a]) % int(kg[a])) // int(r[a])
+        qneg = qneg * int(qg[a]) + qa
+    nm = s.n_modes
+    pick = rng.choice(s.n_channels, 12, replace=False)
+    bins = np.unique(np.concatenate([qlin[pick] * nm + s.ch_nu[pick], qneg[pick] * nm + s.ch_nu[pick]]))
+    keep = np.isin(qlin * nm + s.ch_nu, bins) | np.isin(qneg * nm + s.ch_nu, bins)
+    ref = oracle.phonon_rate(oracle.subset(s, keep), f, nph).reshape(-1)
+    got = dN.reshape(-1)
+    assert np.abs(ref[bins]).max() > 0
+    assert nerr(got[bins], ref[bins], np.abs(got).max()) <= TOL64
+
+
 # ------------------------------------------------------------------ uneven batch
 @pytest.fixture(scope="module")
 def grouped():
