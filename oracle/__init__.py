@@ -28,7 +28,10 @@ Contents, each following the paper (arXiv 2511.03683):
   the paper defers it to its Methods), and its transpose.
 * rk4_step / rk4_adjoint_step   -- classical RK4 for df/dt = I[f] (the
   paper's real-time BTE; the integrator is not named in the text, RK4 is the
-  reading adopted here) and its exact discrete adjoint.
+  reading adopted here) and its exact discrete adjoint, with the drift term
+  when rates are given.
+* rk4_coupled_step, even_in_q   -- electrons and phonons stepped together,
+  the phonons of q and -q as a pair (even part of the rate).
 * transport_*                   -- linearised steady-state BTE (Eq. 1 with the
   collision integral linearised at f0), iterated to self-consistency.
 
