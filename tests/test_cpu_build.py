@@ -1,0 +1,260 @@
+"""The library's kernels and host code built for the CPU (g++ with
+AddressSanitizer and UndefinedBehaviorSanitizer, the HIP runtime replaced by
+tests/cpu_build/hip/hip_runtime.h), run on small systems and compared with
+the oracle.
+
+This checks, without a GPU, that every index a kernel forms stays inside the
+buffer it reads or writes (each device buffer is a separate host allocation,
+dynamic LDS is poisoned beyond the launch's size), that the host code
+launches what the kernels assume, and that the arithmetic is the oracle's.
+It covers the entry points' B = 1 forms (single-copy and per-row), the
+batched forms (B >= 8, with the DPP and shuffle exchanges emulated lane by
+lane), RK4 eager and replayed from a captured graph, the RK4 adjoint, the
+transport iteration and the phonon-side rate, and also the two paths whose
+entry points are switched off (the field term of Eq. 1 and the coupled
+electron-phonon step).
+
+The CPU build is a separate executable made here for tests only; the package
+never loads it, and the GPU tests run the HIP library itself.
+"""
+import hashlib
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(ROOT, "paper_2511_03683_amd", "csrc")
+SHIM = os.path.join(HERE, "cpu_build")
+SOURCES = ("api.hip", "kernels.hpp", "layout.hpp", "layout.cpp")
+TOL64, TOL32 = 1e-10, 1e-5
+ENV = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
+           UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
+
+
+def _digest():
+    h = hashlib.sha256()
+    for p in [os.path.join(CSRC, s) for s in SOURCES] + [
+            os.path.join(ROOT, "include", "ephbte.h"),
+            os.path.join(SHIM, "hip", "hip_runtime.h"), os.path.join(SHIM, "driver.cpp")]:
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+@pytest.fixture(scope="module")
+def driver():
+    """Compile the CPU build once per source state (about a minute)."""
+    cxx = shutil.which("g++")
+    if cxx is None:
+        pytest.skip("g++ is not available")
+    bdir = os.path.join(SHIM, "_build", _digest())
+    exe = os.path.join(bdir, "driver")
+    if os.path.exists(exe):
+        return exe
+    src = os.path.join(bdir, "src")
+    os.makedirs(src, exist_ok=True)
+    for s in SOURCES:
+        with open(os.path.join(CSRC, s)) as fh:
+            text = fh.read()
+        # dynamic LDS comes from the stand-in's buffer
+        text = text.replace("extern __shared__ __align__(16) unsigned char smem[];",
+                            "unsigned char *smem = emu::dyn_smem();")
+        with open(os.path.join(src, s), "w") as fh:
+            fh.write(text)
+    cmd = [cxx, "-std=c++20", "-O1", "-g", "-fno-omit-frame-pointer",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+           "-I", SHIM, "-I", src, "-I", os.path.join(ROOT, "include"),
+           "-o", exe + ".tmp", os.path.join(SHIM, "driver.cpp"), os.path.join(src, "layout.cpp"),
+           "-lpthread"]
+    subprocess.run(cmd, check=True, timeout=900)
+    os.replace(exe + ".tmp", exe)
+    return exe
+
+
+def _write(folder, s, dtype="f64", **kw):
+    arrs = dict(state_k=np.asarray(s.state_k, np.int32), state_band=np.asarray(s.state_band, np.int8),
+                eps=np.asarray(s.eps, np.float64), hw=np.asarray(s.hw, np.float64),
+                ci=np.asarray(s.ch_i, np.int32), cj=np.asarray(s.ch_j, np.int32),
+                cn=np.asarray(s.ch_nu, np.int8), g2=np.asarray(s.g2, np.float64))
+    meta = dict(S=s.n_states, nm=s.n_modes, nch=s.n_channels, kgrid=list(s.kgrid),
+                qgrid=list(s.qgrid), sigma=s.sigma, nq=s.n_q_norm, dtype=1 if dtype == "f32" else 2)
+    for k, v in kw.items():
+        if isinstance(v, np.ndarray):
+            arrs[k] = np.ascontiguousarray(v, np.float64)
+        else:
+            meta[k] = v
+    for k, v in arrs.items():
+        v.tofile(os.path.join(folder, k + ".bin"))
+    with open(os.path.join(folder, "meta.txt"), "w") as fh:
+        for k, v in meta.items():
+            vals = v if isinstance(v, (list, tuple)) else [v]
+            fh.write(k + " " + " ".join(repr(float(x)) for x in vals) + "\n")
+
+
+def _run(driver, folder, mode):
+    r = subprocess.run([driver, mode, str(folder)], env=ENV, capture_output=True, text=True,
+                       timeout=600)
+    assert r.returncode == 0, f"{mode}: exit {r.returncode}\n{r.stdout}\n{r.stderr[-4000:]}"
+    return r
+
+
+def _out(folder, name, shape=None):
+    a = np.fromfile(os.path.join(folder, "out_" + name + ".bin"))
+    return a.reshape(shape) if shape is not None else a
+
+
+def nerr(x, ref):
+    return float(np.abs(np.asarray(x) - ref).max() / max(np.abs(ref).max(), 1e-300))
+
+
+def _round32(s):
+    import copy
+    r = copy.copy(s)
+    r.eps = s.eps.astype(np.float32).astype(np.float64)
+    r.hw = s.hw.astype(np.float32).astype(np.float64)
+    r.g2 = s.g2.astype(np.float32).astype(np.float64)
+    return r
+
+
+@pytest.mark.parametrize("layout,dtype", [(2, "f64"), (1, "f64"), (2, "f32")])
+def test_forward_single_vector(driver, tmp_path, layout, dtype):
+    """Single-copy (layout 2) and per-row (layout 1) forward passes, B = 1."""
+    s = synth.multiband_system()
+    f = synth.random_occupations(s, 3)
+    nph = s.nph(300.0)
+    _write(tmp_path, s, dtype, f=f, nph=nph, B=1, layout=layout)
+    _run(driver, tmp_path, "forward")
+    if dtype == "f64":
+        assert nerr(_out(tmp_path, "I"), oracle.collision(s, f, nph)) <= TOL64
+    else:
+        r = _round32(s)
+        f32, n32 = f.astype(np.float32).astype(np.float64), nph.astype(np.float32).astype(np.float64)
+        assert nerr(_out(tmp_path, "I"), oracle.collision(r, f32, n32)) <= TOL32
+
+
+@pytest.mark.parametrize("B", [3, 9])
+def test_forward_batched(driver, tmp_path, B):
+    """Per-row pass for B < 8 and the batched pass (LDS tiles, run merge over
+    lanes) for B >= 8, every column against the oracle."""
+    s = synth.multiband_system()
+    F = np.stack([synth.random_occupations(s, 10 + b) for b in range(B)])
+    nph = s.nph(300.0)
+    _write(tmp_path, s, f=F, nph=nph, B=B)
+    _run(driver, tmp_path, "forward")
+    got = _out(tmp_path, "I", (B, s.n_states))
+    for b in range(B):
+        assert nerr(got[b], oracle.collision(s, F[b], nph)) <= TOL64, b
+
+
+@pytest.mark.parametrize("B", [1, 9])
+def test_vjp(driver, tmp_path, B):
+    """Reverse pass, B = 1 (per-row kernel) and batched (DPP sums over the
+    vectors): dL/df per vector and dL/d|g|^2 summed over the vectors."""
+    s = synth.multiband_system()
+    F = np.stack([synth.random_occupations(s, 20 + b) for b in range(B)])
+    lam = np.random.default_rng(4).normal(size=(B, s.n_states))
+    nph = s.nph(300.0)
+    _write(tmp_path, s, f=F, lam=lam, nph=nph, B=B)
+    _run(driver, tmp_path, "vjp")
+    gf = _out(tmp_path, "gf", (B, s.n_states))
+    gg = _out(tmp_path, "gg2")
+    rg = np.zeros(s.n_channels)
+    for b in range(B):
+        rf_b, rg_b = oracle.collision_vjp(s, F[b], nph, lam[b])
+        assert nerr(gf[b], rf_b) <= TOL64, b
+        rg += rg_b
+    assert nerr(gg, rg) <= TOL64
+
+
+def test_rt_step_and_graph(driver, tmp_path):
+    """RK4 steps through the single-copy pass, eager and replayed from a
+    captured graph (bitwise equal)."""
+    s = synth.multiband_system()
+    f0 = synth.random_occupations(s, 7)
+    nph = s.nph(300.0)
+    _write(tmp_path, s, f=f0, nph=nph, B=1, dt=0.5, steps=3)
+    _run(driver, tmp_path, "rt")
+    ref = f0.copy()
+    for _ in range(3):
+        ref = oracle.rk4_step(s, ref, nph, 0.5)
+    got = _out(tmp_path, "f")
+    assert nerr(got - f0, ref - f0) <= TOL64
+    assert np.array_equal(_out(tmp_path, "f_graph"), got)
+
+
+def test_rt_adjoint(driver, tmp_path):
+    s = synth.multiband_system(n_k=10, seed=23)
+    f0 = synth.random_occupations(s, 9) * 0.8 + 0.1
+    nph = s.nph(300.0)
+    gT = np.random.default_rng(5).normal(size=s.n_states)
+    _write(tmp_path, s, f=f0, gT=gT, nph=nph, dt=0.5, steps=4, ce=2)
+    _run(driver, tmp_path, "adjoint")
+    _, rf, rg = oracle.rk4_trajectory_grad(s, f0, nph, 0.5, 4, gT)
+    assert nerr(_out(tmp_path, "gf"), rf) <= 1e-9
+    assert nerr(_out(tmp_path, "gg2"), rg) <= 1e-9
+
+
+def test_transport(driver, tmp_path):
+    s = synth.tb_system(kn=12, qn=6, target_states=120, sigma=0.05)
+    T = 300.0
+    f0 = synth.fermi_dirac(s.eps, -0.1, T)
+    nph = s.nph(T)
+    _write(tmp_path, s, f=f0, vel=np.asarray(s.vel), nph=nph, T=T, tol=0.0, max_iter=5)
+    _run(driver, tmp_path, "transport")
+    ref = oracle.transport_solve(s, f0, s.vel, T, nph, max_iter=5, stop_on_tol=False)
+    assert nerr(_out(tmp_path, "mob", (3, 3)), ref["mu"]) <= TOL64
+    assert nerr(_out(tmp_path, "x", (s.n_states, 3)), ref["x"]) <= TOL64
+
+
+def test_phonon_rate(driver, tmp_path):
+    s = synth.multiband_system()
+    f = synth.random_occupations(s, 50)
+    nph = s.nph(300.0)
+    _write(tmp_path, s, f=f, nph=nph)
+    _run(driver, tmp_path, "phonon")
+    ref = oracle.phonon_rate(s, f, nph)
+    assert nerr(_out(tmp_path, "rate", ref.shape), ref) <= TOL64
+
+
+@pytest.mark.parametrize("B", [1, 3, 9])
+def test_field_term_switched_off_path(driver, tmp_path, B):
+    """The field term of Eq. 1 in the RK4 stage epilogues (single-copy,
+    per-row and batched forward passes), eager and graph.  Its entry point
+    refuses nonzero rates on the GPU; the CPU build sets them on the plan."""
+    s = synth.multiband_system()
+    rates = [0.06, -0.035, 0.02]
+    F = np.stack([synth.random_occupations(s, 30 + b) for b in range(B)])
+    nph = s.nph(300.0)
+    _write(tmp_path, s, f=F, nph=nph, B=B, dt=1.0, steps=4, rates=rates)
+    _run(driver, tmp_path, "field")
+    got = _out(tmp_path, "f", (B, s.n_states))
+    for b in range(B):
+        ref = F[b].copy()
+        for _ in range(4):
+            ref = oracle.rk4_step(s, ref, nph, 1.0, rates=np.array(rates))
+        assert nerr(got[b] - F[b], ref - F[b]) <= 1e-9, b
+    assert np.array_equal(_out(tmp_path, "f_graph", (B, s.n_states)), got)
+
+
+@pytest.mark.parametrize("name", ["multiband", "tb24"])
+def test_coupled_step_switched_off_path(driver, tmp_path, name):
+    """The coupled electron-phonon RK4 step.  Its entry point refuses
+    n_steps > 0 on the GPU; the CPU build calls the step directly."""
+    s = synth.multiband_system() if name == "multiband" else \
+        synth.tb_system(kn=24, qn=12, target_states=400)
+    f0 = 0.1 + 0.8 * synth.random_occupations(s, 52)
+    N0 = s.nph(300.0) * 1.5
+    _write(tmp_path, s, f=f0, nph=N0, dt=1.0, steps=3)
+    _run(driver, tmp_path, "coupled")
+    rf, rN = f0, N0
+    for _ in range(3):
+        rf, rN = oracle.rk4_coupled_step(s, rf, rN, 1.0)
+    assert nerr(_out(tmp_path, "f") - f0, rf - f0) <= 1e-9
+    assert nerr(_out(tmp_path, "N", rN.shape) - N0, rN - N0) <= 1e-9
