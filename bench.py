@@ -95,6 +95,9 @@ def main():
     ap.add_argument("--batch-only", action="store_true",
                     help="after the main step run only the B = 64 forward and reverse passes "
                          "(for tracing the batched kernels)")
+    ap.add_argument("--single-only", action="store_true",
+                    help="after the main step run only the B = 1 reverse pass, the phonon-side "
+                         "rate and the transport iterations (for tracing their kernels)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-channels", type=int, default=100_000_000)
     ap.add_argument("--dtype", choices=("f64", "f32"), default="f64",
@@ -103,9 +106,9 @@ def main():
                     help="also run a plain 1 GiB read + 1 GiB write elementwise kernel "
                          "(hardware-counter calibration)")
     args = ap.parse_args()
-    if args.dtype != "f64" and not (args.no_forms or args.batch_only):
+    if args.dtype != "f64" and not (args.no_forms or args.batch_only or args.single_only):
         ap.error("--dtype f32 times the main step only; add --no-forms or --batch-only")
-    if args.batch_only:
+    if args.batch_only or args.single_only:
         args.no_forms = True
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -194,6 +197,39 @@ def main():
         f"(wall {wall:.2f}s for {args.steps})")
 
     forms = {}
+
+    def vjp_b1(reps):
+        lam = tens(rng.normal(size=s.n_states), torch.float64)
+        gg = torch.zeros(nch, dtype=torch.float64, device=dev)
+        ms_v, _ = timed(lambda: E.collision_vjp(plan64, f64, n64, lam, want_f=True, gg2=gg), reps, 1)
+        forms["vjp_f64_b1"] = dict(ms=ms_v, channels_per_s=nch / (ms_v * 1e-3),
+                                   algorithmic_GBps=VJP_BYTES_PER_CHANNEL["f64"] * nch / (ms_v * 1e-3) / 1e9)
+        return ms_v
+
+    def phonon_rate(reps):
+        dN = torch.empty((s.n_q, s.n_modes), dtype=torch.float64, device=dev)
+        msp, _ = timed(lambda: E.phonon_rate(plan64, f64, n64, out=dN), reps, 1)
+        forms["phonon_rate_f64"] = dict(ms=msp, channels_per_s=nch / (msp * 1e-3),
+                                        bins=int(s.n_q * s.n_modes),
+                                        note="one 64-bit integer atomic per entry into its (q, mode) bin")
+        log(f"phonon rate fp64: {msp:.3f} ms")
+
+    def transport_iter():
+        vel = tens(s.vel, torch.float64)
+        f0 = tens(synth.fermi_dirac(s.eps, -0.1, 300.0), torch.float64)
+        t1, _ = timed(lambda: E.iterate_transport(plan64, f0, vel, 300.0, n64, tol=0.0, max_iter=1), 1, 1)
+        t6, _ = timed(lambda: E.iterate_transport(plan64, f0, vel, 300.0, n64, tol=0.0, max_iter=6), 1, 0)
+        forms["transport_iter_f64"] = dict(ms_per_iteration=(t6 - t1) / 5.0, ms_setup_plus_one=t1)
+        log(f"transport fp64: {(t6 - t1) / 5:.3f} ms/iteration, setup+1 {t1:.3f} ms")
+        return vel, f0
+
+    if args.single_only:
+        if args.dtype != "f64":
+            ap.error("--single-only times the FP64 plan")
+        ms_v = vjp_b1(args.steps)
+        log(f"vjp fp64: {ms_v:.3f} ms")
+        phonon_rate(args.steps)
+        transport_iter()
     if args.batch_only:
         B = 64
         tuned = E.autotune(plan64, B)
@@ -221,18 +257,12 @@ def main():
                                         layout="duplicated rows")
         log(f"fwd fp64 per-row pass: {msr:.3f} ms")
         # reverse mode (dL/df and dL/dg2), FP64
-        lam = tens(rng.normal(size=s.n_states), torch.float64)
-        gg = torch.zeros(nch, dtype=torch.float64, device=dev)
-        vjp = lambda: E.collision_vjp(plan64, f64, n64, lam, want_f=True, gg2=gg)
-        ms_v, _ = timed(vjp, max(3, args.steps // 4), 1)
-        forms["vjp_f64_b1"] = dict(ms=ms_v, channels_per_s=nch / (ms_v * 1e-3),
-                                   algorithmic_GBps=VJP_BYTES_PER_CHANNEL["f64"] * nch / (ms_v * 1e-3) / 1e9)
+        ms_v = vjp_b1(max(3, args.steps // 4))
         forms["fwd_plus_adjoint_f64_b1"] = dict(
             ms=ms + ms_v, channels_per_s=nch / ((ms + ms_v) * 1e-3),
             algorithmic_GBps=(BYTES_PER_CHANNEL["f64"] + VJP_BYTES_PER_CHANNEL["f64"]) * nch
             / ((ms + ms_v) * 1e-3) / 1e9)
         log(f"vjp fp64: {ms_v:.3f} ms")
-        del gg
         # batched B = 64: 16 temperatures x 4 fields, sub-tile size from the autotuner
         B = 64
         F_np = synth.batch_occupations(s)
@@ -258,20 +288,9 @@ def main():
         log(f"vjp fp64 B=64: {msbv:.3f} ms ({forms['vjp_f64_b64']['ratio_vs_b1']:.2f}x per vector)")
         del F, IB, LB, ggb
         # phonon side of the same processes (dN/dt of every (q, mode)), FP64
-        dN = torch.empty((s.n_q, s.n_modes), dtype=torch.float64, device=dev)
-        msp, _ = timed(lambda: E.phonon_rate(plan64, f64, n64, out=dN), max(3, args.steps // 4), 1)
-        forms["phonon_rate_f64"] = dict(ms=msp, channels_per_s=nch / (msp * 1e-3),
-                                        bins=int(s.n_q * s.n_modes),
-                                        note="one 64-bit integer atomic per entry into its (q, mode) bin")
-        log(f"phonon rate fp64: {msp:.3f} ms")
-        del dN
+        phonon_rate(max(3, args.steps // 4))
         # transport iteration, FP64
-        vel = tens(s.vel, torch.float64)
-        f0 = tens(synth.fermi_dirac(s.eps, -0.1, 300.0), torch.float64)
-        t1, _ = timed(lambda: E.iterate_transport(plan64, f0, vel, 300.0, n64, tol=0.0, max_iter=1), 1, 1)
-        t6, _ = timed(lambda: E.iterate_transport(plan64, f0, vel, 300.0, n64, tol=0.0, max_iter=6), 1, 0)
-        forms["transport_iter_f64"] = dict(ms_per_iteration=(t6 - t1) / 5.0, ms_setup_plus_one=t1)
-        log(f"transport fp64: {(t6 - t1) / 5:.3f} ms/iteration, setup+1 {t1:.3f} ms")
+        vel, f0 = transport_iter()
         forms["transport_solve_f64"] = transport_solve(E, plan64, f0, vel, n64, timed)
         del vel, f0
         # differentiation: adjoint through 200 RK4 steps (checkpoint every 20) of
