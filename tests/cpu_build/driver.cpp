@@ -136,8 +136,12 @@ int main(int argc, char **argv) {
     p.n_q_norm = meta("nq");
     p.dtype = f32 ? EPHBTE_F32 : EPHBTE_F64;
     p.device = 0;
+    ephbte_build_opts opts{};
+    opts.energy_nsigma = meta("energy_nsigma", 0.0);
+    opts.g2_min = meta("g2_min", 0.0);
+    opts.elastic_modes = static_cast<uint32_t>(meta("elastic_modes", 0));
     ephbte_plan plan = nullptr;
-    check(ephbte_build_channels(&p, nullptr, &plan), "build_channels");
+    check(ephbte_build_channels(&p, &opts, &plan), "build_channels");
     const int layout = static_cast<int>(meta("layout", 0));
     if (layout) {
         ephbte_tuning t{};
@@ -145,21 +149,26 @@ int main(int argc, char **argv) {
         check(ephbte_set_tuning(plan, &t), "set_tuning");
     }
     Dev dv{f32};
-    auto nph = rd<double>("nph.bin", nqm);
+    // per-vector baths: nph holds B tables of [Nq][n_modes]
+    const int per_batch = static_cast<int>(meta("nph_per_batch", 0));
+    auto nph = rd<double>("nph.bin", per_batch ? nqm * B : nqm);
     void *dN = dv.up(nph);
 
     if (mode == "forward") {
         auto f = rd<double>("f.bin", static_cast<size_t>(B) * S);
         void *df = dv.up(f), *dI = dv.alloc(static_cast<size_t>(B) * S);
-        check(ephbte_collision_integral(plan, B, df, S, dN, 0, dI, S, nullptr), "collision_integral");
+        check(ephbte_collision_integral(plan, B, df, S, dN, per_batch, dI, S, nullptr), "collision_integral");
         wr("out_I.bin", dv.down(dI, static_cast<size_t>(B) * S));
     } else if (mode == "vjp") {
         auto f = rd<double>("f.bin", static_cast<size_t>(B) * S);
         auto lam = rd<double>("lam.bin", static_cast<size_t>(B) * S);
         void *df = dv.up(f), *dl = dv.up(lam), *dg = dv.alloc(static_cast<size_t>(B) * S);
+        // the |g|^2 gradient starts at gg2_fill: overwritten, and 0 for removed channels
+        std::vector<double> fill(static_cast<size_t>(nch), meta("gg2_fill", 0.0));
         double *dgg = nullptr;
         hipMalloc(reinterpret_cast<void **>(&dgg), 8 * static_cast<size_t>(nch));
-        check(ephbte_collision_vjp(plan, B, df, S, dN, 0, dl, S, dg, S, dgg, 0, nullptr), "collision_vjp");
+        hipMemcpy(dgg, fill.data(), 8 * static_cast<size_t>(nch), hipMemcpyHostToDevice);
+        check(ephbte_collision_vjp(plan, B, df, S, dN, per_batch, dl, S, dg, S, dgg, 0, nullptr), "collision_vjp");
         wr("out_gf.bin", dv.down(dg, static_cast<size_t>(B) * S));
         std::vector<double> gg(static_cast<size_t>(nch));
         hipMemcpy(gg.data(), dgg, 8 * static_cast<size_t>(nch), hipMemcpyDeviceToHost);

@@ -9,7 +9,8 @@ dynamic LDS is poisoned beyond the launch's size), that the host code
 launches what the kernels assume, and that the arithmetic is the oracle's.
 It covers the entry points' B = 1 forms (single-copy and per-row), the
 batched forms (B >= 8, with the DPP and shuffle exchanges emulated lane by
-lane), RK4 eager and replayed from a captured graph, the RK4 adjoint, the
+lane), channel selection at build, elastic mechanisms, per-vector phonon
+baths, RK4 eager and replayed from a captured graph, the RK4 adjoint, the
 transport iteration and the phonon-side rate, and also the two paths whose
 entry points are switched off (the field term of Eq. 1 and the coupled
 electron-phonon step).
@@ -54,10 +55,16 @@ def driver():
     cxx = shutil.which("g++")
     if cxx is None:
         pytest.skip("g++ is not available")
-    bdir = os.path.join(SHIM, "_build", _digest())
+    root = os.path.join(SHIM, "_build")
+    digest = _digest()
+    bdir = os.path.join(root, digest)
     exe = os.path.join(bdir, "driver")
     if os.path.exists(exe):
         return exe
+    if os.path.isdir(root):   # builds of earlier source states
+        for old in os.listdir(root):
+            if old != digest:
+                shutil.rmtree(os.path.join(root, old), ignore_errors=True)
     src = os.path.join(bdir, "src")
     os.makedirs(src, exist_ok=True)
     for s in SOURCES:
@@ -258,3 +265,64 @@ def test_coupled_step_switched_off_path(driver, tmp_path, name):
         rf, rN = oracle.rk4_coupled_step(s, rf, rN, 1.0)
     assert nerr(_out(tmp_path, "f") - f0, rf - f0) <= 1e-9
     assert nerr(_out(tmp_path, "N", rN.shape) - N0, rN - N0) <= 1e-9
+
+
+def test_channel_selection(driver, tmp_path):
+    """A plan built with the energy window and |g|^2 floor computes Eq. 2
+    over the oracle's kept channels; removed channels get zero gradients."""
+    s = synth.tb_system(kn=12, qn=6, target_states=120, sigma=0.05)
+    nsig, g2min = 2.5, 5e-4
+    keep = oracle.select_channels(s, nsig, g2min)
+    assert 0 < keep.sum() < s.n_channels
+    sub = oracle.subset(s, keep)
+    f = synth.random_occupations(s, 31)
+    lam = np.random.default_rng(8).normal(size=s.n_states)
+    nph = s.nph(300.0)
+    _write(tmp_path, s, f=f, lam=lam, nph=nph, energy_nsigma=nsig, g2_min=g2min, gg2_fill=7.0)
+    _run(driver, tmp_path, "forward")
+    assert nerr(_out(tmp_path, "I"), oracle.collision(sub, f, nph)) <= TOL64
+    _run(driver, tmp_path, "vjp")
+    rf, rg = oracle.collision_vjp(sub, f, nph, lam)
+    gg = _out(tmp_path, "gg2")
+    assert nerr(_out(tmp_path, "gf"), rf) <= TOL64
+    assert np.all(gg[~keep] == 0.0)
+    assert nerr(gg[keep], rg) <= TOL64
+
+
+def test_elastic_mechanism(driver, tmp_path):
+    """A defect mechanism flagged elastic beside phonon modes."""
+    s = synth.defect_system(6, with_phonons=True)
+    e = s.meta["elastic_mode"]
+    f = synth.random_occupations(s, 14)
+    lam = np.random.default_rng(9).normal(size=s.n_states)
+    nph = s.nph(300.0)
+    _write(tmp_path, s, f=f, lam=lam, nph=nph, elastic_modes=1 << e)
+    _run(driver, tmp_path, "forward")
+    assert nerr(_out(tmp_path, "I"), oracle.collision(s, f, nph)) <= TOL64
+    _run(driver, tmp_path, "vjp")
+    rf, rg = oracle.collision_vjp(s, f, nph, lam)
+    assert nerr(_out(tmp_path, "gf"), rf) <= TOL64
+    assert nerr(_out(tmp_path, "gg2"), rg) <= TOL64
+
+
+def test_bath_per_vector(driver, tmp_path):
+    """nph [B, Nq, n_modes]: each vector against the oracle with its own bath."""
+    s = synth.multiband_system()
+    temps = [150.0, 300.0, 450.0]
+    B = len(temps)
+    F = np.stack([synth.random_occupations(s, 40 + b) for b in range(B)])
+    NPH = np.stack([s.nph(T) for T in temps])
+    L = np.random.default_rng(5).normal(size=(B, s.n_states))
+    _write(tmp_path, s, f=F, lam=L, nph=NPH, B=B, nph_per_batch=1)
+    _run(driver, tmp_path, "forward")
+    got = _out(tmp_path, "I", (B, s.n_states))
+    for b in range(B):
+        assert nerr(got[b], oracle.collision(s, F[b], NPH[b])) <= TOL64, b
+    _run(driver, tmp_path, "vjp")
+    gf = _out(tmp_path, "gf", (B, s.n_states))
+    rg = 0
+    for b in range(B):
+        rf_b, rg_b = oracle.collision_vjp(s, F[b], NPH[b], L[b])
+        assert nerr(gf[b], rf_b) <= TOL64, b
+        rg = rg + rg_b
+    assert nerr(_out(tmp_path, "gg2"), rg) <= TOL64
