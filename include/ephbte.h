@@ -321,6 +321,19 @@ ephbte_status ephbte_set_tuning(ephbte_plan plan, const ephbte_tuning *tuning);
 ephbte_status ephbte_autotune(ephbte_plan plan, int32_t batch, ephbte_tuning *chosen,
                               const char *cache_path);
 
+/* Launch timing of the forward pass's main kernel, for measurement (not a
+ * step of the method): the single-copy kernel at B = 1, the per-row kernel for
+ * B = 2 .. 7 (or layout 1) and the batched kernel for B >= 8.
+ * mode 1: clears the record and starts it; every eager launch of that kernel
+ *   on this plan is then bracketed by two HIP events recorded on its launch
+ *   stream (launches under graph capture are not timed; at most 4096 launches
+ *   per period are, later ones are not).
+ * mode 0: stops it, waits for the recorded events, and returns the number of
+ *   timed launches in *launches and their mean duration in ms in *mean_ms
+ *   (0 when none); both host pointers may be NULL.
+ * INVALID_ARGUMENT for another mode; HIP_ERROR if an event fails. */
+ephbte_status ephbte_kernel_timing(ephbte_plan plan, int32_t mode, double *mean_ms, int64_t *launches);
+
 /* Plan facts: out[0]=S, [1]=n_channels passed at build, [2]=entries,
  * [3]=chunks, [4]=dtype, [5]=device, [6]=device bytes held,
  * [7]=chunk_entries, [8]=block_threads, [9]=channels kept by the selection. */

@@ -73,6 +73,8 @@ SYMBOLS = {
     "ephbte_set_tuning": ([_P, ctypes.POINTER(Tuning)], ctypes.c_int32),
     "ephbte_autotune": ([_P, ctypes.c_int32, ctypes.POINTER(Tuning), ctypes.c_char_p], ctypes.c_int32),
     "ephbte_plan_info": ([_P, _P], ctypes.c_int32),
+    "ephbte_kernel_timing": ([_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                              ctypes.POINTER(ctypes.c_int64)], ctypes.c_int32),
     "ephbte_set_field": ([_P, _P], ctypes.c_int32),
     "ephbte_phonon_rate": ([_P, _P, _P, _P, _P], ctypes.c_int32),
     "ephbte_rt_step_coupled": ([_P, _P, _P, ctypes.c_double, ctypes.c_int32, _P], ctypes.c_int32),
@@ -463,6 +465,17 @@ def set_field(plan: Plan, rates) -> None:
     if r.shape != (3,):
         raise ValueError("rates must hold 3 values")
     _check(load_library().ephbte_set_field(plan.handle, r.ctypes.data), "set_field")
+
+
+def kernel_timing(plan: Plan, start: bool):
+    """Launch timing of the forward pass's main kernel (see
+    ephbte_kernel_timing): start=True clears and starts it; start=False stops
+    it and returns (mean_ms, launches) of the eager launches since the start."""
+    mean = ctypes.c_double(0.0)
+    n = ctypes.c_int64(0)
+    _check(load_library().ephbte_kernel_timing(plan.handle, 1 if start else 0, ctypes.byref(mean),
+                                               ctypes.byref(n)), "kernel_timing")
+    return None if start else (float(mean.value), int(n.value))
 
 
 def plan_info(plan: Plan) -> dict:

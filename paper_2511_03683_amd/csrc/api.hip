@@ -154,6 +154,11 @@ struct ephbte_plan_s {
     hipStream_t last_stream = nullptr;
     bool has_last = false;
     std::vector<GraphEntry> graphs;
+    // launch timing of the forward pass's main kernel (ephbte_kernel_timing):
+    // a pair of events per eager launch, recorded on its stream, reused
+    bool ktime_on = false;
+    std::vector<hipEvent_t> ktime_ev;
+    size_t ktime_used = 0;
     int64_t ws_gen = 0;   // bumped whenever a workspace moves
     size_t layout_bytes = 0;
 
@@ -244,6 +249,7 @@ void free_plan(ephbte_plan P) {
     if (P->ev_a) (void)hipEventDestroy(P->ev_a);
     if (P->ev_b) (void)hipEventDestroy(P->ev_b);
     if (P->ev_last) (void)hipEventDestroy(P->ev_last);
+    for (hipEvent_t e : P->ktime_ev) (void)hipEventDestroy(e);
     if (P->own_stream) (void)hipStreamDestroy(P->own_stream);
     delete P;
 }
@@ -482,13 +488,39 @@ size_t batch_lds_bytes(ephbte_plan P, int pt) {
                                                                           : sizeof(StateRec<float>)));
 }
 
+bool capturing(hipStream_t s);
+
+// launches timed per ephbte_kernel_timing period; later ones are not timed
+constexpr size_t kTimedLaunches = 4096;
+
+// Event before a launch of the forward kernel when timing is on (not under
+// graph capture); returns the pair's index for ktime_end, or -1.
+int64_t ktime_begin(ephbte_plan P, hipStream_t s) {
+    if (!P->ktime_on || P->ktime_used >= kTimedLaunches || capturing(s)) return -1;
+    const size_t i = P->ktime_used;
+    while (P->ktime_ev.size() < 2 * (i + 1)) {
+        hipEvent_t e = nullptr;
+        HIPC(hipEventCreate(&e));
+        P->ktime_ev.push_back(e);
+    }
+    HIPC(hipEventRecord(P->ktime_ev[2 * i], s));
+    ++P->ktime_used;
+    return static_cast<int64_t>(i);
+}
+
+void ktime_end(ephbte_plan P, hipStream_t s, int64_t i) {
+    if (i >= 0) HIPC(hipEventRecord(P->ktime_ev[2 * static_cast<size_t>(i) + 1], s));
+}
+
 template <typename T>
 void enqueue_forward_batched(ephbte_plan P, int B, const T *f, int64_t ldf, const Epi<T> &E,
                              hipStream_t s) {
     const size_t shm = batch_lds_bytes(P, P->pt);
     dim3 grid(static_cast<unsigned>(P->n_btiles), (B + 63) / 64);
+    const int64_t kt = ktime_begin(P, s);
     hipLaunchKernelGGL((k_fwd_batched<T, kBatchDPW>), grid, dim3(kBatchThreads), shm, s,
                        batch_args<T>(P), f, ldf, B, E);
+    ktime_end(P, s, kt);
     HIPC(hipGetLastError());
 }
 
@@ -609,12 +641,14 @@ void enqueue_forward(ephbte_plan P, int B, const T *f, int64_t ldf, const void *
         // registers a lane has at 1024 threads per workgroup
         constexpr int U = sizeof(T) == 8 ? 2 : 4;
         const size_t shm = sym_lds_bytes(P->dtype, P->sym_lds_states);
+        const int64_t kt = ktime_begin(P, s);
         if (P->padq)
             hipLaunchKernelGGL((k_fwd_sym<T, U, true>), dim3(static_cast<unsigned>(P->n_sym_tiles)), dim3(1024), shm,
                                s, a, f, part);
         else
             hipLaunchKernelGGL((k_fwd_sym<T, U, false>), dim3(static_cast<unsigned>(P->n_sym_tiles)), dim3(1024), shm,
                                s, a, f, part);
+        ktime_end(P, s, kt);
         hipLaunchKernelGGL((k_sym_finish<T>), dim3((P->S + 255) / 256), dim3(256), 0, s, a, f,
                            (const T *)part, E);
         HIPC(hipGetLastError());
@@ -623,12 +657,14 @@ void enqueue_forward(ephbte_plan P, int B, const T *f, int64_t ldf, const void *
     TiledArgs<T> a = tiled_args<T>(P);
     T *part = static_cast<T *>(P->part.p);
     dim3 grid(tile_grid(P, P->n_tiles), B);
+    const int64_t kt = ktime_begin(P, s);
     if (P->padq)
         hipLaunchKernelGGL((k_fwd_tiled<T, 4, 512, true>), grid, dim3(P->block_threads),
                            tiled_lds_bytes(P), s, a, f, ldf, part, E);
     else
         hipLaunchKernelGGL((k_fwd_tiled<T, 4, 512, false>), grid, dim3(P->block_threads),
                            tiled_lds_bytes(P), s, a, f, ldf, part, E);
+    ktime_end(P, s, kt);
     if (!P->fused) {
         dim3 g2((P->S + 255) / 256, B);
         hipLaunchKernelGGL((k_tiled_finish<T>), g2, dim3(256), 0, s, a, f, ldf, (const T *)part, E);
@@ -2126,6 +2162,31 @@ ephbte_status ephbte_set_field(ephbte_plan plan, const double rate[3]) {
     for (int a = 0; a < 3; ++a) plan->drift_rate[a] = rate[a];
     plan->drift_on = on;
     return EPHBTE_OK;
+}
+
+ephbte_status ephbte_kernel_timing(ephbte_plan plan, int32_t mode, double *mean_ms, int64_t *launches) {
+    if (!plan) return fail(EPHBTE_INVALID_ARGUMENT, "plan is NULL");
+    if (mode != 0 && mode != 1) return fail(EPHBTE_INVALID_ARGUMENT, "mode must be 0 (stop) or 1 (start)");
+    try {
+        DeviceGuard g(plan->device);
+        double total = 0.0;
+        const size_t n = plan->ktime_used;
+        if (mode == 0) {
+            for (size_t i = 0; i < n; ++i) {
+                HIPC(hipEventSynchronize(plan->ktime_ev[2 * i + 1]));
+                float ms = 0.0f;
+                HIPC(hipEventElapsedTime(&ms, plan->ktime_ev[2 * i], plan->ktime_ev[2 * i + 1]));
+                total += ms;
+            }
+        }
+        if (mean_ms) *mean_ms = mode == 0 && n > 0 ? total / static_cast<double>(n) : 0.0;
+        if (launches) *launches = mode == 0 ? static_cast<int64_t>(n) : 0;
+        plan->ktime_used = 0;
+        plan->ktime_on = mode == 1;
+        return EPHBTE_OK;
+    } catch (const HipError &e) {
+        return fail(EPHBTE_HIP_ERROR, std::string(e.where) + ": " + hipGetErrorString(e.e));
+    }
 }
 
 ephbte_status ephbte_plan_info(ephbte_plan plan, int64_t out[10]) {

@@ -157,8 +157,13 @@ int main(int argc, char **argv) {
     if (mode == "forward") {
         auto f = rd<double>("f.bin", static_cast<size_t>(B) * S);
         void *df = dv.up(f), *dI = dv.alloc(static_cast<size_t>(B) * S);
+        check(ephbte_kernel_timing(plan, 1, nullptr, nullptr), "kernel_timing start");
         check(ephbte_collision_integral(plan, B, df, S, dN, per_batch, dI, S, nullptr), "collision_integral");
+        double kms = 0;
+        int64_t kn = 0;
+        check(ephbte_kernel_timing(plan, 0, &kms, &kn), "kernel_timing stop");
         wr("out_I.bin", dv.down(dI, static_cast<size_t>(B) * S));
+        wr("out_timing.bin", {kms, static_cast<double>(kn)});
     } else if (mode == "vjp") {
         auto f = rd<double>("f.bin", static_cast<size_t>(B) * S);
         auto lam = rd<double>("lam.bin", static_cast<size_t>(B) * S);

@@ -138,6 +138,8 @@ def test_forward_single_vector(driver, tmp_path, layout, dtype):
     nph = s.nph(300.0)
     _write(tmp_path, s, dtype, f=f, nph=nph, B=1, layout=layout)
     _run(driver, tmp_path, "forward")
+    # one launch of the forward kernel, bracketed by the timing events
+    assert _out(tmp_path, "timing")[1] == 1
     if dtype == "f64":
         assert nerr(_out(tmp_path, "I"), oracle.collision(s, f, nph)) <= TOL64
     else:

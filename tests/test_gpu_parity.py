@@ -712,6 +712,29 @@ def test_update_g2(E):
     plan.close()
 
 
+def test_kernel_timing(E):
+    """The forward kernel's launch timing: one timed launch per eager call,
+    none under graph capture, none once stopped."""
+    s = synth.multiband_system()
+    plan = E.build_channels(s, device=0)
+    f, nph = dev(synth.random_occupations(s, 2)), dev(s.nph(300.0))
+    say("kernel timing")
+    E.kernel_timing(plan, True)
+    for _ in range(3):
+        E.collision_integral(plan, f, nph)
+    ms, n = E.kernel_timing(plan, False)
+    assert n == 3 and 0.0 < ms < 1000.0
+    E.kernel_timing(plan, True)
+    fe = dev(synth.random_occupations(s, 3))
+    E.rt_step(plan, fe, nph, 0.5, 2, use_graph=False)   # 2 steps x 4 stages, eager
+    E.rt_step(plan, fe, nph, 0.5, 4, use_graph=True)    # captured and replayed: not timed
+    ms, n = E.kernel_timing(plan, False)
+    assert n == 8 and ms > 0.0
+    E.collision_integral(plan, f, nph)
+    assert E.kernel_timing(plan, False) == (0.0, 0)
+    plan.close()
+
+
 # ------------------------------------------------------------------ RK4
 def test_rt_step_matches_oracle_and_graph_replay(E):
     s = synth.multiband_system()
