@@ -20,7 +20,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
 #include <functional>
+#include <numeric>
 #include <memory>
 #include <mutex>
 #include <sys/mman.h>
@@ -283,6 +285,29 @@ inline void *fresh_stack(unsigned char *base) {
     for (int r = 0; r < 6; ++r) *--sp = nullptr;              // rbp rbx r12 r13 r14 r15
     return sp;
 }
+// Order in which workgroups, and the work-items of a workgroup, are run:
+// CPU_BUILD_ORDER = forward (default), reverse, or shuffle:<seed>.  Results
+// that do not depend on scheduling must not change with it.
+inline std::vector<int> run_order(int n, unsigned long long salt) {
+    std::vector<int> o(static_cast<size_t>(n));
+    std::iota(o.begin(), o.end(), 0);
+    static const char *mode = getenv("CPU_BUILD_ORDER");
+    if (!mode || !strcmp(mode, "forward")) return o;
+    if (!strcmp(mode, "reverse")) {
+        std::reverse(o.begin(), o.end());
+        return o;
+    }
+    if (strncmp(mode, "shuffle:", 8) != 0) { fprintf(stderr, "cpu build: CPU_BUILD_ORDER=%s\n", mode); abort(); }
+    unsigned long long x = (strtoull(mode + 8, nullptr, 10) + 1) * 0x9E3779B97F4A7C15ull ^ (salt * 0xBF58476D1CE4E5B9ull);
+    for (int i = n - 1; i > 0; --i) {   // Fisher-Yates with xorshift64*
+        x ^= x >> 12;
+        x ^= x << 25;
+        x ^= x >> 27;
+        const int j = static_cast<int>((x * 2685821657736338717ull) % static_cast<unsigned long long>(i + 1));
+        std::swap(o[static_cast<size_t>(i)], o[static_cast<size_t>(j)]);
+    }
+    return o;
+}
 template <class... KP, class Tup>
 void run(void (*k)(KP...), dim3 g, dim3 b, size_t shm, Tup args) {
     ++n_launch;
@@ -292,9 +317,12 @@ void run(void (*k)(KP...), dim3 g, dim3 b, size_t shm, Tup args) {
     if (verbose) fprintf(stderr, "EMU launch %lld grid %u,%u,%u block %d shm %zu\n", n_launch, g.x, g.y, g.z, nt, shm);
     const int nw = (nt + 63) / 64;
     std::vector<Wave> waves(nw);
-    for (unsigned bz = 0; bz < g.z; ++bz)
-        for (unsigned by = 0; by < g.y; ++by)
-            for (unsigned bx = 0; bx < g.x; ++bx) {
+    const int nb = static_cast<int>(g.x * g.y * g.z);
+    const std::vector<int> blocks = run_order(nb, static_cast<unsigned long long>(n_launch));
+    for (int bi : blocks) {
+                const unsigned bx = static_cast<unsigned>(bi) % g.x, by = (static_cast<unsigned>(bi) / g.x) % g.y,
+                               bz = static_cast<unsigned>(bi) / (g.x * g.y);
+                const std::vector<int> lanes = run_order(nt, static_cast<unsigned long long>(n_blocks) * 7919u + 1u);
                 ++n_blocks;
                 __asan_unpoison_memory_region(lds, kLds);
                 std::memset(lds, 0xFF, kLds);
@@ -316,7 +344,7 @@ void run(void (*k)(KP...), dim3 g, dim3 b, size_t shm, Tup args) {
                     blk.f[t].state = RUN;
                 }
                 for (;;) {
-                    for (int t = 0; t < nt; ++t) {
+                    for (int t : lanes) {
                         if (blk.f[t].state != RUN) continue;
                         blk.cur = t;
                         ctx.tid = dim3(t % b.x, (t / b.x) % b.y, t / (b.x * b.y));

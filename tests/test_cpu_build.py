@@ -105,8 +105,9 @@ def _write(folder, s, dtype="f64", **kw):
             fh.write(k + " " + " ".join(repr(float(x)) for x in vals) + "\n")
 
 
-def _run(driver, folder, mode):
-    r = subprocess.run([driver, mode, str(folder)], env=ENV, capture_output=True, text=True,
+def _run(driver, folder, mode, order=None):
+    env = ENV if order is None else dict(ENV, CPU_BUILD_ORDER=order)
+    r = subprocess.run([driver, mode, str(folder)], env=env, capture_output=True, text=True,
                        timeout=600)
     assert r.returncode == 0, f"{mode}: exit {r.returncode}\n{r.stdout}\n{r.stderr[-4000:]}"
     return r
@@ -328,3 +329,24 @@ def test_bath_per_vector(driver, tmp_path):
         assert nerr(gf[b], rf_b) <= TOL64, b
         rg = rg + rg_b
     assert nerr(_out(tmp_path, "gg2"), rg) <= TOL64
+
+
+@pytest.mark.parametrize("mode,B,dtype", [("forward", 1, "f64"), ("forward", 1, "f32"),
+                                          ("forward", 9, "f64"), ("vjp", 1, "f64"),
+                                          ("vjp", 9, "f64"), ("phonon", 1, "f64")])
+def test_results_do_not_depend_on_scheduling(driver, tmp_path, mode, B, dtype):
+    """Bitwise the same outputs when workgroups, and the work-items inside each,
+    run in forward, reverse or shuffled order: the partner-side and phonon-bin
+    sums are integer atomics and every floating-point sum has a fixed order."""
+    s = synth.multiband_system()
+    F = np.stack([synth.random_occupations(s, 60 + b) for b in range(B)])
+    lam = np.random.default_rng(12).normal(size=(B, s.n_states))
+    _write(tmp_path, s, dtype, f=F, lam=lam, nph=s.nph(300.0), B=B)
+    names = {"forward": ["I"], "vjp": ["gf", "gg2"], "phonon": ["rate"]}[mode]
+    outs = []
+    for order in ("forward", "reverse", "shuffle:1", "shuffle:2"):
+        _run(driver, tmp_path, mode, order)
+        outs.append([_out(tmp_path, n) for n in names])
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b)
