@@ -142,12 +142,16 @@ int main(int argc, char **argv) {
     opts.elastic_modes = static_cast<uint32_t>(meta("elastic_modes", 0));
     ephbte_plan plan = nullptr;
     check(ephbte_build_channels(&p, &opts, &plan), "build_channels");
-    const int layout = static_cast<int>(meta("layout", 0));
-    if (layout) {
-        ephbte_tuning t{};
-        t.layout = layout;
+    // tuning knobs (0 keeps the plan's value)
+    ephbte_tuning t{};
+    t.layout = static_cast<int32_t>(meta("layout", 0));
+    t.chunk_entries = static_cast<int32_t>(meta("chunk_entries", 0));
+    t.block_threads = static_cast<int32_t>(meta("block_threads", 0));
+    t.xcd_map = static_cast<int32_t>(meta("xcd_map", 0));
+    t.batch_partners = static_cast<int32_t>(meta("batch_partners", 0));
+    t.tile_entries = static_cast<int32_t>(meta("tile_entries", 0));
+    if (t.layout || t.chunk_entries || t.block_threads || t.xcd_map || t.batch_partners || t.tile_entries)
         check(ephbte_set_tuning(plan, &t), "set_tuning");
-    }
     Dev dv{f32};
     // per-vector baths: nph holds B tables of [Nq][n_modes]
     const int per_batch = static_cast<int>(meta("nph_per_batch", 0));

@@ -350,3 +350,33 @@ def test_results_do_not_depend_on_scheduling(driver, tmp_path, mode, B, dtype):
     for o in outs[1:]:
         for a, b in zip(outs[0], o):
             assert np.array_equal(a, b)
+
+
+TUNINGS = [dict(chunk_entries=37, block_threads=64),
+           dict(chunk_entries=256, block_threads=128, xcd_map=2, layout=1),
+           dict(block_threads=512, tile_entries=500, xcd_map=1),
+           dict(chunk_entries=37, layout=1, tile_entries=100)]
+
+
+@pytest.mark.parametrize("k", range(len(TUNINGS)))
+def test_tuning_variants(driver, tmp_path, k):
+    """Chunk sizes that split destinations (chunk partials summed in order),
+    block sizes, tile targets and XCD maps: the forward pass (B = 1 and the
+    batched pass with 16-partner sub-tiles) and the reverse pass against the
+    oracle."""
+    tune = TUNINGS[k]
+    s = synth.random_channel_system(n_states=60, n_channels=900, seed=3)
+    F = np.stack([synth.random_occupations(s, 70 + b) for b in range(9)])
+    lam = np.random.default_rng(13).normal(size=(9, s.n_states))
+    nph = s.nph(300.0)
+    _write(tmp_path, s, f=F[:1], lam=lam[:1], nph=nph, B=1, **tune)
+    _run(driver, tmp_path, "forward")
+    assert nerr(_out(tmp_path, "I"), oracle.collision(s, F[0], nph)) <= TOL64
+    _run(driver, tmp_path, "vjp")
+    rf, rg = oracle.collision_vjp(s, F[0], nph, lam[0])
+    assert nerr(_out(tmp_path, "gf"), rf) <= TOL64 and nerr(_out(tmp_path, "gg2"), rg) <= TOL64
+    _write(tmp_path, s, f=F, nph=nph, B=9, batch_partners=16, **tune)
+    _run(driver, tmp_path, "forward")
+    got = _out(tmp_path, "I", (9, s.n_states))
+    for b in range(9):
+        assert nerr(got[b], oracle.collision(s, F[b], nph)) <= TOL64, b
