@@ -16,6 +16,7 @@ class CollisionIntegral(torch.autograd.Function):
     @staticmethod
     def forward(ctx, f, g2, plan, nph):
         ctx.plan = plan
+        ctx.g2_dtype = g2.dtype
         ctx.save_for_backward(f, nph)
         return binding.collision_integral(plan, f, nph)
 
@@ -27,6 +28,9 @@ class CollisionIntegral(torch.autograd.Function):
         gf, gg2 = binding.collision_vjp(plan, f, nph, gI.contiguous(),
                                         want_f=ctx.needs_input_grad[0],
                                         gg2=True if want_g2 else None)
+        # the library accumulates dL/d|g|^2 in FP64; autograd wants g2's dtype
+        if gg2 is not None:
+            gg2 = gg2.to(ctx.g2_dtype)
         return gf, gg2, None, None
 
 
@@ -34,6 +38,7 @@ class RtSolve(torch.autograd.Function):
     @staticmethod
     def forward(ctx, f0, g2, plan, nph, dt_fs, n_steps, checkpoint_every=20, use_graph=False):
         ctx.plan = plan
+        ctx.g2_dtype = g2.dtype
         ctx.args = (float(dt_fs), int(n_steps), int(checkpoint_every))
         ctx.save_for_backward(f0, nph)
         fT = f0.detach().clone()
@@ -47,6 +52,8 @@ class RtSolve(torch.autograd.Function):
         gf0, gg2 = binding.rt_adjoint(ctx.plan, f0, nph, dt, n, ce, gfT.contiguous(),
                                       want_f=True,
                                       gg2=True if ctx.needs_input_grad[1] else None)
+        if gg2 is not None:
+            gg2 = gg2.to(ctx.g2_dtype)
         return gf0, gg2, None, None, None, None, None, None
 
 
