@@ -217,6 +217,11 @@ int main(int argc, char **argv) {
         check(ephbte_phonon_rate(plan, df, dN, dr, nullptr), "phonon_rate");
         wr("out_rate.bin", dv.down(dr, nqm));
     } else if (mode == "adjoint") {
+        if (g_meta.count("rates")) {
+            // the field term in the adjoint stages (switched off at the entry point)
+            for (int a = 0; a < 3; ++a) plan->drift_rate[a] = g_meta["rates"].at(a);
+            plan->drift_on = true;
+        }
         const double dt = meta("dt");
         const int n = static_cast<int>(meta("steps"));
         const int ce = static_cast<int>(meta("ce"));

@@ -380,3 +380,46 @@ def test_tuning_variants(driver, tmp_path, k):
     got = _out(tmp_path, "I", (9, s.n_states))
     for b in range(9):
         assert nerr(got[b], oracle.collision(s, F[b], nph)) <= TOL64, b
+
+
+def test_field_term_in_the_adjoint(driver, tmp_path):
+    """The discrete RK4 adjoint with the field term (its transpose in the
+    adjoint stage epilogues), against the oracle's adjoint with drift."""
+    s = synth.multiband_system(n_k=10, seed=23)
+    f0 = synth.random_occupations(s, 9) * 0.8 + 0.1
+    nph = s.nph(300.0)
+    rates = [0.06, -0.035, 0.02]
+    gT = np.random.default_rng(6).normal(size=s.n_states)
+    _write(tmp_path, s, f=f0, gT=gT, nph=nph, dt=1.0, steps=4, ce=2, rates=rates)
+    _run(driver, tmp_path, "adjoint")
+    _, rf, rg = oracle.rk4_trajectory_grad(s, f0, nph, 1.0, 4, gT, rates=np.array(rates))
+    assert nerr(_out(tmp_path, "gf"), rf) <= 1e-9
+    assert nerr(_out(tmp_path, "gg2"), rg) <= 1e-9
+
+
+@pytest.mark.parametrize("mode,B", [("forward", 9), ("vjp", 1), ("vjp", 9)])
+def test_fp32_passes(driver, tmp_path, mode, B):
+    """FP32 batched forward and reverse passes against the FP64 oracle on the
+    FP32-rounded inputs."""
+    s = synth.multiband_system()
+    r = _round32(s)
+    F = np.stack([synth.random_occupations(s, 80 + b) for b in range(B)]).astype(np.float32).astype(np.float64)
+    lam = np.random.default_rng(14).normal(size=(B, s.n_states)).astype(np.float32).astype(np.float64)
+    nph = s.nph(300.0).astype(np.float32).astype(np.float64)
+    _write(tmp_path, s, "f32", f=F, lam=lam, nph=nph, B=B)
+    _run(driver, tmp_path, mode)
+    if mode == "forward":
+        got = _out(tmp_path, "I", (B, s.n_states))
+        for b in range(B):
+            ref = oracle.collision(r, F[b], nph)
+            rin, rout = oracle.collision_inout(r, F[b], nph)
+            scale = max(np.abs(ref).max(), 1e-2 * max(rin.max(), rout.max()))
+            assert np.abs(got[b] - ref).max() / scale <= TOL32, b
+    else:
+        gf = _out(tmp_path, "gf", (B, s.n_states))
+        rg = 0
+        for b in range(B):
+            rf_b, rg_b = oracle.collision_vjp(r, F[b], nph, lam[b])
+            assert nerr(gf[b], rf_b) <= TOL32, b
+            rg = rg + rg_b
+        assert nerr(_out(tmp_path, "gg2"), rg) <= TOL32
