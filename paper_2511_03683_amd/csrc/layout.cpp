@@ -393,9 +393,12 @@ std::vector<Tile> make_tiles(const ChunkTable &ct, const std::vector<int64_t> &r
         }
         t.c1 = c;
         t.lds = kind;
-        if (kind == 1 && hi >= lo) {
-            t.p_lo = lo;
-            t.p_hi = hi;
+        if (kind == 1) {
+            // a tile whose destinations have no partners still stages one state
+            // (state 0): its chunks are empty, but their masked lanes read window
+            // slot 0, which must hold a state, not whatever the LDS held before
+            t.p_lo = hi >= lo ? lo : 0;
+            t.p_hi = hi >= lo ? hi : 0;
         }
         tiles.push_back(t);
     }

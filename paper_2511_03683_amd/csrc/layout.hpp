@@ -67,7 +67,8 @@ ChunkTable make_chunks_seg(const std::vector<int64_t> &seg_beg, const std::vecto
 // Each tile holds at most target_entries entries (at least one chunk).
 struct Tile {
     int64_t c0, c1;        // chunks [c0, c1)
-    int32_t p_lo, p_hi;    // LDS window of partner states (inclusive; empty if p_hi < p_lo)
+    int32_t p_lo, p_hi;    // LDS window of partner states (inclusive; at least one state
+                           // when lds = 1, see make_tiles)
     int32_t lds;           // 1: partners staged in LDS, 0: read from global memory
     int32_t pad;
 };

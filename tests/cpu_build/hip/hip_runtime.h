@@ -219,7 +219,33 @@ namespace emu {
 inline emu_graph *capture = nullptr;
 inline int n_cu = 256;
 }
-inline hipError_t hipMalloc(void **p, size_t n) { *p = aligned_alloc(256, (n + 255) / 256 * 256); if (!*p) return 1; std::memset(*p, 0xA5, n); __asan_poison_memory_region((char *)*p + n, (n + 255) / 256 * 256 - n); return hipSuccess; }
+// Fill of fresh device memory and of LDS at the start of each workgroup:
+// CPU_BUILD_FILL = pattern (default: 0xA5 for device memory, 0xFF for LDS) or
+// random:<seed> (bytes from a counter-based generator), so that a read of
+// memory nothing wrote sees values that differ from run to run.
+inline void fill_unwritten(void *p, size_t n, unsigned char pattern) {
+    static const char *mode = getenv("CPU_BUILD_FILL");
+    if (!mode || strncmp(mode, "random:", 7) != 0) {
+        std::memset(p, pattern, n);
+        return;
+    }
+    static unsigned long long ctr = strtoull(mode + 7, nullptr, 10) * 0x9E3779B97F4A7C15ull;
+    unsigned char *b = static_cast<unsigned char *>(p);
+    for (size_t i = 0; i < n; i += 8) {
+        unsigned long long z = (ctr += 0x9E3779B97F4A7C15ull);   // splitmix64
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        std::memcpy(b + i, &z, std::min<size_t>(8, n - i));
+    }
+}
+inline hipError_t hipMalloc(void **p, size_t n) {
+    *p = aligned_alloc(256, (n + 255) / 256 * 256);
+    if (!*p) return 1;
+    fill_unwritten(*p, n, 0xA5);
+    __asan_poison_memory_region((char *)*p + n, (n + 255) / 256 * 256 - n);
+    return hipSuccess;
+}
 inline hipError_t hipFree(void *p) { free(p); return hipSuccess; }
 inline hipError_t hipHostMalloc(void **p, size_t n, unsigned) { return hipMalloc(p, n); }
 inline hipError_t hipHostFree(void *p) { free(p); return hipSuccess; }
@@ -325,7 +351,7 @@ void run(void (*k)(KP...), dim3 g, dim3 b, size_t shm, Tup args) {
                 const std::vector<int> lanes = run_order(nt, static_cast<unsigned long long>(n_blocks) * 7919u + 1u);
                 ++n_blocks;
                 __asan_unpoison_memory_region(lds, kLds);
-                std::memset(lds, 0xFF, kLds);
+                fill_unwritten(lds, kLds, 0xFF);
                 __asan_poison_memory_region(lds + shm, kLds - shm);
                 for (int w = 0; w < nw; ++w) {
                     waves[w].n = std::min(64, nt - 64 * w);

@@ -105,8 +105,12 @@ def _write(folder, s, dtype="f64", **kw):
             fh.write(k + " " + " ".join(repr(float(x)) for x in vals) + "\n")
 
 
-def _run(driver, folder, mode, order=None):
-    env = ENV if order is None else dict(ENV, CPU_BUILD_ORDER=order)
+def _run(driver, folder, mode, order=None, fill=None):
+    env = dict(ENV)
+    if order is not None:
+        env["CPU_BUILD_ORDER"] = order
+    if fill is not None:
+        env["CPU_BUILD_FILL"] = fill
     r = subprocess.run([driver, mode, str(folder)], env=env, capture_output=True, text=True,
                        timeout=600)
     assert r.returncode == 0, f"{mode}: exit {r.returncode}\n{r.stdout}\n{r.stderr[-4000:]}"
@@ -423,3 +427,33 @@ def test_fp32_passes(driver, tmp_path, mode, B):
             assert nerr(gf[b], rf_b) <= TOL32, b
             rg = rg + rg_b
         assert nerr(_out(tmp_path, "gg2"), rg) <= TOL32
+
+
+UNWRITTEN_CASES = [("forward", dict(B=1)), ("forward", dict(B=1, layout=1)), ("forward", dict(B=9)),
+                   ("vjp", dict(B=1)), ("vjp", dict(B=9)), ("phonon", dict()),
+                   ("rt", dict(B=1, dt=0.5, steps=2)),
+                   ("field", dict(B=1, dt=1.0, steps=2, rates=[0.06, -0.035, 0.02])),
+                   ("coupled", dict(dt=1.0, steps=2))]
+
+
+@pytest.mark.parametrize("k", range(len(UNWRITTEN_CASES)))
+def test_results_do_not_read_unwritten_memory(driver, tmp_path, k):
+    """Fresh device memory and each workgroup's LDS filled with random bytes
+    (two seeds) instead of fixed patterns: the outputs are bitwise the same,
+    so no result depends on memory that nothing wrote (on the GPU, LDS holds
+    whatever the previous workgroup left)."""
+    mode, kw = UNWRITTEN_CASES[k]
+    s = synth.multiband_system()
+    B = kw.get("B", 1)
+    F = np.stack([0.1 + 0.8 * synth.random_occupations(s, 90 + b) for b in range(B)])
+    lam = np.random.default_rng(15).normal(size=(B, s.n_states))
+    _write(tmp_path, s, f=F, lam=lam, nph=s.nph(300.0), **kw)
+    names = {"forward": ["I"], "vjp": ["gf", "gg2"], "phonon": ["rate"], "rt": ["f", "f_graph"],
+             "field": ["f", "f_graph"], "coupled": ["f", "N"]}[mode]
+    outs = []
+    for fill in (None, "random:1", "random:2"):
+        _run(driver, tmp_path, mode, fill=fill)
+        outs.append([_out(tmp_path, n) for n in names])
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b)
