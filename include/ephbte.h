@@ -230,7 +230,6 @@ ephbte_status ephbte_phonon_rate(ephbte_plan plan, const void *f, const void *np
  * N even and, with hw even, moves the same energy.  Each stage packs the
  * stage's N and runs the electron pass (stage update fused in its epilogue)
  * and the phonon pass.  B = 1; no HIP graph.
- * Currently switched off: n_steps > 0 returns INVALID_ARGUMENT.
  */
 ephbte_status ephbte_rt_step_coupled(ephbte_plan plan, void *f, void *nph, double dt_fs,
                                      int32_t n_steps, void *stream);
@@ -247,7 +246,6 @@ ephbte_status ephbte_rt_step_coupled(ephbte_plan plan, void *f, void *nph, doubl
  * never include it.  INVALID_ARGUMENT for a non-finite rate, or for a nonzero
  * one when some (k, band) is held by two states of the plan.  Drops cached
  * HIP graphs.  Synchronous.
- * Currently switched off: any nonzero rate returns INVALID_ARGUMENT.
  */
 ephbte_status ephbte_set_field(ephbte_plan plan, const double rate[3]);
 

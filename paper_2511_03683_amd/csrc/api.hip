@@ -1903,8 +1903,6 @@ ephbte_status ephbte_rt_step_coupled(ephbte_plan plan, void *f, void *nph, doubl
     return guarded(plan, stream, [&]() -> ephbte_status {
         if (!f || !nph) return fail(EPHBTE_INVALID_ARGUMENT, "f and nph must be non-NULL");
         if (n_steps < 0) return fail(EPHBTE_INVALID_ARGUMENT, "n_steps must be >= 0");
-        // switched off: the driver below is kept but not reached
-        if (n_steps > 0) return fail(EPHBTE_INVALID_ARGUMENT, "the coupled step is not available");
         if (!std::isfinite(dt_fs)) return fail(EPHBTE_INVALID_ARGUMENT, "dt_fs must be finite");
         const int64_t nbin = static_cast<int64_t>(plan->nq[0]) * plan->nq[1] * plan->nq[2] * plan->nm;
         if (overlaps(nph, esize(plan) * nbin, f, esize(plan) * plan->S))
@@ -2150,8 +2148,6 @@ ephbte_status ephbte_set_field(ephbte_plan plan, const double rate[3]) {
     if (on && !plan->nbr_ok)
         return fail(EPHBTE_INVALID_ARGUMENT,
                     "the field term needs each (k, band) held by one state (give state_band)");
-    // the field path is switched off: its device code is kept but not reached
-    if (on) return fail(EPHBTE_INVALID_ARGUMENT, "the field term is not available (only 0 rates are accepted)");
     try {
         DeviceGuard g(plan->device);
         HIPC(hipDeviceSynchronize());

@@ -3,8 +3,7 @@
 //   driver <mode> <folder>
 // The folder holds meta.txt ("key value" lines) and raw little-endian arrays;
 // results are written back as FP64 arrays named out_*.bin.  Test
-// infrastructure: it links the library's sources directly and may set plan
-// fields that the C ABI does not expose (the switched-off field term).
+// infrastructure: it links the library's sources directly.
 #include "api.hip"
 
 #include <fstream>
@@ -186,10 +185,8 @@ int main(int argc, char **argv) {
         const double dt = meta("dt");
         const int n = static_cast<int>(meta("steps"));
         if (mode == "field") {
-            // the entry point refuses nonzero rates while the path is off; set
-            // the plan's field directly
-            for (int a = 0; a < 3; ++a) plan->drift_rate[a] = g_meta["rates"].at(a);
-            plan->drift_on = true;
+            const double rates[3] = {g_meta["rates"].at(0), g_meta["rates"].at(1), g_meta["rates"].at(2)};
+            check(ephbte_set_field(plan, rates), "set_field");
         }
         auto f = rd<double>("f.bin", static_cast<size_t>(B) * S);
         void *fe = dv.up(f), *fg = dv.up(f);
@@ -198,17 +195,11 @@ int main(int argc, char **argv) {
         wr("out_f.bin", dv.down(fe, static_cast<size_t>(B) * S));
         wr("out_f_graph.bin", dv.down(fg, static_cast<size_t>(B) * S));
     } else if (mode == "coupled") {
-        // the entry point refuses n_steps > 0 while the path is off; call the
-        // step directly
         const double dt = meta("dt");
         const int n = static_cast<int>(meta("steps"));
         auto f = rd<double>("f.bin", static_cast<size_t>(S));
         void *df = dv.up(f);
-        check(guarded(plan, nullptr, [&]() -> ephbte_status {
-                  if (f32) return rt_coupled_impl<float>(plan, static_cast<float *>(df), static_cast<float *>(dN), dt, n, nullptr);
-                  return rt_coupled_impl<double>(plan, static_cast<double *>(df), static_cast<double *>(dN), dt, n, nullptr);
-              }),
-              "coupled step");
+        check(ephbte_rt_step_coupled(plan, df, dN, dt, n, nullptr), "rt_step_coupled");
         wr("out_f.bin", dv.down(df, static_cast<size_t>(S)));
         wr("out_N.bin", dv.down(dN, nqm));
     } else if (mode == "phonon") {
@@ -218,9 +209,8 @@ int main(int argc, char **argv) {
         wr("out_rate.bin", dv.down(dr, nqm));
     } else if (mode == "adjoint") {
         if (g_meta.count("rates")) {
-            // the field term in the adjoint stages (switched off at the entry point)
-            for (int a = 0; a < 3; ++a) plan->drift_rate[a] = g_meta["rates"].at(a);
-            plan->drift_on = true;
+            const double rates[3] = {g_meta["rates"].at(0), g_meta["rates"].at(1), g_meta["rates"].at(2)};
+            check(ephbte_set_field(plan, rates), "set_field");
         }
         const double dt = meta("dt");
         const int n = static_cast<int>(meta("steps"));

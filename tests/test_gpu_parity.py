@@ -653,8 +653,6 @@ def test_phonon_rate_skips_elastic_mechanisms(E):
     plan.close()
 
 
-@pytest.mark.skip(reason="coupled step switched off: its first GPU run faulted the GPU and the "
-                         "cause was not found, so the case stays off the GPU")
 @pytest.mark.parametrize("name,dtype", [("multiband", "f64"), ("tb24", "f64"), ("multiband", "f32")])
 def test_rt_step_coupled_matches_oracle(E, name, dtype):
     """Electrons and phonons stepped together against the oracle's coupled
@@ -682,10 +680,6 @@ def test_rt_step_coupled_matches_oracle(E, name, dtype):
     plan.close()
 
 
-@pytest.mark.skip(reason="faulted the GPU (illegal memory access in its first forward call on the "
-                         "48-state multi-band system) when it ran as the first GPU test of a "
-                         "process; it passes inside the full suite and in the CPU build; cause not "
-                         "found, so the case stays off the GPU")
 def test_autograd_function(E):
     from paper_2511_03683_amd.autograd import collision
     s = synth.multiband_system()
@@ -810,9 +804,6 @@ def test_rt_adjoint_matches_oracle(E):
 RATES = np.array([0.06, -0.035, 0.02])   # 1/fs: a strong field, so the drift is felt in a few steps
 
 
-@pytest.mark.skip(reason="field path switched off: its first GPU run faulted the GPU; the "
-                         "cause was not found (in-range neighbour table and device loads checked "
-                         "on the CPU), so the case stays off the GPU")
 @pytest.mark.parametrize("dtype,B", [("f64", 1), ("f64", 3), ("f64", 9), ("f32", 1)])
 def test_rt_step_with_field(E, dtype, B):
     """Eq. 1 with the field term: RK4 with collisions and drift against the
@@ -850,9 +841,6 @@ def test_rt_step_with_field(E, dtype, B):
     plan2.close()
 
 
-@pytest.mark.skip(reason="field path switched off: its first GPU run faulted the GPU; the "
-                         "cause was not found (in-range neighbour table and device loads checked "
-                         "on the CPU), so the case stays off the GPU")
 def test_rt_adjoint_with_field(E):
     """Discrete adjoint through RK4 steps with collisions and drift against the
     oracle's (whose drift transpose is the scattered matrix, not -D)."""
@@ -871,14 +859,31 @@ def test_rt_adjoint_with_field(E):
     plan.close()
 
 
-def test_field_term_is_refused(E):
-    """The field path is switched off: zero rates are accepted (and change
-    nothing), nonzero ones are refused."""
+def test_field_term_arguments(E):
+    """set_field refuses non-finite rates, and nonzero rates on a plan where a
+    (k, band) is held by two states; zero rates give back the field-free step."""
+    import copy
     s = synth.multiband_system()
     plan = E.build_channels(s, device=0)
-    say("field switched off")
+    say("field term arguments")
+    with pytest.raises(E.EphbteError, match="finite"):
+        E.set_field(plan, [np.nan, 0.0, 0.0])
+    nph = dev(s.nph(300.0))
+    f1, f2 = dev(synth.random_occupations(s, 5)), dev(synth.random_occupations(s, 5))
+    E.set_field(plan, RATES)
     E.set_field(plan, [0.0, 0.0, 0.0])
-    with pytest.raises(E.EphbteError, match="not available"):
+    E.rt_step(plan, f1, nph, 0.5, 2)
+    plan2 = E.build_channels(s, device=0)
+    E.rt_step(plan2, f2, nph, 0.5, 2)
+    assert np.array_equal(host(f1), host(f2))
+    plan.close()
+    plan2.close()
+    # without bands the two states of each k point share (k, band 0)
+    nb = copy.copy(s)
+    nb.state_band = np.zeros_like(s.state_band)
+    plan = E.build_channels(nb, device=0)
+    E.set_field(plan, [0.0, 0.0, 0.0])
+    with pytest.raises(E.EphbteError, match="band"):
         E.set_field(plan, RATES)
     plan.close()
 
