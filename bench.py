@@ -321,6 +321,31 @@ def main():
                                        collision_evaluations=8 * n_adj, vjp_calls=4 * n_adj,
                                        loss="mean carrier energy at t = steps x 1 fs")
         log(f"rt adjoint fp64 ({n_adj} steps): {msa:.1f} ms")
+        # field-driven dynamics (Eq. 1 with the drift term): 1e5 V/m along x, FP64
+        rates = synth.field_drift_rates([1e5, 0.0, 0.0], s.kgrid)
+        n_f = 10 if args.quick else 50
+        ff = fp0.clone()
+        try:
+            E.set_field(plan64, rates)
+            msf, _ = timed(lambda: E.rt_step(plan64, ff, n64, 1.0, n_f, use_graph=True), 1, 1)
+            forms["rt_step_field_f64"] = dict(steps=n_f, dt_fs=1.0, ms_per_step=msf / n_f,
+                                              field_V_per_m=[1e5, 0.0, 0.0],
+                                              rates_per_fs=[float(r) for r in rates])
+            log(f"rt step with field fp64: {msf / n_f:.3f} ms/step")
+        except E.EphbteError as e:
+            forms["rt_step_field_f64"] = dict(error=str(e))
+        finally:
+            E.set_field(plan64, [0.0, 0.0, 0.0])
+        # coupled electron-phonon dynamics: f and N stepped together, FP64
+        n_c = 2 if args.quick else 5
+        fc, Nc = fp0.clone(), n64.clone()
+        msc, _ = timed(lambda: E.rt_step_coupled(plan64, fc, Nc, 1.0, n_c), 1, 1)
+        forms["rt_step_coupled_f64"] = dict(steps=n_c, dt_fs=1.0, ms_per_step=msc / n_c,
+                                            phonon_bins=int(s.n_q * s.n_modes),
+                                            per_stage="pack of the stage's N, electron pass, "
+                                                      "phonon pass, even-part update of N")
+        log(f"coupled rt step fp64: {msc / n_c:.3f} ms/step")
+        del ff, fc, Nc
         # FP64 reference trajectory for the FP32 dynamics check below
         n_ref = 20 if args.quick else 200
         fref = fp0.clone()
