@@ -229,7 +229,10 @@ ephbte_status ephbte_phonon_rate(ephbte_plan plan, const void *f, const void *np
  * q; the phonons of q and -q therefore evolve as a pair, which keeps an even
  * N even and, with hw even, moves the same energy.  Each stage packs the
  * stage's N and runs the electron pass (stage update fused in its epilogue)
- * and the phonon pass.  B = 1; no HIP graph.
+ * and the phonon pass.  B = 1; no HIP graph; the field term of
+ * ephbte_set_field is not applied here.  INVALID_ARGUMENT for NULL f or nph,
+ * n_steps < 0, a non-finite dt_fs, or nph overlapping f; n_steps = 0 does
+ * nothing.
  */
 ephbte_status ephbte_rt_step_coupled(ephbte_plan plan, void *f, void *nph, double dt_fs,
                                      int32_t n_steps, void *stream);
