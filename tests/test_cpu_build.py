@@ -456,3 +456,32 @@ def test_results_do_not_read_unwritten_memory(driver, tmp_path, k):
     for o in outs[1:]:
         for a, b in zip(outs[0], o):
             assert np.array_equal(a, b)
+
+
+SWEEP_SYSTEMS = {
+    "parabolic4": lambda: synth.parabolic_system(4),
+    "random_order": lambda: synth.random_channel_system(n_states=60, n_channels=900, seed=3),
+    "tb12": lambda: synth.tb_system(kn=12, qn=6, target_states=120, sigma=0.05),
+    "defect": lambda: synth.defect_system(6, with_phonons=True),
+}
+
+
+@pytest.mark.parametrize("name", sorted(SWEEP_SYSTEMS))
+def test_other_systems_do_not_read_unwritten_memory(driver, tmp_path, name):
+    """The random-fill check on four more systems (dense, unstructured,
+    multi-band tight-binding, one elastic mechanism): forward at B = 1 and 9,
+    reverse at B = 1, bitwise the same under two random fills."""
+    s = SWEEP_SYSTEMS[name]()
+    extra = dict(elastic_modes=1 << s.meta["elastic_mode"]) if name == "defect" else {}
+    for mode, B in (("forward", 1), ("forward", 9), ("vjp", 1)):
+        F = np.stack([0.05 + 0.9 * synth.random_occupations(s, 100 + b) for b in range(B)])
+        lam = np.random.default_rng(16).normal(size=(B, s.n_states))
+        _write(tmp_path, s, f=F, lam=lam, nph=s.nph(300.0), B=B, **extra)
+        names = ["I"] if mode == "forward" else ["gf", "gg2"]
+        outs = []
+        for fill in (None, "random:11", "random:12"):
+            _run(driver, tmp_path, mode, fill=fill)
+            outs.append([_out(tmp_path, n) for n in names])
+        for o in outs[1:]:
+            for a, b in zip(outs[0], o):
+                assert np.array_equal(a, b), (name, mode, B)
