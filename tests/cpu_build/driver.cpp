@@ -202,6 +202,29 @@ int main(int argc, char **argv) {
         check(ephbte_rt_step_coupled(plan, df, dN, dt, n, nullptr), "rt_step_coupled");
         wr("out_f.bin", dv.down(df, static_cast<size_t>(S)));
         wr("out_N.bin", dv.down(dN, nqm));
+    } else if (mode == "update_g2") {
+        // new |g|^2 (caller order, FP64 on the device), then the forward pass
+        auto g2n = rd<double>("g2_new.bin", static_cast<size_t>(nch));
+        double *dg = nullptr;
+        hipMalloc(reinterpret_cast<void **>(&dg), 8 * static_cast<size_t>(nch));
+        hipMemcpy(dg, g2n.data(), 8 * static_cast<size_t>(nch), hipMemcpyHostToDevice);
+        check(ephbte_update_g2(plan, dg, nullptr), "update_g2");
+        auto f = rd<double>("f.bin", static_cast<size_t>(B) * S);
+        void *df = dv.up(f), *dI = dv.alloc(static_cast<size_t>(B) * S);
+        check(ephbte_collision_integral(plan, B, df, S, dN, 0, dI, S, nullptr), "collision_integral");
+        wr("out_I.bin", dv.down(dI, static_cast<size_t>(B) * S));
+    } else if (mode == "autotune") {
+        // tune twice with one cache file: the second call reads the entry back
+        const std::string cache = g_dir + "/tune.json";
+        ephbte_tuning a{}, b{};
+        check(ephbte_autotune(plan, B, &a, cache.c_str()), "autotune");
+        check(ephbte_autotune(plan, B, &b, cache.c_str()), "autotune (cached)");
+        wr("out_tune.bin", {double(a.chunk_entries), double(a.block_threads), double(a.batch_partners),
+                            double(b.chunk_entries), double(b.block_threads), double(b.batch_partners)});
+        auto f = rd<double>("f.bin", static_cast<size_t>(B) * S);
+        void *df = dv.up(f), *dI = dv.alloc(static_cast<size_t>(B) * S);
+        check(ephbte_collision_integral(plan, B, df, S, dN, 0, dI, S, nullptr), "collision_integral");
+        wr("out_I.bin", dv.down(dI, static_cast<size_t>(B) * S));
     } else if (mode == "phonon") {
         auto f = rd<double>("f.bin", static_cast<size_t>(S));
         void *df = dv.up(f), *dr = dv.alloc(nqm);

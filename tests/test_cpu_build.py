@@ -10,7 +10,8 @@ launches what the kernels assume, and that the arithmetic is the oracle's.
 It covers the entry points' B = 1 forms (single-copy and per-row), the
 batched forms (B >= 8, with the DPP and shuffle exchanges emulated lane by
 lane), channel selection at build, elastic mechanisms, per-vector phonon
-baths, RK4 eager and replayed from a captured graph, the RK4 adjoint, the
+baths, an uneven group of systems, new |g|^2 loaded into a plan, the
+autotuner and its cache, RK4 eager and replayed from a captured graph, the RK4 adjoint, the
 transport iteration, the phonon-side rate, the field term of Eq. 1 and the
 coupled electron-phonon step.  Fresh device memory and LDS can be filled with
 random bytes and workgroups run in any order, so that a result depending on
@@ -485,3 +486,48 @@ def test_other_systems_do_not_read_unwritten_memory(driver, tmp_path, name):
         for o in outs[1:]:
             for a, b in zip(outs[0], o):
                 assert np.array_equal(a, b), (name, mode, B)
+
+
+def test_update_g2(driver, tmp_path):
+    """New |g|^2 loaded into a built plan (caller order): the forward pass
+    follows them."""
+    s = synth.multiband_system()
+    f = synth.random_occupations(s, 17)
+    nph = s.nph(300.0)
+    g2n = s.g2 * np.random.default_rng(18).uniform(0.5, 2.0, size=s.n_channels)
+    _write(tmp_path, s, f=f, nph=nph, g2_new=g2n)
+    _run(driver, tmp_path, "update_g2")
+    assert nerr(_out(tmp_path, "I"), oracle.collision(s, f, nph, g2=g2n)) <= TOL64
+
+
+@pytest.mark.parametrize("B", [1, 9])
+def test_autotune_with_cache(driver, tmp_path, B):
+    """The autotuner times its candidates, writes the choice to the cache file,
+    and the second call reads the same choice back; the tuned plan still
+    matches the oracle."""
+    import json
+    s = synth.multiband_system()
+    F = np.stack([synth.random_occupations(s, 110 + b) for b in range(B)])
+    nph = s.nph(300.0)
+    _write(tmp_path, s, f=F, nph=nph, B=B)
+    _run(driver, tmp_path, "autotune")
+    t = _out(tmp_path, "tune")
+    assert np.array_equal(t[:3], t[3:])
+    with open(tmp_path / "tune.json") as fh:
+        cache = json.load(fh)
+    assert len(cache) == 1
+    got = _out(tmp_path, "I", (B, s.n_states))
+    for b in range(B):
+        assert nerr(got[b], oracle.collision(s, F[b], nph)) <= TOL64, b
+
+
+def test_grouped_uneven_systems(driver, tmp_path):
+    """Four systems of 100 .. 3000 channels concatenated into one problem and
+    evaluated by one forward pass, every state against the oracle."""
+    base = synth.tb_system(kn=12, qn=6, target_states=120, sigma=0.05, with_channels=False)
+    s = synth.grouped_system(n_systems=4, ch_min=100, ch_max=3000, base=base)
+    f = synth.random_occupations(s, 19)
+    nph = s.nph(300.0)
+    _write(tmp_path, s, f=f, nph=nph)
+    _run(driver, tmp_path, "forward")
+    assert nerr(_out(tmp_path, "I"), oracle.collision(s, f, nph)) <= TOL64
