@@ -225,6 +225,37 @@ int main(int argc, char **argv) {
         void *df = dv.up(f), *dI = dv.alloc(static_cast<size_t>(B) * S);
         check(ephbte_collision_integral(plan, B, df, S, dN, 0, dI, S, nullptr), "collision_integral");
         wr("out_I.bin", dv.down(dI, static_cast<size_t>(B) * S));
+    } else if (mode == "tiles") {
+        // tile tables of the plan (device memory is host memory here): every
+        // LDS tile has a window of 1 .. cap states that holds every partner of
+        // its chunks, and the tiles cover the chunks in order
+        struct Set { const TileRec *t; int64_t n; const int64_t *beg, *end; int64_t nch; int cap; };
+        const Set sets[3] = {
+            {plan->tiles, plan->n_tiles, plan->chunk_beg, nullptr, plan->n_chunks, plan->lds_states},
+            {plan->small_tiles, plan->n_small_tiles, plan->chunk_beg, nullptr, plan->n_chunks, plan->lds_states},
+            {plan->sym_tiles, plan->n_sym_tiles, plan->sym_chunk_beg, plan->sym_chunk_end, plan->n_sym_chunks,
+             plan->sym_lds_states}};
+        std::vector<double> bad(3, 0.0);
+        for (int k = 0; k < 3; ++k) {
+            const Set &x = sets[k];
+            int64_t next = 0;
+            for (int64_t i = 0; i < x.n; ++i) {
+                const TileRec t = x.t[i];
+                if (t.c0 != next || t.c1 < t.c0) bad[k] += 1;
+                next = t.c1;
+                if (!t.lds) continue;
+                if (t.p_hi < t.p_lo || t.p_hi - t.p_lo + 1 > x.cap || t.p_lo < 0 || t.p_hi >= S) bad[k] += 1;
+                for (int64_t c = t.c0; c < t.c1; ++c) {
+                    const int64_t e1 = x.end ? x.end[c] : x.beg[c + 1];
+                    for (int64_t e = x.beg[c]; e < e1; ++e) {
+                        const int p = static_cast<int>(plan->pnu[e] >> 3);
+                        if (p < t.p_lo || p > t.p_hi) bad[k] += 1;
+                    }
+                }
+            }
+            if (next != x.nch) bad[k] += 1;
+        }
+        wr("out_tiles.bin", bad);
     } else if (mode == "phonon") {
         auto f = rd<double>("f.bin", static_cast<size_t>(S));
         void *df = dv.up(f), *dr = dv.alloc(nqm);

@@ -531,3 +531,24 @@ def test_grouped_uneven_systems(driver, tmp_path):
     _write(tmp_path, s, f=f, nph=nph)
     _run(driver, tmp_path, "forward")
     assert nerr(_out(tmp_path, "I"), oracle.collision(s, f, nph)) <= TOL64
+
+
+@pytest.mark.parametrize("name,tune", [("multiband", {}), ("multiband", dict(chunk_entries=5)),
+                                       ("parabolic4", {}), ("random_order", dict(chunk_entries=37)),
+                                       ("tb12", {}), ("defect", {}), ("grouped", {})])
+def test_tile_tables(driver, tmp_path, name, tune):
+    """Every LDS tile of the three tile tables (forward, reverse/transport,
+    single copy) stages 1 .. cap states, its window holds every partner of its
+    chunks, and the tiles cover the chunks in order."""
+    if name == "multiband":
+        s = synth.multiband_system()
+    elif name == "grouped":
+        base = synth.tb_system(kn=12, qn=6, target_states=120, sigma=0.05, with_channels=False)
+        s = synth.grouped_system(n_systems=4, ch_min=100, ch_max=3000, base=base)
+    else:
+        s = SWEEP_SYSTEMS[name]()
+    if name == "defect":
+        tune = dict(tune, elastic_modes=1 << s.meta["elastic_mode"])
+    _write(tmp_path, s, f=synth.random_occupations(s, 1), nph=s.nph(300.0), **tune)
+    _run(driver, tmp_path, "tiles")
+    assert np.all(_out(tmp_path, "tiles") == 0), _out(tmp_path, "tiles")
