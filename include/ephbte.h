@@ -44,8 +44,16 @@
  * Errors: every call returns a status and never throws.  Arguments are checked
  *   before any work is enqueued; on error nothing is enqueued and
  *   ephbte_last_error() (thread-local) describes the failure.
- * Determinism: no atomics; every reduction has a fixed order, so results are
- *   bitwise reproducible run to run for a given plan and launch configuration.
+ * Determinism: results are bitwise reproducible run to run for a given plan
+ *   and launch configuration.  Floating-point sums have a fixed order and use
+ *   no atomics.  Two passes use integer atomics on 64-bit fixed-point values:
+ *   the single-copy forward pass (partner side of each channel) and the
+ *   phonon-side rate (its (q, mode) bins).  Integer addition is associative,
+ *   so those sums do not depend on the order of arrival.  The fixed-point
+ *   scale is a power of two chosen per call from max |N| of the call's table
+ *   and the largest sum of |g|^2 over one state's channels; it assumes
+ *   occupations f in [0, 1] (a caller's f outside that range, or RK stage
+ *   inputs that leave it, can overflow the partner-side sums).
  */
 #ifndef EPHBTE_H
 #define EPHBTE_H

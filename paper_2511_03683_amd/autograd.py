@@ -22,6 +22,8 @@ class CollisionIntegral(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, gI):
+        if ctx.needs_input_grad[3]:
+            raise NotImplementedError("collision: no gradient with respect to the phonon occupations")
         f, nph = ctx.saved_tensors
         plan = ctx.plan
         want_g2 = ctx.needs_input_grad[1]
@@ -47,6 +49,8 @@ class RtSolve(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, gfT):
+        if ctx.needs_input_grad[3]:
+            raise NotImplementedError("rt_solve: no gradient with respect to the phonon occupations")
         f0, nph = ctx.saved_tensors
         dt, n, ce = ctx.args
         gf0, gg2 = binding.rt_adjoint(ctx.plan, f0, nph, dt, n, ce, gfT.contiguous(),

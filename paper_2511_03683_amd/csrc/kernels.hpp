@@ -12,7 +12,10 @@
 // (coalesced pnu/g2 streams), gather the partner's state record, occupation
 // and phonon data (cache resident), evaluate the two Gaussians and fold the
 // entry into two running sums, then combine lanes with a fixed
-// shuffle tree and waves through LDS in fixed order.  No atomics anywhere.
+// shuffle tree and waves through LDS in fixed order.  Floating-point sums
+// never use atomics; the single-copy pass and the phonon-side rate add
+// 64-bit fixed-point integers with integer atomics, which are associative,
+// so every result is bitwise reproducible.
 //
 // Entry algebra (Eq. 2 with the golden-rule occupation factors).  With
 // da = exp(-(e_d - e_p + hw)^2 / 2 s^2), de = exp(-(e_d - e_p - hw)^2 / 2 s^2)
@@ -500,11 +503,15 @@ __device__ __forceinline__ void fwd_chunk2(const TiledArgs<T> &A, const T *__res
             T ep, fp;
             uint32_t kp;
             if (LDS) {
+                // a masked lane reads slot 0 (inside the allocation) and then
+                // replaces what it read: partner = destination, so its table
+                // index is the q = 0 entry and its operands are finite,
+                // whatever the slot holds
                 const int pl = v ? p - p_lo : 0;
                 const Pair2<T> ef = s_ef[pl];
-                ep = ef.a;
-                fp = ef.b;
-                kp = s_kq[pl];
+                ep = v ? ef.a : sd.eps;
+                fp = v ? ef.b : T(0);
+                kp = v ? s_kq[pl] : kd;
             } else {
                 const StateRec<T> sp = A.st[p];
                 ep = sp.eps;
@@ -675,11 +682,13 @@ __device__ __forceinline__ void sym_chunk(const TiledArgs<T> &A, const T *__rest
             T ep, fp;
             uint32_t kp;
             if (LDS) {
+                // a masked lane: partner = destination (finite operands, the
+                // q = 0 table entry); it adds zero to slot 0 of the window
                 const int pl = v ? p - p_lo : 0;
                 const Pair2<T> ef = s_ef[pl];
-                ep = ef.a;
-                fp = ef.b;
-                kp = s_kq[pl];
+                ep = v ? ef.a : sd.eps;
+                fp = v ? ef.b : T(0);
+                kp = v ? s_kq[pl] : kd;
                 plo[u] = pl;
             } else {
                 const StateRec<T> sp = A.st[p];
@@ -888,11 +897,15 @@ __device__ __forceinline__ void vjp_chunk2(const TiledArgs<T> &A, const T *__res
             T ep, fp;
             uint32_t kp;
             if (LDS) {
+                // a masked lane reads slot 0 (inside the allocation) and then
+                // replaces what it read: partner = destination, so its table
+                // index is the q = 0 entry and its operands are finite,
+                // whatever the slot holds
                 const int pl = v ? p - p_lo : 0;
                 const Pair2<T> ef = s_ef[pl];
-                ep = ef.a;
-                fp = ef.b;
-                kp = s_kq[pl];
+                ep = v ? ef.a : sd.eps;
+                fp = v ? ef.b : T(0);
+                kp = v ? s_kq[pl] : kd;
             } else {
                 const StateRec<T> sp = A.st[p];
                 ep = sp.eps;
@@ -1042,10 +1055,12 @@ __device__ __forceinline__ void tr_chunk(const TiledArgs<T> &A, const T *__restr
             const int p = static_cast<int>(pn[u] >> 3);
             T x0, x1, x2;
             if (LDS) {
+                // a masked lane reads slot 0 and discards it (its weight is 0,
+                // and 0 times a stale non-finite value would not be)
                 const int pl = v ? p - p_lo : 0;
-                x0 = s_x[3 * pl];
-                x1 = s_x[3 * pl + 1];
-                x2 = s_x[3 * pl + 2];
+                x0 = v ? s_x[3 * pl] : T(0);
+                x1 = v ? s_x[3 * pl + 1] : T(0);
+                x2 = v ? s_x[3 * pl + 2] : T(0);
             } else {
                 const Vec4<T> xp = x[p];
                 x0 = xp.x;

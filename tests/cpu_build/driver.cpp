@@ -151,6 +151,29 @@ int main(int argc, char **argv) {
     t.tile_entries = static_cast<int32_t>(meta("tile_entries", 0));
     if (t.layout || t.chunk_entries || t.block_threads || t.xcd_map || t.batch_partners || t.tile_entries)
         check(ephbte_set_tuning(plan, &t), "set_tuning");
+    // empty_windows: every LDS tile whose chunks hold no entries gets an empty
+    // partner window (nothing staged), the shape that once made masked lanes
+    // read an unwritten LDS slot; the kernels must not depend on that slot
+    if (meta("empty_windows", 0.0) != 0.0) {
+        double emptied = 0;
+        struct Set { TileRec *t; int64_t n; const int64_t *beg, *end; };
+        const Set sets[3] = {{plan->tiles, plan->n_tiles, plan->chunk_beg, nullptr},
+                             {plan->small_tiles, plan->n_small_tiles, plan->chunk_beg, nullptr},
+                             {plan->sym_tiles, plan->n_sym_tiles, plan->sym_chunk_beg, plan->sym_chunk_end}};
+        for (const Set &x : sets) {
+            for (int64_t i = 0; i < x.n; ++i) {
+                TileRec &t = x.t[i];
+                if (!t.lds) continue;
+                int64_t ents = 0;
+                for (int64_t c = t.c0; c < t.c1; ++c) ents += (x.end ? x.end[c] : x.beg[c + 1]) - x.beg[c];
+                if (ents == 0) {
+                    t.p_hi = t.p_lo - 1;
+                    emptied += 1;
+                }
+            }
+        }
+        wr("out_emptied.bin", {emptied});
+    }
     Dev dv{f32};
     // per-vector baths: nph holds B tables of [Nq][n_modes]
     const int per_batch = static_cast<int>(meta("nph_per_batch", 0));

@@ -459,6 +459,40 @@ def test_results_do_not_read_unwritten_memory(driver, tmp_path, k):
             assert np.array_equal(a, b)
 
 
+EMPTY_WINDOW_CASES = [("forward", dict(B=1)), ("forward", dict(B=1, layout=1)), ("vjp", dict(B=1)),
+                      ("rt", dict(B=1, dt=0.5, steps=2)), ("transport", dict())]
+
+
+@pytest.mark.parametrize("k", range(len(EMPTY_WINDOW_CASES)))
+def test_masked_lanes_ignore_empty_windows(driver, tmp_path, k):
+    """Tiles whose chunks hold no entries are given an empty partner window
+    (nothing staged in LDS) and LDS is filled with random bytes: the masked
+    lanes of those chunks must form their table index and operands without
+    the window, so the outputs are bitwise those of the plain run."""
+    mode, kw = EMPTY_WINDOW_CASES[k]
+    s = synth.multiband_system()
+    B = kw.get("B", 1)
+    F = np.stack([0.1 + 0.8 * synth.random_occupations(s, 120 + b) for b in range(B)])
+    lam = np.random.default_rng(19).normal(size=(B, s.n_states))
+    if mode == "transport":
+        f0 = synth.fermi_dirac(s.eps, float(np.min(s.eps)) - 0.05, 300.0)
+        vel = np.random.default_rng(20).normal(size=(s.n_states, 3)) * 1e5
+        _write(tmp_path, s, f=f0, vel=vel, nph=s.nph(300.0), T=300.0, tol=0.0, max_iter=4)
+        names = ["x", "mob"]
+    else:
+        _write(tmp_path, s, f=F, lam=lam, nph=s.nph(300.0), **kw)
+        names = {"forward": ["I"], "vjp": ["gf", "gg2"], "rt": ["f", "f_graph"]}[mode]
+    _run(driver, tmp_path, mode)
+    ref = [_out(tmp_path, n) for n in names]
+    with open(os.path.join(tmp_path, "meta.txt"), "a") as fh:
+        fh.write("empty_windows 1.0\n")
+    for fill in ("random:21", "random:22"):
+        _run(driver, tmp_path, mode, fill=fill)
+        assert _out(tmp_path, "emptied")[0] > 0, "the system has tiles without entries"
+        for n, a in zip(names, ref):
+            assert np.array_equal(_out(tmp_path, n), a), (mode, n, fill)
+
+
 SWEEP_SYSTEMS = {
     "parabolic4": lambda: synth.parabolic_system(4),
     "random_order": lambda: synth.random_channel_system(n_states=60, n_channels=900, seed=3),

@@ -45,7 +45,40 @@ def host(t):
 
 def nerr(x, ref, scale=None):
     s = np.abs(ref).max() if scale is None else scale
-    return float(np.abs(np.asarray(x) - ref).max() / max(s, 1e-300))
+    err = float(np.abs(np.asarray(x) - ref).max() / max(s, 1e-300))
+    print(f"[gpu-err] {err:.3e}", flush=True)
+    return err
+
+
+def rate_bound(sys, nph):
+    """Per-state bound on |I_d| that holds for any f in [0, 1]: every channel
+    of d adds at most C |g|^2 (2 N_max + 1) / (sigma sqrt(2 pi)) in magnitude
+    (C = 2 pi / (hbar N_q); each Gaussian is at most its peak)."""
+    C = 2 * np.pi / (oracle.HBAR_EV_FS * sys.n_q_norm) / (sys.sigma * np.sqrt(2 * np.pi))
+    w = np.asarray(sys.g2, np.float64) * (2 * np.abs(nph).max() + 1) * C
+    S = sys.n_states
+    return (np.bincount(sys.ch_i, weights=w, minlength=S) + np.bincount(sys.ch_j, weights=w, minlength=S))
+
+
+def plausible(x, bound):
+    """Every unsampled output is finite and within the per-state bound."""
+    x = np.asarray(x)
+    assert np.isfinite(x).all()
+    assert np.all(np.abs(x) <= bound * (1 + 1e-6) + 1e-300)
+
+
+def incident(sys, rows):
+    """Keep mask of the channels that touch the given states."""
+    return np.isin(sys.ch_i, rows) | np.isin(sys.ch_j, rows)
+
+
+def gross_scale(sys, f, nph, ref, rows=None):
+    """Norm of the FP32 bar: max(max|I_ref|, 1e-2 max(in, out)) over the rows
+    compared, from the oracle (in - out = I)."""
+    rin, rout = oracle.collision_inout(sys, f, nph)
+    if rows is not None:
+        rin, rout, ref = rin[rows], rout[rows], ref[rows]
+    return max(np.abs(ref).max(), 1e-2 * max(rin.max(), rout.max()))
 
 
 def round32(s):
@@ -661,7 +694,7 @@ def test_rt_step_coupled_matches_oracle(E, name, dtype):
     f0 = 0.1 + 0.8 * synth.random_occupations(s, 52)
     N0 = s.nph(300.0) * 1.5
     dt, n = 1.0, 3
-    r, tdt, tol = s, torch.float64, 1e-9
+    r, tdt, tol = s, torch.float64, TOL64
     if dtype == "f32":
         f0, N0 = f0.astype(np.float32).astype(np.float64), N0.astype(np.float32).astype(np.float64)
         r, tdt, tol = round32(s), torch.float32, 1e-5
@@ -793,8 +826,8 @@ def test_rt_adjoint_matches_oracle(E):
     for ce in (1, 2, 5):
         gf0, gg = E.rt_adjoint(plan, dev(f0), dev(nph), dt, n, ce, dev(gT), gg2=True)
         outs.append((host(gf0), host(gg)))
-        assert nerr(outs[-1][0], rf) <= 1e-9
-        assert nerr(outs[-1][1], rg) <= 1e-9
+        assert nerr(outs[-1][0], rf) <= TOL64
+        assert nerr(outs[-1][1], rg) <= TOL64
     for o in outs[1:]:
         assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1]), \
             "checkpointing does not change the gradient"
@@ -813,7 +846,7 @@ def test_rt_step_with_field(E, dtype, B):
     nph = s.nph(300.0)
     F = np.stack([synth.random_occupations(s, 30 + b) for b in range(B)])
     dt, n = 1.0, 4
-    r, tdt, tol = s, torch.float64, 1e-9
+    r, tdt, tol = s, torch.float64, TOL64
     if dtype == "f32":
         F, nph = F.astype(np.float32).astype(np.float64), nph.astype(np.float32).astype(np.float64)
         r, tdt, tol = round32(s), torch.float32, 1e-5
@@ -854,8 +887,8 @@ def test_rt_adjoint_with_field(E):
     E.set_field(plan, RATES)
     say("rt_adjoint field")
     gf0, gg = E.rt_adjoint(plan, dev(f0), dev(nph), dt, n, 2, dev(gT), gg2=True)
-    assert nerr(host(gf0), rf) <= 1e-9
-    assert nerr(host(gg), rg) <= 1e-9
+    assert nerr(host(gf0), rf) <= TOL64
+    assert nerr(host(gg), rg) <= TOL64
     plan.close()
 
 
@@ -902,8 +935,8 @@ def test_rt_solve_autograd(E):
     L.backward()
     gT = host((eps * fT.sum() - (eps * fT).sum()) / fT.sum() ** 2)
     _, rf, rg = oracle.rk4_trajectory_grad(s, host(f0), s.nph(300.0), 0.5, 4, gT)
-    assert nerr(host(f0.grad), rf) <= 1e-9
-    assert nerr(host(g2.grad), rg) <= 1e-9
+    assert nerr(host(f0.grad), rf) <= TOL64
+    assert nerr(host(g2.grad), rg) <= TOL64
     plan.close()
 
 
@@ -928,14 +961,15 @@ def test_transport_matches_oracle(E, dtype):
         conv = E.iterate_transport(plan, dev(f0), dev(s.vel), T, dev(nph), tol=1e-10, max_iter=500)
         refc = oracle.transport_solve(s, f0, s.vel, T, nph, tol=1e-10, max_iter=500)
         assert conv["converged"] and conv["iters"] == refc["iters"]
-        assert nerr(conv["mu"], refc["mu"]) <= 1e-9
+        assert nerr(conv["mu"], refc["mu"]) <= TOL64
     else:
         r = round32(s)
         f32 = f0.astype(np.float32).astype(np.float64)
         ref = oracle.transport_solve(r, f32, s.vel.astype(np.float32).astype(np.float64), T,
                                      nph.astype(np.float32).astype(np.float64), max_iter=k,
                                      stop_on_tol=False)
-        assert nerr(out["mu"], ref["mu"]) <= 1e-4
+        assert nerr(out["mu"], ref["mu"]) <= TOL32
+        assert nerr(host(out["x"]), ref["x"]) <= TOL32
     plan.close()
 
 
@@ -956,7 +990,7 @@ def test_transport_fp32_stops_at_its_floor(E):
     assert out["stagnated"] or (out["converged"] and out["resid"] == 0.0)
     ref = oracle.transport_solve(s, f0, s.vel, T, nph, tol=1e-12, max_iter=2000)
     assert ref["converged"]
-    assert nerr(out["mu"], ref["mu"]) <= 1e-4
+    assert nerr(out["mu"], ref["mu"]) <= TOL32
     plan.close()
 
 
@@ -969,7 +1003,10 @@ def c2():
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_full_size_sampled_parity(E, c2, dtype):
     """The 100^3/50^3, ~2e8-channel system in the launch configuration the
-    benchmark times; the oracle evaluates 48 sampled destinations."""
+    benchmark times; the oracle evaluates 48 sampled destinations, and the
+    error is normalised by the oracle's values there (FP32: by their gross
+    rates, as on the small systems).  Every other output is checked against
+    a per-state bound."""
     s = c2
     rng = np.random.default_rng(17)
     f = np.clip(synth.fermi_dirac(s.eps, 0.05, 300.0) * (0.8 + 0.4 * rng.uniform(size=s.n_states)), 0, 1)
@@ -982,20 +1019,22 @@ def test_full_size_sampled_parity(E, c2, dtype):
     plan = E.build_channels(s, dtype=dtype, device=0)
     I = host(E.collision_integral(plan, dev(f, tdt), dev(nph, tdt)))
     plan.close()
-    mask = np.zeros(s.n_states, bool)
-    mask[rng.choice(s.n_states, 48, replace=False)] = True
-    r = s if dtype == "f64" else round32(s)
-    ref = oracle.collision(r, f, nph, mask=mask)
-    tol = TOL64 if dtype == "f64" else TOL32
+    dests = rng.choice(s.n_states, 48, replace=False)
+    r = oracle.subset(s if dtype == "f64" else round32(s), incident(s, dests))
+    ref = oracle.collision(r, f, nph)
+    plausible(I, rate_bound(s, nph))
     if dtype == "f64":
         assert abs(I.sum()) <= 1e-10 * np.abs(I).sum()
-    assert nerr(I[mask], ref[mask], np.abs(I).max()) <= tol
+        assert nerr(I[dests], ref[dests]) <= TOL64
+    else:
+        assert nerr(I[dests], ref[dests], gross_scale(r, f, nph, ref, dests)) <= TOL32
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_full_size_batched_sampled_parity(E, c2, dtype):
     """B = 64 vectors of the full-size system in one pass, as the benchmark
-    times it; two columns checked on 32 sampled destinations."""
+    times it; two columns checked on 32 sampled destinations, normalised by
+    the oracle there; every column within the per-state bound."""
     s = c2
     rng = np.random.default_rng(23)
     B = 64
@@ -1011,13 +1050,15 @@ def test_full_size_batched_sampled_parity(E, c2, dtype):
     plan = E.build_channels(s, dtype=dtype, device=0)
     I = host(E.collision_integral(plan, dev(F, tdt), dev(nph, tdt)))
     plan.close()
-    mask = np.zeros(s.n_states, bool)
-    mask[rng.choice(s.n_states, 32, replace=False)] = True
-    r = s if dtype == "f64" else round32(s)
-    tol = TOL64 if dtype == "f64" else TOL32
+    plausible(I, rate_bound(s, nph)[None, :])
+    dests = rng.choice(s.n_states, 32, replace=False)
+    r = oracle.subset(s if dtype == "f64" else round32(s), incident(s, dests))
     for b in (7, 63):
-        ref = oracle.collision(r, F[b], nph, mask=mask)
-        assert nerr(I[b][mask], ref[mask], np.abs(I[b]).max()) <= tol, b
+        ref = oracle.collision(r, F[b], nph)
+        if dtype == "f64":
+            assert nerr(I[b][dests], ref[dests]) <= TOL64, b
+        else:
+            assert nerr(I[b][dests], ref[dests], gross_scale(r, F[b], nph, ref, dests)) <= TOL32, b
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
@@ -1050,8 +1091,9 @@ def test_full_size_batched_vjp_sampled_parity(E, c2, dtype):
         rf[b] = f_b
         rg += g_b
     tol = TOL64 if dtype == "f64" else TOL32
-    assert nerr(gf[:, dests], rf[:, dests], np.abs(gf).max()) <= tol
-    assert nerr(gg[inc], rg, np.abs(gg).max()) <= tol
+    assert np.isfinite(gf).all() and np.isfinite(gg).all()
+    assert nerr(gf[:, dests], rf[:, dests]) <= tol
+    assert nerr(gg[inc], rg) <= tol
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
@@ -1076,8 +1118,9 @@ def test_full_size_vjp_sampled_parity(E, c2, dtype):
     inc = np.isin(s.ch_i, dests) | np.isin(s.ch_j, dests)
     rf, rg = oracle.collision_vjp(oracle.subset(s if dtype == "f64" else round32(s), inc), f, nph, lam)
     tol = TOL64 if dtype == "f64" else TOL32
-    assert nerr(gf[dests], rf[dests], np.abs(gf).max()) <= tol
-    assert nerr(gg[inc], rg, np.abs(gg).max()) <= tol
+    assert np.isfinite(gf).all() and np.isfinite(gg).all()
+    assert nerr(gf[dests], rf[dests]) <= tol
+    assert nerr(gg[inc], rg) <= tol
 
 
 def test_full_size_phonon_rate_sampled_parity(E, c2):
@@ -1111,7 +1154,8 @@ def test_full_size_phonon_rate_sampled_parity(E, c2):
     ref = oracle.phonon_rate(oracle.subset(s, keep), f, nph).reshape(-1)
     got = dN.reshape(-1)
     assert np.abs(ref[bins]).max() > 0
-    assert nerr(got[bins], ref[bins], np.abs(got).max()) <= TOL64
+    assert np.isfinite(got).all()
+    assert nerr(got[bins], ref[bins]) <= TOL64
 
 
 # ------------------------------------------------------------------ uneven batch
@@ -1141,12 +1185,17 @@ def test_grouped_uneven_systems_one_launch(E, grouped, dtype):
     for m in range(len(offs) - 1):
         mask[rng.choice(np.arange(offs[m], offs[m + 1]), 3, replace=False)] = True
     r = s if dtype == "f64" else round32(s)
+    plausible(I, rate_bound(s, nph))
     ref = oracle.collision(r, f, nph, mask=mask)
-    tol = TOL64 if dtype == "f64" else TOL32
+    if dtype == "f32":
+        rin, rout = oracle.collision_inout(r, f, nph)
     for m in range(len(offs) - 1):
-        sl = slice(offs[m], offs[m + 1])
-        sub = mask[sl]
-        assert nerr(I[sl][sub], ref[sl][sub], np.abs(I[sl]).max()) <= tol, m
+        rows = np.arange(offs[m], offs[m + 1])[mask[offs[m]:offs[m + 1]]]
+        if dtype == "f64":
+            assert nerr(I[rows], ref[rows]) <= TOL64, m
+        else:
+            scale = max(np.abs(ref[rows]).max(), 1e-2 * max(rin[rows].max(), rout[rows].max()))
+            assert nerr(I[rows], ref[rows], scale) <= TOL32, m
 
 
 # ------------------------------------------------------------------ gradients
@@ -1166,8 +1215,8 @@ def test_rt_adjoint_cpu_reference_512k(E):
     say("rt_adjoint 512-k vs oracle")
     gf0, gg = E.rt_adjoint(plan, dev(f0), dev(nph), dt, n, 2, dev(gT), gg2=True)
     plan.close()
-    assert nerr(host(gf0), rf) <= 1e-9
-    assert nerr(host(gg), rg) <= 1e-9
+    assert nerr(host(gf0), rf) <= TOL64
+    assert nerr(host(gg), rg) <= TOL64
 
 
 def test_full_size_rt_adjoint_finite_differences(E, c2):
