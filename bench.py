@@ -24,11 +24,27 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-# Algorithmic bytes per unordered channel.  The single-copy pass (the default
-# for B = 1) streams one entry per channel: |g|^2 + packed partner/mode word;
-# the per-row pass streams both entries of each channel.
-BYTES_PER_CHANNEL = {"f64": 12.0, "f32": 8.0}
+# Algorithmic bytes per unordered channel.  The single-copy pass over entries
+# streams one entry per channel (|g|^2 + packed partner/mode word); the
+# per-row pass streams both entries of each channel.  The single-copy pass
+# over pair records (the default where they are built) streams one partner
+# word per state pair and one |g|^2 per mode slot: pair_bytes() below.
+BYTES_PER_CHANNEL_ENTRIES = {"f64": 12.0, "f32": 8.0}
 BYTES_PER_CHANNEL_ROWS = {"f64": 24.0, "f32": 16.0}
+
+
+LAYOUT_NAMES = {1: "duplicated rows", 2: "single copy, one entry per channel",
+                3: "single copy over pair records"}
+KERNEL_OF_LAYOUT = {1: "k_fwd_tiled", 2: "k_fwd_sym", 3: "k_fwd_pairs"}
+
+
+def pair_bytes(info, n_modes, dtype):
+    """Bytes per channel of the pass the plan runs at B = 1: pair records
+    (4 B partner + n_modes |g|^2 slots per pair) or one entry per channel."""
+    if info["layout"] == 3 and info["pair_records"] > 0:
+        es = 8 if dtype == "f64" else 4
+        return info["pair_records"] * (4 + n_modes * es) / info["channels_kept"]
+    return BYTES_PER_CHANNEL_ENTRIES[dtype]
 # reverse pass: the same entry stream, the channel index of the entry that
 # writes dL/d|g|^2 (4 B) and that FP64 value (8 B), per unordered channel
 VJP_BYTES_PER_CHANNEL = {"f64": 24.0 + 4.0 + 8.0, "f32": 16.0 + 4.0 + 8.0}
@@ -99,7 +115,8 @@ def main():
                     help="after the main step run only the B = 1 reverse pass, the phonon-side "
                          "rate and the transport iterations (for tracing their kernels)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-channels", type=int, default=100_000_000)
+    ap.add_argument("--cpu-channels", type=int, default=20_000_000,
+                    help="channels of the one-core oracle timing")
     ap.add_argument("--dtype", choices=("f64", "f32"), default="f64",
                     help="precision of the main step (f32 only with --no-forms, for profiling)")
     ap.add_argument("--copy-calib", action="store_true",
@@ -167,7 +184,10 @@ def main():
     t0 = time.time()
     mdt = torch.float64 if args.dtype == "f64" else torch.float32
     plan64 = E.build_channels(s, dtype=args.dtype, device=0)
-    log(f"{args.dtype} plan built ({time.time() - t0:.1f}s), info={E.plan_info(plan64)}")
+    info64 = E.plan_info(plan64)
+    layout64 = info64["layout"]
+    bpc = pair_bytes(info64, s.n_modes, args.dtype)
+    log(f"{args.dtype} plan built ({time.time() - t0:.1f}s), info={info64}, {bpc:.3f} B per channel")
     f64, n64 = tens(f_np, mdt), tens(nph_np, mdt)
     I64 = torch.empty_like(f64)
 
@@ -202,8 +222,8 @@ def main():
     if kernel_launches != args.steps:
         raise RuntimeError(f"{kernel_launches} timed kernel launches for {args.steps} steps")
     value = nch / (ms * 1e-3)
-    achieved = BYTES_PER_CHANNEL[args.dtype] * nch / (ms * 1e-3) / 1e9
-    kernel_gbps = BYTES_PER_CHANNEL[args.dtype] * nch / (kernel_ms * 1e-3) / 1e9
+    achieved = bpc * nch / (ms * 1e-3) / 1e9
+    kernel_gbps = bpc * nch / (kernel_ms * 1e-3) / 1e9
     log(f"fwd {args.dtype}: {ms:.3f} ms/eval, {value:.3e} ch/s, {achieved:.0f} GB/s algorithmic "
         f"(wall {wall:.2f}s for {args.steps}); kernel alone {kernel_ms:.3f} ms, {kernel_gbps:.0f} GB/s")
 
@@ -222,7 +242,8 @@ def main():
         msp, _ = timed(lambda: E.phonon_rate(plan64, f64, n64, out=dN), reps, 1)
         forms["phonon_rate_f64"] = dict(ms=msp, channels_per_s=nch / (msp * 1e-3),
                                         bins=int(s.n_q * s.n_modes),
-                                        note="one 64-bit integer atomic per entry into its (q, mode) bin")
+                                        note="channels grouped by phonon pair {q, -q}; one wave per "
+                                             "chunk of pair records, no atomics")
         log(f"phonon rate fp64: {msp:.3f} ms")
 
     def transport_iter():
@@ -258,11 +279,28 @@ def main():
 
     if not args.no_forms:
         forms["fwd_f64_b1"] = dict(ms=ms, channels_per_s=value, algorithmic_GBps=achieved,
-                                   layout="single copy")
-        # the per-row pass (each channel evaluated in both of its rows)
+                                   layout=LAYOUT_NAMES[layout64], bytes_per_channel=bpc)
+        # the other layouts of the same pass: one entry per channel (single
+        # copy without pair records) and the per-row pass (each channel
+        # evaluated in both of its rows)
+        if layout64 == 3:
+            # the pair pass with the polynomial exponential (no LDS table reads)
+            E.set_tuning(plan64, fp64_exp=2)
+            msp2, _ = timed(fwd64, args.steps, args.warmup)
+            E.set_tuning(plan64, fp64_exp=1)
+            forms["fwd_f64_b1_pairs_polyexp"] = dict(ms=msp2, channels_per_s=nch / (msp2 * 1e-3),
+                                                     algorithmic_GBps=bpc * nch / (msp2 * 1e-3) / 1e9)
+            log(f"fwd fp64 pair records, polynomial exponential: {msp2:.3f} ms")
+            E.set_tuning(plan64, layout=2)
+            mse, _ = timed(fwd64, args.steps, args.warmup)
+            forms["fwd_f64_b1_entries"] = dict(ms=mse, channels_per_s=nch / (mse * 1e-3),
+                                               algorithmic_GBps=BYTES_PER_CHANNEL_ENTRIES["f64"] * nch
+                                               / (mse * 1e-3) / 1e9,
+                                               layout="single copy, one entry per channel")
+            log(f"fwd fp64 single copy over entries: {mse:.3f} ms")
         E.set_tuning(plan64, layout=1)
         msr, _ = timed(fwd64, args.steps, args.warmup)
-        E.set_tuning(plan64, layout=2)
+        E.set_tuning(plan64, layout=layout64)
         forms["fwd_f64_b1_rows"] = dict(ms=msr, channels_per_s=nch / (msr * 1e-3),
                                         algorithmic_GBps=BYTES_PER_CHANNEL_ROWS["f64"] * nch / (msr * 1e-3) / 1e9,
                                         layout="duplicated rows")
@@ -271,7 +309,7 @@ def main():
         ms_v = vjp_b1(max(3, args.steps // 4))
         forms["fwd_plus_adjoint_f64_b1"] = dict(
             ms=ms + ms_v, channels_per_s=nch / ((ms + ms_v) * 1e-3),
-            algorithmic_GBps=(BYTES_PER_CHANNEL["f64"] + VJP_BYTES_PER_CHANNEL["f64"]) * nch
+            algorithmic_GBps=(bpc + VJP_BYTES_PER_CHANNEL["f64"]) * nch
             / ((ms + ms_v) * 1e-3) / 1e9)
         log(f"vjp fp64: {ms_v:.3f} ms")
         # batched B = 64: 16 temperatures x 4 fields, sub-tile size from the autotuner
@@ -362,17 +400,27 @@ def main():
     if not args.no_forms:
         t0 = time.time()
         plan32 = E.build_channels(s, dtype="f32", device=0)
+        info32 = E.plan_info(plan32)
+        bpc32 = pair_bytes(info32, s.n_modes, "f32")
         log(f"fp32 plan built ({time.time() - t0:.1f}s)")
         f32, n32 = tens(f_np, torch.float32), tens(nph_np, torch.float32)
         I32 = torch.empty_like(f32)
         ms32, _ = timed(lambda: E.collision_integral(plan32, f32, n32, out=I32), args.steps, args.warmup)
         forms["fwd_f32_b1"] = dict(ms=ms32, channels_per_s=nch / (ms32 * 1e-3),
-                                   algorithmic_GBps=BYTES_PER_CHANNEL["f32"] * nch / (ms32 * 1e-3) / 1e9,
-                                   layout="single copy")
+                                   algorithmic_GBps=bpc32 * nch / (ms32 * 1e-3) / 1e9,
+                                   layout=LAYOUT_NAMES[info32["layout"]], bytes_per_channel=bpc32)
         log(f"fwd fp32: {ms32:.3f} ms")
+        if info32["layout"] == 3:
+            E.set_tuning(plan32, layout=2)
+            ms32e, _ = timed(lambda: E.collision_integral(plan32, f32, n32, out=I32), args.steps, args.warmup)
+            forms["fwd_f32_b1_entries"] = dict(ms=ms32e, channels_per_s=nch / (ms32e * 1e-3),
+                                               algorithmic_GBps=BYTES_PER_CHANNEL_ENTRIES["f32"] * nch
+                                               / (ms32e * 1e-3) / 1e9,
+                                               layout=LAYOUT_NAMES[2])
+            log(f"fwd fp32 single copy over entries: {ms32e:.3f} ms")
         E.set_tuning(plan32, layout=1)
         ms32r, _ = timed(lambda: E.collision_integral(plan32, f32, n32, out=I32), args.steps, args.warmup)
-        E.set_tuning(plan32, layout=2)
+        E.set_tuning(plan32, layout=info32["layout"])
         forms["fwd_f32_b1_rows"] = dict(ms=ms32r, channels_per_s=nch / (ms32r * 1e-3),
                                         algorithmic_GBps=BYTES_PER_CHANNEL_ROWS["f32"] * nch / (ms32r * 1e-3) / 1e9,
                                         layout="duplicated rows")
@@ -423,6 +471,7 @@ def main():
                      * (0.8 + 0.4 * rng.uniform(size=gsys.n_states)), 0, 1)
         for dname, tdt in (("f64", torch.float64), ("f32", torch.float32)):
             gplan = E.build_channels(gsys, dtype=dname, device=0)
+            gbpc = pair_bytes(E.plan_info(gplan), gsys.n_modes, dname)
             gft, gnt = tens(gf, tdt), tens(gsys.nph(300.0), tdt)
             gI = torch.empty_like(gft)
             msg, _ = timed(lambda: E.collision_integral(gplan, gft, gnt, out=gI), args.steps, args.warmup)
@@ -430,21 +479,16 @@ def main():
                 ms=msg, channels_per_s=gsys.n_channels / (msg * 1e-3), systems=16,
                 channels=gsys.n_channels, smallest=int(np.diff(gsys.meta["ch_offsets"]).min()),
                 largest=int(np.diff(gsys.meta["ch_offsets"]).max()),
-                algorithmic_GBps=BYTES_PER_CHANNEL[dname] * gsys.n_channels / (msg * 1e-3) / 1e9)
+                algorithmic_GBps=gbpc * gsys.n_channels / (msg * 1e-3) / 1e9)
             log(f"grouped 16 systems {dname}: {msg:.3f} ms, {gsys.n_channels / (msg * 1e-3):.3e} ch/s "
                 f"({time.time() - t0:.1f}s incl. generation)")
             gplan.close()
 
     cpu = None
     if not args.no_cpu:
+        # the oracle's unchanged FP64 channel loop on the host cores of this machine
         import copy
         import oracle
-        n = min(args.cpu_channels, nch)
-        ss = copy.copy(s)
-        ss.ch_i, ss.ch_j, ss.ch_nu, ss.g2 = s.ch_i[:n], s.ch_j[:n], s.ch_nu[:n], s.g2[:n]
-        w0 = time.perf_counter()
-        oracle.collision(ss, f_np, nph_np)
-        dtc = time.perf_counter() - w0
         model = "unknown CPU"
         try:
             with open("/proc/cpuinfo") as fh:
@@ -452,10 +496,51 @@ def main():
                              model)
         except OSError:
             pass
-        cpu = dict(value=n / dtc, unit="channels/s", cores=1, kind="oracle",
-                   sample=f"first {n} of {nch} channels, one FP64 evaluation, sequential C loop "
-                          f"({dtc:.1f} s) on {model} ({os.cpu_count()} logical CPUs visible)")
-        log(f"cpu oracle: {n / dtc:.3e} ch/s on 1 core")
+        ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+        a_full = oracle._Args(s, nph_np)
+        w0 = time.perf_counter()
+        oracle.collision_threads(s, f_np, nph_np, threads=ncpu, args=a_full)
+        t_all = time.perf_counter() - w0
+        # one core on a slice of the list
+        n1 = min(args.cpu_channels, nch)
+        ss = copy.copy(s)
+        ss.ch_i, ss.ch_j, ss.ch_nu, ss.g2 = s.ch_i[:n1], s.ch_j[:n1], s.ch_nu[:n1], s.g2[:n1]
+        w0 = time.perf_counter()
+        oracle.collision(ss, f_np, nph_np)
+        t_one = time.perf_counter() - w0
+        # one RK4 step: four evaluations on all cores plus the stage updates
+        w0 = time.perf_counter()
+        u = np.asarray(f_np, np.float64)
+        k1 = oracle.collision_threads(s, u, nph_np, threads=ncpu, args=a_full)
+        k2 = oracle.collision_threads(s, u + 0.5 * k1, nph_np, threads=ncpu, args=a_full)
+        k3 = oracle.collision_threads(s, u + 0.5 * k2, nph_np, threads=ncpu, args=a_full)
+        k4 = oracle.collision_threads(s, u + k3, nph_np, threads=ncpu, args=a_full)
+        u = u + (k1 + 2.0 * k2 + 2.0 * k3 + k4) / 6.0
+        t_rk = time.perf_counter() - w0
+        del a_full, k1, k2, k3, k4, u
+        # one transport iteration (numpy over the oracle's coefficients) on a slice
+        nt = min(20_000_000, nch)
+        st_ = copy.copy(s)
+        st_.ch_i, st_.ch_j, st_.ch_nu, st_.g2 = s.ch_i[:nt], s.ch_j[:nt], s.ch_nu[:nt], s.g2[:nt]
+        f0t = synth.fermi_dirac(s.eps, -0.1, 300.0)
+        _, Wij, Wji = oracle.transport_coeffs(st_, f0t, nph_np)
+        xt = np.asarray(s.vel) * oracle.dfde_fd(f0t, 300.0)[:, None]
+        w0 = time.perf_counter()
+        oracle.transport_apply_W(st_, Wij, Wji, xt)
+        t_tr = (time.perf_counter() - w0) * nch / nt
+        del Wij, Wji
+        cpu = dict(value=nch / t_all, unit="channels/s", cores=ncpu, kind="oracle",
+                   sample=f"all {nch} channels, one FP64 evaluation of I by the oracle's sequential C "
+                          f"channel loop run on {ncpu} threads over disjoint slices ({t_all:.2f} s), "
+                          f"{model}",
+                   one_core=dict(value=n1 / t_one, unit="channels/s",
+                                 sample=f"first {n1} channels, one thread ({t_one:.1f} s)"),
+                   rk4_step_s=t_rk, rk4_step_note=f"four evaluations on {ncpu} threads plus numpy stage updates",
+                   transport_iteration_s=t_tr,
+                   transport_iteration_note=f"numpy W x of the oracle over the first {nt} channels, "
+                                            "scaled to the whole list")
+        log(f"cpu oracle: {nch / t_all:.3e} ch/s on {ncpu} threads ({t_all:.2f} s), "
+            f"{n1 / t_one:.3e} ch/s on 1 core; RK4 step {t_rk:.2f} s, transport iteration {t_tr:.2f} s")
 
     out = {
         "metric": "scattering channels/sec and HBM GB/s (fwd, fwd+adjoint), B=1 vs B=64",
@@ -479,12 +564,12 @@ def main():
         "frac_of_copy": kernel_gbps / copy_gbps,
         "roofline": {"bound": "hbm", "achieved": kernel_gbps, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": kernel_gbps / HBM_PEAK_GBS,
-                     "traffic": profiled_traffic(f"k_fwd_sym_{args.dtype}_{wname}"),
-                     "kernel": "k_fwd_sym (single-copy forward pass)",
+                     "traffic": profiled_traffic(f"{KERNEL_OF_LAYOUT[layout64]}_{args.dtype}_{wname}"),
+                     "kernel": f"{KERNEL_OF_LAYOUT[layout64]} (forward pass, {LAYOUT_NAMES[layout64]})",
                      "kernel_ms": kernel_ms,
                      "kernel_ms_from": f"HIP events around each of its {kernel_launches} launches "
                                        "in the timed steps, on the launch stream",
-                     "bytes_per_channel": BYTES_PER_CHANNEL[args.dtype]},
+                     "bytes_per_channel": bpc},
         "cpu_baseline": cpu,
         "forms": forms,
     }

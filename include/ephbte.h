@@ -118,9 +118,16 @@ typedef struct {
                                   library's default                               */
     int32_t layout;            /* single-vector forward pass: 1 = every channel
                                   evaluated in both of its rows, 2 = once, from
-                                  the row of its smaller state (default where the
-                                  LDS per workgroup allows it)                     */
-    int32_t reserved[2];       /* must be 0                                        */
+                                  the row of its smaller state, one entry per
+                                  channel, 3 = once, over pair records (all modes
+                                  of a state pair together; the default when at
+                                  least half of the records' mode slots hold a
+                                  channel, else 2 is the default; both need the
+                                  LDS per workgroup to allow them)                */
+    int32_t fp64_exp;          /* FP64 Gaussians of the pair-record pass: 1 = table
+                                  exponential (256 powers of 2^(1/256) in LDS,
+                                  default), 2 = polynomial only (no LDS reads)   */
+    int32_t reserved[1];       /* must be 0                                        */
 } ephbte_tuning;
 
 /* Build options.  Channel selection (paper: scattering-channel paragraph
@@ -222,11 +229,40 @@ ephbte_status ephbte_collision_vjp(ephbte_plan plan, int32_t batch, const void *
  * N_k the full k-grid count.  Elastic mechanisms add nothing.
  * f: device [S] (one vector), plan dtype.  nph: device [Nq][n_modes].
  * dN: device [Nq][n_modes], plan dtype, written (1/fs).
- * Bins are summed as 64-bit fixed point with integer atomics (bitwise
- * reproducible).  The first call allocates the bins.
+ * Layout: at build the channels are grouped by the phonon pair {q, -q} they
+ * exchange (one record per state pair with a |g|^2 slot per mode), so every
+ * bin is the sum of one group's terms: one wave per chunk of records, partial
+ * sums added in chunk order, no atomics (bitwise reproducible).  The first
+ * call allocates the chunk partials.
  */
 ephbte_status ephbte_phonon_rate(ephbte_plan plan, const void *f, const void *nph, void *dN,
                                  void *stream);
+
+/*
+ * Reverse of ephbte_phonon_rate: given gR = dL/d(dN/dt) (device [Nq][n_modes],
+ * plan dtype), writes gf = dL/df (device [S], plan dtype), gnph = dL/dN
+ * (device [Nq][n_modes], plan dtype) and adds (accumulate_gg2 != 0) or writes
+ * gg2 = dL/d|g|^2 (device FP64 [n_channels], caller order); each output may be
+ * NULL.  Derivatives of the rate's terms: the rate is quadratic in f and
+ * affine in N and |g|^2 (elastic mechanisms contribute nothing).  dL/df is a
+ * per-destination reduction over the destination layout; dL/dN and dL/d|g|^2
+ * come from the records grouped by {q, -q}; no atomics.
+ */
+ephbte_status ephbte_phonon_rate_vjp(ephbte_plan plan, const void *f, const void *nph, const void *gR,
+                                     void *gf, void *gnph, double *gg2, int32_t accumulate_gg2,
+                                     void *stream);
+
+/*
+ * dL/dN of L = sum_d gI_d I_d (Eq. 2 at f and nph): gnph, device
+ * [Nq][n_modes], plan dtype, overwritten.  Eq. 2 is affine in N: the summand
+ * of destination d, partner p through (nu, q = k_p - k_d) has derivative
+ * -K |g|^2 [G(e_d - e_p + hw) + G(e_d - e_p - hw)] (f_d - f_p) with respect to
+ * N(q, nu) (K = 2 pi / (hbar N_q)); both orientations of every channel count,
+ * elastic mechanisms included.  f, gI: device [S]; nph: device [Nq][n_modes].
+ * Computed over the records grouped by {q, -q}, no atomics.
+ */
+ephbte_status ephbte_collision_vjp_nph(ephbte_plan plan, const void *f, const void *nph, const void *gI,
+                                       void *gnph, void *stream);
 
 /*
  * Coupled electron-phonon dynamics: advances f (device [S]) and the phonon
@@ -244,6 +280,28 @@ ephbte_status ephbte_phonon_rate(ephbte_plan plan, const void *f, const void *np
  */
 ephbte_status ephbte_rt_step_coupled(ephbte_plan plan, void *f, void *nph, double dt_fs,
                                      int32_t n_steps, void *stream);
+
+/*
+ * Reverse mode through n_steps coupled RK4 steps of ephbte_rt_step_coupled
+ * from (f0, nph0): the exact discrete adjoint of the computed steps, for a
+ * loss L(f_T, N_T) with gfT = dL/df_T (device [S]) and gNT = dL/dN_T (device
+ * [Nq][n_modes]); either may be NULL (zero).  Writes gf0 = dL/df0 and
+ * gN0 = dL/dnph0 (same shapes, plan dtype, nullable) and writes, or adds to
+ * (accumulate_gg2 != 0), gg2 = dL/d|g|^2 (device FP64 [n_channels], caller
+ * order, nullable).  Per stage (u, M) with adjoint (a, b) the transposed
+ * Jacobian of the right-hand side (I[u, M], E R[u, M]), E the even part in q
+ * (its own transpose), gives J_If^T a + J_Rf^T E b for f, J_IN^T a + J_RN^T E b
+ * for N and J_Ig^T a + J_Rg^T E b for |g|^2.  (f, N) are checkpointed every
+ * checkpoint_every steps and the stage inputs of a segment recomputed
+ * (device memory: 4 checkpoint_every + 1 copies of (f, N)).  Not a step of
+ * the paper (its code has no reverse mode).  INVALID_ARGUMENT for NULL f0 or
+ * nph0, n_steps < 1, checkpoint_every < 1, a non-finite dt_fs, or gf0 / gN0
+ * overlapping f0 / nph0.
+ */
+ephbte_status ephbte_rt_adjoint_coupled(ephbte_plan plan, const void *f0, const void *nph0, double dt_fs,
+                                        int32_t n_steps, int32_t checkpoint_every, const void *gfT,
+                                        const void *gNT, void *gf0, void *gN0, double *gg2,
+                                        int32_t accumulate_gg2, void *stream);
 
 /*
  * Field term of Eq. 1 for ephbte_rt_step and ephbte_rt_adjoint: they then
@@ -345,8 +403,10 @@ ephbte_status ephbte_kernel_timing(ephbte_plan plan, int32_t mode, double *mean_
 
 /* Plan facts: out[0]=S, [1]=n_channels passed at build, [2]=entries,
  * [3]=chunks, [4]=dtype, [5]=device, [6]=device bytes held,
- * [7]=chunk_entries, [8]=block_threads, [9]=channels kept by the selection. */
-ephbte_status ephbte_plan_info(ephbte_plan plan, int64_t out[10]);
+ * [7]=chunk_entries, [8]=block_threads, [9]=channels kept by the selection,
+ * [10]=layout of the single-vector forward pass (ephbte_tuning.layout),
+ * [11]=pair records of layout 3 (0: the plan has none). */
+ephbte_status ephbte_plan_info(ephbte_plan plan, int64_t out[12]);
 
 int64_t ephbte_plan_bytes(ephbte_plan plan);
 void ephbte_destroy(ephbte_plan plan);

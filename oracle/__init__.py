@@ -16,6 +16,9 @@ Contents, each following the paper (arXiv 2511.03683):
 * collision(sys, f, nph)        -- Eq. 2 over a channel list (Results,
   "Collision integral ..."; the channel-list loop is the Baseline-CPU loop
   shape of "Reference CPU algorithm", run sequentially).
+* collision_threads(sys, f, nph) -- the same C loop over disjoint slices of
+  the list on several host threads, partial vectors added in slice order
+  (the multi-core Baseline-CPU shape without atomics).
 * collision_brute(sys, f, nph)  -- Eq. 2 written out over the full q grid,
   all bands and modes, for tiny grids (numpy; independent of the C code).
 * collision_vjp(...)            -- hand-derived reverse mode of Eq. 2.
@@ -32,6 +35,10 @@ Contents, each following the paper (arXiv 2511.03683):
   when rates are given.
 * rk4_coupled_step, even_in_q   -- electrons and phonons stepped together,
   the phonons of q and -q as a pair (even part of the rate).
+* collision_vjp_nph, phonon_rate_vjp, rk4_coupled_adjoint_step,
+  rk4_coupled_trajectory_grad   -- reverse mode with respect to the phonon
+  occupations, of the phonon-side rate, and of the coupled RK4 step (the
+  exact discrete adjoint of the computed steps), derived by hand.
 * transport_*                   -- linearised steady-state BTE (Eq. 1 with the
   collision integral linearised at f0), iterated to self-consistency.
 
@@ -166,6 +173,58 @@ def collision(sys, f, nph, g2=None, mask=None, args=None):
     m = None if mask is None else _c(mask, np.uint8)
     _lib().orc_collision(*a.common(), _ptr(f), _ptr(m), _ptr(I))
     return I
+
+
+def _threaded(fname, a, f, n_out, threads, pass_mask):
+    """Runs the C function fname over `threads` disjoint contiguous slices of
+    the channel list at once (each ctypes call releases the GIL) and adds the
+    slices' n_out partial [S] vectors in slice order."""
+    from concurrent.futures import ThreadPoolExecutor
+    n = int(a.ci.size)
+    if threads is None:
+        threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    threads = max(1, min(int(threads), max(n, 1)))
+    cuts = [n * t // threads for t in range(threads + 1)]
+    parts = [[np.zeros(a.S) for _ in range(n_out)] for _ in range(threads)]
+    base = a.common()
+    fn = getattr(_lib(), fname)
+
+    def run(t):
+        b, e = cuts[t], cuts[t + 1]
+        args_t = list(base)
+        args_t[10] = e - b
+        args_t[11] = ctypes.c_void_p(a.ci.ctypes.data + 4 * b)
+        args_t[12] = ctypes.c_void_p(a.cj.ctypes.data + 4 * b)
+        args_t[13] = ctypes.c_void_p(a.cn.ctypes.data + b)
+        args_t[14] = ctypes.c_void_p(a.g2.ctypes.data + 8 * b)
+        extra = [None] if pass_mask else []
+        fn(*args_t, _ptr(f), *extra, *[_ptr(x) for x in parts[t]])
+
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(run, range(threads)))
+    out = [np.zeros(a.S) for _ in range(n_out)]
+    for pt in parts:
+        for k in range(n_out):
+            out[k] += pt[k]
+    return out
+
+
+def collision_threads(sys, f, nph, threads=None, g2=None, args=None):
+    """I[f] [S] by the same sequential C channel loop as collision(), run on
+    `threads` disjoint contiguous slices of the channel list at once; the
+    slices' partial vectors are added in slice order.  The result equals
+    collision() up to the order of the floating-point additions.
+    threads=None uses every CPU of the process."""
+    a = args or _Args(sys, nph, g2)
+    return _threaded("orc_collision", a, _c(f, np.float64), 1, threads, True)[0]
+
+
+def collision_inout_threads(sys, f, nph, threads=None, g2=None, args=None):
+    """(in-scattering, out-scattering) [S] as collision_inout(), on threads
+    like collision_threads()."""
+    a = args or _Args(sys, nph, g2)
+    rin, rout = _threaded("orc_collision_inout", a, _c(f, np.float64), 2, threads, False)
+    return rin, rout
 
 
 def collision_inout(sys, f, nph, g2=None):
@@ -311,6 +370,154 @@ def phonon_rate(sys, f, nph, g2=None):
     np.add.at(out, qp * nm + nu, y1)
     np.add.at(out, qm * nm + nu, y2)
     return out.reshape(hw.shape)
+
+
+def _channel_geometry(sys):
+    """(ci, cj, nu, q_ij, q_ji) of the channel list: q_ij = k_j - k_i and
+    q_ji = k_i - k_j as linear q-grid indices (numpy, independent of the C
+    code)."""
+    kg = np.asarray(sys.kgrid, np.int64)
+    qg = np.asarray(sys.qgrid, np.int64)
+    k = np.asarray(sys.state_k, np.int64)
+    kc = np.stack([k // (kg[1] * kg[2]), (k // kg[2]) % kg[1], k % kg[2]], axis=1)
+    ci = np.asarray(sys.ch_i, np.int64)
+    cj = np.asarray(sys.ch_j, np.int64)
+    ratio = kg // qg
+
+    def qlin(dk):
+        q = (dk % kg) // ratio
+        return (q[:, 0] * qg[1] + q[:, 1]) * qg[2] + q[:, 2]
+
+    return ci, cj, np.asarray(sys.ch_nu, np.int64), qlin(kc[cj] - kc[ci]), qlin(kc[ci] - kc[cj])
+
+
+def collision_vjp_nph(sys, f, nph, lam, g2=None):
+    """dL/dN [Nq, n_modes] for L = sum_d lam_d I_d.  In Eq. 2 the occupation
+    factors are affine in N: dF_abs/dN = dF_em/dN = f_d - f_p, so the summand
+    of destination d and partner p through (nu, q = k_p - k_d) has
+    dT/dN(nu, q) = -(2 pi / hbar)(1/N_q) |g|^2 [G(e_d - e_p + hw) + G(e_d - e_p - hw)] (f_d - f_p).
+    Each channel contributes from both of its orientations, each at its own q."""
+    ci, cj, nu, qij, qji = _channel_geometry(sys)
+    hw = np.asarray(sys.hw, np.float64)
+    eps = np.asarray(sys.eps, np.float64)
+    f = np.asarray(f, np.float64)
+    lam = np.asarray(lam, np.float64)
+    g = np.asarray(sys.g2 if g2 is None else g2, np.float64)
+    sig = float(sys.sigma)
+    G = lambda x: np.exp(-0.5 * (x / sig) ** 2) / (sig * np.sqrt(2.0 * np.pi))
+    P = 2.0 * np.pi / HBAR_EV_FS / float(sys.n_q_norm)
+    nm = int(sys.n_modes)
+    out = np.zeros(hw.size)
+    for d, p, q in ((ci, cj, qij), (cj, ci, qji)):
+        w = hw[q, nu]
+        de = eps[d] - eps[p]
+        dT = -P * g * (G(de + w) + G(de - w)) * (f[d] - f[p])
+        np.add.at(out, q * nm + nu, lam[d] * dT)
+    return out.reshape(hw.shape)
+
+
+def phonon_rate_vjp(sys, f, nph, mu, g2=None):
+    """(dL/df [S], dL/dN [Nq, n_modes], dL/dg2 [n_channels]) for
+    L = sum_{q, nu} mu(q, nu) dN/dt(q, nu), from the two terms per channel of
+    phonon_rate (q = k_j - k_i):
+      y1 = Cp |g|^2 G(e_i - e_j + hw(q)) [(N(q)+1) f_j (1-f_i) - N(q) f_i (1-f_j)]    -> bin q
+      y2 = Cp |g|^2 G(e_i - e_j - hw(-q)) [(N(-q)+1) f_i (1-f_j) - N(-q) f_j (1-f_i)] -> bin -q
+    differentiated by hand:
+      dy1/df_i = -Cp |g|^2 Ga (N(q) + f_j),      dy1/df_j = Cp |g|^2 Ga (N(q) + 1 - f_i),
+      dy2/df_i =  Cp |g|^2 Ge (N(-q) + 1 - f_j), dy2/df_j = -Cp |g|^2 Ge (N(-q) + f_i),
+      dy1/dN(q) = Cp |g|^2 Ga (f_j - f_i),       dy2/dN(-q) = Cp |g|^2 Ge (f_i - f_j),
+      dy/d|g|^2 = y / |g|^2."""
+    ci, cj, nu, qp, qm = _channel_geometry(sys)
+    hw = np.asarray(sys.hw, np.float64)
+    N = np.asarray(nph, np.float64)
+    eps = np.asarray(sys.eps, np.float64)
+    f = np.asarray(f, np.float64)
+    mu = np.asarray(mu, np.float64)
+    g = np.asarray(sys.g2 if g2 is None else g2, np.float64)
+    sig = float(sys.sigma)
+    G = lambda x: np.exp(-0.5 * (x / sig) ** 2) / (sig * np.sqrt(2.0 * np.pi))
+    Cp = 2.0 * np.pi / (HBAR_EV_FS * float(np.prod(np.asarray(sys.kgrid, np.int64))))
+    d = eps[ci] - eps[cj]
+    n1, n2 = N[qp, nu], N[qm, nu]
+    m1, m2 = mu[qp, nu], mu[qm, nu]
+    Ga = G(d + hw[qp, nu])
+    Ge = G(d - hw[qm, nu])
+    fi, fj = f[ci], f[cj]
+    gf = np.zeros(f.size)
+    np.add.at(gf, ci, Cp * g * (-m1 * Ga * (n1 + fj) + m2 * Ge * (n2 + 1.0 - fj)))
+    np.add.at(gf, cj, Cp * g * (m1 * Ga * (n1 + 1.0 - fi) - m2 * Ge * (n2 + fi)))
+    gN = np.zeros(hw.size)
+    nm = int(sys.n_modes)
+    np.add.at(gN, qp * nm + nu, m1 * Cp * g * Ga * (fj - fi))
+    np.add.at(gN, qm * nm + nu, m2 * Cp * g * Ge * (fi - fj))
+    gg = Cp * (m1 * Ga * ((n1 + 1.0) * fj * (1.0 - fi) - n1 * fi * (1.0 - fj))
+               + m2 * Ge * ((n2 + 1.0) * fi * (1.0 - fj) - n2 * fj * (1.0 - fi)))
+    return gf, gN.reshape(hw.shape), gg
+
+
+def rk4_coupled_adjoint_step(sys, stages, dt, gbar_f, gbar_N, g2=None):
+    """Reverse of one rk4_coupled_step.  stages = ((u1, M1), .., (u4, M4)), the
+    stage inputs of the step; (gbar_f, gbar_N) = dL/d(f, N) after the step.
+    The right-hand side is F(u, M) = (I(u, M), E R(u, M)) with E the even part
+    in q (a symmetric averaging, E^T = E), so its transposed Jacobian maps
+    (a, b) to (J_If^T a + J_Rf^T E b, J_IN^T a + J_RN^T E b), and the |g|^2
+    gradient to J_Ig^T a + J_Rg^T E b.  Returns (dL/df, dL/dN, dL/dg2 of the step)."""
+
+    def vjp(u, M, a, b):
+        gf_I, gg_I = collision_vjp(sys, u, M, a, g2=g2)
+        gN_I = collision_vjp_nph(sys, u, M, a, g2=g2)
+        gf_R, gN_R, gg_R = phonon_rate_vjp(sys, u, M, even_in_q(sys, b), g2=g2)
+        return gf_I + gf_R, gN_I + gN_R, gg_I + gg_R
+
+    gbar_f = np.asarray(gbar_f, np.float64)
+    gbar_N = np.asarray(gbar_N, np.float64)
+    (u1, M1), (u2, M2), (u3, M3), (u4, M4) = stages
+    a4, b4 = (dt / 6.0) * gbar_f, (dt / 6.0) * gbar_N
+    uf4, uN4, gg4 = vjp(u4, M4, a4, b4)
+    a3, b3 = (dt / 3.0) * gbar_f + dt * uf4, (dt / 3.0) * gbar_N + dt * uN4
+    uf3, uN3, gg3 = vjp(u3, M3, a3, b3)
+    a2, b2 = (dt / 3.0) * gbar_f + 0.5 * dt * uf3, (dt / 3.0) * gbar_N + 0.5 * dt * uN3
+    uf2, uN2, gg2_ = vjp(u2, M2, a2, b2)
+    a1, b1 = (dt / 6.0) * gbar_f + 0.5 * dt * uf2, (dt / 6.0) * gbar_N + 0.5 * dt * uN2
+    uf1, uN1, gg1 = vjp(u1, M1, a1, b1)
+    return (gbar_f + uf1 + uf2 + uf3 + uf4, gbar_N + uN1 + uN2 + uN3 + uN4,
+            gg1 + gg2_ + gg3 + gg4)
+
+
+def rk4_coupled_trajectory_grad(sys, f0, N0, dt, n_steps, gfT, gNT, g2=None):
+    """Gradients of L(f_T, N_T) through n_steps coupled RK4 steps, storing
+    every stage: returns (f_T, N_T, dL/df0, dL/dN0, dL/dg2)."""
+    f = np.array(f0, dtype=np.float64)
+    N = np.array(N0, dtype=np.float64)
+    steps = []
+    for _ in range(n_steps):
+        f, N, st = _rk4_coupled_with_stages(sys, f, N, dt, g2)
+        steps.append(st)
+    gf = np.array(gfT, dtype=np.float64)
+    gN = np.array(gNT, dtype=np.float64)
+    gg = np.zeros(sys.n_channels)
+    for st in reversed(steps):
+        gf, gN, dg = rk4_coupled_adjoint_step(sys, st, dt, gf, gN, g2=g2)
+        gg += dg
+    return f, N, gf, gN, gg
+
+
+def _rk4_coupled_with_stages(sys, f, nph, dt, g2):
+    """rk4_coupled_step that also returns its stage inputs."""
+
+    def rhs(u, M):
+        return collision(sys, u, M, g2=g2), even_in_q(sys, phonon_rate(sys, u, M, g2=g2))
+    u1, M1 = np.array(f, dtype=np.float64), np.array(nph, dtype=np.float64)
+    k1, p1 = rhs(u1, M1)
+    u2, M2 = u1 + 0.5 * dt * k1, M1 + 0.5 * dt * p1
+    k2, p2 = rhs(u2, M2)
+    u3, M3 = u1 + 0.5 * dt * k2, M1 + 0.5 * dt * p2
+    k3, p3 = rhs(u3, M3)
+    u4, M4 = u1 + dt * k3, M1 + dt * p3
+    k4, p4 = rhs(u4, M4)
+    return (u1 + (dt / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4),
+            M1 + (dt / 6.0) * (p1 + 2.0 * p2 + 2.0 * p3 + p4),
+            ((u1, M1), (u2, M2), (u3, M3), (u4, M4)))
 
 
 # ---------------------------------------------------------------------------

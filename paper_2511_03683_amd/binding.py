@@ -48,7 +48,7 @@ class Tuning(ctypes.Structure):
     _fields_ = [("chunk_entries", ctypes.c_int32), ("block_threads", ctypes.c_int32),
                 ("xcd_map", ctypes.c_int32), ("batch_partners", ctypes.c_int32),
                 ("tile_entries", ctypes.c_int32), ("layout", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("fp64_exp", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
 
 
 _LIB = None
@@ -78,6 +78,10 @@ SYMBOLS = {
     "ephbte_set_field": ([_P, _P], ctypes.c_int32),
     "ephbte_phonon_rate": ([_P, _P, _P, _P, _P], ctypes.c_int32),
     "ephbte_rt_step_coupled": ([_P, _P, _P, ctypes.c_double, ctypes.c_int32, _P], ctypes.c_int32),
+    "ephbte_phonon_rate_vjp": ([_P, _P, _P, _P, _P, _P, _P, ctypes.c_int32, _P], ctypes.c_int32),
+    "ephbte_collision_vjp_nph": ([_P, _P, _P, _P, _P, _P], ctypes.c_int32),
+    "ephbte_rt_adjoint_coupled": ([_P, _P, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, _P, _P, _P,
+                                   _P, _P, ctypes.c_int32, _P], ctypes.c_int32),
     "ephbte_plan_bytes": ([_P], ctypes.c_int64),
     "ephbte_destroy": ([_P], None),
     "ephbte_status_string": ([ctypes.c_int32], ctypes.c_char_p),
@@ -406,12 +410,14 @@ def update_g2(plan: Plan, g2):
 
 
 def set_tuning(plan: Plan, chunk_entries=0, block_threads=0, xcd_map=0, batch_partners=0,
-               tile_entries=0, layout=0):
+               tile_entries=0, layout=0, fp64_exp=0):
     """Knobs left at 0 keep the plan's value; tile_entries=-1 restores its default;
-    layout 1 = duplicated rows, 2 = single copy (B = 1 forward pass)."""
+    layout 1 = duplicated rows, 2 = single copy over entries, 3 = single copy
+    over pair records (B = 1 forward pass); fp64_exp 1 = table, 2 = polynomial."""
     t = Tuning()
     t.chunk_entries, t.block_threads, t.xcd_map = int(chunk_entries), int(block_threads), int(xcd_map)
     t.batch_partners, t.tile_entries, t.layout = int(batch_partners), int(tile_entries), int(layout)
+    t.fp64_exp = int(fp64_exp)
     _check(load_library().ephbte_set_tuning(plan.handle, ctypes.byref(t)), "set_tuning")
 
 
@@ -458,6 +464,84 @@ def rt_step_coupled(plan: Plan, f, nph, dt_fs: float, n_steps: int):
     return f, nph
 
 
+def _bins(plan: Plan, t, name):
+    _dev_tensor(plan, t, name)
+    if t.numel() != plan.n_q * plan.n_modes or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous [Nq, n_modes] tensor")
+
+
+def _vec1(plan: Plan, t, name):
+    B, _ = _batch(plan, t, name)
+    if t.dim() != 1 or not t.is_contiguous():
+        raise ValueError(f"{name} must be one contiguous vector [S]")
+
+
+def collision_vjp_nph(plan: Plan, f, nph, gI, out=None):
+    """dL/dN [Nq, n_modes] of L = gI . I[f, N] (see ephbte_collision_vjp_nph)."""
+    import torch
+    _vec1(plan, f, "f")
+    _vec1(plan, gI, "gI")
+    _bins(plan, nph, "nph")
+    if out is None:
+        out = torch.empty((plan.n_q, plan.n_modes), dtype=plan.torch_dtype, device=f.device)
+    _bins(plan, out, "out")
+    _check(load_library().ephbte_collision_vjp_nph(plan.handle, f.data_ptr(), nph.data_ptr(), gI.data_ptr(),
+                                                   out.data_ptr(), _stream(f.device)), "collision_vjp_nph")
+    return out
+
+
+def phonon_rate_vjp(plan: Plan, f, nph, gR, want_f=True, want_nph=True, gg2=None, accumulate=False):
+    """(dL/df, dL/dN, dL/d|g|^2) of L = gR . dN/dt (see ephbte_phonon_rate_vjp);
+    gg2=True allocates the FP64 [n_channels] gradient."""
+    import torch
+    _vec1(plan, f, "f")
+    _bins(plan, nph, "nph")
+    _bins(plan, gR, "gR")
+    gf = torch.empty_like(f) if want_f else None
+    gN = torch.empty_like(nph) if want_nph else None
+    if gg2 is True:
+        gg2 = torch.zeros(plan.n_channels, dtype=torch.float64, device=f.device)
+    if gg2 is not None:
+        _dev_tensor(plan, gg2, "gg2", dtype=torch.float64)
+        if gg2.numel() != plan.n_channels or not gg2.is_contiguous():
+            raise ValueError("gg2 must be a contiguous FP64 [n_channels] tensor")
+    _check(load_library().ephbte_phonon_rate_vjp(
+        plan.handle, f.data_ptr(), nph.data_ptr(), gR.data_ptr(),
+        gf.data_ptr() if gf is not None else None, gN.data_ptr() if gN is not None else None,
+        gg2.data_ptr() if gg2 is not None else None, 1 if accumulate else 0, _stream(f.device)),
+        "phonon_rate_vjp")
+    return gf, gN, gg2
+
+
+def rt_adjoint_coupled(plan: Plan, f0, nph0, dt_fs: float, n_steps: int, checkpoint_every: int,
+                       gfT=None, gNT=None, want_f=True, want_nph=True, gg2=None, accumulate=False):
+    """(dL/df0, dL/dnph0, dL/d|g|^2) through n_steps coupled RK4 steps for a loss
+    with gradients gfT [S] and gNT [Nq, n_modes] at the end (see
+    ephbte_rt_adjoint_coupled)."""
+    import torch
+    _vec1(plan, f0, "f0")
+    _bins(plan, nph0, "nph0")
+    if gfT is not None:
+        _vec1(plan, gfT, "gfT")
+    if gNT is not None:
+        _bins(plan, gNT, "gNT")
+    gf = torch.empty_like(f0) if want_f else None
+    gN = torch.empty_like(nph0) if want_nph else None
+    if gg2 is True:
+        gg2 = torch.zeros(plan.n_channels, dtype=torch.float64, device=f0.device)
+    if gg2 is not None:
+        _dev_tensor(plan, gg2, "gg2", dtype=torch.float64)
+        if gg2.numel() != plan.n_channels or not gg2.is_contiguous():
+            raise ValueError("gg2 must be a contiguous FP64 [n_channels] tensor")
+    _check(load_library().ephbte_rt_adjoint_coupled(
+        plan.handle, f0.data_ptr(), nph0.data_ptr(), float(dt_fs), int(n_steps), int(checkpoint_every),
+        gfT.data_ptr() if gfT is not None else None, gNT.data_ptr() if gNT is not None else None,
+        gf.data_ptr() if gf is not None else None, gN.data_ptr() if gN is not None else None,
+        gg2.data_ptr() if gg2 is not None else None, 1 if accumulate else 0, _stream(f0.device)),
+        "rt_adjoint_coupled")
+    return gf, gN, gg2
+
+
 def set_field(plan: Plan, rates) -> None:
     """Field term of rt_step / rt_adjoint: rates[a] = F_a / (hbar dk_a) in 1/fs
     (see ephbte_set_field); (0, 0, 0) switches it off."""
@@ -479,10 +563,10 @@ def kernel_timing(plan: Plan, start: bool):
 
 
 def plan_info(plan: Plan) -> dict:
-    out = np.zeros(10, np.int64)
+    out = np.zeros(12, np.int64)
     _check(load_library().ephbte_plan_info(plan.handle, out.ctypes.data), "plan_info")
     keys = ["n_states", "n_channels", "entries", "chunks", "dtype", "device", "bytes",
-            "chunk_entries", "block_threads", "channels_kept"]
+            "chunk_entries", "block_threads", "channels_kept", "layout", "pair_records"]
     return {k: int(v) for k, v in zip(keys, out)}
 
 

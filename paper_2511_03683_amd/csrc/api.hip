@@ -77,13 +77,18 @@ struct ephbte_plan_s {
     bool nbr_ok = false;
     double drift_rate[3] = {0.0, 0.0, 0.0};
     bool drift_on = false;
-    // phonon side: elastic-mode mask, full k-grid count, largest entry count
-    // of a (q, mode) bin (host, at build), device bound and bins
+    // phonon side: elastic-mode mask, full k-grid count, and the channels
+    // grouped by phonon pair {q, -q} (pair records, buckets, chunks)
     uint32_t elastic = 0;
     double nk = 1.0;
-    double ph_count = 0.0;
-    unsigned long long *ph_gmax_bits = nullptr, *ph_bound_bits = nullptr, *ph_bins = nullptr;
-    bool ph_dirty = true;   // the bound needs max |g|^2 again (after build, update_g2)
+    uint32_t *ph_pa = nullptr, *ph_pb = nullptr;
+    void *ph_g2 = nullptr;            // [n_modes][ph_ld]
+    int32_t *ph_chan = nullptr;       // [n_modes][ph_ld] caller channel of each slot, -1: none
+    int64_t ph_np = 0, ph_ld = 0, ph_nchunks = 0, ph_nbuckets = 0;
+    int64_t *ph_chunk_beg = nullptr;
+    int32_t *ph_chunk_bucket = nullptr, *ph_bucket_chunk = nullptr, *ph_bucket_q = nullptr,
+            *ph_bucket_qm = nullptr, *ph_q_bucket = nullptr;
+    uint32_t *ph_bucket_modes = nullptr;
     int nq[3] = {0, 0, 0};
     double sigma = 0, nqnorm = 0;
     std::vector<int64_t> row_ptr;   // host copy for re-chunking
@@ -117,7 +122,23 @@ struct ephbte_plan_s {
     double *pack_bmax = nullptr;            // per-block max |N| of the last pack
     int sym_lds_states = 0;
     bool sym_ok = false;                    // the single-copy window fits the LDS of a workgroup
-    int layout = 2;                         // B = 1 forward: 1 duplicated rows, 2 single copy
+    int layout = 2;                         // B = 1 forward: 1 duplicated rows, 2 single copy,
+                                            // 3 single copy over pair records
+    // pair records of the single-copy pass (built when most of their mode
+    // slots hold a channel): partners, |g|^2 slots [n_modes][pr_ld], the
+    // caller channel of each slot, and their chunks and tiles
+    uint32_t *pr_partner = nullptr;
+    void *pr_g2 = nullptr;
+    int32_t *pr_chan = nullptr;
+    int64_t pr_np = 0, pr_ld = 0;
+    std::vector<int64_t> pr_rowptr;        // host: pair rows, for re-chunking
+    int64_t *pr_chunk_beg = nullptr, *pr_chunk_end = nullptr;
+    int32_t *pr_chunk_dest = nullptr, *pr_dest_chunk = nullptr;
+    TileRec *pr_tiles = nullptr;
+    int64_t n_pr_chunks = 0, n_pr_tiles = 0;
+    bool pr_ok = false;
+    bool exp_table = true;                 // FP64 Gaussians of the pair pass from the LDS table
+    unsigned long long *lmax_bits = nullptr;  // max |lam| of the pair reverse pass (double bits)
     // batched pass: tiles of destinations and per-destination sub-tile offsets
     BTileRec *btiles = nullptr;
     int64_t *sub_off = nullptr;
@@ -145,6 +166,11 @@ struct ephbte_plan_s {
     DevBuf tr_W, tr_tau_inv, tr_tau, tr_rhs, tr_xa, tr_xb, tr_part, tr_red, tr_red2;
     DevBuf adj_ck, adj_U, adj_la, adj_lb, adj_acc, adj_g, adj_f;
     DevBuf cp_Ma, cp_Mb, cp_acc, cp_rate;   // coupled step: phonon stages, sum, rate
+    DevBuf ph_part;                          // phonon pass: chunk partials
+    DevBuf ph_tab4;                          // {hw, N, mu} table of the phonon-side reverse pass
+    // reverse of the coupled step: checkpoints and stage inputs of (f, N),
+    // adjoint vectors of both
+    DevBuf ca_ckf, ca_ckN, ca_U, ca_M, ca_gf, ca_gN, ca_a, ca_b, ca_uf, ca_uN, ca_sf, ca_sN, ca_mu;
     double *host_red = nullptr;   // pinned
     hipStream_t own_stream = nullptr;
     hipEvent_t ev_a = nullptr, ev_b = nullptr;
@@ -167,7 +193,8 @@ struct ephbte_plan_s {
         const DevBuf *w[] = {&part,  &sym_part, &rk_ua, &rk_ub, &rk_acc, &hwN, &tr_W,  &tr_tau_inv, &tr_tau,
                              &tr_rhs, &tr_xa, &tr_xb, &tr_part, &tr_red, &tr_red2, &adj_ck,
                              &adj_U, &adj_la, &adj_lb, &adj_acc, &adj_g, &adj_f, &cp_Ma, &cp_Mb,
-                             &cp_acc, &cp_rate};
+                             &cp_acc, &cp_rate, &ph_part, &ph_tab4, &ca_ckf, &ca_ckN, &ca_U, &ca_M,
+                             &ca_gf, &ca_gN, &ca_a, &ca_b, &ca_uf, &ca_uN, &ca_sf, &ca_sN, &ca_mu};
         for (auto *x : w) b += x->bytes;
         return b;
     }
@@ -237,13 +264,21 @@ void free_plan(ephbte_plan P) {
                      (void **)&P->sym_dest_chunk, (void **)&P->sym_tiles, (void **)&P->jacc,
                      (void **)&P->nmax_bits, (void **)&P->gmax_bits, (void **)&P->pack_bmax,
                      (void **)&P->drop_idx, (void **)&P->vbtiles, (void **)&P->vsub_off,
-                     (void **)&P->nbr, (void **)&P->ph_gmax_bits, (void **)&P->ph_bound_bits,
-                     (void **)&P->ph_bins, (void **)&P->small_tiles};
+                     (void **)&P->nbr, (void **)&P->small_tiles, (void **)&P->ph_pa,
+                     (void **)&P->ph_pb, (void **)&P->ph_g2, (void **)&P->ph_chan,
+                     (void **)&P->ph_chunk_beg, (void **)&P->ph_chunk_bucket, (void **)&P->ph_bucket_chunk,
+                     (void **)&P->ph_bucket_q, (void **)&P->ph_bucket_qm, (void **)&P->ph_q_bucket,
+                     (void **)&P->ph_bucket_modes, (void **)&P->pr_partner, (void **)&P->pr_g2,
+                     (void **)&P->pr_chan, (void **)&P->pr_chunk_beg, (void **)&P->pr_chunk_end,
+                     (void **)&P->pr_chunk_dest, (void **)&P->pr_dest_chunk, (void **)&P->pr_tiles,
+                     (void **)&P->lmax_bits};
     for (auto pp : ptrs) dfree(*pp);
     DevBuf *w[] = {&P->part,   &P->sym_part, &P->rk_ua,  &P->rk_ub,   &P->rk_acc, &P->hwN, &P->tr_W,   &P->tr_tau_inv,
                    &P->tr_tau, &P->tr_rhs, &P->tr_xa,   &P->tr_xb,  &P->tr_part, &P->tr_red,
                    &P->tr_red2, &P->adj_ck, &P->adj_U,  &P->adj_la, &P->adj_lb, &P->adj_acc,
-                   &P->adj_g,  &P->adj_f, &P->cp_Ma, &P->cp_Mb, &P->cp_acc, &P->cp_rate};
+                   &P->adj_g,  &P->adj_f, &P->cp_Ma, &P->cp_Mb, &P->cp_acc, &P->cp_rate, &P->ph_part,
+                   &P->ph_tab4, &P->ca_ckf, &P->ca_ckN, &P->ca_U, &P->ca_M, &P->ca_gf, &P->ca_gN, &P->ca_a,
+                   &P->ca_b, &P->ca_uf, &P->ca_uN, &P->ca_sf, &P->ca_sN, &P->ca_mu};
     for (auto *b : w) dfree(b->p);
     if (P->host_red) (void)hipHostFree(P->host_red);
     if (P->ev_a) (void)hipEventDestroy(P->ev_a);
@@ -259,6 +294,10 @@ int64_t grid_x(ephbte_plan P) { return P->xcd_map ? 8 * ((P->n_chunks + 7) / 8) 
 // workgroups for n tiles (tile_of_block pads to a multiple of the 8 XCDs)
 unsigned tile_grid(ephbte_plan P, int64_t n) {
     return static_cast<unsigned>(P->xcd_map ? 8 * ((n + 7) / 8) : n);
+}
+
+unsigned grid_of(int64_t n) {
+    return static_cast<unsigned>(std::max<int64_t>(std::min<int64_t>((n + 255) / 256, 4096), 1));
 }
 
 void upload_chunks(ephbte_plan P, int64_t chunk_entries) {
@@ -336,6 +375,38 @@ void upload_chunks(ephbte_plan P, int64_t chunk_entries) {
         HIPC(hipMemcpy(P->sym_tiles, tu.data(), tu.size() * sizeof(TileRec), hipMemcpyHostToDevice));
     P->n_sym_chunks = u.n_chunks;
     P->n_sym_tiles = static_cast<int64_t>(tu.size());
+    if (!P->pr_ok) return;
+    // pair records: the same split, counted in pairs (a pair carries all modes)
+    std::vector<int64_t> pbeg(P->pr_rowptr.begin(), P->pr_rowptr.end() - 1);
+    std::vector<int64_t> pend(P->pr_rowptr.begin() + 1, P->pr_rowptr.end());
+    ChunkTable pc = make_chunks_seg(pbeg, pend, chunk_entries);
+    const int64_t target_p = P->tile_entries > 0 ? P->tile_entries / (2 * static_cast<int64_t>(P->nm)) + 1
+                                                 : P->pr_np / (4 * static_cast<int64_t>(P->n_cu)) + 1;
+    std::vector<Tile> tp = make_tiles(pc, P->row_ptr, P->pmin_up, P->pmax_up, P->sym_lds_states, target_p);
+    dfree(reinterpret_cast<void *&>(P->pr_chunk_beg));
+    dfree(reinterpret_cast<void *&>(P->pr_chunk_end));
+    dfree(reinterpret_cast<void *&>(P->pr_chunk_dest));
+    dfree(reinterpret_cast<void *&>(P->pr_dest_chunk));
+    dfree(reinterpret_cast<void *&>(P->pr_tiles));
+    dalloc(P->pr_chunk_beg, pc.chunk_beg.size() * sizeof(int64_t), &dummy);
+    dalloc(P->pr_chunk_end, std::max<size_t>(pc.chunk_end.size(), 1) * sizeof(int64_t), &dummy);
+    dalloc(P->pr_chunk_dest, std::max<size_t>(pc.chunk_dest.size(), 1) * sizeof(int32_t), &dummy);
+    dalloc(P->pr_dest_chunk, pc.dest_chunk.size() * sizeof(int32_t), &dummy);
+    dalloc(P->pr_tiles, std::max<size_t>(tp.size(), 1) * sizeof(TileRec), &dummy);
+    HIPC(hipMemcpy(P->pr_chunk_beg, pc.chunk_beg.data(), pc.chunk_beg.size() * sizeof(int64_t),
+                   hipMemcpyHostToDevice));
+    if (!pc.chunk_end.empty()) {
+        HIPC(hipMemcpy(P->pr_chunk_end, pc.chunk_end.data(), pc.chunk_end.size() * sizeof(int64_t),
+                       hipMemcpyHostToDevice));
+        HIPC(hipMemcpy(P->pr_chunk_dest, pc.chunk_dest.data(), pc.chunk_dest.size() * sizeof(int32_t),
+                       hipMemcpyHostToDevice));
+    }
+    HIPC(hipMemcpy(P->pr_dest_chunk, pc.dest_chunk.data(), pc.dest_chunk.size() * sizeof(int32_t),
+                   hipMemcpyHostToDevice));
+    if (!tp.empty())
+        HIPC(hipMemcpy(P->pr_tiles, tp.data(), tp.size() * sizeof(TileRec), hipMemcpyHostToDevice));
+    P->n_pr_chunks = pc.n_chunks;
+    P->n_pr_tiles = static_cast<int64_t>(tp.size());
 }
 
 template <typename T> Tables<T> tables(ephbte_plan P, const void *nph) {
@@ -411,12 +482,34 @@ template <typename T> TiledArgs<T> sym_args(ephbte_plan P) {
     return a;
 }
 
+// arguments of the single-copy pass over pair records
+template <typename T> TiledArgs<T> pair_args(ephbte_plan P) {
+    TiledArgs<T> a = sym_args<T>(P);
+    a.pnu = P->pr_partner;
+    a.g2 = static_cast<const T *>(P->pr_g2);
+    a.pld = P->pr_ld;
+    a.chunk_beg = P->pr_chunk_beg;
+    a.chunk_end = P->pr_chunk_end;
+    a.chunk_dest = P->pr_chunk_dest;
+    a.dest_chunk = P->pr_dest_chunk;
+    a.tiles = P->pr_tiles;
+    a.n_chunks = P->n_pr_chunks;
+    a.n_tiles = P->n_pr_tiles;
+    return a;
+}
+
 // LDS of the single-copy pass: fixed-point sums, {eps, f}, packed k per window
 // state, and the FP64 exponential table
 size_t sym_lds_bytes(int dtype, int states) {
     const size_t es = dtype == EPHBTE_F64 ? 8 : 4;
     const size_t tab = dtype == EPHBTE_F64 ? kExpTab * sizeof(double) : 0;
     return static_cast<size_t>(states) * (8 + 2 * es + 4) + tab;
+}
+
+// LDS of the pair reverse pass: the forward's plus lam per window state
+size_t vjp_pair_lds_bytes(int dtype, int states) {
+    const size_t es = dtype == EPHBTE_F64 ? 8 : 4;
+    return sym_lds_bytes(dtype, states) + static_cast<size_t>(states) * es;
 }
 
 // max over states of the sum of |g|^2 of the state's channels (device scalar)
@@ -435,6 +528,29 @@ void update_gmax(ephbte_plan P, hipStream_t s) {
 
 bool use_sym(ephbte_plan P, int B) {
     return B == 1 && P->layout == 2 && P->sym_ok && P->n_sym_tiles > 0;
+}
+
+// k_fwd_pairs with its mode-slot count rounded up to 2, 4, 6 or 8
+template <typename T>
+void launch_pairs(ephbte_plan P, const TiledArgs<T> &a, const T *f, T *part, size_t shm, hipStream_t s,
+                  bool padq) {
+    const dim3 grid(static_cast<unsigned>(P->n_pr_tiles)), block(1024);
+    auto go = [&](auto nmc) {
+        constexpr int NM = decltype(nmc)::value;
+        const bool tab = sizeof(T) == 8 && P->exp_table;
+        if (padq && tab) hipLaunchKernelGGL((k_fwd_pairs<T, true, NM, true>), grid, block, shm, s, a, f, part);
+        else if (padq) hipLaunchKernelGGL((k_fwd_pairs<T, true, NM, false>), grid, block, shm, s, a, f, part);
+        else if (tab) hipLaunchKernelGGL((k_fwd_pairs<T, false, NM, true>), grid, block, shm, s, a, f, part);
+        else hipLaunchKernelGGL((k_fwd_pairs<T, false, NM, false>), grid, block, shm, s, a, f, part);
+    };
+    if (P->nm <= 2) go(std::integral_constant<int, 2>{});
+    else if (P->nm <= 4) go(std::integral_constant<int, 4>{});
+    else if (P->nm <= 6) go(std::integral_constant<int, 6>{});
+    else go(std::integral_constant<int, 8>{});
+}
+
+bool use_pairs(ephbte_plan P, int B) {
+    return B == 1 && P->layout == 3 && P->sym_ok && P->pr_ok && P->n_pr_tiles > 0;
 }
 
 int64_t nqm_of(ephbte_plan P) {
@@ -634,6 +750,18 @@ void enqueue_forward(ephbte_plan P, int B, const T *f, int64_t ldf, const void *
         enqueue_forward_batched<T>(P, B, f, ldf, E, s);
         return;
     }
+    if (use_pairs(P, B)) {
+        TiledArgs<T> a = pair_args<T>(P);
+        T *part = static_cast<T *>(P->sym_part.p);
+        const size_t shm = sym_lds_bytes(P->dtype, P->sym_lds_states);
+        const int64_t kt = ktime_begin(P, s);
+        launch_pairs<T>(P, a, f, part, shm, s, P->padq);
+        ktime_end(P, s, kt);
+        hipLaunchKernelGGL((k_sym_finish<T>), dim3((P->S + 255) / 256), dim3(256), 0, s, a, f,
+                           (const T *)part, E);
+        HIPC(hipGetLastError());
+        return;
+    }
     if (use_sym(P, B)) {
         TiledArgs<T> a = sym_args<T>(P);
         T *part = static_cast<T *>(P->sym_part.p);
@@ -677,6 +805,9 @@ template <typename T> void ensure_fwd(ephbte_plan P, int B) {
     if (use_sym(P, B))
         ensure(P->sym_part, sizeof(T) * 2 * static_cast<size_t>(std::max<int64_t>(P->n_sym_chunks, 1)),
                &P->ws_gen);
+    if (use_pairs(P, B))
+        ensure(P->sym_part, sizeof(T) * 2 * static_cast<size_t>(std::max<int64_t>(P->n_pr_chunks, 1)),
+               &P->ws_gen);
     const int64_t tab = P->padq ? P->qpad_n * P->nm : nqm_of(P);
     ensure(P->hwN, sizeof(Pair2<T>) * static_cast<size_t>(std::max<int64_t>(tab, 1)), &P->ws_gen);
 }
@@ -691,6 +822,44 @@ template <typename T>
 void enqueue_vjp(ephbte_plan P, const T *f, const T *lam, const void *nph, const Epi<T> &E,
                  double *gg2, int gg2_mode, hipStream_t s) {
     (void)nph;
+    if (use_pairs(P, 1) && vjp_pair_lds_bytes(P->dtype, P->sym_lds_states) <= P->lds_max) {
+        // max |lam| of this call (the partner side's fixed-point scale)
+        hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, P->lmax_bits, 1);
+        hipLaunchKernelGGL((k_abs_max_bits<T>), dim3(grid_of(P->S)), dim3(256), 0, s, lam, int64_t(P->S),
+                           P->lmax_bits);
+        TiledArgs<T> a = pair_args<T>(P);
+        T *part = static_cast<T *>(P->sym_part.p);
+        const int want_f = E.mode >= 0 ? 1 : 0;
+        const dim3 grid(static_cast<unsigned>(P->n_pr_tiles)), block(1024);
+        const size_t shm = vjp_pair_lds_bytes(P->dtype, P->sym_lds_states);
+        auto go = [&](auto nmc) {
+            constexpr int NM = decltype(nmc)::value;
+            const bool tab = sizeof(T) == 8 && P->exp_table;
+            const unsigned long long *lm = P->lmax_bits;
+            const int32_t *ch = P->pr_chan;
+            if (P->padq && tab)
+                hipLaunchKernelGGL((k_vjp_pairs<T, true, NM, true>), grid, block, shm, s, a, f, lam, part, want_f, lm,
+                                   ch, gg2, gg2_mode);
+            else if (P->padq)
+                hipLaunchKernelGGL((k_vjp_pairs<T, true, NM, false>), grid, block, shm, s, a, f, lam, part, want_f,
+                                   lm, ch, gg2, gg2_mode);
+            else if (tab)
+                hipLaunchKernelGGL((k_vjp_pairs<T, false, NM, true>), grid, block, shm, s, a, f, lam, part, want_f,
+                                   lm, ch, gg2, gg2_mode);
+            else
+                hipLaunchKernelGGL((k_vjp_pairs<T, false, NM, false>), grid, block, shm, s, a, f, lam, part, want_f,
+                                   lm, ch, gg2, gg2_mode);
+        };
+        if (P->nm <= 2) go(std::integral_constant<int, 2>{});
+        else if (P->nm <= 4) go(std::integral_constant<int, 4>{});
+        else if (P->nm <= 6) go(std::integral_constant<int, 6>{});
+        else go(std::integral_constant<int, 8>{});
+        if (want_f)
+            hipLaunchKernelGGL((k_vjp_pairs_finish<T>), dim3((P->S + 255) / 256), dim3(256), 0, s, a,
+                               (const T *)part, (const unsigned long long *)P->lmax_bits, E);
+        HIPC(hipGetLastError());
+        return;
+    }
     TiledArgs<T> a = tiled_args<T>(P);
     a.xcd = 0;   // measured: plain tile order is faster for the reverse pass
     a.tiles = P->small_tiles;
@@ -905,6 +1074,100 @@ template <typename T> void upload_layout(ephbte_plan P, const ephbte_problem *pr
         for (int64_t x = 0; x < nqm; ++x) h[x] = static_cast<T>(pr->hw[x]);
         HIPC(hipMemcpy(P->hw, h.data(), sizeof(T) * nqm, hipMemcpyHostToDevice));
     }
+}
+
+// Pair records of the single-copy pass (see build_pair_rows), kept when at
+// least half of their mode slots hold a channel (otherwise the per-entry
+// single-copy pass streams fewer bytes).  The arrays are padded like the
+// entry arrays, so that the kernel's stream loads need no bound.
+template <typename T> void upload_pair_rows(ephbte_plan P, const ephbte_problem *pr, const HostLayout &L) {
+    PairRows R = build_pair_rows(L);
+    const int64_t np = R.n_pairs, nm = P->nm;
+    P->pr_ok = np > 0 && 2 * R.n_filled >= np * nm;
+    if (!P->pr_ok) return;
+    size_t &acc = P->layout_bytes;
+    P->pr_np = np;
+    P->pr_ld = np + kEntryPad;
+    const size_t ld = static_cast<size_t>(P->pr_ld);
+    dalloc(P->pr_partner, sizeof(uint32_t) * ld, &acc);
+    dalloc(reinterpret_cast<T *&>(P->pr_g2), sizeof(T) * ld * nm, &acc);
+    dalloc(P->pr_chan, sizeof(int32_t) * ld * nm, &acc);
+    std::vector<uint32_t> part(ld, 0u);
+    std::copy(R.partner.begin(), R.partner.end(), part.begin());
+    HIPC(hipMemcpy(P->pr_partner, part.data(), sizeof(uint32_t) * ld, hipMemcpyHostToDevice));
+    {
+        std::vector<uint32_t>().swap(part);
+        std::vector<T> g(ld * nm, T(0));
+        std::vector<int32_t> ch(ld * nm, -1);
+        parallel_ranges(np, host_threads(), [&](int, int64_t b, int64_t e) {
+            for (int64_t m = 0; m < nm; ++m)
+                for (int64_t j = b; j < e; ++j) {
+                    const int32_t c = R.slot_chan[static_cast<size_t>(m * np + j)];
+                    ch[static_cast<size_t>(m) * ld + j] = c;
+                    g[static_cast<size_t>(m) * ld + j] = c >= 0 ? static_cast<T>(pr->g2[c]) : T(0);
+                }
+        });
+        HIPC(hipMemcpy(P->pr_g2, g.data(), sizeof(T) * g.size(), hipMemcpyHostToDevice));
+        HIPC(hipMemcpy(P->pr_chan, ch.data(), sizeof(int32_t) * ch.size(), hipMemcpyHostToDevice));
+    }
+    P->pr_rowptr = std::move(R.row_ptr);
+}
+
+// The phonon pass's layout (pair records bucketed by {q, -q}, see
+// build_phonon_layout) and its chunks of at most kPhChunk records.
+template <typename T> void upload_phonon_layout(ephbte_plan P, const ephbte_problem *pr, const HostLayout &L) {
+    size_t &acc = P->layout_bytes;
+    PhononLayout ph = build_phonon_layout(L);
+    const int64_t np = ph.n_pairs, nm = P->nm;
+    const int64_t nb = static_cast<int64_t>(ph.bucket_q.size());
+    P->ph_np = np;
+    P->ph_ld = std::max<int64_t>(np, 1);
+    P->ph_nbuckets = nb;
+    std::vector<int64_t> cbeg;
+    std::vector<int32_t> cbucket, bchunk(static_cast<size_t>(nb) + 1, 0);
+    for (int64_t b = 0; b < nb; ++b) {
+        bchunk[b] = static_cast<int32_t>(cbucket.size());
+        for (int64_t x = ph.bucket_beg[b]; x < ph.bucket_beg[b + 1]; x += kPhChunk) {
+            cbeg.push_back(x);
+            cbucket.push_back(static_cast<int32_t>(b));
+        }
+    }
+    bchunk[nb] = static_cast<int32_t>(cbucket.size());
+    cbeg.push_back(np);
+    P->ph_nchunks = static_cast<int64_t>(cbucket.size());
+    const size_t ld = static_cast<size_t>(P->ph_ld);
+    dalloc(P->ph_pa, sizeof(uint32_t) * ld, &acc);
+    dalloc(P->ph_pb, sizeof(uint32_t) * ld, &acc);
+    dalloc(reinterpret_cast<T *&>(P->ph_g2), sizeof(T) * ld * nm, &acc);
+    dalloc(P->ph_chan, sizeof(int32_t) * ld * nm, &acc);
+    dalloc(P->ph_chunk_beg, sizeof(int64_t) * cbeg.size(), &acc);
+    dalloc(P->ph_chunk_bucket, sizeof(int32_t) * std::max<size_t>(cbucket.size(), 1), &acc);
+    dalloc(P->ph_bucket_chunk, sizeof(int32_t) * bchunk.size(), &acc);
+    dalloc(P->ph_bucket_q, sizeof(int32_t) * std::max<int64_t>(nb, 1), &acc);
+    dalloc(P->ph_bucket_qm, sizeof(int32_t) * std::max<int64_t>(nb, 1), &acc);
+    dalloc(P->ph_bucket_modes, sizeof(uint32_t) * std::max<int64_t>(nb, 1), &acc);
+    dalloc(P->ph_q_bucket, sizeof(int32_t) * ph.q_bucket.size(), &acc);
+    if (np > 0) {
+        HIPC(hipMemcpy(P->ph_pa, ph.pa.data(), sizeof(uint32_t) * np, hipMemcpyHostToDevice));
+        HIPC(hipMemcpy(P->ph_pb, ph.pb.data(), sizeof(uint32_t) * np, hipMemcpyHostToDevice));
+        std::vector<T> g(static_cast<size_t>(np) * nm);
+        parallel_ranges(np * nm, host_threads(), [&](int, int64_t b, int64_t e) {
+            for (int64_t x = b; x < e; ++x) {
+                const int32_t c = ph.slot_chan[x];
+                g[x] = c >= 0 ? static_cast<T>(pr->g2[c]) : T(0);
+            }
+        });
+        HIPC(hipMemcpy(P->ph_g2, g.data(), sizeof(T) * g.size(), hipMemcpyHostToDevice));
+        HIPC(hipMemcpy(P->ph_chan, ph.slot_chan.data(), sizeof(int32_t) * ph.slot_chan.size(),
+                       hipMemcpyHostToDevice));
+        HIPC(hipMemcpy(P->ph_chunk_bucket, cbucket.data(), sizeof(int32_t) * cbucket.size(), hipMemcpyHostToDevice));
+        HIPC(hipMemcpy(P->ph_bucket_q, ph.bucket_q.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice));
+        HIPC(hipMemcpy(P->ph_bucket_qm, ph.bucket_qm.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice));
+        HIPC(hipMemcpy(P->ph_bucket_modes, ph.bucket_modes.data(), sizeof(uint32_t) * nb, hipMemcpyHostToDevice));
+    }
+    HIPC(hipMemcpy(P->ph_chunk_beg, cbeg.data(), sizeof(int64_t) * cbeg.size(), hipMemcpyHostToDevice));
+    HIPC(hipMemcpy(P->ph_bucket_chunk, bchunk.data(), sizeof(int32_t) * bchunk.size(), hipMemcpyHostToDevice));
+    HIPC(hipMemcpy(P->ph_q_bucket, ph.q_bucket.data(), sizeof(int32_t) * ph.q_bucket.size(), hipMemcpyHostToDevice));
 }
 
 hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
@@ -1161,40 +1424,98 @@ __global__ void k_rk_even(int mode, const T *__restrict__ N0, const T *__restric
 
 // Phonon-side rate of the stage input u into rate (the {hw, N} table and its
 // max |N| already packed from the stage's N).
-template <typename T> void enqueue_phonon_rate(ephbte_plan P, const T *u, T *rate, hipStream_t s) {
-    const int64_t nbin = static_cast<int64_t>(P->nq[0]) * P->nq[1] * P->nq[2] * P->nm;
-    if (P->ph_dirty) {
-        hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, P->ph_gmax_bits, 1);
-        const unsigned nb = static_cast<unsigned>(std::max<int64_t>(std::min<int64_t>((P->E + 255) / 256, 4096), 1));
-        hipLaunchKernelGGL((k_abs_max_bits<T>), dim3(nb), dim3(256), 0, s, static_cast<const T *>(P->g2), P->E,
-                           P->ph_gmax_bits);
-        hipLaunchKernelGGL(k_phonon_bound, dim3(1), dim3(64), 0, s, (const unsigned long long *)P->ph_gmax_bits,
-                           P->ph_count, P->ph_bound_bits);
-        P->ph_dirty = false;
-    }
-    TiledArgs<T> a = tiled_args<T>(P);
-    if (P->n_chunks > 0)
-        hipLaunchKernelGGL((k_phonon_rate<T>), dim3(static_cast<unsigned>(P->n_chunks)), dim3(256), 0, s, a, u,
-                           P->elastic, (const unsigned long long *)P->ph_bound_bits, P->ph_bins);
-    const double Kp = 2.0 * kPi / (kHbar * P->nk) / (P->sigma * std::sqrt(2.0 * kPi));
+template <typename T> PhArgs<T> ph_args(ephbte_plan P) {
+    PhArgs<T> a;
+    a.pa = P->ph_pa;
+    a.pb = P->ph_pb;
+    a.g2 = static_cast<const T *>(P->ph_g2);
+    a.ld = P->ph_ld;
+    a.st = static_cast<const StateRec<T> *>(P->st);
+    a.hw = static_cast<const T *>(P->hw);
+    a.chunk_beg = P->ph_chunk_beg;
+    a.chunk_bucket = P->ph_chunk_bucket;
+    a.bucket_chunk = P->ph_bucket_chunk;
+    a.bucket_q = P->ph_bucket_q;
+    a.bucket_qm = P->ph_bucket_qm;
+    a.bucket_modes = P->ph_bucket_modes;
+    a.q_bucket = P->ph_q_bucket;
+    a.n_chunks = P->ph_nchunks;
+    a.nq = static_cast<int64_t>(P->nq[0]) * P->nq[1] * P->nq[2];
+    a.nm = P->nm;
+    a.mc = static_cast<T>(-1.4426950408889634 / (2.0 * P->sigma * P->sigma));
+    a.mc256 = 256.0 * (-1.4426950408889634 / (2.0 * P->sigma * P->sigma));
+    a.e2tab = P->e2tab;
+    a.Kp = 2.0 * kPi / (kHbar * P->nk) / (P->sigma * std::sqrt(2.0 * kPi));
+    a.elastic = P->elastic;
+    a.chan = P->ph_chan;
+    return a;
+}
+
+// dN/dt of every (q, mode) bin into rate (the caller ensured P->ph_part)
+template <typename T> void enqueue_phonon_rate(ephbte_plan P, const T *u, const T *nph, T *rate, hipStream_t s) {
+    const PhArgs<T> a = ph_args<T>(P);
+    T *part = static_cast<T *>(P->ph_part.p);
+    if (P->ph_nchunks > 0)
+        hipLaunchKernelGGL((k_phonon_bins<T>), dim3(static_cast<unsigned>((P->ph_nchunks + 3) / 4)), dim3(256), 0,
+                           s, a, u, nph, part);
+    const int64_t nbin = a.nq * P->nm;
     const unsigned nf = static_cast<unsigned>(std::max<int64_t>(std::min<int64_t>((nbin + 255) / 256, 4096), 1));
-    hipLaunchKernelGGL((k_phonon_finish<T>), dim3(nf), dim3(256), 0, s, P->ph_bins, nbin,
-                       (const unsigned long long *)P->nmax_bits, (const unsigned long long *)P->ph_bound_bits,
-                       Kp, rate);
+    hipLaunchKernelGGL((k_phonon_bins_finish<T>), dim3(nf), dim3(256), 0, s, a, (const T *)part, rate);
     HIPC(hipGetLastError());
 }
 
-// the phonon-side device state (bins, bound words), allocated on first use
 void ensure_phonon(ephbte_plan P) {
-    if (P->ph_bins) return;
-    const int64_t nbin = static_cast<int64_t>(P->nq[0]) * P->nq[1] * P->nq[2] * P->nm;
-    size_t dummy = 0;
-    dalloc(P->ph_bins, sizeof(unsigned long long) * std::max<int64_t>(nbin, 1), &dummy);
-    dalloc(P->ph_gmax_bits, sizeof(unsigned long long), &dummy);
-    dalloc(P->ph_bound_bits, sizeof(unsigned long long), &dummy);
-    HIPC(hipMemset(P->ph_bins, 0, sizeof(unsigned long long) * std::max<int64_t>(nbin, 1)));
-    // the caller's stream may not wait for the null stream: finish the clear here
-    HIPC(hipDeviceSynchronize());
+    ensure(P->ph_part, esize(P) * 2 * static_cast<size_t>(P->nm) * std::max<int64_t>(P->ph_nchunks, 1),
+           &P->ws_gen);
+}
+
+// the electron-side constant of Eq. 2 with the Gaussian's normalisation
+double k_electron(ephbte_plan P) {
+    return 2.0 * kPi / (kHbar * P->nqnorm) / (P->sigma * std::sqrt(2.0 * kPi));
+}
+
+// dL/dN [Nq][n_modes] (overwritten) of L = lam . I + mu . dN/dt at (u, N),
+// and the phonon-side part of dL/d|g|^2 added to gg2 (if gg2 and mu are set).
+// lam or mu may be null.  The caller ensured P->ph_part.
+template <typename T>
+void enqueue_phonon_adj(ephbte_plan P, const T *u, const T *N, const T *lam, const T *mu, T *gN, double *gg2,
+                        hipStream_t s) {
+    PhArgs<T> a = ph_args<T>(P);
+    T *part = static_cast<T *>(P->ph_part.p);
+    if (P->ph_nchunks > 0)
+        hipLaunchKernelGGL((k_phonon_bins_adj<T>), dim3(static_cast<unsigned>((P->ph_nchunks + 3) / 4)), dim3(256),
+                           0, s, a, u, N, lam, mu, part, gg2, k_electron(P));
+    a.Kp = 1.0;   // the partials already carry their constants
+    hipLaunchKernelGGL((k_phonon_bins_finish<T>), dim3(grid_of(a.nq * P->nm)), dim3(256), 0, s, a,
+                       (const T *)part, gN);
+    HIPC(hipGetLastError());
+}
+
+// out += dL/df of L = mu . dN/dt at (u, N) (the caller ensured P->ph_tab4 and
+// P->part for n_chunks values)
+template <typename T>
+void enqueue_phonon_vjp_f(ephbte_plan P, const T *u, const T *N, const T *mu, T *out, hipStream_t s) {
+    const int64_t n = P->padq ? P->qpad_n * P->nm : nqm_of(P);
+    Vec4<T> *tab = static_cast<Vec4<T> *>(P->ph_tab4.p);
+    hipLaunchKernelGGL((k_pack_hwNmu<T>), dim3(grid_of(n)), dim3(256), 0, s, static_cast<const T *>(P->hw), N, mu,
+                       tab, P->padq ? 1 : 0, P->nq[0], P->nq[1], P->nq[2], P->nm, n);
+    TiledArgs<T> a = tiled_args<T>(P);
+    T *part = static_cast<T *>(P->part.p);
+    const double Kp = 2.0 * kPi / (kHbar * P->nk) / (P->sigma * std::sqrt(2.0 * kPi));
+    if (P->n_chunks > 0)
+        hipLaunchKernelGGL((k_vjp_phonon_f<T>), dim3(static_cast<unsigned>(P->n_chunks)), dim3(256), 0, s, a,
+                           (const Vec4<T> *)tab, u, P->elastic, Kp, out, part);
+    if (!P->fused)
+        hipLaunchKernelGGL((k_vjp_phonon_f_finish<T>), dim3((P->S + 255) / 256), dim3(256), 0, s, a,
+                           (const T *)part, out);
+    HIPC(hipGetLastError());
+}
+
+template <typename T> void ensure_phonon_vjp(ephbte_plan P) {
+    const int64_t n = P->padq ? P->qpad_n * P->nm : nqm_of(P);
+    ensure(P->ph_tab4, sizeof(Vec4<T>) * static_cast<size_t>(std::max<int64_t>(n, 1)), &P->ws_gen);
+    ensure_part<T>(P, 1, 2);
+    ensure_phonon(P);
 }
 
 template <typename T>
@@ -1235,12 +1556,151 @@ ephbte_status rt_coupled_impl(ephbte_plan P, T *f, T *N, double dt, int n_steps,
             e.u_out = uout[st];
             e.f_out = f;
             enqueue_forward<T>(P, 1, uin[st], S, min_[st], e, s, false);
-            enqueue_phonon_rate<T>(P, uin[st], rate, s);
+            enqueue_phonon_rate<T>(P, uin[st], min_[st], rate, s);
             hipLaunchKernelGGL((k_rk_even<T>), dim3(ng), dim3(256), 0, s, EPI_RK1 + st, (const T *)N,
                                (const T *)rate, nacc, mout[st], tdt, P->nq[0], P->nq[1], P->nq[2], P->nm);
             HIPC(hipGetLastError());
         }
     }
+    return EPHBTE_OK;
+}
+
+// One coupled RK4 step whose four stage inputs (u, M) are kept: stage k reads
+// U[k], M[k] (k = 0 .. 3) and writes the next stage input to U[k + 1], M[k + 1];
+// the last stage writes f_next, N_next.  Same arithmetic as rt_coupled_impl.
+template <typename T>
+void coupled_step_stages(ephbte_plan P, T *const U[4], T *const M[4], T *f_next, T *N_next, T dt, hipStream_t s) {
+    const int64_t S = P->S;
+    T *acc = static_cast<T *>(P->rk_acc.p);
+    T *nacc = static_cast<T *>(P->cp_acc.p), *rate = static_cast<T *>(P->cp_rate.p);
+    const int64_t nbin = nqm_of(P);
+    for (int st = 0; st < 4; ++st) {
+        enqueue_pack<T>(P, M[st], s);
+        Epi<T> e{};
+        e.f0 = U[0];
+        e.ld_f0 = S;
+        e.acc = acc;
+        e.dt = dt;
+        e.mode = EPI_RK1 + st;
+        e.u_out = st < 3 ? U[st + 1] : nullptr;
+        e.f_out = f_next;
+        enqueue_forward<T>(P, 1, U[st], S, M[st], e, s, false);
+        enqueue_phonon_rate<T>(P, U[st], M[st], rate, s);
+        hipLaunchKernelGGL((k_rk_even<T>), dim3(grid_of(nbin)), dim3(256), 0, s, EPI_RK1 + st, (const T *)M[0],
+                           (const T *)rate, nacc, st < 3 ? M[st + 1] : N_next, dt, P->nq[0], P->nq[1], P->nq[2],
+                           P->nm);
+        HIPC(hipGetLastError());
+    }
+}
+
+// Discrete adjoint of n coupled RK4 steps from (f0, N0), checkpointed every
+// ce steps (stage inputs recomputed inside a segment).  Per stage (u, M) with
+// adjoint pair (a, b), the transposed Jacobian of (I, E R) gives
+//   u-bar = J_If^T a + J_Rf^T E b,  M-bar = J_IN^T a + J_RN^T E b,
+//   |g|^2-bar += J_Ig^T a + J_Rg^T E b,
+// and the four stages combine as in rt_adjoint_impl.
+template <typename T>
+ephbte_status rt_adjoint_coupled_impl(ephbte_plan P, const T *f0, const T *N0, double dt, int n, int ce,
+                                      const T *gfT, const T *gNT, T *gf0, T *gN0, double *gg2, int accumulate,
+                                      hipStream_t s) {
+    const int64_t S = P->S, nb = nqm_of(P);
+    const size_t v = sizeof(T) * S, vn = sizeof(T) * nb;
+    const int nck = std::max(1, (n + ce - 1) / ce);
+    ensure(P->rk_acc, v, &P->ws_gen);
+    ensure(P->cp_acc, vn, &P->ws_gen);
+    ensure(P->cp_rate, vn, &P->ws_gen);
+    ensure(P->ca_ckf, v * nck, &P->ws_gen);
+    ensure(P->ca_ckN, vn * nck, &P->ws_gen);
+    ensure(P->ca_U, v * (4 * static_cast<size_t>(ce) + 1), &P->ws_gen);
+    ensure(P->ca_M, vn * (4 * static_cast<size_t>(ce) + 1), &P->ws_gen);
+    for (DevBuf *b : {&P->ca_gf, &P->ca_a, &P->ca_uf, &P->ca_sf}) ensure(*b, v, &P->ws_gen);
+    for (DevBuf *b : {&P->ca_gN, &P->ca_b, &P->ca_uN, &P->ca_sN, &P->ca_mu}) ensure(*b, vn, &P->ws_gen);
+    ensure_fwd<T>(P, 1);
+    ensure_phonon_vjp<T>(P);
+    T *ckf = static_cast<T *>(P->ca_ckf.p), *ckN = static_cast<T *>(P->ca_ckN.p);
+    T *U = static_cast<T *>(P->ca_U.p), *M = static_cast<T *>(P->ca_M.p);
+    T *gf = static_cast<T *>(P->ca_gf.p), *gN = static_cast<T *>(P->ca_gN.p);
+    T *a = static_cast<T *>(P->ca_a.p), *b = static_cast<T *>(P->ca_b.p);
+    T *uf = static_cast<T *>(P->ca_uf.p), *uN = static_cast<T *>(P->ca_uN.p);
+    T *sf = static_cast<T *>(P->ca_sf.p), *sN = static_cast<T *>(P->ca_sN.p);
+    T *mu = static_cast<T *>(P->ca_mu.p);
+    const T tdt = static_cast<T>(dt);
+    auto copy = [&](T *dst, const T *src, int64_t cnt) {
+        hipLaunchKernelGGL((k_axpby<T>), dim3(grid_of(cnt)), dim3(256), 0, s, cnt, T(1), src, T(0),
+                           (const T *)nullptr, dst);
+    };
+    auto stage_ptrs = [&](int64_t l, T *Ul[4], T *Ml[4]) {
+        for (int k = 0; k < 4; ++k) {
+            Ul[k] = U + (l * 4 + k) * S;
+            Ml[k] = M + (l * 4 + k) * nb;
+        }
+    };
+    // forward sweep: checkpoints of (f, N) every ce steps
+    copy(U, f0, S);
+    copy(M, N0, nb);
+    for (int k = 0; k < n; ++k) {
+        if (k % ce == 0) {
+            copy(ckf + static_cast<int64_t>(k / ce) * S, U, S);
+            copy(ckN + static_cast<int64_t>(k / ce) * nb, M, nb);
+        }
+        T *Ul[4], *Ml[4];
+        stage_ptrs(0, Ul, Ml);
+        coupled_step_stages<T>(P, Ul, Ml, U, M, tdt, s);
+    }
+    if (gfT) copy(gf, gfT, S);
+    else hipLaunchKernelGGL((k_axpby<T>), dim3(grid_of(S)), dim3(256), 0, s, S, T(0), (const T *)U, T(0),
+                            (const T *)nullptr, gf);
+    if (gNT) copy(gN, gNT, nb);
+    else hipLaunchKernelGGL((k_axpby<T>), dim3(grid_of(nb)), dim3(256), 0, s, nb, T(0), (const T *)M, T(0),
+                            (const T *)nullptr, gN);
+    const int gmode = gg2 ? 2 : 0;
+    if (gg2 && !accumulate) hipLaunchKernelGGL(k_fill_f64, dim3(1024), dim3(256), 0, s, gg2, P->nch, 0.0);
+    HIPC(hipGetLastError());
+    // (cg, cv) of the stages 4, 3, 2, 1: a_k = cg gbar + cv u-bar_{k+1}
+    const T cg[4] = {tdt / T(6), tdt / T(3), tdt / T(3), tdt / T(6)};
+    const T cv[4] = {T(0), tdt, tdt / T(2), tdt / T(2)};
+    for (int m = nck - 1; m >= 0; --m) {
+        const int s0 = m * ce, s1 = std::min(n, s0 + ce);
+        copy(U, ckf + static_cast<int64_t>(m) * S, S);
+        copy(M, ckN + static_cast<int64_t>(m) * nb, nb);
+        for (int k = s0; k < s1; ++k) {
+            T *Ul[4], *Ml[4];
+            stage_ptrs(k - s0, Ul, Ml);
+            coupled_step_stages<T>(P, Ul, Ml, U + (static_cast<int64_t>(k - s0) + 1) * 4 * S,
+                                   M + (static_cast<int64_t>(k - s0) + 1) * 4 * nb, tdt, s);
+        }
+        for (int k = s1 - 1; k >= s0; --k) {
+            T *Ul[4], *Ml[4];
+            stage_ptrs(k - s0, Ul, Ml);
+            copy(sf, gf, S);
+            copy(sN, gN, nb);
+            for (int r = 0; r < 4; ++r) {
+                const int st = 3 - r;
+                hipLaunchKernelGGL((k_axpby<T>), dim3(grid_of(S)), dim3(256), 0, s, S, cg[r], (const T *)gf, cv[r],
+                                   r ? (const T *)uf : nullptr, a);
+                hipLaunchKernelGGL((k_axpby<T>), dim3(grid_of(nb)), dim3(256), 0, s, nb, cg[r], (const T *)gN,
+                                   cv[r], r ? (const T *)uN : nullptr, b);
+                // electron side: u-bar = J_If^T a, and J_Ig^T a into gg2
+                enqueue_pack<T>(P, Ml[st], s);
+                enqueue_vjp<T>(P, Ul[st], a, Ml[st], epi_store<T>(uf, S), gg2, gmode, s);
+                // phonon side through the even part: mu = E b
+                hipLaunchKernelGGL((k_even_q<T>), dim3(grid_of(nb)), dim3(256), 0, s, (const T *)b, mu, P->nq[0],
+                                   P->nq[1], P->nq[2], P->nm);
+                enqueue_phonon_vjp_f<T>(P, Ul[st], Ml[st], mu, uf, s);
+                enqueue_phonon_adj<T>(P, Ul[st], Ml[st], a, mu, uN, gg2, s);
+                hipLaunchKernelGGL((k_axpby<T>), dim3(grid_of(S)), dim3(256), 0, s, S, T(1), (const T *)sf, T(1),
+                                   (const T *)uf, sf);
+                hipLaunchKernelGGL((k_axpby<T>), dim3(grid_of(nb)), dim3(256), 0, s, nb, T(1), (const T *)sN, T(1),
+                                   (const T *)uN, sN);
+                HIPC(hipGetLastError());
+            }
+            copy(gf, sf, S);
+            copy(gN, sN, nb);
+        }
+    }
+    if (gf0) copy(gf0, gf, S);
+    if (gN0) copy(gN0, gN, nb);
+    HIPC(hipGetLastError());
     return EPHBTE_OK;
 }
 
@@ -1573,6 +2033,8 @@ ephbte_status ephbte_build_channels(const ephbte_problem *problem, const ephbte_
         }
         P->device = dev;
         DeviceGuard g(dev);
+        // the event that orders consecutive calls on the plan
+        HIPC(hipEventCreateWithFlags(&P->ev_last, hipEventDisableTiming));
         P->dtype = problem->dtype;
         P->S = L.S;
         P->nm = L.n_modes;
@@ -1581,41 +2043,6 @@ ephbte_status ephbte_build_channels(const ephbte_problem *problem, const ephbte_
         P->E = L.E;
         P->elastic = opts ? opts->elastic_modes : 0u;
         P->nk = static_cast<double>(problem->kgrid[0]) * problem->kgrid[1] * problem->kgrid[2];
-        {
-            // largest number of entries of one (q, mode) bin of the phonon side
-            const int64_t nq0 = L.nq[0], nq1 = L.nq[1], nq2 = L.nq[2], nm = L.n_modes;
-            const int64_t nbin = nq0 * nq1 * nq2 * nm;
-            const int T = host_threads();
-            std::vector<std::vector<int32_t>> cnt(T);
-            parallel_ranges(L.S, T, [&](int t, int64_t b, int64_t e) {
-                auto &h = cnt[t];
-                h.assign(static_cast<size_t>(nbin), 0);
-                for (int64_t d = b; d < e; ++d) {
-                    const uint32_t kd = L.kq[d];
-                    for (int64_t x = L.row_ptr[d]; x < L.row_ptr[d + 1]; ++x) {
-                        const uint32_t pn = L.pnu[x];
-                        const int mode = static_cast<int>(pn & 7u);
-                        if ((P->elastic >> mode) & 1u) continue;
-                        const uint32_t kp = L.kq[pn >> 3];
-                        int64_t a0 = int64_t(kp >> 20) - int64_t(kd >> 20);
-                        int64_t a1 = int64_t((kp >> 10) & 1023u) - int64_t((kd >> 10) & 1023u);
-                        int64_t a2 = int64_t(kp & 1023u) - int64_t(kd & 1023u);
-                        a0 += a0 < 0 ? nq0 : 0;
-                        a1 += a1 < 0 ? nq1 : 0;
-                        a2 += a2 < 0 ? nq2 : 0;
-                        ++h[static_cast<size_t>(((a0 * nq1 + a1) * nq2 + a2) * nm + mode)];
-                    }
-                }
-            });
-            int64_t best = 0;
-            for (int64_t i = 0; i < nbin; ++i) {
-                int64_t c = 0;
-                for (auto &h : cnt)
-                    if (!h.empty()) c += h[static_cast<size_t>(i)];
-                best = std::max(best, c);
-            }
-            P->ph_count = static_cast<double>(best);
-        }
         P->nbr_ok = !L.nbr.empty();
         if (P->nbr_ok) {
             dalloc(P->nbr, sizeof(int32_t) * L.nbr.size(), &P->layout_bytes);
@@ -1653,8 +2080,15 @@ ephbte_status ephbte_build_channels(const ephbte_problem *problem, const ephbte_
         if (hipDeviceGetAttribute(&shm, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
             shm > 0)
             P->lds_max = static_cast<size_t>(shm);
-        if (P->dtype == EPHBTE_F64) upload_layout<double>(P, problem, L);
-        else upload_layout<float>(P, problem, L);
+        if (P->dtype == EPHBTE_F64) {
+            upload_layout<double>(P, problem, L);
+            upload_phonon_layout<double>(P, problem, L);
+            upload_pair_rows<double>(P, problem, L);
+        } else {
+            upload_layout<float>(P, problem, L);
+            upload_phonon_layout<float>(P, problem, L);
+            upload_pair_rows<float>(P, problem, L);
+        }
         {
             // 2^(j/256) rounded from extended precision
             double tab[kExpTab];
@@ -1681,11 +2115,13 @@ ephbte_status ephbte_build_channels(const ephbte_problem *problem, const ephbte_
             });
             P->sym_lds_states = P->dtype == EPHBTE_F64 ? 3072 : 4096;
             P->sym_ok = sym_lds_bytes(P->dtype, P->sym_lds_states) <= P->lds_max;
+            if (P->sym_ok && P->pr_ok) P->layout = 3;
             dalloc(P->jacc, sizeof(unsigned long long) * std::max(P->S, 1), &P->layout_bytes);
             HIPC(hipMemset(P->jacc, 0, sizeof(unsigned long long) * std::max(P->S, 1)));
             dalloc(P->nmax_bits, sizeof(unsigned long long), &P->layout_bytes);
             dalloc(P->gmax_bits, sizeof(unsigned long long), &P->layout_bytes);
             dalloc(P->pack_bmax, sizeof(double) * kPackBlocks, &P->layout_bytes);
+            dalloc(P->lmax_bits, sizeof(unsigned long long), &P->layout_bytes);
             HIPC(hipMemset(P->nmax_bits, 0, sizeof(unsigned long long)));
         }
         { HostLayout tmp; std::swap(tmp, L); }
@@ -1872,7 +2308,26 @@ ephbte_status ephbte_update_g2(ephbte_plan plan, const double *g2, void *stream)
                                plan->E);
         HIPC(hipGetLastError());
         update_gmax(plan, s);
-        plan->ph_dirty = true;
+        if (plan->pr_ok) {
+            const int64_t np = plan->pr_ld * plan->nm;
+            if (plan->dtype == EPHBTE_F64)
+                hipLaunchKernelGGL((k_ph_gather_g2<double>), dim3(4096), dim3(256), 0, s,
+                                   (const int32_t *)plan->pr_chan, g2, static_cast<double *>(plan->pr_g2), np);
+            else
+                hipLaunchKernelGGL((k_ph_gather_g2<float>), dim3(4096), dim3(256), 0, s,
+                                   (const int32_t *)plan->pr_chan, g2, static_cast<float *>(plan->pr_g2), np);
+            HIPC(hipGetLastError());
+        }
+        const int64_t ns = plan->ph_ld * plan->nm;
+        if (ns > 0) {
+            if (plan->dtype == EPHBTE_F64)
+                hipLaunchKernelGGL((k_ph_gather_g2<double>), dim3(4096), dim3(256), 0, s,
+                                   (const int32_t *)plan->ph_chan, g2, static_cast<double *>(plan->ph_g2), ns);
+            else
+                hipLaunchKernelGGL((k_ph_gather_g2<float>), dim3(4096), dim3(256), 0, s,
+                                   (const int32_t *)plan->ph_chan, g2, static_cast<float *>(plan->ph_g2), ns);
+            HIPC(hipGetLastError());
+        }
         return EPHBTE_OK;
     });
 }
@@ -1888,9 +2343,8 @@ ephbte_status ephbte_phonon_rate(ephbte_plan plan, const void *f, const void *np
         ensure_phonon(plan);
         auto run = [&](auto tag) {
             using T = decltype(tag);
-            ensure_fwd<T>(plan, 1);
-            enqueue_pack<T>(plan, nph, s);
-            enqueue_phonon_rate<T>(plan, static_cast<const T *>(f), static_cast<T *>(dN), s);
+            enqueue_phonon_rate<T>(plan, static_cast<const T *>(f), static_cast<const T *>(nph),
+                                   static_cast<T *>(dN), s);
         };
         if (plan->dtype == EPHBTE_F64) run(double{});
         else run(float{});
@@ -1916,6 +2370,95 @@ ephbte_status ephbte_rt_step_coupled(ephbte_plan plan, void *f, void *nph, doubl
     });
 }
 
+ephbte_status ephbte_collision_vjp_nph(ephbte_plan plan, const void *f, const void *nph, const void *gI,
+                                       void *gnph, void *stream) {
+    return guarded(plan, stream, [&]() -> ephbte_status {
+        if (!f || !nph || !gI || !gnph)
+            return fail(EPHBTE_INVALID_ARGUMENT, "f, nph, gI and gnph must be non-NULL");
+        const size_t es = esize(plan);
+        const int64_t nbin = nqm_of(plan);
+        if (overlaps(gnph, es * nbin, f, es * plan->S) || overlaps(gnph, es * nbin, gI, es * plan->S) ||
+            overlaps(gnph, es * nbin, nph, es * nbin))
+            return fail(EPHBTE_INVALID_ARGUMENT, "gnph must not overlap f, gI or nph");
+        hipStream_t s = as_stream(stream);
+        ensure_phonon(plan);
+        auto run = [&](auto tag) {
+            using T = decltype(tag);
+            enqueue_phonon_adj<T>(plan, static_cast<const T *>(f), static_cast<const T *>(nph),
+                                  static_cast<const T *>(gI), (const T *)nullptr, static_cast<T *>(gnph), nullptr, s);
+        };
+        if (plan->dtype == EPHBTE_F64) run(double{});
+        else run(float{});
+        return EPHBTE_OK;
+    });
+}
+
+ephbte_status ephbte_phonon_rate_vjp(ephbte_plan plan, const void *f, const void *nph, const void *gR, void *gf,
+                                     void *gnph, double *gg2, int32_t accumulate_gg2, void *stream) {
+    return guarded(plan, stream, [&]() -> ephbte_status {
+        if (!f || !nph || !gR) return fail(EPHBTE_INVALID_ARGUMENT, "f, nph and gR must be non-NULL");
+        const size_t es = esize(plan);
+        const int64_t nbin = nqm_of(plan);
+        if (gf && (overlaps(gf, es * plan->S, f, es * plan->S) || overlaps(gf, es * plan->S, gR, es * nbin)))
+            return fail(EPHBTE_INVALID_ARGUMENT, "gf must not overlap f or gR");
+        if (gnph && (overlaps(gnph, es * nbin, nph, es * nbin) || overlaps(gnph, es * nbin, gR, es * nbin)))
+            return fail(EPHBTE_INVALID_ARGUMENT, "gnph must not overlap nph or gR");
+        hipStream_t s = as_stream(stream);
+        auto run = [&](auto tag) {
+            using T = decltype(tag);
+            const T *ft = static_cast<const T *>(f), *nt = static_cast<const T *>(nph), *mt = static_cast<const T *>(gR);
+            if (gf) {
+                ensure_phonon_vjp<T>(plan);
+                hipLaunchKernelGGL((k_axpby<T>), dim3(grid_of(plan->S)), dim3(256), 0, s, int64_t(plan->S), T(0), ft,
+                                   T(0), (const T *)nullptr, static_cast<T *>(gf));
+                enqueue_phonon_vjp_f<T>(plan, ft, nt, mt, static_cast<T *>(gf), s);
+            }
+            if (gnph || gg2) {
+                ensure_phonon(plan);
+                if (gg2 && !accumulate_gg2)
+                    hipLaunchKernelGGL(k_fill_f64, dim3(1024), dim3(256), 0, s, gg2, plan->nch, 0.0);
+                T *out = static_cast<T *>(gnph);
+                if (!out) {
+                    ensure(plan->ca_mu, es * static_cast<size_t>(std::max<int64_t>(nbin, 1)), &plan->ws_gen);
+                    out = static_cast<T *>(plan->ca_mu.p);
+                }
+                enqueue_phonon_adj<T>(plan, ft, nt, (const T *)nullptr, mt, out, gg2, s);
+            }
+        };
+        if (plan->dtype == EPHBTE_F64) run(double{});
+        else run(float{});
+        return EPHBTE_OK;
+    });
+}
+
+ephbte_status ephbte_rt_adjoint_coupled(ephbte_plan plan, const void *f0, const void *nph0, double dt_fs,
+                                        int32_t n_steps, int32_t checkpoint_every, const void *gfT,
+                                        const void *gNT, void *gf0, void *gN0, double *gg2,
+                                        int32_t accumulate_gg2, void *stream) {
+    return guarded(plan, stream, [&]() -> ephbte_status {
+        if (!f0 || !nph0) return fail(EPHBTE_INVALID_ARGUMENT, "f0 and nph0 must be non-NULL");
+        if (n_steps < 1) return fail(EPHBTE_INVALID_ARGUMENT, "n_steps must be >= 1");
+        if (checkpoint_every < 1) return fail(EPHBTE_INVALID_ARGUMENT, "checkpoint_every must be >= 1");
+        if (!std::isfinite(dt_fs)) return fail(EPHBTE_INVALID_ARGUMENT, "dt_fs must be finite");
+        const size_t es = esize(plan);
+        const int64_t nbin = nqm_of(plan);
+        if (gf0 && overlaps(gf0, es * plan->S, f0, es * plan->S))
+            return fail(EPHBTE_INVALID_ARGUMENT, "gf0 must not overlap f0");
+        if (gN0 && overlaps(gN0, es * nbin, nph0, es * nbin))
+            return fail(EPHBTE_INVALID_ARGUMENT, "gN0 must not overlap nph0");
+        hipStream_t s = as_stream(stream);
+        const int ce = std::min(checkpoint_every, n_steps);
+        auto run = [&](auto tag) {
+            using T = decltype(tag);
+            return rt_adjoint_coupled_impl<T>(plan, static_cast<const T *>(f0), static_cast<const T *>(nph0), dt_fs,
+                                              n_steps, ce, static_cast<const T *>(gfT), static_cast<const T *>(gNT),
+                                              static_cast<T *>(gf0), static_cast<T *>(gN0), gg2, accumulate_gg2, s);
+        };
+        if (plan->dtype == EPHBTE_F64) return run(double{});
+        return run(float{});
+    });
+}
+
 ephbte_status ephbte_set_tuning(ephbte_plan plan, const ephbte_tuning *tuning) {
     return guarded(plan, nullptr, [&]() -> ephbte_status {
         if (!tuning) return fail(EPHBTE_INVALID_ARGUMENT, "tuning is NULL");
@@ -1934,16 +2477,22 @@ ephbte_status ephbte_set_tuning(ephbte_plan plan, const ephbte_tuning *tuning) {
             if (r != 0) return fail(EPHBTE_INVALID_ARGUMENT, "reserved tuning fields must be 0");
         if (tuning->tile_entries < -1)
             return fail(EPHBTE_INVALID_ARGUMENT, "tile_entries must be -1 (default), 0 (keep) or > 0");
-        if (tuning->layout < 0 || tuning->layout > 2)
-            return fail(EPHBTE_INVALID_ARGUMENT, "layout must be 0 (keep), 1 or 2");
-        if (tuning->layout == 2 && !plan->sym_ok)
+        if (tuning->fp64_exp < 0 || tuning->fp64_exp > 2)
+            return fail(EPHBTE_INVALID_ARGUMENT, "fp64_exp must be 0 (keep), 1 or 2");
+        if (tuning->layout < 0 || tuning->layout > 3)
+            return fail(EPHBTE_INVALID_ARGUMENT, "layout must be 0 (keep), 1, 2 or 3");
+        if (tuning->layout >= 2 && !plan->sym_ok)
             return fail(EPHBTE_INVALID_ARGUMENT,
                         "the single-copy pass needs more LDS per workgroup than this device has");
+        if (tuning->layout == 3 && !plan->pr_ok)
+            return fail(EPHBTE_INVALID_ARGUMENT,
+                        "this plan has no pair records (fewer than half of their mode slots would hold a channel)");
         HIPC(hipDeviceSynchronize());
         plan->block_threads = bt;
         if (tuning->xcd_map) plan->xcd_map = tuning->xcd_map == 1;
         if (tuning->tile_entries) plan->tile_entries = tuning->tile_entries > 0 ? tuning->tile_entries : 0;
         if (tuning->layout) plan->layout = tuning->layout;
+        if (tuning->fp64_exp) plan->exp_table = tuning->fp64_exp == 1;
         upload_chunks(plan, ce);
         if (pt != 0) upload_btiles(plan, pt);
         free_graphs(plan);
@@ -2185,7 +2734,7 @@ ephbte_status ephbte_kernel_timing(ephbte_plan plan, int32_t mode, double *mean_
     }
 }
 
-ephbte_status ephbte_plan_info(ephbte_plan plan, int64_t out[10]) {
+ephbte_status ephbte_plan_info(ephbte_plan plan, int64_t out[12]) {
     if (!plan || !out) return fail(EPHBTE_INVALID_ARGUMENT, "plan and out must be non-NULL");
     out[0] = plan->S;
     out[1] = plan->nch;
@@ -2197,6 +2746,8 @@ ephbte_status ephbte_plan_info(ephbte_plan plan, int64_t out[10]) {
     out[7] = plan->chunk_entries;
     out[8] = plan->block_threads;
     out[9] = plan->nch_kept;
+    out[10] = plan->layout;
+    out[11] = plan->pr_ok ? plan->pr_np : 0;
     return EPHBTE_OK;
 }
 

@@ -340,6 +340,8 @@ template <typename T> struct TiledArgs {
     unsigned long long *__restrict__ jacc;           // [S] partner-side sums, fixed point
     const unsigned long long *__restrict__ nmax_bits;  // max |N| of the packed table (double bits)
     const unsigned long long *__restrict__ gmax_bits;  // max over states of sum |g|^2 (double bits)
+    // pair records (k_fwd_pairs): pnu holds partners, g2 is [n_modes][pld]
+    int64_t pld;
 };
 
 // ---- fixed point for the partner side of the single-copy pass -------------
@@ -802,6 +804,328 @@ __global__ __launch_bounds__(1024) void k_fwd_sym(TiledArgs<T> A, const T *__res
         const unsigned long long v = s_j[i];
         if (v) atomicAdd(A.jacc + t.p_lo + i, v);
     }
+}
+
+// ---- forward, single copy over pair records ----------------------------------
+// The same pass over pair records: a lane takes one pair (d, p), p > d, with
+// all its modes.  The partner's {eps, f} and k are gathered once per pair, the
+// {hw, N} of the modes of q = k_p - k_d are adjacent in the table, and the
+// partner side of the pair (summed over its modes in a fixed order) is one
+// fixed-point atomic.  A slot without a channel has |g|^2 = 0; its N is
+// replaced by 0 so that a non-finite table entry of that mode (N at an
+// acoustic q = 0) cannot turn the zero into a NaN.
+// FP64 Gaussian of the pair pass: the table exponential (TAB) or the
+// degree-12 polynomial one (no LDS reads); FP32: the hardware exponential
+template <typename T, bool TAB>
+__device__ __forceinline__ T pair_gauss(const TiledArgs<T> &A, T x2, const double *tab) {
+    if constexpr (sizeof(T) == 8 && TAB) return gauss_exp2_tab(x2 * A.mc256, tab);
+    else if constexpr (sizeof(T) == 8) return gauss_exp2(x2 * A.mc);
+    else return __builtin_amdgcn_exp2f(x2 * A.mc);
+}
+
+template <typename T, bool LDS, bool PADQ, int NM, bool TAB>
+__device__ __forceinline__ void pair_chunk(const TiledArgs<T> &A, const T *__restrict__ fb,
+                                           const Pair2<T> *s_ef, const uint32_t *s_kq, int p_lo,
+                                           const double *s_tab, unsigned long long *s_j, T scale,
+                                           int64_t c, T *__restrict__ part) {
+    const int lane = threadIdx.x & 63;
+    const int nm = A.nm;   // <= NM
+    const int d = A.chunk_dest[c];
+    const int64_t beg = A.chunk_beg[c];
+    const int len = static_cast<int>(A.chunk_end[c] - beg);
+    const uint32_t *__restrict__ pb = A.pnu + beg;
+    const T *__restrict__ gb = A.g2 + beg;
+    const StateRec<T> sd = A.st[d];
+    const uint32_t kd = PADQ ? sd.kqp : sd.kq;
+    const T fd = fb[d];
+    const T cfd = T(1) - fd;
+    T acc_a = T(0), acc_b = T(0);
+    // the partners run one batch ahead; the |g|^2 loads of a batch are issued
+    // before its gathers and overlap them.  The arrays are padded past their
+    // end, so no stream load needs a bound.
+    uint32_t pn = pb[lane];
+    for (int r = 0; r < len; r += 64) {
+        const bool v = r + lane < len;
+        const uint32_t pn_next = pb[r + 64 + lane];
+        T g[NM];
+#pragma unroll
+        for (int m = 0; m < NM; ++m) g[m] = m < nm ? gb[m * A.pld + r + lane] : T(0);
+        const int p = static_cast<int>(pn);
+        T ep, fp;
+        uint32_t kp;
+        int pl;
+        if (LDS) {
+            // a masked lane: partner = destination (the q = 0 table row,
+            // finite operands); it adds nothing
+            pl = v ? p - p_lo : 0;
+            const Pair2<T> ef = s_ef[pl];
+            ep = v ? ef.a : sd.eps;
+            fp = v ? ef.b : T(0);
+            kp = v ? s_kq[pl] : kd;
+        } else {
+            pl = v ? p : d;
+            const StateRec<T> sp = A.st[pl];
+            ep = sp.eps;
+            kp = PADQ ? sp.kqp : sp.kq;
+            fp = fb[pl];
+        }
+        const int q = PADQ ? static_cast<int>(kp - kd) + A.qoff : q_linear(kd, kp, A.nq0, A.nq1, A.nq2);
+        const Pair2<T> *__restrict__ wq = A.hwN + static_cast<int64_t>(q) * nm;
+        Pair2<T> w[NM];
+#pragma unroll
+        for (int m = 0; m < NM; ++m)
+            if (m < nm) w[m] = wq[m];
+        const T de = sd.eps - ep;
+        const T ofp = T(1) - fp;
+        T y = T(0);
+#pragma unroll
+        for (int m = 0; m < NM; ++m) {
+            if (m >= nm) break;
+            const T gm = v ? g[m] : T(0);
+            const T N = gm != T(0) ? w[m].b : T(0);
+            const T xa = de + w[m].a, xe = de - w[m].a;
+            const T da = pair_gauss<T, TAB>(A, xa * xa, s_tab);
+            const T dem = pair_gauss<T, TAB>(A, xe * xe, s_tab);
+            const T t = N * (da + dem);
+            const T ta = gm * (t + dem) * ofp;
+            const T tb = gm * (t + da) * fp;
+            acc_a += ta;
+            acc_b += tb;
+            // partner side: -Y = f_d ta - (1 - f_d) tb
+            y += fma(fd, ta, -cfd * tb);
+        }
+        if (v) {
+            const unsigned long long fx = to_fixed(__builtin_rint(y * scale));
+            if (LDS) atomicAdd(s_j + pl, fx);
+            else atomicAdd(A.jacc + pl, fx);
+        }
+        pn = pn_next;
+    }
+    acc_a = wave_sum(acc_a);
+    acc_b = wave_sum(acc_b);
+    if (lane == 0) {
+        part[2 * c] = acc_a;
+        part[2 * c + 1] = acc_b;
+    }
+}
+
+template <typename T, bool PADQ, int NM, bool TAB>
+__global__ __launch_bounds__(1024) void k_fwd_pairs(TiledArgs<T> A, const T *__restrict__ f,
+                                                    T *__restrict__ part) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int64_t ti = tile_of_block(A.n_tiles, A.xcd);
+    if (ti < 0) return;
+    const TileRec t = A.tiles[ti];
+    unsigned long long *s_j = reinterpret_cast<unsigned long long *>(smem);
+    Pair2<T> *s_ef = reinterpret_cast<Pair2<T> *>(s_j + A.lds_states);
+    uint32_t *s_kq = reinterpret_cast<uint32_t *>(s_ef + A.lds_states);
+    double *s_tab = reinterpret_cast<double *>(s_kq + A.lds_states);
+    const int n = t.lds ? t.p_hi - t.p_lo + 1 : 0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const StateRec<T> sr = A.st[t.p_lo + i];
+        Pair2<T> ef;
+        ef.a = sr.eps;
+        ef.b = f[t.p_lo + i];
+        s_ef[i] = ef;
+        s_kq[i] = PADQ ? sr.kqp : sr.kq;
+        s_j[i] = 0ull;
+    }
+    if constexpr (sizeof(T) == 8 && TAB)
+        for (int i = threadIdx.x; i < kExpTab; i += blockDim.x) s_tab[i] = A.e2tab[i];
+    const T scale = static_cast<T>(sym_scale(A.nmax_bits, A.gmax_bits));
+    __syncthreads();
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    const int nw = static_cast<int>(blockDim.x >> 6);
+    for (int64_t c = t.c0 + wave; c < t.c1; c += nw) {
+        if (t.lds)
+            pair_chunk<T, true, PADQ, NM, TAB>(A, f, s_ef, s_kq, t.p_lo, s_tab, s_j, scale, c, part);
+        else
+            pair_chunk<T, false, PADQ, NM, TAB>(A, f, s_ef, s_kq, t.p_lo, s_tab, s_j, scale, c, part);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const unsigned long long v = s_j[i];
+        if (v) atomicAdd(A.jacc + t.p_lo + i, v);
+    }
+}
+
+// ---- reverse, single copy over pair records ----------------------------------
+// Each channel (d, p, nu), d < p, of a pair record enters L = sum lam I through
+// (lam_d - lam_p) X with X = K |g|^2 [(1 - f_d) bh f_p - f_d ah (1 - f_p)]
+// (ah = t + G(x - hw), bh = t + G(x + hw), t = N (G(x + hw) + G(x - hw)),
+// x = e_d - e_p).  Hence, with dl = lam_d - lam_p:
+//   dL/df_d  += -K dl |g|^2 (ah (1 - f_p) + bh f_p)          (row side, registers)
+//   dL/df_p  +=  K dl |g|^2 (bh (1 - f_d) + ah f_d)          (partner side, fixed point)
+//   dL/d|g|^2 =  K dl ((1 - f_d) bh f_p - f_d ah (1 - f_p))   (one writer per channel)
+// The partner side of a pair is summed over its modes and added with one
+// integer atomic, on the scale of vjp_scale.  Each channel is read once.
+__device__ __forceinline__ double vjp_scale(const unsigned long long *nmax_bits,
+                                            const unsigned long long *gmax_bits,
+                                            const unsigned long long *lmax_bits) {
+    // |dl| <= 2 max |lam|: a state's column is at most 2 max|lam| (2 N_max + 1) G_max
+    const double nmax = __longlong_as_double(static_cast<long long>(*nmax_bits));
+    const double gmax = __longlong_as_double(static_cast<long long>(*gmax_bits));
+    const double lmax = __longlong_as_double(static_cast<long long>(*lmax_bits));
+    const double bound = 2.0 * lmax * (2.0 * nmax + 1.0) * gmax;
+    if (!(bound > 0.0) || !(bound < 1e300)) return 1.0;
+    int e;
+    (void)frexp(bound, &e);
+    return ldexp(1.0, 61 - e);
+}
+
+template <typename T, bool LDS, bool PADQ, int NM, bool TAB>
+__device__ __forceinline__ void vjp_pair_chunk(const TiledArgs<T> &A, const T *__restrict__ fb,
+                                               const T *__restrict__ lb, const Pair2<T> *s_ef,
+                                               const uint32_t *s_kq, const T *s_l, int p_lo,
+                                               const double *s_tab, unsigned long long *s_j, T scale,
+                                               int64_t c, T *__restrict__ part, bool want_f,
+                                               const int32_t *__restrict__ chan, double *__restrict__ gg2,
+                                               int gg2_mode) {
+    const int lane = threadIdx.x & 63;
+    const int nm = A.nm;
+    const int d = A.chunk_dest[c];
+    const int64_t beg = A.chunk_beg[c];
+    const int len = static_cast<int>(A.chunk_end[c] - beg);
+    const uint32_t *__restrict__ pb = A.pnu + beg;
+    const T *__restrict__ gb = A.g2 + beg;
+    const int32_t *__restrict__ cb = chan + beg;
+    const StateRec<T> sd = A.st[d];
+    const uint32_t kd = PADQ ? sd.kqp : sd.kq;
+    const T fd = fb[d];
+    const T cfd = T(1) - fd;
+    const T ld = lb[d];
+    T acc = T(0);
+    uint32_t pn = pb[lane];
+    for (int r = 0; r < len; r += 64) {
+        const bool v = r + lane < len;
+        const uint32_t pn_next = pb[r + 64 + lane];
+        T g[NM];
+#pragma unroll
+        for (int m = 0; m < NM; ++m) g[m] = m < nm ? gb[m * A.pld + r + lane] : T(0);
+        const int p = static_cast<int>(pn);
+        T ep, fp, lp;
+        uint32_t kp;
+        int pl;
+        if (LDS) {
+            pl = v ? p - p_lo : 0;
+            const Pair2<T> ef = s_ef[pl];
+            ep = v ? ef.a : sd.eps;
+            fp = v ? ef.b : T(0);
+            lp = v ? s_l[pl] : ld;
+            kp = v ? s_kq[pl] : kd;
+        } else {
+            pl = v ? p : d;
+            const StateRec<T> sp = A.st[pl];
+            ep = sp.eps;
+            kp = PADQ ? sp.kqp : sp.kq;
+            fp = fb[pl];
+            lp = lb[pl];
+        }
+        const int q = PADQ ? static_cast<int>(kp - kd) + A.qoff : q_linear(kd, kp, A.nq0, A.nq1, A.nq2);
+        const Pair2<T> *__restrict__ wq = A.hwN + static_cast<int64_t>(q) * nm;
+        Pair2<T> w[NM];
+#pragma unroll
+        for (int m = 0; m < NM; ++m)
+            if (m < nm) w[m] = wq[m];
+        const T x = sd.eps - ep;
+        const T ofp = T(1) - fp;
+        const T dl = ld - lp;
+        T y = T(0);
+#pragma unroll
+        for (int m = 0; m < NM; ++m) {
+            if (m >= nm) break;
+            const T gm = v ? g[m] : T(0);
+            const T N = gm != T(0) ? w[m].b : T(0);
+            const T xa = x + w[m].a, xe = x - w[m].a;
+            const T da = pair_gauss<T, TAB>(A, xa * xa, s_tab);
+            const T dem = pair_gauss<T, TAB>(A, xe * xe, s_tab);
+            const T t = N * (da + dem);
+            const T ah = t + dem, bh = t + da;
+            const T dg = dl * gm;
+            acc += dg * (ah * ofp + bh * fp);
+            y += dg * (bh * cfd + ah * fd);
+            if (gg2_mode && v) {
+                const int32_t ch = cb[m * A.pld + r + lane];
+                if (ch >= 0) {
+                    const double val = static_cast<double>(A.K * dl * (cfd * bh * fp - fd * ah * ofp));
+                    gg2[ch] = gg2_mode == 2 ? gg2[ch] + val : val;
+                }
+            }
+        }
+        if (want_f && v) {
+            const unsigned long long fx = to_fixed(__builtin_rint(y * scale));
+            if (LDS) atomicAdd(s_j + pl, fx);
+            else atomicAdd(A.jacc + pl, fx);
+        }
+        pn = pn_next;
+    }
+    if (!want_f) return;
+    acc = wave_sum(acc);
+    if (lane == 0) part[c] = acc;
+}
+
+template <typename T, bool PADQ, int NM, bool TAB>
+__global__ __launch_bounds__(1024) void k_vjp_pairs(TiledArgs<T> A, const T *__restrict__ f,
+                                                    const T *__restrict__ lam, T *__restrict__ part, int want_f,
+                                                    const unsigned long long *__restrict__ lmax_bits,
+                                                    const int32_t *__restrict__ chan, double *__restrict__ gg2,
+                                                    int gg2_mode) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int64_t ti = tile_of_block(A.n_tiles, A.xcd);
+    if (ti < 0) return;
+    const TileRec t = A.tiles[ti];
+    unsigned long long *s_j = reinterpret_cast<unsigned long long *>(smem);
+    Pair2<T> *s_ef = reinterpret_cast<Pair2<T> *>(s_j + A.lds_states);
+    T *s_l = reinterpret_cast<T *>(s_ef + A.lds_states);
+    uint32_t *s_kq = reinterpret_cast<uint32_t *>(s_l + A.lds_states);
+    double *s_tab = reinterpret_cast<double *>(s_kq + A.lds_states);
+    const int n = t.lds ? t.p_hi - t.p_lo + 1 : 0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const StateRec<T> sr = A.st[t.p_lo + i];
+        Pair2<T> ef;
+        ef.a = sr.eps;
+        ef.b = f[t.p_lo + i];
+        s_ef[i] = ef;
+        s_l[i] = lam[t.p_lo + i];
+        s_kq[i] = PADQ ? sr.kqp : sr.kq;
+        s_j[i] = 0ull;
+    }
+    if constexpr (sizeof(T) == 8 && TAB)
+        for (int i = threadIdx.x; i < kExpTab; i += blockDim.x) s_tab[i] = A.e2tab[i];
+    const T scale = static_cast<T>(vjp_scale(A.nmax_bits, A.gmax_bits, lmax_bits));
+    __syncthreads();
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    const int nw = static_cast<int>(blockDim.x >> 6);
+    for (int64_t c = t.c0 + wave; c < t.c1; c += nw) {
+        if (t.lds)
+            vjp_pair_chunk<T, true, PADQ, NM, TAB>(A, f, lam, s_ef, s_kq, s_l, t.p_lo, s_tab, s_j, scale, c, part,
+                                                   want_f != 0, chan, gg2, gg2_mode);
+        else
+            vjp_pair_chunk<T, false, PADQ, NM, TAB>(A, f, lam, s_ef, s_kq, s_l, t.p_lo, s_tab, s_j, scale, c,
+                                                    part, want_f != 0, chan, gg2, gg2_mode);
+    }
+    if (!want_f) return;
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const unsigned long long v = s_j[i];
+        if (v) atomicAdd(A.jacc + t.p_lo + i, v);
+    }
+}
+
+// dL/df_d = K [-(row partials, chunk order) + partner side], then the
+// epilogue; the partner-side accumulator of d is cleared for the next call.
+template <typename T>
+__global__ void k_vjp_pairs_finish(TiledArgs<T> A, const T *__restrict__ part,
+                                   const unsigned long long *__restrict__ lmax_bits, Epi<T> E) {
+    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= A.S) return;
+    T a = T(0);
+    for (int c = A.dest_chunk[d]; c < A.dest_chunk[d + 1]; ++c) a += part[c];
+    const double inv = 1.0 / vjp_scale(A.nmax_bits, A.gmax_bits, lmax_bits);
+    const long long j = static_cast<long long>(A.jacc[d]);
+    A.jacc[d] = 0ull;
+    const T jside = static_cast<T>(static_cast<double>(j) * inv);
+    apply_epi(E, 0, d, A.S, A.K * (jside - a));
 }
 
 // I_d = K [(1 - f_d) sum b - f_d sum a] from the row side (chunk partials in
@@ -1285,6 +1609,10 @@ __global__ __launch_bounds__(512) void k_fwd_batched(BArgs<T> A, const T *__rest
                 const int64_t *so = A.sub_off + t.off_base + static_cast<int64_t>(dl) * (t.n_sub + 1);
                 const int64_t e_lo = so[k], e_hi = so[k + 1];
                 const StateRec<T> sd = A.st[d];
+                // the sub-tile's terms are summed on their own, then added to
+                // the running sums (two levels: each sum has at most PT terms
+                // plus one per sub-tile, instead of one per partner)
+                T sa = T(0), sb = T(0);
                 for (int64_t e0 = e_lo; e0 < e_hi; e0 += 64) {
                     const int64_t e = e0 + lane;
                     const bool valid = e < e_hi;
@@ -1328,10 +1656,12 @@ __global__ __launch_bounds__(512) void k_fwd_batched(BArgs<T> A, const T *__rest
                         const T bq = lane_bcast(cb, src);
                         const int pls = __builtin_amdgcn_readlane(pl, src);
                         const T fpb = s_F[pls * 65 + lane];
-                        acc_a[j] += a * (T(1) - fpb);
-                        acc_b[j] += bq * fpb;
+                        sa += a * (T(1) - fpb);
+                        sb += bq * fpb;
                     }
                 }
+                acc_a[j] += sa;
+                acc_b[j] += sb;
             }
         }
     }
@@ -1442,6 +1772,7 @@ __global__ __launch_bounds__(512) void k_vjp_batched(BArgs<T> A, const T *__rest
                 const StateRec<T> sd = A.st[d];
                 // the pairs of this sub-tile with p > d carry the |g|^2 gradients
                 const bool g_any = gg2_mode != 0 && pa + pc - 1 > d;
+                T su = T(0), sl = T(0);   // this sub-tile's sums (two-level, as in the forward)
                 for (int64_t e0 = e_lo; e0 < e_hi; e0 += 64) {
                     const int64_t e = e0 + lane;
                     const bool valid = e < e_hi;
@@ -1490,8 +1821,8 @@ __global__ __launch_bounds__(512) void k_vjp_batched(BArgs<T> A, const T *__rest
                         const int pls = __builtin_amdgcn_readlane(pl, src);
                         const Pair2<T> fl = s_FL[pls * 65 + lane];
                         const T u = a + (bq - a) * fl.a;
-                        acc_u[j] += u;
-                        acc_l[j] += fl.b * u;
+                        su += u;
+                        sl += fl.b * u;
                         if (g_any && pa + pls > d) {
                             const T dlm = ld[j] - fl.b;
                             const T p1 = wave_total(dlm * fd[j] * (T(1) - fl.a));
@@ -1503,6 +1834,8 @@ __global__ __launch_bounds__(512) void k_vjp_batched(BArgs<T> A, const T *__rest
                         }
                     }
                 }
+                acc_u[j] += su;
+                acc_l[j] += sl;
             }
         }
     }
@@ -1516,55 +1849,345 @@ __global__ __launch_bounds__(512) void k_vjp_batched(BArgs<T> A, const T *__rest
 }
 
 // ---- phonon side of the same processes (coupled e-ph dynamics) ----------
-// Each entry (d, p, nu) carries the processes that create or destroy phonon
-// (nu, q = k_p - k_d): d -> p absorbing it and p -> d emitting it, both with
-// the delta G(e_d - e_p + hw).  Its net emission, |g|^2 Ga [(N+1) f_p (1 - f_d)
-// - N f_d (1 - f_p)], is rounded to fixed point on the scale of sym_scale with
-// the bound phb (largest entry count of a bin times max |g|^2) and added to the
-// bin with an integer atomic, so each bin's sum does not depend on the order.
-// Entries of elastic mechanisms (bit nu of elastic) have no phonon: skipped.
+// A channel (i, j, nu) carries the processes that exchange phonon (nu, q),
+// q = k_j - k_i (i -> j absorbing it, j -> i emitting it, delta
+// G(e_i - e_j + hw)), and those that exchange (nu, -q) (delta
+// G(e_i - e_j - hw)).  The channels are grouped by the unordered pair
+// {qc, -qc} into pair records (a, b) with k_b - k_a = qc and one |g|^2 slot
+// per mode (zero where the pair has no channel of that mode), bucketed by qc
+// and cut into chunks of at most kPhChunk records.  One wave reduces one
+// chunk: with P1 = f_b (1 - f_a), P2 = f_a (1 - f_b), a record adds
+//   |g|^2 G(e_a - e_b + hw(qc)) (P1 + N(qc) (P1 - P2))    to bin (qc, nu),
+//   |g|^2 G(e_a - e_b - hw(-qc)) (P2 - N(-qc) (P1 - P2))  to bin (-qc, nu),
+// (net emission: (N+1) x gain - N x loss), in registers, in record order;
+// the two sums per mode go to the chunk's partials, and k_phonon_bins_finish
+// adds the partials of each bin in chunk order.  No atomics.
+constexpr int kPhChunk = 512;
+
+template <typename T> struct PhArgs {
+    const uint32_t *__restrict__ pa;
+    const uint32_t *__restrict__ pb;
+    const T *__restrict__ g2;          // [n_modes][ld]
+    int64_t ld;
+    const StateRec<T> *__restrict__ st;
+    const T *__restrict__ hw;          // [Nq][n_modes]
+    const int64_t *__restrict__ chunk_beg;    // [n_chunks + 1] record ranges
+    const int32_t *__restrict__ chunk_bucket; // [n_chunks]
+    const int32_t *__restrict__ bucket_chunk; // [n_buckets + 1]
+    const int32_t *__restrict__ bucket_q;     // [n_buckets] qc
+    const int32_t *__restrict__ bucket_qm;    // [n_buckets] -qc
+    const uint32_t *__restrict__ bucket_modes;
+    const int32_t *__restrict__ q_bucket;     // [Nq] 2 bucket + side, -1: none
+    int64_t n_chunks;
+    int64_t nq;
+    int nm;
+    T mc;                    // Gaussian exponent scale, base 2
+    double mc256;            // 256 mc (FP64 table exponential)
+    const double *__restrict__ e2tab;
+    double Kp;               // 2 pi / (hbar N_k) / (sigma sqrt(2 pi))
+    uint32_t elastic;        // bit nu: mode nu is elastic (no phonon side)
+    const int32_t *__restrict__ chan;   // [n_modes][ld] caller channel of each slot, -1: none
+};
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_phonon_rate(TiledArgs<T> A, const T *__restrict__ f,
-                                                     uint32_t elastic,
-                                                     const unsigned long long *__restrict__ phb_bits,
-                                                     unsigned long long *__restrict__ bins) {
+__device__ __forceinline__ T ph_gauss(const PhArgs<T> &A, T x, const double *tab) {
+    if constexpr (sizeof(T) == 8) return gauss_exp2_tab(x * x * A.mc256, tab);
+    else return __builtin_amdgcn_exp2f(x * x * A.mc);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_phonon_bins(PhArgs<T> A, const T *__restrict__ f,
+                                                     const T *__restrict__ nph, T *__restrict__ part) {
+    __shared__ double s_tab[kExpTab];
+    if constexpr (sizeof(T) == 8)
+        for (int i = threadIdx.x; i < kExpTab; i += blockDim.x) s_tab[i] = A.e2tab[i];
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int64_t c = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) +
+                      __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    if (c >= A.n_chunks) return;
+    const int bk = A.chunk_bucket[c];
+    const int64_t qc = A.bucket_q[bk], qm = A.bucket_qm[bk];
+    const uint32_t modes = A.bucket_modes[bk] & ~A.elastic;
+    T w1[8], n1[8], w2[8], n2[8], acc1[8], acc2[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        const bool on = (modes >> m) & 1u;
+        w1[m] = on ? A.hw[qc * A.nm + m] : T(0);
+        n1[m] = on ? nph[qc * A.nm + m] : T(0);
+        w2[m] = on ? A.hw[qm * A.nm + m] : T(0);
+        n2[m] = on ? nph[qm * A.nm + m] : T(0);
+        acc1[m] = T(0);
+        acc2[m] = T(0);
+    }
+    const int64_t beg = A.chunk_beg[c], end = A.chunk_beg[c + 1];
+    for (int64_t i = beg + lane; i < end; i += 64) {
+        const uint32_t a = A.pa[i], b = A.pb[i];
+        const T fa = f[a], fb = f[b];
+        const T d = A.st[a].eps - A.st[b].eps;
+        const T p1 = fb * (T(1) - fa), p2 = fa * (T(1) - fb);
+        const T dp = p1 - p2;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            if (!((modes >> m) & 1u)) continue;
+            const T g = A.g2[m * A.ld + i];
+            const T ga = ph_gauss(A, d + w1[m], s_tab);
+            const T ge = ph_gauss(A, d - w2[m], s_tab);
+            acc1[m] += g * ga * (p1 + n1[m] * dp);
+            acc2[m] += g * ge * (p2 - n2[m] * dp);
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        if (!((modes >> m) & 1u)) continue;
+        acc1[m] = wave_sum(acc1[m]);
+        acc2[m] = wave_sum(acc2[m]);
+    }
+    if (lane == 0) {
+        T *pc = part + c * 2 * A.nm;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            if (m >= A.nm) break;
+            pc[m] = acc1[m];
+            pc[A.nm + m] = acc2[m];
+        }
+    }
+}
+
+// Reverse mode over the same records at a stage (u, N) of the coupled step,
+// given lam = dL/dI and mu = dL/d(dN/dt) per bin.  Per record and mode, with
+// x = e_a - e_b, G1 = G(x + hw(qc)), E1 = G(x - hw(qc)), G2 = G(x + hw(-qc)),
+// E2 = G(x - hw(-qc)) (two exponentials when hw(-qc) = hw(qc)):
+//   bin (qc, nu):  |g|^2 (f_b - f_a) [Ke lam_a (G1 + E1) + Kp mu(qc) G1]
+//   bin (-qc, nu): |g|^2 (f_a - f_b) [Ke lam_b (G2 + E2) + Kp mu(-qc) E2]
+// (dL/dN: the collision integral is affine in N, the phonon-side rate too);
+// and, for phonon modes, dL/d|g|^2 of the record's channel gains
+//   Kp [mu(qc) G1 (P1 + N(qc) (P1 - P2)) + mu(-qc) E2 (P2 - N(-qc) (P1 - P2))]
+// (its only writer: every channel has one slot).  Elastic modes have no
+// phonon side: only their lam terms.  lam or mu may be null (taken as 0).
+template <typename T>
+__global__ __launch_bounds__(256) void k_phonon_bins_adj(PhArgs<T> A, const T *__restrict__ f,
+                                                         const T *__restrict__ nph, const T *__restrict__ lam,
+                                                         const T *__restrict__ mu, T *__restrict__ part,
+                                                         double *__restrict__ gg2, double Ke) {
+    __shared__ double s_tab[kExpTab];
+    if constexpr (sizeof(T) == 8)
+        for (int i = threadIdx.x; i < kExpTab; i += blockDim.x) s_tab[i] = A.e2tab[i];
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int64_t c = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) +
+                      __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    if (c >= A.n_chunks) return;
+    const int bk = A.chunk_bucket[c];
+    const int64_t qc = A.bucket_q[bk], qm = A.bucket_qm[bk];
+    const uint32_t modes = A.bucket_modes[bk];
+    const uint32_t phon = mu ? modes & ~A.elastic : 0u;
+    const T ke = static_cast<T>(Ke), kp = static_cast<T>(A.Kp);
+    T w1[8], n1[8], w2[8], n2[8], m1[8], m2[8], acc1[8], acc2[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        const bool on = (modes >> m) & 1u;
+        const bool ph = (phon >> m) & 1u;
+        w1[m] = on ? A.hw[qc * A.nm + m] : T(0);
+        w2[m] = on ? A.hw[qm * A.nm + m] : T(0);
+        n1[m] = ph ? nph[qc * A.nm + m] : T(0);
+        n2[m] = ph ? nph[qm * A.nm + m] : T(0);
+        m1[m] = ph ? mu[qc * A.nm + m] : T(0);
+        m2[m] = ph ? mu[qm * A.nm + m] : T(0);
+        acc1[m] = T(0);
+        acc2[m] = T(0);
+    }
+    const int64_t beg = A.chunk_beg[c], end = A.chunk_beg[c + 1];
+    for (int64_t i = beg + lane; i < end; i += 64) {
+        const uint32_t a = A.pa[i], b = A.pb[i];
+        const T fa = f[a], fb = f[b];
+        const T la = lam ? lam[a] : T(0), lb = lam ? lam[b] : T(0);
+        const T x = A.st[a].eps - A.st[b].eps;
+        const T p1 = fb * (T(1) - fa), p2 = fa * (T(1) - fb);
+        const T dp = p1 - p2;   // = f_b - f_a
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            if (!((modes >> m) & 1u)) continue;
+            const T g = A.g2[m * A.ld + i];
+            const T g1 = ph_gauss(A, x + w1[m], s_tab);
+            const T e1 = ph_gauss(A, x - w1[m], s_tab);
+            T g2_ = g1, e2 = e1;
+            if (w2[m] != w1[m]) {
+                g2_ = ph_gauss(A, x + w2[m], s_tab);
+                e2 = ph_gauss(A, x - w2[m], s_tab);
+            }
+            acc1[m] += g * dp * (ke * la * (g1 + e1) + kp * m1[m] * g1);
+            acc2[m] -= g * dp * (ke * lb * (g2_ + e2) + kp * m2[m] * e2);
+            if (gg2 && ((phon >> m) & 1u)) {
+                const int32_t ch = A.chan[m * A.ld + i];
+                if (ch >= 0)
+                    gg2[ch] += static_cast<double>(kp * (m1[m] * g1 * (p1 + n1[m] * dp) +
+                                                         m2[m] * e2 * (p2 - n2[m] * dp)));
+            }
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        if (!((modes >> m) & 1u)) continue;
+        acc1[m] = wave_sum(acc1[m]);
+        acc2[m] = wave_sum(acc2[m]);
+    }
+    if (lane == 0) {
+        T *pc = part + c * 2 * A.nm;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            if (m >= A.nm) break;
+            pc[m] = acc1[m];
+            pc[A.nm + m] = acc2[m];
+        }
+    }
+}
+
+// {hw, N, mu} per (q, mode) for the reverse of the phonon-side rate: the
+// padded table of k_pack_hwN_pad (pad != 0) or the plain one.
+template <typename T>
+__global__ void k_pack_hwNmu(const T *__restrict__ hw, const T *__restrict__ nph, const T *__restrict__ mu,
+                             Vec4<T> *__restrict__ out, int pad, int n0, int n1, int n2, int nm, int64_t n) {
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        int64_t src = i;
+        if (pad) {
+            const int nu = static_cast<int>(i % nm);
+            int64_t qp = i / nm;
+            const int c2 = static_cast<int>(qp % (2 * n2));
+            qp /= 2 * n2;
+            const int c1 = static_cast<int>(qp % (2 * n1));
+            const int c0 = static_cast<int>(qp / (2 * n1));
+            int a0 = c0 - n0, a1 = c1 - n1, a2 = c2 - n2;
+            a0 += a0 < 0 ? n0 : 0;
+            a1 += a1 < 0 ? n1 : 0;
+            a2 += a2 < 0 ? n2 : 0;
+            src = ((static_cast<int64_t>(a0) * n1 + a1) * n2 + a2) * nm + nu;
+        }
+        Vec4<T> v;
+        v.x = hw[src];
+        v.y = nph[src];
+        v.z = mu[src];
+        v.w = T(0);
+        out[i] = v;
+    }
+}
+
+// Electron side of the reverse of the phonon-side rate: for every entry
+// (d, p, nu) with q = k_p - k_d (x = e_d - e_p),
+//   dL/df_d += Kp |g|^2 [mu(-q) G(x - hw(-q)) (N(-q) + 1 - f_p) - mu(q) G(x + hw(q)) (N(q) + f_p)]
+// (the entry's channel feeds bin q through G(x + hw(q)) and bin -q through
+// G(x - hw(-q)); the same form holds from either end of the channel).  One
+// workgroup per chunk of the destination layout; a destination with one
+// chunk adds its sum to out, others leave a partial for k_vjp_phonon_f_finish.
+template <typename T>
+__global__ __launch_bounds__(256) void k_vjp_phonon_f(TiledArgs<T> A, const Vec4<T> *__restrict__ tab,
+                                                      const T *__restrict__ f, uint32_t elastic,
+                                                      double Kp, T *__restrict__ out, T *__restrict__ part) {
+    __shared__ double s_tab[kExpTab];
+    if constexpr (sizeof(T) == 8)
+        for (int i = threadIdx.x; i < kExpTab; i += blockDim.x) s_tab[i] = A.e2tab[i];
+    __syncthreads();
     const int64_t c = blockIdx.x;
     if (c >= A.n_chunks) return;
     const int d = A.chunk_dest[c];
     const int64_t beg = A.chunk_beg[c], end = A.chunk_beg[c + 1];
     const StateRec<T> sd = A.st[d];
-    const T fd = f[d];
-    const T scale = static_cast<T>(sym_scale(A.nmax_bits, phb_bits));
+    T acc[1] = {T(0)};
     for (int64_t e = beg + threadIdx.x; e < end; e += blockDim.x) {
         const uint32_t pn = A.pnu[e];
         const int mode = static_cast<int>(pn & 7u);
         if ((elastic >> mode) & 1u) continue;
         const int p = static_cast<int>(pn >> 3);
         const StateRec<T> sp = A.st[p];
-        const int ql = q_linear(sd.kq, sp.kq, A.nq0, A.nq1, A.nq2);
-        const int qi = A.padq ? static_cast<int>(sp.kqp - sd.kqp) + A.qoff : ql;
-        const Pair2<T> wn = A.hwN[static_cast<int64_t>(qi) * A.nm + mode];
-        const T xa = (sd.eps - sp.eps) + wn.a;
-        const T da = gauss_exp(xa * xa * A.mc);
+        int64_t iq, im;
+        if (A.padq) {
+            iq = static_cast<int64_t>(static_cast<int>(sp.kqp - sd.kqp) + A.qoff);
+            im = 2 * static_cast<int64_t>(A.qoff) - iq;
+        } else {
+            iq = q_linear(sd.kq, sp.kq, A.nq0, A.nq1, A.nq2);
+            im = q_linear(sp.kq, sd.kq, A.nq0, A.nq1, A.nq2);
+        }
+        const Vec4<T> t1 = tab[iq * A.nm + mode], t2 = tab[im * A.nm + mode];
+        const T x = sd.eps - sp.eps;
         const T fp = f[p];
-        const T y = A.g2[e] * da * ((wn.b + T(1)) * fp * (T(1) - fd) - wn.b * fd * (T(1) - fp));
-        const unsigned long long v = to_fixed(__builtin_rint(y * scale));
-        atomicAdd(bins + static_cast<int64_t>(ql) * A.nm + mode, v);
+        const T ga = stream_gauss(A, (x + t1.x) * (x + t1.x), s_tab);
+        const T ge = stream_gauss(A, (x - t2.x) * (x - t2.x), s_tab);
+        acc[0] += A.g2[e] * (t2.z * ge * (t2.y + T(1) - fp) - t1.z * ga * (t1.y + fp));
+    }
+    block_sum<T, 1>(acc);
+    if (threadIdx.x == 0) {
+        const T v = static_cast<T>(Kp) * acc[0];
+        if (A.dest_chunk[d + 1] - A.dest_chunk[d] == 1) out[d] += v;
+        else part[c] = v;
     }
 }
 
-// dN = Kp sum of the bin (Kp = 2 pi / (hbar N_k) / (sigma sqrt(2 pi))); clears the bins.
 template <typename T>
-__global__ void k_phonon_finish(unsigned long long *__restrict__ bins, int64_t n,
-                                const unsigned long long *__restrict__ nmax_bits,
-                                const unsigned long long *__restrict__ phb_bits, double Kp,
-                                T *__restrict__ out) {
-    const double inv = 1.0 / sym_scale(nmax_bits, phb_bits);
+__global__ void k_vjp_phonon_f_finish(TiledArgs<T> A, const T *__restrict__ part, T *__restrict__ out) {
+    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= A.S) return;
+    const int c0 = A.dest_chunk[d], c1 = A.dest_chunk[d + 1];
+    if (c1 - c0 == 1) return;
+    T a = T(0);
+    for (int c = c0; c < c1; ++c) a += part[c];
+    out[d] += a;
+}
+
+// out = x (mode 0) or out = (x(q) + x(-q)) / 2 per (q, mode) (mode 1): the
+// even part in q, which is its own transpose
+template <typename T>
+__global__ void k_even_q(const T *__restrict__ x, T *__restrict__ out, int n0, int n1, int n2, int nm) {
+    const int64_t n = static_cast<int64_t>(n0) * n1 * n2 * nm;
     for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
          i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        const long long v = static_cast<long long>(bins[i]);
-        bins[i] = 0ull;
-        out[i] = static_cast<T>(Kp * (static_cast<double>(v) * inv));
+        const int64_t q = i / nm;
+        const int nu = static_cast<int>(i - q * nm);
+        const int a2 = static_cast<int>(q % n2), a1 = static_cast<int>((q / n2) % n1),
+                  a0 = static_cast<int>(q / (static_cast<int64_t>(n1) * n2));
+        const int64_t qm = (static_cast<int64_t>((n0 - a0) % n0) * n1 + (n1 - a1) % n1) * n2 + (n2 - a2) % n2;
+        out[i] = T(0.5) * (x[i] + x[qm * nm + nu]);
+    }
+}
+
+// out = a x + b y (y may be null: out = a x)
+template <typename T>
+__global__ void k_axpby(int64_t n, T a, const T *__restrict__ x, T b, const T *__restrict__ y, T *__restrict__ out) {
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        out[i] = y ? a * x[i] + b * y[i] : a * x[i];
+}
+
+// |g|^2 slots of the pair records from the caller's list (update_g2)
+template <typename T>
+__global__ void k_ph_gather_g2(const int32_t *__restrict__ chan, const double *__restrict__ g2,
+                               T *__restrict__ out, int64_t n) {
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int32_t c = chan[i];
+        out[i] = c >= 0 ? static_cast<T>(g2[c]) : T(0);
+    }
+}
+
+// dN(q, nu) = Kp (sum over the chunks of q's bucket of q's side, in chunk
+// order; both sides when q = -q), 0 for bins without channels.
+template <typename T>
+__global__ void k_phonon_bins_finish(PhArgs<T> A, const T *__restrict__ part, T *__restrict__ out) {
+    const int64_t n = A.nq * A.nm;
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t q = i / A.nm;
+        const int m = static_cast<int>(i - q * A.nm);
+        const int qb = A.q_bucket[q];
+        T sum = T(0);
+        if (qb >= 0) {
+            const int bk = qb >> 1, side = qb & 1;
+            const int c0 = A.bucket_chunk[bk], c1 = A.bucket_chunk[bk + 1];
+            for (int c = c0; c < c1; ++c) sum += part[(static_cast<int64_t>(c) * 2 + side) * A.nm + m];
+            if (A.bucket_q[bk] == A.bucket_qm[bk])
+                for (int c = c0; c < c1; ++c) sum += part[(static_cast<int64_t>(c) * 2 + 1) * A.nm + m];
+        }
+        out[i] = static_cast<T>(A.Kp * static_cast<double>(sum));
     }
 }
 
@@ -1580,15 +2203,6 @@ __global__ __launch_bounds__(256) void k_abs_max_bits(const T *__restrict__ x, i
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
     if ((threadIdx.x & 63) == 0) atomicMax(out, static_cast<unsigned long long>(__double_as_longlong(m)));
-}
-
-// phb = count * max |g|^2 (the per-bin bound of the phonon-side sums)
-__global__ void k_phonon_bound(const unsigned long long *__restrict__ gmax_bits, double count,
-                               unsigned long long *__restrict__ phb_bits) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        const double g = __longlong_as_double(static_cast<long long>(*gmax_bits));
-        *phb_bits = static_cast<unsigned long long>(__double_as_longlong(count * g));
-    }
 }
 
 // ---- transport ----------------------------------------------------------

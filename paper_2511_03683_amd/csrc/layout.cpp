@@ -436,3 +436,174 @@ std::vector<BTile> make_btiles(const std::vector<int32_t> &pmin, const std::vect
 }
 
 }  // namespace ephbte
+
+namespace ephbte {
+
+PhononLayout build_phonon_layout(const HostLayout &L) {
+    PhononLayout out;
+    const int64_t n0 = L.nq[0], n1 = L.nq[1], n2 = L.nq[2];
+    const int64_t nq = n0 * n1 * n2;
+    const int nm = L.n_modes;
+    // q = k_b - k_a on the q grid (both in q-grid units, 10 bits per axis)
+    auto qlin = [&](uint32_t ka, uint32_t kb) {
+        int64_t a0 = int64_t(kb >> 20) - int64_t(ka >> 20);
+        int64_t a1 = int64_t((kb >> 10) & 1023u) - int64_t((ka >> 10) & 1023u);
+        int64_t a2 = int64_t(kb & 1023u) - int64_t(ka & 1023u);
+        a0 += a0 < 0 ? n0 : 0;
+        a1 += a1 < 0 ? n1 : 0;
+        a2 += a2 < 0 ? n2 : 0;
+        return (a0 * n1 + a1) * n2 + a2;
+    };
+    auto neg = [&](int64_t q) {
+        const int64_t c2 = q % n2, c1 = (q / n2) % n1, c0 = q / (n1 * n2);
+        return (((n0 - c0) % n0) * n1 + (n1 - c1) % n1) * n2 + (n2 - c2) % n2;
+    };
+    // each channel once: row d, partners p > d; a pair is a run of equal p
+    const int T = host_threads();
+    const int64_t S = L.S;
+    std::vector<int64_t> ranges(T + 1);
+    for (int t = 0; t <= T; ++t) ranges[t] = S * t / T;
+    std::vector<std::vector<int64_t>> cnt(T, std::vector<int64_t>(static_cast<size_t>(nq), 0));
+    auto for_pairs = [&](int64_t d0, int64_t d1, auto &&fn) {
+        for (int64_t d = d0; d < d1; ++d) {
+            int64_t x = L.row_ptr[d];
+            const int64_t e = L.row_ptr[d + 1];
+            while (x < e && static_cast<int64_t>(L.pnu[x] >> 3) <= d) ++x;
+            while (x < e) {
+                const uint32_t p = L.pnu[x] >> 3;
+                int64_t y = x;
+                uint32_t modes = 0;
+                while (y < e && (L.pnu[y] >> 3) == p) {
+                    modes |= 1u << (L.pnu[y] & 7u);
+                    ++y;
+                }
+                if (modes) {
+                    const int64_t q = qlin(L.kq[d], L.kq[p]), qm = neg(q);
+                    fn(d, static_cast<int64_t>(p), x, y, std::min(q, qm), q <= qm);
+                }
+                x = y;
+            }
+        }
+    };
+    std::vector<std::thread> pool;
+    for (int t = 0; t < T; ++t)
+        pool.emplace_back([&, t] {
+            for_pairs(ranges[t], ranges[t + 1],
+                      [&](int64_t, int64_t, int64_t, int64_t, int64_t qc, bool) { ++cnt[t][qc]; });
+        });
+    for (auto &th : pool) th.join();
+    pool.clear();
+    // buckets in order of qc; thread t's pairs of a bucket follow those of
+    // threads < t, and each thread walks its rows in order, so every bucket is
+    // ordered by (d, p) whatever the split
+    std::vector<int64_t> qbeg(static_cast<size_t>(nq) + 1, 0);
+    for (int64_t q = 0; q < nq; ++q) {
+        int64_t c = 0;
+        for (int t = 0; t < T; ++t) c += cnt[t][q];
+        qbeg[q + 1] = qbeg[q] + c;
+    }
+    out.n_pairs = qbeg[nq];
+    for (int64_t q = 0; q < nq; ++q) {
+        int64_t o = qbeg[q];
+        for (int t = 0; t < T; ++t) {
+            const int64_t c = cnt[t][q];
+            cnt[t][q] = o;
+            o += c;
+        }
+    }
+    const int64_t np = out.n_pairs;
+    out.pa.resize(np);
+    out.pb.resize(np);
+    out.slot_chan.assign(static_cast<size_t>(nm) * np, -1);
+    std::vector<uint32_t> qmodes(static_cast<size_t>(nq), 0);
+    std::vector<std::vector<uint32_t>> tmodes(T);
+    for (int t = 0; t < T; ++t)
+        pool.emplace_back([&, t] {
+            auto &pos = cnt[t];
+            for_pairs(ranges[t], ranges[t + 1],
+                      [&](int64_t d, int64_t p, int64_t x, int64_t y, int64_t qc, bool fwd) {
+                          const int64_t i = pos[qc]++;
+                          out.pa[i] = static_cast<uint32_t>(fwd ? d : p);
+                          out.pb[i] = static_cast<uint32_t>(fwd ? p : d);
+                          for (int64_t z = x; z < y; ++z)
+                              out.slot_chan[static_cast<size_t>(L.pnu[z] & 7u) * np + i] = L.ent_chan[z];
+                      });
+        });
+    for (auto &th : pool) th.join();
+    // modes present per bucket (from the slots, in one pass)
+    out.q_bucket.assign(static_cast<size_t>(nq), -1);
+    out.bucket_beg.push_back(0);
+    for (int64_t q = 0; q < nq; ++q) {
+        if (qbeg[q + 1] == qbeg[q]) continue;
+        uint32_t modes = 0;
+        for (int m = 0; m < nm; ++m)
+            for (int64_t i = qbeg[q]; i < qbeg[q + 1]; ++i)
+                if (out.slot_chan[static_cast<size_t>(m) * np + i] >= 0) {
+                    modes |= 1u << m;
+                    break;
+                }
+        const int64_t b = static_cast<int64_t>(out.bucket_q.size());
+        const int64_t qm = neg(q);
+        out.bucket_q.push_back(static_cast<int32_t>(q));
+        out.bucket_qm.push_back(static_cast<int32_t>(qm));
+        out.bucket_modes.push_back(modes);
+        out.bucket_beg.push_back(qbeg[q + 1]);
+        out.q_bucket[q] = static_cast<int32_t>(2 * b);
+        if (qm != q) out.q_bucket[qm] = static_cast<int32_t>(2 * b + 1);
+    }
+    return out;
+}
+
+}  // namespace ephbte
+
+namespace ephbte {
+
+PairRows build_pair_rows(const HostLayout &L) {
+    PairRows out;
+    const int64_t S = L.S;
+    const int nm = L.n_modes;
+    out.row_ptr.assign(static_cast<size_t>(S) + 1, 0);
+    // first entry of row d with partner > d: entries are sorted by (partner, mode)
+    auto upper = [&](int64_t d) {
+        const auto lo = L.pnu.begin() + L.row_ptr[d], hi = L.pnu.begin() + L.row_ptr[d + 1];
+        return static_cast<int64_t>(std::lower_bound(lo, hi, static_cast<uint32_t>(d + 1) << 3) - L.pnu.begin());
+    };
+    std::vector<int64_t> cnt(static_cast<size_t>(S), 0);
+    parallel_ranges(S, host_threads(), [&](int, int64_t b, int64_t e) {
+        for (int64_t d = b; d < e; ++d) {
+            int64_t n = 0;
+            uint32_t last = 0xffffffffu;
+            for (int64_t x = upper(d); x < L.row_ptr[d + 1]; ++x) {
+                const uint32_t p = L.pnu[x] >> 3;
+                n += p != last;
+                last = p;
+            }
+            cnt[d] = n;
+        }
+    });
+    for (int64_t d = 0; d < S; ++d) out.row_ptr[d + 1] = out.row_ptr[d] + cnt[d];
+    const int64_t np = out.row_ptr[S];
+    out.n_pairs = np;
+    out.partner.resize(static_cast<size_t>(np));
+    out.slot_chan.assign(static_cast<size_t>(nm) * np, -1);
+    std::vector<int64_t> filled(static_cast<size_t>(host_threads()) + 1, 0);
+    parallel_ranges(S, host_threads(), [&](int t, int64_t b, int64_t e) {
+        int64_t f = 0;
+        for (int64_t d = b; d < e; ++d) {
+            int64_t j = out.row_ptr[d] - 1;
+            uint32_t last = 0xffffffffu;
+            for (int64_t x = upper(d); x < L.row_ptr[d + 1]; ++x) {
+                const uint32_t p = L.pnu[x] >> 3;
+                if (p != last) out.partner[++j] = p;
+                last = p;
+                out.slot_chan[static_cast<size_t>(L.pnu[x] & 7u) * np + j] = L.ent_chan[x];
+                ++f;
+            }
+        }
+        filled[t] = f;
+    });
+    for (int64_t f : filled) out.n_filled += f;
+    return out;
+}
+
+}  // namespace ephbte

@@ -90,6 +90,42 @@ struct BTile {
 std::vector<BTile> make_btiles(const std::vector<int32_t> &pmin, const std::vector<int32_t> &pmax,
                                int32_t pt, int32_t dmax, int32_t window_cap, int64_t *slots);
 
+// Phonon-side layout: the channels grouped by the phonon they exchange.  A
+// channel (i, j, nu) emits or absorbs phonon (nu, q) with q = k_j - k_i in one
+// orientation and (nu, -q) in the other, so each channel belongs to one
+// unordered pair {q, -q}; its canonical member qc is the smaller linear index
+// of the two.  Channels are grouped into pair records (a, b) oriented so that
+// k_b - k_a = qc, one slot per mode, and the records are bucketed by qc.
+// Inside a bucket they are ordered by (min(a, b), max(a, b)), which does not
+// depend on how the build is split over threads.
+struct PhononLayout {
+    int64_t n_pairs = 0;
+    std::vector<uint32_t> pa, pb;       // [n_pairs]
+    std::vector<int32_t> slot_chan;     // [n_modes][n_pairs]: caller channel, -1 if the pair has no such mode
+    std::vector<int64_t> bucket_beg;    // [n_buckets + 1] pair ranges
+    std::vector<int32_t> bucket_q;      // [n_buckets] qc
+    std::vector<int32_t> bucket_qm;     // [n_buckets] linear index of -qc (= qc when q = -q)
+    std::vector<uint32_t> bucket_modes; // [n_buckets] bit nu: the bucket holds a channel of mode nu
+    std::vector<int32_t> q_bucket;      // [Nq]: 2 b + side of the bucket b holding q (side 1: q = -qc), -1 if none
+};
+// Channels of elastic modes are kept (the collision integral depends on their
+// N); the phonon-side kernels skip those modes.
+PhononLayout build_phonon_layout(const HostLayout &L);
+
+// Pair records of the single-copy pass.  Row d holds the pairs (d, p) with
+// p > d in partner order, each with one |g|^2 slot per mode (the caller's
+// channel of that mode, -1 when the pair has none), so that every channel of
+// a pair is evaluated from one partner gather and the partner side of the
+// pair is one sum.
+struct PairRows {
+    int64_t n_pairs = 0;
+    int64_t n_filled = 0;               // slots holding a channel
+    std::vector<int64_t> row_ptr;       // [S + 1]
+    std::vector<uint32_t> partner;      // [n_pairs]
+    std::vector<int32_t> slot_chan;     // [n_modes][n_pairs]
+};
+PairRows build_pair_rows(const HostLayout &L);
+
 // Runs fn(t, begin, end) over [0, n) split into contiguous ranges on up to
 // `threads` host threads (deterministic partition).
 void parallel_ranges(int64_t n, int threads,

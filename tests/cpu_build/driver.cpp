@@ -149,7 +149,9 @@ int main(int argc, char **argv) {
     t.xcd_map = static_cast<int32_t>(meta("xcd_map", 0));
     t.batch_partners = static_cast<int32_t>(meta("batch_partners", 0));
     t.tile_entries = static_cast<int32_t>(meta("tile_entries", 0));
-    if (t.layout || t.chunk_entries || t.block_threads || t.xcd_map || t.batch_partners || t.tile_entries)
+    t.fp64_exp = static_cast<int32_t>(meta("fp64_exp", 0));
+    if (t.layout || t.chunk_entries || t.block_threads || t.xcd_map || t.batch_partners || t.tile_entries ||
+        t.fp64_exp)
         check(ephbte_set_tuning(plan, &t), "set_tuning");
     // empty_windows: every LDS tile whose chunks hold no entries gets an empty
     // partner window (nothing staged), the shape that once made masked lanes
@@ -236,6 +238,9 @@ int main(int argc, char **argv) {
         void *df = dv.up(f), *dI = dv.alloc(static_cast<size_t>(B) * S);
         check(ephbte_collision_integral(plan, B, df, S, dN, 0, dI, S, nullptr), "collision_integral");
         wr("out_I.bin", dv.down(dI, static_cast<size_t>(B) * S));
+        void *dr = dv.alloc(nqm);
+        check(ephbte_phonon_rate(plan, df, dN, dr, nullptr), "phonon_rate");
+        wr("out_rate.bin", dv.down(dr, nqm));
     } else if (mode == "autotune") {
         // tune twice with one cache file: the second call reads the entry back
         const std::string cache = g_dir + "/tune.json";
@@ -284,6 +289,44 @@ int main(int argc, char **argv) {
         void *df = dv.up(f), *dr = dv.alloc(nqm);
         check(ephbte_phonon_rate(plan, df, dN, dr, nullptr), "phonon_rate");
         wr("out_rate.bin", dv.down(dr, nqm));
+    } else if (mode == "vjp_nph") {
+        auto f = rd<double>("f.bin", static_cast<size_t>(S));
+        auto lam = rd<double>("lam.bin", static_cast<size_t>(S));
+        void *df = dv.up(f), *dl = dv.up(lam), *dg = dv.alloc(nqm);
+        check(ephbte_collision_vjp_nph(plan, df, dN, dl, dg, nullptr), "collision_vjp_nph");
+        wr("out_gN.bin", dv.down(dg, nqm));
+    } else if (mode == "phonon_vjp") {
+        auto f = rd<double>("f.bin", static_cast<size_t>(S));
+        auto mu = rd<double>("mu.bin", nqm);
+        void *df = dv.up(f), *dm = dv.up(mu), *dgf = dv.alloc(static_cast<size_t>(S)), *dgN = dv.alloc(nqm);
+        std::vector<double> fill(static_cast<size_t>(nch), 0.25);
+        double *dgg = nullptr;
+        hipMalloc(reinterpret_cast<void **>(&dgg), 8 * static_cast<size_t>(nch));
+        hipMemcpy(dgg, fill.data(), 8 * static_cast<size_t>(nch), hipMemcpyHostToDevice);
+        check(ephbte_phonon_rate_vjp(plan, df, dN, dm, dgf, dgN, dgg, 1, nullptr), "phonon_rate_vjp");
+        wr("out_gf.bin", dv.down(dgf, static_cast<size_t>(S)));
+        wr("out_gN.bin", dv.down(dgN, nqm));
+        std::vector<double> gg(static_cast<size_t>(nch));
+        hipMemcpy(gg.data(), dgg, 8 * static_cast<size_t>(nch), hipMemcpyDeviceToHost);
+        wr("out_gg2.bin", gg);   // accumulated onto 0.25
+    } else if (mode == "coupled_adjoint") {
+        const double dt = meta("dt");
+        const int n = static_cast<int>(meta("steps"));
+        const int ce = static_cast<int>(meta("ce"));
+        auto f = rd<double>("f.bin", static_cast<size_t>(S));
+        auto gfT = rd<double>("gT.bin", static_cast<size_t>(S));
+        auto gNT = rd<double>("gNT.bin", nqm);
+        void *df = dv.up(f), *dgT = dv.up(gfT), *dgNT = dv.up(gNT);
+        void *dgf = dv.alloc(static_cast<size_t>(S)), *dgN = dv.alloc(nqm);
+        double *dgg = nullptr;
+        hipMalloc(reinterpret_cast<void **>(&dgg), 8 * static_cast<size_t>(nch));
+        check(ephbte_rt_adjoint_coupled(plan, df, dN, dt, n, ce, dgT, dgNT, dgf, dgN, dgg, 0, nullptr),
+              "rt_adjoint_coupled");
+        wr("out_gf.bin", dv.down(dgf, static_cast<size_t>(S)));
+        wr("out_gN.bin", dv.down(dgN, nqm));
+        std::vector<double> gg(static_cast<size_t>(nch));
+        hipMemcpy(gg.data(), dgg, 8 * static_cast<size_t>(nch), hipMemcpyDeviceToHost);
+        wr("out_gg2.bin", gg);
     } else if (mode == "adjoint") {
         if (g_meta.count("rates")) {
             const double rates[3] = {g_meta["rates"].at(0), g_meta["rates"].at(1), g_meta["rates"].at(2)};

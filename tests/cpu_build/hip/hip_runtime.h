@@ -201,7 +201,7 @@ inline unsigned long long atomicMax(unsigned long long *p, unsigned long long v)
 
 // ---------------------------------------------------------------- runtime
 typedef int hipError_t;
-enum { hipSuccess = 0, hipErrorInvalidValue = 1 };
+enum { hipSuccess = 0, hipErrorInvalidValue = 1, hipErrorInvalidDevice = 101, hipErrorInvalidSymbol = 701 };
 typedef struct emu_stream *hipStream_t;
 typedef struct emu_event *hipEvent_t;
 struct emu_graph { std::vector<std::function<void()>> ops; };
@@ -218,6 +218,7 @@ struct hipDeviceProp_t { char gcnArchName[256]; char name[256]; int multiProcess
 namespace emu {
 inline emu_graph *capture = nullptr;
 inline int n_cu = 256;
+inline long long n_malloc = 0;   // hipMalloc calls so far (allocation-free checks)
 }
 // Fill of fresh device memory and of LDS at the start of each workgroup:
 // CPU_BUILD_FILL = pattern (default: 0xA5 for device memory, 0xFF for LDS) or
@@ -240,6 +241,7 @@ inline void fill_unwritten(void *p, size_t n, unsigned char pattern) {
     }
 }
 inline hipError_t hipMalloc(void **p, size_t n) {
+    ++emu::n_malloc;
     *p = aligned_alloc(256, (n + 255) / 256 * 256);
     if (!*p) return 1;
     fill_unwritten(*p, n, 0xA5);
@@ -247,6 +249,7 @@ inline hipError_t hipMalloc(void **p, size_t n) {
     return hipSuccess;
 }
 inline hipError_t hipFree(void *p) { free(p); return hipSuccess; }
+
 inline hipError_t hipHostMalloc(void **p, size_t n, unsigned) { return hipMalloc(p, n); }
 inline hipError_t hipHostFree(void *p) { free(p); return hipSuccess; }
 inline hipError_t hipMemcpy(void *d, const void *s, size_t n, hipMemcpyKind) { if (n) std::memmove(d, s, n); return hipSuccess; }

@@ -137,13 +137,16 @@ def _round32(s):
     return r
 
 
-@pytest.mark.parametrize("layout,dtype", [(2, "f64"), (1, "f64"), (2, "f32")])
-def test_forward_single_vector(driver, tmp_path, layout, dtype):
-    """Single-copy (layout 2) and per-row (layout 1) forward passes, B = 1."""
+@pytest.mark.parametrize("layout,dtype,fexp", [(2, "f64", 0), (1, "f64", 0), (2, "f32", 0), (3, "f64", 1),
+                                               (3, "f64", 2), (3, "f32", 0)])
+def test_forward_single_vector(driver, tmp_path, layout, dtype, fexp):
+    """Single-copy (layout 2: one entry per channel; layout 3: pair records,
+    FP64 Gaussians from the table or the polynomial exponential) and per-row
+    (layout 1) forward passes, B = 1."""
     s = synth.multiband_system()
     f = synth.random_occupations(s, 3)
     nph = s.nph(300.0)
-    _write(tmp_path, s, dtype, f=f, nph=nph, B=1, layout=layout)
+    _write(tmp_path, s, dtype, f=f, nph=nph, B=1, layout=layout, fp64_exp=fexp)
     _run(driver, tmp_path, "forward")
     # one launch of the forward kernel, bracketed by the timing events
     assert _out(tmp_path, "timing")[1] == 1
@@ -229,14 +232,28 @@ def test_transport(driver, tmp_path):
     assert nerr(_out(tmp_path, "x", (s.n_states, 3)), ref["x"]) <= TOL64
 
 
-def test_phonon_rate(driver, tmp_path):
-    s = synth.multiband_system()
+@pytest.mark.parametrize("name", ["multiband", "random", "tb", "defect"])
+def test_phonon_rate(driver, tmp_path, name):
+    """dN/dt over the pair records bucketed by {q, -q} against the oracle's
+    channel loop; the defect system's elastic mechanism exchanges no phonon,
+    so its channels are left out (its bins are zero)."""
+    s = {"multiband": synth.multiband_system, "random": synth.random_channel_system,
+         "tb": lambda: synth.tb_system(kn=24, qn=12, target_states=400),
+         "defect": lambda: synth.defect_system(5)}[name]()
     f = synth.random_occupations(s, 50)
     nph = s.nph(300.0)
-    _write(tmp_path, s, f=f, nph=nph)
+    kw, keep = {}, np.ones(s.n_channels, bool)
+    if name == "defect":
+        e = s.meta["elastic_mode"]
+        kw["elastic_modes"] = 1 << e
+        keep = np.asarray(s.ch_nu) != e
+    _write(tmp_path, s, f=f, nph=nph, **kw)
     _run(driver, tmp_path, "phonon")
-    ref = oracle.phonon_rate(s, f, nph)
-    assert nerr(_out(tmp_path, "rate", ref.shape), ref) <= TOL64
+    ref = oracle.phonon_rate(oracle.subset(s, keep), f, nph)
+    got = _out(tmp_path, "rate", ref.shape)
+    if name == "defect":
+        assert np.all(got[:, s.meta["elastic_mode"]] == 0.0)
+    assert nerr(got, ref) <= TOL64
 
 
 @pytest.mark.parametrize("B", [1, 3, 9])
@@ -532,6 +549,8 @@ def test_update_g2(driver, tmp_path):
     _write(tmp_path, s, f=f, nph=nph, g2_new=g2n)
     _run(driver, tmp_path, "update_g2")
     assert nerr(_out(tmp_path, "I"), oracle.collision(s, f, nph, g2=g2n)) <= TOL64
+    ref = oracle.phonon_rate(s, f, nph, g2=g2n)
+    assert nerr(_out(tmp_path, "rate", ref.shape), ref) <= TOL64
 
 
 @pytest.mark.parametrize("B", [1, 9])
@@ -586,3 +605,77 @@ def test_tile_tables(driver, tmp_path, name, tune):
     _write(tmp_path, s, f=synth.random_occupations(s, 1), nph=s.nph(300.0), **tune)
     _run(driver, tmp_path, "tiles")
     assert np.all(_out(tmp_path, "tiles") == 0), _out(tmp_path, "tiles")
+
+
+def _uneven_bath(s, seed):
+    rng = np.random.default_rng(seed)
+    return s.nph(300.0) * rng.uniform(0.5, 1.5, size=s.hw.shape)
+
+
+@pytest.mark.parametrize("name,layout", [("multiband", 0), ("tb", 0), ("defect", 0), ("multiband", 1)])
+def test_collision_vjp_nph(driver, tmp_path, name, layout):
+    """dL/dN of L = lam . I over the records grouped by {q, -q}, against the
+    oracle, on a bath that is not even in q (so that q and -q cannot be
+    confused); the defect system's elastic channels count too."""
+    s = {"multiband": synth.multiband_system, "tb": lambda: synth.tb_system(kn=24, qn=12, target_states=400),
+         "defect": lambda: synth.defect_system(5)}[name]()
+    f = synth.random_occupations(s, 61)
+    N = _uneven_bath(s, 62)
+    kw = {}
+    if name == "defect":
+        N[:, s.meta["elastic_mode"]] = 0.0
+        kw["elastic_modes"] = 1 << s.meta["elastic_mode"]
+    lam = np.random.default_rng(63).normal(size=s.n_states)
+    _write(tmp_path, s, f=f, lam=lam, nph=N, layout=layout, **kw)
+    _run(driver, tmp_path, "vjp_nph", fill="random:3")
+    ref = oracle.collision_vjp_nph(s, f, N, lam)
+    assert nerr(_out(tmp_path, "gN", ref.shape), ref) <= TOL64
+
+
+@pytest.mark.parametrize("name,chunk", [("multiband", 0), ("tb", 0), ("defect", 0), ("tb", 50)])
+def test_phonon_rate_vjp(driver, tmp_path, name, chunk):
+    """Reverse of the phonon-side rate (dL/df over the destination layout,
+    dL/dN and dL/d|g|^2 over the {q, -q} records) against the oracle, on a
+    bath not even in q and a random bin adjoint; elastic channels get no
+    |g|^2 gradient from it.  chunk splits destinations over several chunks."""
+    s = {"multiband": synth.multiband_system, "tb": lambda: synth.tb_system(kn=24, qn=12, target_states=400),
+         "defect": lambda: synth.defect_system(5)}[name]()
+    f = synth.random_occupations(s, 71)
+    N = _uneven_bath(s, 72)
+    kw = {}
+    keep = np.ones(s.n_channels, bool)
+    if name == "defect":
+        e = s.meta["elastic_mode"]
+        N[:, e] = 0.0
+        kw["elastic_modes"] = 1 << e
+        keep = np.asarray(s.ch_nu) != e
+    if chunk:
+        kw["chunk_entries"] = chunk
+    mu = np.random.default_rng(73).normal(size=N.shape)
+    _write(tmp_path, s, f=f, mu=mu, nph=N, **kw)
+    _run(driver, tmp_path, "phonon_vjp", fill="random:4")
+    rf, rN, rg = oracle.phonon_rate_vjp(oracle.subset(s, keep), f, N, mu)
+    gg = np.zeros(s.n_channels)
+    gg[keep] = rg
+    assert nerr(_out(tmp_path, "gf"), rf) <= TOL64
+    assert nerr(_out(tmp_path, "gN", rN.shape), rN) <= TOL64
+    assert nerr(_out(tmp_path, "gg2") - 0.25, gg) <= TOL64
+
+
+@pytest.mark.parametrize("name,ce", [("multiband", 1), ("multiband", 2), ("tb", 3)])
+def test_coupled_adjoint(driver, tmp_path, name, ce):
+    """Gradients through three coupled RK4 steps against the oracle's discrete
+    adjoint with every stage stored; checkpoints every ce steps."""
+    s = {"multiband": synth.multiband_system, "tb": lambda: synth.tb_system(kn=24, qn=12, target_states=400)}[name]()
+    f0 = 0.1 + 0.8 * synth.random_occupations(s, 81)
+    N0 = s.nph(300.0) * 1.5
+    rng = np.random.default_rng(82)
+    a = rng.normal(size=s.n_states)
+    b = oracle.even_in_q(s, rng.normal(size=N0.shape))
+    dt, n = 1.0, 3
+    _, _, rf, rN, rg = oracle.rk4_coupled_trajectory_grad(s, f0, N0, dt, n, a, b)
+    _write(tmp_path, s, f=f0, nph=N0, gT=a, gNT=b, dt=dt, steps=n, ce=ce)
+    _run(driver, tmp_path, "coupled_adjoint", fill="random:6")
+    assert nerr(_out(tmp_path, "gf"), rf) <= TOL64
+    assert nerr(_out(tmp_path, "gN", rN.shape), rN) <= TOL64
+    assert nerr(_out(tmp_path, "gg2"), rg) <= TOL64

@@ -158,9 +158,10 @@ def test_split_segments_and_launch_shapes(E, tuning):
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("name", ["parabolic8_random", "multiband", "random_order", "tb24"])
 def test_single_copy_and_duplicated_layouts(E, name, dtype):
-    """The B = 1 forward pass in both layouts (each channel evaluated in both of
-    its rows, or once with fixed-point partner sums) against the oracle; the
-    single-copy result is bitwise reproducible, also with rows split in chunks."""
+    """The B = 1 forward pass in every layout (each channel evaluated in both of
+    its rows; once with fixed-point partner sums, one entry per channel; once
+    over pair records, where the plan has them) against the oracle; each
+    result is bitwise reproducible, also with rows split in chunks."""
     mk, occ = SYSTEMS[name]
     s = mk()
     f = np.clip(occ(s), 0, 1)
@@ -180,13 +181,16 @@ def test_single_copy_and_duplicated_layouts(E, name, dtype):
     plan = E.build_channels(s, dtype=dtype, device=0)
     say(f"layouts {dtype} {name}")
     got = {}
-    for layout, chunk in ((1, -1), (2, -1), (2, 37), (1, 37)):
-        E.set_tuning(plan, layout=layout, chunk_entries=65536 if chunk < 0 else chunk)
+    cases = [(1, -1, 0), (2, -1, 0), (2, 37, 0), (1, 37, 0)]
+    if E.plan_info(plan)["pair_records"] > 0:
+        cases += [(3, -1, 1), (3, 5, 1), (3, -1, 2)]
+    for layout, chunk, fexp in cases:
+        E.set_tuning(plan, layout=layout, chunk_entries=65536 if chunk < 0 else chunk, fp64_exp=fexp)
         a = host(E.collision_integral(plan, dev(f, tdt), dev(nph, tdt)))
         b = host(E.collision_integral(plan, dev(f, tdt), dev(nph, tdt)))
-        assert np.array_equal(a, b), (layout, chunk)
-        assert nerr(a, ref, scale) <= tol, (layout, chunk)
-        got[(layout, chunk)] = a
+        assert np.array_equal(a, b), (layout, chunk, fexp)
+        assert nerr(a, ref, scale) <= tol, (layout, chunk, fexp)
+        got[(layout, chunk, fexp)] = a
     plan.close()
 
 
@@ -713,6 +717,140 @@ def test_rt_step_coupled_matches_oracle(E, name, dtype):
     plan.close()
 
 
+def _uneven_bath(s, seed):
+    """A positive phonon table that is not even in q: a q / -q mix-up in a
+    reverse mode changes the result."""
+    return s.nph(300.0) * np.random.default_rng(seed).uniform(0.5, 1.5, size=s.hw.shape)
+
+
+@pytest.mark.parametrize("name,dtype", [("multiband", "f64"), ("tb24", "f64"), ("multiband", "f32")])
+def test_collision_vjp_nph_matches_oracle(E, name, dtype):
+    s = PH_SYSTEMS[name]()
+    f = synth.random_occupations(s, 61)
+    N = _uneven_bath(s, 62)
+    lam = np.random.default_rng(63).normal(size=s.n_states)
+    r, tdt, tol = s, torch.float64, TOL64
+    if dtype == "f32":
+        f, N, lam = (x.astype(np.float32).astype(np.float64) for x in (f, N, lam))
+        r, tdt, tol = round32(s), torch.float32, TOL32
+    plan = E.build_channels(s, dtype=dtype, device=0)
+    say(f"collision vjp nph {name} {dtype}")
+    got = host(E.collision_vjp_nph(plan, dev(f, tdt), dev(N, tdt), dev(lam, tdt)))
+    plan.close()
+    assert nerr(got, oracle.collision_vjp_nph(r, f, N, lam)) <= tol
+
+
+@pytest.mark.parametrize("name,dtype", [("multiband", "f64"), ("tb24", "f64"), ("multiband", "f32")])
+def test_phonon_rate_vjp_matches_oracle(E, name, dtype):
+    s = PH_SYSTEMS[name]()
+    f = synth.random_occupations(s, 71)
+    N = _uneven_bath(s, 72)
+    mu = np.random.default_rng(73).normal(size=N.shape)
+    r, tdt, tol = s, torch.float64, TOL64
+    if dtype == "f32":
+        f, N, mu = (x.astype(np.float32).astype(np.float64) for x in (f, N, mu))
+        r, tdt, tol = round32(s), torch.float32, TOL32
+    plan = E.build_channels(s, dtype=dtype, device=0)
+    say(f"phonon rate vjp {name} {dtype}")
+    gf, gN, gg = E.phonon_rate_vjp(plan, dev(f, tdt), dev(N, tdt), dev(mu, tdt), gg2=True)
+    plan.close()
+    rf, rN, rg = oracle.phonon_rate_vjp(r, f, N, mu)
+    assert nerr(host(gf), rf) <= tol
+    assert nerr(host(gN), rN) <= tol
+    assert nerr(host(gg), rg) <= tol
+
+
+@pytest.mark.parametrize("name,dtype,ce", [("multiband", "f64", 1), ("multiband", "f64", 2), ("tb24", "f64", 3),
+                                           ("multiband", "f32", 2)])
+def test_rt_adjoint_coupled_matches_oracle(E, name, dtype, ce):
+    """Gradients with respect to f0, N0 and |g|^2 through three coupled RK4
+    steps against the oracle's discrete adjoint with every stage stored."""
+    s = PH_SYSTEMS[name]()
+    f0 = 0.1 + 0.8 * synth.random_occupations(s, 81)
+    N0 = s.nph(300.0) * 1.5
+    rng = np.random.default_rng(82)
+    a = rng.normal(size=s.n_states)
+    b = oracle.even_in_q(s, rng.normal(size=N0.shape))
+    dt, n = 1.0, 3
+    r, tdt, tol = s, torch.float64, TOL64
+    if dtype == "f32":
+        f0, N0, a, b = (x.astype(np.float32).astype(np.float64) for x in (f0, N0, a, b))
+        r, tdt, tol = round32(s), torch.float32, TOL32
+    _, _, rf, rN, rg = oracle.rk4_coupled_trajectory_grad(r, f0, N0, dt, n, a, b)
+    plan = E.build_channels(s, dtype=dtype, device=0)
+    say(f"coupled adjoint {name} {dtype} ce={ce}")
+    gf, gN, gg = E.rt_adjoint_coupled(plan, dev(f0, tdt), dev(N0, tdt), dt, n, ce, dev(a, tdt), dev(b, tdt),
+                                      gg2=True)
+    plan.close()
+    assert nerr(host(gf), rf) <= tol
+    assert nerr(host(gN), rN) <= tol
+    assert nerr(host(gg), rg) <= tol
+
+
+def test_coupled_autograd(E):
+    """CoupledSolve: the loss's gradients with respect to f0, N0 and |g|^2 from
+    torch autograd equal the oracle's discrete adjoint; and the nph gradient of
+    CollisionIntegral equals the oracle's."""
+    from paper_2511_03683_amd.autograd import collision, coupled_solve
+    s = synth.multiband_system()
+    plan = E.build_channels(s, device=0)
+    f0 = dev(0.1 + 0.8 * synth.random_occupations(s, 91)).requires_grad_(True)
+    N0 = dev(s.nph(300.0) * 1.5).requires_grad_(True)
+    g2 = dev(s.g2).requires_grad_(True)
+    eps = dev(s.eps)
+    say("coupled autograd")
+    fT, NT = coupled_solve(f0, N0, g2, plan, 1.0, 3, 2)
+    L = (eps * fT).sum() / fT.sum() + 0.01 * NT.sum()
+    L.backward()
+    fTh = host(fT)
+    gT = (s.eps * fTh.sum() - s.eps @ fTh) / fTh.sum() ** 2
+    gNT = np.full(s.hw.shape, 0.01)
+    _, _, rf, rN, rg = oracle.rk4_coupled_trajectory_grad(s, host(f0), host(N0), 1.0, 3, gT, gNT)
+    assert nerr(host(f0.grad), rf) <= TOL64
+    assert nerr(host(N0.grad), rN) <= TOL64
+    assert nerr(host(g2.grad), rg) <= TOL64
+    f = dev(synth.random_occupations(s, 92))
+    N = dev(_uneven_bath(s, 93)).requires_grad_(True)
+    lam = np.random.default_rng(94).normal(size=s.n_states)
+    (collision(f, dev(s.g2), plan, N) * dev(lam)).sum().backward()
+    assert nerr(host(N.grad), oracle.collision_vjp_nph(s, host(f), host(N), lam)) <= TOL64
+    plan.close()
+
+
+def test_full_size_coupled_adjoint_finite_differences(E, c2):
+    """dL/dN0 and dL/df0 through 5 coupled RK4 steps of 1 fs of the full-size
+    system (L = mean carrier energy plus the mean phonon occupation at the
+    end), against central differences along a random even direction of N0
+    and a random direction of f0."""
+    s = c2
+    rng = np.random.default_rng(95)
+    f0 = dev(synth.pulse_occupations(s, center=0.2))
+    N0 = dev(s.nph(300.0))
+    eps = dev(s.eps)
+    dt, n = 1.0, 5
+    plan = E.build_channels(s, device=0)
+
+    def loss(ff, NN):
+        ff, NN = ff.clone(), NN.clone()
+        E.rt_step_coupled(plan, ff, NN, dt, n)
+        torch.cuda.synchronize()
+        return float((eps * ff).sum() / ff.sum() + NN.mean()), ff, NN
+
+    say("full-size coupled adjoint vs finite differences")
+    L0, fT, NT = loss(f0, N0)
+    gT = ((eps * fT.sum() - (eps * fT).sum()) / fT.sum() ** 2).contiguous()
+    gNT = torch.full_like(NT, 1.0 / NT.numel())
+    gf, gN, _ = E.rt_adjoint_coupled(plan, f0, N0, dt, n, 2, gT, gNT)
+    V = dev(oracle.even_in_q(s, rng.normal(size=s.hw.shape) * s.nph(300.0)))
+    h = 1e-4
+    fd = (loss(f0, N0 + h * V)[0] - loss(f0, N0 - h * V)[0]) / (2 * h)
+    assert fd == pytest.approx(float((gN * V).sum()), rel=1e-5)
+    v = dev(rng.normal(size=s.n_states) * 1e-2)
+    fd = (loss(f0 + h * v, N0)[0] - loss(f0 - h * v, N0)[0]) / (2 * h)
+    assert fd == pytest.approx(float((gf * v).sum()), rel=1e-5)
+    plan.close()
+
+
 def test_autograd_function(E):
     from paper_2511_03683_amd.autograd import collision
     s = synth.multiband_system()
@@ -1000,13 +1138,21 @@ def c2():
     return synth.tb_system()
 
 
+def full_norm(r, f, nph, ref, dtype, args=None):
+    """Norm of the full-vector error: max|I_ref| (FP64); for FP32
+    max(max|I_ref|, 1e-2 max(in, out)) over every state, from the oracle
+    (reading 15: a near-equilibrium vector is judged against its gross rates)."""
+    if dtype == "f64":
+        return np.abs(ref).max()
+    rin, rout = oracle.collision_inout_threads(r, f, nph, args=args)
+    return max(np.abs(ref).max(), 1e-2 * max(rin.max(), rout.max()))
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_full_size_sampled_parity(E, c2, dtype):
+def test_full_size_parity(E, c2, dtype):
     """The 100^3/50^3, ~2e8-channel system in the launch configuration the
-    benchmark times; the oracle evaluates 48 sampled destinations, and the
-    error is normalised by the oracle's values there (FP32: by their gross
-    rates, as on the small systems).  Every other output is checked against
-    a per-state bound."""
+    benchmark times, every output against the oracle's channel loop over the
+    whole list (run on all host threads)."""
     s = c2
     rng = np.random.default_rng(17)
     f = np.clip(synth.fermi_dirac(s.eps, 0.05, 300.0) * (0.8 + 0.4 * rng.uniform(size=s.n_states)), 0, 1)
@@ -1019,22 +1165,21 @@ def test_full_size_sampled_parity(E, c2, dtype):
     plan = E.build_channels(s, dtype=dtype, device=0)
     I = host(E.collision_integral(plan, dev(f, tdt), dev(nph, tdt)))
     plan.close()
-    dests = rng.choice(s.n_states, 48, replace=False)
-    r = oracle.subset(s if dtype == "f64" else round32(s), incident(s, dests))
-    ref = oracle.collision(r, f, nph)
-    plausible(I, rate_bound(s, nph))
+    r = s if dtype == "f64" else round32(s)
+    a = oracle._Args(r, nph)
+    ref = oracle.collision_threads(r, f, nph, args=a)
+    say(f"full-size {dtype} oracle done")
+    assert np.isfinite(I).all()
     if dtype == "f64":
         assert abs(I.sum()) <= 1e-10 * np.abs(I).sum()
-        assert nerr(I[dests], ref[dests]) <= TOL64
-    else:
-        assert nerr(I[dests], ref[dests], gross_scale(r, f, nph, ref, dests)) <= TOL32
+    assert nerr(I, ref, full_norm(r, f, nph, ref, dtype, args=a)) <= (TOL64 if dtype == "f64" else TOL32)
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_full_size_batched_sampled_parity(E, c2, dtype):
+def test_full_size_batched_parity(E, c2, dtype):
     """B = 64 vectors of the full-size system in one pass, as the benchmark
-    times it; two columns checked on 32 sampled destinations, normalised by
-    the oracle there; every column within the per-state bound."""
+    times it; two columns checked in full against the oracle's channel loop
+    over the whole list; every column within the per-state bound."""
     s = c2
     rng = np.random.default_rng(23)
     B = 64
@@ -1051,14 +1196,12 @@ def test_full_size_batched_sampled_parity(E, c2, dtype):
     I = host(E.collision_integral(plan, dev(F, tdt), dev(nph, tdt)))
     plan.close()
     plausible(I, rate_bound(s, nph)[None, :])
-    dests = rng.choice(s.n_states, 32, replace=False)
-    r = oracle.subset(s if dtype == "f64" else round32(s), incident(s, dests))
+    r = s if dtype == "f64" else round32(s)
+    a = oracle._Args(r, nph)
     for b in (7, 63):
-        ref = oracle.collision(r, F[b], nph)
-        if dtype == "f64":
-            assert nerr(I[b][dests], ref[dests]) <= TOL64, b
-        else:
-            assert nerr(I[b][dests], ref[dests], gross_scale(r, F[b], nph, ref, dests)) <= TOL32, b
+        ref = oracle.collision_threads(r, F[b], nph, args=a)
+        err = nerr(I[b], ref, full_norm(r, F[b], nph, ref, dtype, args=a))
+        assert err <= (TOL64 if dtype == "f64" else TOL32), b
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
@@ -1158,6 +1301,45 @@ def test_full_size_phonon_rate_sampled_parity(E, c2):
     assert nerr(got[bins], ref[bins]) <= TOL64
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_full_size_transport_iteration(E, c2, dtype):
+    """One transport iteration of the full-size system in the launch
+    configuration the benchmark times: x after k + 1 iterations at 32 sampled
+    destinations against the oracle's update x_d = tau_d (v_d df0/de +
+    sum_p W_dp x_p) of the GPU's x after k iterations (tau and W of a
+    destination need only its incident channels), and the mobility against
+    the host sum over the GPU's x."""
+    s = c2
+    T = 300.0
+    f0 = synth.fermi_dirac(s.eps, -0.1, T)
+    nph = s.nph(T)
+    vel = np.asarray(s.vel, np.float64)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    r = s
+    if dtype == "f32":
+        f0 = f0.astype(np.float32).astype(np.float64)
+        nph = nph.astype(np.float32).astype(np.float64)
+        vel = vel.astype(np.float32).astype(np.float64)
+        r = round32(s)
+    say(f"full-size transport iteration {dtype}")
+    plan = E.build_channels(s, dtype=dtype, device=0)
+    k = 3
+    outs = [E.iterate_transport(plan, dev(f0, tdt), dev(vel, tdt), T, dev(nph, tdt), tol=0.0,
+                                max_iter=n, want_x=True) for n in (k, k + 1)]
+    plan.close()
+    xk, xk1 = host(outs[0]["x"]), host(outs[1]["x"])
+    rng = np.random.default_rng(53)
+    dests = rng.choice(s.n_states, 32, replace=False)
+    sub = oracle.subset(r, incident(s, dests))
+    tau_inv, Wij, Wji = oracle.transport_coeffs(sub, f0, nph)
+    b = vel * oracle.dfde_fd(f0, T)[:, None]
+    ref = (b + oracle.transport_apply_W(sub, Wij, Wji, xk))[dests] / tau_inv[dests, None]
+    tol = TOL64 if dtype == "f64" else TOL32
+    assert np.isfinite(xk1).all()
+    assert nerr(xk1[dests], ref) <= tol
+    assert nerr(outs[1]["mu"], oracle.mobility_cm2(vel, xk1, f0)) <= tol
+
+
 # ------------------------------------------------------------------ uneven batch
 @pytest.fixture(scope="module")
 def grouped():
@@ -1167,7 +1349,8 @@ def grouped():
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_grouped_uneven_systems_one_launch(E, grouped, dtype):
     """16 systems of 1e5 .. 1e7 channels concatenated into one problem and
-    evaluated by one launch; sampled states of every system against the oracle."""
+    evaluated by one launch; every system's output against the oracle's
+    channel loop, each normalised by its own vector (normwise per system)."""
     s = grouped
     rng = np.random.default_rng(31)
     f = np.clip(synth.fermi_dirac(s.eps, 0.05, 300.0) * (0.8 + 0.4 * rng.uniform(size=s.n_states)), 0, 1)
@@ -1181,21 +1364,19 @@ def test_grouped_uneven_systems_one_launch(E, grouped, dtype):
     I = host(E.collision_integral(plan, dev(f, tdt), dev(nph, tdt)))
     plan.close()
     offs = s.meta["offsets"]
-    mask = np.zeros(s.n_states, bool)
-    for m in range(len(offs) - 1):
-        mask[rng.choice(np.arange(offs[m], offs[m + 1]), 3, replace=False)] = True
     r = s if dtype == "f64" else round32(s)
-    plausible(I, rate_bound(s, nph))
-    ref = oracle.collision(r, f, nph, mask=mask)
+    a = oracle._Args(r, nph)
+    ref = oracle.collision_threads(r, f, nph, args=a)
     if dtype == "f32":
-        rin, rout = oracle.collision_inout(r, f, nph)
+        rin, rout = oracle.collision_inout_threads(r, f, nph, args=a)
+    assert np.isfinite(I).all()
     for m in range(len(offs) - 1):
-        rows = np.arange(offs[m], offs[m + 1])[mask[offs[m]:offs[m + 1]]]
+        sl = slice(offs[m], offs[m + 1])
         if dtype == "f64":
-            assert nerr(I[rows], ref[rows]) <= TOL64, m
+            assert nerr(I[sl], ref[sl]) <= TOL64, m
         else:
-            scale = max(np.abs(ref[rows]).max(), 1e-2 * max(rin[rows].max(), rout[rows].max()))
-            assert nerr(I[rows], ref[rows], scale) <= TOL32, m
+            scale = max(np.abs(ref[sl]).max(), 1e-2 * max(rin[sl].max(), rout[sl].max()))
+            assert nerr(I[sl], ref[sl], scale) <= TOL32, m
 
 
 # ------------------------------------------------------------------ gradients
@@ -1220,14 +1401,15 @@ def test_rt_adjoint_cpu_reference_512k(E):
 
 
 def test_full_size_rt_adjoint_finite_differences(E, c2):
-    """dL/d|g|^2 through 20 RK4 steps (checkpoint every 5) of the full-size
-    system, L = mean carrier energy at the end, against central differences
-    on the 32 entries of largest |dL/dg2| and along one random direction."""
+    """dL/d|g|^2 through 200 RK4 steps of 1 fs (checkpoint every 20) of the
+    full-size system, the pulse inside the energy window, L = mean carrier
+    energy at 200 fs, against central differences on the 32 entries of
+    largest |dL/dg2| and along one random direction."""
     s = c2
     nph = dev(s.nph(300.0))
     eps = dev(s.eps)
     f0 = dev(synth.pulse_occupations(s, center=0.2))
-    dt, n = 1.0, 20
+    dt, n = 1.0, 200
     plan = E.build_channels(s, device=0)
     g2 = dev(s.g2)
 
@@ -1241,10 +1423,12 @@ def test_full_size_rt_adjoint_finite_differences(E, c2):
     say("full-size adjoint vs finite differences")
     L0, fT = loss(g2)
     gT = ((eps * fT.sum() - (eps * fT).sum()) / fT.sum() ** 2).contiguous()
-    _, gg = E.rt_adjoint(plan, f0, nph, dt, n, 5, gT, want_f=False, gg2=True)
+    _, gg = E.rt_adjoint(plan, f0, nph, dt, n, 20, gT, want_f=False, gg2=True)
     gg = host(gg)
     top = np.argsort(-np.abs(gg))[:32]
-    for c in top:
+    for k, c in enumerate(top):
+        if k % 8 == 0:
+            say(f"finite differences {k} / 32")
         h = 1e-2 * s.g2[c]
         gp = g2.clone()
         gp[c] += h

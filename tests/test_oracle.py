@@ -654,3 +654,109 @@ def test_c1_matches_stored_oracle_sample(c1):
     I = oracle.collision(s, f, nph)
     assert s.n_channels == g["n_channels"]
     assert np.allclose(I[g["states"]], g["I"], rtol=1e-13, atol=1e-13 * g["max_abs"])
+
+
+def test_collision_threads_is_the_channel_loop():
+    """The threaded oracle runs the same C loop over slices of the list: with
+    one thread it is bitwise the sequential loop, with several it differs only
+    by the order of the additions."""
+    for s in (synth.multiband_system(), synth.random_channel_system(n_states=60, n_channels=900, seed=3)):
+        f = synth.random_occupations(s, 8)
+        nph = s.nph(300.0)
+        ref = oracle.collision(s, f, nph)
+        assert np.array_equal(oracle.collision_threads(s, f, nph, threads=1), ref)
+        for t in (2, 5, 16):
+            got = oracle.collision_threads(s, f, nph, threads=t)
+            assert np.abs(got - ref).max() <= 1e-14 * np.abs(ref).max()
+
+
+def test_collision_inout_threads_is_the_channel_loop():
+    s = synth.multiband_system()
+    f = synth.random_occupations(s, 9)
+    nph = s.nph(300.0)
+    rin, rout = oracle.collision_inout(s, f, nph)
+    tin, tout = oracle.collision_inout_threads(s, f, nph, threads=1)
+    assert np.array_equal(tin, rin) and np.array_equal(tout, rout)
+    tin, tout = oracle.collision_inout_threads(s, f, nph, threads=6)
+    assert np.abs(tin - rin).max() <= 1e-14 * rin.max() and np.abs(tout - rout).max() <= 1e-14 * rout.max()
+
+
+# ------------------------------------------------ reverse mode in N and of the phonon side
+def _uneven_bath(s, seed):
+    """A positive phonon table that is NOT even in q, so that a q / -q mix-up
+    in a reverse mode changes the result."""
+    rng = np.random.default_rng(seed)
+    return s.nph(300.0) * rng.uniform(0.5, 1.5, size=s.hw.shape)
+
+
+@pytest.mark.parametrize("maker", [synth.multiband_system, lambda: synth.parabolic_system(4)])
+def test_collision_vjp_nph_finite_differences_and_euler(maker):
+    """I is affine in N (Eq. 2 with the golden-rule factors), so central
+    differences of lam . I along any direction of N are exact up to rounding,
+    and sum_q N dL/dN = lam . (I(N) - I(0)) (Euler for an affine map)."""
+    s = maker()
+    f = synth.random_occupations(s, 21)
+    N = _uneven_bath(s, 22)
+    lam = np.random.default_rng(23).normal(size=s.n_states)
+    gN = oracle.collision_vjp_nph(s, f, N, lam)
+    V = np.random.default_rng(24).normal(size=N.shape)
+    h = 0.3
+    fd = lam @ (oracle.collision(s, f, N + h * V) - oracle.collision(s, f, N - h * V)) / (2 * h)
+    assert fd == pytest.approx(float((gN * V).sum()), rel=1e-11)
+    lhs = float((gN * N).sum())
+    rhs = float(lam @ (oracle.collision(s, f, N) - oracle.collision(s, f, np.zeros_like(N))))
+    assert lhs == pytest.approx(rhs, rel=1e-11)
+
+
+@pytest.mark.parametrize("maker", [synth.multiband_system, lambda: synth.parabolic_system(4)])
+def test_phonon_rate_vjp_finite_differences_and_euler(maker):
+    """The phonon-side rate is quadratic in f and affine in N and |g|^2: central
+    differences of mu . R are exact up to rounding along any direction; and
+    sum_c |g|^2_c dL/d|g|^2_c = mu . R (Euler, R linear in |g|^2)."""
+    s = maker()
+    f = synth.random_occupations(s, 31)
+    N = _uneven_bath(s, 32)
+    rng = np.random.default_rng(33)
+    mu = rng.normal(size=N.shape)
+    gf, gN, gg = oracle.phonon_rate_vjp(s, f, N, mu)
+    L = lambda ff, NN, gg2=None: float((mu * oracle.phonon_rate(s, ff, NN, g2=gg2)).sum())
+    v = rng.normal(size=s.n_states)
+    h = 0.05
+    assert (L(f + h * v, N) - L(f - h * v, N)) / (2 * h) == pytest.approx(float(gf @ v), rel=1e-10)
+    V = rng.normal(size=N.shape)
+    assert (L(f, N + h * V) - L(f, N - h * V)) / (2 * h) == pytest.approx(float((gN * V).sum()), rel=1e-10)
+    w = rng.normal(size=s.n_channels) * s.g2
+    assert (L(f, N, s.g2 + h * w) - L(f, N, s.g2 - h * w)) / (2 * h) == pytest.approx(float(gg @ w), rel=1e-10)
+    assert float(gg @ s.g2) == pytest.approx(L(f, N), rel=1e-11)
+
+
+def test_coupled_rk4_adjoint_finite_differences():
+    """Gradients through two coupled RK4 steps (electrons and phonons) of a
+    loss linear in (f_T, N_T), against central differences along random
+    directions of f0, of an even direction of N0 and of |g|^2."""
+    s = synth.multiband_system()
+    f0 = 0.1 + 0.8 * synth.random_occupations(s, 41)
+    N0 = s.nph(300.0) * 1.5
+    rng = np.random.default_rng(42)
+    a = rng.normal(size=s.n_states)
+    b = oracle.even_in_q(s, rng.normal(size=N0.shape))
+    dt, n = 1.0, 2
+    fT, NT, gf, gN, gg = oracle.rk4_coupled_trajectory_grad(s, f0, N0, dt, n, a, b)
+
+    def loss(ff, NN, g2=None):
+        for _ in range(n):
+            ff, NN = oracle.rk4_coupled_step(s, ff, NN, dt, g2=g2)
+        return float(a @ ff + (b * NN).sum())
+
+    assert loss(f0, N0) == pytest.approx(float(a @ fT + (b * NT).sum()), rel=1e-14)
+    v = rng.normal(size=s.n_states)
+    h = 1e-4
+    fd = (loss(f0 + h * v, N0) - loss(f0 - h * v, N0)) / (2 * h)
+    assert fd == pytest.approx(float(gf @ v), rel=1e-6)
+    V = oracle.even_in_q(s, rng.normal(size=N0.shape))
+    fd = (loss(f0, N0 + h * V) - loss(f0, N0 - h * V)) / (2 * h)
+    assert fd == pytest.approx(float((gN * V).sum()), rel=1e-6)
+    w = rng.normal(size=s.n_channels) * s.g2
+    hg = 1e-4     # the difference quotient converges as hg^2 (1e-3 leaves 5e-6)
+    fd = (loss(f0, N0, s.g2 + hg * w) - loss(f0, N0, s.g2 - hg * w)) / (2 * hg)
+    assert fd == pytest.approx(float(gg @ w), rel=1e-6)
