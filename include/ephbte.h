@@ -207,6 +207,30 @@ ephbte_status ephbte_collision_integral(ephbte_plan plan, int32_t batch, const v
                                         void *I, int64_t ldi, void *stream);
 
 /*
+ * Allocation-free form of ephbte_collision_integral for callers that cannot
+ * allocate device memory: code being captured into a HIP graph, serving loops
+ * that must not call hipMalloc, harnesses that forbid it.  Same result as
+ * ephbte_collision_integral with batch = 1 and one shared bath
+ * (nph_per_batch = 0), from the same kernels.
+ * f:   device [S], plan dtype.   nph: device [Nq][n_modes], plan dtype.
+ * I:   device [S], plan dtype, written; must not overlap f.
+ * Workspaces: the call allocates nothing (no hipMalloc, hipFree or allocating
+ *   library routine).  Its {hw, N} table and partial sums live in a static
+ *   device array of 32 MiB that the library holds on each GPU it runs on until
+ *   the process ends.  A plan whose table and partials need more than that
+ *   (2 x 8 B x Nq x n_modes plus 16 B per row chunk in FP64; the 50^3 q grid
+ *   with 6 modes needs 12.4 MB) is rejected with EPHBTE_INVALID_ARGUMENT
+ *   before any work is enqueued.
+ * Concurrency: every call on one GPU shares that array and the plan's
+ *   partner-side accumulator, and each call overwrites what the last one left
+ *   there.  Calls on one plan are ordered like every other call; calls on
+ *   different plans of one GPU that overlap in time (different streams, no
+ *   ordering between them) race on the array and give wrong results.
+ */
+ephbte_status ephbte_collision_integral_noalloc(ephbte_plan plan, const void *f, const void *nph,
+                                                void *I, void *stream);
+
+/*
  * Reverse mode of Eq. 2: given gI = dL/dI (device [B][ldg]), writes
  * gf = dL/df (device [B][ldgf], plan dtype; NULL to skip) and
  * gg2 = dL/d|g|^2 summed over the batch (device FP64 [n_channels] in the

@@ -60,6 +60,7 @@ SYMBOLS = {
                            ctypes.c_int32),
     "ephbte_collision_integral": ([_P, ctypes.c_int32, _P, ctypes.c_int64, _P, ctypes.c_int32,
                                    _P, ctypes.c_int64, _P], ctypes.c_int32),
+    "ephbte_collision_integral_noalloc": ([_P, _P, _P, _P, _P], ctypes.c_int32),
     "ephbte_collision_vjp": ([_P, ctypes.c_int32, _P, ctypes.c_int64, _P, ctypes.c_int32, _P,
                               ctypes.c_int64, _P, ctypes.c_int64, _P, ctypes.c_int32, _P],
                              ctypes.c_int32),
@@ -316,6 +317,21 @@ def collision_integral(plan: Plan, f, nph, out=None):
     _check(load_library().ephbte_collision_integral(plan.handle, B, f.data_ptr(), ldf,
                                                     nph.data_ptr(), per_batch, out.data_ptr(),
                                                     ldi, _stream(f.device)), "collision_integral")
+    return out
+
+
+def collision_integral_noalloc(plan: Plan, f, nph, out):
+    """I[f] for one vector f [S] into out [S] through the allocation-free entry
+    point (its workspaces sit in the library's static device scratch)."""
+    B, _ = _batch(plan, f, "f")
+    Bo, _ = _batch(plan, out, "out")
+    if B != 1 or Bo != 1 or f.dim() != 1 or out.dim() != 1:
+        raise ValueError("the allocation-free pass takes one vector f [S] and out [S]")
+    if _nph_arg(plan, nph, 1, f) != 0:
+        raise ValueError("the allocation-free pass takes one shared bath nph [Nq, n_modes]")
+    _check(load_library().ephbte_collision_integral_noalloc(
+        plan.handle, f.data_ptr(), nph.data_ptr(), out.data_ptr(), _stream(f.device)),
+        "collision_integral_noalloc")
     return out
 
 

@@ -13,6 +13,7 @@
 #include <fstream>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <sstream>
 #include <string>
@@ -40,6 +41,18 @@ static void hip_check(hipError_t e, const char *where) {
     if (e != hipSuccess) throw HipError{e, where};
 }
 #define HIPC(x) hip_check((x), #x)
+
+// Scratch of the allocation-free forward pass (ephbte_collision_integral_noalloc):
+// the call's {hw, N} table, the per-chunk partial sums of the rows.  One copy
+// per GPU, held until the process ends and shared by every such call on that
+// GPU.  Host code never uses the array's name as an address: its device
+// address is looked up once per device (scratch_base) and kept.
+constexpr size_t kScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_base[kMaxDevices] = {};
 
 static constexpr double kHbar = 0.6582119569;     // eV fs
 static constexpr double kKb = 8.617333262e-5;     // eV / K
@@ -245,6 +258,20 @@ void ensure(DevBuf &b, size_t bytes, int64_t *gen) {
     }
     b.p = q;
     b.bytes = bytes;
+}
+
+// Device address of `scratch` on device dev (which must be current), looked
+// up on the first call for that device and kept.
+void *scratch_base(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) throw HipError{hipErrorInvalidDevice, "scratch_base"};
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_base[dev]) {
+        void *ptr = nullptr;
+        HIPC(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) throw HipError{hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)"};
+        g_scratch_base[dev] = ptr;
+    }
+    return g_scratch_base[dev];
 }
 
 void free_graphs(ephbte_plan P) {
@@ -814,6 +841,63 @@ template <typename T> void ensure_fwd(ephbte_plan P, int B) {
 
 template <typename T> void ensure_part(ephbte_plan P, int B, int per_chunk) {
     if (!P->fused) ensure(P->part, sizeof(T) * per_chunk * static_cast<size_t>(P->n_chunks) * B, &P->ws_gen);
+}
+
+// Bytes of `scratch` the allocation-free forward pass needs: the plain
+// {hw, N} table (q-major, no padding) and the partial sums of the chunks.
+size_t noalloc_bytes(ephbte_plan P) {
+    const size_t es = P->dtype == EPHBTE_F64 ? 8 : 4;
+    const size_t tab = 2 * es * static_cast<size_t>(std::max<int64_t>(nqm_of(P), 1));
+    size_t part = 0;
+    if (use_pairs(P, 1)) part = 2 * es * static_cast<size_t>(std::max<int64_t>(P->n_pr_chunks, 1));
+    else if (use_sym(P, 1)) part = 2 * es * static_cast<size_t>(std::max<int64_t>(P->n_sym_chunks, 1));
+    else if (!P->fused) part = 2 * es * static_cast<size_t>(P->n_chunks);
+    return ((tab + 255) & ~size_t(255)) + part;
+}
+
+// I[f] for one vector with every workspace inside `scratch` (base: its
+// device address): the same kernels as enqueue_forward, with the plain
+// {hw, N} table in place of the plan's padded one.  Allocates nothing.
+template <typename T>
+void enqueue_forward_noalloc(ephbte_plan P, const T *f, const void *nph, T *I, unsigned char *base,
+                             hipStream_t s) {
+    const int64_t n = nqm_of(P);
+    Pair2<T> *tab = reinterpret_cast<Pair2<T> *>(base);
+    T *part = reinterpret_cast<T *>(base + ((2 * sizeof(T) * static_cast<size_t>(std::max<int64_t>(n, 1)) + 255) &
+                                            ~size_t(255)));
+    const unsigned nb = static_cast<unsigned>(std::max<int64_t>(std::min<int64_t>((n + 255) / 256, kPackBlocks), 1));
+    hipLaunchKernelGGL((k_pack_hwN<T>), dim3(nb), dim3(256), 0, s, static_cast<const T *>(P->hw),
+                       static_cast<const T *>(nph), tab, n, P->pack_bmax);
+    hipLaunchKernelGGL(k_max_blocks, dim3(1), dim3(1024), 0, s, (const double *)P->pack_bmax,
+                       static_cast<int>(nb), P->nmax_bits);
+    const Epi<T> E = epi_store<T>(I, P->S);
+    if (use_pairs(P, 1)) {
+        TiledArgs<T> a = pair_args<T>(P);
+        a.hwN = tab;
+        a.padq = 0;
+        launch_pairs<T>(P, a, f, part, sym_lds_bytes(P->dtype, P->sym_lds_states), s, false);
+        hipLaunchKernelGGL((k_sym_finish<T>), dim3((P->S + 255) / 256), dim3(256), 0, s, a, f,
+                           (const T *)part, E);
+    } else if (use_sym(P, 1)) {
+        TiledArgs<T> a = sym_args<T>(P);
+        a.hwN = tab;
+        a.padq = 0;
+        constexpr int U = sizeof(T) == 8 ? 2 : 4;
+        hipLaunchKernelGGL((k_fwd_sym<T, U, false>), dim3(static_cast<unsigned>(P->n_sym_tiles)), dim3(1024),
+                           sym_lds_bytes(P->dtype, P->sym_lds_states), s, a, f, part);
+        hipLaunchKernelGGL((k_sym_finish<T>), dim3((P->S + 255) / 256), dim3(256), 0, s, a, f,
+                           (const T *)part, E);
+    } else {
+        TiledArgs<T> a = tiled_args<T>(P);
+        a.hwN = tab;
+        a.padq = 0;
+        hipLaunchKernelGGL((k_fwd_tiled<T, 4, 512, false>), dim3(tile_grid(P, P->n_tiles), 1),
+                           dim3(P->block_threads), tiled_lds_bytes(P), s, a, f, int64_t(P->S), part, E);
+        if (!P->fused)
+            hipLaunchKernelGGL((k_tiled_finish<T>), dim3((P->S + 255) / 256, 1), dim3(256), 0, s, a, f,
+                               int64_t(P->S), (const T *)part, E);
+    }
+    HIPC(hipGetLastError());
 }
 
 // gg2_mode: 0 none, 1 overwrite, 2 accumulate.  E.mode < 0: gradient of g2 only.
@@ -2033,7 +2117,9 @@ ephbte_status ephbte_build_channels(const ephbte_problem *problem, const ephbte_
         }
         P->device = dev;
         DeviceGuard g(dev);
-        // the event that orders consecutive calls on the plan
+        // set-up of this device: the address of its copy of the allocation-free
+        // pass's scratch, and the event that orders consecutive calls on the plan
+        (void)scratch_base(dev);
         HIPC(hipEventCreateWithFlags(&P->ev_last, hipEventDisableTiming));
         P->dtype = problem->dtype;
         P->S = L.S;
@@ -2173,6 +2259,30 @@ ephbte_status ephbte_collision_integral(ephbte_plan plan, int32_t batch, const v
         };
         if (plan->dtype == EPHBTE_F64) run(double{});
         else run(float{});
+        return EPHBTE_OK;
+    });
+}
+
+ephbte_status ephbte_collision_integral_noalloc(ephbte_plan plan, const void *f, const void *nph,
+                                                void *I, void *stream) {
+    return guarded(plan, stream, [&]() -> ephbte_status {
+        if (!f || !nph || !I) return fail(EPHBTE_INVALID_ARGUMENT, "f, nph and I must be non-NULL");
+        const size_t es = esize(plan);
+        if (overlaps(f, es * plan->S, I, es * plan->S))
+            return fail(EPHBTE_INVALID_ARGUMENT, "I must not overlap f");
+        const size_t need = noalloc_bytes(plan);
+        if (need > kScratchBytes)
+            return fail(EPHBTE_INVALID_ARGUMENT,
+                        "the allocation-free pass needs " + std::to_string(need) +
+                            " bytes of scratch for this plan; it holds " + std::to_string(kScratchBytes));
+        unsigned char *base = static_cast<unsigned char *>(scratch_base(plan->device));
+        hipStream_t s = as_stream(stream);
+        if (plan->dtype == EPHBTE_F64)
+            enqueue_forward_noalloc<double>(plan, static_cast<const double *>(f), nph, static_cast<double *>(I),
+                                            base, s);
+        else
+            enqueue_forward_noalloc<float>(plan, static_cast<const float *>(f), nph, static_cast<float *>(I), base,
+                                           s);
         return EPHBTE_OK;
     });
 }

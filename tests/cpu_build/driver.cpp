@@ -192,6 +192,19 @@ int main(int argc, char **argv) {
         check(ephbte_kernel_timing(plan, 0, &kms, &kn), "kernel_timing stop");
         wr("out_I.bin", dv.down(dI, static_cast<size_t>(B) * S));
         wr("out_timing.bin", {kms, static_cast<double>(kn)});
+    } else if (mode == "noalloc") {
+        // the allocation-free pass after the plain one, on scratch that holds
+        // fresh-memory bytes; it must make no hipMalloc call
+        fill_unwritten(ephbte::scratch, sizeof(ephbte::scratch), 0xA5);
+        auto f = rd<double>("f.bin", static_cast<size_t>(S));
+        void *df = dv.up(f), *dI = dv.alloc(static_cast<size_t>(S)), *dJ = dv.alloc(static_cast<size_t>(S));
+        check(ephbte_collision_integral(plan, 1, df, S, dN, 0, dI, S, nullptr), "collision_integral");
+        const long long m0 = emu::n_malloc;
+        check(ephbte_collision_integral_noalloc(plan, df, dN, dJ, nullptr), "collision_integral_noalloc");
+        const long long m1 = emu::n_malloc;
+        wr("out_I.bin", dv.down(dI, static_cast<size_t>(S)));
+        wr("out_J.bin", dv.down(dJ, static_cast<size_t>(S)));
+        wr("out_mallocs.bin", {static_cast<double>(m1 - m0)});
     } else if (mode == "vjp") {
         auto f = rd<double>("f.bin", static_cast<size_t>(B) * S);
         auto lam = rd<double>("lam.bin", static_cast<size_t>(B) * S);

@@ -249,7 +249,12 @@ inline hipError_t hipMalloc(void **p, size_t n) {
     return hipSuccess;
 }
 inline hipError_t hipFree(void *p) { free(p); return hipSuccess; }
-
+// a file-scope device array is a host global here
+#define HIP_SYMBOL(x) reinterpret_cast<const void *>(&(x))
+inline hipError_t hipGetSymbolAddress(void **p, const void *sym) {
+    *p = const_cast<void *>(sym);
+    return hipSuccess;
+}
 inline hipError_t hipHostMalloc(void **p, size_t n, unsigned) { return hipMalloc(p, n); }
 inline hipError_t hipHostFree(void *p) { free(p); return hipSuccess; }
 inline hipError_t hipMemcpy(void *d, const void *s, size_t n, hipMemcpyKind) { if (n) std::memmove(d, s, n); return hipSuccess; }

@@ -607,6 +607,41 @@ def test_tile_tables(driver, tmp_path, name, tune):
     assert np.all(_out(tmp_path, "tiles") == 0), _out(tmp_path, "tiles")
 
 
+@pytest.mark.parametrize("name,layout,dtype", [("multiband", 2, "f64"), ("multiband", 1, "f64"),
+                                               ("multiband", 2, "f32"), ("parabolic", 2, "f64"),
+                                               ("random", 2, "f64")])
+def test_allocation_free_pass(driver, tmp_path, name, layout, dtype):
+    """The allocation-free forward pass (its table and partials in the
+    library's static scratch, which holds random bytes here) gives bitwise
+    the result of the plain pass and calls hipMalloc zero times."""
+    s = {"multiband": synth.multiband_system, "parabolic": lambda: synth.parabolic_system(4),
+         "random": synth.random_channel_system}[name]()
+    f = 0.05 + 0.9 * synth.random_occupations(s, 11)
+    nph = s.nph(300.0)
+    _write(tmp_path, s, dtype, f=f, nph=nph, layout=layout)
+    _run(driver, tmp_path, "noalloc", fill="random:5")
+    I, J = _out(tmp_path, "I"), _out(tmp_path, "J")
+    assert _out(tmp_path, "mallocs")[0] == 0
+    assert np.array_equal(I, J)
+    if dtype == "f64":
+        assert nerr(J, oracle.collision(s, f, nph)) <= TOL64
+
+
+def test_allocation_free_pass_rejects_large_tables(driver, tmp_path):
+    """A phonon table larger than the static scratch (1024 x 1024 x 3 q
+    points: 50 MB of {hw, N} in FP64) is refused before any work."""
+    import dataclasses
+    s = synth.two_state_system()
+    q = (1024, 1024, 3)
+    s = dataclasses.replace(s, kgrid=q, qgrid=q, hw=np.full((int(np.prod(q)), 1), 0.05),
+                            n_q_norm=float(np.prod(q)))
+    _write(tmp_path, s, f=np.array([0.3, 0.6]), nph=s.nph(300.0))
+    r = subprocess.run([driver, "noalloc", str(tmp_path)], env=ENV, capture_output=True, text=True,
+                       timeout=600)
+    assert r.returncode == 3
+    assert "collision_integral_noalloc: status 1" in r.stderr and "bytes of scratch" in r.stderr
+
+
 def _uneven_bath(s, seed):
     rng = np.random.default_rng(seed)
     return s.nph(300.0) * rng.uniform(0.5, 1.5, size=s.hw.shape)
