@@ -5,10 +5,12 @@ k grid, 0.3 eV window, 50^3 q grid, 3 Debye + 3 Einstein modes, lognormal
 |g|^2, sigma = 8 meV, ~2e8 unordered channels), synthetic and seeded.
 
 A step is one evaluation of I[f] (Eq. 2) over every channel at B = 1 in FP64
--- the operator every other form is built from.  `value` is scattering
-channels per second of that step with all inputs resident in HBM.  The other
-forms (FP32, forward + reverse, B = 64, RK4 step, transport iteration) are
-timed after the main loop and reported under "forms".
+-- the operator every other form is built from -- by the plan's default
+pass (single copy over pair records).  `value` is scattering channels per
+second of that step with all inputs resident in HBM.  The other forms (the
+other layouts, FP32, forward + reverse, B = 64 with its ALU roofline, RK4
+step, transport iteration, phonon side, coupled step, CPU oracle on all host
+cores) are timed after the main loop and reported under "forms".
 
 Prints one JSON line.  Options: --steps K --warmup W --gpus 1 [--quick]
 """
@@ -36,6 +38,24 @@ BYTES_PER_CHANNEL_ROWS = {"f64": 24.0, "f32": 16.0}
 LAYOUT_NAMES = {1: "duplicated rows", 2: "single copy, one entry per channel",
                 3: "single copy over pair records"}
 KERNEL_OF_LAYOUT = {1: "k_fwd_tiled", 2: "k_fwd_sym", 3: "k_fwd_pairs"}
+
+
+# Published MI355X vector peaks (TFLOP/s) for the ALU-bound batched passes
+VECTOR_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
+
+
+def batched_alu_roofline(ms, dtype, pairs, entries, B, reverse=False):
+    """ALU roofline of a B-vector pass from its algorithmic floating-point
+    operations: per entry the coefficients (two Gaussians and about 20 other
+    operations: 30 counted), per merged run of one partner (one pair, both
+    orientations: 2 x pairs runs) and vector 5 operations forward
+    (acc_a += a (1 - f), acc_b += b f) or 12 reverse (u, the two sums over
+    the vectors' products, and the dL/df accumulation)."""
+    flops = 30.0 * entries + (12.0 if reverse else 5.0) * 2.0 * pairs * B
+    achieved = flops / (ms * 1e-3) / 1e12
+    peak = VECTOR_PEAK_TFLOPS[dtype]
+    return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+            "flops_per_pass": flops}
 
 
 def pair_bytes(info, n_modes, dtype):
@@ -319,7 +339,9 @@ def main():
         F = tens(F_np, torch.float64)
         IB = torch.empty_like(F)
         msb, _ = timed(lambda: E.collision_integral(plan64, F, n64, out=IB), 3, 1)
+        npairs_b = max(info64["pair_records"], 1)
         forms["fwd_f64_b64"] = dict(ms=msb, per_vector_channels_per_s=B * nch / (msb * 1e-3),
+                                    alu_roofline=batched_alu_roofline(msb, "f64", npairs_b, 2 * nch, B),
                                     ratio_vs_b1=(B * nch / (msb * 1e-3)) / value,
                                     batch_partners=tuned["batch_partners"],
                                     vectors="16 temperatures (100-400 K) x 4 fields (0-1e5 V/m)")
@@ -330,6 +352,7 @@ def main():
         ggb = torch.zeros(nch, dtype=torch.float64, device=dev)
         msbv, _ = timed(lambda: E.collision_vjp(plan64, F, n64, LB, want_f=True, gg2=ggb), 3, 1)
         forms["vjp_f64_b64"] = dict(ms=msbv, per_vector_channels_per_s=B * nch / (msbv * 1e-3),
+                                    alu_roofline=batched_alu_roofline(msbv, "f64", npairs_b, 2 * nch, B, True),
                                     ratio_vs_b1=(B * nch / (msbv * 1e-3)) / (nch / (ms_v * 1e-3)))
         forms["fwd_plus_adjoint_f64_b64"] = dict(
             ms=msb + msbv, per_vector_channels_per_s=B * nch / ((msb + msbv) * 1e-3),
@@ -429,14 +452,18 @@ def main():
         F32 = tens(synth.batch_occupations(s), torch.float32)
         IB32 = torch.empty_like(F32)
         msb32, _ = timed(lambda: E.collision_integral(plan32, F32, n32, out=IB32), 3, 1)
+        npairs_b32 = max(info32["pair_records"], 1)
         forms["fwd_f32_b64"] = dict(ms=msb32, per_vector_channels_per_s=64 * nch / (msb32 * 1e-3),
+                                    alu_roofline=batched_alu_roofline(msb32, "f32", npairs_b32, 2 * nch, 64),
                                     ratio_vs_b1=(64 * nch / (msb32 * 1e-3)) / (nch / (ms32 * 1e-3)),
                                     batch_partners=tuned32["batch_partners"])
         log(f"fwd fp32 B=64: {msb32:.3f} ms ({forms['fwd_f32_b64']['ratio_vs_b1']:.2f}x per vector)")
         LB32 = tens(rng.normal(size=(64, s.n_states)), torch.float32)
         gg32 = torch.zeros(nch, dtype=torch.float64, device=dev)
         msbv32, _ = timed(lambda: E.collision_vjp(plan32, F32, n32, LB32, want_f=True, gg2=gg32), 3, 1)
-        forms["vjp_f32_b64"] = dict(ms=msbv32, per_vector_channels_per_s=64 * nch / (msbv32 * 1e-3))
+        forms["vjp_f32_b64"] = dict(ms=msbv32, per_vector_channels_per_s=64 * nch / (msbv32 * 1e-3),
+                                    alu_roofline=batched_alu_roofline(msbv32, "f32", npairs_b32, 2 * nch, 64,
+                                                                      True))
         log(f"vjp fp32 B=64: {msbv32:.3f} ms")
         del F32, IB32, LB32, gg32
         forms["transport_solve_f32"] = transport_solve(

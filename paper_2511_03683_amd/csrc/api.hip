@@ -143,6 +143,7 @@ struct ephbte_plan_s {
     uint32_t *pr_partner = nullptr;
     void *pr_g2 = nullptr;
     int32_t *pr_chan = nullptr;
+    int32_t *pr_ch0 = nullptr;             // first channel of a record whose slots are consecutive, else -1
     int64_t pr_np = 0, pr_ld = 0;
     std::vector<int64_t> pr_rowptr;        // host: pair rows, for re-chunking
     int64_t *pr_chunk_beg = nullptr, *pr_chunk_end = nullptr;
@@ -298,7 +299,7 @@ void free_plan(ephbte_plan P) {
                      (void **)&P->ph_bucket_modes, (void **)&P->pr_partner, (void **)&P->pr_g2,
                      (void **)&P->pr_chan, (void **)&P->pr_chunk_beg, (void **)&P->pr_chunk_end,
                      (void **)&P->pr_chunk_dest, (void **)&P->pr_dest_chunk, (void **)&P->pr_tiles,
-                     (void **)&P->lmax_bits};
+                     (void **)&P->lmax_bits, (void **)&P->pr_ch0};
     for (auto pp : ptrs) dfree(*pp);
     DevBuf *w[] = {&P->part,   &P->sym_part, &P->rk_ua,  &P->rk_ub,   &P->rk_acc, &P->hwN, &P->tr_W,   &P->tr_tau_inv,
                    &P->tr_tau, &P->tr_rhs, &P->tr_xa,   &P->tr_xb,  &P->tr_part, &P->tr_red,
@@ -557,7 +558,7 @@ bool use_sym(ephbte_plan P, int B) {
     return B == 1 && P->layout == 2 && P->sym_ok && P->n_sym_tiles > 0;
 }
 
-// k_fwd_pairs with its mode-slot count rounded up to 2, 4, 6 or 8
+// k_fwd_pairs with its mode-slot count rounded up to 1, 2, 3, 4, 6 or 8
 template <typename T>
 void launch_pairs(ephbte_plan P, const TiledArgs<T> &a, const T *f, T *part, size_t shm, hipStream_t s,
                   bool padq) {
@@ -570,7 +571,9 @@ void launch_pairs(ephbte_plan P, const TiledArgs<T> &a, const T *f, T *part, siz
         else if (tab) hipLaunchKernelGGL((k_fwd_pairs<T, false, NM, true>), grid, block, shm, s, a, f, part);
         else hipLaunchKernelGGL((k_fwd_pairs<T, false, NM, false>), grid, block, shm, s, a, f, part);
     };
-    if (P->nm <= 2) go(std::integral_constant<int, 2>{});
+    if (P->nm <= 1) go(std::integral_constant<int, 1>{});
+    else if (P->nm <= 2) go(std::integral_constant<int, 2>{});
+    else if (P->nm <= 3) go(std::integral_constant<int, 3>{});
     else if (P->nm <= 4) go(std::integral_constant<int, 4>{});
     else if (P->nm <= 6) go(std::integral_constant<int, 6>{});
     else go(std::integral_constant<int, 8>{});
@@ -914,27 +917,29 @@ void enqueue_vjp(ephbte_plan P, const T *f, const T *lam, const void *nph, const
         TiledArgs<T> a = pair_args<T>(P);
         T *part = static_cast<T *>(P->sym_part.p);
         const int want_f = E.mode >= 0 ? 1 : 0;
-        const dim3 grid(static_cast<unsigned>(P->n_pr_tiles)), block(1024);
+        const dim3 grid(static_cast<unsigned>(P->n_pr_tiles)), block(kVjpPairThreads);
         const size_t shm = vjp_pair_lds_bytes(P->dtype, P->sym_lds_states);
         auto go = [&](auto nmc) {
             constexpr int NM = decltype(nmc)::value;
             const bool tab = sizeof(T) == 8 && P->exp_table;
             const unsigned long long *lm = P->lmax_bits;
-            const int32_t *ch = P->pr_chan;
+            const int32_t *ch = P->pr_chan, *c0 = P->pr_ch0;
             if (P->padq && tab)
                 hipLaunchKernelGGL((k_vjp_pairs<T, true, NM, true>), grid, block, shm, s, a, f, lam, part, want_f, lm,
-                                   ch, gg2, gg2_mode);
+                                   ch, c0, gg2, gg2_mode);
             else if (P->padq)
                 hipLaunchKernelGGL((k_vjp_pairs<T, true, NM, false>), grid, block, shm, s, a, f, lam, part, want_f,
-                                   lm, ch, gg2, gg2_mode);
+                                   lm, ch, c0, gg2, gg2_mode);
             else if (tab)
                 hipLaunchKernelGGL((k_vjp_pairs<T, false, NM, true>), grid, block, shm, s, a, f, lam, part, want_f,
-                                   lm, ch, gg2, gg2_mode);
+                                   lm, ch, c0, gg2, gg2_mode);
             else
                 hipLaunchKernelGGL((k_vjp_pairs<T, false, NM, false>), grid, block, shm, s, a, f, lam, part, want_f,
-                                   lm, ch, gg2, gg2_mode);
+                                   lm, ch, c0, gg2, gg2_mode);
         };
-        if (P->nm <= 2) go(std::integral_constant<int, 2>{});
+        if (P->nm <= 1) go(std::integral_constant<int, 1>{});
+        else if (P->nm <= 2) go(std::integral_constant<int, 2>{});
+        else if (P->nm <= 3) go(std::integral_constant<int, 3>{});
         else if (P->nm <= 4) go(std::integral_constant<int, 4>{});
         else if (P->nm <= 6) go(std::integral_constant<int, 6>{});
         else go(std::integral_constant<int, 8>{});
@@ -1193,6 +1198,18 @@ template <typename T> void upload_pair_rows(ephbte_plan P, const ephbte_problem 
         });
         HIPC(hipMemcpy(P->pr_g2, g.data(), sizeof(T) * g.size(), hipMemcpyHostToDevice));
         HIPC(hipMemcpy(P->pr_chan, ch.data(), sizeof(int32_t) * ch.size(), hipMemcpyHostToDevice));
+        // records whose slots hold the channels c0, c0 + 1, .., c0 + n_modes - 1
+        std::vector<int32_t> c0(ld, -1);
+        parallel_ranges(np, host_threads(), [&](int, int64_t b, int64_t e) {
+            for (int64_t j = b; j < e; ++j) {
+                const int32_t first = ch[static_cast<size_t>(j)];
+                bool run = first >= 0;
+                for (int64_t m = 1; run && m < nm; ++m) run = ch[static_cast<size_t>(m) * ld + j] == first + m;
+                c0[static_cast<size_t>(j)] = run ? first : -1;
+            }
+        });
+        dalloc(P->pr_ch0, sizeof(int32_t) * ld, &acc);
+        HIPC(hipMemcpy(P->pr_ch0, c0.data(), sizeof(int32_t) * ld, hipMemcpyHostToDevice));
     }
     P->pr_rowptr = std::move(R.row_ptr);
 }

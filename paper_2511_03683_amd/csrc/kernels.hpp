@@ -840,16 +840,27 @@ __device__ __forceinline__ void pair_chunk(const TiledArgs<T> &A, const T *__res
     const T fd = fb[d];
     const T cfd = T(1) - fd;
     T acc_a = T(0), acc_b = T(0);
-    // the partners run one batch ahead; the |g|^2 loads of a batch are issued
-    // before its gathers and overlap them.  The arrays are padded past their
-    // end, so no stream load needs a bound.
+    // the stream (partner and |g|^2 slots) runs one batch ahead of the
+    // gathers and the evaluation.  The arrays are padded past their end, so
+    // no stream load needs a bound.
+    // Mode slots past nm (NM rounds nm up) re-read the last mode and count
+    // as empty, so the mode loops carry no branch.
     uint32_t pn = pb[lane];
+    T g[NM];
+#pragma unroll
+    for (int m = 0; m < NM; ++m) {
+        const T x = gb[min(m, nm - 1) * A.pld + lane];
+        g[m] = m < nm ? x : T(0);
+    }
     for (int r = 0; r < len; r += 64) {
         const bool v = r + lane < len;
         const uint32_t pn_next = pb[r + 64 + lane];
-        T g[NM];
+        T g_next[NM];
 #pragma unroll
-        for (int m = 0; m < NM; ++m) g[m] = m < nm ? gb[m * A.pld + r + lane] : T(0);
+        for (int m = 0; m < NM; ++m) {
+            const T x = gb[min(m, nm - 1) * A.pld + r + 64 + lane];
+            g_next[m] = m < nm ? x : T(0);
+        }
         const int p = static_cast<int>(pn);
         T ep, fp;
         uint32_t kp;
@@ -873,14 +884,12 @@ __device__ __forceinline__ void pair_chunk(const TiledArgs<T> &A, const T *__res
         const Pair2<T> *__restrict__ wq = A.hwN + static_cast<int64_t>(q) * nm;
         Pair2<T> w[NM];
 #pragma unroll
-        for (int m = 0; m < NM; ++m)
-            if (m < nm) w[m] = wq[m];
+        for (int m = 0; m < NM; ++m) w[m] = wq[min(m, nm - 1)];
         const T de = sd.eps - ep;
         const T ofp = T(1) - fp;
         T y = T(0);
 #pragma unroll
         for (int m = 0; m < NM; ++m) {
-            if (m >= nm) break;
             const T gm = v ? g[m] : T(0);
             const T N = gm != T(0) ? w[m].b : T(0);
             const T xa = de + w[m].a, xe = de - w[m].a;
@@ -900,6 +909,8 @@ __device__ __forceinline__ void pair_chunk(const TiledArgs<T> &A, const T *__res
             else atomicAdd(A.jacc + pl, fx);
         }
         pn = pn_next;
+#pragma unroll
+        for (int m = 0; m < NM; ++m) g[m] = g_next[m];
     }
     acc_a = wave_sum(acc_a);
     acc_b = wave_sum(acc_b);
@@ -956,7 +967,9 @@ __global__ __launch_bounds__(1024) void k_fwd_pairs(TiledArgs<T> A, const T *__r
 // x = e_d - e_p).  Hence, with dl = lam_d - lam_p:
 //   dL/df_d  += -K dl |g|^2 (ah (1 - f_p) + bh f_p)          (row side, registers)
 //   dL/df_p  +=  K dl |g|^2 (bh (1 - f_d) + ah f_d)          (partner side, fixed point)
-//   dL/d|g|^2 =  K dl ((1 - f_d) bh f_p - f_d ah (1 - f_p))   (one writer per channel)
+//   dL/d|g|^2 =  K dl ((1 - f_d) bh f_p - f_d ah (1 - f_p))   (one writer per channel;
+//                chan0 holds the record's first channel when its slots are the
+//                consecutive channels of the caller's list, else -1)
 // The partner side of a pair is summed over its modes and added with one
 // integer atomic, on the scale of vjp_scale.  Each channel is read once.
 __device__ __forceinline__ double vjp_scale(const unsigned long long *nmax_bits,
@@ -973,13 +986,19 @@ __device__ __forceinline__ double vjp_scale(const unsigned long long *nmax_bits,
     return ldexp(1.0, 61 - e);
 }
 
+// threads per workgroup of the pair reverse pass: 12 waves, so that a lane
+// may hold up to 168 registers (the pass keeps more values live than the
+// forward's 128)
+constexpr int kVjpPairThreads = 768;
+
 template <typename T, bool LDS, bool PADQ, int NM, bool TAB>
 __device__ __forceinline__ void vjp_pair_chunk(const TiledArgs<T> &A, const T *__restrict__ fb,
                                                const T *__restrict__ lb, const Pair2<T> *s_ef,
                                                const uint32_t *s_kq, const T *s_l, int p_lo,
                                                const double *s_tab, unsigned long long *s_j, T scale,
                                                int64_t c, T *__restrict__ part, bool want_f,
-                                               const int32_t *__restrict__ chan, double *__restrict__ gg2,
+                                               const int32_t *__restrict__ chan,
+                                               const int32_t *__restrict__ chan0, double *__restrict__ gg2,
                                                int gg2_mode) {
     const int lane = threadIdx.x & 63;
     const int nm = A.nm;
@@ -989,6 +1008,7 @@ __device__ __forceinline__ void vjp_pair_chunk(const TiledArgs<T> &A, const T *_
     const uint32_t *__restrict__ pb = A.pnu + beg;
     const T *__restrict__ gb = A.g2 + beg;
     const int32_t *__restrict__ cb = chan + beg;
+    const int32_t *__restrict__ cb0 = chan0 + beg;
     const StateRec<T> sd = A.st[d];
     const uint32_t kd = PADQ ? sd.kqp : sd.kq;
     const T fd = fb[d];
@@ -999,9 +1019,14 @@ __device__ __forceinline__ void vjp_pair_chunk(const TiledArgs<T> &A, const T *_
     for (int r = 0; r < len; r += 64) {
         const bool v = r + lane < len;
         const uint32_t pn_next = pb[r + 64 + lane];
+        // mode slots past nm re-read the last mode and count as empty
         T g[NM];
 #pragma unroll
-        for (int m = 0; m < NM; ++m) g[m] = m < nm ? gb[m * A.pld + r + lane] : T(0);
+        for (int m = 0; m < NM; ++m) {
+            const T x = gb[min(m, nm - 1) * A.pld + r + lane];
+            g[m] = m < nm ? x : T(0);
+        }
+        const int32_t c0 = gg2_mode ? cb0[r + lane] : -1;
         const int p = static_cast<int>(pn);
         T ep, fp, lp;
         uint32_t kp;
@@ -1023,20 +1048,17 @@ __device__ __forceinline__ void vjp_pair_chunk(const TiledArgs<T> &A, const T *_
         }
         const int q = PADQ ? static_cast<int>(kp - kd) + A.qoff : q_linear(kd, kp, A.nq0, A.nq1, A.nq2);
         const Pair2<T> *__restrict__ wq = A.hwN + static_cast<int64_t>(q) * nm;
-        Pair2<T> w[NM];
-#pragma unroll
-        for (int m = 0; m < NM; ++m)
-            if (m < nm) w[m] = wq[m];
         const T x = sd.eps - ep;
         const T ofp = T(1) - fp;
         const T dl = ld - lp;
         T y = T(0);
+        double gv[NM];
 #pragma unroll
         for (int m = 0; m < NM; ++m) {
-            if (m >= nm) break;
+            const Pair2<T> wm = wq[min(m, nm - 1)];
             const T gm = v ? g[m] : T(0);
-            const T N = gm != T(0) ? w[m].b : T(0);
-            const T xa = x + w[m].a, xe = x - w[m].a;
+            const T N = gm != T(0) ? wm.b : T(0);
+            const T xa = x + wm.a, xe = x - wm.a;
             const T da = pair_gauss<T, TAB>(A, xa * xa, s_tab);
             const T dem = pair_gauss<T, TAB>(A, xe * xe, s_tab);
             const T t = N * (da + dem);
@@ -1044,11 +1066,27 @@ __device__ __forceinline__ void vjp_pair_chunk(const TiledArgs<T> &A, const T *_
             const T dg = dl * gm;
             acc += dg * (ah * ofp + bh * fp);
             y += dg * (bh * cfd + ah * fd);
-            if (gg2_mode && v) {
-                const int32_t ch = cb[m * A.pld + r + lane];
-                if (ch >= 0) {
-                    const double val = static_cast<double>(A.K * dl * (cfd * bh * fp - fd * ah * ofp));
-                    gg2[ch] = gg2_mode == 2 ? gg2[ch] + val : val;
+            gv[m] = static_cast<double>(A.K * dl * (cfd * bh * fp - fd * ah * ofp));
+        }
+        if (gg2_mode && v) {
+            if (c0 >= 0 && NM == nm && (NM & 1) == 0 && (c0 & 1) == 0) {
+                // the record's channels are consecutive in the caller's order
+                // and 16-byte aligned: the lane writes them as whole pairs, and
+                // consecutive records fill consecutive memory
+                double2 *dst = reinterpret_cast<double2 *>(gg2 + c0);
+#pragma unroll
+                for (int k = 0; k < NM / 2; ++k) {
+                    double2 o = gg2_mode == 2 ? dst[k] : make_double2(0.0, 0.0);
+                    o.x += gv[2 * k];
+                    o.y += gv[2 * k + 1];
+                    dst[k] = o;
+                }
+            } else {
+#pragma unroll
+                for (int m = 0; m < NM; ++m) {
+                    if (m >= nm) break;
+                    const int32_t ch = c0 >= 0 ? c0 + m : cb[m * A.pld + r + lane];
+                    if (ch >= 0) gg2[ch] = gg2_mode == 2 ? gg2[ch] + gv[m] : gv[m];
                 }
             }
         }
@@ -1065,10 +1103,11 @@ __device__ __forceinline__ void vjp_pair_chunk(const TiledArgs<T> &A, const T *_
 }
 
 template <typename T, bool PADQ, int NM, bool TAB>
-__global__ __launch_bounds__(1024) void k_vjp_pairs(TiledArgs<T> A, const T *__restrict__ f,
+__global__ __launch_bounds__(kVjpPairThreads) void k_vjp_pairs(TiledArgs<T> A, const T *__restrict__ f,
                                                     const T *__restrict__ lam, T *__restrict__ part, int want_f,
                                                     const unsigned long long *__restrict__ lmax_bits,
-                                                    const int32_t *__restrict__ chan, double *__restrict__ gg2,
+                                                    const int32_t *__restrict__ chan,
+                                                    const int32_t *__restrict__ chan0, double *__restrict__ gg2,
                                                     int gg2_mode) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int64_t ti = tile_of_block(A.n_tiles, A.xcd);
@@ -1099,10 +1138,10 @@ __global__ __launch_bounds__(1024) void k_vjp_pairs(TiledArgs<T> A, const T *__r
     for (int64_t c = t.c0 + wave; c < t.c1; c += nw) {
         if (t.lds)
             vjp_pair_chunk<T, true, PADQ, NM, TAB>(A, f, lam, s_ef, s_kq, s_l, t.p_lo, s_tab, s_j, scale, c, part,
-                                                   want_f != 0, chan, gg2, gg2_mode);
+                                                   want_f != 0, chan, chan0, gg2, gg2_mode);
         else
             vjp_pair_chunk<T, false, PADQ, NM, TAB>(A, f, lam, s_ef, s_kq, s_l, t.p_lo, s_tab, s_j, scale, c,
-                                                    part, want_f != 0, chan, gg2, gg2_mode);
+                                                    part, want_f != 0, chan, chan0, gg2, gg2_mode);
     }
     if (!want_f) return;
     __syncthreads();

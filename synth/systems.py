@@ -522,6 +522,16 @@ def tb_system(kn=100, qn=50, nb=4, target_states=23000, window=0.3, a=LATTICE_A,
                             energy_cutoff=energy_cutoff))
 
 
+def tb_two_band_system(**kw) -> System:
+    """The tight-binding transport workload's model with a seed (124) whose
+    0.3 eV window holds two bands: 15,544 states of the lowest band and 7,465
+    of the next, 23,009 in all, 1.98e8 channels (intra- and inter-band pairs;
+    pairs at the same k have no acoustic channel, q = 0)."""
+    kw.setdefault("seed", 124)
+    kw.setdefault("name", "tb100_2band")
+    return tb_system(**kw)
+
+
 def multiband_system(kn=6, qn=3, nb=2, n_k=24, e_max=0.25, a=LATTICE_A,
                      debye_kms=(4.0,), einstein_eV=(0.02, 0.045), sigma=0.015,
                      seed=19) -> System:

@@ -30,6 +30,11 @@
 #include <vector>
 #include <sanitizer/asan_interface.h>
 
+struct alignas(16) double2 {
+    double x, y;
+};
+inline double2 make_double2(double a, double b) { return double2{a, b}; }
+
 struct dim3 {
     unsigned x, y, z;
     constexpr dim3(unsigned a = 1, unsigned b = 1, unsigned c = 1) : x(a), y(b), z(c) {}

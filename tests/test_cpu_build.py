@@ -714,3 +714,48 @@ def test_coupled_adjoint(driver, tmp_path, name, ce):
     assert nerr(_out(tmp_path, "gf"), rf) <= TOL64
     assert nerr(_out(tmp_path, "gN", rN.shape), rN) <= TOL64
     assert nerr(_out(tmp_path, "gg2"), rg) <= TOL64
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_pair_records_with_rounded_up_mode_count(driver, tmp_path, dtype):
+    """Five modes: the pair-record kernels run with their mode-slot count
+    rounded up to six, the sixth slot re-reading the fifth and counting as
+    empty.  Forward and reverse (dL/df, dL/d|g|^2) against the oracle."""
+    s = synth.tb_system(kn=24, qn=12, target_states=300, einstein_eV=(0.02, 0.05))
+    assert s.n_modes == 5
+    f = 0.05 + 0.9 * synth.random_occupations(s, 101)
+    nph = s.nph(300.0)
+    lam = np.random.default_rng(102).normal(size=s.n_states)
+    _write(tmp_path, s, dtype, f=f, lam=lam, nph=nph, B=1, layout=3)
+    _run(driver, tmp_path, "forward", fill="random:7")
+    _run(driver, tmp_path, "vjp", fill="random:8")
+    r = s if dtype == "f64" else _round32(s)
+    if dtype == "f32":
+        f, nph, lam = (x.astype(np.float32).astype(np.float64) for x in (f, nph, lam))
+    tol = TOL64 if dtype == "f64" else TOL32
+    ref = oracle.collision(r, f, nph)
+    if dtype == "f64":
+        assert nerr(_out(tmp_path, "I"), ref) <= tol
+    else:
+        rin, rout = oracle.collision_inout(r, f, nph)
+        scale = max(np.abs(ref).max(), 1e-2 * max(rin.max(), rout.max()))
+        assert np.abs(_out(tmp_path, "I") - ref).max() / scale <= tol
+    rf, rg = oracle.collision_vjp(r, f, nph, lam)
+    assert nerr(_out(tmp_path, "gf"), rf) <= tol
+    assert nerr(_out(tmp_path, "gg2"), rg) <= tol
+
+
+@pytest.mark.parametrize("layout,fill", [(3, "random:9"), (2, None)])
+def test_vjp_six_modes(driver, tmp_path, layout, fill):
+    """Reverse pass on the six-mode tight-binding system: over pair records
+    (whose consecutive channels are written as 16-byte pairs) and over
+    entries; every |g|^2 gradient is overwritten (the buffer starts at 0.5)."""
+    s = synth.tb_system(kn=24, qn=12, target_states=400)
+    f = synth.random_occupations(s, 111)
+    lam = np.random.default_rng(112).normal(size=s.n_states)
+    nph = s.nph(300.0)
+    _write(tmp_path, s, f=f, lam=lam, nph=nph, B=1, layout=layout, gg2_fill=0.5)
+    _run(driver, tmp_path, "vjp", fill=fill)
+    rf, rg = oracle.collision_vjp(s, f, nph, lam)
+    assert nerr(_out(tmp_path, "gf"), rf) <= TOL64
+    assert nerr(_out(tmp_path, "gg2"), rg) <= TOL64

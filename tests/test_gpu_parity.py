@@ -1175,6 +1175,38 @@ def test_full_size_parity(E, c2, dtype):
     assert nerr(I, ref, full_norm(r, f, nph, ref, dtype, args=a)) <= (TOL64 if dtype == "f64" else TOL32)
 
 
+@pytest.fixture(scope="module")
+def c2b():
+    return synth.tb_two_band_system()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_full_size_two_band_parity(E, c2b, dtype):
+    """The two-band variant of the full-size workload (two bands in the 0.3 eV
+    window, inter-band channels, pair records with partly filled mode slots):
+    every output of the default B = 1 pass against the oracle's channel loop
+    over the whole list."""
+    s = c2b
+    rng = np.random.default_rng(19)
+    assert len(np.unique(s.state_band)) == 2
+    f = np.clip(synth.fermi_dirac(s.eps, 0.05, 300.0) * (0.8 + 0.4 * rng.uniform(size=s.n_states)), 0, 1)
+    nph = s.nph(300.0)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    r = s
+    if dtype == "f32":
+        f = f.astype(np.float32).astype(np.float64)
+        nph = nph.astype(np.float32).astype(np.float64)
+        r = round32(s)
+    say(f"full-size two-band {dtype} S={s.n_states} Nch={s.n_channels}")
+    plan = E.build_channels(s, dtype=dtype, device=0)
+    I = host(E.collision_integral(plan, dev(f, tdt), dev(nph, tdt)))
+    plan.close()
+    a = oracle._Args(r, nph)
+    ref = oracle.collision_threads(r, f, nph, args=a)
+    assert np.isfinite(I).all()
+    assert nerr(I, ref, full_norm(r, f, nph, ref, dtype, args=a)) <= (TOL64 if dtype == "f64" else TOL32)
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_full_size_batched_parity(E, c2, dtype):
     """B = 64 vectors of the full-size system in one pass, as the benchmark
