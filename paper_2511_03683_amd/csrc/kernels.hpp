@@ -814,6 +814,19 @@ __global__ __launch_bounds__(1024) void k_fwd_sym(TiledArgs<T> A, const T *__res
 // fixed-point atomic.  A slot without a channel has |g|^2 = 0; its N is
 // replaced by 0 so that a non-finite table entry of that mode (N at an
 // acoustic q = 0) cannot turn the zero into a NaN.
+
+// v where keep holds, else +0, by masking the bits: unlike a select of a
+// loaded value, this cannot be turned into a load under a branch (which would
+// make the wave wait for every load in flight, the next batch's stream too)
+__device__ __forceinline__ double keep_or_zero(double v, bool keep) {
+    const unsigned long long m = keep ? ~0ull : 0ull;
+    return __longlong_as_double(static_cast<long long>(static_cast<unsigned long long>(__double_as_longlong(v)) & m));
+}
+__device__ __forceinline__ float keep_or_zero(float v, bool keep) {
+    const int m = keep ? -1 : 0;
+    return __int_as_float(__float_as_int(v) & m);
+}
+
 // FP64 Gaussian of the pair pass: the table exponential (TAB) or the
 // degree-12 polynomial one (no LDS reads); FP32: the hardware exponential
 template <typename T, bool TAB>
@@ -844,35 +857,34 @@ __device__ __forceinline__ void pair_chunk(const TiledArgs<T> &A, const T *__res
     // gathers and the evaluation.  The arrays are padded past their end, so
     // no stream load needs a bound.
     // Mode slots past nm (NM rounds nm up) re-read the last mode and count
-    // as empty, so the mode loops carry no branch.
-    uint32_t pn = pb[lane];
-    T g[NM];
+    // as empty, so the mode loops carry no branch.  The stream values are
+    // kept as loaded and masked where they are used: a mask applied at the
+    // end of the batch would make the wave wait there for the loads it has
+    // just issued.
+    // Two register sets alternate (the loop is unrolled twice), so the
+    // values loaded for the next batch need no copy at the end of a batch,
+    // which would wait for them.
+    uint32_t pn0 = pb[lane], pn1 = 0;
+    T g0[NM], g1[NM];
 #pragma unroll
-    for (int m = 0; m < NM; ++m) {
-        const T x = gb[min(m, nm - 1) * A.pld + lane];
-        g[m] = m < nm ? x : T(0);
-    }
-    for (int r = 0; r < len; r += 64) {
+    for (int m = 0; m < NM; ++m) g0[m] = gb[min(m, nm - 1) * A.pld + lane];
+    auto batch = [&](int r, const uint32_t pn, const T (&g)[NM], uint32_t &pn_next, T (&g_next)[NM]) {
         const bool v = r + lane < len;
-        const uint32_t pn_next = pb[r + 64 + lane];
-        T g_next[NM];
-#pragma unroll
-        for (int m = 0; m < NM; ++m) {
-            const T x = gb[min(m, nm - 1) * A.pld + r + 64 + lane];
-            g_next[m] = m < nm ? x : T(0);
-        }
         const int p = static_cast<int>(pn);
         T ep, fp;
         uint32_t kp;
         int pl;
+        // A masked lane takes a valid partner (the window's first state, or
+        // the destination) and |g|^2 = 0, so its operands are finite and it
+        // adds nothing.  The partner's values are loaded unconditionally: a
+        // choice between a loaded value and another one is compiled into a
+        // branch around the load, which waits for every load in flight.
         if (LDS) {
-            // a masked lane: partner = destination (the q = 0 table row,
-            // finite operands); it adds nothing
             pl = v ? p - p_lo : 0;
             const Pair2<T> ef = s_ef[pl];
-            ep = v ? ef.a : sd.eps;
-            fp = v ? ef.b : T(0);
-            kp = v ? s_kq[pl] : kd;
+            ep = ef.a;
+            fp = ef.b;
+            kp = s_kq[pl];
         } else {
             pl = v ? p : d;
             const StateRec<T> sp = A.st[pl];
@@ -885,13 +897,24 @@ __device__ __forceinline__ void pair_chunk(const TiledArgs<T> &A, const T *__res
         Pair2<T> w[NM];
 #pragma unroll
         for (int m = 0; m < NM; ++m) w[m] = wq[min(m, nm - 1)];
+        // the next batch's stream loads are issued after this batch's table
+        // gathers: loads complete in issue order for the wait counter, so
+        // waiting for the gathers does not wait for the stream.  The
+        // scheduling barriers keep that order and keep the compiler from
+        // sinking any of these loads towards their first use, which would
+        // serialise the gathers.
+        __builtin_amdgcn_sched_barrier(0);
+        pn_next = pb[r + 64 + lane];
+#pragma unroll
+        for (int m = 0; m < NM; ++m) g_next[m] = gb[min(m, nm - 1) * A.pld + r + 64 + lane];
+        __builtin_amdgcn_sched_barrier(0);
         const T de = sd.eps - ep;
         const T ofp = T(1) - fp;
         T y = T(0);
 #pragma unroll
         for (int m = 0; m < NM; ++m) {
-            const T gm = v ? g[m] : T(0);
-            const T N = gm != T(0) ? w[m].b : T(0);
+            const T gm = v && m < nm ? g[m] : T(0);
+            const T N = keep_or_zero(w[m].b, gm != T(0));
             const T xa = de + w[m].a, xe = de - w[m].a;
             const T da = pair_gauss<T, TAB>(A, xa * xa, s_tab);
             const T dem = pair_gauss<T, TAB>(A, xe * xe, s_tab);
@@ -908,9 +931,11 @@ __device__ __forceinline__ void pair_chunk(const TiledArgs<T> &A, const T *__res
             if (LDS) atomicAdd(s_j + pl, fx);
             else atomicAdd(A.jacc + pl, fx);
         }
-        pn = pn_next;
-#pragma unroll
-        for (int m = 0; m < NM; ++m) g[m] = g_next[m];
+    };
+    for (int r = 0; r < len; r += 128) {
+        batch(r, pn0, g0, pn1, g1);
+        if (r + 64 >= len) break;
+        batch(r + 64, pn1, g1, pn0, g0);
     }
     acc_a = wave_sum(acc_a);
     acc_b = wave_sum(acc_b);
@@ -1019,25 +1044,24 @@ __device__ __forceinline__ void vjp_pair_chunk(const TiledArgs<T> &A, const T *_
     for (int r = 0; r < len; r += 64) {
         const bool v = r + lane < len;
         const uint32_t pn_next = pb[r + 64 + lane];
-        // mode slots past nm re-read the last mode and count as empty
+        // mode slots past nm re-read the last mode and count as empty; the
+        // values are masked where they are used (see pair_chunk)
         T g[NM];
 #pragma unroll
-        for (int m = 0; m < NM; ++m) {
-            const T x = gb[min(m, nm - 1) * A.pld + r + lane];
-            g[m] = m < nm ? x : T(0);
-        }
+        for (int m = 0; m < NM; ++m) g[m] = gb[min(m, nm - 1) * A.pld + r + lane];
         const int32_t c0 = gg2_mode ? cb0[r + lane] : -1;
         const int p = static_cast<int>(pn);
         T ep, fp, lp;
         uint32_t kp;
         int pl;
+        // a masked lane takes a valid partner and |g|^2 = 0 (see pair_chunk)
         if (LDS) {
             pl = v ? p - p_lo : 0;
             const Pair2<T> ef = s_ef[pl];
-            ep = v ? ef.a : sd.eps;
-            fp = v ? ef.b : T(0);
-            lp = v ? s_l[pl] : ld;
-            kp = v ? s_kq[pl] : kd;
+            ep = ef.a;
+            fp = ef.b;
+            lp = s_l[pl];
+            kp = s_kq[pl];
         } else {
             pl = v ? p : d;
             const StateRec<T> sp = A.st[pl];
@@ -1048,6 +1072,11 @@ __device__ __forceinline__ void vjp_pair_chunk(const TiledArgs<T> &A, const T *_
         }
         const int q = PADQ ? static_cast<int>(kp - kd) + A.qoff : q_linear(kd, kp, A.nq0, A.nq1, A.nq2);
         const Pair2<T> *__restrict__ wq = A.hwN + static_cast<int64_t>(q) * nm;
+        Pair2<T> w[NM];
+#pragma unroll
+        for (int m = 0; m < NM; ++m) w[m] = wq[min(m, nm - 1)];
+        // all table gathers are in flight before the first is waited for
+        __builtin_amdgcn_sched_barrier(0);
         const T x = sd.eps - ep;
         const T ofp = T(1) - fp;
         const T dl = ld - lp;
@@ -1055,9 +1084,9 @@ __device__ __forceinline__ void vjp_pair_chunk(const TiledArgs<T> &A, const T *_
         double gv[NM];
 #pragma unroll
         for (int m = 0; m < NM; ++m) {
-            const Pair2<T> wm = wq[min(m, nm - 1)];
-            const T gm = v ? g[m] : T(0);
-            const T N = gm != T(0) ? wm.b : T(0);
+            const Pair2<T> wm = w[m];
+            const T gm = v && m < nm ? g[m] : T(0);
+            const T N = keep_or_zero(wm.b, gm != T(0));
             const T xa = x + wm.a, xe = x - wm.a;
             const T da = pair_gauss<T, TAB>(A, xa * xa, s_tab);
             const T dem = pair_gauss<T, TAB>(A, xe * xe, s_tab);

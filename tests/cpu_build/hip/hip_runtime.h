@@ -150,6 +150,7 @@ inline unsigned long long __ballot(int p) {
 #define __builtin_amdgcn_readfirstlane(x) (x)
 inline int __builtin_amdgcn_readlane(int v, int src) { return emu::xchg(v, src); }
 inline float __builtin_amdgcn_exp2f(float x) { return exp2f(x); }
+inline void __builtin_amdgcn_sched_barrier(int) {}
 // DPP moves with the controls the library uses: row_shr:1..15 within rows
 // of 16 lanes, row_bcast:15 (lane 15 of each row to the next row) and
 // row_bcast:31 (lane 31 to rows 2 and 3).  Rows outside row_mask, and lanes
