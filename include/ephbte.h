@@ -127,7 +127,11 @@ typedef struct {
     int32_t fp64_exp;          /* FP64 Gaussians of the pair-record pass: 1 = table
                                   exponential (256 powers of 2^(1/256) in LDS,
                                   default), 2 = polynomial only (no LDS reads)   */
-    int32_t reserved[1];       /* must be 0                                        */
+    int32_t table_order;       /* order of the {hw, N} table over the box of q
+                                  differences: 1 = the modes of one q adjacent
+                                  (one 16-byte row per mode, default),
+                                  2 = one block per mode (a wave's gathers of
+                                  one mode at neighbouring q share cache lines) */
 } ephbte_tuning;
 
 /* Build options.  Channel selection (paper: scattering-channel paragraph

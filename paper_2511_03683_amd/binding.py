@@ -48,7 +48,7 @@ class Tuning(ctypes.Structure):
     _fields_ = [("chunk_entries", ctypes.c_int32), ("block_threads", ctypes.c_int32),
                 ("xcd_map", ctypes.c_int32), ("batch_partners", ctypes.c_int32),
                 ("tile_entries", ctypes.c_int32), ("layout", ctypes.c_int32),
-                ("fp64_exp", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
+                ("fp64_exp", ctypes.c_int32), ("table_order", ctypes.c_int32)]
 
 
 _LIB = None
@@ -426,14 +426,15 @@ def update_g2(plan: Plan, g2):
 
 
 def set_tuning(plan: Plan, chunk_entries=0, block_threads=0, xcd_map=0, batch_partners=0,
-               tile_entries=0, layout=0, fp64_exp=0):
+               tile_entries=0, layout=0, fp64_exp=0, table_order=0):
     """Knobs left at 0 keep the plan's value; tile_entries=-1 restores its default;
     layout 1 = duplicated rows, 2 = single copy over entries, 3 = single copy
-    over pair records (B = 1 forward pass); fp64_exp 1 = table, 2 = polynomial."""
+    over pair records (B = 1 forward pass); fp64_exp 1 = table, 2 = polynomial;
+    table_order 1 = the modes of one q adjacent, 2 = one block per mode."""
     t = Tuning()
     t.chunk_entries, t.block_threads, t.xcd_map = int(chunk_entries), int(block_threads), int(xcd_map)
     t.batch_partners, t.tile_entries, t.layout = int(batch_partners), int(tile_entries), int(layout)
-    t.fp64_exp = int(fp64_exp)
+    t.fp64_exp, t.table_order = int(fp64_exp), int(table_order)
     _check(load_library().ephbte_set_tuning(plan.handle, ctypes.byref(t)), "set_tuning")
 
 

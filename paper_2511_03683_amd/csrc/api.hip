@@ -170,7 +170,10 @@ struct ephbte_plan_s {
     // phonon table indexed by padded k differences (one subtraction per entry)
     bool padq = false;
     int qoff = 0;
-    int64_t qpad_n = 0;         // padded q points
+    int64_t qpad_n = 0;         // rows of the box table (QBox)
+    QBox qbox{};
+    uint32_t qorg[3] = {0, 0, 0};   // per-axis origin of the shifted k coordinates
+    bool tab_mm = false;        // box table stored one block per mode
     int chunk_entries = 0;
     int64_t tile_entries = 0;   // 0: default target per tile
     int block_threads = 256;
@@ -437,6 +440,13 @@ void upload_chunks(ephbte_plan P, int64_t chunk_entries) {
     P->n_pr_tiles = static_cast<int64_t>(tp.size());
 }
 
+// element (q, mode) of the plan's {hw, N} table is at q tq + mode tm
+void table_strides(ephbte_plan P, int64_t *tq, int64_t *tm) {
+    const bool mm = P->padq && P->tab_mm;
+    *tq = mm ? 1 : P->nm;
+    *tm = mm ? P->qpad_n : 1;
+}
+
 template <typename T> Tables<T> tables(ephbte_plan P, const void *nph) {
     Tables<T> t;
     t.pnu = P->pnu;
@@ -468,6 +478,7 @@ template <typename T> TiledArgs<T> tiled_args(ephbte_plan P) {
     a.g2 = static_cast<const T *>(P->g2);
     a.st = static_cast<const StateRec<T> *>(P->st);
     a.hwN = static_cast<const Pair2<T> *>(P->hwN.p);
+    table_strides(P, &a.tq, &a.tm);
     a.chunk_beg = P->chunk_beg;
     a.chunk_dest = P->chunk_dest;
     a.dest_chunk = P->dest_chunk;
@@ -605,6 +616,7 @@ BArgs<T> batch_args(ephbte_plan P, const BTileRec *tiles, const int64_t *sub_off
     a.g2 = static_cast<const T *>(P->g2);
     a.st = static_cast<const StateRec<T> *>(P->st);
     a.hwN = static_cast<const Pair2<T> *>(P->hwN.p);
+    table_strides(P, &a.tq, &a.tm);
     a.btiles = tiles;
     a.sub_off = sub_off;
     a.S = P->S;
@@ -751,8 +763,8 @@ template <typename T> void enqueue_pack(ephbte_plan P, const void *nph, hipStrea
         const int64_t n = P->qpad_n * P->nm;
         nb = static_cast<unsigned>(std::max<int64_t>(std::min<int64_t>((n + 255) / 256, kPackBlocks), 1));
         hipLaunchKernelGGL((k_pack_hwN_pad<T>), dim3(nb), dim3(256), 0, s, static_cast<const T *>(P->hw),
-                           static_cast<const T *>(nph), static_cast<Pair2<T> *>(P->hwN.p), P->nq[0],
-                           P->nq[1], P->nq[2], P->nm, n, bmax);
+                           static_cast<const T *>(nph), static_cast<Pair2<T> *>(P->hwN.p), P->qbox, P->nm,
+                           P->qpad_n, P->tab_mm ? 1 : 0, bmax);
     } else {
         const int64_t n = nqm_of(P);
         nb = static_cast<unsigned>(std::max<int64_t>(std::min<int64_t>((n + 255) / 256, kPackBlocks), 1));
@@ -878,6 +890,8 @@ void enqueue_forward_noalloc(ephbte_plan P, const T *f, const void *nph, T *I, u
         TiledArgs<T> a = pair_args<T>(P);
         a.hwN = tab;
         a.padq = 0;
+        a.tq = P->nm;
+        a.tm = 1;
         launch_pairs<T>(P, a, f, part, sym_lds_bytes(P->dtype, P->sym_lds_states), s, false);
         hipLaunchKernelGGL((k_sym_finish<T>), dim3((P->S + 255) / 256), dim3(256), 0, s, a, f,
                            (const T *)part, E);
@@ -885,6 +899,8 @@ void enqueue_forward_noalloc(ephbte_plan P, const T *f, const void *nph, T *I, u
         TiledArgs<T> a = sym_args<T>(P);
         a.hwN = tab;
         a.padq = 0;
+        a.tq = P->nm;
+        a.tm = 1;
         constexpr int U = sizeof(T) == 8 ? 2 : 4;
         hipLaunchKernelGGL((k_fwd_sym<T, U, false>), dim3(static_cast<unsigned>(P->n_sym_tiles)), dim3(1024),
                            sym_lds_bytes(P->dtype, P->sym_lds_states), s, a, f, part);
@@ -894,6 +910,8 @@ void enqueue_forward_noalloc(ephbte_plan P, const T *f, const void *nph, T *I, u
         TiledArgs<T> a = tiled_args<T>(P);
         a.hwN = tab;
         a.padq = 0;
+        a.tq = P->nm;
+        a.tm = 1;
         hipLaunchKernelGGL((k_fwd_tiled<T, 4, 512, false>), dim3(tile_grid(P, P->n_tiles), 1),
                            dim3(P->block_threads), tiled_lds_bytes(P), s, a, f, int64_t(P->S), part, E);
         if (!P->fused)
@@ -1096,6 +1114,36 @@ size_t esize(ephbte_plan P) { return P->dtype == EPHBTE_F64 ? 8 : 4; }
 // loads land in this zero padding
 constexpr int64_t kEntryPad = 4096;
 
+// Shifted k coordinates of the box table: per axis an origin o and the
+// extent span of c = (k - o) mod Nq over the states.  Differences of c agree
+// with those of k modulo Nq, so any origin gives the same q; placing o at the
+// end of the largest unoccupied (circular) run of coordinates keeps a window
+// of states around k = 0 in one run instead of split across the wrap, which
+// makes span, and the box of all differences, as small as it can be.
+void q_box_of(const HostLayout &L, uint32_t org[3], int span[3]) {
+    for (int a = 0; a < 3; ++a) {
+        const int n = L.nq[a], sh = 20 - 10 * a;
+        std::vector<char> occ(n, 0);
+        for (int64_t s = 0; s < L.S; ++s) occ[(L.kq[s] >> sh) & 1023u] = 1;
+        int best_len = 0, best_end = 0;
+        for (int c = 0; c < n; ++c) {
+            if (occ[c]) continue;
+            int len = 0;
+            while (len < n && !occ[(c + len) % n]) ++len;
+            if (len > best_len) {
+                best_len = len;
+                best_end = (c + len) % n;
+            }
+            if (len == n) break;
+        }
+        org[a] = best_len > 0 && best_len < n ? static_cast<uint32_t>(best_end) : 0u;
+        int top = 0;
+        for (int c = 0; c < n; ++c)
+            if (occ[(c + static_cast<int>(org[a])) % n]) top = c;
+        span[a] = top + 1;
+    }
+}
+
 template <typename T> void upload_layout(ephbte_plan P, const ephbte_problem *pr, HostLayout &L) {
     size_t &acc = P->layout_bytes;
     const int64_t E = L.E, S = L.S;
@@ -1117,31 +1165,6 @@ template <typename T> void upload_layout(ephbte_plan P, const ephbte_problem *pr
         HIPC(hipMemcpy(P->g2, g.data(), sizeof(T) * E, hipMemcpyHostToDevice));
     }
     {
-        // Padded coordinates are taken from a per-axis origin o: c' = (c - o) mod Nq.
-        // Differences of c' agree with those of c modulo Nq, so the padded table
-        // gives the same q for any origin; placing o at the end of the largest
-        // unoccupied (circular) run of coordinates keeps the states of a window
-        // around k = 0 in one box instead of split across the wrap, so the
-        // differences of all pairs fall in one compact region of the table (one
-        // image per q), which is what the L2 has to hold.
-        uint32_t org[3] = {0, 0, 0};
-        for (int a = 0; a < 3; ++a) {
-            const int n = L.nq[a], sh = 20 - 10 * a;
-            std::vector<char> occ(n, 0);
-            for (int64_t s = 0; s < S; ++s) occ[(L.kq[s] >> sh) & 1023u] = 1;
-            int best_len = 0, best_end = 0;
-            for (int c = 0; c < n; ++c) {
-                if (occ[c]) continue;
-                int len = 0;
-                while (len < n && !occ[(c + len) % n]) ++len;
-                if (len > best_len) {
-                    best_len = len;
-                    best_end = (c + len) % n;
-                }
-                if (len == n) break;
-            }
-            org[a] = best_len > 0 && best_len < n ? static_cast<uint32_t>(best_end) : 0u;
-        }
         std::vector<StateRec<T>> st(S);
         for (int64_t s = 0; s < S; ++s) {
             std::memset(&st[s], 0, sizeof(StateRec<T>));
@@ -1151,9 +1174,10 @@ template <typename T> void upload_layout(ephbte_plan P, const ephbte_problem *pr
                 uint32_t c[3];
                 for (int a = 0; a < 3; ++a) {
                     const uint32_t n = static_cast<uint32_t>(L.nq[a]);
-                    c[a] = (((L.kq[s] >> (20 - 10 * a)) & 1023u) + n - org[a]) % n;
+                    c[a] = (((L.kq[s] >> (20 - 10 * a)) & 1023u) + n - P->qorg[a]) % n;
                 }
-                st[s].kqp = (c[0] * (2u * L.nq[1]) + c[1]) * (2u * L.nq[2]) + c[2];
+                const uint32_t b1 = static_cast<uint32_t>(P->qbox.b[1]), b2 = static_cast<uint32_t>(P->qbox.b[2]);
+                st[s].kqp = (c[0] * b1 + c[1]) * b2 + c[2];
             }
         }
         HIPC(hipMemcpy(P->st, st.data(), sizeof(StateRec<T>) * S, hipMemcpyHostToDevice));
@@ -1599,7 +1623,7 @@ void enqueue_phonon_vjp_f(ephbte_plan P, const T *u, const T *N, const T *mu, T 
     const int64_t n = P->padq ? P->qpad_n * P->nm : nqm_of(P);
     Vec4<T> *tab = static_cast<Vec4<T> *>(P->ph_tab4.p);
     hipLaunchKernelGGL((k_pack_hwNmu<T>), dim3(grid_of(n)), dim3(256), 0, s, static_cast<const T *>(P->hw), N, mu,
-                       tab, P->padq ? 1 : 0, P->nq[0], P->nq[1], P->nq[2], P->nm, n);
+                       tab, P->padq ? 1 : 0, P->qbox, P->nm, n);
     TiledArgs<T> a = tiled_args<T>(P);
     T *part = static_cast<T *>(P->part.p);
     const double Kp = 2.0 * kPi / (kHbar * P->nk) / (P->sigma * std::sqrt(2.0 * kPi));
@@ -2161,12 +2185,20 @@ ephbte_status ephbte_build_channels(const ephbte_problem *problem, const ephbte_
         P->sigma = problem->sigma;
         P->nqnorm = problem->n_q_norm;
         {
-            const int64_t qp = int64_t(2) * L.nq[0] * 2 * L.nq[1] * 2 * L.nq[2];
+            int span[3];
+            q_box_of(L, P->qorg, span);
+            int64_t rows = 1;
+            for (int a = 0; a < 3; ++a) {
+                P->qbox.n[a] = L.nq[a];
+                P->qbox.b[a] = 2 * span[a] - 1;
+                P->qbox.h[a] = span[a] - 1;
+                rows *= P->qbox.b[a];
+            }
             const size_t pair_bytes = P->dtype == EPHBTE_F64 ? 16 : 8;
-            if (qp * L.n_modes * static_cast<int64_t>(pair_bytes) <= (int64_t(256) << 20)) {
+            if (rows * L.n_modes * static_cast<int64_t>(pair_bytes) <= (int64_t(256) << 20)) {
                 P->padq = true;
-                P->qpad_n = qp;
-                P->qoff = (L.nq[0] * (2 * L.nq[1]) + L.nq[1]) * (2 * L.nq[2]) + L.nq[2];
+                P->qpad_n = rows;
+                P->qoff = (P->qbox.h[0] * P->qbox.b[1] + P->qbox.h[1]) * P->qbox.b[2] + P->qbox.h[2];
             }
         }
         P->row_ptr = L.row_ptr;
@@ -2600,8 +2632,8 @@ ephbte_status ephbte_set_tuning(ephbte_plan plan, const ephbte_tuning *tuning) {
         if (pt != 0 && (pt < 16 || pt > 1024 || batch_lds_bytes(plan, pt) > plan->lds_max))
             return fail(EPHBTE_INVALID_ARGUMENT,
                         "batch_partners must be in [16, 1024] and fit the LDS of one workgroup");
-        for (int r : tuning->reserved)
-            if (r != 0) return fail(EPHBTE_INVALID_ARGUMENT, "reserved tuning fields must be 0");
+        if (tuning->table_order < 0 || tuning->table_order > 2)
+            return fail(EPHBTE_INVALID_ARGUMENT, "table_order must be 0 (keep), 1 or 2");
         if (tuning->tile_entries < -1)
             return fail(EPHBTE_INVALID_ARGUMENT, "tile_entries must be -1 (default), 0 (keep) or > 0");
         if (tuning->fp64_exp < 0 || tuning->fp64_exp > 2)
@@ -2620,6 +2652,7 @@ ephbte_status ephbte_set_tuning(ephbte_plan plan, const ephbte_tuning *tuning) {
         if (tuning->tile_entries) plan->tile_entries = tuning->tile_entries > 0 ? tuning->tile_entries : 0;
         if (tuning->layout) plan->layout = tuning->layout;
         if (tuning->fp64_exp) plan->exp_table = tuning->fp64_exp == 1;
+        if (tuning->table_order) plan->tab_mm = tuning->table_order == 2;
         upload_chunks(plan, ce);
         if (pt != 0) upload_btiles(plan, pt);
         free_graphs(plan);

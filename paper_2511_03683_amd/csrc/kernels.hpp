@@ -35,9 +35,10 @@
 namespace ephbte {
 
 // kq:  k in q-grid units, 10 bits per axis (a0 << 20 | a1 << 10 | a2)
-// kqp: the same k as a linear index on a grid padded to (2 Nq0, 2 Nq1, 2 Nq2),
-//      so that kqp_p - kqp_d + offset is the padded index of q = k_p - k_d
-//      (each axis difference + Nq lies in [1, 2 Nq), so no borrow crosses axes)
+// kqp: the same k in shifted coordinates c (0 .. span - 1 per axis) as the
+//      linear index (c0 b1 + c1) b2 + c2 on the (b0, b1, b2) = 2 span - 1 box
+//      of QBox, so that kqp_p - kqp_d + offset is the box row of q = k_p - k_d
+//      (each axis difference + span - 1 lies in [0, b), so no borrow crosses axes)
 template <typename T> struct StateRec;
 template <> struct alignas(16) StateRec<double> {
     double eps;
@@ -321,15 +322,17 @@ template <typename T> struct TiledArgs {
     const uint32_t *__restrict__ pnu;
     const T *__restrict__ g2;
     const StateRec<T> *__restrict__ st;
-    const Pair2<T> *__restrict__ hwN;   // [Nq * n_modes] {hw, N}
+    const Pair2<T> *__restrict__ hwN;   // {hw, N} of (q, mode) at hwN[q tq + mode tm]
+    int64_t tq, tm;                     // (n_modes, 1): the modes of one q adjacent;
+                                        // (1, table rows): one block per mode
     const int64_t *__restrict__ chunk_beg;
     const int32_t *__restrict__ chunk_dest;
     const int32_t *__restrict__ dest_chunk;
     const TileRec *__restrict__ tiles;
     int64_t n_chunks;
     int S, nm, nq0, nq1, nq2, lds_states;
-    int padq;          // 1: hwN is the padded table indexed by kqp differences
-    int qoff;          // padded index of q = 0 difference
+    int padq;          // 1: hwN is the box table of QBox, indexed by kqp differences
+    int qoff;          // box row of the q = 0 difference
     T mc, K;
     const double *__restrict__ e2tab;   // 2^(j/256), j = 0 .. 255 (FP64 kernels)
     double mc256;                       // 256 mc, the table exponential's scale
@@ -425,28 +428,49 @@ __global__ void k_pack_hwN(const T *__restrict__ hw, const T *__restrict__ nph,
     block_max_to(m, bmax + blockIdx.x);
 }
 
-// Padded table: entry (qp, nu) holds {hw, N} of q = (c - Nq) mod Nq per axis,
-// where c are the axis coordinates of qp on the (2 Nq0, 2 Nq1, 2 Nq2) grid.
-// The modes of one q are contiguous, so partners at neighbouring k (consecutive
-// q along the last axis) read neighbouring table bytes.
+// The padded q table.  States carry k in shifted coordinates c (per axis, 0
+// .. span - 1 after a per-axis origin); a pair's difference c_p - c_d lies in
+// [-(span - 1), span - 1], so the row x = c_p - c_d + (span - 1) of a
+// (2 span - 1)-point axis names it without a modulo, and the three axes give
+// the row of one box, qp = (x0 b1 + x1) b2 + x2.  The q it stands for is
+// (x - (span - 1)) mod Nq per axis.  The box holds every difference between
+// two states, so every row is filled; its size follows the extent of the
+// states in k, not the q grid.
+struct QBox {
+    int n[3];   // q grid
+    int b[3];   // box axis lengths, 2 span - 1
+    int h[3];   // span - 1
+};
+
+__device__ __forceinline__ int64_t box_q(int64_t qp, const QBox &B) {
+    int x[3];
+    x[2] = static_cast<int>(qp % B.b[2]);
+    qp /= B.b[2];
+    x[1] = static_cast<int>(qp % B.b[1]);
+    x[0] = static_cast<int>(qp / B.b[1]);
+    int64_t q = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        int v = x[a] - B.h[a];
+        v += v < 0 ? B.n[a] : 0;
+        q = q * B.n[a] + v;
+    }
+    return q;
+}
+
+// {hw, N} of every (row, mode) of the box: entry i is (qp, nu) with
+// i = qp nm + nu (mode_major = 0) or i = nu rows + qp (mode_major = 1).
 template <typename T>
 __global__ void k_pack_hwN_pad(const T *__restrict__ hw, const T *__restrict__ nph,
-                               Pair2<T> *__restrict__ out, int n0, int n1, int n2, int nm,
-                               int64_t n, double *bmax) {
+                               Pair2<T> *__restrict__ out, QBox B, int nm, int64_t rows, int mode_major,
+                               double *bmax) {
     double m = 0.0;
+    const int64_t n = rows * nm;
     for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
          i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        const int nu = static_cast<int>(i % nm);
-        int64_t qp = i / nm;
-        const int c2 = static_cast<int>(qp % (2 * n2));
-        qp /= 2 * n2;
-        const int c1 = static_cast<int>(qp % (2 * n1));
-        const int c0 = static_cast<int>(qp / (2 * n1));
-        int a0 = c0 - n0, a1 = c1 - n1, a2 = c2 - n2;
-        a0 += a0 < 0 ? n0 : 0;
-        a1 += a1 < 0 ? n1 : 0;
-        a2 += a2 < 0 ? n2 : 0;
-        const int64_t q = (static_cast<int64_t>(a0) * n1 + a1) * n2 + a2;
+        const int nu = static_cast<int>(mode_major ? i / rows : i % nm);
+        const int64_t qp = mode_major ? i % rows : i / nm;
+        const int64_t q = box_q(qp, B);
         Pair2<T> v;
         v.a = hw[q * nm + nu];
         v.b = nph[q * nm + nu];
@@ -522,7 +546,7 @@ __device__ __forceinline__ void fwd_chunk2(const TiledArgs<T> &A, const T *__res
             }
             const int q = PADQ ? static_cast<int>(kp - kd) + A.qoff
                                : q_linear(kd, kp, A.nq0, A.nq1, A.nq2);
-            const Pair2<T> w = A.hwN[static_cast<int64_t>(q) * A.nm + (pn[u] & 7u)];
+            const Pair2<T> w = A.hwN[static_cast<int64_t>(q) * A.tq + static_cast<int64_t>(pn[u] & 7u) * A.tm];
             if constexpr (M) {
                 // a table entry without channels may hold a non-finite N, so both
                 // fields are replaced (using both keeps the {hw, N} pair one
@@ -701,7 +725,7 @@ __device__ __forceinline__ void sym_chunk(const TiledArgs<T> &A, const T *__rest
             }
             const int q = PADQ ? static_cast<int>(kp - kd) + A.qoff
                                : q_linear(kd, kp, A.nq0, A.nq1, A.nq2);
-            const Pair2<T> w = A.hwN[static_cast<int64_t>(q) * A.nm + (pn[u] & 7u)];
+            const Pair2<T> w = A.hwN[static_cast<int64_t>(q) * A.tq + static_cast<int64_t>(pn[u] & 7u) * A.tm];
             if constexpr (M) {
                 // a table entry without channels may hold a non-finite N; the
                 // masked lanes then add zero to partner slot 0 (or state p)
@@ -893,10 +917,10 @@ __device__ __forceinline__ void pair_chunk(const TiledArgs<T> &A, const T *__res
             fp = fb[pl];
         }
         const int q = PADQ ? static_cast<int>(kp - kd) + A.qoff : q_linear(kd, kp, A.nq0, A.nq1, A.nq2);
-        const Pair2<T> *__restrict__ wq = A.hwN + static_cast<int64_t>(q) * nm;
+        const Pair2<T> *__restrict__ wq = A.hwN + static_cast<int64_t>(q) * A.tq;
         Pair2<T> w[NM];
 #pragma unroll
-        for (int m = 0; m < NM; ++m) w[m] = wq[min(m, nm - 1)];
+        for (int m = 0; m < NM; ++m) w[m] = wq[min(m, nm - 1) * A.tm];
         // the next batch's stream loads are issued after this batch's table
         // gathers: loads complete in issue order for the wait counter, so
         // waiting for the gathers does not wait for the stream.  The
@@ -1071,10 +1095,10 @@ __device__ __forceinline__ void vjp_pair_chunk(const TiledArgs<T> &A, const T *_
             lp = lb[pl];
         }
         const int q = PADQ ? static_cast<int>(kp - kd) + A.qoff : q_linear(kd, kp, A.nq0, A.nq1, A.nq2);
-        const Pair2<T> *__restrict__ wq = A.hwN + static_cast<int64_t>(q) * nm;
+        const Pair2<T> *__restrict__ wq = A.hwN + static_cast<int64_t>(q) * A.tq;
         Pair2<T> w[NM];
 #pragma unroll
-        for (int m = 0; m < NM; ++m) w[m] = wq[min(m, nm - 1)];
+        for (int m = 0; m < NM; ++m) w[m] = wq[min(m, nm - 1) * A.tm];
         // all table gathers are in flight before the first is waited for
         __builtin_amdgcn_sched_barrier(0);
         const T x = sd.eps - ep;
@@ -1307,7 +1331,7 @@ __device__ __forceinline__ void vjp_chunk2(const TiledArgs<T> &A, const T *__res
             const T lp = lb[p];
             const int q = PADQ ? static_cast<int>(kp - kd) + A.qoff
                                : q_linear(kd, kp, A.nq0, A.nq1, A.nq2);
-            const Pair2<T> w = A.hwN[static_cast<int64_t>(q) * A.nm + (pn[u] & 7u)];
+            const Pair2<T> w = A.hwN[static_cast<int64_t>(q) * A.tq + static_cast<int64_t>(pn[u] & 7u) * A.tm];
             if constexpr (M) {
                 // a table entry without channels may hold a non-finite N
                 o.wn[u].a = v ? w.a : T(0);
@@ -1585,6 +1609,7 @@ template <typename T> struct BArgs {
     const T *__restrict__ g2;
     const StateRec<T> *__restrict__ st;
     const Pair2<T> *__restrict__ hwN;
+    int64_t tq, tm;                          // as in TiledArgs
     const BTileRec *__restrict__ btiles;
     const int64_t *__restrict__ sub_off;   // per destination: n_sub + 1 entry offsets
     int S, nm, nq0, nq1, nq2, pt;
@@ -1693,7 +1718,7 @@ __global__ __launch_bounds__(512) void k_fwd_batched(BArgs<T> A, const T *__rest
                         const StateRec<T> sp = s_ek[pl];
                         const int q = A.padq ? static_cast<int>(sp.kqp - sd.kqp) + A.qoff
                                              : q_linear(sd.kq, sp.kq, A.nq0, A.nq1, A.nq2);
-                        const Pair2<T> wn = A.hwN[static_cast<int64_t>(q) * A.nm + (pn & 7u)];
+                        const Pair2<T> wn = A.hwN[static_cast<int64_t>(q) * A.tq + static_cast<int64_t>(pn & 7u) * A.tm];
                         const T de = sd.eps - sp.eps;
                         const T xa = de + wn.a, xe = de - wn.a;
                         const T da = gauss_exp(xa * xa * A.mc);
@@ -1854,7 +1879,7 @@ __global__ __launch_bounds__(512) void k_vjp_batched(BArgs<T> A, const T *__rest
                         const StateRec<T> sp = s_ek[pl];
                         const int q = A.padq ? static_cast<int>(sp.kqp - sd.kqp) + A.qoff
                                              : q_linear(sd.kq, sp.kq, A.nq0, A.nq1, A.nq2);
-                        const Pair2<T> wn = A.hwN[static_cast<int64_t>(q) * A.nm + (pn & 7u)];
+                        const Pair2<T> wn = A.hwN[static_cast<int64_t>(q) * A.tq + static_cast<int64_t>(pn & 7u) * A.tm];
                         const T de = sd.eps - sp.eps;
                         const T xa = de + wn.a, xe = de - wn.a;
                         const T da = gauss_exp(xa * xa * A.mc);
@@ -2112,26 +2137,15 @@ __global__ __launch_bounds__(256) void k_phonon_bins_adj(PhArgs<T> A, const T *_
 }
 
 // {hw, N, mu} per (q, mode) for the reverse of the phonon-side rate: the
-// padded table of k_pack_hwN_pad (pad != 0) or the plain one.
+// box of k_pack_hwN_pad with the modes of one row adjacent (pad != 0), or the
+// plain table.
 template <typename T>
 __global__ void k_pack_hwNmu(const T *__restrict__ hw, const T *__restrict__ nph, const T *__restrict__ mu,
-                             Vec4<T> *__restrict__ out, int pad, int n0, int n1, int n2, int nm, int64_t n) {
+                             Vec4<T> *__restrict__ out, int pad, QBox B, int nm, int64_t n) {
     for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
          i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         int64_t src = i;
-        if (pad) {
-            const int nu = static_cast<int>(i % nm);
-            int64_t qp = i / nm;
-            const int c2 = static_cast<int>(qp % (2 * n2));
-            qp /= 2 * n2;
-            const int c1 = static_cast<int>(qp % (2 * n1));
-            const int c0 = static_cast<int>(qp / (2 * n1));
-            int a0 = c0 - n0, a1 = c1 - n1, a2 = c2 - n2;
-            a0 += a0 < 0 ? n0 : 0;
-            a1 += a1 < 0 ? n1 : 0;
-            a2 += a2 < 0 ? n2 : 0;
-            src = ((static_cast<int64_t>(a0) * n1 + a1) * n2 + a2) * nm + nu;
-        }
+        if (pad) src = box_q(i / nm, B) * nm + i % nm;
         Vec4<T> v;
         v.x = hw[src];
         v.y = nph[src];

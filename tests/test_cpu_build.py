@@ -137,16 +137,17 @@ def _round32(s):
     return r
 
 
-@pytest.mark.parametrize("layout,dtype,fexp", [(2, "f64", 0), (1, "f64", 0), (2, "f32", 0), (3, "f64", 1),
-                                               (3, "f64", 2), (3, "f32", 0)])
-def test_forward_single_vector(driver, tmp_path, layout, dtype, fexp):
+@pytest.mark.parametrize("layout,dtype,fexp,order", [(2, "f64", 0, 1), (1, "f64", 0, 1), (2, "f32", 0, 1),
+                                                     (3, "f64", 1, 1), (3, "f64", 2, 1), (3, "f32", 0, 1),
+                                                     (3, "f64", 1, 2), (2, "f64", 0, 2), (1, "f32", 0, 2)])
+def test_forward_single_vector(driver, tmp_path, layout, dtype, fexp, order):
     """Single-copy (layout 2: one entry per channel; layout 3: pair records,
     FP64 Gaussians from the table or the polynomial exponential) and per-row
-    (layout 1) forward passes, B = 1."""
+    (layout 1) forward passes, B = 1, with the {hw, N} table in either order."""
     s = synth.multiband_system()
     f = synth.random_occupations(s, 3)
     nph = s.nph(300.0)
-    _write(tmp_path, s, dtype, f=f, nph=nph, B=1, layout=layout, fp64_exp=fexp)
+    _write(tmp_path, s, dtype, f=f, nph=nph, B=1, layout=layout, fp64_exp=fexp, table_order=order)
     _run(driver, tmp_path, "forward")
     # one launch of the forward kernel, bracketed by the timing events
     assert _out(tmp_path, "timing")[1] == 1
@@ -158,29 +159,31 @@ def test_forward_single_vector(driver, tmp_path, layout, dtype, fexp):
         assert nerr(_out(tmp_path, "I"), oracle.collision(r, f32, n32)) <= TOL32
 
 
-@pytest.mark.parametrize("B", [3, 9])
-def test_forward_batched(driver, tmp_path, B):
+@pytest.mark.parametrize("B,order", [(3, 1), (9, 1), (3, 2), (9, 2)])
+def test_forward_batched(driver, tmp_path, B, order):
     """Per-row pass for B < 8 and the batched pass (LDS tiles, run merge over
-    lanes) for B >= 8, every column against the oracle."""
+    lanes) for B >= 8, every column against the oracle, with the {hw, N}
+    table in either order."""
     s = synth.multiband_system()
     F = np.stack([synth.random_occupations(s, 10 + b) for b in range(B)])
     nph = s.nph(300.0)
-    _write(tmp_path, s, f=F, nph=nph, B=B)
+    _write(tmp_path, s, f=F, nph=nph, B=B, table_order=order)
     _run(driver, tmp_path, "forward")
     got = _out(tmp_path, "I", (B, s.n_states))
     for b in range(B):
         assert nerr(got[b], oracle.collision(s, F[b], nph)) <= TOL64, b
 
 
-@pytest.mark.parametrize("B", [1, 9])
-def test_vjp(driver, tmp_path, B):
+@pytest.mark.parametrize("B,order", [(1, 1), (9, 1), (1, 2), (9, 2)])
+def test_vjp(driver, tmp_path, B, order):
     """Reverse pass, B = 1 (per-row kernel) and batched (DPP sums over the
-    vectors): dL/df per vector and dL/d|g|^2 summed over the vectors."""
+    vectors): dL/df per vector and dL/d|g|^2 summed over the vectors, with
+    the {hw, N} table in either order."""
     s = synth.multiband_system()
     F = np.stack([synth.random_occupations(s, 20 + b) for b in range(B)])
     lam = np.random.default_rng(4).normal(size=(B, s.n_states))
     nph = s.nph(300.0)
-    _write(tmp_path, s, f=F, lam=lam, nph=nph, B=B)
+    _write(tmp_path, s, f=F, lam=lam, nph=nph, B=B, table_order=order)
     _run(driver, tmp_path, "vjp")
     gf = _out(tmp_path, "gf", (B, s.n_states))
     gg = _out(tmp_path, "gg2")
@@ -447,6 +450,7 @@ def test_fp32_passes(driver, tmp_path, mode, B):
 
 
 UNWRITTEN_CASES = [("forward", dict(B=1)), ("forward", dict(B=1, layout=1)), ("forward", dict(B=9)),
+                   ("forward", dict(B=1, table_order=2)), ("vjp", dict(B=1, table_order=2)),
                    ("vjp", dict(B=1)), ("vjp", dict(B=9)), ("phonon", dict()),
                    ("rt", dict(B=1, dt=0.5, steps=2)),
                    ("field", dict(B=1, dt=1.0, steps=2, rates=[0.06, -0.035, 0.02])),
@@ -716,17 +720,18 @@ def test_coupled_adjoint(driver, tmp_path, name, ce):
     assert nerr(_out(tmp_path, "gg2"), rg) <= TOL64
 
 
-@pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_pair_records_with_rounded_up_mode_count(driver, tmp_path, dtype):
+@pytest.mark.parametrize("dtype,order", [("f64", 1), ("f32", 1), ("f64", 2), ("f32", 2)])
+def test_pair_records_with_rounded_up_mode_count(driver, tmp_path, dtype, order):
     """Five modes: the pair-record kernels run with their mode-slot count
     rounded up to six, the sixth slot re-reading the fifth and counting as
-    empty.  Forward and reverse (dL/df, dL/d|g|^2) against the oracle."""
+    empty.  Forward and reverse (dL/df, dL/d|g|^2) against the oracle, with
+    the {hw, N} table in either order."""
     s = synth.tb_system(kn=24, qn=12, target_states=300, einstein_eV=(0.02, 0.05))
     assert s.n_modes == 5
     f = 0.05 + 0.9 * synth.random_occupations(s, 101)
     nph = s.nph(300.0)
     lam = np.random.default_rng(102).normal(size=s.n_states)
-    _write(tmp_path, s, dtype, f=f, lam=lam, nph=nph, B=1, layout=3)
+    _write(tmp_path, s, dtype, f=f, lam=lam, nph=nph, B=1, layout=3, table_order=order)
     _run(driver, tmp_path, "forward", fill="random:7")
     _run(driver, tmp_path, "vjp", fill="random:8")
     r = s if dtype == "f64" else _round32(s)
@@ -745,8 +750,8 @@ def test_pair_records_with_rounded_up_mode_count(driver, tmp_path, dtype):
     assert nerr(_out(tmp_path, "gg2"), rg) <= tol
 
 
-@pytest.mark.parametrize("layout,fill", [(3, "random:9"), (2, None)])
-def test_vjp_six_modes(driver, tmp_path, layout, fill):
+@pytest.mark.parametrize("layout,fill,order", [(3, "random:9", 1), (2, None, 1), (3, "random:10", 2)])
+def test_vjp_six_modes(driver, tmp_path, layout, fill, order):
     """Reverse pass on the six-mode tight-binding system: over pair records
     (whose consecutive channels are written as 16-byte pairs) and over
     entries; every |g|^2 gradient is overwritten (the buffer starts at 0.5)."""
@@ -754,7 +759,7 @@ def test_vjp_six_modes(driver, tmp_path, layout, fill):
     f = synth.random_occupations(s, 111)
     lam = np.random.default_rng(112).normal(size=s.n_states)
     nph = s.nph(300.0)
-    _write(tmp_path, s, f=f, lam=lam, nph=nph, B=1, layout=layout, gg2_fill=0.5)
+    _write(tmp_path, s, f=f, lam=lam, nph=nph, B=1, layout=layout, gg2_fill=0.5, table_order=order)
     _run(driver, tmp_path, "vjp", fill=fill)
     rf, rg = oracle.collision_vjp(s, f, nph, lam)
     assert nerr(_out(tmp_path, "gf"), rf) <= TOL64
