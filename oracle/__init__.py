@@ -22,6 +22,10 @@ Contents, each following the paper (arXiv 2511.03683):
 * collision_brute(sys, f, nph)  -- Eq. 2 written out over the full q grid,
   all bands and modes, for tiny grids (numpy; independent of the C code).
 * collision_vjp(...)            -- hand-derived reverse mode of Eq. 2.
+* collision_bose(sys, n, nph), collision_bose_vjp(...) -- the same golden
+  rule with Bose factors (1 + n) for phonon modes as the states: three-phonon
+  scattering on the channel list (Discussion: other mechanisms on the same
+  data structure), written out in numpy, and its hand-derived reverse mode.
 * phonon_rate(sys, f, nph)      -- dN/dt of every phonon (q, mode) from the
   same channel list: the phonon side of the four golden-rule processes
   behind Eq. 2 (coupled electron-phonon dynamics; the paper cites it, the
@@ -276,6 +280,79 @@ def collision_elastic(sys, f, modes=None, g2=None):
     np.add.at(I, ci, X)
     np.add.at(I, cj, -X)
     return I
+
+
+def _bose_terms(sys, n, nph, g2):
+    """Per orientation (destination d, partner p) of every channel: the arrays
+    the Bose collision integral and its reverse mode are built from."""
+    ci, cj, nu, qij, qji = _channel_geometry(sys)
+    hw = np.asarray(sys.hw, np.float64)
+    N = np.asarray(nph, np.float64)
+    eps = np.asarray(sys.eps, np.float64)
+    g = np.asarray(sys.g2 if g2 is None else g2, np.float64)
+    sig = float(sys.sigma)
+    G = lambda x: np.exp(-0.5 * (x / sig) ** 2) / (sig * np.sqrt(2.0 * np.pi))
+    C = 2.0 * np.pi / HBAR_EV_FS / float(sys.n_q_norm)
+    out = []
+    for d, p, q in ((ci, cj, qij), (cj, ci, qji)):
+        w, Nq = hw[q, nu], N[q, nu]
+        x = eps[d] - eps[p]
+        Gp, Gm = G(x + w), G(x - w)
+        out.append((d, p, q, Gp, Gm, Nq))
+    return out, g, C
+
+
+def collision_bose(sys, n, nph, g2=None):
+    """Phonon-phonon (three-phonon) collision integral [S] in FP64 over the
+    channel list (Discussion: other scattering mechanisms on the same data
+    structure).  The states are phonon modes with energies e = eps and
+    occupations n; a channel (i, j, nu) couples modes d and p through the
+    third phonon (nu, q = q_p - q_d, energy w, occupation N), and the golden
+    rule of Eq. 2 applies with Bose factors: a mode that receives a quantum
+    carries the enhancement 1 + n where a fermion carries 1 - f.  For
+    x = e_d - e_p the four processes give mode d
+      G(x - w) [n_p N (1 + n_d) - n_d (1 + n_p)(N + 1)]   (p + phonon <-> d)
+      G(x + w) [n_p (1 + n_d)(N + 1) - n_d N (1 + n_p)]   (p <-> d + phonon)
+    times C |V|^2, C = 2 pi / (hbar N_q), summed over both orientations of
+    every channel."""
+    n = np.asarray(n, np.float64)
+    terms, g, C = _bose_terms(sys, n, nph, g2)
+    I = np.zeros(int(sys.n_states))
+    for d, p, q, Gp, Gm, Nq in terms:
+        gain = n[p] * (1.0 + n[d])
+        loss = n[d] * (1.0 + n[p])
+        T = C * g * (Gm * (gain * Nq - loss * (Nq + 1.0)) + Gp * (gain * (Nq + 1.0) - loss * Nq))
+        np.add.at(I, d, T)
+    return I
+
+
+def collision_bose_vjp(sys, n, nph, lam, g2=None):
+    """(dL/dn [S], dL/dg2 [n_channels], dL/dN [Nq, n_modes]) for
+    L = sum_d lam_d I_d of collision_bose.  Per orientation the term is
+    C |V|^2 (A gain - B loss) with A = G(x - w) N + G(x + w)(N + 1),
+    B = G(x - w)(N + 1) + G(x + w) N, gain = n_p (1 + n_d), loss = n_d (1 + n_p);
+    its derivatives: d/dn_d = C |V|^2 (A n_p - B (1 + n_p)),
+    d/dn_p = C |V|^2 (A (1 + n_d) - B n_d), d/d|V|^2 = C (A gain - B loss),
+    d/dN = C |V|^2 (G(x - w) + G(x + w)) (gain - loss)."""
+    n = np.asarray(n, np.float64)
+    lam = np.asarray(lam, np.float64)
+    terms, g, C = _bose_terms(sys, n, nph, g2)
+    nm = int(sys.n_modes)
+    nu = np.asarray(sys.ch_nu, np.int64)
+    gn = np.zeros(int(sys.n_states))
+    gg = np.zeros(g.size)
+    gN = np.zeros(np.asarray(sys.hw).size)
+    for d, p, q, Gp, Gm, Nq in terms:
+        A = Gm * Nq + Gp * (Nq + 1.0)
+        B = Gm * (Nq + 1.0) + Gp * Nq
+        gain = n[p] * (1.0 + n[d])
+        loss = n[d] * (1.0 + n[p])
+        l = lam[d]
+        np.add.at(gn, d, l * C * g * (A * n[p] - B * (1.0 + n[p])))
+        np.add.at(gn, p, l * C * g * (A * (1.0 + n[d]) - B * n[d]))
+        gg += l * C * (A * gain - B * loss)
+        np.add.at(gN, q * nm + nu, l * C * g * (Gm + Gp) * (gain - loss))
+    return gn, gg, gN.reshape(np.asarray(sys.hw).shape)
 
 
 def collision_brute(sys, f, nph):

@@ -532,6 +532,39 @@ def tb_two_band_system(**kw) -> System:
     return tb_system(**kw)
 
 
+def ph_ph_system(n=6, a=LATTICE_A, debye_kms=(4.0, 7.0), einstein_eV=(0.030,), sigma=0.002,
+                 hw_min=1e-3, seed=31, name=None) -> System:
+    """Phonon-phonon (three-phonon) scattering on the channel-list layout
+    (Bose plans): the states are the phonon modes (q, branch) of an n^3 grid
+    with hbar omega >= hw_min (the acoustic modes at q = 0 are left out), with
+    energies from the same Debye/Einstein model as the e-ph systems; a
+    channel (i, j, nu) couples modes i and j through the third phonon of
+    branch nu at q = q_j - q_i, whose energy is the table hw of the same
+    model.  Every pair and third branch with hbar omega >= hw_min is a
+    channel; |V3|^2 is the seeded lognormal of the e-ph systems (eV^2, the
+    same scale: a stand-in, not anharmonic data)."""
+    qgrid = (n, n, n)
+    hw = phonon_table(qgrid, a, debye_kms, einstein_eV)
+    nq, nb = hw.shape
+    qi, bi = np.meshgrid(np.arange(nq), np.arange(nb), indexing="ij")
+    keep = hw[qi, bi] >= hw_min
+    state_k = qi[keep].astype(np.int32)
+    band = bi[keep].astype(np.int8)
+    eps = hw[qi, bi][keep].astype(np.float64)
+    key = (state_k.astype(np.int64) * nb + band).astype(np.int64)
+    ch = enumerate_channels(state_k, qgrid, qgrid, hw, key, seed, hw_min=hw_min)
+    return System(name=name or f"phph{n}", kgrid=qgrid, qgrid=qgrid, state_k=state_k, state_band=band,
+                  eps=eps, n_modes=nb, hw=hw, ch_i=ch[0], ch_j=ch[1], ch_nu=ch[2], g2=ch[3], sigma=sigma,
+                  n_q_norm=float(nq), lattice_a=a, meta=dict(seed=seed, statistics="bose"))
+
+
+def bose_occupations(system: System, T: float = 300.0, seed: int = 5, amp: float = 0.3) -> np.ndarray:
+    """Bose-Einstein occupations of the modes at T, each scaled by a seeded
+    factor in [1 - amp, 1 + amp] (out of equilibrium)."""
+    rng = np.random.default_rng(seed)
+    return bose_einstein(np.asarray(system.eps, np.float64), T) * (1.0 + amp * (2.0 * rng.uniform(size=system.n_states) - 1.0))
+
+
 def multiband_system(kn=6, qn=3, nb=2, n_k=24, e_max=0.25, a=LATTICE_A,
                      debye_kms=(4.0,), einstein_eV=(0.02, 0.045), sigma=0.015,
                      seed=19) -> System:

@@ -760,3 +760,95 @@ def test_coupled_rk4_adjoint_finite_differences():
     hg = 1e-4     # the difference quotient converges as hg^2 (1e-3 leaves 5e-6)
     fd = (loss(f0, N0, s.g2 + hg * w) - loss(f0, N0, s.g2 - hg * w)) / (2 * hg)
     assert fd == pytest.approx(float(gg @ w), rel=1e-6)
+
+
+# ---------------------------------------------------------------------------
+# Bose statistics: phonon-phonon scattering on the channel list
+# ---------------------------------------------------------------------------
+def test_bose_two_mode_spontaneous_and_stimulated_decay():
+    """Mode 1 sits exactly one third-phonon energy above mode 0.  With one
+    quantum in mode 1, mode 0 empty and no third phonons, the golden rule
+    gives spontaneous decay 1 -> 0 + phonon at rate C |V|^2 G(0); with m
+    quanta already in mode 0 the decay is stimulated by (1 + m) (Bose
+    enhancement of the receiving mode), and with N third phonons present the
+    emission carries N + 1 while the reverse absorption n_0 N (1 + n_1)
+    appears."""
+    V2, sig, w = 3e-3, 0.002, 0.02
+    s = synth.two_state_system(dE=w, hw=w, g2=V2, sigma=sig, nq=2)
+    C = 2 * math.pi / HBAR / 2 * V2 * _G(0.0, sig)
+    zero = np.zeros((2, 1))
+    I = oracle.collision_bose(s, np.array([0.0, 1.0]), zero)
+    assert I[0] == pytest.approx(C, rel=1e-13)
+    assert I[1] == pytest.approx(-C, rel=1e-13)
+    m = 2.5
+    I = oracle.collision_bose(s, np.array([m, 1.0]), zero)
+    assert I[1] == pytest.approx(-C * (1 + m), rel=1e-13)
+    N = 0.7
+    n0, n1 = 0.4, 1.3
+    I = oracle.collision_bose(s, np.array([n0, n1]), np.full((2, 1), N))
+    expect0 = C * (n1 * (1 + n0) * (N + 1) - n0 * N * (1 + n1))
+    assert I[0] == pytest.approx(expect0, rel=1e-12)
+    assert I[1] == pytest.approx(-expect0, rel=1e-12)
+
+
+def test_bose_equilibrium_on_resonant_ladder():
+    """Bose-Einstein mode occupations with third phonons at the same
+    temperature are a fixed point when every channel is on resonance (the
+    counter-process Gaussian underflows): n_p N (1 + n_d) = n_d (1 + n_p)(N + 1)
+    for e_d = e_p + w.  Modes hotter than the bath relax (I != 0)."""
+    s = synth.ladder_system()
+    s.eps = s.eps + 0.01                       # positive mode energies
+    nph = s.nph(300.0)
+    n_eq = synth.bose_einstein(s.eps, 300.0)
+    n_hot = synth.bose_einstein(s.eps, 900.0)
+    I_eq = oracle.collision_bose(s, n_eq, nph)
+    I_hot = oracle.collision_bose(s, n_hot, nph)
+    assert np.abs(I_hot).max() > 0
+    assert np.abs(I_eq).max() <= 1e-13 * np.abs(I_hot).max()
+
+
+def test_bose_conserves_mode_quanta_and_matches_fermi_at_negated_occupations():
+    """Every process moves one quantum between the two modes of its channel
+    (the third phonon is created or destroyed on its own), so sum_d I_d = 0
+    when hw and N are even in q.  Term by term the Bose brackets are minus the
+    Fermi brackets of Eq. 2 at f = -n, so collision_bose(n) equals
+    -collision(-n), the C oracle written independently."""
+    s = synth.ph_ph_system(n=4)
+    n = synth.bose_occupations(s, 300.0, seed=8)
+    nph = synth.bose_einstein(s.hw, 250.0)
+    I = oracle.collision_bose(s, n, nph)
+    scale = np.abs(I).max()
+    assert scale > 0
+    assert abs(I.sum()) <= 1e-13 * scale * math.sqrt(s.n_states)
+    assert np.abs(I + oracle.collision(s, -n, nph)).max() <= 1e-13 * scale
+
+
+def test_bose_vjp_central_differences():
+    """collision_bose is quadratic in n and linear in |V|^2 and N, so central
+    differences of L = lam . I are exact up to rounding."""
+    s = synth.ph_ph_system(n=3)
+    rng = np.random.default_rng(12)
+    n = synth.bose_occupations(s, 300.0, seed=9)
+    nph = synth.bose_einstein(s.hw, 300.0) * (1 + 0.2 * rng.uniform(size=s.hw.shape))
+    lam = rng.normal(size=s.n_states)
+    gn, gg, gN = oracle.collision_bose_vjp(s, n, nph, lam)
+    L = lambda n_, N_, g_: float(lam @ oracle.collision_bose(s, n_, N_, g2=g_))
+    for d in rng.choice(s.n_states, 6, replace=False):
+        h = 1e-3
+        e = np.zeros(s.n_states)
+        e[d] = h
+        fd = (L(n + e, nph, s.g2) - L(n - e, nph, s.g2)) / (2 * h)
+        assert fd == pytest.approx(gn[d], rel=1e-8, abs=1e-10 * np.abs(gn).max())
+    for c in rng.choice(s.n_channels, 6, replace=False):
+        h = 1e-4 * s.g2[c]
+        e = np.zeros(s.n_channels)
+        e[c] = h
+        fd = (L(n, nph, s.g2 + e) - L(n, nph, s.g2 - e)) / (2 * h)
+        assert fd == pytest.approx(gg[c], rel=1e-8, abs=1e-10 * np.abs(gg).max())
+    nz = np.argwhere(np.abs(gN) > 1e-6 * np.abs(gN).max())
+    for qi, nu in nz[rng.choice(len(nz), 6, replace=False)]:
+        h = 1e-3
+        e = np.zeros_like(nph)
+        e[qi, nu] = h
+        fd = (L(n, nph + e, s.g2) - L(n, nph - e, s.g2)) / (2 * h)
+        assert fd == pytest.approx(gN[qi, nu], rel=1e-8, abs=1e-10 * np.abs(gN).max())
