@@ -653,11 +653,15 @@ def drift_transpose(sys, lam, rates, nbr=None):
 # ---------------------------------------------------------------------------
 # real-time BTE: classical RK4 and its discrete adjoint
 # ---------------------------------------------------------------------------
-def rk4_step(sys, f, nph, dt, g2=None, return_stages=False, rates=None, nbr=None):
+def rk4_step(sys, f, nph, dt, g2=None, return_stages=False, rates=None, nbr=None, statistics="fermi"):
     """One classical fourth-order Runge-Kutta step of df/dt = I[f] (+ the
-    drift term of Eq. 1 when rates is given)."""
+    drift term of Eq. 1 when rates is given).  statistics="bose": dn/dt of
+    collision_bose (phonon modes as the states; no drift term)."""
     a = _Args(sys, nph, g2)
-    if rates is None:
+    if statistics == "bose":
+        assert rates is None
+        I = lambda u: collision_bose(sys, u, nph, g2=g2)
+    elif rates is None:
         I = lambda u: collision(sys, u, nph, args=a)
     else:
         nbr = drift_neighbors(sys) if nbr is None else nbr
@@ -707,12 +711,15 @@ def rk4_coupled_step(sys, f, nph, dt, g2=None):
             M1 + (dt / 6.0) * (p1 + 2.0 * p2 + 2.0 * p3 + p4))
 
 
-def rk4_adjoint_step(sys, stages, nph, dt, gbar, g2=None, rates=None, nbr=None):
+def rk4_adjoint_step(sys, stages, nph, dt, gbar, g2=None, rates=None, nbr=None, statistics="fermi"):
     """Reverse of one RK4 step.  Given gbar = dL/df_{n+1} and the stage inputs
     (u1..u4) of the step, return (dL/df_n, dL/dg2 contribution of the step).
     With rates, each stage's transposed Jacobian also holds D^T."""
     u1, u2, u3, u4 = stages
-    if rates is None:
+    if statistics == "bose":
+        assert rates is None
+        vjp = lambda u, lam: collision_bose_vjp(sys, u, nph, lam, g2=g2)[:2]
+    elif rates is None:
         vjp = lambda u, lam: collision_vjp(sys, u, nph, lam, g2=g2)
     else:
         nbr = drift_neighbors(sys) if nbr is None else nbr
@@ -731,18 +738,18 @@ def rk4_adjoint_step(sys, stages, nph, dt, gbar, g2=None, rates=None, nbr=None):
     return gbar + ub1 + ub2 + ub3 + ub4, gg1 + gg2_ + gg3 + gg4
 
 
-def rk4_trajectory_grad(sys, f0, nph, dt, n_steps, gT, g2=None, rates=None):
+def rk4_trajectory_grad(sys, f0, nph, dt, n_steps, gT, g2=None, rates=None, statistics="fermi"):
     """Gradients of L(f_T) through n_steps RK4 steps, storing every stage."""
     nbr = None if rates is None else drift_neighbors(sys)
     f = np.array(f0, dtype=np.float64)
     stages = []
     for _ in range(n_steps):
-        f, st = rk4_step(sys, f, nph, dt, g2=g2, return_stages=True, rates=rates, nbr=nbr)
+        f, st = rk4_step(sys, f, nph, dt, g2=g2, return_stages=True, rates=rates, nbr=nbr, statistics=statistics)
         stages.append(st)
     g = np.array(gT, dtype=np.float64)
     gg = np.zeros(sys.n_channels)
     for st in reversed(stages):
-        g, dg = rk4_adjoint_step(sys, st, nph, dt, g, g2=g2, rates=rates, nbr=nbr)
+        g, dg = rk4_adjoint_step(sys, st, nph, dt, g, g2=g2, rates=rates, nbr=nbr, statistics=statistics)
         gg += dg
     return f, g, gg
 

@@ -533,7 +533,7 @@ def tb_two_band_system(**kw) -> System:
 
 
 def ph_ph_system(n=6, a=LATTICE_A, debye_kms=(4.0, 7.0), einstein_eV=(0.030,), sigma=0.002,
-                 hw_min=1e-3, seed=31, name=None) -> System:
+                 hw_min=1e-3, v2_scale=1e-4, seed=31, name=None) -> System:
     """Phonon-phonon (three-phonon) scattering on the channel-list layout
     (Bose plans): the states are the phonon modes (q, branch) of an n^3 grid
     with hbar omega >= hw_min (the acoustic modes at q = 0 are left out), with
@@ -541,8 +541,10 @@ def ph_ph_system(n=6, a=LATTICE_A, debye_kms=(4.0, 7.0), einstein_eV=(0.030,), s
     channel (i, j, nu) couples modes i and j through the third phonon of
     branch nu at q = q_j - q_i, whose energy is the table hw of the same
     model.  Every pair and third branch with hbar omega >= hw_min is a
-    channel; |V3|^2 is the seeded lognormal of the e-ph systems (eV^2, the
-    same scale: a stand-in, not anharmonic data)."""
+    channel; |V3|^2 is the seeded lognormal of the e-ph systems times
+    v2_scale (a stand-in, not anharmonic data, scaled so that the modes relax
+    over picoseconds, as phonons do, rather than over the femtoseconds of
+    electrons)."""
     qgrid = (n, n, n)
     hw = phonon_table(qgrid, a, debye_kms, einstein_eV)
     nq, nb = hw.shape
@@ -554,7 +556,8 @@ def ph_ph_system(n=6, a=LATTICE_A, debye_kms=(4.0, 7.0), einstein_eV=(0.030,), s
     key = (state_k.astype(np.int64) * nb + band).astype(np.int64)
     ch = enumerate_channels(state_k, qgrid, qgrid, hw, key, seed, hw_min=hw_min)
     return System(name=name or f"phph{n}", kgrid=qgrid, qgrid=qgrid, state_k=state_k, state_band=band,
-                  eps=eps, n_modes=nb, hw=hw, ch_i=ch[0], ch_j=ch[1], ch_nu=ch[2], g2=ch[3], sigma=sigma,
+                  eps=eps, n_modes=nb, hw=hw, ch_i=ch[0], ch_j=ch[1], ch_nu=ch[2], g2=ch[3] * v2_scale,
+                  sigma=sigma,
                   n_q_norm=float(nq), lattice_a=a, meta=dict(seed=seed, statistics="bose"))
 
 

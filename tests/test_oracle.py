@@ -852,3 +852,34 @@ def test_bose_vjp_central_differences():
         e[qi, nu] = h
         fd = (L(n, nph + e, s.g2) - L(n, nph - e, s.g2)) / (2 * h)
         assert fd == pytest.approx(gN[qi, nu], rel=1e-8, abs=1e-10 * np.abs(gN).max())
+
+
+def test_bose_rk4_trajectory_gradient_finite_differences():
+    """The discrete adjoint of RK4 steps of dn/dt = collision_bose(n) against
+    central differences of L = g_T . n_T (a polynomial in n0 and |V|^2 of
+    degree 2^(4 steps) and 4, so the h^2 truncation is checked to its size)."""
+    s = synth.ph_ph_system(n=3)
+    rng = np.random.default_rng(14)
+    n0 = synth.bose_occupations(s, 300.0, seed=15)
+    nph = synth.bose_einstein(s.hw, 300.0)
+    gT = rng.normal(size=s.n_states)
+    dt, steps = 200.0, 3
+    _, gn, gg = oracle.rk4_trajectory_grad(s, n0, nph, dt, steps, gT, statistics="bose")
+
+    def L(n_, g_):
+        n = np.array(n_)
+        for _ in range(steps):
+            n = oracle.rk4_step(s, n, nph, dt, g2=g_, statistics="bose")
+        return float(gT @ n)
+    for d in rng.choice(s.n_states, 4, replace=False):
+        h = 1e-4
+        e = np.zeros(s.n_states)
+        e[d] = h
+        fd = (L(n0 + e, s.g2) - L(n0 - e, s.g2)) / (2 * h)
+        assert fd == pytest.approx(gn[d], rel=1e-6, abs=1e-8 * np.abs(gn).max())
+    for c in rng.choice(s.n_channels, 4, replace=False):
+        h = 1e-3 * s.g2[c]
+        e = np.zeros(s.n_channels)
+        e[c] = h
+        fd = (L(n0, s.g2 + e) - L(n0, s.g2 - e)) / (2 * h)
+        assert fd == pytest.approx(gg[c], rel=1e-6, abs=1e-8 * np.abs(gg).max())
