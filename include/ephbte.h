@@ -46,14 +46,16 @@
  *   ephbte_last_error() (thread-local) describes the failure.
  * Determinism: results are bitwise reproducible run to run for a given plan
  *   and launch configuration.  Floating-point sums have a fixed order and use
- *   no atomics.  Two passes use integer atomics on 64-bit fixed-point values:
- *   the single-copy forward pass (partner side of each channel) and the
- *   phonon-side rate (its (q, mode) bins).  Integer addition is associative,
- *   so those sums do not depend on the order of arrival.  The fixed-point
- *   scale is a power of two chosen per call from max |N| of the call's table
- *   and the largest sum of |g|^2 over one state's channels; it assumes
+ *   no atomics.  The single-copy passes (forward and reverse, layouts 2 and 3)
+ *   add the partner side of each channel or pair with integer atomics on
+ *   64-bit fixed-point values; integer addition is associative, so those sums
+ *   do not depend on the order of arrival.  The phonon-side rate uses no
+ *   atomics.  The fixed-point scale is a power of two chosen per call from
+ *   max |N| of the call's table, the largest sum of |g|^2 over one state's
+ *   channels (and max |lambda| in the reverse pass); Fermi plans assume
  *   occupations f in [0, 1] (a caller's f outside that range, or RK stage
- *   inputs that leave it, can overflow the partner-side sums).
+ *   inputs that leave it, can overflow the partner-side sums), Bose plans
+ *   take max |n| of each pass's input into the scale.
  */
 #ifndef EPHBTE_H
 #define EPHBTE_H
@@ -150,7 +152,22 @@ typedef struct {
                                   be 0 at every q, and the caller passes N = 0 for
                                   it, so that Eq. 2 reduces to the elastic golden
                                   rule K |g|^2 G(eps_i - eps_j) (f_j - f_i)         */
-    int32_t reserved[3];       /* must be 0                                        */
+    int32_t statistics;        /* 0: Fermi (electrons, Eq. 2 as written).
+                                  1: Bose: the same integral over the same channel
+                                  list with the blocking factors (1 - f) replaced
+                                  by the enhancement factors (1 + n), for
+                                  phonon-phonon (three-phonon) scattering: states
+                                  are phonon modes (energy in eps, occupation n in
+                                  the f arguments), a channel (i, j, nu) couples
+                                  modes i and j through the third phonon of branch
+                                  nu at q = k_j - k_i, whose energy and occupation
+                                  are hw and N (paper, Discussion: other scattering
+                                  mechanisms on the same data structure).  Bose
+                                  plans serve the collision integral, its reverse
+                                  passes (collision_vjp, collision_vjp_nph), the
+                                  RK4 steps and their adjoint; the other entry
+                                  points return INVALID_ARGUMENT for them.        */
+    int32_t reserved[2];       /* must be 0                                        */
 } ephbte_build_opts;
 
 /*

@@ -41,7 +41,8 @@ class Problem(ctypes.Structure):
 
 class BuildOpts(ctypes.Structure):
     _fields_ = [("energy_nsigma", ctypes.c_double), ("g2_min", ctypes.c_double),
-                ("elastic_modes", ctypes.c_uint32), ("reserved", ctypes.c_int32 * 3)]
+                ("elastic_modes", ctypes.c_uint32), ("statistics", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class Tuning(ctypes.Structure):
@@ -189,6 +190,7 @@ class Plan:
         self.n_q = int(np.prod(system.qgrid))
         self.dtype = dtype
         self.device = device
+        self.statistics = "fermi"
 
     @property
     def torch_dtype(self):
@@ -239,22 +241,31 @@ def _batch(plan, t, name):
 
 
 # ---------------------------------------------------------------- entry points
-def _opts(energy_nsigma: float, g2_min: float, elastic_modes: int = 0):
+STATISTICS = {"fermi": 0, "bose": 1}
+
+
+def _opts(energy_nsigma: float, g2_min: float, elastic_modes: int = 0, statistics: str = "fermi"):
     """BuildOpts pointer, or None (defaults) when every option is 0."""
-    if not energy_nsigma and not g2_min and not elastic_modes:
+    if statistics not in STATISTICS:
+        raise ValueError("statistics must be 'fermi' or 'bose'")
+    if not energy_nsigma and not g2_min and not elastic_modes and statistics == "fermi":
         return None
     o = BuildOpts()
     o.energy_nsigma = float(energy_nsigma)
     o.g2_min = float(g2_min)
     o.elastic_modes = int(elastic_modes)
+    o.statistics = STATISTICS[statistics]
     return ctypes.byref(o)
 
 
 def build_channels(system, dtype="f64", device: Optional[int] = None,
-                   energy_nsigma: float = 0.0, g2_min: float = 0.0, elastic_modes: int = 0) -> Plan:
+                   energy_nsigma: float = 0.0, g2_min: float = 0.0, elastic_modes: int = 0,
+                   statistics: str = "fermi") -> Plan:
     """Build the device channel layout of a problem (see ephbte_build_channels).
     energy_nsigma > 0 and g2_min > 0 select channels; elastic_modes is the bit
-    mask of elastic (hw = 0, N = 0) mechanisms (ephbte_build_opts)."""
+    mask of elastic (hw = 0, N = 0) mechanisms; statistics "bose" makes the
+    states phonon modes with occupations n (blocking factors 1 + n: phonon-phonon
+    scattering; ephbte_build_opts)."""
     lib = load_library()
     code = _dtype_code(dtype)
     if device is None:
@@ -262,10 +273,12 @@ def build_channels(system, dtype="f64", device: Optional[int] = None,
         device = torch.cuda.current_device()
     pr, keep = _problem(system, code, device)
     h = ctypes.c_void_p()
-    _check(lib.ephbte_build_channels(ctypes.byref(pr), _opts(energy_nsigma, g2_min, elastic_modes),
+    _check(lib.ephbte_build_channels(ctypes.byref(pr), _opts(energy_nsigma, g2_min, elastic_modes, statistics),
                                      ctypes.byref(h)), "build_channels")
     del keep
-    return Plan(h.value, system, code, device)
+    plan = Plan(h.value, system, code, device)
+    plan.statistics = statistics
+    return plan
 
 
 def layout_host(system, energy_nsigma: float = 0.0, g2_min: float = 0.0, elastic_modes: int = 0):

@@ -94,6 +94,11 @@ struct ephbte_plan_s {
     // grouped by phonon pair {q, -q} (pair records, buckets, chunks)
     uint32_t elastic = 0;
     double nk = 1.0;
+    // Bose statistics (ephbte_build_opts.statistics = 1): the entry points
+    // map n to f = -n for the kernels (see boson_neg); max |f| of each pass's
+    // input sets the fixed-point scale
+    bool boson = false;
+    unsigned long long *fmax_bits = nullptr;
     uint32_t *ph_pa = nullptr, *ph_pb = nullptr;
     void *ph_g2 = nullptr;            // [n_modes][ph_ld]
     int32_t *ph_chan = nullptr;       // [n_modes][ph_ld] caller channel of each slot, -1: none
@@ -188,6 +193,8 @@ struct ephbte_plan_s {
     // reverse of the coupled step: checkpoints and stage inputs of (f, N),
     // adjoint vectors of both
     DevBuf ca_ckf, ca_ckN, ca_U, ca_M, ca_gf, ca_gN, ca_a, ca_b, ca_uf, ca_uN, ca_sf, ca_sN, ca_mu;
+    DevBuf bs_x, bs_y;                       // Bose plans: negated inputs
+    DevBuf nvec;                             // per-vector baths of the batched pass
     double *host_red = nullptr;   // pinned
     hipStream_t own_stream = nullptr;
     hipEvent_t ev_a = nullptr, ev_b = nullptr;
@@ -211,7 +218,8 @@ struct ephbte_plan_s {
                              &tr_rhs, &tr_xa, &tr_xb, &tr_part, &tr_red, &tr_red2, &adj_ck,
                              &adj_U, &adj_la, &adj_lb, &adj_acc, &adj_g, &adj_f, &cp_Ma, &cp_Mb,
                              &cp_acc, &cp_rate, &ph_part, &ph_tab4, &ca_ckf, &ca_ckN, &ca_U, &ca_M,
-                             &ca_gf, &ca_gN, &ca_a, &ca_b, &ca_uf, &ca_uN, &ca_sf, &ca_sN, &ca_mu};
+                             &ca_gf, &ca_gN, &ca_a, &ca_b, &ca_uf, &ca_uN, &ca_sf, &ca_sN, &ca_mu,
+                             &bs_x, &bs_y, &nvec};
         for (auto *x : w) b += x->bytes;
         return b;
     }
@@ -302,14 +310,14 @@ void free_plan(ephbte_plan P) {
                      (void **)&P->ph_bucket_modes, (void **)&P->pr_partner, (void **)&P->pr_g2,
                      (void **)&P->pr_chan, (void **)&P->pr_chunk_beg, (void **)&P->pr_chunk_end,
                      (void **)&P->pr_chunk_dest, (void **)&P->pr_dest_chunk, (void **)&P->pr_tiles,
-                     (void **)&P->lmax_bits, (void **)&P->pr_ch0};
+                     (void **)&P->lmax_bits, (void **)&P->pr_ch0, (void **)&P->fmax_bits};
     for (auto pp : ptrs) dfree(*pp);
     DevBuf *w[] = {&P->part,   &P->sym_part, &P->rk_ua,  &P->rk_ub,   &P->rk_acc, &P->hwN, &P->tr_W,   &P->tr_tau_inv,
                    &P->tr_tau, &P->tr_rhs, &P->tr_xa,   &P->tr_xb,  &P->tr_part, &P->tr_red,
                    &P->tr_red2, &P->adj_ck, &P->adj_U,  &P->adj_la, &P->adj_lb, &P->adj_acc,
                    &P->adj_g,  &P->adj_f, &P->cp_Ma, &P->cp_Mb, &P->cp_acc, &P->cp_rate, &P->ph_part,
                    &P->ph_tab4, &P->ca_ckf, &P->ca_ckN, &P->ca_U, &P->ca_M, &P->ca_gf, &P->ca_gN, &P->ca_a,
-                   &P->ca_b, &P->ca_uf, &P->ca_uN, &P->ca_sf, &P->ca_sN, &P->ca_mu};
+                   &P->ca_b, &P->ca_uf, &P->ca_uN, &P->ca_sf, &P->ca_sN, &P->ca_mu, &P->bs_x, &P->bs_y, &P->nvec};
     for (auto *b : w) dfree(b->p);
     if (P->host_red) (void)hipHostFree(P->host_red);
     if (P->ev_a) (void)hipEventDestroy(P->ev_a);
@@ -503,6 +511,7 @@ template <typename T> TiledArgs<T> tiled_args(ephbte_plan P) {
     a.jacc = P->jacc;
     a.nmax_bits = P->nmax_bits;
     a.gmax_bits = P->gmax_bits;
+    a.fmax_bits = P->boson ? P->fmax_bits : nullptr;
     return a;
 }
 
@@ -676,9 +685,47 @@ void enqueue_forward_batched(ephbte_plan P, int B, const T *f, int64_t ldf, cons
     const size_t shm = batch_lds_bytes(P, P->pt);
     dim3 grid(static_cast<unsigned>(P->n_btiles), (B + 63) / 64);
     const int64_t kt = ktime_begin(P, s);
-    hipLaunchKernelGGL((k_fwd_batched<T, kBatchDPW>), grid, dim3(kBatchThreads), shm, s,
-                       batch_args<T>(P), f, ldf, B, E);
+    hipLaunchKernelGGL((k_fwd_batched<T, kBatchDPW, 0>), grid, dim3(kBatchThreads), shm, s,
+                       batch_args<T>(P), f, ldf, B, E, (const T *)nullptr, int64_t(0));
     ktime_end(P, s, kt);
+    HIPC(hipGetLastError());
+}
+
+// I for B >= 8 vectors with a bath per vector (nph: B tables [Nq][n_modes]):
+// per group of 64 vectors, their N on the rows of the {hw, N} table
+// ([row][mode][64], in P->nvec) and one batched launch that applies each
+// entry's N-free coefficients as the shared-bath pass does and its N
+// coefficient with each vector's N.  The {hw, N} table must hold this plan's
+// hw (its N column is not read).
+template <typename T>
+void enqueue_forward_batched_pv(ephbte_plan P, int B, const T *f, int64_t ldf, const T *nph, T *I, int64_t ldi,
+                                hipStream_t s) {
+    const size_t shm = batch_lds_bytes(P, P->pt);
+    const int64_t rows = P->padq ? P->qpad_n : static_cast<int64_t>(P->nq[0]) * P->nq[1] * P->nq[2];
+    const int64_t ld = rows * P->nm * 64;
+    ensure(P->nvec, sizeof(T) * static_cast<size_t>(ld), &P->ws_gen);
+    const int64_t tab = nqm_of(P);
+    T *nv = static_cast<T *>(P->nvec.p);
+    for (int g = 0; g * 64 < B; ++g) {
+        const int nb = std::min(64, B - g * 64);
+        hipLaunchKernelGGL((k_pack_nvec<T>), dim3(grid_of(ld)), dim3(256), 0, s, nph + g * 64 * tab, nv,
+                           P->padq ? 1 : 0, P->qbox, P->nm, rows, nb, ld);
+        const Epi<T> E = epi_store<T>(I + g * 64 * ldi, ldi);
+        const dim3 grid(static_cast<unsigned>(P->n_btiles), 1);
+        const BArgs<T> a = batch_args<T>(P);
+        const T *fg = f + g * 64 * ldf;
+        auto go = [&](auto rc) {
+            constexpr int RUN = decltype(rc)::value;
+            hipLaunchKernelGGL((k_fwd_batched<T, kBatchDPW, RUN>), grid, dim3(kBatchThreads), shm, s, a, fg, ldf, nb,
+                               E, (const T *)nv, int64_t(0));
+        };
+        if (P->nm <= 1) go(std::integral_constant<int, 1>{});
+        else if (P->nm <= 2) go(std::integral_constant<int, 2>{});
+        else if (P->nm <= 3) go(std::integral_constant<int, 3>{});
+        else if (P->nm <= 4) go(std::integral_constant<int, 4>{});
+        else if (P->nm <= 6) go(std::integral_constant<int, 6>{});
+        else go(std::integral_constant<int, 8>{});
+    }
     HIPC(hipGetLastError());
 }
 
@@ -784,6 +831,13 @@ size_t tiled_lds_bytes(ephbte_plan P) {
 // Enqueue I[f] for B vectors with epilogue E (no allocation inside; the
 // caller ensured P->part and P->hwN are large enough).  pack = false when the
 // {hw, N} table already holds this call's occupations.
+// max |f| over one vector into P->fmax_bits: the fixed-point scale of the
+// single-copy passes for occupations outside [0, 1] (Bose plans)
+template <typename T> void enqueue_fmax(ephbte_plan P, const T *f, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, P->fmax_bits, 1);
+    hipLaunchKernelGGL((k_abs_max_bits<T>), dim3(grid_of(P->S)), dim3(256), 0, s, f, int64_t(P->S), P->fmax_bits);
+}
+
 template <typename T>
 void enqueue_forward(ephbte_plan P, int B, const T *f, int64_t ldf, const void *nph,
                      const Epi<T> &E, hipStream_t s, bool pack = true) {
@@ -792,6 +846,7 @@ void enqueue_forward(ephbte_plan P, int B, const T *f, int64_t ldf, const void *
         enqueue_forward_batched<T>(P, B, f, ldf, E, s);
         return;
     }
+    if (P->boson && (use_pairs(P, B) || use_sym(P, B))) enqueue_fmax<T>(P, f, s);
     if (use_pairs(P, B)) {
         TiledArgs<T> a = pair_args<T>(P);
         T *part = static_cast<T *>(P->sym_part.p);
@@ -932,6 +987,7 @@ void enqueue_vjp(ephbte_plan P, const T *f, const T *lam, const void *nph, const
         hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, P->lmax_bits, 1);
         hipLaunchKernelGGL((k_abs_max_bits<T>), dim3(grid_of(P->S)), dim3(256), 0, s, lam, int64_t(P->S),
                            P->lmax_bits);
+        if (P->boson) enqueue_fmax<T>(P, f, s);
         TiledArgs<T> a = pair_args<T>(P);
         T *part = static_cast<T *>(P->sym_part.p);
         const int want_f = E.mode >= 0 ? 1 : 0;
@@ -2093,6 +2149,29 @@ std::string tune_key(ephbte_plan P, int batch) {
 }  // namespace
 
 // =================================================================== C ABI
+// Bose plans.  With the blocking factors (1 + n) in place of (1 - f), every
+// term of Eq. 2 at occupations n is minus the Fermi term at f = -n, so
+// I_B(n) = -I_F(-n): the entry points run the Fermi kernels on -n and negate
+// what comes back (gradients follow by the chain rule, see each entry point).
+template <typename T>
+const T *boson_neg(ephbte_plan P, DevBuf &buf, const void *src, int64_t lds, int B, hipStream_t s) {
+    ensure(buf, sizeof(T) * static_cast<size_t>(P->S) * B, &P->ws_gen);
+    T *dst = static_cast<T *>(buf.p);
+    hipLaunchKernelGGL((k_neg_rows<T>), dim3(grid_of(static_cast<int64_t>(P->S) * B)), dim3(256), 0, s,
+                       static_cast<const T *>(src), lds, dst, int64_t(P->S), B, P->S);
+    return dst;
+}
+template <typename T> void neg_in_place(ephbte_plan P, void *x, int64_t ld, int B, hipStream_t s) {
+    T *p = static_cast<T *>(x);
+    hipLaunchKernelGGL((k_neg_rows<T>), dim3(grid_of(static_cast<int64_t>(P->S) * B)), dim3(256), 0, s,
+                       (const T *)p, ld, p, ld, B, P->S);
+}
+
+ephbte_status boson_unsupported(const char *what) {
+    return fail(EPHBTE_INVALID_ARGUMENT,
+                std::string(what) + " is defined for Fermi statistics only (this plan was built with statistics = 1)");
+}
+
 extern "C" {
 
 const char *ephbte_status_string(ephbte_status s) {
@@ -2169,6 +2248,7 @@ ephbte_status ephbte_build_channels(const ephbte_problem *problem, const ephbte_
         P->nch_kept = L.n_channels;
         P->E = L.E;
         P->elastic = opts ? opts->elastic_modes : 0u;
+        P->boson = opts && opts->statistics == 1;
         P->nk = static_cast<double>(problem->kgrid[0]) * problem->kgrid[1] * problem->kgrid[2];
         P->nbr_ok = !L.nbr.empty();
         if (P->nbr_ok) {
@@ -2257,7 +2337,9 @@ ephbte_status ephbte_build_channels(const ephbte_problem *problem, const ephbte_
             dalloc(P->gmax_bits, sizeof(unsigned long long), &P->layout_bytes);
             dalloc(P->pack_bmax, sizeof(double) * kPackBlocks, &P->layout_bytes);
             dalloc(P->lmax_bits, sizeof(unsigned long long), &P->layout_bytes);
+            dalloc(P->fmax_bits, sizeof(unsigned long long), &P->layout_bytes);
             HIPC(hipMemset(P->nmax_bits, 0, sizeof(unsigned long long)));
+            HIPC(hipMemset(P->fmax_bits, 0, sizeof(unsigned long long)));
         }
         { HostLayout tmp; std::swap(tmp, L); }
         P->block_threads = 512;
@@ -2292,19 +2374,30 @@ ephbte_status ephbte_collision_integral(ephbte_plan plan, int32_t batch, const v
         auto run = [&](auto tag) {
             using T = decltype(tag);
             const T *ft = static_cast<const T *>(f);
+            int64_t ldft = ldf;
             T *It = static_cast<T *>(I);
+            if (plan->boson) {   // I_B(n) = -I_F(-n)
+                ft = boson_neg<T>(plan, plan->bs_x, f, ldf, batch, s);
+                ldft = plan->S;
+            }
             if (!nph_per_batch || batch == 1) {
                 ensure_fwd<T>(plan, batch);
-                enqueue_forward<T>(plan, batch, ft, ldf, nph, epi_store<T>(It, ldi), s);
-                return;
+                enqueue_forward<T>(plan, batch, ft, ldft, nph, epi_store<T>(It, ldi), s);
+            } else if (batch >= plan->batch_min && plan->n_btiles > 0) {
+                // a bath per vector, batched: the table's hw from the first bath's pack
+                ensure_fwd<T>(plan, batch);
+                enqueue_pack<T>(plan, nph, s);
+                enqueue_forward_batched_pv<T>(plan, batch, ft, ldft, static_cast<const T *>(nph), It, ldi, s);
+            } else {
+                // one bath per vector: the {hw, N} table differs per vector, so
+                // each vector is a single-vector pass after its own pack
+                ensure_fwd<T>(plan, 1);
+                const int64_t tab = nqm_of(plan);
+                for (int b = 0; b < batch; ++b)
+                    enqueue_forward<T>(plan, 1, ft + b * ldft, ldft, static_cast<const T *>(nph) + b * tab,
+                                       epi_store<T>(It + b * ldi, ldi), s);
             }
-            // one bath per vector: the {hw, N} table differs per vector, so
-            // each vector is a single-vector pass after its own pack
-            ensure_fwd<T>(plan, 1);
-            const int64_t tab = nqm_of(plan);
-            for (int b = 0; b < batch; ++b)
-                enqueue_forward<T>(plan, 1, ft + b * ldf, ldf, static_cast<const T *>(nph) + b * tab,
-                                   epi_store<T>(It + b * ldi, ldi), s);
+            if (plan->boson) neg_in_place<T>(plan, It, ldi, batch, s);
         };
         if (plan->dtype == EPHBTE_F64) run(double{});
         else run(float{});
@@ -2316,6 +2409,7 @@ ephbte_status ephbte_collision_integral_noalloc(ephbte_plan plan, const void *f,
                                                 void *I, void *stream) {
     return guarded(plan, stream, [&]() -> ephbte_status {
         if (!f || !nph || !I) return fail(EPHBTE_INVALID_ARGUMENT, "f, nph and I must be non-NULL");
+        if (plan->boson) return boson_unsupported("the allocation-free pass");
         const size_t es = esize(plan);
         if (overlaps(f, es * plan->S, I, es * plan->S))
             return fail(EPHBTE_INVALID_ARGUMENT, "I must not overlap f");
@@ -2336,11 +2430,13 @@ ephbte_status ephbte_collision_integral_noalloc(ephbte_plan plan, const void *f,
     });
 }
 
-ephbte_status ephbte_collision_vjp(ephbte_plan plan, int32_t batch, const void *f, int64_t ldf,
-                                   const void *nph, int32_t nph_per_batch, const void *gI,
-                                   int64_t ldg, void *gf, int64_t ldgf, double *gg2,
+ephbte_status ephbte_collision_vjp(ephbte_plan plan, int32_t batch, const void *f_in, int64_t ldf_in,
+                                   const void *nph, int32_t nph_per_batch, const void *gI_in,
+                                   int64_t ldg_in, void *gf, int64_t ldgf, double *gg2,
                                    int32_t accumulate_gg2, void *stream) {
     return guarded(plan, stream, [&]() -> ephbte_status {
+        const void *f = f_in, *gI = gI_in;
+        const int64_t ldf = ldf_in, ldg = ldg_in;
         if (batch < 1 || batch > 65535) return fail(EPHBTE_INVALID_ARGUMENT, "batch must be in [1, 65535]");
         if (!f || !nph || !gI) return fail(EPHBTE_INVALID_ARGUMENT, "f, nph and gI must be non-NULL");
         if (ldf < plan->S || ldg < plan->S || (gf && ldgf < plan->S))
@@ -2357,21 +2453,30 @@ ephbte_status ephbte_collision_vjp(ephbte_plan plan, int32_t batch, const void *
             ensure_fwd<T>(plan, 1);
             const int64_t S = plan->S, tab = nqm_of(plan);
             const bool per_batch = nph_per_batch && batch > 1;
+            const void *f = f_in, *gI = gI_in;
+            int64_t ldf = ldf_in, ldg = ldg_in;
+            if (plan->boson) {
+                // L = sum lam I_B(n) = sum (-lam) I_F(-n): the Fermi pass on
+                // (-n, -lam) gives dL/d|g|^2 as it is and -dL/dn
+                f = boson_neg<T>(plan, plan->bs_x, f_in, ldf_in, batch, s);
+                gI = boson_neg<T>(plan, plan->bs_y, gI_in, ldg_in, batch, s);
+                ldf = ldg = S;
+            }
             if (gg2 && !accumulate_gg2 && plan->n_drop > 0) {
                 const unsigned nb = static_cast<unsigned>(std::min<int64_t>((plan->n_drop + 255) / 256, 1024));
                 hipLaunchKernelGGL(k_zero_at, dim3(nb), dim3(256), 0, s, gg2, (const int32_t *)plan->drop_idx,
                                    plan->n_drop);
             }
+            bool done = false;
             if (!per_batch) {
                 enqueue_pack<T>(plan, nph, s);
-                if (enqueue_vjp_batched<T>(plan, batch, static_cast<const T *>(f), ldf,
-                                           static_cast<const T *>(gI), ldg, static_cast<T *>(gf), ldgf,
-                                           gg2, gg2 ? (accumulate_gg2 ? 2 : 1) : 0, s))
-                    return;
+                done = enqueue_vjp_batched<T>(plan, batch, static_cast<const T *>(f), ldf,
+                                              static_cast<const T *>(gI), ldg, static_cast<T *>(gf), ldgf,
+                                              gg2, gg2 ? (accumulate_gg2 ? 2 : 1) : 0, s);
             }
             // the kernels take unit-stride vectors of length S; strided
             // batch members are addressed one vector at a time
-            for (int b = 0; b < batch; ++b) {
+            for (int b = 0; b < batch && !done; ++b) {
                 const T *nb = static_cast<const T *>(nph) + (per_batch ? b * tab : 0);
                 if (per_batch) enqueue_pack<T>(plan, nb, s);
                 const T *fb = static_cast<const T *>(f) + b * ldf;
@@ -2385,6 +2490,7 @@ ephbte_status ephbte_collision_vjp(ephbte_plan plan, int32_t batch, const void *
                 const int gmode = gg2 ? ((accumulate_gg2 || b > 0) ? 2 : 1) : 0;
                 enqueue_vjp<T>(plan, fb, lb, nb, e, gg2, gmode, s);
             }
+            if (plan->boson && gf) neg_in_place<T>(plan, gf, ldgf, batch, s);
         };
         if (plan->dtype == EPHBTE_F64) run(double{});
         else run(float{});
@@ -2403,11 +2509,17 @@ ephbte_status ephbte_rt_step(ephbte_plan plan, int32_t batch, void *f, int64_t l
         if (!std::isfinite(dt_fs)) return fail(EPHBTE_INVALID_ARGUMENT, "dt must be finite");
         if (n_steps == 0) return EPHBTE_OK;
         hipStream_t s = as_stream(stream);
-        if (plan->dtype == EPHBTE_F64)
-            return rt_step_impl<double>(plan, batch, static_cast<double *>(f), ldf, nph, dt_fs,
-                                        n_steps, use_graph, s);
-        return rt_step_impl<float>(plan, batch, static_cast<float *>(f), ldf, nph, dt_fs, n_steps,
-                                   use_graph, s);
+        // Bose plans: u = -n obeys du/dt = -I_B(n) = I_F(u), the Fermi steps
+        auto run = [&](auto tag) -> ephbte_status {
+            using T = decltype(tag);
+            if (plan->boson) neg_in_place<T>(plan, f, ldf, batch, s);
+            const ephbte_status st =
+                rt_step_impl<T>(plan, batch, static_cast<T *>(f), ldf, nph, dt_fs, n_steps, use_graph, s);
+            if (plan->boson) neg_in_place<T>(plan, f, ldf, batch, s);
+            return st;
+        };
+        if (plan->dtype == EPHBTE_F64) return run(double{});
+        return run(float{});
     });
 }
 
@@ -2421,13 +2533,22 @@ ephbte_status ephbte_rt_adjoint(ephbte_plan plan, const void *f0, const void *np
         if (!std::isfinite(dt_fs)) return fail(EPHBTE_INVALID_ARGUMENT, "dt must be finite");
         hipStream_t s = as_stream(stream);
         const int ce = std::min(checkpoint_every, n_steps);
-        if (plan->dtype == EPHBTE_F64)
-            return rt_adjoint_impl<double>(plan, static_cast<const double *>(f0), nph, dt_fs,
-                                           n_steps, ce, static_cast<const double *>(gfT),
-                                           static_cast<double *>(gf0), gg2, accumulate_gg2, s);
-        return rt_adjoint_impl<float>(plan, static_cast<const float *>(f0), nph, dt_fs, n_steps, ce,
-                                      static_cast<const float *>(gfT), static_cast<float *>(gf0),
-                                      gg2, accumulate_gg2, s);
+        // Bose plans: n(T) = -u(T) with u the Fermi trajectory from -n(0), so
+        // the Fermi adjoint of -dL/dn(T) gives dL/d|g|^2 and -dL/dn(0)
+        auto run = [&](auto tag) -> ephbte_status {
+            using T = decltype(tag);
+            const T *x0 = static_cast<const T *>(f0), *gx = static_cast<const T *>(gfT);
+            if (plan->boson) {
+                x0 = boson_neg<T>(plan, plan->bs_x, f0, plan->S, 1, s);
+                gx = boson_neg<T>(plan, plan->bs_y, gfT, plan->S, 1, s);
+            }
+            const ephbte_status st = rt_adjoint_impl<T>(plan, x0, nph, dt_fs, n_steps, ce, gx,
+                                                        static_cast<T *>(gf0), gg2, accumulate_gg2, s);
+            if (plan->boson && gf0) neg_in_place<T>(plan, gf0, plan->S, 1, s);
+            return st;
+        };
+        if (plan->dtype == EPHBTE_F64) return run(double{});
+        return run(float{});
     });
 }
 
@@ -2436,6 +2557,7 @@ ephbte_status ephbte_iterate_transport(ephbte_plan plan, const void *f0, const v
                                        void *x_out, double *mobility, int32_t *iters,
                                        double *resid, void *stream) {
     return guarded(plan, stream, [&]() -> ephbte_status {
+        if (plan->boson) return boson_unsupported("the transport iteration");
         if (!f0 || !vel || !nph || !mobility)
             return fail(EPHBTE_INVALID_ARGUMENT, "f0, vel, nph and mobility must be non-NULL");
         if (!(T_K > 0.0) || !std::isfinite(T_K)) return fail(EPHBTE_INVALID_ARGUMENT, "T_K must be > 0");
@@ -2494,6 +2616,7 @@ ephbte_status ephbte_update_g2(ephbte_plan plan, const double *g2, void *stream)
 ephbte_status ephbte_phonon_rate(ephbte_plan plan, const void *f, const void *nph, void *dN,
                                  void *stream) {
     return guarded(plan, stream, [&]() -> ephbte_status {
+        if (plan->boson) return boson_unsupported("the phonon-side rate");
         if (!f || !nph || !dN) return fail(EPHBTE_INVALID_ARGUMENT, "f, nph and dN must be non-NULL");
         const int64_t nbin = static_cast<int64_t>(plan->nq[0]) * plan->nq[1] * plan->nq[2] * plan->nm;
         if (overlaps(dN, esize(plan) * nbin, f, esize(plan) * plan->S))
@@ -2514,6 +2637,7 @@ ephbte_status ephbte_phonon_rate(ephbte_plan plan, const void *f, const void *np
 ephbte_status ephbte_rt_step_coupled(ephbte_plan plan, void *f, void *nph, double dt_fs,
                                      int32_t n_steps, void *stream) {
     return guarded(plan, stream, [&]() -> ephbte_status {
+        if (plan->boson) return boson_unsupported("the coupled electron-phonon step");
         if (!f || !nph) return fail(EPHBTE_INVALID_ARGUMENT, "f and nph must be non-NULL");
         if (n_steps < 0) return fail(EPHBTE_INVALID_ARGUMENT, "n_steps must be >= 0");
         if (!std::isfinite(dt_fs)) return fail(EPHBTE_INVALID_ARGUMENT, "dt_fs must be finite");
@@ -2543,8 +2667,13 @@ ephbte_status ephbte_collision_vjp_nph(ephbte_plan plan, const void *f, const vo
         ensure_phonon(plan);
         auto run = [&](auto tag) {
             using T = decltype(tag);
-            enqueue_phonon_adj<T>(plan, static_cast<const T *>(f), static_cast<const T *>(nph),
-                                  static_cast<const T *>(gI), (const T *)nullptr, static_cast<T *>(gnph), nullptr, s);
+            const T *x = static_cast<const T *>(f), *l = static_cast<const T *>(gI);
+            if (plan->boson) {   // dL/dN of sum (-lam) I_F(-n)
+                x = boson_neg<T>(plan, plan->bs_x, f, plan->S, 1, s);
+                l = boson_neg<T>(plan, plan->bs_y, gI, plan->S, 1, s);
+            }
+            enqueue_phonon_adj<T>(plan, x, static_cast<const T *>(nph), l, (const T *)nullptr, static_cast<T *>(gnph),
+                                  nullptr, s);
         };
         if (plan->dtype == EPHBTE_F64) run(double{});
         else run(float{});
@@ -2555,6 +2684,7 @@ ephbte_status ephbte_collision_vjp_nph(ephbte_plan plan, const void *f, const vo
 ephbte_status ephbte_phonon_rate_vjp(ephbte_plan plan, const void *f, const void *nph, const void *gR, void *gf,
                                      void *gnph, double *gg2, int32_t accumulate_gg2, void *stream) {
     return guarded(plan, stream, [&]() -> ephbte_status {
+        if (plan->boson) return boson_unsupported("the reverse of the phonon-side rate");
         if (!f || !nph || !gR) return fail(EPHBTE_INVALID_ARGUMENT, "f, nph and gR must be non-NULL");
         const size_t es = esize(plan);
         const int64_t nbin = nqm_of(plan);
@@ -2595,6 +2725,7 @@ ephbte_status ephbte_rt_adjoint_coupled(ephbte_plan plan, const void *f0, const 
                                         const void *gNT, void *gf0, void *gN0, double *gg2,
                                         int32_t accumulate_gg2, void *stream) {
     return guarded(plan, stream, [&]() -> ephbte_status {
+        if (plan->boson) return boson_unsupported("the adjoint of the coupled step");
         if (!f0 || !nph0) return fail(EPHBTE_INVALID_ARGUMENT, "f0 and nph0 must be non-NULL");
         if (n_steps < 1) return fail(EPHBTE_INVALID_ARGUMENT, "n_steps must be >= 1");
         if (checkpoint_every < 1) return fail(EPHBTE_INVALID_ARGUMENT, "checkpoint_every must be >= 1");
@@ -2854,6 +2985,7 @@ ephbte_status ephbte_set_field(ephbte_plan plan, const double rate[3]) {
         if (!std::isfinite(rate[a])) return fail(EPHBTE_INVALID_ARGUMENT, "field rates must be finite");
         on = on || rate[a] != 0.0;
     }
+    if (on && plan->boson) return boson_unsupported("the field term");
     if (on && !plan->nbr_ok)
         return fail(EPHBTE_INVALID_ARGUMENT,
                     "the field term needs each (k, band) held by one state (give state_band)");

@@ -345,6 +345,9 @@ template <typename T> struct TiledArgs {
     const unsigned long long *__restrict__ gmax_bits;  // max over states of sum |g|^2 (double bits)
     // pair records (k_fwd_pairs): pnu holds partners, g2 is [n_modes][pld]
     int64_t pld;
+    // occupations outside [0, 1] (the Bose plans' negated n): max |f| of the
+    // call's input (double bits), or null when f lies in [0, 1]
+    const unsigned long long *__restrict__ fmax_bits;
 };
 
 // ---- fixed point for the partner side of the single-copy pass -------------
@@ -354,12 +357,20 @@ template <typename T> struct TiledArgs {
 // |N| <= N_max, f in [0, 1] and the Gaussians <= 1, one entry's share is at
 // most |g|^2 (2 N_max + 1), a state's column at most (2 N_max + 1) G_max with
 // G_max the largest sum of |g|^2 over one state's channels; s puts that bound
-// below 2^61.
+// below 2^61.  With |f| <= m instead, the occupation products of a term,
+// at most 1 in [0, 1], are at most (1 + 2m)^2, a factor on the bound.
+__device__ __forceinline__ double occ_factor(const unsigned long long *fmax_bits) {
+    if (!fmax_bits) return 1.0;
+    const double m = __longlong_as_double(static_cast<long long>(*fmax_bits));
+    return (1.0 + 2.0 * m) * (1.0 + 2.0 * m);
+}
+
 __device__ __forceinline__ double sym_scale(const unsigned long long *nmax_bits,
-                                            const unsigned long long *gmax_bits) {
+                                            const unsigned long long *gmax_bits,
+                                            const unsigned long long *fmax_bits) {
     const double nmax = __longlong_as_double(static_cast<long long>(*nmax_bits));
     const double gmax = __longlong_as_double(static_cast<long long>(*gmax_bits));
-    const double bound = (2.0 * nmax + 1.0) * gmax;
+    const double bound = (2.0 * nmax + 1.0) * gmax * occ_factor(fmax_bits);
     if (!(bound > 0.0) || !(bound < 1e300)) return 1.0;
     int e;
     (void)frexp(bound, &e);   // bound < 2^e
@@ -813,7 +824,7 @@ __global__ __launch_bounds__(1024) void k_fwd_sym(TiledArgs<T> A, const T *__res
     }
     if constexpr (sizeof(T) == 8)
         for (int i = threadIdx.x; i < kExpTab; i += blockDim.x) s_tab[i] = A.e2tab[i];
-    const T scale = static_cast<T>(sym_scale(A.nmax_bits, A.gmax_bits));
+    const T scale = static_cast<T>(sym_scale(A.nmax_bits, A.gmax_bits, A.fmax_bits));
     __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
     const int nw = static_cast<int>(blockDim.x >> 6);
@@ -992,7 +1003,7 @@ __global__ __launch_bounds__(1024) void k_fwd_pairs(TiledArgs<T> A, const T *__r
     }
     if constexpr (sizeof(T) == 8 && TAB)
         for (int i = threadIdx.x; i < kExpTab; i += blockDim.x) s_tab[i] = A.e2tab[i];
-    const T scale = static_cast<T>(sym_scale(A.nmax_bits, A.gmax_bits));
+    const T scale = static_cast<T>(sym_scale(A.nmax_bits, A.gmax_bits, A.fmax_bits));
     __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
     const int nw = static_cast<int>(blockDim.x >> 6);
@@ -1023,12 +1034,14 @@ __global__ __launch_bounds__(1024) void k_fwd_pairs(TiledArgs<T> A, const T *__r
 // integer atomic, on the scale of vjp_scale.  Each channel is read once.
 __device__ __forceinline__ double vjp_scale(const unsigned long long *nmax_bits,
                                             const unsigned long long *gmax_bits,
-                                            const unsigned long long *lmax_bits) {
+                                            const unsigned long long *lmax_bits,
+                                            const unsigned long long *fmax_bits) {
     // |dl| <= 2 max |lam|: a state's column is at most 2 max|lam| (2 N_max + 1) G_max
+    // (times occ_factor when f leaves [0, 1])
     const double nmax = __longlong_as_double(static_cast<long long>(*nmax_bits));
     const double gmax = __longlong_as_double(static_cast<long long>(*gmax_bits));
     const double lmax = __longlong_as_double(static_cast<long long>(*lmax_bits));
-    const double bound = 2.0 * lmax * (2.0 * nmax + 1.0) * gmax;
+    const double bound = 2.0 * lmax * (2.0 * nmax + 1.0) * gmax * occ_factor(fmax_bits);
     if (!(bound > 0.0) || !(bound < 1e300)) return 1.0;
     int e;
     (void)frexp(bound, &e);
@@ -1184,7 +1197,7 @@ __global__ __launch_bounds__(kVjpPairThreads) void k_vjp_pairs(TiledArgs<T> A, c
     }
     if constexpr (sizeof(T) == 8 && TAB)
         for (int i = threadIdx.x; i < kExpTab; i += blockDim.x) s_tab[i] = A.e2tab[i];
-    const T scale = static_cast<T>(vjp_scale(A.nmax_bits, A.gmax_bits, lmax_bits));
+    const T scale = static_cast<T>(vjp_scale(A.nmax_bits, A.gmax_bits, lmax_bits, A.fmax_bits));
     __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
     const int nw = static_cast<int>(blockDim.x >> 6);
@@ -1213,7 +1226,7 @@ __global__ void k_vjp_pairs_finish(TiledArgs<T> A, const T *__restrict__ part,
     if (d >= A.S) return;
     T a = T(0);
     for (int c = A.dest_chunk[d]; c < A.dest_chunk[d + 1]; ++c) a += part[c];
-    const double inv = 1.0 / vjp_scale(A.nmax_bits, A.gmax_bits, lmax_bits);
+    const double inv = 1.0 / vjp_scale(A.nmax_bits, A.gmax_bits, lmax_bits, A.fmax_bits);
     const long long j = static_cast<long long>(A.jacc[d]);
     A.jacc[d] = 0ull;
     const T jside = static_cast<T>(static_cast<double>(j) * inv);
@@ -1233,7 +1246,7 @@ __global__ void k_sym_finish(TiledArgs<T> A, const T *__restrict__ f, const T *_
         a += part[2 * c];
         b += part[2 * c + 1];
     }
-    const double inv = 1.0 / sym_scale(A.nmax_bits, A.gmax_bits);
+    const double inv = 1.0 / sym_scale(A.nmax_bits, A.gmax_bits, A.fmax_bits);
     const long long j = static_cast<long long>(A.jacc[d]);
     A.jacc[d] = 0ull;
     const T fd = f[d];
@@ -1662,9 +1675,16 @@ template <> __device__ __forceinline__ float lane_bcast(float v, int src) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
 }
 
-template <typename T, int DPW>
+// RUN = 0: one phonon table for all vectors.  RUN > 0: a bath per vector
+// (RUN bounds the entries of one pair, the mode count rounded up): N comes
+// from nvec, [row][mode][64] per group of 64 vectors (row = the q index of
+// the shared table), and an entry's coefficients split into the part without
+// N, summed over the pair's modes as before, and |g|^2 (G(x + hw) +
+// G(x - hw)), applied per vector with that vector's N.
+template <typename T, int DPW, int RUN>
 __global__ __launch_bounds__(512) void k_fwd_batched(BArgs<T> A, const T *__restrict__ f,
-                                                     int64_t ldf, int B, Epi<T> E) {
+                                                     int64_t ldf, int B, Epi<T> E,
+                                                     const T *__restrict__ nvec, int64_t nvec_ld) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int PT = A.pt;
     T *s_F = reinterpret_cast<T *>(smem);                                   // [PT][65]
@@ -1710,7 +1730,8 @@ __global__ __launch_bounds__(512) void k_fwd_batched(BArgs<T> A, const T *__rest
                     const int64_t e = e0 + lane;
                     const bool valid = e < e_hi;
                     int pl = -1 - lane;     // distinct for invalid lanes: never merged
-                    T ca = T(0), cb = T(0);
+                    T ca = T(0), cb = T(0), c1 = T(0);
+                    int ti = 0;
                     if (valid) {
                         const uint32_t pn = A.pnu[e];
                         const T g = A.g2[e];
@@ -1723,9 +1744,16 @@ __global__ __launch_bounds__(512) void k_fwd_batched(BArgs<T> A, const T *__rest
                         const T xa = de + wn.a, xe = de - wn.a;
                         const T da = gauss_exp(xa * xa * A.mc);
                         const T dem = gauss_exp(xe * xe * A.mc);
-                        const T tt = wn.b * (da + dem);
-                        ca = g * (tt + dem);
-                        cb = g * (tt + da);
+                        if constexpr (RUN > 0) {
+                            ca = g * dem;
+                            cb = g * da;
+                            c1 = g * (da + dem);
+                            ti = q * A.nm + static_cast<int>(pn & 7u);
+                        } else {
+                            const T tt = wn.b * (da + dem);
+                            ca = g * (tt + dem);
+                            cb = g * (tt + da);
+                        }
                     }
                     // sum each run of equal partners into its first lane (a run is
                     // one pair over its modes, at most kMaxRun lanes)
@@ -1742,15 +1770,42 @@ __global__ __launch_bounds__(512) void k_fwd_batched(BArgs<T> A, const T *__rest
                     const int prev = __shfl_up(pl, 1, 64);
                     const bool head = valid && (lane == 0 || prev != pl);
                     unsigned long long m = __ballot(head);
-                    while (m) {
-                        const int src = __builtin_ctzll(m);
-                        m &= m - 1;
-                        const T a = lane_bcast(ca, src);
-                        const T bq = lane_bcast(cb, src);
-                        const int pls = __builtin_amdgcn_readlane(pl, src);
-                        const T fpb = s_F[pls * 65 + lane];
-                        sa += a * (T(1) - fpb);
-                        sb += bq * fpb;
+                    if constexpr (RUN > 0) {
+                        // the run of a head ends at the next head or at the
+                        // last valid lane; each of its entries adds
+                        // c1 N_b(q, mode) for this lane's vector b
+                        const int nvalid = static_cast<int>(min<int64_t>(64, e_hi - e0));
+                        const T *__restrict__ nv = nvec + static_cast<int64_t>(blockIdx.y) * nvec_ld + lane;
+                        while (m) {
+                            const int src = __builtin_ctzll(m);
+                            m &= m - 1;
+                            const int end = m ? __builtin_ctzll(m) : nvalid;
+                            T nsum = T(0);
+#pragma unroll
+                            for (int r = 0; r < RUN; ++r) {
+                                // entries past the run re-read its last one, weighted 0
+                                const int j = min(src + r, end - 1);
+                                const T w = src + r < end ? lane_bcast(c1, j) : T(0);
+                                nsum += w * nv[static_cast<int64_t>(__builtin_amdgcn_readlane(ti, j)) * 64];
+                            }
+                            const T a = lane_bcast(ca, src) + nsum;
+                            const T bq = lane_bcast(cb, src) + nsum;
+                            const int pls = __builtin_amdgcn_readlane(pl, src);
+                            const T fpb = s_F[pls * 65 + lane];
+                            sa += a * (T(1) - fpb);
+                            sb += bq * fpb;
+                        }
+                    } else {
+                        while (m) {
+                            const int src = __builtin_ctzll(m);
+                            m &= m - 1;
+                            const T a = lane_bcast(ca, src);
+                            const T bq = lane_bcast(cb, src);
+                            const int pls = __builtin_amdgcn_readlane(pl, src);
+                            const T fpb = s_F[pls * 65 + lane];
+                            sa += a * (T(1) - fpb);
+                            sb += bq * fpb;
+                        }
                     }
                 }
                 acc_a[j] += sa;
@@ -2136,6 +2191,27 @@ __global__ __launch_bounds__(256) void k_phonon_bins_adj(PhArgs<T> A, const T *_
     }
 }
 
+// Per-vector baths of the batched pass: entry ((g rows + row) nm + nu) 64 + j
+// holds N of vector 64 g + j (0 past the last vector) at the table row `row`
+// (a box row when pad != 0, else a q index) and mode nu.  nph holds B tables
+// of [Nq][nm].
+template <typename T>
+__global__ void k_pack_nvec(const T *__restrict__ nph, T *__restrict__ out, int pad, QBox Bx, int nm,
+                            int64_t rows, int B, int64_t n) {
+    const int64_t tab = static_cast<int64_t>(Bx.n[0]) * Bx.n[1] * Bx.n[2] * nm;
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int j = static_cast<int>(i & 63);
+        int64_t r = i >> 6;
+        const int nu = static_cast<int>(r % nm);
+        r /= nm;
+        const int64_t row = r % rows;
+        const int b = static_cast<int>(r / rows) * 64 + j;
+        const int64_t q = pad ? box_q(row, Bx) : row;
+        out[i] = b < B ? nph[static_cast<int64_t>(b) * tab + q * nm + nu] : T(0);
+    }
+}
+
 // {hw, N, mu} per (q, mode) for the reverse of the phonon-side rate: the
 // box of k_pack_hwN_pad with the modes of one row adjacent (pad != 0), or the
 // plain table.
@@ -2238,6 +2314,18 @@ __global__ void k_axpby(int64_t n, T a, const T *__restrict__ x, T b, const T *_
     for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
          i += static_cast<int64_t>(gridDim.x) * blockDim.x)
         out[i] = y ? a * x[i] + b * y[i] : a * x[i];
+}
+
+// dst[b][d] = -src[b][d] for B rows of S values (row strides lds, ldd; dst may
+// be src)
+template <typename T>
+__global__ void k_neg_rows(const T *src, int64_t lds, T *dst, int64_t ldd, int B, int S) {
+    const int64_t n = static_cast<int64_t>(B) * S;
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t b = i / S, d = i - b * S;
+        dst[b * ldd + d] = -src[b * lds + d];
+    }
 }
 
 // |g|^2 slots of the pair records from the caller's list (update_g2)

@@ -67,6 +67,8 @@ ephbte_status build_host_layout(const ephbte_problem *p, const ephbte_build_opts
         elastic = opts->elastic_modes;
         if (!std::isfinite(e_nsig) || e_nsig < 0.0) return bad("energy_nsigma must be finite and >= 0");
         if (!std::isfinite(g2_min) || g2_min < 0.0) return bad("g2_min must be finite and >= 0");
+        if (opts->statistics != 0 && opts->statistics != 1)
+            return bad("statistics must be 0 (Fermi) or 1 (Bose)");
         for (int32_t x : opts->reserved)
             if (x != 0) return bad("reserved build options must be 0");
     }

@@ -139,6 +139,7 @@ int main(int argc, char **argv) {
     opts.energy_nsigma = meta("energy_nsigma", 0.0);
     opts.g2_min = meta("g2_min", 0.0);
     opts.elastic_modes = static_cast<uint32_t>(meta("elastic_modes", 0));
+    opts.statistics = static_cast<int32_t>(meta("statistics", 0));
     ephbte_plan plan = nullptr;
     check(ephbte_build_channels(&p, &opts, &plan), "build_channels");
     // tuning knobs (0 keeps the plan's value)
@@ -359,6 +360,20 @@ int main(int argc, char **argv) {
         std::vector<double> gg(static_cast<size_t>(nch));
         hipMemcpy(gg.data(), dgg, 8 * static_cast<size_t>(nch), hipMemcpyDeviceToHost);
         wr("out_gg2.bin", gg);
+    } else if (mode == "bose_rejects") {
+        // entry points defined for Fermi statistics only: status of each call
+        auto f = rd<double>("f.bin", static_cast<size_t>(S));
+        void *df = dv.up(f), *dx = dv.alloc(static_cast<size_t>(S)), *dr = dv.alloc(nqm);
+        std::vector<double> st;
+        st.push_back(ephbte_collision_integral_noalloc(plan, df, dN, dx, nullptr));
+        st.push_back(ephbte_phonon_rate(plan, df, dN, dr, nullptr));
+        st.push_back(ephbte_rt_step_coupled(plan, df, dr, 1.0, 1, nullptr));
+        const double rates[3] = {0.01, 0.0, 0.0};
+        st.push_back(ephbte_set_field(plan, rates));
+        double mob[9];
+        st.push_back(ephbte_iterate_transport(plan, df, dx, 300.0, dN, 0.0, 1, nullptr, mob, nullptr, nullptr,
+                                              nullptr));
+        wr("out_status.bin", st);
     } else if (mode == "transport") {
         auto f0 = rd<double>("f.bin", static_cast<size_t>(S));
         auto vel = rd<double>("vel.bin", static_cast<size_t>(S) * 3);

@@ -121,7 +121,7 @@ def test_selection_of_every_channel_and_option_errors():
     lib = E.load_library()
     pr, keep = binding._problem(s, binding.F64, -1)
     o = binding.BuildOpts()
-    o.reserved[2] = 1
+    o.reserved[1] = 1
     rp = np.zeros(3, np.int64)
     assert lib.ephbte_layout_host(ctypes.byref(pr), ctypes.byref(o), rp.ctypes.data, None, None,
                                   None) == binding.INVALID_ARGUMENT

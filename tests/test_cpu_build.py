@@ -332,19 +332,32 @@ def test_elastic_mechanism(driver, tmp_path):
     assert nerr(_out(tmp_path, "gg2"), rg) <= TOL64
 
 
-def test_bath_per_vector(driver, tmp_path):
-    """nph [B, Nq, n_modes]: each vector against the oracle with its own bath."""
+@pytest.mark.parametrize("B,dtype", [(3, "f64"), (9, "f64"), (70, "f64"), (9, "f32")])
+def test_bath_per_vector(driver, tmp_path, B, dtype):
+    """nph [B, Nq, n_modes]: each vector against the oracle with its own bath;
+    B >= 8 runs the batched pass with the baths in groups of 64 vectors (70:
+    two groups), under a random fill of fresh memory."""
     s = synth.multiband_system()
-    temps = [150.0, 300.0, 450.0]
-    B = len(temps)
+    temps = [150.0 + 37.0 * b for b in range(B)]
     F = np.stack([synth.random_occupations(s, 40 + b) for b in range(B)])
     NPH = np.stack([s.nph(T) for T in temps])
     L = np.random.default_rng(5).normal(size=(B, s.n_states))
-    _write(tmp_path, s, f=F, lam=L, nph=NPH, B=B, nph_per_batch=1)
-    _run(driver, tmp_path, "forward")
+    _write(tmp_path, s, dtype, f=F, lam=L, nph=NPH, B=B, nph_per_batch=1)
+    _run(driver, tmp_path, "forward", fill="random:%d" % B)
     got = _out(tmp_path, "I", (B, s.n_states))
+    if dtype == "f32":
+        r = _round32(s)
+        for b in range(B):
+            fb, nb = F[b].astype(np.float32).astype(np.float64), NPH[b].astype(np.float32).astype(np.float64)
+            ref = oracle.collision(r, fb, nb)
+            rin, rout = oracle.collision_inout(r, fb, nb)
+            scale = max(np.abs(ref).max(), 1e-2 * max(rin.max(), rout.max()))
+            assert np.abs(got[b] - ref).max() / scale <= TOL32, b
+        return
     for b in range(B):
         assert nerr(got[b], oracle.collision(s, F[b], NPH[b])) <= TOL64, b
+    if B > 9:
+        return
     _run(driver, tmp_path, "vjp")
     gf = _out(tmp_path, "gf", (B, s.n_states))
     rg = 0
@@ -764,3 +777,76 @@ def test_vjp_six_modes(driver, tmp_path, layout, fill, order):
     rf, rg = oracle.collision_vjp(s, f, nph, lam)
     assert nerr(_out(tmp_path, "gf"), rf) <= TOL64
     assert nerr(_out(tmp_path, "gg2"), rg) <= TOL64
+
+
+BOSE_CASES = [("forward", dict(B=1, layout=3)), ("forward", dict(B=1, layout=2)), ("forward", dict(B=1, layout=1)),
+              ("forward", dict(B=9)), ("forward", dict(B=3, nph_per_batch=1)), ("forward", dict(B=9, nph_per_batch=1)),
+              ("vjp", dict(B=1, layout=3)), ("vjp", dict(B=1, layout=1)), ("vjp", dict(B=9)),
+              ("vjp_nph", dict()), ("rt", dict(B=1, dt=200.0, steps=2)),
+              ("adjoint", dict(dt=200.0, steps=3, ce=2))]
+
+
+@pytest.mark.parametrize("k", range(len(BOSE_CASES)))
+def test_bose_plan(driver, tmp_path, k):
+    """Phonon-phonon scattering on a Bose plan (statistics = 1): every entry
+    point it serves against the oracle's Bose integral, under random fills of
+    fresh memory: forward over the three layouts, batched and with a bath per
+    vector; reverse (dL/dn, dL/d|V|^2) at B = 1 and batched; dL/dN; RK4 steps
+    and their adjoint."""
+    mode, kw = BOSE_CASES[k]
+    s = synth.ph_ph_system(n=4)
+    B = kw.get("B", 1)
+    rng = np.random.default_rng(40 + k)
+    F = np.stack([synth.bose_occupations(s, 300.0, seed=50 + b) for b in range(B)])
+    lam = rng.normal(size=(B, s.n_states))
+    per = kw.get("nph_per_batch", 0)
+    tabs = [synth.bose_einstein(s.hw, 250.0 + 30.0 * b) for b in range(B if per else 1)]
+    nph = np.stack(tabs) if per else tabs[0]
+    gT = rng.normal(size=s.n_states)
+    _write(tmp_path, s, f=F, lam=lam, nph=nph, gT=gT, statistics=1, **kw)
+    _run(driver, tmp_path, mode, fill="random:%d" % (60 + k))
+    if mode == "forward":
+        got = _out(tmp_path, "I", (B, s.n_states))
+        for b in range(B):
+            ref = oracle.collision_bose(s, F[b], tabs[b if per else 0])
+            assert nerr(got[b], ref) <= TOL64, b
+    elif mode == "vjp":
+        gf = _out(tmp_path, "gf", (B, s.n_states))
+        rg = 0
+        for b in range(B):
+            rn, rg_b, _ = oracle.collision_bose_vjp(s, F[b], nph, lam[b])
+            assert nerr(gf[b], rn) <= TOL64, b
+            rg = rg + rg_b
+        assert nerr(_out(tmp_path, "gg2"), rg) <= TOL64
+    elif mode == "vjp_nph":
+        _, _, rN = oracle.collision_bose_vjp(s, F[0], nph, lam[0])
+        assert nerr(_out(tmp_path, "gN", rN.shape), rN) <= TOL64
+    elif mode == "rt":
+        ref = F[0]
+        for _ in range(kw["steps"]):
+            ref = oracle.rk4_step(s, ref, nph, kw["dt"], statistics="bose")
+        # the increment over the steps carries the bar
+        for name in ("f", "f_graph"):
+            assert nerr(_out(tmp_path, name) - F[0], ref - F[0]) <= TOL64, name
+    else:
+        _, rn, rg = oracle.rk4_trajectory_grad(s, F[0], nph, kw["dt"], kw["steps"], gT, statistics="bose")
+        assert nerr(_out(tmp_path, "gf"), rn) <= TOL64
+        assert nerr(_out(tmp_path, "gg2"), rg) <= TOL64
+
+
+def test_bose_plan_fp32_and_rejections(driver, tmp_path):
+    """FP32 Bose forward pass over pair records against the oracle on
+    FP32-rounded inputs, and the entry points defined for Fermi statistics
+    only (allocation-free pass, phonon-side rate, coupled step, field term,
+    transport) return INVALID_ARGUMENT on a Bose plan."""
+    s = synth.ph_ph_system(n=4)
+    n = synth.bose_occupations(s, 300.0, seed=70)
+    nph = synth.bose_einstein(s.hw, 300.0)
+    _write(tmp_path, s, "f32", f=n, nph=nph, B=1, layout=3, statistics=1)
+    _run(driver, tmp_path, "forward")
+    r = _round32(s)
+    n32, N32 = n.astype(np.float32).astype(np.float64), nph.astype(np.float32).astype(np.float64)
+    assert nerr(_out(tmp_path, "I"), oracle.collision_bose(r, n32, N32)) <= TOL32
+    _write(tmp_path, s, f=n, nph=nph, B=1, statistics=1)
+    _run(driver, tmp_path, "bose_rejects")
+    assert _out(tmp_path, "status").tolist() == [1.0] * 5   # EPHBTE_INVALID_ARGUMENT

@@ -494,13 +494,13 @@ def test_vjp_fp32(E):
     plan.close()
 
 
-@pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_bath_per_vector(E, dtype):
+@pytest.mark.parametrize("dtype,B", [("f64", 5), ("f32", 5), ("f64", 20), ("f32", 70)])
+def test_bath_per_vector(E, dtype, B):
     """nph [B, Nq, n_modes]: vector b sees the bath of its own temperature,
-    forward and reverse (dL/d|g|^2 summed over the vectors)."""
+    forward and reverse (dL/d|g|^2 summed over the vectors); B >= 8 runs the
+    forward pass batched, the baths in groups of 64 vectors."""
     s = synth.tb_system(kn=24, qn=12, target_states=400)
-    temps = [150.0, 300.0, 450.0, 220.0, 600.0]
-    B = len(temps)
+    temps = [[150.0, 300.0, 450.0, 220.0, 600.0][b % 5] + 7.0 * b for b in range(B)]
     F = np.stack([np.clip(synth.random_occupations(s, 20 + b), 0, 1) for b in range(B)])
     NPH = np.stack([s.nph(T) for T in temps])
     L = np.random.default_rng(5).normal(size=(B, s.n_states))
@@ -1133,6 +1133,133 @@ def test_transport_fp32_stops_at_its_floor(E):
 
 
 # ------------------------------------------------------------------ full size
+# ---------------------------------------------------------------------------
+# phonon-phonon scattering: Bose plans (statistics "bose")
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def phph():
+    s = synth.ph_ph_system(n=6)
+    n = synth.bose_occupations(s, 300.0, seed=80)
+    return s, n, synth.bose_einstein(s.hw, 250.0)
+
+
+def _bose_ref(s, n, nph, dtype):
+    if dtype == "f64":
+        return oracle.collision_bose(s, n, nph), TOL64, torch.float64, n, nph
+    r = round32(s)
+    n32, N32 = n.astype(np.float32).astype(np.float64), nph.astype(np.float32).astype(np.float64)
+    return oracle.collision_bose(r, n32, N32), TOL32, torch.float32, n32, N32
+
+
+@pytest.mark.parametrize("dtype,layout", [("f64", 3), ("f64", 2), ("f64", 1), ("f32", 3), ("f32", 1)])
+def test_bose_forward_matches_oracle(E, phph, dtype, layout):
+    """Three-phonon collision integral of a Bose plan (646 modes, 6.2e5
+    channels) against the oracle's Bose integral, over each layout."""
+    s, n, nph = phph
+    ref, tol, tdt, n_in, N_in = _bose_ref(s, n, nph, dtype)
+    plan = E.build_channels(s, dtype=dtype, device=0, statistics="bose")
+    E.set_tuning(plan, layout=layout)
+    say(f"bose forward {dtype} layout {layout} S={s.n_states} Nch={s.n_channels}")
+    I = host(E.collision_integral(plan, dev(n_in, tdt), dev(N_in, tdt)))
+    assert nerr(I, ref) <= tol
+    plan.close()
+
+
+def test_bose_forward_larger_grid(E):
+    """An 8^3 grid (1534 modes, 3.5e6 channels), FP64 over pair records."""
+    s = synth.ph_ph_system(n=8)
+    n = synth.bose_occupations(s, 300.0, seed=81)
+    nph = synth.bose_einstein(s.hw, 320.0)
+    plan = E.build_channels(s, device=0, statistics="bose")
+    say(f"bose forward 8^3 S={s.n_states} Nch={s.n_channels}")
+    I = host(E.collision_integral(plan, dev(n), dev(nph)))
+    assert nerr(I, oracle.collision_bose(s, n, nph)) <= TOL64
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_bose_batched_reverse_and_baths(E, phph, dtype):
+    """Bose plan, B = 9: forward and reverse (dL/dn per vector, dL/d|V|^2
+    summed) through the batched kernels; B = 4 with a bath per vector; the
+    reverse at B = 1 and dL/dN."""
+    s, n0, nph = phph
+    B = 9
+    F = np.stack([synth.bose_occupations(s, 300.0, seed=90 + b) for b in range(B)])
+    L = np.random.default_rng(91).normal(size=(B, s.n_states))
+    r, tol, tdt = s, TOL64, torch.float64
+    NPH = np.stack([synth.bose_einstein(s.hw, 200.0 + 50.0 * b) for b in range(4)])
+    N1 = nph
+    if dtype == "f32":
+        F, L, NPH, N1 = (a.astype(np.float32).astype(np.float64) for a in (F, L, NPH, nph))
+        r, tol, tdt = round32(s), TOL32, torch.float32
+    plan = E.build_channels(s, dtype=dtype, device=0, statistics="bose")
+    say(f"bose batched {dtype} B={B}")
+    I = host(E.collision_integral(plan, dev(F, tdt), dev(N1, tdt)))
+    for b in range(B):
+        assert nerr(I[b], oracle.collision_bose(r, F[b], N1)) <= tol, b
+    gf, gg = E.collision_vjp(plan, dev(F, tdt), dev(N1, tdt), dev(L, tdt), gg2=True)
+    gf, gg = host(gf), host(gg)
+    rg = 0
+    for b in range(B):
+        rn, rg_b, _ = oracle.collision_bose_vjp(r, F[b], N1, L[b])
+        assert nerr(gf[b], rn) <= tol, b
+        rg = rg + rg_b
+    assert nerr(gg, rg) <= tol
+    say(f"bose bath per vector {dtype}")
+    I4 = host(E.collision_integral(plan, dev(F[:4], tdt), dev(NPH, tdt)))
+    for b in range(4):
+        assert nerr(I4[b], oracle.collision_bose(r, F[b], NPH[b])) <= tol, b
+    say(f"bose reverse B=1 and dL/dN {dtype}")
+    gf1, gg1 = E.collision_vjp(plan, dev(F[0], tdt), dev(N1, tdt), dev(L[0], tdt), gg2=True)
+    rn, rg1, rN = oracle.collision_bose_vjp(r, F[0], N1, L[0])
+    assert nerr(host(gf1), rn) <= tol
+    assert nerr(host(gg1), rg1) <= tol
+    gN = host(E.collision_vjp_nph(plan, dev(F[0], tdt), dev(N1, tdt), dev(L[0], tdt)))
+    assert nerr(gN, rN) <= tol
+    plan.close()
+
+
+def test_bose_rt_steps_and_adjoint(E, phph):
+    """RK4 steps of dn/dt = I_B[n] (eager and graph replay, bitwise equal)
+    and their checkpointed adjoint, against the oracle."""
+    s, n0, nph = phph
+    dt, steps = 200.0, 4
+    ref = n0.copy()
+    for _ in range(steps):
+        ref = oracle.rk4_step(s, ref, nph, dt, statistics="bose")
+    plan = E.build_channels(s, device=0, statistics="bose")
+    say("bose rt steps")
+    a, b = dev(n0), dev(n0)
+    E.rt_step(plan, a, dev(nph), dt, steps)
+    E.rt_step(plan, b, dev(nph), dt, steps, use_graph=True)
+    a, b = host(a), host(b)
+    assert np.array_equal(a, b)
+    assert nerr(a - n0, ref - n0) <= TOL64
+    gT = np.random.default_rng(92).normal(size=s.n_states)
+    _, rn, rg = oracle.rk4_trajectory_grad(s, n0, nph, dt, 3, gT, statistics="bose")
+    say("bose rt adjoint")
+    for ce in (1, 3):
+        gn, gg = E.rt_adjoint(plan, dev(n0), dev(nph), dt, 3, ce, dev(gT), gg2=True)
+        assert nerr(host(gn), rn) <= TOL64
+        assert nerr(host(gg), rg) <= TOL64
+    plan.close()
+
+
+def test_bose_plan_rejects_fermi_only_entry_points(E, phph):
+    s, n0, nph = phph
+    plan = E.build_channels(s, device=0, statistics="bose")
+    say("bose rejections")
+    with pytest.raises(E.EphbteError, match="Fermi statistics only"):
+        E.phonon_rate(plan, dev(n0), dev(nph))
+    with pytest.raises(E.EphbteError, match="Fermi statistics only"):
+        E.set_field(plan, [0.01, 0.0, 0.0])
+    with pytest.raises(E.EphbteError, match="Fermi statistics only"):
+        E.collision_integral_noalloc(plan, dev(n0), dev(nph), dev(np.zeros(s.n_states)))
+    with pytest.raises(ValueError):
+        E.build_channels(s, device=0, statistics="anyon")
+    plan.close()
+
+
 @pytest.fixture(scope="module")
 def c2():
     return synth.tb_system()
