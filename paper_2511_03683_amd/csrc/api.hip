@@ -691,6 +691,13 @@ void enqueue_forward_batched(ephbte_plan P, int B, const T *f, int64_t ldf, cons
     HIPC(hipGetLastError());
 }
 
+// the per-vector N of 64 vectors on the table rows, addressed by 32-bit byte
+// offsets in the batched pass
+bool pv_table_fits(ephbte_plan P) {
+    const int64_t rows = P->padq ? P->qpad_n : static_cast<int64_t>(P->nq[0]) * P->nq[1] * P->nq[2];
+    return rows * P->nm * 64 * (P->dtype == EPHBTE_F64 ? 8 : 4) < (int64_t(1) << 31);
+}
+
 // I for B >= 8 vectors with a bath per vector (nph: B tables [Nq][n_modes]):
 // per group of 64 vectors, their N on the rows of the {hw, N} table
 // ([row][mode][64], in P->nvec) and one batched launch that applies each
@@ -717,7 +724,7 @@ void enqueue_forward_batched_pv(ephbte_plan P, int B, const T *f, int64_t ldf, c
         auto go = [&](auto rc) {
             constexpr int RUN = decltype(rc)::value;
             hipLaunchKernelGGL((k_fwd_batched<T, kBatchDPW, RUN>), grid, dim3(kBatchThreads), shm, s, a, fg, ldf, nb,
-                               E, (const T *)nv, int64_t(0));
+                               E, (const T *)nv, ld);
         };
         if (P->nm <= 1) go(std::integral_constant<int, 1>{});
         else if (P->nm <= 2) go(std::integral_constant<int, 2>{});
@@ -2383,7 +2390,7 @@ ephbte_status ephbte_collision_integral(ephbte_plan plan, int32_t batch, const v
             if (!nph_per_batch || batch == 1) {
                 ensure_fwd<T>(plan, batch);
                 enqueue_forward<T>(plan, batch, ft, ldft, nph, epi_store<T>(It, ldi), s);
-            } else if (batch >= plan->batch_min && plan->n_btiles > 0) {
+            } else if (batch >= plan->batch_min && plan->n_btiles > 0 && pv_table_fits(plan)) {
                 // a bath per vector, batched: the table's hw from the first bath's pack
                 ensure_fwd<T>(plan, batch);
                 enqueue_pack<T>(plan, nph, s);

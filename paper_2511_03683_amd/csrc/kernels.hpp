@@ -1675,10 +1675,23 @@ template <> __device__ __forceinline__ float lane_bcast(float v, int src) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
 }
 
+// Fourth word of a raw buffer resource on gfx9-family parts (32-bit data
+// format; no swizzle, no index stride)
+constexpr int kBufferDword3 = 0x00020000;
+
+template <typename T> __device__ __forceinline__ T buffer_load_value(__amdgpu_buffer_rsrc_t r, int voff, int soff);
+template <> __device__ __forceinline__ double buffer_load_value(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+template <> __device__ __forceinline__ float buffer_load_value(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+
 // RUN = 0: one phonon table for all vectors.  RUN > 0: a bath per vector
 // (RUN bounds the entries of one pair, the mode count rounded up): N comes
-// from nvec, [row][mode][64] per group of 64 vectors (row = the q index of
-// the shared table), and an entry's coefficients split into the part without
+// from nvec, [row][mode][64] for the launch's 64 vectors (nvec_ld values; row
+// = the q index of the shared table), and an entry's coefficients split into
+// the part without
 // N, summed over the pair's modes as before, and |g|^2 (G(x + hw) +
 // G(x - hw)), applied per vector with that vector's N.
 template <typename T, int DPW, int RUN>
@@ -1775,18 +1788,30 @@ __global__ __launch_bounds__(512) void k_fwd_batched(BArgs<T> A, const T *__rest
                         // last valid lane; each of its entries adds
                         // c1 N_b(q, mode) for this lane's vector b
                         const int nvalid = static_cast<int>(min<int64_t>(64, e_hi - e0));
-                        const T *__restrict__ nv = nvec + static_cast<int64_t>(blockIdx.y) * nvec_ld + lane;
-                        while (m) {
-                            const int src = __builtin_ctzll(m);
-                            m &= m - 1;
-                            const int end = m ? __builtin_ctzll(m) : nvalid;
+                        // buffer loads: the row offset is a scalar operand and
+                        // the lane offset a fixed register, so a load needs no
+                        // address registers (whose reuse would make the wave
+                        // wait for loads in flight); reads past the table
+                        // return 0
+                        const __amdgpu_buffer_rsrc_t nvr = __builtin_amdgcn_make_buffer_rsrc(
+                            const_cast<T *>(nvec), 0, static_cast<int>(nvec_ld * sizeof(T)), kBufferDword3);
+                        const int lane_off = lane * static_cast<int>(sizeof(T));
+                        // entries past a run re-read its last one, weighted 0
+                        auto load_run = [&](int src, int end, T (&buf)[RUN]) {
+#pragma unroll
+                            for (int r = 0; r < RUN; ++r) {
+                                const int j = min(src + r, end - 1);
+                                const int row = __builtin_amdgcn_readlane(ti, j) * 64 * static_cast<int>(sizeof(T));
+                                buf[r] = buffer_load_value<T>(nvr, lane_off, row);
+                            }
+                        };
+                        auto apply_run = [&](int src, int end, const T (&buf)[RUN]) {
                             T nsum = T(0);
 #pragma unroll
                             for (int r = 0; r < RUN; ++r) {
-                                // entries past the run re-read its last one, weighted 0
                                 const int j = min(src + r, end - 1);
                                 const T w = src + r < end ? lane_bcast(c1, j) : T(0);
-                                nsum += w * nv[static_cast<int64_t>(__builtin_amdgcn_readlane(ti, j)) * 64];
+                                nsum += w * buf[r];
                             }
                             const T a = lane_bcast(ca, src) + nsum;
                             const T bq = lane_bcast(cb, src) + nsum;
@@ -1794,6 +1819,35 @@ __global__ __launch_bounds__(512) void k_fwd_batched(BArgs<T> A, const T *__rest
                             const T fpb = s_F[pls * 65 + lane];
                             sa += a * (T(1) - fpb);
                             sb += bq * fpb;
+                        };
+                        // two runs in flight: the next run's N loads are
+                        // issued before this run's are waited for (two
+                        // register sets, so nothing is copied between them).
+                        // Past the last run the loads repeat the current
+                        // one, so every step issues the same number of loads
+                        // and the wait for a run never covers the next.
+                        if (m) {
+                            T b0[RUN], b1[RUN];
+                            int s0 = __builtin_ctzll(m), s1, t1;
+                            m &= m - 1;
+                            int t0 = m ? __builtin_ctzll(m) : nvalid;
+                            load_run(s0, t0, b0);
+                            while (true) {
+                                const bool h1 = m != 0;
+                                s1 = h1 ? __builtin_ctzll(m) : s0;
+                                m &= m - 1;
+                                t1 = h1 ? (m ? __builtin_ctzll(m) : nvalid) : t0;
+                                load_run(s1, t1, b1);
+                                apply_run(s0, t0, b0);
+                                if (!h1) break;
+                                const bool h0 = m != 0;
+                                s0 = h0 ? __builtin_ctzll(m) : s1;
+                                m &= m - 1;
+                                t0 = h0 ? (m ? __builtin_ctzll(m) : nvalid) : t1;
+                                load_run(s0, t0, b0);
+                                apply_run(s1, t1, b1);
+                                if (!h0) break;
+                            }
                         }
                     } else {
                         while (m) {

@@ -151,6 +151,26 @@ inline unsigned long long __ballot(int p) {
 inline int __builtin_amdgcn_readlane(int v, int src) { return emu::xchg(v, src); }
 inline float __builtin_amdgcn_exp2f(float x) { return exp2f(x); }
 inline void __builtin_amdgcn_sched_barrier(int) {}
+// raw buffer resources: base, size in bytes; loads past the size return 0
+struct __amdgpu_buffer_rsrc_t {
+    const unsigned char *base;
+    int num;
+};
+inline __amdgpu_buffer_rsrc_t __builtin_amdgcn_make_buffer_rsrc(void *p, short, int num, int) {
+    return {static_cast<const unsigned char *>(p), num};
+}
+inline unsigned long long __builtin_amdgcn_raw_buffer_load_b64(__amdgpu_buffer_rsrc_t r, int voff, int soff, int) {
+    const long long o = static_cast<long long>(voff) + soff;
+    unsigned long long v = 0;
+    if (o >= 0 && o + 8 <= r.num) std::memcpy(&v, r.base + o, 8);
+    return v;
+}
+inline unsigned __builtin_amdgcn_raw_buffer_load_b32(__amdgpu_buffer_rsrc_t r, int voff, int soff, int) {
+    const long long o = static_cast<long long>(voff) + soff;
+    unsigned v = 0;
+    if (o >= 0 && o + 4 <= r.num) std::memcpy(&v, r.base + o, 4);
+    return v;
+}
 // DPP moves with the controls the library uses: row_shr:1..15 within rows
 // of 16 lanes, row_bcast:15 (lane 15 of each row to the next row) and
 // row_bcast:31 (lane 31 to rows 2 and 3).  Rows outside row_mask, and lanes
