@@ -358,7 +358,16 @@ def main():
             ms=msb + msbv, per_vector_channels_per_s=B * nch / ((msb + msbv) * 1e-3),
             ratio_vs_b1=(ms + ms_v) * B / (msb + msbv))
         log(f"vjp fp64 B=64: {msbv:.3f} ms ({forms['vjp_f64_b64']['ratio_vs_b1']:.2f}x per vector)")
-        del F, IB, LB, ggb
+        # the same 64 vectors, each with its own bath (Bose-Einstein at its
+        # temperature): the batched pass with N per vector
+        temps = np.repeat(np.linspace(100.0, 400.0, 16), 4)
+        NB = tens(np.stack([s.nph(float(T)) for T in temps]), torch.float64)
+        mspv, _ = timed(lambda: E.collision_integral(plan64, F, NB, out=IB), 3, 1)
+        forms["fwd_f64_b64_bath_per_vector"] = dict(ms=mspv, per_vector_channels_per_s=B * nch / (mspv * 1e-3),
+                                                    ratio_vs_shared_bath=mspv / msb,
+                                                    baths="Bose-Einstein at each vector's temperature")
+        log(f"fwd fp64 B=64, bath per vector: {mspv:.3f} ms ({mspv / msb:.2f}x the shared bath)")
+        del F, IB, LB, ggb, NB
         # phonon side of the same processes (dN/dt of every (q, mode)), FP64
         phonon_rate(max(3, args.steps // 4))
         # transport iteration, FP64

@@ -945,7 +945,9 @@ __device__ __forceinline__ void pair_chunk(const TiledArgs<T> &A, const T *__res
         __builtin_amdgcn_sched_barrier(0);
         const T de = sd.eps - ep;
         const T ofp = T(1) - fp;
-        T y = T(0);
+        // the pair's sums over its modes of a = |g|^2 (t + G(x - hw)) and
+        // b = |g|^2 (t + G(x + hw)); the occupation factors are the pair's
+        T sa = T(0), sb = T(0);
 #pragma unroll
         for (int m = 0; m < NM; ++m) {
             const T gm = v && m < nm ? g[m] : T(0);
@@ -954,13 +956,14 @@ __device__ __forceinline__ void pair_chunk(const TiledArgs<T> &A, const T *__res
             const T da = pair_gauss<T, TAB>(A, xa * xa, s_tab);
             const T dem = pair_gauss<T, TAB>(A, xe * xe, s_tab);
             const T t = N * (da + dem);
-            const T ta = gm * (t + dem) * ofp;
-            const T tb = gm * (t + da) * fp;
-            acc_a += ta;
-            acc_b += tb;
-            // partner side: -Y = f_d ta - (1 - f_d) tb
-            y += fma(fd, ta, -cfd * tb);
+            sa = fma(gm, t + dem, sa);
+            sb = fma(gm, t + da, sb);
         }
+        const T ta = sa * ofp, tb = sb * fp;
+        acc_a += ta;
+        acc_b += tb;
+        // partner side: -Y = f_d ta - (1 - f_d) tb
+        const T y = fma(fd, ta, -cfd * tb);
         if (v) {
             const unsigned long long fx = to_fixed(__builtin_rint(y * scale));
             if (LDS) atomicAdd(s_j + pl, fx);
@@ -1048,10 +1051,10 @@ __device__ __forceinline__ double vjp_scale(const unsigned long long *nmax_bits,
     return ldexp(1.0, 61 - e);
 }
 
-// threads per workgroup of the pair reverse pass: 12 waves, so that a lane
-// may hold up to 168 registers (the pass keeps more values live than the
-// forward's 128)
-constexpr int kVjpPairThreads = 768;
+// threads per workgroup of the pair reverse pass: 16 waves, as the forward
+// (a lane holds at most 128 registers; the pass needs about 100 with the
+// modes summed per pair)
+constexpr int kVjpPairThreads = 1024;
 
 template <typename T, bool LDS, bool PADQ, int NM, bool TAB>
 __device__ __forceinline__ void vjp_pair_chunk(const TiledArgs<T> &A, const T *__restrict__ fb,
@@ -1117,7 +1120,10 @@ __device__ __forceinline__ void vjp_pair_chunk(const TiledArgs<T> &A, const T *_
         const T x = sd.eps - ep;
         const T ofp = T(1) - fp;
         const T dl = ld - lp;
-        T y = T(0);
+        // per mode dL/d|g|^2 = kb bh - ka ah; the pair's sums of |g|^2 ah and
+        // |g|^2 bh serve both occupation sides
+        const T kb = A.K * dl * cfd * fp, ka = A.K * dl * fd * ofp;
+        T sa = T(0), sb = T(0);
         double gv[NM];
 #pragma unroll
         for (int m = 0; m < NM; ++m) {
@@ -1129,11 +1135,12 @@ __device__ __forceinline__ void vjp_pair_chunk(const TiledArgs<T> &A, const T *_
             const T dem = pair_gauss<T, TAB>(A, xe * xe, s_tab);
             const T t = N * (da + dem);
             const T ah = t + dem, bh = t + da;
-            const T dg = dl * gm;
-            acc += dg * (ah * ofp + bh * fp);
-            y += dg * (bh * cfd + ah * fd);
-            gv[m] = static_cast<double>(A.K * dl * (cfd * bh * fp - fd * ah * ofp));
+            sa = fma(gm, ah, sa);
+            sb = fma(gm, bh, sb);
+            gv[m] = static_cast<double>(fma(kb, bh, -ka * ah));
         }
+        acc += dl * fma(sa, ofp, sb * fp);
+        const T y = dl * fma(sb, cfd, sa * fd);
         if (gg2_mode && v) {
             if (c0 >= 0 && NM == nm && (NM & 1) == 0 && (c0 & 1) == 0) {
                 // the record's channels are consecutive in the caller's order
