@@ -818,7 +818,7 @@ template <typename T> void enqueue_pack(ephbte_plan P, const void *nph, hipStrea
         nb = static_cast<unsigned>(std::max<int64_t>(std::min<int64_t>((n + 255) / 256, kPackBlocks), 1));
         hipLaunchKernelGGL((k_pack_hwN_pad<T>), dim3(nb), dim3(256), 0, s, static_cast<const T *>(P->hw),
                            static_cast<const T *>(nph), static_cast<Pair2<T> *>(P->hwN.p), P->qbox, P->nm,
-                           P->qpad_n, P->tab_mm ? 1 : 0, bmax);
+                           static_cast<int>(P->qpad_n), P->tab_mm ? 1 : 0, bmax);
     } else {
         const int64_t n = nqm_of(P);
         nb = static_cast<unsigned>(std::max<int64_t>(std::min<int64_t>((n + 255) / 256, kPackBlocks), 1));

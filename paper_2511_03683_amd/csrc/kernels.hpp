@@ -453,13 +453,14 @@ struct QBox {
     int h[3];   // span - 1
 };
 
-__device__ __forceinline__ int64_t box_q(int64_t qp, const QBox &B) {
+// (box rows and q points are below 2^31: 32-bit arithmetic)
+__device__ __forceinline__ int box_q(int qp, const QBox &B) {
     int x[3];
-    x[2] = static_cast<int>(qp % B.b[2]);
+    x[2] = qp % B.b[2];
     qp /= B.b[2];
-    x[1] = static_cast<int>(qp % B.b[1]);
-    x[0] = static_cast<int>(qp / B.b[1]);
-    int64_t q = 0;
+    x[1] = qp % B.b[1];
+    x[0] = qp / B.b[1];
+    int q = 0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         int v = x[a] - B.h[a];
@@ -471,16 +472,16 @@ __device__ __forceinline__ int64_t box_q(int64_t qp, const QBox &B) {
 
 // {hw, N} of every (row, mode) of the box: entry i is (qp, nu) with
 // i = qp nm + nu (mode_major = 0) or i = nu rows + qp (mode_major = 1).
+// The table holds fewer than 2^31 entries (the plan sizes it under 256 MB).
 template <typename T>
 __global__ void k_pack_hwN_pad(const T *__restrict__ hw, const T *__restrict__ nph,
-                               Pair2<T> *__restrict__ out, QBox B, int nm, int64_t rows, int mode_major,
+                               Pair2<T> *__restrict__ out, QBox B, int nm, int rows, int mode_major,
                                double *bmax) {
     double m = 0.0;
-    const int64_t n = rows * nm;
-    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
-         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        const int nu = static_cast<int>(mode_major ? i / rows : i % nm);
-        const int64_t qp = mode_major ? i % rows : i / nm;
+    const int n = rows * nm;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int nu = mode_major ? i / rows : i % nm;
+        const int qp = mode_major ? i % rows : i / nm;
         const int64_t q = box_q(qp, B);
         Pair2<T> v;
         v.a = hw[q * nm + nu];
@@ -2268,7 +2269,7 @@ __global__ void k_pack_nvec(const T *__restrict__ nph, T *__restrict__ out, int 
         r /= nm;
         const int64_t row = r % rows;
         const int b = static_cast<int>(r / rows) * 64 + j;
-        const int64_t q = pad ? box_q(row, Bx) : row;
+        const int64_t q = pad ? box_q(static_cast<int>(row), Bx) : row;
         out[i] = b < B ? nph[static_cast<int64_t>(b) * tab + q * nm + nu] : T(0);
     }
 }
@@ -2282,7 +2283,7 @@ __global__ void k_pack_hwNmu(const T *__restrict__ hw, const T *__restrict__ nph
     for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
          i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         int64_t src = i;
-        if (pad) src = box_q(i / nm, B) * nm + i % nm;
+        if (pad) src = static_cast<int64_t>(box_q(static_cast<int>(i / nm), B)) * nm + i % nm;
         Vec4<T> v;
         v.x = hw[src];
         v.y = nph[src];
