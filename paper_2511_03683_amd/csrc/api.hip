@@ -178,6 +178,10 @@ struct ephbte_plan_s {
     int64_t qpad_n = 0;         // rows of the box table (QBox)
     QBox qbox{};
     uint32_t qorg[3] = {0, 0, 0};   // per-axis origin of the shifted k coordinates
+    // box rows some entry references (ascending); the packs write only these,
+    // the others stay zero from the table's allocation
+    int32_t *used_rows = nullptr;
+    int64_t n_used_rows = 0;
     bool tab_mm = false;        // box table stored one block per mode
     int chunk_entries = 0;
     int64_t tile_entries = 0;   // 0: default target per tile
@@ -272,6 +276,17 @@ void ensure(DevBuf &b, size_t bytes, int64_t *gen) {
     b.bytes = bytes;
 }
 
+// ensure() for tables whose packs write only the referenced rows: a new
+// allocation is cleared once (finite zeros where masked lanes may read)
+void ensure_zeroed(ephbte_plan P, DevBuf &b, size_t bytes) {
+    const int64_t gen = P->ws_gen;
+    ensure(b, bytes, &P->ws_gen);
+    if (P->ws_gen != gen) {
+        HIPC(hipMemset(b.p, 0, b.bytes));
+        HIPC(hipDeviceSynchronize());
+    }
+}
+
 // Device address of `scratch` on device dev (which must be current), looked
 // up on the first call for that device and kept.
 void *scratch_base(int dev) {
@@ -310,7 +325,8 @@ void free_plan(ephbte_plan P) {
                      (void **)&P->ph_bucket_modes, (void **)&P->pr_partner, (void **)&P->pr_g2,
                      (void **)&P->pr_chan, (void **)&P->pr_chunk_beg, (void **)&P->pr_chunk_end,
                      (void **)&P->pr_chunk_dest, (void **)&P->pr_dest_chunk, (void **)&P->pr_tiles,
-                     (void **)&P->lmax_bits, (void **)&P->pr_ch0, (void **)&P->fmax_bits};
+                     (void **)&P->lmax_bits, (void **)&P->pr_ch0, (void **)&P->fmax_bits,
+                     (void **)&P->used_rows};
     for (auto pp : ptrs) dfree(*pp);
     DevBuf *w[] = {&P->part,   &P->sym_part, &P->rk_ua,  &P->rk_ub,   &P->rk_acc, &P->hwN, &P->tr_W,   &P->tr_tau_inv,
                    &P->tr_tau, &P->tr_rhs, &P->tr_xa,   &P->tr_xb,  &P->tr_part, &P->tr_red,
@@ -710,13 +726,15 @@ void enqueue_forward_batched_pv(ephbte_plan P, int B, const T *f, int64_t ldf, c
     const size_t shm = batch_lds_bytes(P, P->pt);
     const int64_t rows = P->padq ? P->qpad_n : static_cast<int64_t>(P->nq[0]) * P->nq[1] * P->nq[2];
     const int64_t ld = rows * P->nm * 64;
-    ensure(P->nvec, sizeof(T) * static_cast<size_t>(ld), &P->ws_gen);
+    ensure_zeroed(P, P->nvec, sizeof(T) * static_cast<size_t>(ld));
     const int64_t tab = nqm_of(P);
     T *nv = static_cast<T *>(P->nvec.p);
+    const int n_rows = static_cast<int>(P->padq ? P->n_used_rows : rows);
     for (int g = 0; g * 64 < B; ++g) {
         const int nb = std::min(64, B - g * 64);
-        hipLaunchKernelGGL((k_pack_nvec<T>), dim3(grid_of(ld)), dim3(256), 0, s, nph + g * 64 * tab, nv,
-                           P->padq ? 1 : 0, P->qbox, P->nm, rows, nb, ld);
+        hipLaunchKernelGGL((k_pack_nvec<T>), dim3(grid_of(static_cast<int64_t>(n_rows) * P->nm * 64)), dim3(256), 0,
+                           s, nph + g * 64 * tab, nv, P->padq ? 1 : 0, P->qbox, P->nm, (const int32_t *)P->used_rows,
+                           n_rows, nb);
         const Epi<T> E = epi_store<T>(I + g * 64 * ldi, ldi);
         const dim3 grid(static_cast<unsigned>(P->n_btiles), 1);
         const BArgs<T> a = batch_args<T>(P);
@@ -814,11 +832,12 @@ template <typename T> void enqueue_pack(ephbte_plan P, const void *nph, hipStrea
     double *bmax = P->pack_bmax;
     unsigned nb;
     if (P->padq) {
-        const int64_t n = P->qpad_n * P->nm;
+        const int64_t n = P->n_used_rows * P->nm;
         nb = static_cast<unsigned>(std::max<int64_t>(std::min<int64_t>((n + 255) / 256, kPackBlocks), 1));
         hipLaunchKernelGGL((k_pack_hwN_pad<T>), dim3(nb), dim3(256), 0, s, static_cast<const T *>(P->hw),
                            static_cast<const T *>(nph), static_cast<Pair2<T> *>(P->hwN.p), P->qbox, P->nm,
-                           static_cast<int>(P->qpad_n), P->tab_mm ? 1 : 0, bmax);
+                           static_cast<int>(P->qpad_n), (const int32_t *)P->used_rows,
+                           static_cast<int>(P->n_used_rows), P->tab_mm ? 1 : 0, bmax);
     } else {
         const int64_t n = nqm_of(P);
         nb = static_cast<unsigned>(std::max<int64_t>(std::min<int64_t>((n + 255) / 256, kPackBlocks), 1));
@@ -913,7 +932,7 @@ template <typename T> void ensure_fwd(ephbte_plan P, int B) {
         ensure(P->sym_part, sizeof(T) * 2 * static_cast<size_t>(std::max<int64_t>(P->n_pr_chunks, 1)),
                &P->ws_gen);
     const int64_t tab = P->padq ? P->qpad_n * P->nm : nqm_of(P);
-    ensure(P->hwN, sizeof(Pair2<T>) * static_cast<size_t>(std::max<int64_t>(tab, 1)), &P->ws_gen);
+    ensure_zeroed(P, P->hwN, sizeof(Pair2<T>) * static_cast<size_t>(std::max<int64_t>(tab, 1)));
 }
 
 template <typename T> void ensure_part(ephbte_plan P, int B, int per_chunk) {
@@ -1244,6 +1263,29 @@ template <typename T> void upload_layout(ephbte_plan P, const ephbte_problem *pr
             }
         }
         HIPC(hipMemcpy(P->st, st.data(), sizeof(StateRec<T>) * S, hipMemcpyHostToDevice));
+        if (P->padq) {
+            // box rows the entries reference (both orientations of every
+            // channel, and q = 0): the only rows a call packs
+            const int T_ = host_threads();
+            std::vector<std::vector<uint8_t>> marks(T_, std::vector<uint8_t>(static_cast<size_t>(P->qpad_n), 0));
+            parallel_ranges(S, T_, [&](int t, int64_t b, int64_t e) {
+                std::vector<uint8_t> &m = marks[t];
+                for (int64_t d = b; d < e; ++d)
+                    for (int64_t x = L.row_ptr[d]; x < L.row_ptr[d + 1]; ++x) {
+                        const int p = static_cast<int>(L.pnu[x] >> 3);
+                        m[static_cast<int64_t>(static_cast<int>(st[p].kqp - st[d].kqp) + P->qoff)] = 1;
+                    }
+            });
+            std::vector<int32_t> used;
+            for (int64_t r = 0; r < P->qpad_n; ++r) {
+                bool on = r == P->qoff;
+                for (int t = 0; t < T_ && !on; ++t) on = marks[t][r] != 0;
+                if (on) used.push_back(static_cast<int32_t>(r));
+            }
+            P->n_used_rows = static_cast<int64_t>(used.size());
+            dalloc(P->used_rows, sizeof(int32_t) * used.size(), &acc);
+            HIPC(hipMemcpy(P->used_rows, used.data(), sizeof(int32_t) * used.size(), hipMemcpyHostToDevice));
+        }
     }
     {
         std::vector<T> h(nqm);
@@ -1683,10 +1725,10 @@ void enqueue_phonon_adj(ephbte_plan P, const T *u, const T *N, const T *lam, con
 // P->part for n_chunks values)
 template <typename T>
 void enqueue_phonon_vjp_f(ephbte_plan P, const T *u, const T *N, const T *mu, T *out, hipStream_t s) {
-    const int64_t n = P->padq ? P->qpad_n * P->nm : nqm_of(P);
+    const int64_t n = P->padq ? P->n_used_rows * P->nm : nqm_of(P);
     Vec4<T> *tab = static_cast<Vec4<T> *>(P->ph_tab4.p);
     hipLaunchKernelGGL((k_pack_hwNmu<T>), dim3(grid_of(n)), dim3(256), 0, s, static_cast<const T *>(P->hw), N, mu,
-                       tab, P->padq ? 1 : 0, P->qbox, P->nm, n);
+                       tab, P->padq ? 1 : 0, P->qbox, P->nm, (const int32_t *)P->used_rows, n);
     TiledArgs<T> a = tiled_args<T>(P);
     T *part = static_cast<T *>(P->part.p);
     const double Kp = 2.0 * kPi / (kHbar * P->nk) / (P->sigma * std::sqrt(2.0 * kPi));
@@ -1701,7 +1743,7 @@ void enqueue_phonon_vjp_f(ephbte_plan P, const T *u, const T *N, const T *mu, T 
 
 template <typename T> void ensure_phonon_vjp(ephbte_plan P) {
     const int64_t n = P->padq ? P->qpad_n * P->nm : nqm_of(P);
-    ensure(P->ph_tab4, sizeof(Vec4<T>) * static_cast<size_t>(std::max<int64_t>(n, 1)), &P->ws_gen);
+    ensure_zeroed(P, P->ph_tab4, sizeof(Vec4<T>) * static_cast<size_t>(std::max<int64_t>(n, 1)));
     ensure_part<T>(P, 1, 2);
     ensure_phonon(P);
 }

@@ -470,23 +470,24 @@ __device__ __forceinline__ int box_q(int qp, const QBox &B) {
     return q;
 }
 
-// {hw, N} of every (row, mode) of the box: entry i is (qp, nu) with
-// i = qp nm + nu (mode_major = 0) or i = nu rows + qp (mode_major = 1).
-// The table holds fewer than 2^31 entries (the plan sizes it under 256 MB).
+// {hw, N} of the box rows `used` (the rows some entry references), every
+// mode: row qp, mode nu at qp nm + nu (mode_major = 0) or nu rows + qp
+// (mode_major = 1).  The table holds fewer than 2^31 entries (the plan sizes
+// it under 256 MB); rows not listed keep their zeros.
 template <typename T>
 __global__ void k_pack_hwN_pad(const T *__restrict__ hw, const T *__restrict__ nph,
-                               Pair2<T> *__restrict__ out, QBox B, int nm, int rows, int mode_major,
-                               double *bmax) {
+                               Pair2<T> *__restrict__ out, QBox B, int nm, int rows,
+                               const int32_t *__restrict__ used, int n_used, int mode_major, double *bmax) {
     double m = 0.0;
-    const int n = rows * nm;
+    const int n = n_used * nm;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const int nu = mode_major ? i / rows : i % nm;
-        const int qp = mode_major ? i % rows : i / nm;
+        const int nu = i % nm;
+        const int qp = used[i / nm];
         const int64_t q = box_q(qp, B);
         Pair2<T> v;
         v.a = hw[q * nm + nu];
         v.b = nph[q * nm + nu];
-        out[i] = v;
+        out[mode_major ? nu * rows + qp : qp * nm + nu] = v;
         m = fmax(m, fabs(static_cast<double>(v.b)));
     }
     block_max_to(m, bmax + blockIdx.x);
@@ -2253,24 +2254,24 @@ __global__ __launch_bounds__(256) void k_phonon_bins_adj(PhArgs<T> A, const T *_
     }
 }
 
-// Per-vector baths of the batched pass: entry ((g rows + row) nm + nu) 64 + j
-// holds N of vector 64 g + j (0 past the last vector) at the table row `row`
-// (a box row when pad != 0, else a q index) and mode nu.  nph holds B tables
-// of [Nq][nm].
+// Per-vector baths of the batched pass, 64 vectors: entry (row nm + nu) 64 + j
+// holds N of vector j (0 past the last of the B vectors) at table row `row`
+// and mode nu, for the box rows in `used` (pad != 0; other rows keep their
+// zeros) or every q (pad = 0, n_rows = Nq).  nph holds B tables of [Nq][nm].
 template <typename T>
 __global__ void k_pack_nvec(const T *__restrict__ nph, T *__restrict__ out, int pad, QBox Bx, int nm,
-                            int64_t rows, int B, int64_t n) {
+                            const int32_t *__restrict__ used, int n_rows, int B) {
     const int64_t tab = static_cast<int64_t>(Bx.n[0]) * Bx.n[1] * Bx.n[2] * nm;
+    const int64_t n = static_cast<int64_t>(n_rows) * nm * 64;
     for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
          i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         const int j = static_cast<int>(i & 63);
-        int64_t r = i >> 6;
+        const int64_t r = i >> 6;
         const int nu = static_cast<int>(r % nm);
-        r /= nm;
-        const int64_t row = r % rows;
-        const int b = static_cast<int>(r / rows) * 64 + j;
-        const int64_t q = pad ? box_q(static_cast<int>(row), Bx) : row;
-        out[i] = b < B ? nph[static_cast<int64_t>(b) * tab + q * nm + nu] : T(0);
+        const int u = static_cast<int>(r / nm);
+        const int row = pad ? used[u] : u;
+        const int64_t q = pad ? box_q(row, Bx) : row;
+        out[(static_cast<int64_t>(row) * nm + nu) * 64 + j] = j < B ? nph[static_cast<int64_t>(j) * tab + q * nm + nu] : T(0);
     }
 }
 
@@ -2279,17 +2280,23 @@ __global__ void k_pack_nvec(const T *__restrict__ nph, T *__restrict__ out, int 
 // plain table.
 template <typename T>
 __global__ void k_pack_hwNmu(const T *__restrict__ hw, const T *__restrict__ nph, const T *__restrict__ mu,
-                             Vec4<T> *__restrict__ out, int pad, QBox B, int nm, int64_t n) {
+                             Vec4<T> *__restrict__ out, int pad, QBox B, int nm, const int32_t *__restrict__ used,
+                             int64_t n) {
+    // pad != 0: n = (rows in used) nm, other box rows keep their zeros
     for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
          i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        int64_t src = i;
-        if (pad) src = static_cast<int64_t>(box_q(static_cast<int>(i / nm), B)) * nm + i % nm;
+        int64_t src = i, dst = i;
+        if (pad) {
+            const int row = used[i / nm];
+            src = static_cast<int64_t>(box_q(row, B)) * nm + i % nm;
+            dst = static_cast<int64_t>(row) * nm + i % nm;
+        }
         Vec4<T> v;
         v.x = hw[src];
         v.y = nph[src];
         v.z = mu[src];
         v.w = T(0);
-        out[i] = v;
+        out[dst] = v;
     }
 }
 
