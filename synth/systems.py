@@ -605,7 +605,7 @@ def parabolic_states(n=60, a=20.0, m_eff=0.3) -> tuple:
     return eps, vel
 
 
-def pulse_occupations(system: System, mu=-0.1, T=300.0, amplitude=0.1, center=0.5,
+def pulse_occupations(system: System, mu=-0.1, T=300.0, amplitude=0.1, center=0.2,
                       width=0.05) -> np.ndarray:
     """Fermi-Dirac background plus a Gaussian electron pulse:
     f = FD(eps; mu, T) + amplitude * exp(-(eps - center)^2 / (2 width^2)), clipped to [0, 1]."""
