@@ -134,6 +134,12 @@ typedef struct {
                                   (one 16-byte row per mode, default),
                                   2 = one block per mode (a wave's gathers of
                                   one mode at neighbouring q share cache lines) */
+    int32_t pair_window;       /* partner states per LDS window of the pair-record
+                                  passes, 64 .. the most the LDS of a workgroup
+                                  holds for the reverse pass (default 3072 FP64,
+                                  4096 FP32)                                     */
+    int32_t pair_threads;      /* threads per workgroup of the pair-record forward
+                                  pass: 256, 512, 768 or 1024 (default)         */
 } ephbte_tuning;
 
 /* Build options.  Channel selection (paper: scattering-channel paragraph

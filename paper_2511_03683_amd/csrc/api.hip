@@ -139,6 +139,8 @@ struct ephbte_plan_s {
     unsigned long long *nmax_bits = nullptr, *gmax_bits = nullptr;
     double *pack_bmax = nullptr;            // per-block max |N| of the last pack
     int sym_lds_states = 0;
+    int pr_lds_states = 0;      // partner window of the pair-record passes
+    int pr_threads = 1024;      // threads per workgroup of the pair forward pass
     bool sym_ok = false;                    // the single-copy window fits the LDS of a workgroup
     int layout = 2;                         // B = 1 forward: 1 duplicated rows, 2 single copy,
                                             // 3 single copy over pair records
@@ -437,7 +439,7 @@ void upload_chunks(ephbte_plan P, int64_t chunk_entries) {
     ChunkTable pc = make_chunks_seg(pbeg, pend, chunk_entries);
     const int64_t target_p = P->tile_entries > 0 ? P->tile_entries / (2 * static_cast<int64_t>(P->nm)) + 1
                                                  : P->pr_np / (4 * static_cast<int64_t>(P->n_cu)) + 1;
-    std::vector<Tile> tp = make_tiles(pc, P->row_ptr, P->pmin_up, P->pmax_up, P->sym_lds_states, target_p);
+    std::vector<Tile> tp = make_tiles(pc, P->row_ptr, P->pmin_up, P->pmax_up, P->pr_lds_states, target_p);
     dfree(reinterpret_cast<void *&>(P->pr_chunk_beg));
     dfree(reinterpret_cast<void *&>(P->pr_chunk_end));
     dfree(reinterpret_cast<void *&>(P->pr_chunk_dest));
@@ -549,6 +551,7 @@ template <typename T> TiledArgs<T> sym_args(ephbte_plan P) {
 // arguments of the single-copy pass over pair records
 template <typename T> TiledArgs<T> pair_args(ephbte_plan P) {
     TiledArgs<T> a = sym_args<T>(P);
+    a.lds_states = P->pr_lds_states;
     a.pnu = P->pr_partner;
     a.g2 = static_cast<const T *>(P->pr_g2);
     a.pld = P->pr_ld;
@@ -598,7 +601,7 @@ bool use_sym(ephbte_plan P, int B) {
 template <typename T>
 void launch_pairs(ephbte_plan P, const TiledArgs<T> &a, const T *f, T *part, size_t shm, hipStream_t s,
                   bool padq) {
-    const dim3 grid(static_cast<unsigned>(P->n_pr_tiles)), block(1024);
+    const dim3 grid(static_cast<unsigned>(P->n_pr_tiles)), block(static_cast<unsigned>(P->pr_threads));
     auto go = [&](auto nmc) {
         constexpr int NM = decltype(nmc)::value;
         const bool tab = sizeof(T) == 8 && P->exp_table;
@@ -876,7 +879,7 @@ void enqueue_forward(ephbte_plan P, int B, const T *f, int64_t ldf, const void *
     if (use_pairs(P, B)) {
         TiledArgs<T> a = pair_args<T>(P);
         T *part = static_cast<T *>(P->sym_part.p);
-        const size_t shm = sym_lds_bytes(P->dtype, P->sym_lds_states);
+        const size_t shm = sym_lds_bytes(P->dtype, P->pr_lds_states);
         const int64_t kt = ktime_begin(P, s);
         launch_pairs<T>(P, a, f, part, shm, s, P->padq);
         ktime_end(P, s, kt);
@@ -973,7 +976,7 @@ void enqueue_forward_noalloc(ephbte_plan P, const T *f, const void *nph, T *I, u
         a.padq = 0;
         a.tq = P->nm;
         a.tm = 1;
-        launch_pairs<T>(P, a, f, part, sym_lds_bytes(P->dtype, P->sym_lds_states), s, false);
+        launch_pairs<T>(P, a, f, part, sym_lds_bytes(P->dtype, P->pr_lds_states), s, false);
         hipLaunchKernelGGL((k_sym_finish<T>), dim3((P->S + 255) / 256), dim3(256), 0, s, a, f,
                            (const T *)part, E);
     } else if (use_sym(P, 1)) {
@@ -1008,7 +1011,7 @@ template <typename T>
 void enqueue_vjp(ephbte_plan P, const T *f, const T *lam, const void *nph, const Epi<T> &E,
                  double *gg2, int gg2_mode, hipStream_t s) {
     (void)nph;
-    if (use_pairs(P, 1) && vjp_pair_lds_bytes(P->dtype, P->sym_lds_states) <= P->lds_max) {
+    if (use_pairs(P, 1) && vjp_pair_lds_bytes(P->dtype, P->pr_lds_states) <= P->lds_max) {
         // max |lam| of this call (the partner side's fixed-point scale)
         hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, P->lmax_bits, 1);
         hipLaunchKernelGGL((k_abs_max_bits<T>), dim3(grid_of(P->S)), dim3(256), 0, s, lam, int64_t(P->S),
@@ -1018,7 +1021,7 @@ void enqueue_vjp(ephbte_plan P, const T *f, const T *lam, const void *nph, const
         T *part = static_cast<T *>(P->sym_part.p);
         const int want_f = E.mode >= 0 ? 1 : 0;
         const dim3 grid(static_cast<unsigned>(P->n_pr_tiles)), block(kVjpPairThreads);
-        const size_t shm = vjp_pair_lds_bytes(P->dtype, P->sym_lds_states);
+        const size_t shm = vjp_pair_lds_bytes(P->dtype, P->pr_lds_states);
         auto go = [&](auto nmc) {
             constexpr int NM = decltype(nmc)::value;
             const bool tab = sizeof(T) == 8 && P->exp_table;
@@ -2378,6 +2381,7 @@ ephbte_status ephbte_build_channels(const ephbte_problem *problem, const ephbte_
                 }
             });
             P->sym_lds_states = P->dtype == EPHBTE_F64 ? 3072 : 4096;
+            P->pr_lds_states = P->sym_lds_states;
             P->sym_ok = sym_lds_bytes(P->dtype, P->sym_lds_states) <= P->lds_max;
             if (P->sym_ok && P->pr_ok) P->layout = 3;
             dalloc(P->jacc, sizeof(unsigned long long) * std::max(P->S, 1), &P->layout_bytes);
@@ -2814,6 +2818,13 @@ ephbte_status ephbte_set_tuning(ephbte_plan plan, const ephbte_tuning *tuning) {
                         "batch_partners must be in [16, 1024] and fit the LDS of one workgroup");
         if (tuning->table_order < 0 || tuning->table_order > 2)
             return fail(EPHBTE_INVALID_ARGUMENT, "table_order must be 0 (keep), 1 or 2");
+        const int pw = tuning->pair_window;
+        if (pw != 0 && (pw < 64 || vjp_pair_lds_bytes(plan->dtype, pw) > plan->lds_max))
+            return fail(EPHBTE_INVALID_ARGUMENT,
+                        "pair_window must be >= 64 and fit the reverse pass's LDS of one workgroup");
+        const int pth = tuning->pair_threads;
+        if (pth != 0 && pth != 256 && pth != 512 && pth != 768 && pth != 1024)
+            return fail(EPHBTE_INVALID_ARGUMENT, "pair_threads must be 0 (keep), 256, 512, 768 or 1024");
         if (tuning->tile_entries < -1)
             return fail(EPHBTE_INVALID_ARGUMENT, "tile_entries must be -1 (default), 0 (keep) or > 0");
         if (tuning->fp64_exp < 0 || tuning->fp64_exp > 2)
@@ -2833,6 +2844,8 @@ ephbte_status ephbte_set_tuning(ephbte_plan plan, const ephbte_tuning *tuning) {
         if (tuning->layout) plan->layout = tuning->layout;
         if (tuning->fp64_exp) plan->exp_table = tuning->fp64_exp == 1;
         if (tuning->table_order) plan->tab_mm = tuning->table_order == 2;
+        if (pw) plan->pr_lds_states = pw;
+        if (pth) plan->pr_threads = pth;
         upload_chunks(plan, ce);
         if (pt != 0) upload_btiles(plan, pt);
         free_graphs(plan);

@@ -152,8 +152,10 @@ int main(int argc, char **argv) {
     t.tile_entries = static_cast<int32_t>(meta("tile_entries", 0));
     t.fp64_exp = static_cast<int32_t>(meta("fp64_exp", 0));
     t.table_order = static_cast<int32_t>(meta("table_order", 0));
+    t.pair_window = static_cast<int32_t>(meta("pair_window", 0));
+    t.pair_threads = static_cast<int32_t>(meta("pair_threads", 0));
     if (t.layout || t.chunk_entries || t.block_threads || t.xcd_map || t.batch_partners || t.tile_entries ||
-        t.fp64_exp || t.table_order)
+        t.fp64_exp || t.table_order || t.pair_window || t.pair_threads)
         check(ephbte_set_tuning(plan, &t), "set_tuning");
     // empty_windows: every LDS tile whose chunks hold no entries gets an empty
     // partner window (nothing staged), the shape that once made masked lanes

@@ -763,6 +763,24 @@ def test_pair_records_with_rounded_up_mode_count(driver, tmp_path, dtype, order)
     assert nerr(_out(tmp_path, "gg2"), rg) <= tol
 
 
+@pytest.mark.parametrize("window,threads", [(64, 256), (200, 512), (1000, 768)])
+def test_pair_windows_and_workgroup_sizes(driver, tmp_path, window, threads):
+    """Pair-record passes with smaller LDS windows (more tiles, some on the
+    global partner-side accumulator) and other workgroup sizes: forward and
+    reverse against the oracle under a random fill of fresh memory."""
+    s = synth.tb_system(kn=24, qn=12, target_states=400)
+    f = synth.random_occupations(s, 131)
+    lam = np.random.default_rng(132).normal(size=s.n_states)
+    nph = s.nph(300.0)
+    _write(tmp_path, s, f=f, lam=lam, nph=nph, B=1, layout=3, pair_window=window, pair_threads=threads)
+    _run(driver, tmp_path, "forward", fill="random:%d" % window)
+    assert nerr(_out(tmp_path, "I"), oracle.collision(s, f, nph)) <= TOL64
+    _run(driver, tmp_path, "vjp", fill="random:%d" % threads)
+    rf, rg = oracle.collision_vjp(s, f, nph, lam)
+    assert nerr(_out(tmp_path, "gf"), rf) <= TOL64
+    assert nerr(_out(tmp_path, "gg2"), rg) <= TOL64
+
+
 @pytest.mark.parametrize("layout,fill,order", [(3, "random:9", 1), (2, None, 1), (3, "random:10", 2)])
 def test_vjp_six_modes(driver, tmp_path, layout, fill, order):
     """Reverse pass on the six-mode tight-binding system: over pair records

@@ -195,6 +195,39 @@ def test_single_copy_and_duplicated_layouts(E, name, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_pair_pass_shapes_and_table_order(E, dtype):
+    """The pair-record passes with smaller LDS windows and other workgroup
+    sizes, and with the {hw, N} table one block per mode: forward and reverse
+    against the oracle, the forward bitwise equal to the default shape."""
+    s = synth.tb_system(kn=24, qn=12, target_states=400)
+    f = np.clip(synth.random_occupations(s, 141), 0, 1)
+    lam = np.random.default_rng(142).normal(size=s.n_states)
+    nph = s.nph(300.0)
+    r, tdt, tol = s, torch.float64, TOL64
+    if dtype == "f32":
+        f, lam, nph = (a.astype(np.float32).astype(np.float64) for a in (f, lam, nph))
+        r, tdt, tol = round32(s), torch.float32, TOL32
+    ref = oracle.collision(r, f, nph)
+    rin, rout = oracle.collision_inout(r, f, nph)
+    scale = max(np.abs(ref).max(), 1e-2 * max(rin.max(), rout.max()))
+    rf, rg = oracle.collision_vjp(r, f, nph, lam)
+    plan = E.build_channels(s, dtype=dtype, device=0)
+    assert E.plan_info(plan)["layout"] == 3
+    say(f"pair pass shapes {dtype}")
+    base = None
+    for w, th, order in ((0, 0, 1), (64, 256, 1), (500, 512, 1), (1000, 768, 2), (0, 1024, 2)):
+        E.set_tuning(plan, pair_window=w, pair_threads=th, table_order=order)
+        I = host(E.collision_integral(plan, dev(f, tdt), dev(nph, tdt)))
+        assert nerr(I, ref, scale) <= tol, (w, th, order)
+        if base is None:
+            base = I
+        gf, gg = E.collision_vjp(plan, dev(f, tdt), dev(nph, tdt), dev(lam, tdt), gg2=True)
+        assert nerr(host(gf), rf) <= tol, (w, th, order)
+        assert nerr(host(gg), rg) <= tol, (w, th, order)
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_single_copy_scale_adapts(E, dtype):
     """The single-copy pass's fixed-point scale follows the inputs: |g|^2 scaled
     by 1e6 and 1e-6, phonon occupations of a 3000 K bath, and |g|^2 replaced
