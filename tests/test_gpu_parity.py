@@ -221,6 +221,7 @@ def test_pair_pass_shapes_and_table_order(E, dtype):
         assert nerr(I, ref, scale) <= tol, (w, th, order)
         if base is None:
             base = I
+        assert np.array_equal(I, base), (w, th, order)
         gf, gg = E.collision_vjp(plan, dev(f, tdt), dev(nph, tdt), dev(lam, tdt), gg2=True)
         assert nerr(host(gf), rf) <= tol, (w, th, order)
         assert nerr(host(gg), rg) <= tol, (w, th, order)
