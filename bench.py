@@ -377,6 +377,10 @@ def main():
                                                     ratio_vs_shared_bath=mspv / msb,
                                                     baths="Bose-Einstein at each vector's temperature")
         log(f"fwd fp64 B=64, bath per vector: {mspv:.3f} ms ({mspv / msb:.2f}x the shared bath)")
+        msvpv, _ = timed(lambda: E.collision_vjp(plan64, F, NB, LB, want_f=True, gg2=ggb), 3, 1)
+        forms["vjp_f64_b64_bath_per_vector"] = dict(ms=msvpv, per_vector_channels_per_s=B * nch / (msvpv * 1e-3),
+                                                    ratio_vs_shared_bath=msvpv / msbv)
+        log(f"vjp fp64 B=64, bath per vector: {msvpv:.3f} ms ({msvpv / msbv:.2f}x the shared bath)")
         del F, IB, LB, ggb, NB
         # phonon side of the same processes (dN/dt of every (q, mode)), FP64
         phonon_rate(max(3, args.steps // 4))

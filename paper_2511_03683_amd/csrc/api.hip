@@ -816,9 +816,47 @@ bool enqueue_vjp_batched(ephbte_plan P, int B, const T *f, int64_t ldf, const T 
     for (int b0 = 0; b0 < B; b0 += 64) {
         const int nb = std::min(64, B - b0);
         const int gm = gg2_mode == 0 ? 0 : (b0 == 0 ? gg2_mode : 2);
-        hipLaunchKernelGGL((k_vjp_batched<T, kBatchDPW>), dim3(static_cast<unsigned>(P->n_vbtiles)),
+        hipLaunchKernelGGL((k_vjp_batched<T, kBatchDPW, 0>), dim3(static_cast<unsigned>(P->n_vbtiles)),
                            dim3(kBatchThreads), shm, s, a, f, ldf, lam, ldl, b0, nb, gf, ldgf,
-                           (const int32_t *)P->ent_chan, gg2, gm);
+                           (const int32_t *)P->ent_chan, gg2, gm, (const T *)nullptr, int64_t(0));
+    }
+    HIPC(hipGetLastError());
+    return true;
+}
+
+// The reverse pass for B >= 8 vectors with a bath per vector: per group of
+// 64 vectors their N on the table rows (as the forward pass) and one batched
+// launch.  The {hw, N} table must hold this plan's hw.
+template <typename T>
+bool enqueue_vjp_batched_pv(ephbte_plan P, int B, const T *f, int64_t ldf, const T *nph, const T *lam,
+                            int64_t ldl, T *gf, int64_t ldgf, double *gg2, int gg2_mode, hipStream_t s) {
+    if (B < P->batch_min || P->vpt == 0 || P->n_vbtiles == 0 || !pv_table_fits(P)) return false;
+    const BArgs<T> a = batch_args<T>(P, P->vbtiles, P->vsub_off, P->vpt, P->n_vbtiles);
+    const size_t shm = vjp_batch_lds_bytes(P, P->vpt);
+    const int64_t rows = P->padq ? P->qpad_n : static_cast<int64_t>(P->nq[0]) * P->nq[1] * P->nq[2];
+    const int64_t ld = rows * P->nm * 64;
+    ensure_zeroed(P, P->nvec, sizeof(T) * static_cast<size_t>(ld));
+    const int64_t tab = nqm_of(P);
+    T *nv = static_cast<T *>(P->nvec.p);
+    const int n_rows = static_cast<int>(P->padq ? P->n_used_rows : rows);
+    for (int b0 = 0; b0 < B; b0 += 64) {
+        const int nb = std::min(64, B - b0);
+        hipLaunchKernelGGL((k_pack_nvec<T>), dim3(grid_of(static_cast<int64_t>(n_rows) * P->nm * 64)), dim3(256), 0,
+                           s, nph + b0 * tab, nv, P->padq ? 1 : 0, P->qbox, P->nm, (const int32_t *)P->used_rows,
+                           n_rows, nb);
+        const int gm = gg2_mode == 0 ? 0 : (b0 == 0 ? gg2_mode : 2);
+        auto go = [&](auto rc) {
+            constexpr int RUN = decltype(rc)::value;
+            hipLaunchKernelGGL((k_vjp_batched<T, kBatchDPW, RUN>), dim3(static_cast<unsigned>(P->n_vbtiles)),
+                               dim3(kBatchThreads), shm, s, a, f, ldf, lam, ldl, b0, nb, gf, ldgf,
+                               (const int32_t *)P->ent_chan, gg2, gm, (const T *)nv, ld);
+        };
+        if (P->nm <= 1) go(std::integral_constant<int, 1>{});
+        else if (P->nm <= 2) go(std::integral_constant<int, 2>{});
+        else if (P->nm <= 3) go(std::integral_constant<int, 3>{});
+        else if (P->nm <= 4) go(std::integral_constant<int, 4>{});
+        else if (P->nm <= 6) go(std::integral_constant<int, 6>{});
+        else go(std::integral_constant<int, 8>{});
     }
     HIPC(hipGetLastError());
     return true;
@@ -2526,6 +2564,13 @@ ephbte_status ephbte_collision_vjp(ephbte_plan plan, int32_t batch, const void *
                 done = enqueue_vjp_batched<T>(plan, batch, static_cast<const T *>(f), ldf,
                                               static_cast<const T *>(gI), ldg, static_cast<T *>(gf), ldgf,
                                               gg2, gg2 ? (accumulate_gg2 ? 2 : 1) : 0, s);
+            } else if (batch >= plan->batch_min) {
+                // a bath per vector, batched: the table's hw from the first bath's pack
+                enqueue_pack<T>(plan, nph, s);
+                done = enqueue_vjp_batched_pv<T>(plan, batch, static_cast<const T *>(f), ldf,
+                                                 static_cast<const T *>(nph), static_cast<const T *>(gI), ldg,
+                                                 static_cast<T *>(gf), ldgf, gg2, gg2 ? (accumulate_gg2 ? 2 : 1) : 0,
+                                                 s);
             }
             // the kernels take unit-stride vectors of length S; strided
             // batch members are addressed one vector at a time

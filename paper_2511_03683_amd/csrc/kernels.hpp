@@ -1925,12 +1925,20 @@ template <typename T> __device__ __forceinline__ T wave_total(T v) {
 // reduced across the wave once per run of equal partners and serve every mode
 // of the run.  gg2_mode: 0 none, 1 overwrite, 2 add.  Every slot is written by
 // one lane of one launch: deterministic.
-template <typename T, int DPW>
+// RUN > 0: a bath per vector, N from nvec as in k_fwd_batched (the 64
+// vectors of this launch).  With c = G(x + hw) + G(x - hw) the coefficients
+// split into the N-free parts and c N_b; a channel's |g|^2 gradient is
+//   K [G(x + hw) p2 - G(x - hw) p1 + c sum_b N_b (P2_b - P1_b)],
+// P1_b = (lam_d - lam_p) f_d (1 - f_p), P2_b = (lam_d - lam_p) f_p (1 - f_d),
+// p1 and p2 their sums over the vectors: one more sum over the wave per
+// channel.
+template <typename T, int DPW, int RUN>
 __global__ __launch_bounds__(512) void k_vjp_batched(BArgs<T> A, const T *__restrict__ f, int64_t ldf,
                                                      const T *__restrict__ lam, int64_t ldl, int b0,
                                                      int nb, T *__restrict__ gf, int64_t ldgf,
                                                      const int32_t *__restrict__ ent_chan,
-                                                     double *__restrict__ gg2, int gg2_mode) {
+                                                     double *__restrict__ gg2, int gg2_mode,
+                                                     const T *__restrict__ nvec, int64_t nvec_ld) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int PT = A.pt;
     Pair2<T> *s_FL = reinterpret_cast<Pair2<T> *>(smem);                   // [PT][65]
@@ -1988,8 +1996,9 @@ __global__ __launch_bounds__(512) void k_vjp_batched(BArgs<T> A, const T *__rest
                     const int64_t e = e0 + lane;
                     const bool valid = e < e_hi;
                     int pl = -1 - lane;     // distinct for invalid lanes: never merged
-                    T ca = T(0), cb = T(0), ah = T(0), bh = T(0);
+                    T ca = T(0), cb = T(0), ah = T(0), bh = T(0), c1 = T(0);
                     int32_t ch = -1;
+                    int ti = 0;
                     if (valid) {
                         const uint32_t pn = A.pnu[e];
                         const T g = A.g2[e];
@@ -2002,11 +2011,21 @@ __global__ __launch_bounds__(512) void k_vjp_batched(BArgs<T> A, const T *__rest
                         const T xa = de + wn.a, xe = de - wn.a;
                         const T da = gauss_exp(xa * xa * A.mc);
                         const T dem = gauss_exp(xe * xe * A.mc);
-                        const T tt = wn.b * (da + dem);
-                        ah = tt + dem;
-                        bh = tt + da;
-                        ca = g * ah;
-                        cb = g * bh;
+                        if constexpr (RUN > 0) {
+                            // ah, bh keep the N-free parts; c1 the N coefficient
+                            ah = dem;
+                            bh = da;
+                            ca = g * dem;
+                            cb = g * da;
+                            c1 = g * (da + dem);
+                            ti = q * A.nm + static_cast<int>(pn & 7u);
+                        } else {
+                            const T tt = wn.b * (da + dem);
+                            ah = tt + dem;
+                            bh = tt + da;
+                            ca = g * ah;
+                            cb = g * bh;
+                        }
                         if (g_any && pa + pl > d) ch = ent_chan[e];
                     }
                     // sum each run of equal partners into its first lane (a run is
@@ -2024,23 +2043,76 @@ __global__ __launch_bounds__(512) void k_vjp_batched(BArgs<T> A, const T *__rest
                     const int prev = __shfl_up(pl, 1, 64);
                     const bool head = valid && (lane == 0 || prev != pl);
                     unsigned long long m = __ballot(head);
-                    while (m) {
-                        const int src = __builtin_ctzll(m);
-                        m &= m - 1;
-                        const T a = lane_bcast(ca, src);
-                        const T bq = lane_bcast(cb, src);
-                        const int pls = __builtin_amdgcn_readlane(pl, src);
-                        const Pair2<T> fl = s_FL[pls * 65 + lane];
-                        const T u = a + (bq - a) * fl.a;
-                        su += u;
-                        sl += fl.b * u;
-                        if (g_any && pa + pls > d) {
-                            const T dlm = ld[j] - fl.b;
-                            const T p1 = wave_total(dlm * fd[j] * (T(1) - fl.a));
-                            const T p2 = wave_total(dlm * fl.a * (T(1) - fd[j]));
-                            if (pl == pls && ch >= 0) {
-                                const double v = static_cast<double>(A.K * (bh * p2 - ah * p1));
-                                gg2[ch] = gg2_mode == 2 ? gg2[ch] + v : v;
+                    if constexpr (RUN > 0) {
+                        // a run of entries (one pair over its modes) ends at
+                        // the next head or the last valid lane; its N per
+                        // vector through a buffer resource (reads past the
+                        // table return 0)
+                        const int nvalid = static_cast<int>(min<int64_t>(64, e_hi - e0));
+                        const __amdgpu_buffer_rsrc_t nvr = __builtin_amdgcn_make_buffer_rsrc(
+                            const_cast<T *>(nvec), 0, static_cast<int>(nvec_ld * sizeof(T)), kBufferDword3);
+                        const int lane_off = lane * static_cast<int>(sizeof(T));
+                        while (m) {
+                            const int src = __builtin_ctzll(m);
+                            m &= m - 1;
+                            const int end = m ? __builtin_ctzll(m) : nvalid;
+                            T nv[RUN];
+#pragma unroll
+                            for (int r = 0; r < RUN; ++r) {
+                                const int jj = min(src + r, end - 1);
+                                const int row = __builtin_amdgcn_readlane(ti, jj) * 64 * static_cast<int>(sizeof(T));
+                                nv[r] = buffer_load_value<T>(nvr, lane_off, row);
+                            }
+                            T nsum = T(0);
+#pragma unroll
+                            for (int r = 0; r < RUN; ++r) {
+                                const int jj = min(src + r, end - 1);
+                                const T w = src + r < end ? lane_bcast(c1, jj) : T(0);
+                                nsum += w * nv[r];
+                            }
+                            const T a = lane_bcast(ca, src) + nsum;
+                            const T bq = lane_bcast(cb, src) + nsum;
+                            const int pls = __builtin_amdgcn_readlane(pl, src);
+                            const Pair2<T> fl = s_FL[pls * 65 + lane];
+                            const T u = a + (bq - a) * fl.a;
+                            su += u;
+                            sl += fl.b * u;
+                            if (g_any && pa + pls > d) {
+                                const T dlm = ld[j] - fl.b;
+                                const T q1 = dlm * fd[j] * (T(1) - fl.a);
+                                const T q2 = dlm * fl.a * (T(1) - fd[j]);
+                                const T p1 = wave_total(q1);
+                                const T p2 = wave_total(q2);
+#pragma unroll
+                                for (int r = 0; r < RUN; ++r) {
+                                    if (src + r >= end) break;
+                                    const T rn = wave_total(nv[r] * (q2 - q1));
+                                    if (lane == src + r && ch >= 0) {
+                                        const double v = static_cast<double>(A.K * (bh * p2 - ah * p1 + (ah + bh) * rn));
+                                        gg2[ch] = gg2_mode == 2 ? gg2[ch] + v : v;
+                                    }
+                                }
+                            }
+                        }
+                    } else {
+                        while (m) {
+                            const int src = __builtin_ctzll(m);
+                            m &= m - 1;
+                            const T a = lane_bcast(ca, src);
+                            const T bq = lane_bcast(cb, src);
+                            const int pls = __builtin_amdgcn_readlane(pl, src);
+                            const Pair2<T> fl = s_FL[pls * 65 + lane];
+                            const T u = a + (bq - a) * fl.a;
+                            su += u;
+                            sl += fl.b * u;
+                            if (g_any && pa + pls > d) {
+                                const T dlm = ld[j] - fl.b;
+                                const T p1 = wave_total(dlm * fd[j] * (T(1) - fl.a));
+                                const T p2 = wave_total(dlm * fl.a * (T(1) - fd[j]));
+                                if (pl == pls && ch >= 0) {
+                                    const double v = static_cast<double>(A.K * (bh * p2 - ah * p1));
+                                    gg2[ch] = gg2_mode == 2 ? gg2[ch] + v : v;
+                                }
                             }
                         }
                     }

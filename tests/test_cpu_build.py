@@ -334,9 +334,10 @@ def test_elastic_mechanism(driver, tmp_path):
 
 @pytest.mark.parametrize("B,dtype", [(3, "f64"), (9, "f64"), (70, "f64"), (9, "f32")])
 def test_bath_per_vector(driver, tmp_path, B, dtype):
-    """nph [B, Nq, n_modes]: each vector against the oracle with its own bath;
-    B >= 8 runs the batched pass with the baths in groups of 64 vectors (70:
-    two groups), under a random fill of fresh memory."""
+    """nph [B, Nq, n_modes]: each vector against the oracle with its own bath,
+    forward and reverse; B >= 8 runs the batched passes with the baths in
+    groups of 64 vectors (70: two groups), under random fills of fresh
+    memory."""
     s = synth.multiband_system()
     temps = [150.0 + 37.0 * b for b in range(B)]
     F = np.stack([synth.random_occupations(s, 40 + b) for b in range(B)])
@@ -356,9 +357,7 @@ def test_bath_per_vector(driver, tmp_path, B, dtype):
         return
     for b in range(B):
         assert nerr(got[b], oracle.collision(s, F[b], NPH[b])) <= TOL64, b
-    if B > 9:
-        return
-    _run(driver, tmp_path, "vjp")
+    _run(driver, tmp_path, "vjp", fill="random:%d" % (B + 1))
     gf = _out(tmp_path, "gf", (B, s.n_states))
     rg = 0
     for b in range(B):
