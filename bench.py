@@ -533,6 +533,25 @@ def main():
             log(f"grouped 16 systems {dname}: {msg:.3f} ms, {gsys.n_channels / (msg * 1e-3):.3e} ch/s "
                 f"({time.time() - t0:.1f}s incl. generation)")
             gplan.close()
+        # phonon-phonon scattering (a Bose plan): the modes of a 10^3 q grid,
+        # every pair and third branch a channel
+        t0 = time.time()
+        psys = synth.ph_ph_system(n=6 if args.quick else 10)
+        pplan = E.build_channels(psys, dtype="f64", device=0, statistics="bose")
+        pn = tens(synth.bose_occupations(psys, 300.0, seed=5), torch.float64)
+        pN = tens(synth.bose_einstein(psys.hw, 300.0), torch.float64)
+        pI = torch.empty_like(pn)
+        msph, _ = timed(lambda: E.collision_integral(pplan, pn, pN, out=pI), args.steps, args.warmup)
+        pl = tens(rng.normal(size=psys.n_states), torch.float64)
+        pgg = torch.zeros(psys.n_channels, dtype=torch.float64, device=dev)
+        msphv, _ = timed(lambda: E.collision_vjp(pplan, pn, pN, pl, want_f=True, gg2=pgg), args.steps, 1)
+        forms["phonon_phonon_f64"] = dict(ms=msph, reverse_ms=msphv, modes=psys.n_states,
+                                          channels=psys.n_channels,
+                                          channels_per_s=psys.n_channels / (msph * 1e-3),
+                                          plan_layout=LAYOUT_NAMES[E.plan_info(pplan)["layout"]])
+        log(f"phonon-phonon fp64 ({psys.n_states} modes, {psys.n_channels} channels): forward {msph:.3f} ms, "
+            f"reverse {msphv:.3f} ms ({time.time() - t0:.1f}s incl. generation)")
+        pplan.close()
 
     cpu = None
     if not args.no_cpu:
