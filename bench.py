@@ -321,6 +321,16 @@ def main():
             forms["fwd_f64_b1_pairs_polyexp"] = dict(ms=msp2, channels_per_s=nch / (msp2 * 1e-3),
                                                      algorithmic_GBps=bpc * nch / (msp2 * 1e-3) / 1e9)
             log(f"fwd fp64 pair records, polynomial exponential: {msp2:.3f} ms")
+            # the pair passes with the records of each tile in destination
+            # order (the default sorts them by q)
+            E.set_tuning(plan64, pair_order=2)
+            msd, _ = timed(fwd64, args.steps, args.warmup)
+            msdv = vjp_b1(max(3, args.steps // 4))
+            E.set_tuning(plan64, pair_order=1)
+            forms["fwd_f64_b1_pairs_destination_order"] = dict(
+                ms=msd, reverse_ms=msdv, channels_per_s=nch / (msd * 1e-3),
+                algorithmic_GBps=bpc * nch / (msd * 1e-3) / 1e9)
+            log(f"fwd / vjp fp64 pair records in destination order: {msd:.3f} / {msdv:.3f} ms")
             E.set_tuning(plan64, layout=2)
             mse, _ = timed(fwd64, args.steps, args.warmup)
             forms["fwd_f64_b1_entries"] = dict(ms=mse, channels_per_s=nch / (mse * 1e-3),

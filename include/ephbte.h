@@ -140,6 +140,12 @@ typedef struct {
                                   4096 FP32)                                     */
     int32_t pair_threads;      /* threads per workgroup of the pair-record forward
                                   pass: 256, 512, 768 or 1024 (default)         */
+    int32_t pair_order;        /* records of the pair-record passes' LDS tiles:
+                                  1 = sorted by q = k_p - k_d (default: the lanes
+                                  of a wave share rows of the {hw, N} table, and
+                                  both sides of a pair are fixed-point sums),
+                                  2 = by destination (the destination's side
+                                  summed in registers)                         */
 } ephbte_tuning;
 
 /* Build options.  Channel selection (paper: scattering-channel paragraph

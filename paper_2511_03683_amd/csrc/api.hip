@@ -141,6 +141,7 @@ struct ephbte_plan_s {
     int sym_lds_states = 0;
     int pr_lds_states = 0;      // partner window of the pair-record passes
     int pr_threads = 1024;      // threads per workgroup of the pair forward pass
+    int pair_order = 1;         // records of the LDS tiles: 1 q order, 2 destination order
     bool sym_ok = false;                    // the single-copy window fits the LDS of a workgroup
     int layout = 2;                         // B = 1 forward: 1 duplicated rows, 2 single copy,
                                             // 3 single copy over pair records
@@ -153,6 +154,10 @@ struct ephbte_plan_s {
     int32_t *pr_ch0 = nullptr;             // first channel of a record whose slots are consecutive, else -1
     int64_t pr_np = 0, pr_ld = 0;
     std::vector<int64_t> pr_rowptr;        // host: pair rows, for re-chunking
+    std::vector<uint32_t> pr_partner_host; // host: partner of each record, destination order
+    std::vector<uint32_t> pr_perm;         // host: device position -> record in destination
+                                           // order (empty: the same order)
+    std::vector<uint32_t> st_key;          // host: packed box (padded table) or grid coordinates
     int64_t *pr_chunk_beg = nullptr, *pr_chunk_end = nullptr;
     int32_t *pr_chunk_dest = nullptr, *pr_dest_chunk = nullptr;
     TileRec *pr_tiles = nullptr;
@@ -357,6 +362,85 @@ unsigned grid_of(int64_t n) {
     return static_cast<unsigned>(std::max<int64_t>(std::min<int64_t>((n + 255) / 256, 4096), 1));
 }
 
+// Puts the device's pair records in the order of order_pair_tiles (q order
+// inside the LDS tiles when qord, else destination order) and replaces the
+// chunk table and tiles by the renumbered ones.  The stream words are
+// uploaded; the mode slots (|g|^2, channel) and first channels are gathered
+// on the device from their current order.
+void order_pair_records(ephbte_plan P, ChunkTable &pc, std::vector<Tile> &tp, bool qord) {
+    const int64_t np = P->pr_np;
+    RowKey rk;
+    rk.key = P->st_key.data();
+    rk.padq = P->padq;
+    rk.qoff = P->qoff;
+    for (int a = 0; a < 3; ++a) rk.n[a] = P->nq[a];
+    PairOrder o;
+    if (qord) {
+        o = order_pair_tiles(pc, tp, P->pr_partner_host, rk, kPairChunksPerTile, 65536);
+    } else {
+        // destination order: the tiles and chunks as built
+        o.chunks = pc;
+        o.tiles = tp;
+        o.perm.resize(static_cast<size_t>(np));
+        for (int64_t x = 0; x < np; ++x) o.perm[x] = static_cast<uint32_t>(x);
+        o.word = P->pr_partner_host;
+    }
+    // device gather indices: idx[i] = current device position of the record
+    // that goes to position i
+    std::vector<uint32_t> idx(static_cast<size_t>(np));
+    bool same = true;
+    if (P->pr_perm.empty()) {
+        idx = o.perm;
+    } else {
+        std::vector<uint32_t> inv(static_cast<size_t>(np));
+        for (int64_t x = 0; x < np; ++x) inv[P->pr_perm[x]] = static_cast<uint32_t>(x);
+        for (int64_t x = 0; x < np; ++x) idx[x] = inv[o.perm[x]];
+    }
+    for (int64_t x = 0; x < np && same; ++x) same = idx[x] == static_cast<uint32_t>(x);
+    if (!same) {
+        const size_t ld = static_cast<size_t>(P->pr_ld), nm = static_cast<size_t>(P->nm);
+        const size_t es = P->dtype == EPHBTE_F64 ? 8 : 4;
+        uint32_t *d_idx = nullptr;
+        void *g_new = nullptr;
+        int32_t *c_new = nullptr, *c0_new = nullptr;
+        size_t dummy = 0;
+        dalloc(d_idx, sizeof(uint32_t) * static_cast<size_t>(np), &dummy);
+        dalloc(g_new, es * ld * nm, &dummy);
+        dalloc(c_new, sizeof(int32_t) * ld * nm, &dummy);
+        dalloc(c0_new, sizeof(int32_t) * ld, &dummy);
+        HIPC(hipMemcpy(d_idx, idx.data(), sizeof(uint32_t) * static_cast<size_t>(np), hipMemcpyHostToDevice));
+        const dim3 grid(grid_of(static_cast<int64_t>(ld))), block(256);
+        if (es == 8)
+            hipLaunchKernelGGL((k_permute_pairs<double>), grid, block, 0, nullptr, (const uint32_t *)d_idx, np,
+                               static_cast<int64_t>(ld), P->nm, (const double *)P->pr_g2, (double *)g_new,
+                               (const int32_t *)P->pr_chan, c_new, (const int32_t *)P->pr_ch0, c0_new);
+        else
+            hipLaunchKernelGGL((k_permute_pairs<float>), grid, block, 0, nullptr, (const uint32_t *)d_idx, np,
+                               static_cast<int64_t>(ld), P->nm, (const float *)P->pr_g2, (float *)g_new,
+                               (const int32_t *)P->pr_chan, c_new, (const int32_t *)P->pr_ch0, c0_new);
+        HIPC(hipGetLastError());
+        HIPC(hipDeviceSynchronize());
+        dfree(reinterpret_cast<void *&>(d_idx));
+        dfree(P->pr_g2);
+        dfree(reinterpret_cast<void *&>(P->pr_chan));
+        dfree(reinterpret_cast<void *&>(P->pr_ch0));
+        P->pr_g2 = g_new;
+        P->pr_chan = c_new;
+        P->pr_ch0 = c0_new;
+    }
+    {
+        std::vector<uint32_t> w(static_cast<size_t>(P->pr_ld), 0u);
+        std::copy(o.word.begin(), o.word.end(), w.begin());
+        HIPC(hipMemcpy(P->pr_partner, w.data(), sizeof(uint32_t) * w.size(), hipMemcpyHostToDevice));
+    }
+    bool ident = true;
+    for (int64_t x = 0; x < np && ident; ++x) ident = o.perm[x] == static_cast<uint32_t>(x);
+    if (ident) P->pr_perm.clear();
+    else P->pr_perm = std::move(o.perm);
+    pc = std::move(o.chunks);
+    tp = std::move(o.tiles);
+}
+
 void upload_chunks(ephbte_plan P, int64_t chunk_entries) {
     ChunkTable t = make_chunks(P->row_ptr, chunk_entries);
     free_graphs(P);
@@ -439,7 +523,17 @@ void upload_chunks(ephbte_plan P, int64_t chunk_entries) {
     ChunkTable pc = make_chunks_seg(pbeg, pend, chunk_entries);
     const int64_t target_p = P->tile_entries > 0 ? P->tile_entries / (2 * static_cast<int64_t>(P->nm)) + 1
                                                  : P->pr_np / (4 * static_cast<int64_t>(P->n_cu)) + 1;
-    std::vector<Tile> tp = make_tiles(pc, P->row_ptr, P->pmin_up, P->pmax_up, P->pr_lds_states, target_p);
+    // in q order, a tile's window stages its destinations too
+    const bool qord = P->pair_order == 1 && P->pr_np < (int64_t(1) << 32);
+    std::vector<int32_t> wmin;
+    if (qord) {
+        wmin = P->pmin_up;
+        for (int64_t d = 0; d < P->S; ++d)
+            if (P->pmax_up[d] >= P->pmin_up[d]) wmin[d] = static_cast<int32_t>(d);
+    }
+    std::vector<Tile> tp = make_tiles(pc, P->row_ptr, qord ? wmin : P->pmin_up, P->pmax_up, P->pr_lds_states,
+                                      target_p);
+    order_pair_records(P, pc, tp, qord);
     dfree(reinterpret_cast<void *&>(P->pr_chunk_beg));
     dfree(reinterpret_cast<void *&>(P->pr_chunk_end));
     dfree(reinterpret_cast<void *&>(P->pr_chunk_dest));
@@ -1304,6 +1398,8 @@ template <typename T> void upload_layout(ephbte_plan P, const ephbte_problem *pr
             }
         }
         HIPC(hipMemcpy(P->st, st.data(), sizeof(StateRec<T>) * S, hipMemcpyHostToDevice));
+        P->st_key.resize(static_cast<size_t>(S));
+        for (int64_t s = 0; s < S; ++s) P->st_key[s] = P->padq ? st[s].kqp : st[s].kq;
         if (P->padq) {
             // box rows the entries reference (both orientations of every
             // channel, and q = 0): the only rows a call packs
@@ -1382,6 +1478,8 @@ template <typename T> void upload_pair_rows(ephbte_plan P, const ephbte_problem 
         HIPC(hipMemcpy(P->pr_ch0, c0.data(), sizeof(int32_t) * ld, hipMemcpyHostToDevice));
     }
     P->pr_rowptr = std::move(R.row_ptr);
+    P->pr_partner_host = std::move(R.partner);
+    P->pr_perm.clear();
 }
 
 // The phonon pass's layout (pair records bucketed by {q, -q}, see
@@ -2870,6 +2968,8 @@ ephbte_status ephbte_set_tuning(ephbte_plan plan, const ephbte_tuning *tuning) {
         const int pth = tuning->pair_threads;
         if (pth != 0 && pth != 256 && pth != 512 && pth != 768 && pth != 1024)
             return fail(EPHBTE_INVALID_ARGUMENT, "pair_threads must be 0 (keep), 256, 512, 768 or 1024");
+        if (tuning->pair_order < 0 || tuning->pair_order > 2)
+            return fail(EPHBTE_INVALID_ARGUMENT, "pair_order must be 0 (keep), 1 or 2");
         if (tuning->tile_entries < -1)
             return fail(EPHBTE_INVALID_ARGUMENT, "tile_entries must be -1 (default), 0 (keep) or > 0");
         if (tuning->fp64_exp < 0 || tuning->fp64_exp > 2)
@@ -2891,6 +2991,7 @@ ephbte_status ephbte_set_tuning(ephbte_plan plan, const ephbte_tuning *tuning) {
         if (tuning->table_order) plan->tab_mm = tuning->table_order == 2;
         if (pw) plan->pr_lds_states = pw;
         if (pth) plan->pr_threads = pth;
+        if (tuning->pair_order) plan->pair_order = tuning->pair_order;
         upload_chunks(plan, ce);
         if (pt != 0) upload_btiles(plan, pt);
         free_graphs(plan);

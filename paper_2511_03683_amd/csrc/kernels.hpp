@@ -873,6 +873,29 @@ __device__ __forceinline__ T pair_gauss(const TiledArgs<T> &A, T x2, const doubl
     else return __builtin_amdgcn_exp2f(x2 * A.mc);
 }
 
+// The pair's sums over its modes of a = |g|^2 (t + G(x - hw)) and
+// b = |g|^2 (t + G(x + hw)), t = N (G(x + hw) + G(x - hw)), x = de; the
+// occupation factors are the pair's.  Slots past nm, and every slot of a
+// masked lane (v false), count as empty.
+template <typename T, int NM, bool TAB>
+__device__ __forceinline__ void pair_mode_sums(const TiledArgs<T> &A, T de, const Pair2<T> (&w)[NM],
+                                               const T (&g)[NM], bool v, const double *s_tab, T &sa, T &sb) {
+    const int nm = A.nm;
+    sa = T(0);
+    sb = T(0);
+#pragma unroll
+    for (int m = 0; m < NM; ++m) {
+        const T gm = v && m < nm ? g[m] : T(0);
+        const T N = keep_or_zero(w[m].b, gm != T(0));
+        const T xa = de + w[m].a, xe = de - w[m].a;
+        const T da = pair_gauss<T, TAB>(A, xa * xa, s_tab);
+        const T dem = pair_gauss<T, TAB>(A, xe * xe, s_tab);
+        const T t = N * (da + dem);
+        sa = fma(gm, t + dem, sa);
+        sb = fma(gm, t + da, sb);
+    }
+}
+
 template <typename T, bool LDS, bool PADQ, int NM, bool TAB>
 __device__ __forceinline__ void pair_chunk(const TiledArgs<T> &A, const T *__restrict__ fb,
                                            const Pair2<T> *s_ef, const uint32_t *s_kq, int p_lo,
@@ -945,22 +968,9 @@ __device__ __forceinline__ void pair_chunk(const TiledArgs<T> &A, const T *__res
 #pragma unroll
         for (int m = 0; m < NM; ++m) g_next[m] = gb[min(m, nm - 1) * A.pld + r + 64 + lane];
         __builtin_amdgcn_sched_barrier(0);
-        const T de = sd.eps - ep;
         const T ofp = T(1) - fp;
-        // the pair's sums over its modes of a = |g|^2 (t + G(x - hw)) and
-        // b = |g|^2 (t + G(x + hw)); the occupation factors are the pair's
-        T sa = T(0), sb = T(0);
-#pragma unroll
-        for (int m = 0; m < NM; ++m) {
-            const T gm = v && m < nm ? g[m] : T(0);
-            const T N = keep_or_zero(w[m].b, gm != T(0));
-            const T xa = de + w[m].a, xe = de - w[m].a;
-            const T da = pair_gauss<T, TAB>(A, xa * xa, s_tab);
-            const T dem = pair_gauss<T, TAB>(A, xe * xe, s_tab);
-            const T t = N * (da + dem);
-            sa = fma(gm, t + dem, sa);
-            sb = fma(gm, t + da, sb);
-        }
+        T sa, sb;
+        pair_mode_sums<T, NM, TAB>(A, sd.eps - ep, w, g, v, s_tab, sa, sb);
         const T ta = sa * ofp, tb = sb * fp;
         acc_a += ta;
         acc_b += tb;
@@ -982,6 +992,67 @@ __device__ __forceinline__ void pair_chunk(const TiledArgs<T> &A, const T *__res
     if (lane == 0) {
         part[2 * c] = acc_a;
         part[2 * c + 1] = acc_b;
+    }
+}
+
+// The same pass over a q-ordered tile.  Its records are sorted by the table
+// row of q = k_p - k_d (then destination, partner), so the lanes of a batch
+// read a few rows of the {hw, N} table instead of one each.  A record's word
+// holds the window offsets of its partner (high 16 bits) and destination (low
+// 16 bits); the window stages both.  The destination's side of the pair, -y,
+// goes to the same fixed-point accumulator as the partner's, +y, so the
+// chunk's row partials are zero.
+template <typename T, bool PADQ, int NM, bool TAB>
+__device__ __forceinline__ void pair_chunk_q(const TiledArgs<T> &A, const Pair2<T> *s_ef, const uint32_t *s_kq,
+                                             const double *s_tab, unsigned long long *s_j, T scale, int64_t c,
+                                             T *__restrict__ part) {
+    const int lane = threadIdx.x & 63;
+    const int nm = A.nm;
+    const int64_t beg = A.chunk_beg[c];
+    const int len = static_cast<int>(A.chunk_end[c] - beg);
+    const uint32_t *__restrict__ pb = A.pnu + beg;
+    const T *__restrict__ gb = A.g2 + beg;
+    // stream one batch ahead, two register sets (see pair_chunk)
+    uint32_t pn0 = pb[lane], pn1 = 0;
+    T g0[NM], g1[NM];
+#pragma unroll
+    for (int m = 0; m < NM; ++m) g0[m] = gb[min(m, nm - 1) * A.pld + lane];
+    auto batch = [&](int r, const uint32_t pn, const T (&g)[NM], uint32_t &pn_next, T (&g_next)[NM]) {
+        const bool v = r + lane < len;
+        // a masked lane takes window slot 0 as both states (q = 0) and adds nothing
+        const int wd = v ? static_cast<int>(pn & 0xffffu) : 0;
+        const int wp = v ? static_cast<int>(pn >> 16) : 0;
+        const Pair2<T> efd = s_ef[wd], efp = s_ef[wp];
+        const uint32_t kd = s_kq[wd], kp = s_kq[wp];
+        const int q = PADQ ? static_cast<int>(kp - kd) + A.qoff : q_linear(kd, kp, A.nq0, A.nq1, A.nq2);
+        const Pair2<T> *__restrict__ wq = A.hwN + static_cast<int64_t>(q) * A.tq;
+        Pair2<T> w[NM];
+#pragma unroll
+        for (int m = 0; m < NM; ++m) w[m] = wq[min(m, nm - 1) * A.tm];
+        __builtin_amdgcn_sched_barrier(0);
+        pn_next = pb[r + 64 + lane];
+#pragma unroll
+        for (int m = 0; m < NM; ++m) g_next[m] = gb[min(m, nm - 1) * A.pld + r + 64 + lane];
+        __builtin_amdgcn_sched_barrier(0);
+        T sa, sb;
+        pair_mode_sums<T, NM, TAB>(A, efd.a - efp.a, w, g, v, s_tab, sa, sb);
+        const T fd = efd.b, fp = efp.b;
+        const T ta = sa * (T(1) - fp), tb = sb * fp;
+        const T y = fma(fd, ta, -(T(1) - fd) * tb);
+        if (v) {
+            const unsigned long long fx = to_fixed(__builtin_rint(y * scale));
+            atomicAdd(s_j + wp, fx);
+            atomicAdd(s_j + wd, 0ull - fx);
+        }
+    };
+    for (int r = 0; r < len; r += 128) {
+        batch(r, pn0, g0, pn1, g1);
+        if (r + 64 >= len) break;
+        batch(r + 64, pn1, g1, pn0, g0);
+    }
+    if (lane == 0) {
+        part[2 * c] = T(0);
+        part[2 * c + 1] = T(0);
     }
 }
 
@@ -1013,7 +1084,9 @@ __global__ __launch_bounds__(1024) void k_fwd_pairs(TiledArgs<T> A, const T *__r
     const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
     const int nw = static_cast<int>(blockDim.x >> 6);
     for (int64_t c = t.c0 + wave; c < t.c1; c += nw) {
-        if (t.lds)
+        if (t.lds == 2)
+            pair_chunk_q<T, PADQ, NM, TAB>(A, s_ef, s_kq, s_tab, s_j, scale, c, part);
+        else if (t.lds)
             pair_chunk<T, true, PADQ, NM, TAB>(A, f, s_ef, s_kq, t.p_lo, s_tab, s_j, scale, c, part);
         else
             pair_chunk<T, false, PADQ, NM, TAB>(A, f, s_ef, s_kq, t.p_lo, s_tab, s_j, scale, c, part);
@@ -1057,6 +1130,61 @@ __device__ __forceinline__ double vjp_scale(const unsigned long long *nmax_bits,
 // (a lane holds at most 128 registers; the pass needs about 100 with the
 // modes summed per pair)
 constexpr int kVjpPairThreads = 1024;
+
+// chunks of a q-ordered pair tile: one for each wave of a 1024-thread workgroup
+constexpr int kPairChunksPerTile = 16;
+
+// The pair's sums over its modes of |g|^2 ah and |g|^2 bh, and per mode
+// dL/d|g|^2 = kb bh - ka ah (gv); empty slots as in pair_mode_sums.
+template <typename T, int NM, bool TAB>
+__device__ __forceinline__ void vjp_mode_sums(const TiledArgs<T> &A, T x, T kb, T ka, const Pair2<T> (&w)[NM],
+                                              const T (&g)[NM], bool v, const double *s_tab, T &sa, T &sb,
+                                              double (&gv)[NM]) {
+    const int nm = A.nm;
+    sa = T(0);
+    sb = T(0);
+#pragma unroll
+    for (int m = 0; m < NM; ++m) {
+        const Pair2<T> wm = w[m];
+        const T gm = v && m < nm ? g[m] : T(0);
+        const T N = keep_or_zero(wm.b, gm != T(0));
+        const T xa = x + wm.a, xe = x - wm.a;
+        const T da = pair_gauss<T, TAB>(A, xa * xa, s_tab);
+        const T dem = pair_gauss<T, TAB>(A, xe * xe, s_tab);
+        const T t = N * (da + dem);
+        const T ah = t + dem, bh = t + da;
+        sa = fma(gm, ah, sa);
+        sb = fma(gm, bh, sb);
+        gv[m] = static_cast<double>(fma(kb, bh, -ka * ah));
+    }
+}
+
+// Writes (gg2_mode 1) or adds (2) the record's dL/d|g|^2 to its channels:
+// c0 >= 0 when they are the consecutive channels c0, c0 + 1, ..; else each
+// slot's channel is cb[m pld] (-1: no channel)
+template <int NM>
+__device__ __forceinline__ void write_gg2(double *__restrict__ gg2, int gg2_mode, int32_t c0,
+                                          const int32_t *__restrict__ cb, int64_t pld, int nm,
+                                          const double (&gv)[NM]) {
+    if (c0 >= 0 && NM == nm && (NM & 1) == 0 && (c0 & 1) == 0) {
+        // 16-byte aligned: the lane writes them as whole pairs
+        double2 *dst = reinterpret_cast<double2 *>(gg2 + c0);
+#pragma unroll
+        for (int k = 0; k < NM / 2; ++k) {
+            double2 o = gg2_mode == 2 ? dst[k] : make_double2(0.0, 0.0);
+            o.x += gv[2 * k];
+            o.y += gv[2 * k + 1];
+            dst[k] = o;
+        }
+    } else {
+#pragma unroll
+        for (int m = 0; m < NM; ++m) {
+            if (m >= nm) break;
+            const int32_t ch = c0 >= 0 ? c0 + m : cb[m * pld];
+            if (ch >= 0) gg2[ch] = gg2_mode == 2 ? gg2[ch] + gv[m] : gv[m];
+        }
+    }
+}
 
 template <typename T, bool LDS, bool PADQ, int NM, bool TAB>
 __device__ __forceinline__ void vjp_pair_chunk(const TiledArgs<T> &A, const T *__restrict__ fb,
@@ -1125,46 +1253,14 @@ __device__ __forceinline__ void vjp_pair_chunk(const TiledArgs<T> &A, const T *_
         // per mode dL/d|g|^2 = kb bh - ka ah; the pair's sums of |g|^2 ah and
         // |g|^2 bh serve both occupation sides
         const T kb = A.K * dl * cfd * fp, ka = A.K * dl * fd * ofp;
-        T sa = T(0), sb = T(0);
+        T sa, sb;
         double gv[NM];
-#pragma unroll
-        for (int m = 0; m < NM; ++m) {
-            const Pair2<T> wm = w[m];
-            const T gm = v && m < nm ? g[m] : T(0);
-            const T N = keep_or_zero(wm.b, gm != T(0));
-            const T xa = x + wm.a, xe = x - wm.a;
-            const T da = pair_gauss<T, TAB>(A, xa * xa, s_tab);
-            const T dem = pair_gauss<T, TAB>(A, xe * xe, s_tab);
-            const T t = N * (da + dem);
-            const T ah = t + dem, bh = t + da;
-            sa = fma(gm, ah, sa);
-            sb = fma(gm, bh, sb);
-            gv[m] = static_cast<double>(fma(kb, bh, -ka * ah));
-        }
+        vjp_mode_sums<T, NM, TAB>(A, x, kb, ka, w, g, v, s_tab, sa, sb, gv);
         acc += dl * fma(sa, ofp, sb * fp);
         const T y = dl * fma(sb, cfd, sa * fd);
-        if (gg2_mode && v) {
-            if (c0 >= 0 && NM == nm && (NM & 1) == 0 && (c0 & 1) == 0) {
-                // the record's channels are consecutive in the caller's order
-                // and 16-byte aligned: the lane writes them as whole pairs, and
-                // consecutive records fill consecutive memory
-                double2 *dst = reinterpret_cast<double2 *>(gg2 + c0);
-#pragma unroll
-                for (int k = 0; k < NM / 2; ++k) {
-                    double2 o = gg2_mode == 2 ? dst[k] : make_double2(0.0, 0.0);
-                    o.x += gv[2 * k];
-                    o.y += gv[2 * k + 1];
-                    dst[k] = o;
-                }
-            } else {
-#pragma unroll
-                for (int m = 0; m < NM; ++m) {
-                    if (m >= nm) break;
-                    const int32_t ch = c0 >= 0 ? c0 + m : cb[m * A.pld + r + lane];
-                    if (ch >= 0) gg2[ch] = gg2_mode == 2 ? gg2[ch] + gv[m] : gv[m];
-                }
-            }
-        }
+        // consecutive records of a row write consecutive memory when their
+        // channels are consecutive in the caller's order
+        if (gg2_mode && v) write_gg2<NM>(gg2, gg2_mode, c0, cb + r + lane, A.pld, nm, gv);
         if (want_f && v) {
             const unsigned long long fx = to_fixed(__builtin_rint(y * scale));
             if (LDS) atomicAdd(s_j + pl, fx);
@@ -1175,6 +1271,63 @@ __device__ __forceinline__ void vjp_pair_chunk(const TiledArgs<T> &A, const T *_
     if (!want_f) return;
     acc = wave_sum(acc);
     if (lane == 0) part[c] = acc;
+}
+
+// The reverse pass over a q-ordered tile (see pair_chunk_q): both sides of a
+// pair go to the fixed-point accumulator, -K dl (ah (1 - f_p) + bh f_p) |g|^2
+// summed over modes to the destination and the partner's side as in
+// vjp_pair_chunk; the chunk's row partial is zero.
+template <typename T, bool PADQ, int NM, bool TAB>
+__device__ __forceinline__ void vjp_pair_chunk_q(const TiledArgs<T> &A, const Pair2<T> *s_ef,
+                                                 const uint32_t *s_kq, const T *s_l, const double *s_tab,
+                                                 unsigned long long *s_j, T scale, int64_t c, T *__restrict__ part,
+                                                 bool want_f, const int32_t *__restrict__ chan,
+                                                 const int32_t *__restrict__ chan0, double *__restrict__ gg2,
+                                                 int gg2_mode) {
+    const int lane = threadIdx.x & 63;
+    const int nm = A.nm;
+    const int64_t beg = A.chunk_beg[c];
+    const int len = static_cast<int>(A.chunk_end[c] - beg);
+    const uint32_t *__restrict__ pb = A.pnu + beg;
+    const T *__restrict__ gb = A.g2 + beg;
+    const int32_t *__restrict__ cb = chan + beg;
+    const int32_t *__restrict__ cb0 = chan0 + beg;
+    uint32_t pn = pb[lane];
+    for (int r = 0; r < len; r += 64) {
+        const bool v = r + lane < len;
+        const uint32_t pn_next = pb[r + 64 + lane];
+        T g[NM];
+#pragma unroll
+        for (int m = 0; m < NM; ++m) g[m] = gb[min(m, nm - 1) * A.pld + r + lane];
+        const int32_t c0 = gg2_mode ? cb0[r + lane] : -1;
+        // a masked lane takes window slot 0 as both states and adds nothing
+        const int wd = v ? static_cast<int>(pn & 0xffffu) : 0;
+        const int wp = v ? static_cast<int>(pn >> 16) : 0;
+        const Pair2<T> efd = s_ef[wd], efp = s_ef[wp];
+        const T ld = s_l[wd], lp = s_l[wp];
+        const uint32_t kd = s_kq[wd], kp = s_kq[wp];
+        const int q = PADQ ? static_cast<int>(kp - kd) + A.qoff : q_linear(kd, kp, A.nq0, A.nq1, A.nq2);
+        const Pair2<T> *__restrict__ wq = A.hwN + static_cast<int64_t>(q) * A.tq;
+        Pair2<T> w[NM];
+#pragma unroll
+        for (int m = 0; m < NM; ++m) w[m] = wq[min(m, nm - 1) * A.tm];
+        __builtin_amdgcn_sched_barrier(0);
+        const T fd = efd.b, cfd = T(1) - fd, fp = efp.b, ofp = T(1) - fp;
+        const T dl = ld - lp;
+        const T kb = A.K * dl * cfd * fp, ka = A.K * dl * fd * ofp;
+        T sa, sb;
+        double gv[NM];
+        vjp_mode_sums<T, NM, TAB>(A, efd.a - efp.a, kb, ka, w, g, v, s_tab, sa, sb, gv);
+        if (gg2_mode && v) write_gg2<NM>(gg2, gg2_mode, c0, cb + r + lane, A.pld, nm, gv);
+        if (want_f && v) {
+            const T rd = dl * fma(sa, ofp, sb * fp);
+            const T y = dl * fma(sb, cfd, sa * fd);
+            atomicAdd(s_j + wp, to_fixed(__builtin_rint(y * scale)));
+            atomicAdd(s_j + wd, to_fixed(__builtin_rint(-rd * scale)));
+        }
+        pn = pn_next;
+    }
+    if (want_f && lane == 0) part[c] = T(0);
 }
 
 template <typename T, bool PADQ, int NM, bool TAB>
@@ -1211,7 +1364,10 @@ __global__ __launch_bounds__(kVjpPairThreads) void k_vjp_pairs(TiledArgs<T> A, c
     const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
     const int nw = static_cast<int>(blockDim.x >> 6);
     for (int64_t c = t.c0 + wave; c < t.c1; c += nw) {
-        if (t.lds)
+        if (t.lds == 2)
+            vjp_pair_chunk_q<T, PADQ, NM, TAB>(A, s_ef, s_kq, s_l, s_tab, s_j, scale, c, part, want_f != 0, chan,
+                                               chan0, gg2, gg2_mode);
+        else if (t.lds)
             vjp_pair_chunk<T, true, PADQ, NM, TAB>(A, f, lam, s_ef, s_kq, s_l, t.p_lo, s_tab, s_j, scale, c, part,
                                                    want_f != 0, chan, chan0, gg2, gg2_mode);
         else
@@ -2514,6 +2670,27 @@ __global__ __launch_bounds__(256) void k_abs_max_bits(const T *__restrict__ x, i
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
     if ((threadIdx.x & 63) == 0) atomicMax(out, static_cast<unsigned long long>(__double_as_longlong(m)));
+}
+
+// Pair records in a new order: slot m of position i takes slot m of position
+// idx[i] (|g|^2 and channel), and so does the first-channel array; positions
+// np .. ld - 1 get the padding values (|g|^2 0, channel -1).  idx[i] < np.
+template <typename T>
+__global__ __launch_bounds__(256) void k_permute_pairs(const uint32_t *__restrict__ idx, int64_t np, int64_t ld,
+                                                       int nm, const T *__restrict__ g_in, T *__restrict__ g_out,
+                                                       const int32_t *__restrict__ c_in, int32_t *__restrict__ c_out,
+                                                       const int32_t *__restrict__ c0_in,
+                                                       int32_t *__restrict__ c0_out) {
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < ld;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const bool in = i < np;
+        const int64_t j = in ? static_cast<int64_t>(idx[i]) : 0;
+        for (int m = 0; m < nm; ++m) {
+            g_out[m * ld + i] = in ? g_in[m * ld + j] : T(0);
+            c_out[m * ld + i] = in ? c_in[m * ld + j] : -1;
+        }
+        c0_out[i] = in ? c0_in[j] : -1;
+    }
 }
 
 // ---- transport ----------------------------------------------------------

@@ -608,4 +608,122 @@ PairRows build_pair_rows(const HostLayout &L) {
     return out;
 }
 
+int64_t row_of(const RowKey &k, int32_t d, int32_t p) {
+    const uint32_t kd = k.key[d], kp = k.key[p];
+    if (k.padq) return static_cast<int64_t>(static_cast<int32_t>(kp - kd)) + k.qoff;
+    int64_t q = 0;
+    for (int a = 0; a < 3; ++a) {
+        const int sh = 20 - 10 * a;
+        int v = static_cast<int>((kp >> sh) & 1023u) - static_cast<int>((kd >> sh) & 1023u);
+        v += v < 0 ? k.n[a] : 0;
+        q = q * k.n[a] + v;
+    }
+    return q;
+}
+
+PairOrder order_pair_tiles(const ChunkTable &pc, const std::vector<Tile> &tiles,
+                           const std::vector<uint32_t> &partner, const RowKey &rk, int chunks_per_tile,
+                           int64_t max_chunk) {
+    PairOrder o;
+    const int64_t np = static_cast<int64_t>(partner.size());
+    const int64_t nt = static_cast<int64_t>(tiles.size());
+    const int32_t S = static_cast<int32_t>(pc.dest_chunk.size()) - 1;
+    if (chunks_per_tile < 1) chunks_per_tile = 1;
+    if (max_chunk < 1) max_chunk = 1;
+    o.perm.resize(static_cast<size_t>(np));
+    o.word.resize(static_cast<size_t>(np));
+    parallel_ranges(np, host_threads(), [&](int, int64_t b, int64_t e) {
+        for (int64_t x = b; x < e; ++x) {
+            o.perm[x] = static_cast<uint32_t>(x);
+            o.word[x] = partner[x];
+        }
+    });
+    // the tiles that go to q order, and their record ranges
+    std::vector<int64_t> r0(static_cast<size_t>(nt), 0), r1(static_cast<size_t>(nt), 0);
+    std::vector<char> qt(static_cast<size_t>(nt), 0);
+    for (int64_t i = 0; i < nt; ++i) {
+        const Tile &t = tiles[i];
+        if (t.c1 <= t.c0) continue;
+        r0[i] = pc.chunk_beg[t.c0];
+        r1[i] = pc.chunk_end[t.c1 - 1];
+        qt[i] = t.lds == 1 && int64_t(t.p_hi) - t.p_lo < 65536;
+    }
+    parallel_ranges(nt, host_threads(), [&](int, int64_t b, int64_t e) {
+        std::vector<std::pair<uint64_t, uint32_t>> keys;
+        for (int64_t i = b; i < e; ++i) {
+            if (!qt[i]) continue;
+            const Tile &t = tiles[i];
+            keys.clear();
+            bool ok = true;
+            for (int64_t c = t.c0; c < t.c1 && ok; ++c) {
+                const int32_t d = pc.chunk_dest[c];
+                for (int64_t x = pc.chunk_beg[c]; x < pc.chunk_end[c]; ++x) {
+                    const int32_t p = static_cast<int32_t>(partner[x]);
+                    if (d < t.p_lo || d > t.p_hi || p < t.p_lo || p > t.p_hi) {
+                        ok = false;
+                        break;
+                    }
+                    const uint64_t row = static_cast<uint64_t>(row_of(rk, d, p));
+                    keys.emplace_back((row << 32) | (static_cast<uint64_t>(d - t.p_lo) << 16) |
+                                          static_cast<uint64_t>(p - t.p_lo),
+                                      static_cast<uint32_t>(x));
+                }
+            }
+            if (!ok) {
+                qt[i] = 0;   // window does not hold the destinations: destination order
+                continue;
+            }
+            std::sort(keys.begin(), keys.end());
+            for (size_t j = 0; j < keys.size(); ++j) {
+                const size_t at = static_cast<size_t>(r0[i]) + j;
+                const uint64_t k = keys[j].first;
+                o.perm[at] = keys[j].second;
+                o.word[at] = (static_cast<uint32_t>(k & 0xffffu) << 16) | static_cast<uint32_t>((k >> 16) & 0xffffu);
+            }
+        }
+    });
+    // the renumbered chunk table
+    ChunkTable &ct = o.chunks;
+    ct.dest_chunk.assign(static_cast<size_t>(S) + 1, 0);
+    std::vector<int32_t> new_of_old(static_cast<size_t>(pc.n_chunks), 0);
+    o.tiles = tiles;
+    bool any_q = false;
+    for (int64_t i = 0; i < nt; ++i) {
+        Tile &t = o.tiles[i];
+        const int64_t c0 = static_cast<int64_t>(ct.chunk_dest.size());
+        if (qt[i]) {
+            any_q = true;
+            const int64_t len = r1[i] - r0[i];
+            const int64_t per = static_cast<int64_t>(chunks_per_tile) * max_chunk;
+            const int64_t k = static_cast<int64_t>(chunks_per_tile) * std::max<int64_t>(1, (len + per - 1) / per);
+            for (int64_t j = 0; j < k; ++j) {
+                ct.chunk_beg.push_back(r0[i] + len * j / k);
+                ct.chunk_end.push_back(r0[i] + len * (j + 1) / k);
+                ct.chunk_dest.push_back(pc.chunk_dest[t.c0]);
+            }
+            for (int64_t c = t.c0; c < t.c1; ++c) new_of_old[c] = static_cast<int32_t>(c0);
+            t.lds = 2;
+        } else {
+            for (int64_t c = t.c0; c < t.c1; ++c) {
+                new_of_old[c] = static_cast<int32_t>(ct.chunk_dest.size());
+                ct.chunk_beg.push_back(pc.chunk_beg[c]);
+                ct.chunk_end.push_back(pc.chunk_end[c]);
+                ct.chunk_dest.push_back(pc.chunk_dest[c]);
+            }
+        }
+        t.c0 = c0;
+        t.c1 = static_cast<int64_t>(ct.chunk_dest.size());
+    }
+    ct.n_chunks = static_cast<int64_t>(ct.chunk_dest.size());
+    for (int32_t d = 0; d < S; ++d) {
+        const int32_t c = pc.dest_chunk[d];
+        ct.dest_chunk[d] = c < pc.n_chunks ? new_of_old[c] : static_cast<int32_t>(ct.n_chunks);
+    }
+    ct.dest_chunk[S] = static_cast<int32_t>(ct.n_chunks);
+    ct.chunk_beg.push_back(pc.chunk_beg.empty() ? 0 : pc.chunk_beg.back());
+    ct.one_per_dest = pc.one_per_dest && !any_q;
+    return o;
+}
+
 }  // namespace ephbte
+

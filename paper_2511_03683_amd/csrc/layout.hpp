@@ -69,7 +69,9 @@ struct Tile {
     int64_t c0, c1;        // chunks [c0, c1)
     int32_t p_lo, p_hi;    // LDS window of partner states (inclusive; at least one state
                            // when lds = 1, see make_tiles)
-    int32_t lds;           // 1: partners staged in LDS, 0: read from global memory
+    int32_t lds;           // 1: partners staged in LDS, 0: read from global memory,
+                           // 2: staged in LDS with the records in q order (pair records,
+                           // see order_pair_tiles)
     int32_t pad;
 };
 std::vector<Tile> make_tiles(const ChunkTable &ct, const std::vector<int64_t> &row_ptr,
@@ -125,6 +127,40 @@ struct PairRows {
     std::vector<int32_t> slot_chan;     // [n_modes][n_pairs]
 };
 PairRows build_pair_rows(const HostLayout &L);
+
+// Table row of the difference q = k_p - k_d, as the pair pass computes it:
+// with the padded box, (key_p - key_d) + qoff over the states' packed box
+// coordinates; otherwise the linear index of q on the q grid (keys are the
+// packed grid coordinates, 10 bits an axis).
+struct RowKey {
+    const uint32_t *key = nullptr;   // [S]
+    bool padq = false;
+    int32_t qoff = 0;
+    int32_t n[3] = {1, 1, 1};
+};
+int64_t row_of(const RowKey &k, int32_t d, int32_t p);
+
+// Pair records in q order.  Inside every LDS tile (lds = 1) of the pair
+// pass, the records are sorted by (table row of k_p - k_d, destination,
+// partner), so that the lanes of a batch read few rows of the {hw, N} table,
+// and the tile's records are cut into chunks_per_tile equal chunks (a
+// multiple of it when a chunk would exceed max_chunk records).  The window
+// of such a tile must hold its destinations too (p_lo <= every destination
+// with records).  A record's word is then (partner - p_lo) << 16 |
+// (destination - p_lo); elsewhere it stays the absolute partner.  A tile
+// whose window exceeds 65536 states keeps destination order.  The chunk
+// table is renumbered: destinations of a q-ordered tile own no chunk of
+// their own (their dest_chunk ranges cover only q-ordered chunks, which
+// carry no row partials).
+struct PairOrder {
+    ChunkTable chunks;
+    std::vector<Tile> tiles;          // c0, c1 renumbered; lds = 2 for q-ordered tiles
+    std::vector<uint32_t> perm;       // [n_pairs] new position -> record in destination order
+    std::vector<uint32_t> word;       // [n_pairs] stream word of the record at that position
+};
+PairOrder order_pair_tiles(const ChunkTable &pc, const std::vector<Tile> &tiles,
+                           const std::vector<uint32_t> &partner, const RowKey &rk, int chunks_per_tile,
+                           int64_t max_chunk);
 
 // Runs fn(t, begin, end) over [0, n) split into contiguous ranges on up to
 // `threads` host threads (deterministic partition).

@@ -154,8 +154,9 @@ int main(int argc, char **argv) {
     t.table_order = static_cast<int32_t>(meta("table_order", 0));
     t.pair_window = static_cast<int32_t>(meta("pair_window", 0));
     t.pair_threads = static_cast<int32_t>(meta("pair_threads", 0));
+    t.pair_order = static_cast<int32_t>(meta("pair_order", 0));
     if (t.layout || t.chunk_entries || t.block_threads || t.xcd_map || t.batch_partners || t.tile_entries ||
-        t.fp64_exp || t.table_order || t.pair_window || t.pair_threads)
+        t.fp64_exp || t.table_order || t.pair_window || t.pair_threads || t.pair_order)
         check(ephbte_set_tuning(plan, &t), "set_tuning");
     // empty_windows: every LDS tile whose chunks hold no entries gets an empty
     // partner window (nothing staged), the shape that once made masked lanes
@@ -300,6 +301,62 @@ int main(int argc, char **argv) {
             }
             if (next != x.nch) bad[k] += 1;
         }
+        // pair-record tiles: the same, and in a q-ordered tile (lds = 2) every
+        // word decodes to a pair (d, p), p_lo <= d < p <= p_hi, that is the
+        // record the host permutation names, the rows of q = k_p - k_d are
+        // non-decreasing, and the permutation is one
+        double bad_pr = 0, n_q = 0;
+        if (plan->pr_ok) {
+            const int64_t np = plan->pr_np;
+            std::vector<int64_t> row_of_rec(static_cast<size_t>(np));
+            for (int64_t d = 0; d < S; ++d)
+                for (int64_t y = plan->pr_rowptr[d]; y < plan->pr_rowptr[d + 1]; ++y) row_of_rec[y] = d;
+            std::vector<char> seen(static_cast<size_t>(np), 0);
+            ephbte::RowKey rk;
+            rk.key = plan->st_key.data();
+            rk.padq = plan->padq;
+            rk.qoff = plan->qoff;
+            for (int a = 0; a < 3; ++a) rk.n[a] = plan->nq[a];
+            int64_t next = 0;
+            for (int64_t i = 0; i < plan->n_pr_tiles; ++i) {
+                const TileRec t = plan->pr_tiles[i];
+                if (t.c0 != next || t.c1 < t.c0) bad_pr += 1;
+                next = t.c1;
+                if (t.lds && (t.p_hi < t.p_lo || t.p_hi - t.p_lo + 1 > plan->pr_lds_states || t.p_lo < 0 ||
+                              t.p_hi >= S))
+                    bad_pr += 1;
+                n_q += t.lds == 2;
+                int64_t last_row = -1;
+                for (int64_t c = t.c0; c < t.c1; ++c)
+                    for (int64_t x = plan->pr_chunk_beg[c]; x < plan->pr_chunk_end[c]; ++x) {
+                        const uint32_t w = plan->pr_partner[x];
+                        const int64_t y = plan->pr_perm.empty() ? x : plan->pr_perm[x];
+                        if (y < 0 || y >= np || seen[y]) {
+                            bad_pr += 1;
+                            continue;
+                        }
+                        seen[y] = 1;
+                        int64_t d, p;
+                        if (t.lds == 2) {
+                            d = t.p_lo + static_cast<int64_t>(w & 0xffffu);
+                            p = t.p_lo + static_cast<int64_t>(w >> 16);
+                            const int64_t r = ephbte::row_of(rk, static_cast<int32_t>(d), static_cast<int32_t>(p));
+                            if (r < last_row) bad_pr += 1;
+                            last_row = r;
+                            if (d < t.p_lo || p > t.p_hi || d >= p) bad_pr += 1;
+                        } else {
+                            d = row_of_rec[y];
+                            p = w;
+                            if (t.lds && (p < t.p_lo || p > t.p_hi)) bad_pr += 1;
+                        }
+                        if (d != row_of_rec[y] || p != static_cast<int64_t>(plan->pr_partner_host[y])) bad_pr += 1;
+                    }
+            }
+            if (next != plan->n_pr_chunks) bad_pr += 1;
+            for (int64_t y = 0; y < np; ++y) bad_pr += seen[y] ? 0 : 1;
+        }
+        bad.push_back(bad_pr);
+        bad.push_back(-n_q);
         wr("out_tiles.bin", bad);
     } else if (mode == "phonon") {
         auto f = rd<double>("f.bin", static_cast<size_t>(S));

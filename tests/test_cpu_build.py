@@ -603,12 +603,14 @@ def test_grouped_uneven_systems(driver, tmp_path):
 
 
 @pytest.mark.parametrize("name,tune", [("multiband", {}), ("multiband", dict(chunk_entries=5)),
+                                       ("multiband", dict(pair_order=2)), ("tb12", dict(pair_window=64)),
                                        ("parabolic4", {}), ("random_order", dict(chunk_entries=37)),
                                        ("tb12", {}), ("defect", {}), ("grouped", {})])
 def test_tile_tables(driver, tmp_path, name, tune):
-    """Every LDS tile of the three tile tables (forward, reverse/transport,
-    single copy) stages 1 .. cap states, its window holds every partner of its
-    chunks, and the tiles cover the chunks in order."""
+    """Every LDS tile of the four tile tables (forward, reverse/transport,
+    single copy, pair records) stages 1 .. cap states, its window holds every
+    partner of its chunks, and the tiles cover the chunks in order; the
+    q-ordered pair tiles hold every record once, in the order of their q."""
     if name == "multiband":
         s = synth.multiband_system()
     elif name == "grouped":
@@ -620,7 +622,14 @@ def test_tile_tables(driver, tmp_path, name, tune):
         tune = dict(tune, elastic_modes=1 << s.meta["elastic_mode"])
     _write(tmp_path, s, f=synth.random_occupations(s, 1), nph=s.nph(300.0), **tune)
     _run(driver, tmp_path, "tiles")
-    assert np.all(_out(tmp_path, "tiles") == 0), _out(tmp_path, "tiles")
+    out = _out(tmp_path, "tiles")
+    assert np.all(out[:4] == 0), out
+    # q-ordered pair tiles, unless destination order was asked for
+    n_q = -out[4]
+    if tune.get("pair_order") == 2:
+        assert n_q == 0, out
+    elif name in ("multiband", "tb12", "parabolic4"):
+        assert n_q > 0, out
 
 
 @pytest.mark.parametrize("name,layout,dtype", [("multiband", 2, "f64"), ("multiband", 1, "f64"),
@@ -762,16 +771,19 @@ def test_pair_records_with_rounded_up_mode_count(driver, tmp_path, dtype, order)
     assert nerr(_out(tmp_path, "gg2"), rg) <= tol
 
 
-@pytest.mark.parametrize("window,threads", [(64, 256), (200, 512), (1000, 768)])
-def test_pair_windows_and_workgroup_sizes(driver, tmp_path, window, threads):
+@pytest.mark.parametrize("window,threads,order", [(64, 256, 1), (200, 512, 1), (1000, 768, 1), (64, 256, 2),
+                                                 (1000, 1024, 2)])
+def test_pair_windows_and_workgroup_sizes(driver, tmp_path, window, threads, order):
     """Pair-record passes with smaller LDS windows (more tiles, some on the
-    global partner-side accumulator) and other workgroup sizes: forward and
+    global partner-side accumulator), other workgroup sizes, and the records
+    of the LDS tiles in q order (1) or destination order (2): forward and
     reverse against the oracle under a random fill of fresh memory."""
     s = synth.tb_system(kn=24, qn=12, target_states=400)
     f = synth.random_occupations(s, 131)
     lam = np.random.default_rng(132).normal(size=s.n_states)
     nph = s.nph(300.0)
-    _write(tmp_path, s, f=f, lam=lam, nph=nph, B=1, layout=3, pair_window=window, pair_threads=threads)
+    _write(tmp_path, s, f=f, lam=lam, nph=nph, B=1, layout=3, pair_window=window, pair_threads=threads,
+           pair_order=order)
     _run(driver, tmp_path, "forward", fill="random:%d" % window)
     assert nerr(_out(tmp_path, "I"), oracle.collision(s, f, nph)) <= TOL64
     _run(driver, tmp_path, "vjp", fill="random:%d" % threads)
@@ -780,16 +792,19 @@ def test_pair_windows_and_workgroup_sizes(driver, tmp_path, window, threads):
     assert nerr(_out(tmp_path, "gg2"), rg) <= TOL64
 
 
-@pytest.mark.parametrize("layout,fill,order", [(3, "random:9", 1), (2, None, 1), (3, "random:10", 2)])
-def test_vjp_six_modes(driver, tmp_path, layout, fill, order):
+@pytest.mark.parametrize("layout,fill,order,porder", [(3, "random:9", 1, 1), (2, None, 1, 1), (3, "random:10", 2, 1),
+                                                       (3, "random:11", 1, 2)])
+def test_vjp_six_modes(driver, tmp_path, layout, fill, order, porder):
     """Reverse pass on the six-mode tight-binding system: over pair records
-    (whose consecutive channels are written as 16-byte pairs) and over
-    entries; every |g|^2 gradient is overwritten (the buffer starts at 0.5)."""
+    (whose consecutive channels are written as 16-byte pairs; records in q or
+    destination order) and over entries; every |g|^2 gradient is overwritten
+    (the buffer starts at 0.5)."""
     s = synth.tb_system(kn=24, qn=12, target_states=400)
     f = synth.random_occupations(s, 111)
     lam = np.random.default_rng(112).normal(size=s.n_states)
     nph = s.nph(300.0)
-    _write(tmp_path, s, f=f, lam=lam, nph=nph, B=1, layout=layout, gg2_fill=0.5, table_order=order)
+    _write(tmp_path, s, f=f, lam=lam, nph=nph, B=1, layout=layout, gg2_fill=0.5, table_order=order,
+           pair_order=porder)
     _run(driver, tmp_path, "vjp", fill=fill)
     rf, rg = oracle.collision_vjp(s, f, nph, lam)
     assert nerr(_out(tmp_path, "gf"), rf) <= TOL64

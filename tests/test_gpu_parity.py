@@ -197,8 +197,11 @@ def test_single_copy_and_duplicated_layouts(E, name, dtype):
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_pair_pass_shapes_and_table_order(E, dtype):
     """The pair-record passes with smaller LDS windows and other workgroup
-    sizes, and with the {hw, N} table one block per mode: forward and reverse
-    against the oracle, the forward bitwise equal to the default shape."""
+    sizes, with the {hw, N} table one block per mode, and with the records of
+    the LDS tiles in q order or destination order (switched back and forth on
+    one plan): forward and reverse against the oracle; the forward repeats
+    bitwise, and in destination order it is bitwise the same for every shape
+    (its row sums do not depend on the tiles)."""
     s = synth.tb_system(kn=24, qn=12, target_states=400)
     f = np.clip(synth.random_occupations(s, 141), 0, 1)
     lam = np.random.default_rng(142).normal(size=s.n_states)
@@ -215,16 +218,21 @@ def test_pair_pass_shapes_and_table_order(E, dtype):
     assert E.plan_info(plan)["layout"] == 3
     say(f"pair pass shapes {dtype}")
     base = None
-    for w, th, order in ((0, 0, 1), (64, 256, 1), (500, 512, 1), (1000, 768, 2), (0, 1024, 2)):
-        E.set_tuning(plan, pair_window=w, pair_threads=th, table_order=order)
+    for w, th, order, po in ((0, 0, 1, 1), (64, 256, 1, 1), (500, 512, 1, 1), (1000, 768, 2, 1),
+                             (0, 1024, 2, 2), (64, 256, 1, 2), (500, 512, 2, 2), (3072 if dtype == "f64" else 4096,
+                                                                                1024, 1, 1)):
+        case = (w, th, order, po)
+        E.set_tuning(plan, pair_window=w, pair_threads=th, table_order=order, pair_order=po)
         I = host(E.collision_integral(plan, dev(f, tdt), dev(nph, tdt)))
-        assert nerr(I, ref, scale) <= tol, (w, th, order)
-        if base is None:
-            base = I
-        assert np.array_equal(I, base), (w, th, order)
+        assert nerr(I, ref, scale) <= tol, case
+        assert np.array_equal(I, host(E.collision_integral(plan, dev(f, tdt), dev(nph, tdt)))), case
+        if po == 2:
+            if base is None:
+                base = I
+            assert np.array_equal(I, base), case
         gf, gg = E.collision_vjp(plan, dev(f, tdt), dev(nph, tdt), dev(lam, tdt), gg2=True)
-        assert nerr(host(gf), rf) <= tol, (w, th, order)
-        assert nerr(host(gg), rg) <= tol, (w, th, order)
+        assert nerr(host(gf), rf) <= tol, case
+        assert nerr(host(gg), rg) <= tol, case
     plan.close()
 
 
