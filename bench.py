@@ -230,16 +230,27 @@ def main():
         return ev0.elapsed_time(ev1) / reps, wall
 
     fwd64 = lambda: E.collision_integral(plan64, f64, n64, out=I64)
-    # untimed passes for a quarter of a second first, so that the timed steps
-    # see the device in its steady state (clocks, first touches of the fresh
-    # plan's pages) as a serving loop would; then the W warmup steps
-    t_settle, n_settle = time.perf_counter(), 0
-    while time.perf_counter() - t_settle < 0.25:
-        with torch.cuda.stream(stream):
-            for _ in range(20):
-                fwd64()
-        stream.synchronize()
-        n_settle += 20
+
+    def settle(fn, secs=0.25):
+        # untimed passes for a quarter of a second, so that timed steps see the
+        # device in its steady state (clocks, first touches of fresh pages) as
+        # a serving loop would: after the plan is built, and after a tuning
+        # change (which re-tiles on the host while the device idles)
+        t_s, n_s = time.perf_counter(), 0
+        while time.perf_counter() - t_s < secs:
+            with torch.cuda.stream(stream):
+                for _ in range(20):
+                    fn()
+            stream.synchronize()
+            n_s += 20
+        return n_s
+
+    def retune(plan, fn, **kw):
+        E.set_tuning(plan, **kw)
+        settle(fn)
+
+    # then the W warmup steps
+    n_settle = settle(fwd64)
     with torch.cuda.stream(stream):
         for _ in range(args.warmup):
             fwd64()
@@ -315,32 +326,43 @@ def main():
         # evaluated in both of its rows)
         if layout64 == 3:
             # the pair pass with the polynomial exponential (no LDS table reads)
-            E.set_tuning(plan64, fp64_exp=2)
+            retune(plan64, fwd64, fp64_exp=2)
             msp2, _ = timed(fwd64, args.steps, args.warmup)
-            E.set_tuning(plan64, fp64_exp=1)
+            retune(plan64, fwd64, fp64_exp=1)
             forms["fwd_f64_b1_pairs_polyexp"] = dict(ms=msp2, channels_per_s=nch / (msp2 * 1e-3),
                                                      algorithmic_GBps=bpc * nch / (msp2 * 1e-3) / 1e9)
             log(f"fwd fp64 pair records, polynomial exponential: {msp2:.3f} ms")
             # the pair passes with the records of each tile in destination
             # order (the default sorts them by q)
-            E.set_tuning(plan64, pair_order=2)
+            retune(plan64, fwd64, pair_order=2)
             msd, _ = timed(fwd64, args.steps, args.warmup)
             msdv = vjp_b1(max(3, args.steps // 4))
-            E.set_tuning(plan64, pair_order=1)
+            retune(plan64, fwd64, pair_order=1)
             forms["fwd_f64_b1_pairs_destination_order"] = dict(
                 ms=msd, reverse_ms=msdv, channels_per_s=nch / (msd * 1e-3),
                 algorithmic_GBps=bpc * nch / (msd * 1e-3) / 1e9)
             log(f"fwd / vjp fp64 pair records in destination order: {msd:.3f} / {msdv:.3f} ms")
-            E.set_tuning(plan64, layout=2)
+            # q order in groups of 64 table rows: a destination's records stay
+            # together inside a group, so the reverse pass's dL/d|g|^2 writes
+            # are more contiguous
+            retune(plan64, fwd64, pair_rows=64)
+            msg, _ = timed(fwd64, args.steps, args.warmup)
+            msgv = vjp_b1(max(3, args.steps // 4))
+            retune(plan64, fwd64, pair_rows=1)
+            forms["fwd_f64_b1_pairs_rows64"] = dict(
+                ms=msg, reverse_ms=msgv, channels_per_s=nch / (msg * 1e-3),
+                algorithmic_GBps=bpc * nch / (msg * 1e-3) / 1e9)
+            log(f"fwd / vjp fp64 pair records in q order by groups of 64 rows: {msg:.3f} / {msgv:.3f} ms")
+            retune(plan64, fwd64, layout=2)
             mse, _ = timed(fwd64, args.steps, args.warmup)
             forms["fwd_f64_b1_entries"] = dict(ms=mse, channels_per_s=nch / (mse * 1e-3),
                                                algorithmic_GBps=BYTES_PER_CHANNEL_ENTRIES["f64"] * nch
                                                / (mse * 1e-3) / 1e9,
                                                layout="single copy, one entry per channel")
             log(f"fwd fp64 single copy over entries: {mse:.3f} ms")
-        E.set_tuning(plan64, layout=1)
+        retune(plan64, fwd64, layout=1)
         msr, _ = timed(fwd64, args.steps, args.warmup)
-        E.set_tuning(plan64, layout=layout64)
+        retune(plan64, fwd64, layout=layout64)
         forms["fwd_f64_b1_rows"] = dict(ms=msr, channels_per_s=nch / (msr * 1e-3),
                                         algorithmic_GBps=BYTES_PER_CHANNEL_ROWS["f64"] * nch / (msr * 1e-3) / 1e9,
                                         layout="duplicated rows")
@@ -461,22 +483,24 @@ def main():
         log(f"fp32 plan built ({time.time() - t0:.1f}s)")
         f32, n32 = tens(f_np, torch.float32), tens(nph_np, torch.float32)
         I32 = torch.empty_like(f32)
-        ms32, _ = timed(lambda: E.collision_integral(plan32, f32, n32, out=I32), args.steps, args.warmup)
+        fwd32 = lambda: E.collision_integral(plan32, f32, n32, out=I32)
+        settle(fwd32)
+        ms32, _ = timed(fwd32, args.steps, args.warmup)
         forms["fwd_f32_b1"] = dict(ms=ms32, channels_per_s=nch / (ms32 * 1e-3),
                                    algorithmic_GBps=bpc32 * nch / (ms32 * 1e-3) / 1e9,
                                    layout=LAYOUT_NAMES[info32["layout"]], bytes_per_channel=bpc32)
         log(f"fwd fp32: {ms32:.3f} ms")
         if info32["layout"] == 3:
-            E.set_tuning(plan32, layout=2)
-            ms32e, _ = timed(lambda: E.collision_integral(plan32, f32, n32, out=I32), args.steps, args.warmup)
+            retune(plan32, fwd32, layout=2)
+            ms32e, _ = timed(fwd32, args.steps, args.warmup)
             forms["fwd_f32_b1_entries"] = dict(ms=ms32e, channels_per_s=nch / (ms32e * 1e-3),
                                                algorithmic_GBps=BYTES_PER_CHANNEL_ENTRIES["f32"] * nch
                                                / (ms32e * 1e-3) / 1e9,
                                                layout=LAYOUT_NAMES[2])
             log(f"fwd fp32 single copy over entries: {ms32e:.3f} ms")
-        E.set_tuning(plan32, layout=1)
-        ms32r, _ = timed(lambda: E.collision_integral(plan32, f32, n32, out=I32), args.steps, args.warmup)
-        E.set_tuning(plan32, layout=info32["layout"])
+        retune(plan32, fwd32, layout=1)
+        ms32r, _ = timed(fwd32, args.steps, args.warmup)
+        retune(plan32, fwd32, layout=info32["layout"])
         forms["fwd_f32_b1_rows"] = dict(ms=ms32r, channels_per_s=nch / (ms32r * 1e-3),
                                         algorithmic_GBps=BYTES_PER_CHANNEL_ROWS["f32"] * nch / (ms32r * 1e-3) / 1e9,
                                         layout="duplicated rows")

@@ -146,6 +146,13 @@ typedef struct {
                                   both sides of a pair are fixed-point sums),
                                   2 = by destination (the destination's side
                                   summed in registers)                         */
+    int32_t pair_rows;         /* q order of pair_order 1: table rows per sort
+                                  group, a power of 2 up to 65536 (default 1:
+                                  sorted by q itself).  Larger groups keep more
+                                  of a destination's records together, which
+                                  makes the reverse pass's dL/d|g|^2 writes more
+                                  contiguous when the caller lists channels by
+                                  state pair, at some cost to the forward pass */
 } ephbte_tuning;
 
 /* Build options.  Channel selection (paper: scattering-channel paragraph

@@ -51,7 +51,7 @@ class Tuning(ctypes.Structure):
                 ("tile_entries", ctypes.c_int32), ("layout", ctypes.c_int32),
                 ("fp64_exp", ctypes.c_int32), ("table_order", ctypes.c_int32),
                 ("pair_window", ctypes.c_int32), ("pair_threads", ctypes.c_int32),
-                ("pair_order", ctypes.c_int32)]
+                ("pair_order", ctypes.c_int32), ("pair_rows", ctypes.c_int32)]
 
 
 _LIB = None
@@ -442,20 +442,20 @@ def update_g2(plan: Plan, g2):
 
 def set_tuning(plan: Plan, chunk_entries=0, block_threads=0, xcd_map=0, batch_partners=0,
                tile_entries=0, layout=0, fp64_exp=0, table_order=0, pair_window=0, pair_threads=0,
-               pair_order=0):
+               pair_order=0, pair_rows=0):
     """Knobs left at 0 keep the plan's value; tile_entries=-1 restores its default;
     layout 1 = duplicated rows, 2 = single copy over entries, 3 = single copy
     over pair records (B = 1 forward pass); fp64_exp 1 = table, 2 = polynomial;
     table_order 1 = the modes of one q adjacent, 2 = one block per mode;
     pair_window / pair_threads: LDS window (states) and workgroup size of the
     pair-record passes; pair_order 1 = the records of their LDS tiles sorted by
-    q, 2 = by destination."""
+    q (in groups of pair_rows table rows, a power of 2), 2 = by destination."""
     t = Tuning()
     t.chunk_entries, t.block_threads, t.xcd_map = int(chunk_entries), int(block_threads), int(xcd_map)
     t.batch_partners, t.tile_entries, t.layout = int(batch_partners), int(tile_entries), int(layout)
     t.fp64_exp, t.table_order = int(fp64_exp), int(table_order)
     t.pair_window, t.pair_threads = int(pair_window), int(pair_threads)
-    t.pair_order = int(pair_order)
+    t.pair_order, t.pair_rows = int(pair_order), int(pair_rows)
     _check(load_library().ephbte_set_tuning(plan.handle, ctypes.byref(t)), "set_tuning")
 
 

@@ -142,6 +142,7 @@ struct ephbte_plan_s {
     int pr_lds_states = 0;      // partner window of the pair-record passes
     int pr_threads = 1024;      // threads per workgroup of the pair forward pass
     int pair_order = 1;         // records of the LDS tiles: 1 q order, 2 destination order
+    int pair_shift = 0;         // q order by table row >> pair_shift
     bool sym_ok = false;                    // the single-copy window fits the LDS of a workgroup
     int layout = 2;                         // B = 1 forward: 1 duplicated rows, 2 single copy,
                                             // 3 single copy over pair records
@@ -373,6 +374,7 @@ void order_pair_records(ephbte_plan P, ChunkTable &pc, std::vector<Tile> &tp, bo
     rk.key = P->st_key.data();
     rk.padq = P->padq;
     rk.qoff = P->qoff;
+    rk.shift = P->pair_shift;
     for (int a = 0; a < 3; ++a) rk.n[a] = P->nq[a];
     PairOrder o;
     if (qord) {
@@ -2970,6 +2972,9 @@ ephbte_status ephbte_set_tuning(ephbte_plan plan, const ephbte_tuning *tuning) {
             return fail(EPHBTE_INVALID_ARGUMENT, "pair_threads must be 0 (keep), 256, 512, 768 or 1024");
         if (tuning->pair_order < 0 || tuning->pair_order > 2)
             return fail(EPHBTE_INVALID_ARGUMENT, "pair_order must be 0 (keep), 1 or 2");
+        const int prow = tuning->pair_rows;
+        if (prow < 0 || prow > 65536 || (prow & (prow - 1)) != 0)
+            return fail(EPHBTE_INVALID_ARGUMENT, "pair_rows must be 0 (keep) or a power of 2 up to 65536");
         if (tuning->tile_entries < -1)
             return fail(EPHBTE_INVALID_ARGUMENT, "tile_entries must be -1 (default), 0 (keep) or > 0");
         if (tuning->fp64_exp < 0 || tuning->fp64_exp > 2)
@@ -2992,6 +2997,7 @@ ephbte_status ephbte_set_tuning(ephbte_plan plan, const ephbte_tuning *tuning) {
         if (pw) plan->pr_lds_states = pw;
         if (pth) plan->pr_threads = pth;
         if (tuning->pair_order) plan->pair_order = tuning->pair_order;
+        if (prow) plan->pair_shift = __builtin_ctz(static_cast<unsigned>(prow));
         upload_chunks(plan, ce);
         if (pt != 0) upload_btiles(plan, pt);
         free_graphs(plan);

@@ -1292,14 +1292,15 @@ __device__ __forceinline__ void vjp_pair_chunk_q(const TiledArgs<T> &A, const Pa
     const T *__restrict__ gb = A.g2 + beg;
     const int32_t *__restrict__ cb = chan + beg;
     const int32_t *__restrict__ cb0 = chan0 + beg;
-    uint32_t pn = pb[lane];
-    for (int r = 0; r < len; r += 64) {
-        const bool v = r + lane < len;
-        const uint32_t pn_next = pb[r + 64 + lane];
-        T g[NM];
+    // stream one batch ahead, two register sets (see pair_chunk)
+    uint32_t pn0 = pb[lane], pn1 = 0;
+    int32_t h0 = gg2_mode ? cb0[lane] : -1, h1 = -1;
+    T g0[NM], g1[NM];
 #pragma unroll
-        for (int m = 0; m < NM; ++m) g[m] = gb[min(m, nm - 1) * A.pld + r + lane];
-        const int32_t c0 = gg2_mode ? cb0[r + lane] : -1;
+    for (int m = 0; m < NM; ++m) g0[m] = gb[min(m, nm - 1) * A.pld + lane];
+    auto batch = [&](int r, const uint32_t pn, const T (&g)[NM], const int32_t c0, uint32_t &pn_next,
+                     T (&g_next)[NM], int32_t &c0_next) {
+        const bool v = r + lane < len;
         // a masked lane takes window slot 0 as both states and adds nothing
         const int wd = v ? static_cast<int>(pn & 0xffffu) : 0;
         const int wp = v ? static_cast<int>(pn >> 16) : 0;
@@ -1311,6 +1312,11 @@ __device__ __forceinline__ void vjp_pair_chunk_q(const TiledArgs<T> &A, const Pa
         Pair2<T> w[NM];
 #pragma unroll
         for (int m = 0; m < NM; ++m) w[m] = wq[min(m, nm - 1) * A.tm];
+        __builtin_amdgcn_sched_barrier(0);
+        pn_next = pb[r + 64 + lane];
+#pragma unroll
+        for (int m = 0; m < NM; ++m) g_next[m] = gb[min(m, nm - 1) * A.pld + r + 64 + lane];
+        c0_next = gg2_mode ? cb0[r + 64 + lane] : -1;
         __builtin_amdgcn_sched_barrier(0);
         const T fd = efd.b, cfd = T(1) - fd, fp = efp.b, ofp = T(1) - fp;
         const T dl = ld - lp;
@@ -1325,7 +1331,11 @@ __device__ __forceinline__ void vjp_pair_chunk_q(const TiledArgs<T> &A, const Pa
             atomicAdd(s_j + wp, to_fixed(__builtin_rint(y * scale)));
             atomicAdd(s_j + wd, to_fixed(__builtin_rint(-rd * scale)));
         }
-        pn = pn_next;
+    };
+    for (int r = 0; r < len; r += 128) {
+        batch(r, pn0, g0, h0, pn1, g1, h1);
+        if (r + 64 >= len) break;
+        batch(r + 64, pn1, g1, h1, pn0, g0, h0);
     }
     if (want_f && lane == 0) part[c] = T(0);
 }

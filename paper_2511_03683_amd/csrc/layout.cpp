@@ -663,7 +663,7 @@ PairOrder order_pair_tiles(const ChunkTable &pc, const std::vector<Tile> &tiles,
                         ok = false;
                         break;
                     }
-                    const uint64_t row = static_cast<uint64_t>(row_of(rk, d, p));
+                    const uint64_t row = static_cast<uint64_t>(row_of(rk, d, p) >> rk.shift);
                     keys.emplace_back((row << 32) | (static_cast<uint64_t>(d - t.p_lo) << 16) |
                                           static_cast<uint64_t>(p - t.p_lo),
                                       static_cast<uint32_t>(x));

@@ -137,12 +137,16 @@ struct RowKey {
     bool padq = false;
     int32_t qoff = 0;
     int32_t n[3] = {1, 1, 1};
+    int32_t shift = 0;               // order_pair_tiles sorts by row >> shift first
 };
 int64_t row_of(const RowKey &k, int32_t d, int32_t p);
 
 // Pair records in q order.  Inside every LDS tile (lds = 1) of the pair
-// pass, the records are sorted by (table row of k_p - k_d, destination,
-// partner), so that the lanes of a batch read few rows of the {hw, N} table,
+// pass, the records are sorted by (table row of k_p - k_d >> rk.shift,
+// destination, partner), so that the lanes of a batch read few rows of the
+// {hw, N} table (2^shift neighbouring rows form one group, inside which the
+// records of a destination are consecutive, and so are their channels when
+// the caller lists the channels by state pair),
 // and the tile's records are cut into chunks_per_tile equal chunks (a
 // multiple of it when a chunk would exceed max_chunk records).  The window
 // of such a tile must hold its destinations too (p_lo <= every destination

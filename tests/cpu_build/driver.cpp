@@ -155,8 +155,9 @@ int main(int argc, char **argv) {
     t.pair_window = static_cast<int32_t>(meta("pair_window", 0));
     t.pair_threads = static_cast<int32_t>(meta("pair_threads", 0));
     t.pair_order = static_cast<int32_t>(meta("pair_order", 0));
+    t.pair_rows = static_cast<int32_t>(meta("pair_rows", 0));
     if (t.layout || t.chunk_entries || t.block_threads || t.xcd_map || t.batch_partners || t.tile_entries ||
-        t.fp64_exp || t.table_order || t.pair_window || t.pair_threads || t.pair_order)
+        t.fp64_exp || t.table_order || t.pair_window || t.pair_threads || t.pair_order || t.pair_rows)
         check(ephbte_set_tuning(plan, &t), "set_tuning");
     // empty_windows: every LDS tile whose chunks hold no entries gets an empty
     // partner window (nothing staged), the shape that once made masked lanes
@@ -317,6 +318,7 @@ int main(int argc, char **argv) {
             rk.padq = plan->padq;
             rk.qoff = plan->qoff;
             for (int a = 0; a < 3; ++a) rk.n[a] = plan->nq[a];
+            const int shift = plan->pair_shift;
             int64_t next = 0;
             for (int64_t i = 0; i < plan->n_pr_tiles; ++i) {
                 const TileRec t = plan->pr_tiles[i];
@@ -340,7 +342,8 @@ int main(int argc, char **argv) {
                         if (t.lds == 2) {
                             d = t.p_lo + static_cast<int64_t>(w & 0xffffu);
                             p = t.p_lo + static_cast<int64_t>(w >> 16);
-                            const int64_t r = ephbte::row_of(rk, static_cast<int32_t>(d), static_cast<int32_t>(p));
+                            const int64_t r =
+                                ephbte::row_of(rk, static_cast<int32_t>(d), static_cast<int32_t>(p)) >> shift;
                             if (r < last_row) bad_pr += 1;
                             last_row = r;
                             if (d < t.p_lo || p > t.p_hi || d >= p) bad_pr += 1;

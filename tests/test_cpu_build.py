@@ -604,6 +604,7 @@ def test_grouped_uneven_systems(driver, tmp_path):
 
 @pytest.mark.parametrize("name,tune", [("multiband", {}), ("multiband", dict(chunk_entries=5)),
                                        ("multiband", dict(pair_order=2)), ("tb12", dict(pair_window=64)),
+                                       ("tb12", dict(pair_rows=16)),
                                        ("parabolic4", {}), ("random_order", dict(chunk_entries=37)),
                                        ("tb12", {}), ("defect", {}), ("grouped", {})])
 def test_tile_tables(driver, tmp_path, name, tune):
@@ -771,9 +772,9 @@ def test_pair_records_with_rounded_up_mode_count(driver, tmp_path, dtype, order)
     assert nerr(_out(tmp_path, "gg2"), rg) <= tol
 
 
-@pytest.mark.parametrize("window,threads,order", [(64, 256, 1), (200, 512, 1), (1000, 768, 1), (64, 256, 2),
-                                                 (1000, 1024, 2)])
-def test_pair_windows_and_workgroup_sizes(driver, tmp_path, window, threads, order):
+@pytest.mark.parametrize("window,threads,order,rows", [(64, 256, 1, 1), (200, 512, 1, 1), (1000, 768, 1, 4),
+                                                      (64, 256, 2, 1), (1000, 1024, 2, 1), (0, 1024, 1, 64)])
+def test_pair_windows_and_workgroup_sizes(driver, tmp_path, window, threads, order, rows):
     """Pair-record passes with smaller LDS windows (more tiles, some on the
     global partner-side accumulator), other workgroup sizes, and the records
     of the LDS tiles in q order (1) or destination order (2): forward and
@@ -783,7 +784,7 @@ def test_pair_windows_and_workgroup_sizes(driver, tmp_path, window, threads, ord
     lam = np.random.default_rng(132).normal(size=s.n_states)
     nph = s.nph(300.0)
     _write(tmp_path, s, f=f, lam=lam, nph=nph, B=1, layout=3, pair_window=window, pair_threads=threads,
-           pair_order=order)
+           pair_order=order, pair_rows=rows)
     _run(driver, tmp_path, "forward", fill="random:%d" % window)
     assert nerr(_out(tmp_path, "I"), oracle.collision(s, f, nph)) <= TOL64
     _run(driver, tmp_path, "vjp", fill="random:%d" % threads)

@@ -218,11 +218,11 @@ def test_pair_pass_shapes_and_table_order(E, dtype):
     assert E.plan_info(plan)["layout"] == 3
     say(f"pair pass shapes {dtype}")
     base = None
-    for w, th, order, po in ((0, 0, 1, 1), (64, 256, 1, 1), (500, 512, 1, 1), (1000, 768, 2, 1),
-                             (0, 1024, 2, 2), (64, 256, 1, 2), (500, 512, 2, 2), (3072 if dtype == "f64" else 4096,
-                                                                                1024, 1, 1)):
-        case = (w, th, order, po)
-        E.set_tuning(plan, pair_window=w, pair_threads=th, table_order=order, pair_order=po)
+    for w, th, order, po, rows in ((0, 0, 1, 1, 0), (64, 256, 1, 1, 0), (500, 512, 1, 1, 16), (1000, 768, 2, 1, 1),
+                                   (0, 1024, 2, 2, 0), (64, 256, 1, 2, 0), (500, 512, 2, 2, 0),
+                                   (3072 if dtype == "f64" else 4096, 1024, 1, 1, 64)):
+        case = (w, th, order, po, rows)
+        E.set_tuning(plan, pair_window=w, pair_threads=th, table_order=order, pair_order=po, pair_rows=rows)
         I = host(E.collision_integral(plan, dev(f, tdt), dev(nph, tdt)))
         assert nerr(I, ref, scale) <= tol, case
         assert np.array_equal(I, host(E.collision_integral(plan, dev(f, tdt), dev(nph, tdt)))), case
