@@ -1166,16 +1166,28 @@ template <int NM>
 __device__ __forceinline__ void write_gg2(double *__restrict__ gg2, int gg2_mode, int32_t c0,
                                           const int32_t *__restrict__ cb, int64_t pld, int nm,
                                           const double (&gv)[NM]) {
+    // The overwriting stores do not share instructions with the accumulating
+    // ones: a store of either a loaded value or another would wait for every
+    // load in flight, the next batch's stream too.
     if (c0 >= 0 && NM == nm && (NM & 1) == 0 && (c0 & 1) == 0) {
         // 16-byte aligned: the lane writes them as whole pairs
         double2 *dst = reinterpret_cast<double2 *>(gg2 + c0);
+        if (gg2_mode == 2) {
 #pragma unroll
-        for (int k = 0; k < NM / 2; ++k) {
-            double2 o = gg2_mode == 2 ? dst[k] : make_double2(0.0, 0.0);
-            o.x += gv[2 * k];
-            o.y += gv[2 * k + 1];
-            dst[k] = o;
+            for (int k = 0; k < NM / 2; ++k) {
+                double2 o = dst[k];
+                o.x += gv[2 * k];
+                o.y += gv[2 * k + 1];
+                dst[k] = o;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < NM / 2; ++k) dst[k] = make_double2(gv[2 * k], gv[2 * k + 1]);
         }
+    } else if (c0 >= 0 && gg2_mode != 2) {
+#pragma unroll
+        for (int m = 0; m < NM; ++m)
+            if (m < nm) gg2[c0 + m] = gv[m];
     } else {
 #pragma unroll
         for (int m = 0; m < NM; ++m) {
