@@ -47,9 +47,10 @@
  * Determinism: results are bitwise reproducible run to run for a given plan
  *   and launch configuration.  Floating-point sums have a fixed order and use
  *   no atomics.  The single-copy passes (forward and reverse, layouts 2 and 3)
- *   add the partner side of each channel or pair with integer atomics on
- *   64-bit fixed-point values; integer addition is associative, so those sums
- *   do not depend on the order of arrival.  The phonon-side rate uses no
+ *   add the partner side of each channel or pair (and, for the pair records
+ *   in q order, the destination side too) with integer atomics on 64-bit
+ *   fixed-point values; integer addition is associative, so those sums do
+ *   not depend on the order of arrival.  The phonon-side rate uses no
  *   atomics.  The fixed-point scale is a power of two chosen per call from
  *   max |N| of the call's table, the largest sum of |g|^2 over one state's
  *   channels (and max |lambda| in the reverse pass); Fermi plans assume
@@ -237,10 +238,11 @@ ephbte_status ephbte_layout_host(const ephbte_problem *problem, const ephbte_bui
  * I:   device [B][ldi], plan dtype, written.  I must not alias f.
  * B >= 1; ldf, ldi >= S.
  * Reductions: with B = 1 and the single-copy layout every channel is read
- * once; the row side is summed in registers in a fixed order and the partner
- * side in 64-bit fixed point with integer atomics (associative, so the result
- * is bitwise reproducible).  Other forms reduce each destination's entries
- * with no atomics.
+ * once; the partner side is summed in 64-bit fixed point with integer
+ * atomics (associative, so the result is bitwise reproducible), and so is the
+ * row side over pair records in q order (pair_order 1); otherwise the row
+ * side is summed in registers in a fixed order.  Other forms reduce each
+ * destination's entries with no atomics.
  */
 ephbte_status ephbte_collision_integral(ephbte_plan plan, int32_t batch, const void *f,
                                         int64_t ldf, const void *nph, int32_t nph_per_batch,
