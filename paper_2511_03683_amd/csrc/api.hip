@@ -1826,9 +1826,19 @@ template <typename T> PhArgs<T> ph_args(ephbte_plan P) {
 template <typename T> void enqueue_phonon_rate(ephbte_plan P, const T *u, const T *nph, T *rate, hipStream_t s) {
     const PhArgs<T> a = ph_args<T>(P);
     T *part = static_cast<T *>(P->ph_part.p);
-    if (P->ph_nchunks > 0)
-        hipLaunchKernelGGL((k_phonon_bins<T>), dim3(static_cast<unsigned>((P->ph_nchunks + 3) / 4)), dim3(256), 0,
-                           s, a, u, nph, part);
+    if (P->ph_nchunks > 0) {
+        const dim3 grid(static_cast<unsigned>((P->ph_nchunks + 3) / 4)), block(256);
+        auto go = [&](auto nmc) {
+            constexpr int NM = decltype(nmc)::value;
+            hipLaunchKernelGGL((k_phonon_bins<T, NM>), grid, block, 0, s, a, u, nph, part);
+        };
+        if (P->nm <= 1) go(std::integral_constant<int, 1>{});
+        else if (P->nm <= 2) go(std::integral_constant<int, 2>{});
+        else if (P->nm <= 3) go(std::integral_constant<int, 3>{});
+        else if (P->nm <= 4) go(std::integral_constant<int, 4>{});
+        else if (P->nm <= 6) go(std::integral_constant<int, 6>{});
+        else go(std::integral_constant<int, 8>{});
+    }
     const int64_t nbin = a.nq * P->nm;
     const unsigned nf = static_cast<unsigned>(std::max<int64_t>(std::min<int64_t>((nbin + 255) / 256, 4096), 1));
     hipLaunchKernelGGL((k_phonon_bins_finish<T>), dim3(nf), dim3(256), 0, s, a, (const T *)part, rate);

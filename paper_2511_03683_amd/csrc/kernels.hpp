@@ -2356,7 +2356,12 @@ __device__ __forceinline__ T ph_gauss(const PhArgs<T> &A, T x, const double *tab
     else return __builtin_amdgcn_exp2f(x * x * A.mc);
 }
 
-template <typename T>
+// The mode loop is unrolled to NM >= nm slots (1, 2, 3, 4, 6 or 8).  The
+// record stream (a, b and the |g|^2 slots) runs one batch ahead of the state
+// gathers and the evaluation, with two register sets, as in the pair pass;
+// a lane past the chunk's end re-reads the chunk's last record and adds
+// nothing.
+template <typename T, int NM>
 __global__ __launch_bounds__(256) void k_phonon_bins(PhArgs<T> A, const T *__restrict__ f,
                                                      const T *__restrict__ nph, T *__restrict__ part) {
     __shared__ double s_tab[kExpTab];
@@ -2367,50 +2372,70 @@ __global__ __launch_bounds__(256) void k_phonon_bins(PhArgs<T> A, const T *__res
     const int64_t c = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) +
                       __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
     if (c >= A.n_chunks) return;
+    const int nm = A.nm;
     const int bk = A.chunk_bucket[c];
     const int64_t qc = A.bucket_q[bk], qm = A.bucket_qm[bk];
     const uint32_t modes = A.bucket_modes[bk] & ~A.elastic;
-    T w1[8], n1[8], w2[8], n2[8], acc1[8], acc2[8];
+    T w1[NM], n1[NM], w2[NM], n2[NM], acc1[NM], acc2[NM];
 #pragma unroll
-    for (int m = 0; m < 8; ++m) {
-        const bool on = (modes >> m) & 1u;
-        w1[m] = on ? A.hw[qc * A.nm + m] : T(0);
-        n1[m] = on ? nph[qc * A.nm + m] : T(0);
-        w2[m] = on ? A.hw[qm * A.nm + m] : T(0);
-        n2[m] = on ? nph[qm * A.nm + m] : T(0);
+    for (int m = 0; m < NM; ++m) {
+        const bool on = m < nm && ((modes >> m) & 1u);
+        const int mm = min(m, nm - 1);
+        w1[m] = on ? A.hw[qc * nm + mm] : T(0);
+        n1[m] = on ? nph[qc * nm + mm] : T(0);
+        w2[m] = on ? A.hw[qm * nm + mm] : T(0);
+        n2[m] = on ? nph[qm * nm + mm] : T(0);
         acc1[m] = T(0);
         acc2[m] = T(0);
     }
-    const int64_t beg = A.chunk_beg[c], end = A.chunk_beg[c + 1];
-    for (int64_t i = beg + lane; i < end; i += 64) {
-        const uint32_t a = A.pa[i], b = A.pb[i];
+    const int64_t beg = A.chunk_beg[c];
+    const int n = static_cast<int>(A.chunk_beg[c + 1] - beg);
+    auto rec = [&](int r) { return beg + min(r + lane, n - 1); };
+    uint32_t a0 = A.pa[rec(0)], b0 = A.pb[rec(0)], a1 = 0, b1 = 0;
+    T g0[NM], g1[NM];
+#pragma unroll
+    for (int m = 0; m < NM; ++m) g0[m] = A.g2[min(m, nm - 1) * A.ld + rec(0)];
+    auto batch = [&](int r, const uint32_t a, const uint32_t b, const T (&g)[NM], uint32_t &an, uint32_t &bn,
+                     T (&gn)[NM]) {
+        const bool v = r + lane < n;
         const T fa = f[a], fb = f[b];
         const T d = A.st[a].eps - A.st[b].eps;
+        __builtin_amdgcn_sched_barrier(0);
+        const int64_t x = rec(r + 64);
+        an = A.pa[x];
+        bn = A.pb[x];
+#pragma unroll
+        for (int m = 0; m < NM; ++m) gn[m] = A.g2[min(m, nm - 1) * A.ld + x];
+        __builtin_amdgcn_sched_barrier(0);
         const T p1 = fb * (T(1) - fa), p2 = fa * (T(1) - fb);
         const T dp = p1 - p2;
 #pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            if (!((modes >> m) & 1u)) continue;
-            const T g = A.g2[m * A.ld + i];
+        for (int m = 0; m < NM; ++m) {
+            // modes outside the bucket (and elastic ones) add nothing
+            const T gm = keep_or_zero(g[m], v && m < nm && ((modes >> m) & 1u));
             const T ga = ph_gauss(A, d + w1[m], s_tab);
             const T ge = ph_gauss(A, d - w2[m], s_tab);
-            acc1[m] += g * ga * (p1 + n1[m] * dp);
-            acc2[m] += g * ge * (p2 - n2[m] * dp);
+            acc1[m] = fma(gm * ga, fma(n1[m], dp, p1), acc1[m]);
+            acc2[m] = fma(gm * ge, fma(-n2[m], dp, p2), acc2[m]);
         }
+    };
+    for (int r = 0; r < n; r += 128) {
+        batch(r, a0, b0, g0, a1, b1, g1);
+        if (r + 64 >= n) break;
+        batch(r + 64, a1, b1, g1, a0, b0, g0);
     }
 #pragma unroll
-    for (int m = 0; m < 8; ++m) {
-        if (!((modes >> m) & 1u)) continue;
+    for (int m = 0; m < NM; ++m) {
         acc1[m] = wave_sum(acc1[m]);
         acc2[m] = wave_sum(acc2[m]);
     }
     if (lane == 0) {
-        T *pc = part + c * 2 * A.nm;
+        T *pc = part + c * 2 * nm;
 #pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            if (m >= A.nm) break;
+        for (int m = 0; m < NM; ++m) {
+            if (m >= nm) break;
             pc[m] = acc1[m];
-            pc[A.nm + m] = acc2[m];
+            pc[nm + m] = acc2[m];
         }
     }
 }
