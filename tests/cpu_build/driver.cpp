@@ -436,6 +436,28 @@ int main(int argc, char **argv) {
         st.push_back(ephbte_iterate_transport(plan, df, dx, 300.0, dN, 0.0, 1, nullptr, mob, nullptr, nullptr,
                                               nullptr));
         wr("out_status.bin", st);
+    } else if (mode == "tuning_rejects") {
+        // out-of-range tuning knobs are rejected and leave the plan as it was;
+        // then the forward pass still gives I
+        std::vector<double> st;
+        auto one = [&](auto setf) {
+            ephbte_tuning t{};
+            setf(t);
+            st.push_back(ephbte_set_tuning(plan, &t));
+        };
+        one([](ephbte_tuning &t) { t.pair_order = 3; });
+        one([](ephbte_tuning &t) { t.pair_order = -1; });
+        one([](ephbte_tuning &t) { t.pair_rows = 3; });
+        one([](ephbte_tuning &t) { t.pair_rows = 131072; });
+        one([](ephbte_tuning &t) { t.pair_rows = -2; });
+        one([](ephbte_tuning &t) { t.pair_threads = 640; });
+        one([](ephbte_tuning &t) { t.pair_window = 32; });
+        one([](ephbte_tuning &t) { t.table_order = 3; });
+        wr("out_status.bin", st);
+        auto f = rd<double>("f.bin", static_cast<size_t>(S));
+        void *df = dv.up(f), *dI = dv.alloc(static_cast<size_t>(S));
+        check(ephbte_collision_integral(plan, 1, df, S, dN, 0, dI, S, nullptr), "collision_integral");
+        wr("out_I.bin", dv.down(dI, static_cast<size_t>(S)));
     } else if (mode == "transport") {
         auto f0 = rd<double>("f.bin", static_cast<size_t>(S));
         auto vel = rd<double>("vel.bin", static_cast<size_t>(S) * 3);

@@ -793,6 +793,19 @@ def test_pair_windows_and_workgroup_sizes(driver, tmp_path, window, threads, ord
     assert nerr(_out(tmp_path, "gg2"), rg) <= TOL64
 
 
+def test_tuning_rejects_out_of_range_knobs(driver, tmp_path):
+    """Record order, row groups, workgroup size, window and table order out
+    of range: each set_tuning call fails with INVALID_ARGUMENT and leaves the
+    plan's q-ordered pair pass working."""
+    s = synth.tb_system(kn=24, qn=12, target_states=400)
+    f = synth.random_occupations(s, 151)
+    nph = s.nph(300.0)
+    _write(tmp_path, s, f=f, nph=nph, B=1, layout=3)
+    _run(driver, tmp_path, "tuning_rejects")
+    assert _out(tmp_path, "status").tolist() == [1.0] * 8   # EPHBTE_INVALID_ARGUMENT
+    assert nerr(_out(tmp_path, "I"), oracle.collision(s, f, nph)) <= TOL64
+
+
 @pytest.mark.parametrize("layout,fill,order,porder", [(3, "random:9", 1, 1), (2, None, 1, 1), (3, "random:10", 2, 1),
                                                        (3, "random:11", 1, 2)])
 def test_vjp_six_modes(driver, tmp_path, layout, fill, order, porder):
