@@ -1873,9 +1873,20 @@ void enqueue_phonon_adj(ephbte_plan P, const T *u, const T *N, const T *lam, con
                         hipStream_t s) {
     PhArgs<T> a = ph_args<T>(P);
     T *part = static_cast<T *>(P->ph_part.p);
-    if (P->ph_nchunks > 0)
-        hipLaunchKernelGGL((k_phonon_bins_adj<T>), dim3(static_cast<unsigned>((P->ph_nchunks + 3) / 4)), dim3(256),
-                           0, s, a, u, N, lam, mu, part, gg2, k_electron(P));
+    if (P->ph_nchunks > 0) {
+        const dim3 grid(static_cast<unsigned>((P->ph_nchunks + 3) / 4)), block(256);
+        const double ke = k_electron(P);
+        auto go = [&](auto nmc) {
+            constexpr int NM = decltype(nmc)::value;
+            hipLaunchKernelGGL((k_phonon_bins_adj<T, NM>), grid, block, 0, s, a, u, N, lam, mu, part, gg2, ke);
+        };
+        if (P->nm <= 1) go(std::integral_constant<int, 1>{});
+        else if (P->nm <= 2) go(std::integral_constant<int, 2>{});
+        else if (P->nm <= 3) go(std::integral_constant<int, 3>{});
+        else if (P->nm <= 4) go(std::integral_constant<int, 4>{});
+        else if (P->nm <= 6) go(std::integral_constant<int, 6>{});
+        else go(std::integral_constant<int, 8>{});
+    }
     a.Kp = 1.0;   // the partials already carry their constants
     hipLaunchKernelGGL((k_phonon_bins_finish<T>), dim3(grid_of(a.nq * P->nm)), dim3(256), 0, s, a,
                        (const T *)part, gN);

@@ -2451,7 +2451,14 @@ __global__ __launch_bounds__(256) void k_phonon_bins(PhArgs<T> A, const T *__res
 //   Kp [mu(qc) G1 (P1 + N(qc) (P1 - P2)) + mu(-qc) E2 (P2 - N(-qc) (P1 - P2))]
 // (its only writer: every channel has one slot).  Elastic modes have no
 // phonon side: only their lam terms.  lam or mu may be null (taken as 0).
-template <typename T>
+// The mode loop is unrolled to NM >= nm slots and the record stream (a, b,
+// |g|^2 slots and, with gg2, the slots' channels) runs one batch ahead, as in
+// k_phonon_bins.  With gg2, the old values of a batch's channels are loaded
+// before the next batch's stream is issued, so that waiting for them does
+// not wait for the stream; each channel has one slot, so nothing else writes
+// it in between.  A lane past the chunk's end, or a slot without a channel,
+// loads a valid address and stores nothing.
+template <typename T, int NM>
 __global__ __launch_bounds__(256) void k_phonon_bins_adj(PhArgs<T> A, const T *__restrict__ f,
                                                          const T *__restrict__ nph, const T *__restrict__ lam,
                                                          const T *__restrict__ mu, T *__restrict__ part,
@@ -2464,67 +2471,99 @@ __global__ __launch_bounds__(256) void k_phonon_bins_adj(PhArgs<T> A, const T *_
     const int64_t c = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) +
                       __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
     if (c >= A.n_chunks) return;
+    const int nm = A.nm;
     const int bk = A.chunk_bucket[c];
     const int64_t qc = A.bucket_q[bk], qm = A.bucket_qm[bk];
     const uint32_t modes = A.bucket_modes[bk];
     const uint32_t phon = mu ? modes & ~A.elastic : 0u;
+    const bool want_g = gg2 != nullptr && phon != 0u;
     const T ke = static_cast<T>(Ke), kp = static_cast<T>(A.Kp);
-    T w1[8], n1[8], w2[8], n2[8], m1[8], m2[8], acc1[8], acc2[8];
+    T w1[NM], n1[NM], w2[NM], n2[NM], m1[NM], m2[NM], acc1[NM], acc2[NM];
+    bool same = true;   // hw(-qc) = hw(qc) for every mode of the bucket
 #pragma unroll
-    for (int m = 0; m < 8; ++m) {
-        const bool on = (modes >> m) & 1u;
-        const bool ph = (phon >> m) & 1u;
-        w1[m] = on ? A.hw[qc * A.nm + m] : T(0);
-        w2[m] = on ? A.hw[qm * A.nm + m] : T(0);
-        n1[m] = ph ? nph[qc * A.nm + m] : T(0);
-        n2[m] = ph ? nph[qm * A.nm + m] : T(0);
-        m1[m] = ph ? mu[qc * A.nm + m] : T(0);
-        m2[m] = ph ? mu[qm * A.nm + m] : T(0);
+    for (int m = 0; m < NM; ++m) {
+        const int mm = min(m, nm - 1);
+        const bool on = m < nm && ((modes >> m) & 1u);
+        const bool ph = m < nm && ((phon >> m) & 1u);
+        w1[m] = on ? A.hw[qc * nm + mm] : T(0);
+        w2[m] = on ? A.hw[qm * nm + mm] : T(0);
+        n1[m] = ph ? nph[qc * nm + mm] : T(0);
+        n2[m] = ph ? nph[qm * nm + mm] : T(0);
+        m1[m] = ph ? mu[qc * nm + mm] : T(0);
+        m2[m] = ph ? mu[qm * nm + mm] : T(0);
+        same = same && w2[m] == w1[m];
         acc1[m] = T(0);
         acc2[m] = T(0);
     }
-    const int64_t beg = A.chunk_beg[c], end = A.chunk_beg[c + 1];
-    for (int64_t i = beg + lane; i < end; i += 64) {
-        const uint32_t a = A.pa[i], b = A.pb[i];
+    const int64_t beg = A.chunk_beg[c];
+    const int n = static_cast<int>(A.chunk_beg[c + 1] - beg);
+    auto rec = [&](int r) { return beg + min(r + lane, n - 1); };
+    uint32_t a0 = A.pa[rec(0)], b0 = A.pb[rec(0)], a1 = 0, b1 = 0;
+    T g0[NM], g1[NM];
+    int32_t h0[NM], h1[NM];
+#pragma unroll
+    for (int m = 0; m < NM; ++m) {
+        g0[m] = A.g2[min(m, nm - 1) * A.ld + rec(0)];
+        h0[m] = want_g ? A.chan[min(m, nm - 1) * A.ld + rec(0)] : -1;
+    }
+    auto batch = [&](int r, const uint32_t a, const uint32_t b, const T (&g)[NM], const int32_t (&h)[NM],
+                     uint32_t &an, uint32_t &bn, T (&gn)[NM], int32_t (&hn)[NM]) {
+        const bool v = r + lane < n;
         const T fa = f[a], fb = f[b];
         const T la = lam ? lam[a] : T(0), lb = lam ? lam[b] : T(0);
         const T x = A.st[a].eps - A.st[b].eps;
+        double old[NM];
+        if (want_g) {
+#pragma unroll
+            for (int m = 0; m < NM; ++m) old[m] = gg2[h[m] >= 0 ? h[m] : 0];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        const int64_t xi = rec(r + 64);
+        an = A.pa[xi];
+        bn = A.pb[xi];
+#pragma unroll
+        for (int m = 0; m < NM; ++m) {
+            gn[m] = A.g2[min(m, nm - 1) * A.ld + xi];
+            hn[m] = want_g ? A.chan[min(m, nm - 1) * A.ld + xi] : -1;
+        }
+        __builtin_amdgcn_sched_barrier(0);
         const T p1 = fb * (T(1) - fa), p2 = fa * (T(1) - fb);
         const T dp = p1 - p2;   // = f_b - f_a
 #pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            if (!((modes >> m) & 1u)) continue;
-            const T g = A.g2[m * A.ld + i];
-            const T g1 = ph_gauss(A, x + w1[m], s_tab);
+        for (int m = 0; m < NM; ++m) {
+            const bool on = v && m < nm && ((modes >> m) & 1u);
+            const T gm = keep_or_zero(g[m], on);
+            const T gq1 = ph_gauss(A, x + w1[m], s_tab);
             const T e1 = ph_gauss(A, x - w1[m], s_tab);
-            T g2_ = g1, e2 = e1;
-            if (w2[m] != w1[m]) {
-                g2_ = ph_gauss(A, x + w2[m], s_tab);
+            T gq2 = gq1, e2 = e1;
+            if (!same) {
+                gq2 = ph_gauss(A, x + w2[m], s_tab);
                 e2 = ph_gauss(A, x - w2[m], s_tab);
             }
-            acc1[m] += g * dp * (ke * la * (g1 + e1) + kp * m1[m] * g1);
-            acc2[m] -= g * dp * (ke * lb * (g2_ + e2) + kp * m2[m] * e2);
-            if (gg2 && ((phon >> m) & 1u)) {
-                const int32_t ch = A.chan[m * A.ld + i];
-                if (ch >= 0)
-                    gg2[ch] += static_cast<double>(kp * (m1[m] * g1 * (p1 + n1[m] * dp) +
-                                                         m2[m] * e2 * (p2 - n2[m] * dp)));
-            }
+            acc1[m] += gm * dp * (ke * la * (gq1 + e1) + kp * m1[m] * gq1);
+            acc2[m] -= gm * dp * (ke * lb * (gq2 + e2) + kp * m2[m] * e2);
+            if (want_g && on && ((phon >> m) & 1u) && h[m] >= 0)
+                gg2[h[m]] = old[m] + static_cast<double>(kp * (m1[m] * gq1 * (p1 + n1[m] * dp) +
+                                                                m2[m] * e2 * (p2 - n2[m] * dp)));
         }
+    };
+    for (int r = 0; r < n; r += 128) {
+        batch(r, a0, b0, g0, h0, a1, b1, g1, h1);
+        if (r + 64 >= n) break;
+        batch(r + 64, a1, b1, g1, h1, a0, b0, g0, h0);
     }
 #pragma unroll
-    for (int m = 0; m < 8; ++m) {
-        if (!((modes >> m) & 1u)) continue;
+    for (int m = 0; m < NM; ++m) {
         acc1[m] = wave_sum(acc1[m]);
         acc2[m] = wave_sum(acc2[m]);
     }
     if (lane == 0) {
-        T *pc = part + c * 2 * A.nm;
+        T *pc = part + c * 2 * nm;
 #pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            if (m >= A.nm) break;
+        for (int m = 0; m < NM; ++m) {
+            if (m >= nm) break;
             pc[m] = acc1[m];
-            pc[A.nm + m] = acc2[m];
+            pc[nm + m] = acc2[m];
         }
     }
 }
