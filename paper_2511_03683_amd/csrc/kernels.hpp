@@ -2621,6 +2621,10 @@ __global__ void k_pack_hwNmu(const T *__restrict__ hw, const T *__restrict__ nph
 // G(x - hw(-q)); the same form holds from either end of the channel).  One
 // workgroup per chunk of the destination layout; a destination with one
 // chunk adds its sum to out, others leave a partial for k_vjp_phonon_f_finish.
+// The entry stream (partner word, |g|^2) runs one batch ahead of the state
+// and table gathers, with two register sets, as in the pair pass; the
+// entry arrays are padded past their end, so the prefetch needs no bound, and
+// a thread past the row's end (or on an elastic mode) adds nothing.
 template <typename T>
 __global__ __launch_bounds__(256) void k_vjp_phonon_f(TiledArgs<T> A, const Vec4<T> *__restrict__ tab,
                                                       const T *__restrict__ f, uint32_t elastic,
@@ -2634,13 +2638,16 @@ __global__ __launch_bounds__(256) void k_vjp_phonon_f(TiledArgs<T> A, const Vec4
     const int d = A.chunk_dest[c];
     const int64_t beg = A.chunk_beg[c], end = A.chunk_beg[c + 1];
     const StateRec<T> sd = A.st[d];
+    const int64_t stride = blockDim.x;
     T acc[1] = {T(0)};
-    for (int64_t e = beg + threadIdx.x; e < end; e += blockDim.x) {
-        const uint32_t pn = A.pnu[e];
+    int64_t e = beg + threadIdx.x;
+    uint32_t pn0 = A.pnu[e], pn1 = 0;
+    T g0 = A.g2[e], g1 = T(0);
+    auto step = [&](int64_t x, const uint32_t pn, const T g, uint32_t &pn_next, T &g_next) {
         const int mode = static_cast<int>(pn & 7u);
-        if ((elastic >> mode) & 1u) continue;
         const int p = static_cast<int>(pn >> 3);
         const StateRec<T> sp = A.st[p];
+        const T fp = f[p];
         int64_t iq, im;
         if (A.padq) {
             iq = static_cast<int64_t>(static_cast<int>(sp.kqp - sd.kqp) + A.qoff);
@@ -2650,11 +2657,20 @@ __global__ __launch_bounds__(256) void k_vjp_phonon_f(TiledArgs<T> A, const Vec4
             im = q_linear(sp.kq, sd.kq, A.nq0, A.nq1, A.nq2);
         }
         const Vec4<T> t1 = tab[iq * A.nm + mode], t2 = tab[im * A.nm + mode];
-        const T x = sd.eps - sp.eps;
-        const T fp = f[p];
-        const T ga = stream_gauss(A, (x + t1.x) * (x + t1.x), s_tab);
-        const T ge = stream_gauss(A, (x - t2.x) * (x - t2.x), s_tab);
-        acc[0] += A.g2[e] * (t2.z * ge * (t2.y + T(1) - fp) - t1.z * ga * (t1.y + fp));
+        __builtin_amdgcn_sched_barrier(0);
+        pn_next = A.pnu[x + stride];
+        g_next = A.g2[x + stride];
+        __builtin_amdgcn_sched_barrier(0);
+        const T gm = keep_or_zero(g, x < end && !((elastic >> mode) & 1u));
+        const T xe = sd.eps - sp.eps;
+        const T ga = stream_gauss(A, (xe + t1.x) * (xe + t1.x), s_tab);
+        const T ge = stream_gauss(A, (xe - t2.x) * (xe - t2.x), s_tab);
+        acc[0] += gm * (t2.z * ge * (t2.y + T(1) - fp) - t1.z * ga * (t1.y + fp));
+    };
+    for (; e < end; e += 2 * stride) {
+        step(e, pn0, g0, pn1, g1);
+        if (e + stride >= end) break;
+        step(e + stride, pn1, g1, pn0, g0);
     }
     block_sum<T, 1>(acc);
     if (threadIdx.x == 0) {
