@@ -461,7 +461,16 @@ def main():
                                             per_stage="pack of the stage's N, electron pass, "
                                                       "phonon pass, even-part update of N")
         log(f"coupled rt step fp64: {msc / n_c:.3f} ms/step")
-        del ff, fc, Nc
+        # its discrete adjoint: dL/df0, dL/dN0 and dL/d|g|^2 through n_ca
+        # coupled steps, checkpoints every 2, loss = mean carrier energy
+        n_ca = 2 if args.quick else 4
+        gfT = tens(s.eps / s.n_states, torch.float64)
+        gga = torch.zeros(nch, dtype=torch.float64, device=dev)
+        msca, _ = timed(lambda: E.rt_adjoint_coupled(plan64, fp0, n64, 1.0, n_ca, 2, gfT=gfT, gg2=gga), 1, 1)
+        forms["rt_adjoint_coupled_f64"] = dict(steps=n_ca, checkpoint_every=2, dt_fs=1.0,
+                                               ms_per_step=msca / n_ca, gradients="f0, N0, |g|^2")
+        log(f"coupled rt adjoint fp64: {msca / n_ca:.1f} ms/step")
+        del ff, fc, Nc, gga
         # FP64 reference trajectory for the FP32 dynamics check below
         n_ref = 20 if args.quick else 200
         fref = fp0.clone()
