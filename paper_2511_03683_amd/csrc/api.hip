@@ -162,6 +162,7 @@ struct ephbte_plan_s {
     std::vector<uint32_t> st_key;          // host: packed box (padded table) or grid coordinates
     std::array<int64_t, 6> pr_key{};       // settings the pair tiles were built with
     bool pr_key_set = false;
+    bool pr_all_q = false;                 // every pair tile is q-ordered
     int64_t *pr_chunk_beg = nullptr, *pr_chunk_end = nullptr;
     int32_t *pr_chunk_dest = nullptr, *pr_dest_chunk = nullptr;
     TileRec *pr_tiles = nullptr;
@@ -169,6 +170,8 @@ struct ephbte_plan_s {
     bool pr_ok = false;
     bool exp_table = true;                 // FP64 Gaussians of the pair pass from the LDS table
     unsigned long long *lmax_bits = nullptr;  // max |lam| of the pair reverse pass (double bits)
+    unsigned long long *mmax_bits = nullptr;  // max |mu| and max |N| of the phonon side's dL/df over
+                                              // pair records (its own slots: other passes keep theirs)
     // batched pass: tiles of destinations and per-destination sub-tile offsets
     BTileRec *btiles = nullptr;
     int64_t *sub_off = nullptr;
@@ -336,7 +339,7 @@ void free_plan(ephbte_plan P) {
                      (void **)&P->ph_bucket_modes, (void **)&P->pr_partner, (void **)&P->pr_g2,
                      (void **)&P->pr_chan, (void **)&P->pr_chunk_beg, (void **)&P->pr_chunk_end,
                      (void **)&P->pr_chunk_dest, (void **)&P->pr_dest_chunk, (void **)&P->pr_tiles,
-                     (void **)&P->lmax_bits, (void **)&P->pr_ch0, (void **)&P->fmax_bits,
+                     (void **)&P->lmax_bits, (void **)&P->mmax_bits, (void **)&P->pr_ch0, (void **)&P->fmax_bits,
                      (void **)&P->used_rows};
     for (auto pp : ptrs) dfree(*pp);
     DevBuf *w[] = {&P->part,   &P->sym_part, &P->rk_ua,  &P->rk_ub,   &P->rk_acc, &P->hwN, &P->tr_W,   &P->tr_tau_inv,
@@ -570,6 +573,8 @@ void upload_chunks(ephbte_plan P, int64_t chunk_entries) {
     P->n_pr_tiles = static_cast<int64_t>(tp.size());
     P->pr_key = pr_key;
     P->pr_key_set = true;
+    P->pr_all_q = !tp.empty();
+    for (const Tile &t : tp) P->pr_all_q = P->pr_all_q && t.lds == 2;
 }
 
 // element (q, mode) of the plan's {hw, N} table is at q tq + mode tm
@@ -1901,9 +1906,41 @@ void enqueue_phonon_vjp_f(ephbte_plan P, const T *u, const T *N, const T *mu, T 
     Vec4<T> *tab = static_cast<Vec4<T> *>(P->ph_tab4.p);
     hipLaunchKernelGGL((k_pack_hwNmu<T>), dim3(grid_of(n)), dim3(256), 0, s, static_cast<const T *>(P->hw), N, mu,
                        tab, P->padq ? 1 : 0, P->qbox, P->nm, (const int32_t *)P->used_rows, n);
+    const double Kp = 2.0 * kPi / (kHbar * P->nk) / (P->sigma * std::sqrt(2.0 * kPi));
+    if (P->pr_ok && P->pr_all_q && P->sym_ok && P->n_pr_tiles > 0) {
+        // over the q-ordered pair records: max |N| and max |mu| of the call
+        // set the fixed-point scale
+        const int64_t nqm = nqm_of(P);
+        hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, P->mmax_bits, 2);
+        hipLaunchKernelGGL((k_abs_max_bits<T>), dim3(grid_of(nqm)), dim3(256), 0, s, mu, nqm, P->mmax_bits);
+        hipLaunchKernelGGL((k_abs_max_bits<T>), dim3(grid_of(nqm)), dim3(256), 0, s, N, nqm, P->mmax_bits + 1);
+        TiledArgs<T> a = pair_args<T>(P);
+        a.nmax_bits = P->mmax_bits + 1;
+        const dim3 grid(static_cast<unsigned>(P->n_pr_tiles)), block(1024);
+        const size_t shm = sym_lds_bytes(P->dtype, P->pr_lds_states);
+        const unsigned long long *mm = P->mmax_bits;
+        auto go = [&](auto nmc) {
+            constexpr int NM = decltype(nmc)::value;
+            if (P->padq)
+                hipLaunchKernelGGL((k_vjp_phonon_pairs<T, true, NM>), grid, block, shm, s, a, (const Vec4<T> *)tab, u,
+                                   P->elastic, mm);
+            else
+                hipLaunchKernelGGL((k_vjp_phonon_pairs<T, false, NM>), grid, block, shm, s, a, (const Vec4<T> *)tab,
+                                   u, P->elastic, mm);
+        };
+        if (P->nm <= 1) go(std::integral_constant<int, 1>{});
+        else if (P->nm <= 2) go(std::integral_constant<int, 2>{});
+        else if (P->nm <= 3) go(std::integral_constant<int, 3>{});
+        else if (P->nm <= 4) go(std::integral_constant<int, 4>{});
+        else if (P->nm <= 6) go(std::integral_constant<int, 6>{});
+        else go(std::integral_constant<int, 8>{});
+        hipLaunchKernelGGL((k_vjp_phonon_pairs_finish<T>), dim3((P->S + 255) / 256), dim3(256), 0, s, a, mm, Kp,
+                           out);
+        HIPC(hipGetLastError());
+        return;
+    }
     TiledArgs<T> a = tiled_args<T>(P);
     T *part = static_cast<T *>(P->part.p);
-    const double Kp = 2.0 * kPi / (kHbar * P->nk) / (P->sigma * std::sqrt(2.0 * kPi));
     if (P->n_chunks > 0)
         hipLaunchKernelGGL((k_vjp_phonon_f<T>), dim3(static_cast<unsigned>(P->n_chunks)), dim3(256), 0, s, a,
                            (const Vec4<T> *)tab, u, P->elastic, Kp, out, part);
@@ -2559,6 +2596,7 @@ ephbte_status ephbte_build_channels(const ephbte_problem *problem, const ephbte_
             dalloc(P->gmax_bits, sizeof(unsigned long long), &P->layout_bytes);
             dalloc(P->pack_bmax, sizeof(double) * kPackBlocks, &P->layout_bytes);
             dalloc(P->lmax_bits, sizeof(unsigned long long), &P->layout_bytes);
+            dalloc(P->mmax_bits, 2 * sizeof(unsigned long long), &P->layout_bytes);
             dalloc(P->fmax_bits, sizeof(unsigned long long), &P->layout_bytes);
             HIPC(hipMemset(P->nmax_bits, 0, sizeof(unsigned long long)));
             HIPC(hipMemset(P->fmax_bits, 0, sizeof(unsigned long long)));

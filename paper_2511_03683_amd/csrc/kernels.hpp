@@ -2691,6 +2691,109 @@ __global__ void k_vjp_phonon_f_finish(TiledArgs<T> A, const T *__restrict__ part
     out[d] += a;
 }
 
+// The same over pair records when every tile of the pair pass is q-ordered.
+// A lane takes one pair (d, p) with all its modes; seen from p, q and -q swap
+// roles and x = e_d - e_p changes sign, so the channel's two Gaussians
+// ga = G(x + hw(q)) and ge = G(x - hw(-q)) serve both states:
+//   dL/df_d += Kp |g|^2 [mu(-q) ge (N(-q) + 1 - f_p) - mu(q) ga (N(q) + f_p)]
+//   dL/df_p += Kp |g|^2 [mu(q) ga (N(q) + 1 - f_d) - mu(-q) ge (N(-q) + f_d)]
+// Each channel is read once and the lanes of a batch share the table rows of
+// their q.  Both sides are fixed-point LDS sums on the scale of vjp_scale
+// (max |mu| in place of max |lambda|), flushed to the global accumulator;
+// k_vjp_phonon_pairs_finish adds them to out.  A slot without a channel (or
+// of an elastic mode) is masked after its product, since its N may be
+// infinite (acoustic modes at q = 0).
+template <typename T, bool PADQ, int NM>
+__global__ __launch_bounds__(1024) void k_vjp_phonon_pairs(TiledArgs<T> A, const Vec4<T> *__restrict__ tab,
+                                                          const T *__restrict__ f, uint32_t elastic,
+                                                          const unsigned long long *__restrict__ mmax_bits) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int64_t ti = tile_of_block(A.n_tiles, A.xcd);
+    if (ti < 0) return;
+    const TileRec t = A.tiles[ti];
+    unsigned long long *s_j = reinterpret_cast<unsigned long long *>(smem);
+    Pair2<T> *s_ef = reinterpret_cast<Pair2<T> *>(s_j + A.lds_states);
+    uint32_t *s_kq = reinterpret_cast<uint32_t *>(s_ef + A.lds_states);
+    double *s_tab = reinterpret_cast<double *>(s_kq + A.lds_states);
+    const int n = t.p_hi - t.p_lo + 1;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const StateRec<T> sr = A.st[t.p_lo + i];
+        Pair2<T> ef;
+        ef.a = sr.eps;
+        ef.b = f[t.p_lo + i];
+        s_ef[i] = ef;
+        s_kq[i] = PADQ ? sr.kqp : sr.kq;
+        s_j[i] = 0ull;
+    }
+    if constexpr (sizeof(T) == 8)
+        for (int i = threadIdx.x; i < kExpTab; i += blockDim.x) s_tab[i] = A.e2tab[i];
+    const T scale = static_cast<T>(vjp_scale(A.nmax_bits, A.gmax_bits, mmax_bits, A.fmax_bits));
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    const int nw = static_cast<int>(blockDim.x >> 6);
+    const int nm = A.nm;
+    for (int64_t c = t.c0 + wave; c < t.c1; c += nw) {
+        const int64_t beg = A.chunk_beg[c];
+        const int len = static_cast<int>(A.chunk_end[c] - beg);
+        const uint32_t *__restrict__ pb = A.pnu + beg;
+        const T *__restrict__ gb = A.g2 + beg;
+        for (int r = 0; r < len; r += 64) {
+            const bool v = r + lane < len;
+            const uint32_t pn = pb[r + lane];
+            // a masked lane takes window slot 0 as both states and adds nothing
+            const int wd = v ? static_cast<int>(pn & 0xffffu) : 0;
+            const int wp = v ? static_cast<int>(pn >> 16) : 0;
+            const Pair2<T> efd = s_ef[wd], efp = s_ef[wp];
+            const uint32_t kd = s_kq[wd], kp = s_kq[wp];
+            int64_t iq, im;
+            if (PADQ) {
+                iq = static_cast<int64_t>(static_cast<int>(kp - kd) + A.qoff);
+                im = 2 * static_cast<int64_t>(A.qoff) - iq;
+            } else {
+                iq = q_linear(kd, kp, A.nq0, A.nq1, A.nq2);
+                im = q_linear(kp, kd, A.nq0, A.nq1, A.nq2);
+            }
+            const T x = efd.a - efp.a, fd = efd.b, fp = efp.b;
+            T sd = T(0), sp = T(0);
+#pragma unroll
+            for (int m = 0; m < NM; ++m) {
+                const int mm = min(m, nm - 1);
+                const Vec4<T> t1 = tab[iq * nm + mm], t2 = tab[im * nm + mm];
+                const T g = gb[mm * A.pld + r + lane];
+                const bool on = v && m < nm && !((elastic >> m) & 1u) && g != T(0);
+                const T ga = stream_gauss(A, (x + t1.x) * (x + t1.x), s_tab);
+                const T ge = stream_gauss(A, (x - t2.x) * (x - t2.x), s_tab);
+                const T a1 = t1.z * ga, a2 = t2.z * ge;
+                sd += keep_or_zero(g * (a2 * (t2.y + T(1) - fp) - a1 * (t1.y + fp)), on);
+                sp += keep_or_zero(g * (a1 * (t1.y + T(1) - fd) - a2 * (t2.y + fd)), on);
+            }
+            if (v) {
+                atomicAdd(s_j + wd, to_fixed(__builtin_rint(sd * scale)));
+                atomicAdd(s_j + wp, to_fixed(__builtin_rint(sp * scale)));
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const unsigned long long u = s_j[i];
+        if (u) atomicAdd(A.jacc + t.p_lo + i, u);
+    }
+}
+
+// out[d] += Kp (the fixed-point sum of d) / scale; the accumulator of d is
+// cleared for the next call
+template <typename T>
+__global__ void k_vjp_phonon_pairs_finish(TiledArgs<T> A, const unsigned long long *__restrict__ mmax_bits,
+                                          double Kp, T *__restrict__ out) {
+    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= A.S) return;
+    const double inv = 1.0 / vjp_scale(A.nmax_bits, A.gmax_bits, mmax_bits, A.fmax_bits);
+    const long long j = static_cast<long long>(A.jacc[d]);
+    A.jacc[d] = 0ull;
+    out[d] += static_cast<T>(Kp * static_cast<double>(j) * inv);
+}
+
 // out = x (mode 0) or out = (x(q) + x(-q)) / 2 per (q, mode) (mode 1): the
 // even part in q, which is its own transpose
 template <typename T>

@@ -360,6 +360,7 @@ int main(int argc, char **argv) {
         }
         bad.push_back(bad_pr);
         bad.push_back(-n_q);
+        bad.push_back(plan->pr_all_q ? 1.0 : 0.0);
         wr("out_tiles.bin", bad);
     } else if (mode == "phonon") {
         auto f = rd<double>("f.bin", static_cast<size_t>(S));

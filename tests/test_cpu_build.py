@@ -631,6 +631,8 @@ def test_tile_tables(driver, tmp_path, name, tune):
         assert n_q == 0, out
     elif name in ("multiband", "tb12", "parabolic4"):
         assert n_q > 0, out
+        if not tune:   # every pair tile q-ordered: the phonon side's dL/df runs over them
+            assert out[5] == 1, out
 
 
 @pytest.mark.parametrize("name,layout,dtype", [("multiband", 2, "f64"), ("multiband", 1, "f64"),
