@@ -1911,9 +1911,11 @@ void enqueue_phonon_vjp_f(ephbte_plan P, const T *u, const T *N, const T *mu, T 
         // over the q-ordered pair records: max |N| and max |mu| of the call
         // set the fixed-point scale
         const int64_t nqm = nqm_of(P);
+        // (a few hundred workgroups: fewer atomics on the one word)
+        const dim3 gm(std::min<unsigned>(grid_of(nqm), 256u));
         hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, P->mmax_bits, 2);
-        hipLaunchKernelGGL((k_abs_max_bits<T>), dim3(grid_of(nqm)), dim3(256), 0, s, mu, nqm, P->mmax_bits);
-        hipLaunchKernelGGL((k_abs_max_bits<T>), dim3(grid_of(nqm)), dim3(256), 0, s, N, nqm, P->mmax_bits + 1);
+        hipLaunchKernelGGL((k_abs_max_bits<T>), gm, dim3(256), 0, s, mu, nqm, P->mmax_bits);
+        hipLaunchKernelGGL((k_abs_max_bits<T>), gm, dim3(256), 0, s, N, nqm, P->mmax_bits + 1);
         TiledArgs<T> a = pair_args<T>(P);
         a.nmax_bits = P->mmax_bits + 1;
         const dim3 grid(static_cast<unsigned>(P->n_pr_tiles)), block(1024);
